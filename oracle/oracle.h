@@ -1,0 +1,120 @@
+/*
+ * CPU FP64 oracle for the SPH particle loop of "Modeling Neutron Star Oscillations in a
+ * Fixed General Relativistic Background Including Solid Crust Dynamics" (Tsao et al.).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the plain, slow reference that the GPU
+ * path is checked against.  Only the test suite, the smoke check and the benchmark's
+ * CPU-baseline leg may load it; the product path never calls it and shares no code,
+ * header or table with it.
+ *
+ * Every function takes HOST pointers, runs synchronously, and returns an orc_status.
+ * Arrays are structure-of-arrays of length n; the deviatoric stress S and its rate dSdt
+ * are 6*n, component-major in the order xx, yy, zz, xy, xz, yz.
+ * Per-particle sums over neighbours are taken in increasing neighbour index order, so the
+ * oracle is deterministic for any thread count.
+ *
+ * Parity status of each function is stated next to it; "parity unpinned" marks a reading
+ * of the paper with no independent check beyond oracle/GPU consistency.
+ */
+#ifndef SPH_ORACLE_H
+#define SPH_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ORC_OK = 0, ORC_E_ARG = 1, ORC_E_OOM = 3, ORC_E_NGB_CAPACITY = 5,
+  ORC_E_NONFINITE = 6, ORC_E_EOS_DOMAIN = 7
+} orc_status;
+
+enum { ORC_WC2 = 0, ORC_WC4 = 1 };
+enum { ORC_H_FIXED = 0, ORC_H_ADAPTIVE = 1 };
+enum { ORC_NEWTONIAN = 0, ORC_TOV = 1 };
+enum { ORC_EOS_GAMMA = 0, ORC_EOS_TABLE = 1 };
+enum { ORC_MU_CONST = 0, ORC_MU_PFACTOR = 1 };
+enum { ORC_YIELD_PAPER = 0, ORC_YIELD_RADIAL = 1 };
+enum { ORC_Y0_CONST = 0, ORC_Y0_EFACTOR = 1 };
+enum { ORC_BREAK_OFF = 0, ORC_BREAK_ONSET = 1, ORC_BREAK_FLUIDIZE = 2 };
+enum { ORC_ROT_OBJECTIVE = 0, ORC_ROT_LITERAL = 1 };
+enum { ORC_NGB_BRUTE = 0, ORC_NGB_GRID = 1 };
+
+typedef struct {
+  int32_t kernel, h_mode, background, periodic;
+  double eta, box;                 /* periodic box [0, box)^3 */
+  double m;                        /* equal particle mass */
+  /* background: bg[0..3][bg_n] = alpha, dalpha/drbar, psi, dpsi/drbar on rbar_i = i*bg_dr */
+  const double* bg; int32_t bg_n; double bg_dr, bg_M;
+  /* artificial viscosity */
+  double visc_alpha, visc_beta, visc_eps;
+  /* equation of state */
+  int32_t eos; double gamma;
+  const double* tab_lnP; const double* tab_lncs2;  /* [i_rho * tab_nu + i_u] */
+  int32_t tab_nr, tab_nu; double tab_lnr0, tab_dlnr, tab_lnu0, tab_dlnu;
+  /* solid */
+  int32_t mu_mode; double mu_const, mu_pfactor;
+  int32_t yield_mode, y0_mode; double y0_const, y0_over_E;
+  int32_t break_mode; double eps_break;
+  int32_t rotation;
+} orc_params;
+
+typedef struct {
+  int64_t n;
+  double *x, *y, *z, *vx, *vy, *vz, *u, *h, *S;  /* S: 6n */
+  int8_t* type; uint8_t* broken;
+  /* outputs of the evaluation stages */
+  double *D, *rho, *P, *cs, *mu, *Y0, *B;
+  double *ax, *ay, *az, *dudt, *dSdt;            /* dSdt: 6n */
+  double *sdot;                                  /* S:epsdot/D (energy source) */
+} orc_state;
+
+/* Neighbour sets N(a) = { b != a : |x_a - x_b|^2 < (h_a + h_b)^2 } (section "Solid SPH
+ * Equations": the sum runs over particles within the support radius 2 h_ab = h_a + h_b).
+ * Output is CSR: offsets[n+1], ids[offsets[n]] with each list ascending.  cap bounds ids;
+ * on overflow returns ORC_E_NGB_CAPACITY and offsets[n] holds the size needed.
+ * Pinned by: BRUTE vs GRID equality and symmetry on random inputs; 81/93-neighbour lattice. */
+int orc_neighbours(const orc_params* p, int64_t n, const double* x, const double* y,
+                   const double* z, const double* h, int32_t mode,
+                   int64_t* offsets, int32_t* ids, int64_t cap);
+
+/* Smoothing kernel: W(r, h_ab) and F with grad_a W = F (x_a - x_b).
+ * Pinned by: unit normalisation, compact support, finite-difference derivative. */
+void orc_kernel(int32_t kernel, double r, double hab, double* W, double* F);
+
+/* Largest eigenvalue of symmetric 3x3 matrices (6 comps each, xx,yy,zz,xy,xz,yz; AoS here).
+ * Pinned by: LAPACK eigenvalues on random matrices. */
+void orc_lambda_max(int64_t n, const double* s6, double* out);
+
+/* Density D = sum m W, then rho, P, c_s, mu, Y0, B per particle.  Pinned by: lattice density. */
+int orc_density(const orc_params* p, orc_state* st, const int64_t* offsets, const int32_t* ids);
+
+/* Velocity gradient, strain/rotation rates and dS/dt (eqs. solid4-solid6); sdot = S:epsdot/D.
+ * Pinned by: affine-velocity and rigid-rotation tests. */
+int orc_stress_rate(const orc_params* p, orc_state* st, const int64_t* offsets, const int32_t* ids,
+                    double* kappa_G /* optional n: sum |m v_ba grad W| */);
+
+/* Pair forces (eqs. solid2, solid3) and the fixed-background trajectory equation.
+ * Pinned by: pairwise antisymmetry, power balance, static-lattice zero force;
+ * the fixed-background form has "parity unpinned" pieces (see the source). */
+int orc_forces(const orc_params* p, orc_state* st, const int64_t* offsets, const int32_t* ids,
+               double* kappa_a /* optional n */, double* kappa_u /* optional n */);
+
+/* Pair force matrix for the antisymmetry pin: F[a*n + b] (3 comps, AoS) = the contribution of
+ * pair (a,b) to m * (-A^P + A^S) of a, Newtonian.  n <= 4096. */
+int orc_pair_forces(const orc_params* p, orc_state* st, double* F);
+
+/* Von Mises yield scaling of S in place with per-particle Y0 (section "Solid SPH Equations"). */
+void orc_yield(const orc_params* p, int64_t n, double* S, const double* Y0);
+
+/* nsteps kick-drift-kick steps of size dt.  On entry the rates (ax..dSdt) and the per-particle
+ * Y0/B/mu must hold a full evaluation at the current state. */
+int orc_step(const orc_params* p, orc_state* st, double dt, int32_t nsteps, int32_t ngb_mode);
+
+/* One full evaluation: neighbours, density, stress rate, forces. */
+int orc_evaluate(const orc_params* p, orc_state* st, int32_t ngb_mode);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,50 @@
+"""Synthetic tabulated equation of state: a cold piecewise polytrope plus a thermal Gamma-law part.
+
+P(rho, u) = P_cold(rho) + (Gamma_th - 1) rho (u - u_cold(rho))  (the usual hybrid form; the
+piecewise polytrope is the construction the paper cites for crust/core EoS refinement).
+Relativistic sound speed c_s^2 = dP/d(eps) at fixed entropy:
+c_s^2 = (Gamma_i P_cold + Gamma_th P_th) / (rho h),  h = 1 + u + P/rho.
+States with P <= 0 or c_s^2 <= 0 are outside the domain and stored as NaN.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from .params import EosTable
+from .tov import PiecewisePolytrope, density_from_cgs
+
+
+def default_pp() -> PiecewisePolytrope:
+    """3-piece cold EoS: Gamma = 1.35 / 3.0 / 2.7 split at 10^14.7 and 10^15 g/cm^3."""
+    return PiecewisePolytrope(0.41817, [1.35, 3.0, 2.7],
+                              [density_from_cgs(10 ** 14.7), density_from_cgs(1e15)])
+
+
+def hybrid_eos(pp: PiecewisePolytrope, rho, u, gamma_th: float = 1.8):
+    rho = np.asarray(rho, dtype=np.float64)
+    u = np.asarray(u, dtype=np.float64)
+    Pc, uc = pp.from_rho(rho)
+    Gc = pp.gamma_of(rho)
+    Pth = (gamma_th - 1.0) * rho * (u - uc)
+    P = Pc + Pth
+    h = 1.0 + u + P / rho
+    cs2 = (Gc * Pc + gamma_th * Pth) / (rho * h)
+    return P, cs2
+
+
+def make_table(pp: PiecewisePolytrope, gamma_th: float = 1.8, nr: int = 1024, nu: int = 1024,
+               rho_range=(1e-10, 1e-2), u_range=(1e-5, 2.0)) -> EosTable:
+    lnr = np.linspace(math.log(rho_range[0]), math.log(rho_range[1]), nr)
+    lnu = np.linspace(math.log(u_range[0]), math.log(u_range[1]), nu)
+    rho = np.exp(lnr)[:, None]
+    u = np.exp(lnu)[None, :]
+    P, cs2 = hybrid_eos(pp, rho, u, gamma_th)
+    ok = (P > 0) & (cs2 > 0) & np.isfinite(P) & np.isfinite(cs2)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        lnP = np.where(ok, np.log(np.where(ok, P, 1.0)), np.nan)
+        lncs2 = np.where(ok, np.log(np.where(ok, cs2, 1.0)), np.nan)
+    return EosTable(lnP=np.ascontiguousarray(lnP), lncs2=np.ascontiguousarray(lncs2),
+                    lnr0=float(lnr[0]), dlnr=float(lnr[1] - lnr[0]),
+                    lnu0=float(lnu[0]), dlnu=float(lnu[1] - lnu[0]))

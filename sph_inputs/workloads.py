@@ -1,0 +1,148 @@
+"""Seeded synthetic workloads with the shapes of the paper's runs.
+
+lattice(): periodic 16^3 cubic lattice of an elastic solid (Newtonian), the small case.
+star():    a TOV star on spherical shells in the fixed isotropic background with a solid
+           crust in the outer 1 km (mu = factor * P), any particle count.
+pp_star(): the same construction for the piecewise-polytrope + thermal EoS star with the
+           tabulated EoS, used for the mixed-precision / surrogate runs.
+ensemble(): many independent stars of uneven sizes.
+Every random draw uses numpy PCG64 with the stated seed.
+"""
+from __future__ import annotations
+
+import dataclasses
+import functools
+import math
+from typing import Optional
+
+import numpy as np
+
+from . import eos_table as eos_mod
+from .lattice import cfl_dt, cubic_lattice, gaussian_velocities
+from .params import MethodParams
+from .star import crust_mask, l2_perturbation, place_star, profile_at, radial_perturbation
+from .tov import Background, Polytrope, make_background, solve_tov
+
+GAMMA2_K = 83.0233
+GAMMA2_RHOC = 2.133857e-3
+PP_RHOC = 2.255428e-3
+ETA_100 = (3.0 * 100.0 / (32.0 * math.pi)) ** (1.0 / 3.0)   # about 100 neighbours with support 2h
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    params: MethodParams
+    arrays: dict
+    dt: float
+    steps: int
+    bg: Optional[Background] = None
+    star_offsets: Optional[np.ndarray] = None      # ensembles: particle ranges per star
+    star_params: Optional[np.ndarray] = None       # ensembles: (nstars, 2) = m, mu factor
+
+    @property
+    def n(self):
+        return int(self.arrays["x"].shape[0])
+
+    def copy_arrays(self):
+        return {k: v.copy() for k, v in self.arrays.items()}
+
+
+def _arrays(x, y, z, vx, vy, vz, u, h, typ):
+    n = x.shape[0]
+    return dict(x=x, y=y, z=z, vx=vx, vy=vy, vz=vz, u=np.asarray(u, np.float64).copy(),
+                h=np.asarray(h, np.float64).copy(), S=np.zeros((6, n)),
+                type=np.asarray(typ, np.int8).copy(), broken=np.zeros(n, np.uint8),
+                id=np.arange(n, dtype=np.int32))
+
+
+def lattice(n_side: int = 16, seed: int = 1, mu: float = 1.0, y0: float = 1e9, steps: int = 10):
+    """Periodic unit box, Wendland C2, h = 1.3 dx, Gamma = 5/3 with u = 1.5 (P ~ 1), mu = 1."""
+    x, y, z, dx = cubic_lattice(n_side, 1.0)
+    n = x.shape[0]
+    gamma, u0 = 5.0 / 3.0, 1.5
+    cs = math.sqrt(gamma * (gamma - 1.0) * u0)
+    vx, vy, vz = gaussian_velocities(n, 1e-3 * cs, seed)
+    h = np.full(n, 1.3 * dx)
+    p = MethodParams(m=dx**3, kernel="WC2", h_mode="FIXED", eta=1.3, background="NEWTONIAN",
+                     periodic=True, box=1.0, eos="GAMMA_LAW", gamma=gamma, mu_mode="CONST",
+                     mu_const=mu, y0_mode="CONST", y0_const=y0, break_mode="OFF")
+    cL = math.sqrt(cs * cs + 4.0 * mu / 3.0)
+    vmax = np.sqrt(vx * vx + vy * vy + vz * vz)
+    dt = cfl_dt(h, cL, vmax)
+    return Workload("lattice16", p, _arrays(x, y, z, vx, vy, vz, np.full(n, u0), h, np.ones(n)),
+                    dt, steps)
+
+
+@functools.lru_cache(maxsize=4)
+def gamma2_background(n: int = 8192) -> Background:
+    return make_background(solve_tov(Polytrope(GAMMA2_K, 2.0), GAMMA2_RHOC), n)
+
+
+@functools.lru_cache(maxsize=2)
+def pp_background(n: int = 8192) -> Background:
+    return make_background(solve_tov(eos_mod.default_pp(), PP_RHOC), n)
+
+
+@functools.lru_cache(maxsize=2)
+def pp_table(nr: int = 1024, nu: int = 1024):
+    return eos_mod.make_table(eos_mod.default_pp(), 1.8, nr, nu)
+
+
+def _star_common(bg, N, seed, kernel, eta, l, A, mu_factor, plastic, precision, eos, gamma,
+                 table, steps, name, jitter=0.05):
+    x, y, z, rr, m = place_star(bg, N, seed, jitter)
+    rho, P, u, D0 = profile_at(bg, rr)
+    D0 = np.maximum(D0, D0[D0 > 0].min() if np.any(D0 > 0) else 1e-12)
+    h = eta * (m / D0) ** (1.0 / 3.0)
+    if l == 0:
+        vx, vy, vz = radial_perturbation(x, y, z, A, bg.Rbar)
+    else:
+        vx, vy, vz = l2_perturbation(x, y, z, A, bg.Rbar)
+    rb = np.sqrt(x * x + y * y + z * z)
+    typ = crust_mask(bg, rb).astype(np.int8)
+    u = np.maximum(u, np.min(u[u > 0]))
+    kw = dict(m=m, kernel=kernel, h_mode="ADAPTIVE", eta=eta, background="TOV",
+              bg_table=bg.table, bg_dr=bg.drbar, bg_M=bg.M, periodic=False, box=0.0,
+              eos=eos, gamma=gamma, table=table, mu_mode="P_FACTOR", mu_pfactor=mu_factor,
+              precision=precision)
+    if plastic:
+        kw.update(y0_mode="E_FACTOR", y0_over_E=0.2, break_mode="FLUIDIZE", eps_break=0.1)
+    else:
+        kw.update(y0_mode="CONST", y0_const=1e300, break_mode="OFF")
+    p = MethodParams(**kw)
+    # Courant step from the static profile: c_L^2 = c_s^2 + 4 mu / (3 rho)
+    Pm = np.maximum(P, 1e-300)
+    rhom = np.maximum(rho, 1e-300)
+    hen = 1.0 + u + Pm / rhom
+    cs2 = gamma * Pm / (rhom * hen) if eos == "GAMMA_LAW" else eos_mod.hybrid_eos(eos_mod.default_pp(), rhom, u)[1]
+    cs2 = np.maximum(cs2, 0.0)
+    cL = np.sqrt(cs2 + np.where(typ == 1, 4.0 * mu_factor * Pm / (3.0 * rhom), 0.0))
+    vmag = np.sqrt(vx * vx + vy * vy + vz * vz)
+    dt = cfl_dt(h, cL, vmag)
+    return Workload(name, p, _arrays(x, y, z, vx, vy, vz, u, h, typ), dt, steps, bg)
+
+
+def star(N: int = 200_000, seed: int = 2, kernel: str = "WC2", eta: float = 1.3, l: int = 0,
+         A: float = 1e-3, mu_factor: float = 0.01, plastic: bool = False,
+         precision: str = "FP64", steps: int = 100):
+    """Gamma = 2 polytrope star, M = 1.4, R = 12 km, Gamma-law EoS (u = K rho)."""
+    bg = gamma2_background()
+    return _star_common(bg, N, seed, kernel, eta, l, A, mu_factor, plastic, precision,
+                        "GAMMA_LAW", 2.0, None, steps, f"star{N}")
+
+
+def star_2m(N: int = 2_000_000, seed: int = 3, precision: str = "FP32", steps: int = 1000):
+    """2M-particle star: Wendland C4, about 100 neighbours, l = 2 with A = 1e-2, plasticity and
+    maximum-strain breaking (yield strain 0.1)."""
+    return star(N, seed, "WC4", ETA_100, 2, 1e-2, 0.01, True, precision, steps)
+
+
+def pp_star(N: int = 2_000_000, seed: int = 3, precision: str = "FP64", eos: str = "TABLE",
+            steps: int = 1000):
+    """Piecewise-polytrope star with the tabulated hybrid EoS (u = u_cold on the profile)."""
+    bg = pp_background()
+    w = _star_common(bg, N, seed, "WC4", ETA_100, 2, 1e-2, 0.01, True, precision, "TABLE",
+                     1.8, pp_table(), steps, f"ppstar{N}")
+    w.params = w.params.replace(eos=eos)
+    return w
