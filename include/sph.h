@@ -1,0 +1,171 @@
+/*
+ * sph.h - C ABI of the MI355X (gfx950) SPH particle loop for neutron stars with a solid crust,
+ * after Tsao, Sagert, Korobkin, Tews, Lim, Dilts, Loiseau, "Modeling Neutron Star
+ * Oscillations in a Fixed General Relativistic Background Including Solid Crust Dynamics"
+ * (arXiv:2107.07315).
+ *
+ * One step of the method is: neighbour search -> density summation (with the equation of
+ * state) -> velocity gradient and deviatoric stress rate -> momentum/energy pair forces in the
+ * fixed background -> kick-drift-kick integration with von Mises yield and maximum-strain
+ * breaking.  Each stage below is one call; sph_step runs whole steps.
+ *
+ * Conventions
+ *  - Units: G = c = Msun = 1 (section "Fixed metric background", conventions).
+ *  - Memory: every array pointer in sph_state and the table pointers in sph_params are DEVICE
+ *    pointers owned by the caller; the library never frees or reallocates them.  Arrays are
+ *    structure-of-arrays of length n; S and dSdt hold 6*n doubles, component-major in the order
+ *    xx, yy, zz, xy, xz, yz.  Library scratch (sort buffers, cell tables, neighbour lists,
+ *    half-step copies, mixed-precision shadows) is allocated by sph_create for `capacity`
+ *    particles and freed by sph_destroy.
+ *  - Streams: every call is enqueued on the HIP stream given to sph_create and returns without
+ *    waiting, except sph_sync, sph_export_neighbours and the *_get_* helpers, which wait.
+ *  - Errors: argument and call-order errors return immediately with nothing enqueued.  Errors
+ *    found on the device (non-finite fields, neighbour-list overflow, states outside the EoS
+ *    table) are latched in a device status word with the first offending particle and are
+ *    returned by the next sph_sync.
+ *  - Order: sph_build_cells -> sph_density -> sph_stress_rate -> sph_forces.  A stage called
+ *    before its predecessor for the current positions returns SPH_E_ORDER.
+ *  - Reordering: sph_build_cells permutes every particle array of the state in place into the
+ *    cell order it uses (id follows the particles); results are reported in that order.
+ *  - Threads: one host thread per context.
+ */
+#ifndef SPH_H
+#define SPH_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sph_ctx sph_ctx;
+
+typedef enum {
+  SPH_OK = 0,
+  SPH_E_ARG = 1,           /* invalid argument (null pointer, size, mode)                  */
+  SPH_E_HIP = 2,           /* HIP runtime error                                             */
+  SPH_E_OOM = 3,           /* device allocation failed                                      */
+  SPH_E_ORDER = 4,         /* stage called out of order                                     */
+  SPH_E_NGB_CAPACITY = 5,  /* a neighbour list exceeded max_neighbours                      */
+  SPH_E_NONFINITE = 6,     /* a field became NaN/Inf                                        */
+  SPH_E_EOS_DOMAIN = 7     /* (rho, u) outside the tabulated equation of state              */
+} sph_status;
+
+enum { SPH_WC2 = 0, SPH_WC4 = 1 };                         /* Wendland kernels, support 2h  */
+enum { SPH_H_FIXED = 0, SPH_H_ADAPTIVE = 1 };
+enum { SPH_NEWTONIAN = 0, SPH_TOV = 1 };
+enum { SPH_EOS_GAMMA = 0, SPH_EOS_TABLE = 1, SPH_EOS_MLP = 2 };
+enum { SPH_MU_CONST = 0, SPH_MU_PFACTOR = 1 };
+enum { SPH_YIELD_PAPER = 0, SPH_YIELD_RADIAL = 1 };
+enum { SPH_Y0_CONST = 0, SPH_Y0_EFACTOR = 1 };
+enum { SPH_BREAK_OFF = 0, SPH_BREAK_ONSET = 1, SPH_BREAK_FLUIDIZE = 2 };
+enum { SPH_ROT_OBJECTIVE = 0, SPH_ROT_LITERAL = 1 };
+enum { SPH_FP64 = 0, SPH_FP32 = 1 };
+
+/* Particle state (section "Solid SPH Equations": per-particle position, velocity, internal
+ * energy, deviatoric stress; equal mass per particle, section "Fixed metric background").
+ * x,y,z: coordinate positions (isotropic coordinates with the TOV background).
+ * vx,vy,vz: coordinate velocity dx/dt.  u: specific internal energy.  h: smoothing length.
+ * S: deviatoric stress (6 comps).  type: 0 fluid core, 1 solid crust.  broken: 1 once the
+ * maximum-strain criterion fired.  id: caller's particle id, permuted with the particles.
+ * star: optional (may be NULL) index into the ensemble table of sph_ensemble_set.
+ * Outputs: D computational density, rho rest-mass density, P pressure, cs sound speed,
+ * ax..az coordinate acceleration, dudt, dSdt. */
+typedef struct {
+  int64_t n;
+  double *x, *y, *z, *vx, *vy, *vz, *u, *h, *S;
+  int8_t* type;
+  uint8_t* broken;
+  int32_t* id;
+  int32_t* star;
+  double *D, *rho, *P, *cs, *ax, *ay, *az, *dudt, *dSdt;
+} sph_state;
+
+/* Method parameters.  Where the paper leaves a choice open, the field selects it; the defaults
+ * used throughout are noted. */
+typedef struct {
+  int32_t kernel;          /* SPH_WC2 | SPH_WC4                                               */
+  int32_t h_mode;          /* FIXED, or ADAPTIVE: h = eta (m/D)^(1/3) after each step         */
+  int32_t background;      /* NEWTONIAN, or TOV: static isotropic metric from bg table        */
+  int32_t periodic;        /* periodic cube [0, box)^3 with minimum-image pairs               */
+  double eta, box, m;      /* m: particle mass (equal baryon mass per particle)               */
+  const double* bg;        /* device: 4*bg_n doubles alpha, dalpha/drbar, psi, dpsi/drbar    */
+  int32_t bg_n;            /*   on rbar_i = i*bg_dr; exterior Schwarzschild with mass bg_M    */
+  double bg_dr, bg_M;
+  double visc_alpha, visc_beta, visc_eps;   /* Monaghan viscosity (default 1, 2, 0.01)        */
+  int32_t eos;             /* GAMMA: P=(gamma-1) rho u; TABLE: bilinear ln P, ln cs^2;         */
+  double gamma;            /*   MLP: surrogate with table fallback (sph_mlp_*)                */
+  const double* tab_lnP;   /* device: [i_rho * tab_nu + i_u]                                  */
+  const double* tab_lncs2;
+  int32_t tab_nr, tab_nu;
+  double tab_lnr0, tab_dlnr, tab_lnu0, tab_dlnu;
+  int32_t mu_mode;         /* shear modulus of crust particles: CONST mu_const or mu_pfactor*P */
+  double mu_const, mu_pfactor;
+  int32_t yield_mode;      /* PAPER f = min(Y0^2/sigma_v^2, 1) (default) or RADIAL Y0/sigma_v  */
+  int32_t y0_mode;         /* CONST y0_const, or EFACTOR y0_over_E * E                         */
+  double y0_const, y0_over_E;
+  int32_t break_mode;      /* OFF, ONSET (flag only), FLUIDIZE (flag, then S = 0 and mu = 0)   */
+  double eps_break;        /* breaking strain                                                  */
+  int32_t rotation;        /* OBJECTIVE R S - S R (default) or LITERAL S R - R S               */
+  int32_t precision;       /* FP64, or FP32 pair sums with FP64 positions/integration/metric  */
+  int32_t max_neighbours;  /* list capacity per particle (0: 512)                              */
+  int32_t resort_every;    /* inside sph_step: full re-sort every k steps (0: 10)              */
+  int32_t cell_div;        /* cells per smoothing diameter of the finest level (0: 2)          */
+} sph_params;
+
+/* Create a context for up to `capacity` particles on the current HIP device; all work is
+ * enqueued on `hip_stream` (a hipStream_t, may be NULL for the default stream).
+ * Returns SPH_E_ARG for a bad parameter set, SPH_E_OOM if scratch does not fit. */
+sph_status sph_create(const sph_params* params, void* hip_stream, int64_t capacity, sph_ctx** out);
+void sph_destroy(sph_ctx* ctx);
+
+/* Replace the parameters (same capacity).  Invalidates the stage order. */
+sph_status sph_set_params(sph_ctx* ctx, const sph_params* params);
+
+/* Neighbour search set-up (the summation runs over particles within the support radius,
+ * section "Solid SPH Equations"): sort particles into a multi-level cell grid (levels by h),
+ * permute all state arrays into that order, and build exact neighbour lists
+ * N(a) = { b != a : |x_a - x_b|^2 < (h_a + h_b)^2 } evaluated in FP64 without contraction. */
+sph_status sph_build_cells(sph_ctx* ctx, sph_state* st);
+
+/* Density summation D_a = sum_b m W(r_ab, h_ab) including b = a (section "Fixed metric
+ * background": the computational density D = rho sqrt(gamma) W_L recovered by the standard
+ * SPH sum), then rho = D / (psi^6 W_L), P and c_s from the EoS (eq. poly_eos family; the
+ * relativistic sound speed of the setup section), the crust shear modulus and yield stress.
+ * Writes D, rho, P, cs. */
+sph_status sph_density(sph_ctx* ctx, sph_state* st);
+
+/* Velocity gradient and stress rate (eqs. solid4-solid6): strain and rotation rates from
+ * G^ij = sum_b m (v_b - v_a)^i d_j W_ab, dS/dt = 2 mu (epsdot - tr/3) + rotation terms, and
+ * the stress work S:epsdot/D for the energy equation.  Crust particles only; dSdt = 0 elsewhere. */
+sph_status sph_stress_rate(sph_ctx* ctx, sph_state* st);
+
+/* Pair forces (eqs. solid2, solid3) with artificial viscosity, and in TOV mode the fluid
+ * trajectory equation of the fixed-background section with zero shift.  Writes ax..az, dudt. */
+sph_status sph_forces(sph_ctx* ctx, sph_state* st);
+
+/* nsteps kick-drift-kick steps of size dt (dt > 0).  On entry the rates must be those of a full
+ * evaluation at the current state (build_cells, density, stress_rate, forces).  Applies the
+ * von Mises yield scaling after each stress update and the maximum-strain breaking test
+ * (section "Solid SPH Equations"), and the adaptive smoothing length. */
+sph_status sph_step(sph_ctx* ctx, sph_state* st, double dt, int32_t nsteps);
+
+/* Wait for the context's stream; return and clear the first latched device error. */
+sph_status sph_sync(sph_ctx* ctx);
+
+/* Copy the current neighbour lists to host memory as CSR in the particles' current order:
+ * offsets[n+1] (host), ids[offsets[n]] (host, indices into the current order).  Lists are
+ * written unsorted.  Returns SPH_E_NGB_CAPACITY (and offsets) if cap is too small.  Waits. */
+sph_status sph_export_neighbours(sph_ctx* ctx, int64_t* offsets, int32_t* ids, int64_t cap);
+
+/* Human-readable name of a status code (static string). */
+const char* sph_status_string(sph_status s);
+
+/* Kernel timing of the last sph_step call: number of launches and total milliseconds of the
+ * force pass, measured with HIP events on the context stream (0 if timing is off).  Waits. */
+sph_status sph_set_timing(sph_ctx* ctx, int32_t enable);
+sph_status sph_get_timing(sph_ctx* ctx, const char* stage, int32_t* launches, double* ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -81,6 +81,18 @@ void orc_kernel(int32_t kernel, double r, double hab, double* W, double* F) {
   }
 }
 
+/* Condition number of the kernel-gradient factor F with respect to q = r/h_ab:
+ * 1 + q |d ln F / d q|.  Near the support edge F ~ t^k with t = 1 - q/2 small, so a relative
+ * perturbation of q (from rounding r or h_ab) is amplified; the parity bound kappa carries it. */
+static double kernel_cond(int32_t kernel, double r, double hab) {
+  double q = r / hab;
+  if (q >= 2.0) return 1.0;
+  double t = 1.0 - 0.5 * q;
+  if (!(t > 0.0)) return 1.0;
+  double dl = (kernel == ORC_WC4) ? (-2.5 / t + 2.5 / (1.0 + 2.5 * q)) : (-1.5 / t);
+  return 1.0 + q * fabs(dl);
+}
+
 /* ------------------------------------------------------------------------------------ */
 /* neighbour sets                                                                        */
 
@@ -431,11 +443,12 @@ int orc_stress_rate(const orc_params* p, orc_state* st, const int64_t* off, cons
       double W, F;
       orc_kernel(p->kernel, r, 0.5 * (st->h[a] + st->h[b]), &W, &F);
       double g[3] = {F * d[0], F * d[1], F * d[2]};
+      double kc = kernel_cond(p->kernel, r, 0.5 * (st->h[a] + st->h[b]));
       double vba[3] = {st->vx[b] - va[0], st->vy[b] - va[1], st->vz[b] - va[2]};
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
           G[i][j] += p->m * vba[i] * g[j];
-          kap += fabs(p->m * vba[i] * g[j]);
+          kap += fabs(p->m * vba[i] * g[j]) * kc;
         }
     }
     if (kappa_G) kappa_G[a] = kap;
@@ -497,6 +510,7 @@ static pairsum_t pair_sums(const orc_params* p, const orc_state* st, int64_t a, 
     double W, F;
     orc_kernel(p->kernel, r, hab, &W, &F);
     double g[3] = {F * d[0], F * d[1], F * d[2]};
+    double kc = kernel_cond(p->kernel, r, hab);
     double v[3] = {st->vx[a] - st->vx[b], st->vy[a] - st->vy[b], st->vz[a] - st->vz[b]};
     double vr = v[0] * d[0] + v[1] * d[1] + v[2] * d[2];
     double Db = st->D[b];
@@ -510,21 +524,24 @@ static pairsum_t pair_sums(const orc_params* p, const orc_state* st, int64_t a, 
       Pi = (-p->visc_alpha * cbar * muab + p->visc_beta * muab * muab) / Dbar;
     }
     double cP = p->m * (pia + pib + Pi);
-    double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    double gn = fabs(g[0]) + fabs(g[1]) + fabs(g[2]);
     for (int i = 0; i < 3; ++i) o.AP[i] += cP * g[i];
-    o.kP += fabs(cP) * gn;
+    /* kappa: sum of the magnitudes of every elementary product (summation condition bound) */
+    o.kP += p->m * (fabs(pia) + fabs(pib) + fabs(Pi)) * gn * kc;
     s6_to_m(st->S, n, b, Sb);
     double Da2 = Da * Da, Db2 = Db * Db;
     for (int i = 0; i < 3; ++i) {
       double t = 0.0;
-      for (int j = 0; j < 3; ++j) t += (Sa[i][j] / Da2 + Sb[i][j] / Db2) * g[j];
+      for (int j = 0; j < 3; ++j) {
+        t += (Sa[i][j] / Da2 + Sb[i][j] / Db2) * g[j];
+        o.kS += p->m * (fabs(Sa[i][j]) / Da2 + fabs(Sb[i][j]) / Db2) * fabs(g[j]) * kc;
+      }
       o.AS[i] += p->m * t;
-      o.kS += fabs(p->m * t);
     }
     double vg = v[0] * g[0] + v[1] * g[1] + v[2] * g[2];
     double cu = p->m * (pia + 0.5 * Pi) * vg;
     o.udot += cu;
-    o.kU += fabs(cu);
+    o.kU += p->m * (fabs(pia) + 0.5 * fabs(Pi)) * (fabs(v[0] * g[0]) + fabs(v[1] * g[1]) + fabs(v[2] * g[2])) * kc;
   }
   return o;
 }

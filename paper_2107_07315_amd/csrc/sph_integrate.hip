@@ -1,0 +1,132 @@
+// Kick-drift-kick time integration with the solid-model updates of section "Solid SPH
+// Equations": von Mises yield scaling after every stress update and the maximum-strain breaking
+// test eps = lambda_max(S) / E, E = 9 B mu / (3 B + mu).  Memory-bound elementwise kernels.
+#include "sph_internal.h"
+
+namespace {
+
+constexpr int kB = 256;
+
+struct KdkArgs {
+  sph_params p;
+  int64_t n;
+  int64_t hstride;  // stride of the half-step arrays (capacity)
+  double dt;
+  double* x; double* y; double* z;
+  double* vx; double* vy; double* vz;
+  double* u; double* h; double* S;
+  const double* ax; const double* ay; const double* az;
+  const double* dudt; const double* dSdt;
+  uint8_t* broken; const int8_t* type;
+  const double* D; const double* mu; const double* B; const double* Y0;
+  double* half;
+  const int32_t* star; const StarInfo* stars;
+  DevStatus* status;
+};
+
+__device__ __forceinline__ double wrap(double q, int periodic, double box) {
+  if (periodic) {
+    if (q >= box) q -= box;
+    else if (q < 0.0) q += box;
+  }
+  return q;
+}
+
+// half kick, drift, and predictors (velocity, energy, yielded stress) for the evaluation
+__global__ __launch_bounds__(kB) void k_kick_drift(KdkArgs K) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= K.n) return;
+  const double hdt = 0.5 * K.dt;
+  const int64_t n = K.n, hs = K.hstride;
+  double* H = K.half;
+  double vh[3] = {K.vx[a] + hdt * K.ax[a], K.vy[a] + hdt * K.ay[a], K.vz[a] + hdt * K.az[a]};
+  double uh = K.u[a] + hdt * K.dudt[a];
+  double s[6];
+  for (int c = 0; c < 6; ++c) {
+    double sh = K.S[c * n + a] + hdt * K.dSdt[c * n + a];
+    H[(4 + c) * hs + a] = sh;
+    s[c] = sh + hdt * K.dSdt[c * n + a];
+  }
+  H[0 * hs + a] = vh[0];
+  H[1 * hs + a] = vh[1];
+  H[2 * hs + a] = vh[2];
+  H[3 * hs + a] = uh;
+  K.x[a] = wrap(K.x[a] + K.dt * vh[0], K.p.periodic, K.p.box);
+  K.y[a] = wrap(K.y[a] + K.dt * vh[1], K.p.periodic, K.p.box);
+  K.z[a] = wrap(K.z[a] + K.dt * vh[2], K.p.periodic, K.p.box);
+  K.vx[a] = vh[0] + hdt * K.ax[a];
+  K.vy[a] = vh[1] + hdt * K.ay[a];
+  K.vz[a] = vh[2] + hdt * K.az[a];
+  K.u[a] = uh + hdt * K.dudt[a];
+  yield_scale(K.p.yield_mode, K.Y0[a], s);
+  for (int c = 0; c < 6; ++c) K.S[c * n + a] = s[c];
+}
+
+// second half kick, yield, breaking and the adaptive smoothing length
+__global__ __launch_bounds__(kB) void k_kick_final(KdkArgs K) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= K.n) return;
+  const double hdt = 0.5 * K.dt;
+  const int64_t n = K.n, hs = K.hstride;
+  const double* H = K.half;
+  K.vx[a] = H[0 * hs + a] + hdt * K.ax[a];
+  K.vy[a] = H[1 * hs + a] + hdt * K.ay[a];
+  K.vz[a] = H[2 * hs + a] + hdt * K.az[a];
+  K.u[a] = H[3 * hs + a] + hdt * K.dudt[a];
+  double s[6];
+  for (int c = 0; c < 6; ++c) s[c] = H[(4 + c) * hs + a] + hdt * K.dSdt[c * n + a];
+  yield_scale(K.p.yield_mode, K.Y0[a], s);
+  if (K.p.break_mode != SPH_BREAK_OFF && K.type[a] == 1 && !K.broken[a]) {
+    const double mu = K.mu[a], Bm = K.B[a];
+    if (mu > 0.0) {
+      const double E = 9.0 * Bm * mu / (3.0 * Bm + mu);
+      const double lm = lambda_max_sym(s[0], s[1], s[2], s[3], s[4], s[5]);
+      if (lm / E >= K.p.eps_break) {
+        K.broken[a] = 1;
+        if (K.p.break_mode == SPH_BREAK_FLUIDIZE)
+          for (int c = 0; c < 6; ++c) s[c] = 0.0;
+      }
+    }
+  }
+  for (int c = 0; c < 6; ++c) K.S[c * n + a] = s[c];
+  if (K.p.h_mode == SPH_H_ADAPTIVE) {
+    double m = (K.star && K.stars) ? K.stars[K.star[a]].m : K.p.m;
+    K.h[a] = K.p.eta * cbrt(m / K.D[a]);
+  }
+}
+
+KdkArgs make_kdk(sph_ctx* c, sph_state* st, double dt) {
+  KdkArgs K;
+  K.p = c->p;
+  K.n = st->n;
+  K.hstride = c->capacity;
+  K.dt = dt;
+  K.x = st->x; K.y = st->y; K.z = st->z;
+  K.vx = st->vx; K.vy = st->vy; K.vz = st->vz;
+  K.u = st->u; K.h = st->h; K.S = st->S;
+  K.ax = st->ax; K.ay = st->ay; K.az = st->az;
+  K.dudt = st->dudt; K.dSdt = st->dSdt;
+  K.broken = st->broken; K.type = st->type;
+  K.D = st->D; K.mu = c->mu; K.B = c->B; K.Y0 = c->Y0;
+  K.half = c->half;
+  K.star = c->stars ? st->star : nullptr;
+  K.stars = c->stars;
+  K.status = c->status;
+  return K;
+}
+
+}  // namespace
+
+sph_status launch_kick_drift(sph_ctx* c, sph_state* st, double dt) {
+  KdkArgs K = make_kdk(c, st, dt);
+  hipLaunchKernelGGL(k_kick_drift, dim3(grid_for(st->n, kB)), dim3(kB), 0, c->stream, K);
+  HIP_TRY(hipGetLastError());
+  return SPH_OK;
+}
+
+sph_status launch_kick_final(sph_ctx* c, sph_state* st, double dt) {
+  KdkArgs K = make_kdk(c, st, dt);
+  hipLaunchKernelGGL(k_kick_final, dim3(grid_for(st->n, kB)), dim3(kB), 0, c->stream, K);
+  HIP_TRY(hipGetLastError());
+  return SPH_OK;
+}

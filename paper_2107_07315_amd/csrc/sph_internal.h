@@ -1,0 +1,264 @@
+// Internal declarations of the gfx950 SPH particle loop: device helpers shared by the
+// kernel files, the context struct and the host launchers.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/sph.h"
+
+#define SPH_MAX_LEV 4
+#define SPH_PI 3.14159265358979323846
+
+// Multi-level cell grid.  Particles are binned into levels by smoothing length
+// (level l holds h in [hmin 2^l, hmin 2^(l+1)), the top level takes the rest); each level has
+// its own uniform grid whose cells are addressed by a Morton code inside a per-level block of
+// 2^(3 bits) entries starting at base[l].  All fields are computed on the device.
+struct GridInfo {
+  unsigned long long enc_lo[3], enc_hi[3];   // order-preserving encodings for atomics
+  unsigned long long enc_hmin, enc_hmax;
+  unsigned long long hlev_bits[SPH_MAX_LEV]; // max h per level (positive-double bits)
+  double lo[3];
+  double hmin, hmax;
+  double hlev[SPH_MAX_LEV];
+  double cell[SPH_MAX_LEV];
+  int32_t dims[SPH_MAX_LEV][3];
+  int32_t bits[SPH_MAX_LEV];
+  uint32_t base[SPH_MAX_LEV + 1];
+  int32_t nlev;
+  int32_t periodic;
+  double box;
+};
+
+// Per-star parameters of an ensemble (centre of the star's background, particle mass and
+// crust shear-modulus factor).
+struct StarInfo {
+  double cx, cy, cz, m, mu_pfactor, pad[3];
+};
+
+// Device status word: first error code and the particle that raised it.
+struct DevStatus {
+  int32_t code;
+  int32_t particle;
+};
+
+__device__ __forceinline__ void latch_error(DevStatus* s, int code, int particle) {
+  if (atomicCAS(&s->code, 0, code) == 0) s->particle = particle;
+}
+
+// ---- order-preserving double <-> uint64 (for atomic min/max of signed doubles) ------------
+__device__ __forceinline__ unsigned long long enc_double(double v) {
+  unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
+}
+__host__ __device__ __forceinline__ double dec_double(unsigned long long e) {
+  unsigned long long b = (e & 0x8000000000000000ull) ? (e & 0x7fffffffffffffffull) : ~e;
+  double d;
+  __builtin_memcpy(&d, &b, 8);
+  return d;
+}
+
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {  // 10 bits -> every third bit
+  v &= 0x3ffu;
+  v = (v | (v << 16)) & 0x030000ffu;
+  v = (v | (v << 8)) & 0x0300f00fu;
+  v = (v | (v << 4)) & 0x030c30c3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+__device__ __forceinline__ int particle_level(double h, const GridInfo& g) {
+  double ratio = h / g.hmin;
+  int l = 0;
+  while (l < g.nlev - 1 && ratio >= (double)(2 << l)) ++l;
+  return l;
+}
+
+// ---- geometry ---------------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ R min_image(R d, int periodic, R box) {
+  if (periodic) {
+    if (d > (R)0.5 * box) d -= box;
+    else if (d < -(R)0.5 * box) d += box;
+  }
+  return d;
+}
+
+// Exact FP64 neighbour decision r^2 < (h_a + h_b)^2 with every operation rounded separately in
+// the order ((dx dx + dy dy) + dz dz); contraction is switched off for this scope.
+__device__ __forceinline__ bool neighbour_test(double dx, double dy, double dz, double ha, double hb) {
+#pragma clang fp contract(off)
+  double r2 = (dx * dx + dy * dy) + dz * dz;
+  double H = ha + hb;
+  return r2 < H * H;
+}
+
+// ---- Wendland kernels with support 2 h_ab: W and F such that grad_a W = F (x_a - x_b) -------
+template <typename R>
+__device__ __forceinline__ void wendland(int kernel, R r, R hab, R& W, R& F) {
+  R ih = (R)1 / hab;
+  R q = r * ih;
+  if (q >= (R)2) { W = 0; F = 0; return; }
+  R t = (R)1 - (R)0.5 * q;
+  R ih2 = ih * ih, ih3 = ih2 * ih, ih5 = ih3 * ih2;
+  if (kernel == SPH_WC4) {
+    R t2 = t * t, t5 = t2 * t2 * t;
+    W = (R)(495.0 / (256.0 * SPH_PI)) * ih3 * t5 * t * ((R)1 + (R)3 * q + (R)(35.0 / 12.0) * q * q);
+    F = -(R)(1155.0 / (128.0 * SPH_PI)) * ih5 * t5 * ((R)1 + (R)2.5 * q);
+  } else {
+    R t3 = t * t * t;
+    W = (R)(21.0 / (16.0 * SPH_PI)) * ih3 * t3 * t * ((R)1 + (R)2 * q);
+    F = -(R)(105.0 / (16.0 * SPH_PI)) * ih5 * t3;
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ R wendland_self(int kernel, R h) {
+  R ih = (R)1 / h;
+  R ih3 = ih * ih * ih;
+  return kernel == SPH_WC4 ? (R)(495.0 / (256.0 * SPH_PI)) * ih3 : (R)(21.0 / (16.0 * SPH_PI)) * ih3;
+}
+
+// ---- static isotropic background ------------------------------------------------------------
+struct Metric {
+  double alpha, dalpha, psi, dpsi, n[3];
+};
+
+__device__ __forceinline__ Metric metric_at(const sph_params& p, double x, double y, double z) {
+  Metric g;
+  double rb = sqrt(x * x + y * y + z * z);
+  if (rb > 0.0) {
+    double ir = 1.0 / rb;
+    g.n[0] = x * ir; g.n[1] = y * ir; g.n[2] = z * ir;
+  } else {
+    g.n[0] = g.n[1] = g.n[2] = 0.0;
+  }
+  double Rbar = p.bg_dr * (double)(p.bg_n - 1);
+  if (rb <= Rbar) {
+    double t = rb / p.bg_dr;
+    int i = (int)floor(t);
+    if (i > p.bg_n - 2) i = p.bg_n - 2;
+    double f = t - (double)i;
+    const double* T = p.bg;
+    int nb = p.bg_n;
+    g.alpha = (1.0 - f) * T[i] + f * T[i + 1];
+    g.dalpha = (1.0 - f) * T[nb + i] + f * T[nb + i + 1];
+    g.psi = (1.0 - f) * T[2 * nb + i] + f * T[2 * nb + i + 1];
+    g.dpsi = (1.0 - f) * T[3 * nb + i] + f * T[3 * nb + i + 1];
+  } else {
+    double a = p.bg_M / (2.0 * rb);
+    g.psi = 1.0 + a;
+    g.alpha = (1.0 - a) / (1.0 + a);
+    g.dpsi = -a / rb;
+    g.dalpha = 2.0 / ((1.0 + a) * (1.0 + a)) * a / rb;
+  }
+  return g;
+}
+
+// ---- symmetric 3x3 helpers (6 comps xx,yy,zz,xy,xz,yz) ----------------------------------------
+__device__ __forceinline__ double lambda_max_sym(double xx, double yy, double zz, double xy, double xz,
+                                                 double yz) {
+  double q = (xx + yy + zz) * (1.0 / 3.0);
+  double off2 = xy * xy + xz * xz + yz * yz;
+  double a = xx - q, b = yy - q, c = zz - q;
+  double p2 = a * a + b * b + c * c + 2.0 * off2;
+  if (!(p2 > 0.0)) return q;
+  double p = sqrt(p2 / 6.0);
+  double ip = 1.0 / p;
+  a *= ip; b *= ip; c *= ip;
+  double e = xy * ip, f = xz * ip, g = yz * ip;
+  double det = a * (b * c - g * g) - e * (e * c - g * f) + f * (e * g - b * f);
+  double r = 0.5 * det;
+  r = r < -1.0 ? -1.0 : (r > 1.0 ? 1.0 : r);
+  return q + 2.0 * p * cos(acos(r) * (1.0 / 3.0));
+}
+
+// von Mises scaling: f = min(Y0^2/sigma_v^2, 1) (PAPER) or min(Y0/sigma_v, 1) (RADIAL)
+__device__ __forceinline__ void yield_scale(int mode, double Y0, double* s) {
+  double J = s[0] * s[0] + s[1] * s[1] + s[2] * s[2] + 2.0 * (s[3] * s[3] + s[4] * s[4] + s[5] * s[5]);
+  double sv2 = 1.5 * J;
+  if (!(sv2 > 0.0)) return;
+  double f = (mode == SPH_YIELD_RADIAL) ? Y0 / sqrt(sv2) : Y0 * Y0 / sv2;
+  if (f < 1.0)
+    for (int k = 0; k < 6; ++k) s[k] *= f;
+}
+
+// ---- context ----------------------------------------------------------------------------------
+struct SortScratch {
+  uint32_t *keys_alt, *vals_alt;
+  uint32_t* hist;        // 256 * max_blocks
+  int max_blocks;
+};
+
+struct StageTimer {
+  std::vector<hipEvent_t> ev;   // pairs (start, stop)
+  size_t used = 0;
+};
+
+struct sph_ctx {
+  sph_params p;
+  hipStream_t stream;
+  int64_t capacity;
+  int64_t n;            // particles at the last build
+  int device;
+  int32_t gen;          // stage order: 1 cells, 2 density, 3 stress, 4 forces
+  int32_t identity_perm;
+  int32_t steps_since_sort;
+  // grid and sort
+  GridInfo* grid;       // device
+  uint32_t *keys, *vals;  // sorted keys and permutation (sorted position -> particle index)
+  int32_t *cell_start, *cell_end;
+  int64_t max_cells;
+  SortScratch sort;
+  // neighbour lists: entry k of particle a at ((a>>6)*cap + k)*64 + (a&63)
+  int32_t* nbr;
+  int32_t* nbr_count;
+  int32_t cap;
+  // packed gather records (FP64 and FP32 variants)
+  double4* pos4;        // x, y, z, h
+  double4* fv;          // vx, vy, vz, cs
+  double2* fa;          // P/D^2, D (negative D marks a particle that carries deviatoric stress)
+  double* sig;          // S/D^2, 6*cap
+  float4* pos4f;        // x, y, z, h (relative to the star centre)
+  float4* fvf;
+  float2* faf;
+  float* sigf;
+  // internal per-particle fields
+  double *mu, *Y0, *B, *sdot;
+  // half-step copies for kick-drift-kick
+  double* half;         // 10*cap: vx, vy, vz, u, S[6]
+  double* tmp;          // permutation staging, 8 bytes * cap
+  // ensemble
+  StarInfo* stars;      // device, may be null
+  int32_t nstars;
+  // status
+  DevStatus* status;    // device
+  // timing
+  int32_t timing;
+  StageTimer timers[5];
+  // MLP surrogate (optional)
+  void* mlp;
+};
+
+// ---- host launchers (one per kernel file) ------------------------------------------------------
+sph_status sph_sort_pairs(sph_ctx* c, uint32_t* keys, uint32_t* vals, int64_t n);
+sph_status sph_rebin(sph_ctx* c, sph_state* st, bool permute);
+sph_status launch_density(sph_ctx* c, sph_state* st);
+sph_status launch_stress(sph_ctx* c, sph_state* st);
+sph_status launch_forces(sph_ctx* c, sph_state* st);
+sph_status launch_kick_drift(sph_ctx* c, sph_state* st, double dt);
+sph_status launch_kick_final(sph_ctx* c, sph_state* st, double dt);
+sph_status launch_pack(sph_ctx* c, sph_state* st);
+
+enum { TIMER_CELLS = 0, TIMER_DENSITY = 1, TIMER_STRESS = 2, TIMER_FORCES = 3, TIMER_KDK = 4 };
+void timer_begin(sph_ctx* c, int which);
+void timer_end(sph_ctx* c, int which);
+
+#define HIP_TRY(expr)                                   \
+  do {                                                  \
+    hipError_t _e = (expr);                             \
+    if (_e != hipSuccess) return SPH_E_HIP;             \
+  } while (0)
+
+static inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }

@@ -1,0 +1,425 @@
+// Pair passes of the particle loop: density (+ EoS epilogue), velocity gradient / stress rate,
+// and momentum/energy forces (+ fixed-background epilogue).
+//
+// One thread per target particle; a wavefront holds 64 consecutive particles of the cell order
+// and walks their neighbour lists in lockstep (the lists are interleaved per wavefront, so each
+// list read is one 256-byte segment).  Neighbour data is gathered from packed records written
+// by the previous pass.  The pair arithmetic is templated on the pair precision R: double in
+// the FP64 path, float in the mixed-precision path; epilogues (metric, EoS, GR terms) are FP64.
+#include "sph_internal.h"
+
+namespace {
+
+constexpr int kB = 256;
+
+template <typename R>
+__device__ __forceinline__ R wendland_F(int kernel, R r, R hab) {
+  R ih = (R)1 / hab;
+  R q = r * ih;
+  if (q >= (R)2) return (R)0;
+  R t = (R)1 - (R)0.5 * q;
+  R ih2 = ih * ih, ih5 = ih2 * ih2 * ih;
+  if (kernel == SPH_WC4) {
+    R t2 = t * t;
+    return -(R)(1155.0 / (128.0 * SPH_PI)) * ih5 * t2 * t2 * t * ((R)1 + (R)2.5 * q);
+  }
+  return -(R)(105.0 / (16.0 * SPH_PI)) * ih5 * t * t * t;
+}
+
+template <typename R> struct Rec;
+template <> struct Rec<double> {
+  using P4 = double4;
+  using V4 = double4;
+  using A2 = double2;
+};
+template <> struct Rec<float> {
+  using P4 = float4;
+  using V4 = float4;
+  using A2 = float2;
+};
+
+struct PassArgs {
+  sph_params p;
+  int64_t n;
+  int cap;
+  const int32_t* __restrict__ nbr;
+  const int32_t* __restrict__ cnt;
+  const int32_t* __restrict__ star;
+  const StarInfo* __restrict__ stars;
+  DevStatus* status;
+};
+
+__device__ __forceinline__ double particle_mass(const PassArgs& A, int64_t a) {
+  return (A.star && A.stars) ? A.stars[A.star[a]].m : A.p.m;
+}
+__device__ __forceinline__ void star_centre(const PassArgs& A, int64_t a, double& cx, double& cy, double& cz) {
+  cx = cy = cz = 0.0;
+  if (A.star && A.stars) {
+    StarInfo s = A.stars[A.star[a]];
+    cx = s.cx; cy = s.cy; cz = s.cz;
+  }
+}
+
+// ---- equation of state -------------------------------------------------------------------------
+__device__ __forceinline__ int eos_eval(const sph_params& p, double rho, double u, double& P, double& cs2) {
+  if (p.eos == SPH_EOS_TABLE || p.eos == SPH_EOS_MLP) {
+    if (!(rho > 0.0) || !(u > 0.0)) return SPH_E_EOS_DOMAIN;
+    double fr = (log(rho) - p.tab_lnr0) / p.tab_dlnr;
+    double fu = (log(u) - p.tab_lnu0) / p.tab_dlnu;
+    if (!(fr >= 0.0) || !(fu >= 0.0) || fr > (double)(p.tab_nr - 1) || fu > (double)(p.tab_nu - 1))
+      return SPH_E_EOS_DOMAIN;
+    int i = (int)floor(fr), j = (int)floor(fu);
+    i = i > p.tab_nr - 2 ? p.tab_nr - 2 : i;
+    j = j > p.tab_nu - 2 ? p.tab_nu - 2 : j;
+    double a = fr - (double)i, b = fu - (double)j;
+    int64_t o = (int64_t)i * p.tab_nu + j;
+    double v[2];
+    const double* T[2] = {p.tab_lnP, p.tab_lncs2};
+    for (int k = 0; k < 2; ++k) {
+      double f00 = T[k][o], f01 = T[k][o + 1], f10 = T[k][o + p.tab_nu], f11 = T[k][o + p.tab_nu + 1];
+      if (!isfinite(f00) || !isfinite(f01) || !isfinite(f10) || !isfinite(f11)) return SPH_E_EOS_DOMAIN;
+      v[k] = (1.0 - a) * ((1.0 - b) * f00 + b * f01) + a * ((1.0 - b) * f10 + b * f11);
+    }
+    P = exp(v[0]);
+    cs2 = exp(v[1]);
+    return 0;
+  }
+  P = (p.gamma - 1.0) * rho * u;
+  cs2 = (p.background == SPH_TOV) ? p.gamma * P / (rho * (1.0 + u + P / rho)) : p.gamma * P / rho;
+  return 0;
+}
+
+// ---- density --------------------------------------------------------------------------------
+struct DensOut {
+  double *D, *rho, *P, *cs, *mu, *Y0, *B;
+  double4* fv;
+  double2* fa;
+  double* sig;
+  float4* fvf;
+  float2* faf;
+  float* sigf;
+};
+
+template <typename R>
+__global__ __launch_bounds__(kB) void k_density(PassArgs A, const typename Rec<R>::P4* __restrict__ pos,
+                                                const double4* __restrict__ pos64, const double* __restrict__ vx, const double* __restrict__ vy,
+                                                const double* __restrict__ vz, const double* __restrict__ u,
+                                                const double* __restrict__ S, const int8_t* __restrict__ type,
+                                                const uint8_t* __restrict__ broken, DensOut O) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= A.n) return;
+  const sph_params& p = A.p;
+  const typename Rec<R>::P4 pa = pos[a];
+  const int periodic = p.periodic;
+  const R box = (R)p.box;
+  R sum = wendland_self<R>(p.kernel, pa.w);
+  const int32_t* lst = A.nbr + ((a >> 6) * (int64_t)A.cap) * 64 + (a & 63);
+  const int nn = A.cnt[a];
+  for (int k = 0; k < nn; ++k) {
+    const int32_t b = lst[(int64_t)k * 64];
+    const typename Rec<R>::P4 pb = pos[b];
+    R dx = min_image<R>(pa.x - pb.x, periodic, box);
+    R dy = min_image<R>(pa.y - pb.y, periodic, box);
+    R dz = min_image<R>(pa.z - pb.z, periodic, box);
+    R r = sqrt(dx * dx + dy * dy + dz * dz);
+    R W, F;
+    wendland<R>(p.kernel, r, (R)0.5 * (pa.w + pb.w), W, F);
+    sum += W;
+  }
+  const double m = particle_mass(A, a);
+  const double D = m * (double)sum;
+  // epilogue in FP64: rest-mass density from D = rho psi^6 W_L, EoS, shear modulus, yield stress
+  const double va[3] = {vx[a], vy[a], vz[a]};
+  double rho = D, hfac = 1.0;
+  if (p.background == SPH_TOV) {
+    double cx, cy, cz;
+    star_centre(A, a, cx, cy, cz);
+    const double4 p64 = pos64[a];   // the background is always evaluated in FP64
+    Metric g = metric_at(p, p64.x - cx, p64.y - cy, p64.z - cz);
+    double v2 = va[0] * va[0] + va[1] * va[1] + va[2] * va[2];
+    double psi2 = g.psi * g.psi, psi4 = psi2 * psi2;
+    double WL = 1.0 / sqrt(1.0 - psi4 * v2 / (g.alpha * g.alpha));
+    rho = D / (psi4 * psi2 * WL);
+  }
+  double P, cs2;
+  int e = eos_eval(p, rho, u[a], P, cs2);
+  if (e) latch_error(A.status, e, (int)a);
+  if (p.background == SPH_TOV) hfac = 1.0 + u[a] + P / rho;
+  const double cs = sqrt(cs2);
+  const double Bm = rho * hfac * cs2;
+  const bool solid = type[a] == 1 && !(broken[a] && p.break_mode == SPH_BREAK_FLUIDIZE);
+  double mu = 0.0;
+  if (solid) {
+    double fac = p.mu_pfactor;
+    if (A.star && A.stars) fac = A.stars[A.star[a]].mu_pfactor;
+    mu = (p.mu_mode == SPH_MU_PFACTOR) ? fac * P : p.mu_const;
+  }
+  const double E = mu > 0.0 ? 9.0 * Bm * mu / (3.0 * Bm + mu) : 0.0;
+  O.D[a] = D;
+  O.rho[a] = rho;
+  O.P[a] = P;
+  O.cs[a] = cs;
+  O.mu[a] = mu;
+  O.B[a] = Bm;
+  O.Y0[a] = (p.y0_mode == SPH_Y0_EFACTOR) ? p.y0_over_E * E : p.y0_const;
+  const double iD2 = 1.0 / (D * D);
+  const double pi = P * iD2;
+  const bool stressed = solid;
+  const int64_t n = A.n;
+  if (sizeof(R) == 8) {
+    O.fv[a] = make_double4(va[0], va[1], va[2], cs);
+    O.fa[a] = make_double2(pi, stressed ? -D : D);
+    for (int c = 0; c < 6; ++c) O.sig[c * n + a] = S[c * n + a] * iD2;
+  } else {
+    O.fvf[a] = make_float4((float)va[0], (float)va[1], (float)va[2], (float)cs);
+    O.faf[a] = make_float2((float)pi, stressed ? -(float)D : (float)D);
+    for (int c = 0; c < 6; ++c) O.sigf[c * n + a] = (float)(S[c * n + a] * iD2);
+  }
+  if (!isfinite(D) || !isfinite(P) || !isfinite(cs)) latch_error(A.status, SPH_E_NONFINITE, (int)a);
+}
+
+// ---- velocity gradient and stress rate ---------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(kB) void k_stress(PassArgs A, const typename Rec<R>::P4* __restrict__ pos,
+                                               const typename Rec<R>::V4* __restrict__ fv,
+                                               const typename Rec<R>::A2* __restrict__ fa,
+                                               const double* __restrict__ S, const double* __restrict__ mu,
+                                               double* __restrict__ dSdt, double* __restrict__ sdot) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= A.n) return;
+  const int64_t n = A.n;
+  const typename Rec<R>::A2 faa = fa[a];
+  if (!(faa.y < 0)) {  // fluid particle (or fluidized): no deviatoric stress evolution
+    for (int c = 0; c < 6; ++c) dSdt[c * n + a] = 0.0;
+    sdot[a] = 0.0;
+    return;
+  }
+  const sph_params& p = A.p;
+  const typename Rec<R>::P4 pa = pos[a];
+  const typename Rec<R>::V4 va = fv[a];
+  const int periodic = p.periodic;
+  const R box = (R)p.box;
+  R G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  const int32_t* lst = A.nbr + ((a >> 6) * (int64_t)A.cap) * 64 + (a & 63);
+  const int nn = A.cnt[a];
+  for (int k = 0; k < nn; ++k) {
+    const int32_t b = lst[(int64_t)k * 64];
+    const typename Rec<R>::P4 pb = pos[b];
+    const typename Rec<R>::V4 vb = fv[b];
+    R d[3] = {min_image<R>(pa.x - pb.x, periodic, box), min_image<R>(pa.y - pb.y, periodic, box),
+              min_image<R>(pa.z - pb.z, periodic, box)};
+    R r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    R F = wendland_F<R>(p.kernel, r, (R)0.5 * (pa.w + pb.w));
+    R g[3] = {F * d[0], F * d[1], F * d[2]};
+    R v[3] = {vb.x - va.x, vb.y - va.y, vb.z - va.z};
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) G[i][j] += v[i] * g[j];
+  }
+  const double m = particle_mass(A, a);
+  const double D = -(double)faa.y;  // stressed particles store -D
+  const double iD2 = m / (2.0 * D);
+  double ed[3][3], Rd[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      ed[i][j] = ((double)G[i][j] + (double)G[j][i]) * iD2;   // strain rate, eq. solid5
+      Rd[i][j] = ((double)G[i][j] - (double)G[j][i]) * iD2;   // rotation rate, eq. solid6
+    }
+  double Sm[3][3];
+  Sm[0][0] = S[a]; Sm[1][1] = S[n + a]; Sm[2][2] = S[2 * n + a];
+  Sm[0][1] = Sm[1][0] = S[3 * n + a];
+  Sm[0][2] = Sm[2][0] = S[4 * n + a];
+  Sm[1][2] = Sm[2][1] = S[5 * n + a];
+  const double tr3 = (ed[0][0] + ed[1][1] + ed[2][2]) * (1.0 / 3.0);
+  const double tmu = 2.0 * mu[a];
+  const double sgn = (p.rotation == SPH_ROT_LITERAL) ? -1.0 : 1.0;
+  double dS[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double RS = Rd[i][0] * Sm[0][j] + Rd[i][1] * Sm[1][j] + Rd[i][2] * Sm[2][j];
+      double SR = Sm[i][0] * Rd[0][j] + Sm[i][1] * Rd[1][j] + Sm[i][2] * Rd[2][j];
+      dS[i][j] = tmu * (ed[i][j] - (i == j ? tr3 : 0.0)) + sgn * (RS - SR);   // eq. solid4
+    }
+  dSdt[a] = dS[0][0];
+  dSdt[n + a] = dS[1][1];
+  dSdt[2 * n + a] = dS[2][2];
+  dSdt[3 * n + a] = dS[0][1];
+  dSdt[4 * n + a] = dS[0][2];
+  dSdt[5 * n + a] = dS[1][2];
+  double se = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) se += Sm[i][j] * ed[i][j];
+  sdot[a] = se / D;   // stress work S^ij epsdot^ij / rho of eq. solid3
+}
+
+// ---- forces -----------------------------------------------------------------------------------
+struct ForceOut {
+  double *ax, *ay, *az, *dudt;
+};
+
+template <typename R>
+__global__ __launch_bounds__(kB) void k_forces(PassArgs A, const typename Rec<R>::P4* __restrict__ pos,
+                                               const typename Rec<R>::V4* __restrict__ fv,
+                                               const typename Rec<R>::A2* __restrict__ fa,
+                                               const R* __restrict__ sig, const double4* __restrict__ pos64,
+                                               const double* __restrict__ u, const double* __restrict__ P,
+                                               const double* __restrict__ rho, const double* __restrict__ sdot,
+                                               ForceOut O) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= A.n) return;
+  const int64_t n = A.n;
+  const sph_params& p = A.p;
+  const typename Rec<R>::P4 pa = pos[a];
+  const typename Rec<R>::V4 va = fv[a];
+  const typename Rec<R>::A2 faa = fa[a];
+  const bool a_st = faa.y < 0;
+  const R Da = a_st ? -faa.y : faa.y;
+  const R pia = faa.x;
+  R sa[6] = {0, 0, 0, 0, 0, 0};
+  if (a_st)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) sa[c] = sig[c * n + a];
+  const int periodic = p.periodic;
+  const R box = (R)p.box;
+  const R alpha_v = (R)p.visc_alpha, beta_v = (R)p.visc_beta, eps_v = (R)p.visc_eps;
+  R AP[3] = {0, 0, 0}, AS[3] = {0, 0, 0}, ud = 0;
+  const int32_t* lst = A.nbr + ((a >> 6) * (int64_t)A.cap) * 64 + (a & 63);
+  const int nn = A.cnt[a];
+  for (int k = 0; k < nn; ++k) {
+    const int32_t b = lst[(int64_t)k * 64];
+    const typename Rec<R>::P4 pb = pos[b];
+    const typename Rec<R>::V4 vb = fv[b];
+    const typename Rec<R>::A2 fab = fa[b];
+    R d[3] = {min_image<R>(pa.x - pb.x, periodic, box), min_image<R>(pa.y - pb.y, periodic, box),
+              min_image<R>(pa.z - pb.z, periodic, box)};
+    R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    R r = sqrt(r2);
+    R hab = (R)0.5 * (pa.w + pb.w);
+    R F = wendland_F<R>(p.kernel, r, hab);
+    R g[3] = {F * d[0], F * d[1], F * d[2]};
+    R v[3] = {va.x - vb.x, va.y - vb.y, va.z - vb.z};
+    R vr = v[0] * d[0] + v[1] * d[1] + v[2] * d[2];
+    const bool b_st = fab.y < 0;
+    const R Db = b_st ? -fab.y : fab.y;
+    R Pi = 0;
+    if (vr < 0) {   // Monaghan viscosity on approaching pairs
+      R muab = hab * vr / (r2 + eps_v * hab * hab);
+      R cbar = (R)0.5 * (va.w + vb.w);
+      R Dbar = (R)0.5 * (Da + Db);
+      Pi = (-alpha_v * cbar * muab + beta_v * muab * muab) / Dbar;
+    }
+    R cP = pia + fab.x + Pi;
+    AP[0] += cP * g[0];
+    AP[1] += cP * g[1];
+    AP[2] += cP * g[2];
+    ud += (pia + (R)0.5 * Pi) * (v[0] * g[0] + v[1] * g[1] + v[2] * g[2]);
+    if (a_st || b_st) {
+      R s[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) s[c] = sa[c] + (b_st ? sig[c * n + b] : (R)0);
+      AS[0] += s[0] * g[0] + s[3] * g[1] + s[4] * g[2];
+      AS[1] += s[3] * g[0] + s[1] * g[1] + s[5] * g[2];
+      AS[2] += s[4] * g[0] + s[5] * g[1] + s[2] * g[2];
+    }
+  }
+  const double m = particle_mass(A, a);
+  double APd[3] = {m * (double)AP[0], m * (double)AP[1], m * (double)AP[2]};
+  double ASd[3] = {m * (double)AS[0], m * (double)AS[1], m * (double)AS[2]};
+  double acc[3];
+  if (p.background == SPH_TOV) {
+    // trajectory equation, zero shift, gamma_ij = psi^4 delta_ij; pressure coefficient
+    // 1/(W~^2 rho h) so that a TOV star is static; grad P ~= D A^P
+    double cx, cy, cz;
+    star_centre(A, a, cx, cy, cz);
+    const double4 p64 = pos64[a];
+    Metric g = metric_at(p, p64.x - cx, p64.y - cy, p64.z - cz);
+    const double vv[3] = {(double)va.x, (double)va.y, (double)va.z};
+    const double psi2 = g.psi * g.psi, psi4 = psi2 * psi2, psi6 = psi4 * psi2;
+    const double v2 = vv[0] * vv[0] + vv[1] * vv[1] + vv[2] * vv[2];
+    const double WL = 1.0 / sqrt(1.0 - psi4 * v2 / (g.alpha * g.alpha));
+    const double hen = 1.0 + u[a] + P[a] / rho[a];
+    const double fP = g.alpha * g.alpha * psi6 / (WL * hen);
+    const double nv = g.n[0] * vv[0] + g.n[1] * vv[1] + g.n[2] * vv[2];
+    const double c0 = 2.0 * g.dalpha / g.alpha * nv;
+    const double cg = 4.0 * psi2 * g.psi * g.dpsi;
+    const double ipsi4 = 1.0 / psi4;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      double Gi = g.alpha * g.dalpha * g.n[i] + cg * (nv * vv[i] - 0.5 * v2 * g.n[i]);
+      acc[i] = -(fP * APd[i] + Gi) * ipsi4 + c0 * vv[i] + ASd[i];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) acc[i] = -APd[i] + ASd[i];   // eq. solid2
+  }
+  const double du = m * (double)ud + sdot[a];                  // eq. solid3
+  O.ax[a] = acc[0];
+  O.ay[a] = acc[1];
+  O.az[a] = acc[2];
+  O.dudt[a] = du;
+  if (!isfinite(acc[0]) || !isfinite(acc[1]) || !isfinite(acc[2]) || !isfinite(du))
+    latch_error(A.status, SPH_E_NONFINITE, (int)a);
+}
+
+PassArgs make_args(sph_ctx* c, sph_state* st) {
+  PassArgs A;
+  A.p = c->p;
+  A.n = st->n;
+  A.cap = c->cap;
+  A.nbr = c->nbr;
+  A.cnt = c->nbr_count;
+  A.star = c->stars ? st->star : nullptr;
+  A.stars = c->stars;
+  A.status = c->status;
+  return A;
+}
+
+}  // namespace
+
+sph_status launch_density(sph_ctx* c, sph_state* st) {
+  PassArgs A = make_args(c, st);
+  DensOut O{st->D, st->rho, st->P, st->cs, c->mu, c->Y0, c->B, c->fv, c->fa, c->sig, c->fvf, c->faf, c->sigf};
+  dim3 g(grid_for(st->n, kB)), b(kB);
+  if (c->p.precision == SPH_FP32)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_density<float>), g, b, 0, c->stream, A, c->pos4f, c->pos4, st->vx, st->vy,
+                       st->vz, st->u, st->S, st->type, st->broken, O);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_density<double>), g, b, 0, c->stream, A, c->pos4, c->pos4, st->vx, st->vy,
+                       st->vz, st->u, st->S, st->type, st->broken, O);
+  HIP_TRY(hipGetLastError());
+  return SPH_OK;
+}
+
+sph_status launch_stress(sph_ctx* c, sph_state* st) {
+  PassArgs A = make_args(c, st);
+  dim3 g(grid_for(st->n, kB)), b(kB);
+  if (c->p.precision == SPH_FP32)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stress<float>), g, b, 0, c->stream, A, c->pos4f, c->fvf, c->faf, st->S,
+                       c->mu, st->dSdt, c->sdot);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stress<double>), g, b, 0, c->stream, A, c->pos4, c->fv, c->fa, st->S,
+                       c->mu, st->dSdt, c->sdot);
+  HIP_TRY(hipGetLastError());
+  return SPH_OK;
+}
+
+sph_status launch_forces(sph_ctx* c, sph_state* st) {
+  PassArgs A = make_args(c, st);
+  ForceOut O{st->ax, st->ay, st->az, st->dudt};
+  dim3 g(grid_for(st->n, kB)), b(kB);
+  if (c->p.precision == SPH_FP32)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forces<float>), g, b, 0, c->stream, A, c->pos4f, c->fvf, c->faf, c->sigf,
+                       c->pos4, st->u, st->P, st->rho, c->sdot, O);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forces<double>), g, b, 0, c->stream, A, c->pos4, c->fv, c->fa, c->sig,
+                       c->pos4, st->u, st->P, st->rho, c->sdot, O);
+  HIP_TRY(hipGetLastError());
+  return SPH_OK;
+}

@@ -1,0 +1,252 @@
+"""ctypes binding of libsph (include/sph.h).
+
+Argument marshalling only: every stage runs in the HIP kernels of libsph.so.  PyTorch provides
+device memory (tensors) and the HIP stream.  Importing this module does not need a GPU; loading
+the library does, and any call fails loudly if the library or the GPU is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsph.so")
+
+STATUS = {0: "SPH_OK", 1: "SPH_E_ARG", 2: "SPH_E_HIP", 3: "SPH_E_OOM", 4: "SPH_E_ORDER",
+          5: "SPH_E_NGB_CAPACITY", 6: "SPH_E_NONFINITE", 7: "SPH_E_EOS_DOMAIN"}
+
+EXPORTED = ("sph_create", "sph_destroy", "sph_set_params", "sph_build_cells", "sph_density",
+            "sph_stress_rate", "sph_forces", "sph_step", "sph_sync", "sph_export_neighbours",
+            "sph_status_string", "sph_set_timing", "sph_get_timing")
+
+_dp = ctypes.c_void_p
+
+
+class SphParams(ctypes.Structure):
+    _fields_ = [
+        ("kernel", ctypes.c_int32), ("h_mode", ctypes.c_int32), ("background", ctypes.c_int32),
+        ("periodic", ctypes.c_int32), ("eta", ctypes.c_double), ("box", ctypes.c_double),
+        ("m", ctypes.c_double), ("bg", _dp), ("bg_n", ctypes.c_int32), ("bg_dr", ctypes.c_double),
+        ("bg_M", ctypes.c_double), ("visc_alpha", ctypes.c_double), ("visc_beta", ctypes.c_double),
+        ("visc_eps", ctypes.c_double), ("eos", ctypes.c_int32), ("gamma", ctypes.c_double),
+        ("tab_lnP", _dp), ("tab_lncs2", _dp), ("tab_nr", ctypes.c_int32), ("tab_nu", ctypes.c_int32),
+        ("tab_lnr0", ctypes.c_double), ("tab_dlnr", ctypes.c_double), ("tab_lnu0", ctypes.c_double),
+        ("tab_dlnu", ctypes.c_double), ("mu_mode", ctypes.c_int32), ("mu_const", ctypes.c_double),
+        ("mu_pfactor", ctypes.c_double), ("yield_mode", ctypes.c_int32), ("y0_mode", ctypes.c_int32),
+        ("y0_const", ctypes.c_double), ("y0_over_E", ctypes.c_double), ("break_mode", ctypes.c_int32),
+        ("eps_break", ctypes.c_double), ("rotation", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("max_neighbours", ctypes.c_int32), ("resort_every", ctypes.c_int32),
+        ("cell_div", ctypes.c_int32),
+    ]
+
+
+class SphState(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64)] + [(k, _dp) for k in (
+        "x", "y", "z", "vx", "vy", "vz", "u", "h", "S", "type", "broken", "id", "star",
+        "D", "rho", "P", "cs", "ax", "ay", "az", "dudt", "dSdt")]
+
+
+class SphError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {STATUS.get(code, code)}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load libsph.so (torch first, so that the HIP runtime it carries is the one in use)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (HIP runtime comes with torch)
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    P, S = ctypes.POINTER(SphParams), ctypes.POINTER(SphState)
+    vp = ctypes.c_void_p
+    L.sph_create.argtypes = [P, vp, ctypes.c_int64, ctypes.POINTER(vp)]
+    L.sph_destroy.argtypes = [vp]
+    L.sph_destroy.restype = None
+    L.sph_set_params.argtypes = [vp, P]
+    for f in ("sph_build_cells", "sph_density", "sph_stress_rate", "sph_forces"):
+        getattr(L, f).argtypes = [vp, S]
+    L.sph_step.argtypes = [vp, S, ctypes.c_double, ctypes.c_int32]
+    L.sph_sync.argtypes = [vp]
+    L.sph_export_neighbours.argtypes = [vp, vp, vp, ctypes.c_int64]
+    L.sph_status_string.argtypes = [ctypes.c_int]
+    L.sph_status_string.restype = ctypes.c_char_p
+    L.sph_set_timing.argtypes = [vp, ctypes.c_int32]
+    L.sph_get_timing.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32),
+                                 ctypes.POINTER(ctypes.c_double)]
+    _lib = L
+    return L
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise SphError(rc, what)
+
+
+# ------------------------------------------------------------------------------------------
+# state on the device
+
+
+class DeviceState:
+    """Particle state as torch tensors on the GPU plus the sph_state struct pointing at them."""
+
+    F64 = ("x", "y", "z", "vx", "vy", "vz", "u", "h", "D", "rho", "P", "cs", "ax", "ay", "az", "dudt")
+
+    def __init__(self, arrays: dict, device="cuda", star=None):
+        import torch
+        n = int(np.asarray(arrays["x"]).shape[0])
+        self.n = n
+        t = {}
+        dev = torch.device(device)
+        for k in self.F64:
+            src = arrays.get(k)
+            t[k] = (torch.as_tensor(np.ascontiguousarray(src, dtype=np.float64), device=dev).clone()
+                    if src is not None else torch.zeros(n, dtype=torch.float64, device=dev))
+        t["S"] = torch.as_tensor(np.ascontiguousarray(np.asarray(arrays["S"], np.float64).reshape(6, n)),
+                                 device=dev).clone()
+        t["dSdt"] = torch.zeros((6, n), dtype=torch.float64, device=dev)
+        t["type"] = torch.as_tensor(np.asarray(arrays["type"], np.int8), device=dev).clone()
+        t["broken"] = torch.as_tensor(np.asarray(arrays["broken"], np.uint8), device=dev).clone()
+        t["id"] = torch.as_tensor(np.asarray(arrays.get("id", np.arange(n)), np.int32), device=dev).clone()
+        if star is not None:
+            t["star"] = torch.as_tensor(np.asarray(star, np.int32), device=dev).clone()
+        self.t = t
+        self.struct = SphState()
+        self.struct.n = n
+        for k, v in t.items():
+            setattr(self.struct, k, v.data_ptr())
+        if "star" not in t:
+            self.struct.star = None
+
+    def __getitem__(self, k):
+        return self.t[k]
+
+    def numpy(self, keys=None):
+        keys = keys or list(self.t)
+        return {k: self.t[k].cpu().numpy() for k in keys}
+
+
+# ------------------------------------------------------------------------------------------
+# context
+
+
+class Context:
+    """Owns an sph_ctx and the device copies of the background and EoS tables."""
+
+    def __init__(self, params, capacity: int, stream=None, max_neighbours=0, resort_every=0,
+                 cell_div=0):
+        import torch
+        from sph_inputs.params import (BACKGROUNDS, BREAK_MODES, EOS_KINDS, H_MODES, KERNELS, MU_MODES,
+                                       PRECISIONS, ROTATIONS, Y0_MODES, YIELD_MODES)
+        L = load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("libsph needs a GPU: torch.cuda.is_available() is False")
+        self.lib = L
+        self.params = params
+        self._keep = []
+        p = SphParams()
+        p.kernel = KERNELS[params.kernel]
+        p.h_mode = H_MODES[params.h_mode]
+        p.background = BACKGROUNDS[params.background]
+        p.periodic = int(bool(params.periodic))
+        p.eta, p.box, p.m = params.eta, params.box, params.m
+        if params.bg_table is not None:
+            bg = torch.as_tensor(np.ascontiguousarray(params.bg_table, np.float64), device="cuda")
+            self._keep.append(bg)
+            p.bg, p.bg_n, p.bg_dr, p.bg_M = bg.data_ptr(), bg.shape[1], params.bg_dr, params.bg_M
+        p.visc_alpha, p.visc_beta, p.visc_eps = params.visc_alpha, params.visc_beta, params.visc_eps
+        p.eos = EOS_KINDS[params.eos]
+        p.gamma = params.gamma
+        if params.table is not None:
+            tb = params.table
+            a = torch.as_tensor(np.ascontiguousarray(tb.lnP), device="cuda")
+            b = torch.as_tensor(np.ascontiguousarray(tb.lncs2), device="cuda")
+            self._keep += [a, b]
+            p.tab_lnP, p.tab_lncs2, p.tab_nr, p.tab_nu = a.data_ptr(), b.data_ptr(), tb.nr, tb.nu
+            p.tab_lnr0, p.tab_dlnr, p.tab_lnu0, p.tab_dlnu = tb.lnr0, tb.dlnr, tb.lnu0, tb.dlnu
+        p.mu_mode = MU_MODES[params.mu_mode]
+        p.mu_const, p.mu_pfactor = params.mu_const, params.mu_pfactor
+        p.yield_mode = YIELD_MODES[params.yield_mode]
+        p.y0_mode = Y0_MODES[params.y0_mode]
+        p.y0_const, p.y0_over_E = params.y0_const, params.y0_over_E
+        p.break_mode = BREAK_MODES[params.break_mode]
+        p.eps_break = params.eps_break
+        p.rotation = ROTATIONS[params.rotation]
+        p.precision = PRECISIONS[params.precision]
+        p.max_neighbours = max_neighbours
+        p.resort_every = resort_every
+        p.cell_div = cell_div
+        self.p = p
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _check(L.sph_create(ctypes.byref(p), ctypes.c_void_p(self.stream.cuda_stream), int(capacity),
+                            ctypes.byref(h)), "sph_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.sph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # stage calls -----------------------------------------------------------------------------
+    def sph_build_cells(self, st: DeviceState):
+        _check(self.lib.sph_build_cells(self.h, ctypes.byref(st.struct)), "sph_build_cells")
+
+    def sph_density(self, st: DeviceState):
+        _check(self.lib.sph_density(self.h, ctypes.byref(st.struct)), "sph_density")
+
+    def sph_stress_rate(self, st: DeviceState):
+        _check(self.lib.sph_stress_rate(self.h, ctypes.byref(st.struct)), "sph_stress_rate")
+
+    def sph_forces(self, st: DeviceState):
+        _check(self.lib.sph_forces(self.h, ctypes.byref(st.struct)), "sph_forces")
+
+    def sph_step(self, st: DeviceState, dt: float, nsteps: int):
+        _check(self.lib.sph_step(self.h, ctypes.byref(st.struct), float(dt), int(nsteps)), "sph_step")
+
+    def sph_sync(self):
+        _check(self.lib.sph_sync(self.h), "sph_sync")
+
+    def sph_export_neighbours(self, n: int, cap: int = None):
+        off = np.zeros(n + 1, np.int64)
+        cap = cap if cap is not None else 128 * max(n, 1)
+        ids = np.zeros(cap, np.int32)
+        rc = self.lib.sph_export_neighbours(self.h, off.ctypes.data, ids.ctypes.data, cap)
+        if rc == 5:
+            cap = int(off[n])
+            ids = np.zeros(max(cap, 1), np.int32)
+            rc = self.lib.sph_export_neighbours(self.h, off.ctypes.data, ids.ctypes.data, cap)
+        _check(rc, "sph_export_neighbours")
+        return off, ids[: off[n]].copy()
+
+    def sph_set_timing(self, enable: bool):
+        _check(self.lib.sph_set_timing(self.h, int(bool(enable))), "sph_set_timing")
+
+    def sph_get_timing(self, stage: str):
+        n = ctypes.c_int32()
+        ms = ctypes.c_double()
+        _check(self.lib.sph_get_timing(self.h, stage.encode(), ctypes.byref(n), ctypes.byref(ms)),
+               "sph_get_timing")
+        return n.value, ms.value
+
+    # convenience ---------------------------------------------------------------------------
+    def evaluate(self, st: DeviceState):
+        """build_cells -> density -> stress_rate -> forces (the first evaluation of a run)."""
+        self.sph_build_cells(st)
+        self.sph_density(st)
+        self.sph_stress_rate(st)
+        self.sph_forces(st)

@@ -1,0 +1,90 @@
+"""Helpers for GPU-vs-oracle parity tests: run both sides on the same seeded input and compare
+in the oracle's particle order (the GPU reorders particles; `id` follows them)."""
+import numpy as np
+
+import oracle
+
+FIELDS_EVAL = ("D", "rho", "P", "cs", "ax", "ay", "az", "dudt")
+
+
+def gpu_run(w, steps=0, precision=None, ctx_kw=None, params=None):
+    from paper_2107_07315_amd import sph
+    p = params or w.params
+    if precision:
+        p = p.replace(precision=precision)
+    ctx = sph.Context(p, capacity=w.n, **(ctx_kw or {}))
+    st = sph.DeviceState(w.arrays)
+    ctx.evaluate(st)
+    nb = None
+    if steps == 0:
+        off, ids = ctx.sph_export_neighbours(w.n)
+        nb = (off, ids)
+    if steps:
+        ctx.sph_step(st, w.dt, steps)
+    ctx.sph_sync()
+    g = st.numpy()
+    order = np.argsort(g["id"])
+    out = {k: (v[..., order] if v.ndim == 2 else v[order]) for k, v in g.items()}
+    if nb is not None:
+        off, ids = nb
+        ident = g["id"]
+        lists = {}
+        for a in range(w.n):
+            lists[int(ident[a])] = np.sort(ident[ids[off[a]:off[a + 1]]])
+        out["_lists"] = lists
+    ctx.close()
+    return out
+
+
+def oracle_run(w, steps=0, mode=oracle.GRID, params=None):
+    orc = oracle.Oracle(params or w.params)
+    st = oracle.OracleState(w.arrays)
+    k = oracle.run_stages(orc, st, mode, want_kappa=True)
+    if steps:
+        oracle.step(orc, st, w.dt, steps, mode)
+    out = dict(st.a)
+    out.update(kappa_a=k["kappa_a"], kappa_u=k["kappa_u"], kappa_G=k["kappa_G"],
+               offsets=k["offsets"], ids=k["ids"])
+    return out
+
+
+def rel_err(a, b, floor=0.0):
+    return np.abs(a - b) / np.maximum(np.abs(b), floor)
+
+
+def check_lists(g, o, n):
+    off, ids = o["offsets"], o["ids"]
+    bad = 0
+    for a in range(n):
+        if not np.array_equal(g["_lists"][a], ids[off[a]:off[a + 1]]):
+            bad += 1
+    return bad
+
+
+def eval_errors(g, o, mu_scale=1.0):
+    """Per-field worst error of one evaluation, each normalised as the parity criterion states."""
+    e = {}
+    for k in ("D", "rho", "P", "cs"):
+        e[k] = float(np.max(rel_err(g[k], o[k], 1e-300)))
+    ka = o["kappa_a"]
+    for k in ("ax", "ay", "az"):
+        e[k] = float(np.max(np.abs(g[k] - o[k]) / np.maximum(ka, 1e-300)))
+    ku = o["kappa_u"]
+    e["dudt"] = float(np.max(np.abs(g["dudt"] - o["dudt"]) / np.maximum(ku, 1e-300)))
+    # stress rate: absolute error against the scale of its terms
+    kG = o["kappa_G"] / np.maximum(o["D"], 1e-300)
+    Snorm = np.sqrt((o["S"] ** 2).sum(0))
+    mu = o["mu"]
+    scale = (2 * mu + 4 * Snorm) * kG + np.sqrt((o["dSdt"] ** 2).sum(0))
+    diff = np.sqrt(((g["dSdt"] - o["dSdt"]) ** 2).sum(0))
+    e["dSdt"] = float(np.max(np.where(scale > 0, diff / np.maximum(scale, 1e-300), 0.0)))
+    return e
+
+
+def field_errors(g, o, keys):
+    """max |gpu - oracle| / max |oracle| per field (state after time steps)."""
+    e = {}
+    for k in keys:
+        a, b = g[k], o[k]
+        e[k] = float(np.max(np.abs(a - b)) / max(float(np.max(np.abs(b))), 1e-300))
+    return e

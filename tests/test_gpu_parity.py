@@ -1,0 +1,233 @@
+"""GPU (HIP C-ABI) vs CPU FP64 oracle parity on seeded inputs.
+
+Tolerances: neighbour sets bit-exact; one FP64 evaluation agrees to 1e-12, relative for
+positive pointwise fields (D, rho, P, c_s) and relative to the summation bound kappa (the sum of
+|terms|) for the cancelling sums (accelerations, du/dt, dS/dt), since the two sides add the
+same terms in different orders.  After k time steps the state is compared field by field
+relative to each field's largest magnitude (roundoff of order 1e-16 per operation grows through
+the chaotic pair dynamics; the bound used is stated in each test).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from parity import check_lists, eval_errors, field_errors, gpu_run, oracle_run
+from sph_inputs import workloads as W
+from sph_inputs.lattice import random_box
+from sph_inputs.params import MethodParams
+
+pytestmark = pytest.mark.gpu
+
+TOL_EVAL = 1e-12
+
+
+def _print(name, e):
+    print(name, " ".join(f"{k}={v:.2e}" for k, v in e.items()), flush=True)
+
+
+def _assert_eval(g, o, tol=TOL_EVAL, skip=()):
+    e = eval_errors(g, o)
+    _print("eval", e)
+    for k, v in e.items():
+        if k in skip:
+            continue
+        assert v <= tol, (k, v)
+
+
+def test_lattice_evaluation_and_neighbour_sets():
+    w = W.lattice()
+    g = gpu_run(w)
+    o = oracle_run(w, mode=oracle.BRUTE)
+    assert check_lists(g, o, w.n) == 0
+    assert all(len(v) == 80 for v in g["_lists"].values())
+    _assert_eval(g, o)
+
+
+@pytest.mark.parametrize("seed,n", [(0, 3000), (1, 1000), (2, 777)])
+def test_random_variable_h_box(seed, n):
+    # ragged n (not a multiple of 64), smoothing lengths varying 16x, a few huge ones
+    x, y, z = random_box(n, 1.0, seed)
+    rng = np.random.default_rng(50 + seed)
+    h = 0.035 * rng.uniform(0.5, 2.0, n)
+    S = rng.normal(scale=0.2, size=(6, n))
+    S[:3] -= S[:3].mean(0)
+    typ = (rng.uniform(size=n) < 0.5).astype(np.int8)
+    S[:, typ == 0] = 0
+    arr = dict(x=x, y=y, z=z, vx=rng.normal(scale=0.1, size=n), vy=rng.normal(scale=0.1, size=n),
+               vz=rng.normal(scale=0.1, size=n), u=rng.uniform(0.5, 2, n), h=h, S=S, type=typ,
+               broken=np.zeros(n, np.uint8), id=np.arange(n, dtype=np.int32))
+    big = np.zeros(n, bool)
+    big[rng.choice(n, 6, replace=False)] = True
+    for periodic in (False, True):
+        # one periodic image per pair needs 2 h < box / 2
+        arr["h"] = np.where(big, h * (2.0 if periodic else 4.0), h)
+        p = MethodParams(m=1.0 / n, kernel="WC4", periodic=periodic, box=1.0, eos="GAMMA_LAW",
+                         gamma=5 / 3, mu_mode="CONST", mu_const=0.5)
+        w = W.Workload("rand", p, dict(arr), 1e-3, 0)
+        g = gpu_run(w, ctx_kw={"max_neighbours": 1024})
+        o = oracle_run(w, mode=oracle.BRUTE)
+        assert check_lists(g, o, n) == 0
+        _assert_eval(g, o)
+
+
+def test_star_evaluation_tov():
+    w = W.star(20000, seed=2)
+    g = gpu_run(w)
+    o = oracle_run(w)
+    assert check_lists(g, o, w.n) == 0
+    _assert_eval(g, o)
+    assert o["type"].sum() > 100
+
+
+def test_plastic_star_evaluation_and_steps():
+    w = W.star(20000, seed=3, kernel="WC4", eta=W.ETA_100, l=2, A=1e-2, plastic=True)
+    g = gpu_run(w)
+    o = oracle_run(w)
+    assert check_lists(g, o, w.n) == 0
+    _assert_eval(g, o)
+    g = gpu_run(w, steps=5)
+    o = oracle_run(w, steps=5)
+    e = field_errors(g, o, ("x", "y", "z", "vx", "vy", "vz", "u", "h", "S", "D", "ax", "dudt", "dSdt"))
+    _print("5 steps", e)
+    for k, v in e.items():
+        assert v < 1e-9, (k, v)
+    assert np.array_equal(g["broken"], o["broken"])
+
+
+def test_lattice_ten_steps():
+    w = W.lattice()
+    g = gpu_run(w, steps=10)
+    o = oracle_run(w, steps=10)
+    e = field_errors(g, o, ("x", "y", "z", "vx", "vy", "vz", "u", "S", "D", "ax", "dudt", "dSdt"))
+    _print("10 steps", e)
+    for k, v in e.items():
+        assert v < 1e-9, (k, v)
+
+
+def test_table_eos_star():
+    w = W.pp_star(20000, seed=4, eos="TABLE")
+    g = gpu_run(w)
+    o = oracle_run(w)
+    _assert_eval(g, o)
+
+
+def test_fp32_pairs_error_per_field():
+    w = W.star(20000, seed=3, kernel="WC4", eta=W.ETA_100, l=2, A=1e-2, plastic=True)
+    g = gpu_run(w, precision="FP32")
+    o = oracle_run(w)
+    e = eval_errors(g, o)
+    _print("fp32 eval", e)
+    for k in ("D", "rho", "P"):
+        assert e[k] < 1e-4, (k, e[k])
+    for k in ("ax", "ay", "az", "dudt"):
+        assert e[k] < 1e-4, (k, e[k])
+
+
+# ---------------------------------------------------------------------------------------------
+# edge cases and error paths (all forced from the host; every kernel exits normally)
+
+
+def _ctx_state(w, **kw):
+    from paper_2107_07315_amd import sph
+    return sph, sph.Context(w.params, capacity=max(w.n, 1), **kw), sph.DeviceState(w.arrays)
+
+
+def _subset(w, idx):
+    arr = {k: (v[..., idx] if np.ndim(v) == 2 else v[idx]) for k, v in w.arrays.items()}
+    arr["id"] = np.arange(len(idx), dtype=np.int32)
+    return W.Workload(w.name, w.params, arr, w.dt, 0)
+
+
+def test_tiny_and_empty_inputs():
+    w = W.lattice()
+    for n in (1, 2, 63, 65):
+        ws = _subset(w, np.arange(n))
+        ws.params = ws.params.replace(periodic=False, box=0.0)
+        g = gpu_run(ws)
+        o = oracle_run(ws, mode=oracle.BRUTE)
+        assert check_lists(g, o, n) == 0
+        _assert_eval(g, o)
+    # n = 0: every stage is a no-op that succeeds
+    from paper_2107_07315_amd import sph
+    ctx = sph.Context(w.params, capacity=16)
+    st = sph.DeviceState({k: (v[..., :0] if np.ndim(v) == 2 else v[:0]) for k, v in w.arrays.items()})
+    ctx.evaluate(st)
+    ctx.sph_step(st, w.dt, 3)
+    ctx.sph_sync()
+
+
+def test_stage_order_and_argument_errors():
+    w = W.lattice(n_side=8)
+    sph, ctx, st = _ctx_state(w)
+    with pytest.raises(sph.SphError) as e:
+        ctx.sph_density(st)
+    assert e.value.code == 4
+    ctx.sph_build_cells(st)
+    with pytest.raises(sph.SphError) as e:
+        ctx.sph_forces(st)
+    assert e.value.code == 4
+    with pytest.raises(sph.SphError) as e:
+        ctx.sph_step(st, w.dt, 1)
+    assert e.value.code == 4
+    ctx.sph_density(st)
+    ctx.sph_stress_rate(st)
+    ctx.sph_forces(st)
+    with pytest.raises(sph.SphError) as e:
+        ctx.sph_step(st, -1.0, 1)
+    assert e.value.code == 1
+    ctx.sph_sync()
+    # more particles than the context holds
+    big = sph.DeviceState(W.lattice(n_side=9).arrays)
+    with pytest.raises(sph.SphError) as e:
+        ctx.sph_build_cells(big)
+    assert e.value.code == 1
+
+
+def test_neighbour_capacity_error_is_latched():
+    w = W.lattice(n_side=8)
+    sph, ctx, st = _ctx_state(w, max_neighbours=40)   # each particle has 80 neighbours
+    ctx.sph_build_cells(st)
+    with pytest.raises(sph.SphError) as e:
+        ctx.sph_sync()
+    assert e.value.code == 5
+    ctx.sph_sync()    # the status word was cleared
+
+
+def test_periodic_smoothing_length_limit():
+    w = W.lattice(n_side=8)
+    w.arrays["h"][3] = 0.3          # 2h >= box/2: a pair could have two periodic images
+    sph, ctx, st = _ctx_state(w)
+    ctx.sph_build_cells(st)
+    with pytest.raises(sph.SphError) as e:
+        ctx.sph_sync()
+    assert e.value.code == 1
+
+
+def test_nonfinite_and_eos_domain_errors():
+    w = W.lattice(n_side=8)
+    w.arrays["u"][5] = np.nan
+    sph, ctx, st = _ctx_state(w)
+    ctx.evaluate(st)
+    with pytest.raises(sph.SphError) as e:
+        ctx.sph_sync()
+    assert e.value.code == 6
+    wp = W.pp_star(5000, seed=4, eos="TABLE")
+    wp.arrays["u"][0] = 50.0       # above the table's u range
+    sph, ctx, st = _ctx_state(wp)
+    ctx.evaluate(st)
+    with pytest.raises(sph.SphError) as e:
+        ctx.sph_sync()
+    assert e.value.code == 7
+
+
+def test_rebin_without_resort_matches_full_resort():
+    # steps that only re-bin (perm indirection) give the same result as re-sorting every step
+    w = W.star(20000, seed=2)
+    g1 = gpu_run(w, steps=4, ctx_kw={"resort_every": 1})
+    g2 = gpu_run(w, steps=4, ctx_kw={"resort_every": 100})
+    e = field_errors(g2, g1, ("x", "vx", "u", "D", "ax", "dudt"))
+    _print("resort", e)
+    for k, v in e.items():
+        assert v < 1e-11, (k, v)
