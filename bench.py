@@ -1,0 +1,150 @@
+#!/usr/bin/env python3
+"""Throughput of the SPH particle loop on one MI355X: particle-updates/s on the 2M-particle
+piecewise-polytrope neutron star (Wendland C4, ~100 neighbours, l=2 perturbation, plasticity and
+maximum-strain breaking on, fixed TOV background), full steps (cells + density + stress rate +
+forces + kick-drift-kick), FP64 plain vs the mixed-precision path.
+
+Prints one JSON line.  `value` is the headline (mixed-precision) variant; both variants, the
+stage breakdown, the force-pass roofline and the CPU-oracle baseline ride along.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic work of the force pass, counted from the kernel source (fma = 2 FLOP; sqrt,
+# reciprocal and division counted as 1 each): per ordered pair visit 62 FLOP, per particle
+# epilogue 60 FLOP (fixed-background terms).  Algorithmic HBM bytes per particle: the
+# neighbour list (4 B per entry) plus the particle's own records read once (position 32 B,
+# velocity/sound speed 32 B, P/D^2 and D 16 B, u/P/rho/S:epsdot 32 B) and 32 B written;
+# neighbour records are re-reads served by cache, not algorithmic traffic.
+FORCE_FLOP_PER_PAIR = 62
+FORCE_FLOP_PER_PARTICLE = 60
+FORCE_BYTES_PER_PARTICLE_FP64 = 32 + 32 + 16 + 32 + 32
+FORCE_BYTES_PER_PARTICLE_FP32 = 16 + 16 + 8 + 32 + 32
+PEAK = {"FP64": 78.6e12, "FP32": 157.3e12}     # published MI355X vector peaks, FLOP/s
+
+
+def run_variant(w, precision, eos, steps, warmup, timing=True):
+    import torch
+
+    from paper_2107_07315_amd import sph
+    p = w.params.replace(precision=precision, eos=eos)
+    ctx = sph.Context(p, capacity=w.n)
+    st = sph.DeviceState(w.arrays)
+    ctx.evaluate(st)
+    ctx.sph_step(st, w.dt, warmup)
+    ctx.sph_sync()
+    ctx.sph_set_timing(timing)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.sph_step(st, w.dt, steps)
+    ctx.sph_sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / steps
+    stages = {}
+    for s in ("cells", "density", "stress", "forces", "kdk"):
+        n, ms = ctx.sph_get_timing(s)
+        stages[s] = {"launches": n, "ms_total": ms}
+    pairs, maxc = ctx.sph_neighbour_stats()
+    ctx.sph_set_timing(False)
+    ctx.close()
+    del st
+    torch.cuda.empty_cache()
+    fl = stages["forces"]
+    avg_ms = fl["ms_total"] / max(fl["launches"], 1)
+    return {"ms_per_step": ms_step, "value": w.n * steps / (t1 - t0), "stages": stages,
+            "pairs": pairs, "max_neighbours": maxc, "force_avg_ms": avg_ms}
+
+
+def roofline(res, n, precision):
+    flop = res["pairs"] * FORCE_FLOP_PER_PAIR + n * FORCE_FLOP_PER_PARTICLE
+    sec = res["force_avg_ms"] * 1e-3
+    achieved = flop / sec / 1e12
+    peak = PEAK[precision] / 1e12
+    nbytes = res["pairs"] * 4 + n * (FORCE_BYTES_PER_PARTICLE_FP64 if precision == "FP64"
+                                     else FORCE_BYTES_PER_PARTICLE_FP32)
+    return {"kernel": f"k_forces<{'double' if precision == 'FP64' else 'float'}>", "bound": "alu",
+            "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": None,
+            "algorithmic_GBps": round(nbytes / sec / 1e9, 1),
+            "flop_per_launch": flop, "launch_ms": round(res["force_avg_ms"], 4)}
+
+
+def cpu_baseline(w):
+    import oracle
+    orc = oracle.Oracle(w.params.replace(precision="FP64", eos="TABLE"))
+    st = oracle.OracleState(w.arrays)
+    oracle.run_stages(orc, st)             # rates at t = 0 (untimed)
+    t0 = time.perf_counter()
+    oracle.step(orc, st, w.dt, 1)
+    t1 = time.perf_counter()
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(w.n / (t1 - t0), 1), "unit": "particle-updates/s", "cores": cores,
+            "kind": "oracle", "sample": f"1 kick-drift-kick step (neighbours, density, stress rate, "
+            f"forces) of the same {w.n}-particle star in FP64 after one untimed evaluation; "
+            f"{t1 - t0:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=2_000_000)
+    ap.add_argument("--variants", default="FP64,FP32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU sharding is a design note, not built)"}), flush=True)
+        sys.exit(2)
+
+    from sph_inputs import workloads as W
+    w = W.pp_star(args.n, seed=3, eos="TABLE", steps=args.steps)
+    variants = [v.strip() for v in args.variants.split(",") if v.strip()]
+    res = {}
+    for v in variants:
+        res[v] = run_variant(w, v, "TABLE", args.steps, args.warmup)
+        print(f"# {v}: {res[v]['ms_per_step']:.3f} ms/step, {res[v]['value']:.4g} particle-updates/s",
+              file=sys.stderr, flush=True)
+    head = "FP32" if "FP32" in res else variants[0]
+    r = res[head]
+    out = {
+        "metric": "particle-updates/s at 2M particles: FP64 plain vs FP32+EoS-MLP, 1 GPU",
+        "value": r["value"],
+        "unit": "particle-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 pair sums + f64 integration" if head == "FP32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"piecewise-polytrope TOV star, {w.n} particles, Wendland C4 "
+                               f"(~100 neighbours), l=2 A=1e-2, plastic + breaking, tabulated EoS",
+                   "n_particles": w.n, "dt": w.dt, "eos": "TABLE", "precision": head},
+        "variants": {k: {"value": v["value"], "ms_per_step": v["ms_per_step"],
+                         "stages_ms_per_step": {s: round(d["ms_total"] / args.steps, 4)
+                                                for s, d in v["stages"].items()},
+                         "pairs": v["pairs"], "max_neighbours": v["max_neighbours"]}
+                     for k, v in res.items()},
+        "roofline": roofline(r, w.n, head),
+    }
+    if "FP64" in res and "FP32" in res:
+        out["speedup_fp32_vs_fp64"] = round(res["FP32"]["value"] / res["FP64"]["value"], 3)
+        out["roofline_fp64"] = roofline(res["FP64"], w.n, "FP64")
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

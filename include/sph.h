@@ -112,7 +112,8 @@ typedef struct {
   int32_t cell_div;        /* cells per smoothing diameter of the finest level (0: 2)          */
 } sph_params;
 
-/* Create a context for up to `capacity` particles on the current HIP device; all work is
+/* Create a context for up to `capacity` particles on the current HIP device (capacity rounded up
+ * to 64 times max_neighbours must stay below 2^32); all work is
  * enqueued on `hip_stream` (a hipStream_t, may be NULL for the default stream).
  * Returns SPH_E_ARG for a bad parameter set, SPH_E_OOM if scratch does not fit. */
 sph_status sph_create(const sph_params* params, void* hip_stream, int64_t capacity, sph_ctx** out);
@@ -156,6 +157,10 @@ sph_status sph_sync(sph_ctx* ctx);
  * offsets[n+1] (host), ids[offsets[n]] (host, indices into the current order).  Lists are
  * written unsorted.  Returns SPH_E_NGB_CAPACITY (and offsets) if cap is too small.  Waits. */
 sph_status sph_export_neighbours(sph_ctx* ctx, int64_t* offsets, int32_t* ids, int64_t cap);
+
+/* Total number of neighbour-list entries (ordered pairs a->b, b != a) and the longest list of
+ * the current lists.  Waits. */
+sph_status sph_neighbour_stats(sph_ctx* ctx, int64_t* total_pairs, int32_t* max_count);
 
 /* Human-readable name of a status code (static string). */
 const char* sph_status_string(sph_status s);

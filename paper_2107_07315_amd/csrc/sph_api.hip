@@ -89,7 +89,8 @@ void sph_destroy(sph_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
   void* bufs[] = {c->grid, c->keys, c->vals, c->cell_start, c->cell_end, c->sort.keys_alt, c->sort.vals_alt,
-                  c->sort.hist, c->nbr, c->nbr_count, c->pos4, c->fv, c->fa, c->sig, c->pos4f, c->fvf,
+                  c->sort.hist, c->sort.rowtot, c->sort.partial, c->sort.scan_bsum, c->tile_start, c->tile_cnt, c->tile_flag, c->tile_u, c->tile_uoff,
+                  c->tile_usize, c->nbr16, c->nbr_count, c->pos4, c->fv, c->fa, c->sig, c->pos4f, c->fvf,
                   c->faf, c->sigf, c->mu, c->Y0, c->B, c->sdot, c->half, c->tmp, c->stars, c->status};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
@@ -112,16 +113,34 @@ sph_status sph_create(const sph_params* params, void* stream, int64_t capacity, 
   c->stream = (hipStream_t)stream;
   c->capacity = capacity;
   c->cap = params->max_neighbours > 0 ? params->max_neighbours : 512;
+  c->ucap = 8192;   // union members per tile; local indices are 16-bit
+  c->upool = (int64_t)((capacity + 63) / 64 * 64) * c->cap;
+  if (c->upool > (int64_t)0xffffffffll) {   // pool offsets are 32-bit: lower max_neighbours
+    c->~sph_ctx();
+    free(c);
+    return SPH_E_ARG;
+  }
   (void)hipGetDevice(&c->device);
   const int64_t cap = capacity;
   const int64_t capw = (cap + 63) / 64 * 64;
+  c->capw = capw;
+  // every tile holds at least one particle, so capw tiles always suffice; the union pool holds
+  // up to cap entries per particle (the worst case of one particle per tile), capped by 32-bit
+  // offsets
+  c->cap_tiles = capw;
+  c->sort.scan_cap = (capw + 1023) / 1024;
   c->max_cells = kMaxCells;
   c->sort.max_blocks = (int)((cap + 4095) / 4096);
   if ((e = dalloc(&c->grid, 1)) || (e = dalloc(&c->keys, cap)) || (e = dalloc(&c->vals, cap)) ||
       (e = dalloc(&c->cell_start, c->max_cells)) || (e = dalloc(&c->cell_end, c->max_cells)) ||
       (e = dalloc(&c->sort.keys_alt, cap)) || (e = dalloc(&c->sort.vals_alt, cap)) ||
-      (e = dalloc(&c->sort.hist, (size_t)256 * c->sort.max_blocks)) ||
-      (e = dalloc(&c->nbr, (size_t)capw * c->cap)) || (e = dalloc(&c->nbr_count, cap)) ||
+      (e = dalloc(&c->sort.hist, (size_t)256 * c->sort.max_blocks)) || (e = dalloc(&c->sort.rowtot, 256)) ||
+      (e = dalloc(&c->sort.partial, (size_t)8 * 1024)) ||
+      (e = dalloc(&c->tile_u, (size_t)c->upool)) || (e = dalloc(&c->tile_uoff, c->cap_tiles)) ||
+      (e = dalloc(&c->tile_usize, c->cap_tiles)) ||
+      (e = dalloc(&c->tile_start, c->cap_tiles)) || (e = dalloc(&c->tile_cnt, c->cap_tiles)) ||
+      (e = dalloc(&c->tile_flag, capw)) || (e = dalloc(&c->sort.scan_bsum, c->sort.scan_cap + 1)) ||
+      (e = dalloc(&c->nbr16, (size_t)capw * c->cap)) || (e = dalloc(&c->nbr_count, capw)) ||
       (e = dalloc(&c->pos4, cap)) || (e = dalloc(&c->fv, cap)) || (e = dalloc(&c->fa, cap)) ||
       (e = dalloc(&c->sig, 6 * cap)) || (e = dalloc(&c->pos4f, cap)) || (e = dalloc(&c->fvf, cap)) ||
       (e = dalloc(&c->faf, cap)) || (e = dalloc(&c->sigf, 6 * cap)) || (e = dalloc(&c->mu, cap)) ||
@@ -263,25 +282,44 @@ sph_status sph_export_neighbours(sph_ctx* c, int64_t* offsets, int32_t* ids, int
   if (hipStreamSynchronize(c->stream) != hipSuccess) return SPH_E_HIP;
   const int64_t n = c->n;
   if (n == 0) { offsets[0] = 0; return SPH_OK; }
-  int32_t* cnt = (int32_t*)malloc(sizeof(int32_t) * n);
-  const int64_t nw = (n + 63) / 64;
-  int32_t* raw = (int32_t*)malloc(sizeof(int32_t) * nw * 64 * (int64_t)c->cap);
-  if (!cnt || !raw) { free(cnt); free(raw); return SPH_E_OOM; }
-  if (hipMemcpy(cnt, c->nbr_count, sizeof(int32_t) * n, hipMemcpyDeviceToHost) != hipSuccess ||
-      hipMemcpy(raw, c->nbr, sizeof(int32_t) * nw * 64 * (int64_t)c->cap, hipMemcpyDeviceToHost) != hipSuccess) {
-    free(cnt); free(raw);
+  GridInfo g;
+  if (hipMemcpy(&g, c->grid, sizeof(g), hipMemcpyDeviceToHost) != hipSuccess) return SPH_E_HIP;
+  const int64_t ntiles = (int64_t)g.ntiles < c->cap_tiles ? (int64_t)g.ntiles : c->cap_tiles;
+  std::vector<int32_t> cnt(n), usz(ntiles), tst(ntiles), tcn(ntiles);
+  std::vector<uint32_t> uoff(ntiles);
+  std::vector<int32_t> U((size_t)(g.upool_used < c->upool ? g.upool_used : c->upool));
+  std::vector<uint32_t> perm(n);
+  std::vector<uint16_t> raw((size_t)c->cap * c->capw);
+  if (hipMemcpy(cnt.data(), c->nbr_count, sizeof(int32_t) * n, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(usz.data(), c->tile_usize, sizeof(int32_t) * ntiles, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(tst.data(), c->tile_start, sizeof(int32_t) * ntiles, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(tcn.data(), c->tile_cnt, sizeof(int32_t) * ntiles, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(uoff.data(), c->tile_uoff, sizeof(uint32_t) * ntiles, hipMemcpyDeviceToHost) != hipSuccess ||
+      (U.size() && hipMemcpy(U.data(), c->tile_u, sizeof(int32_t) * U.size(), hipMemcpyDeviceToHost) != hipSuccess) ||
+      hipMemcpy(perm.data(), c->vals, sizeof(uint32_t) * n, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(raw.data(), c->nbr16, sizeof(uint16_t) * raw.size(), hipMemcpyDeviceToHost) != hipSuccess)
     return SPH_E_HIP;
-  }
+  std::vector<int32_t> cnt_a(n, 0);
+  for (int64_t p = 0; p < n; ++p) cnt_a[c->identity_perm ? p : perm[p]] = cnt[p];
   offsets[0] = 0;
-  for (int64_t a = 0; a < n; ++a) offsets[a + 1] = offsets[a] + cnt[a];
-  if (offsets[n] > cap || !ids) { free(cnt); free(raw); return SPH_E_NGB_CAPACITY; }
-  for (int64_t a = 0; a < n; ++a) {
-    const int32_t* l = raw + ((a >> 6) * (int64_t)c->cap) * 64 + (a & 63);
-    for (int k = 0; k < cnt[a]; ++k) ids[offsets[a] + k] = l[(int64_t)k * 64];
-  }
-  free(cnt);
-  free(raw);
+  for (int64_t a = 0; a < n; ++a) offsets[a + 1] = offsets[a] + cnt_a[a];
+  if (offsets[n] > cap || !ids) return SPH_E_NGB_CAPACITY;
+  for (int64_t t = 0; t < ntiles; ++t)
+    for (int l = 0; l < tcn[t]; ++l) {
+      const int64_t p = (int64_t)tst[t] + l;
+      const int64_t a = c->identity_perm ? p : perm[p];
+      for (int k = 0; k < cnt[p]; ++k) {
+        const uint16_t loc = raw[(size_t)k * c->capw + p];
+        ids[offsets[a] + k] = U[(size_t)uoff[t] + loc];
+      }
+    }
   return SPH_OK;
+}
+
+sph_status sph_neighbour_stats(sph_ctx* c, int64_t* total_pairs, int32_t* max_count) {
+  if (!c || !total_pairs || !max_count) return SPH_E_ARG;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return SPH_E_HIP;
+  return sph_count_stats(c, total_pairs, max_count);
 }
 
 sph_status sph_set_timing(sph_ctx* c, int32_t enable) {

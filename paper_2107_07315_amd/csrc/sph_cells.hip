@@ -8,20 +8,12 @@
 // (cell size 2 hmax_l / cell_div).  A particle searches every level l within h_a + hmax_l and
 // skips cells whose box lies farther away.  Cells are addressed by Morton codes so that the
 // sorted particle order is spatially compact.  The list build writes exact FP64 lists that all
-// later passes read; the lists are interleaved by wavefront so that lane a of a wave reading its
-// k-th neighbour touches one contiguous 256-byte segment.
+// later passes read, grouped in tiles of 64 particles (see k_build_tiles).
 #include "sph_internal.h"
 
 namespace {
 
 constexpr int kB = 256;
-
-__global__ void k_grid_reset(GridInfo* g) {
-  for (int d = 0; d < 3; ++d) { g->enc_lo[d] = ~0ull; g->enc_hi[d] = 0ull; }
-  g->enc_hmin = ~0ull;
-  g->enc_hmax = 0ull;
-  for (int l = 0; l < SPH_MAX_LEV; ++l) g->hlev_bits[l] = 0ull;
-}
 
 __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
   for (int off = 32; off > 0; off >>= 1) {
@@ -38,33 +30,59 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
   return v;
 }
 
-// Bounding box (positions relative to their star centre) and the h range.
-__global__ __launch_bounds__(kB) void k_bounds(const double4* __restrict__ pos4, int64_t n, GridInfo* g) {
-  unsigned long long lo[3] = {~0ull, ~0ull, ~0ull}, hi[3] = {0, 0, 0}, hmn = ~0ull, hmx = 0;
+// Bounding box and h range: one partial per block (8 encoded values), reduced in set-up.
+__global__ __launch_bounds__(kB) void k_bounds(const double4* __restrict__ pos4, int64_t n,
+                                               unsigned long long* __restrict__ partial) {
+  __shared__ unsigned long long red[4][8];
+  unsigned long long v[8] = {~0ull, ~0ull, ~0ull, 0ull, 0ull, 0ull, ~0ull, 0ull};  // lo xyz, hi xyz, hmin, hmax
   for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < n;
        a += (int64_t)gridDim.x * blockDim.x) {
     double4 p = pos4[a];
     double q[3] = {p.x, p.y, p.z};
     for (int d = 0; d < 3; ++d) {
       unsigned long long e = enc_double(q[d]);
-      lo[d] = e < lo[d] ? e : lo[d];
-      hi[d] = e > hi[d] ? e : hi[d];
+      v[d] = e < v[d] ? e : v[d];
+      v[3 + d] = e > v[3 + d] ? e : v[3 + d];
     }
     unsigned long long e = enc_double(p.w);
-    hmn = e < hmn ? e : hmn;
-    hmx = e > hmx ? e : hmx;
+    v[6] = e < v[6] ? e : v[6];
+    v[7] = e > v[7] ? e : v[7];
   }
-  for (int d = 0; d < 3; ++d) { lo[d] = wave_min_u64(lo[d]); hi[d] = wave_max_u64(hi[d]); }
-  hmn = wave_min_u64(hmn);
-  hmx = wave_max_u64(hmx);
-  if ((threadIdx.x & 63) == 0) {
-    for (int d = 0; d < 3; ++d) { atomicMin(&g->enc_lo[d], lo[d]); atomicMax(&g->enc_hi[d], hi[d]); }
-    atomicMin(&g->enc_hmin, hmn);
-    atomicMax(&g->enc_hmax, hmx);
+  for (int k = 0; k < 8; ++k) {
+    bool mx = (k >= 3 && k < 6) || k == 7;
+    v[k] = mx ? wave_max_u64(v[k]) : wave_min_u64(v[k]);
+  }
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int k = 0; k < 8; ++k) red[wave][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x < 8) {
+    int k = threadIdx.x;
+    bool mx = (k >= 3 && k < 6) || k == 7;
+    unsigned long long r = red[0][k];
+    for (int w = 1; w < 4; ++w) r = mx ? (red[w][k] > r ? red[w][k] : r) : (red[w][k] < r ? red[w][k] : r);
+    partial[(int64_t)blockIdx.x * 8 + k] = r;
   }
 }
 
-__global__ void k_grid_setup1(GridInfo* g, int periodic, double box, DevStatus* st) {
+__global__ __launch_bounds__(64) void k_grid_setup1(GridInfo* g, const unsigned long long* __restrict__ partial,
+                                                    int nblocks, int periodic, double box, DevStatus* st) {
+  unsigned long long v[8] = {~0ull, ~0ull, ~0ull, 0ull, 0ull, 0ull, ~0ull, 0ull};
+  for (int b = threadIdx.x; b < nblocks; b += 64)
+    for (int k = 0; k < 8; ++k) {
+      unsigned long long e = partial[(int64_t)b * 8 + k];
+      bool mx = (k >= 3 && k < 6) || k == 7;
+      v[k] = mx ? (e > v[k] ? e : v[k]) : (e < v[k] ? e : v[k]);
+    }
+  for (int k = 0; k < 8; ++k) {
+    bool mx = (k >= 3 && k < 6) || k == 7;
+    v[k] = mx ? wave_max_u64(v[k]) : wave_min_u64(v[k]);
+  }
+  if (threadIdx.x != 0) return;
+  for (int d = 0; d < 3; ++d) { g->enc_lo[d] = v[d]; g->enc_hi[d] = v[3 + d]; }
+  g->enc_hmin = v[6];
+  g->enc_hmax = v[7];
+  for (int l = 0; l < SPH_MAX_LEV; ++l) g->hlev_bits[l] = 0ull;
   g->periodic = periodic;
   g->box = box;
   for (int d = 0; d < 3; ++d) g->lo[d] = periodic ? 0.0 : dec_double(g->enc_lo[d]);
@@ -203,96 +221,339 @@ __global__ __launch_bounds__(kB) void k_pack_pos(const double* __restrict__ x, c
   if (pos4f) pos4f[a] = make_float4((float)(x[a] - cx), (float)(y[a] - cy), (float)(z[a] - cz), (float)h[a]);
 }
 
-// Ensemble stars occupy disjoint regions of one coordinate frame: the search runs in that
-// frame, so the positions used for binning and testing are the absolute ones.
-__global__ __launch_bounds__(kB) void k_build_lists(const double* __restrict__ x, const double* __restrict__ y,
-                                                    const double* __restrict__ z, const double* __restrict__ h,
-                                                    int64_t n, const GridInfo* __restrict__ gp,
-                                                    const uint32_t* __restrict__ skeys,
-                                                    const uint32_t* __restrict__ perm, int identity,
-                                                    const int32_t* __restrict__ cstart,
-                                                    const int32_t* __restrict__ cend, int cap,
-                                                    int32_t* __restrict__ nbr, int32_t* __restrict__ count,
-                                                    DevStatus* status) {
-  int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= n) return;
+// Tiles: runs of at most 64 consecutive sorted particles that never cross a super-cell (2x2x2
+// cells of one level, a Morton prefix).  Cutting at super-cells keeps every tile spatially
+// compact also in sparse levels, where 64 consecutive particles could otherwise span the star.
+__device__ __forceinline__ int key_level(uint32_t key, const GridInfo& g) {
+  int l = 0;
+  while (l < g.nlev - 1 && key >= g.base[l + 1]) ++l;
+  return l;
+}
+
+__global__ __launch_bounds__(kB) void k_tile_marks(const uint32_t* __restrict__ skeys, int64_t n,
+                                                   const GridInfo* __restrict__ gp,
+                                                   const int32_t* __restrict__ cstart,
+                                                   const int32_t* __restrict__ cend, uint32_t* __restrict__ len,
+                                                   uint32_t* __restrict__ flag) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
   const GridInfo& g = *gp;
-  const double xa = x[a], ya = y[a], za = z[a], ha = h[a];
-  int32_t* out = nbr + ((a >> 6) * (int64_t)cap) * 64 + (a & 63);
-  int cnt = 0;
-  const int periodic = g.periodic;
-  const double box = g.box;
-  for (int l = 0; l < g.nlev; ++l) {
-    const double c = g.cell[l];
-    const double R = (ha + g.hlev[l]) * (1.0 + 1e-9);
-    const double R2 = R * R;
-    int lo3[3], hi3[3];
-    bool wrap[3];
-    const double q[3] = {xa, ya, za};
-    for (int d = 0; d < 3; ++d) {
-      int dim = g.dims[l][d];
-      int l0 = (int)floor((q[d] - R - g.lo[d]) / c);
-      int h0 = (int)floor((q[d] + R - g.lo[d]) / c);
-      wrap[d] = false;
-      if (periodic) {
-        if (h0 - l0 + 1 >= dim) { l0 = 0; h0 = dim - 1; }
-        else wrap[d] = true;
-      } else {
-        l0 = l0 < 0 ? 0 : l0;
-        h0 = h0 > dim - 1 ? dim - 1 : h0;
-      }
-      lo3[d] = l0;
-      hi3[d] = h0;
-    }
-    const uint32_t base = g.base[l];
-    for (int kz = lo3[2]; kz <= hi3[2]; ++kz) {
-      double dz = 0.0;
-      if (!periodic || wrap[2]) {
-        double b0 = g.lo[2] + kz * c, b1 = b0 + c;
-        dz = za < b0 ? b0 - za : (za > b1 ? za - b1 : 0.0);
-      }
-      int cz = kz;
-      if (wrap[2]) cz = (kz % g.dims[l][2] + g.dims[l][2]) % g.dims[l][2];
-      const uint32_t mz = spread3((uint32_t)cz) << 2;
-      for (int ky = lo3[1]; ky <= hi3[1]; ++ky) {
-        double dy = 0.0;
-        if (!periodic || wrap[1]) {
-          double b0 = g.lo[1] + ky * c, b1 = b0 + c;
-          dy = ya < b0 ? b0 - ya : (ya > b1 ? ya - b1 : 0.0);
-        }
-        if (dz * dz + dy * dy >= R2) continue;
-        int cy = ky;
-        if (wrap[1]) cy = (ky % g.dims[l][1] + g.dims[l][1]) % g.dims[l][1];
-        const uint32_t myz = mz | (spread3((uint32_t)cy) << 1);
-        for (int kx = lo3[0]; kx <= hi3[0]; ++kx) {
-          double dx = 0.0;
-          if (!periodic || wrap[0]) {
-            double b0 = g.lo[0] + kx * c, b1 = b0 + c;
-            dx = xa < b0 ? b0 - xa : (xa > b1 ? xa - b1 : 0.0);
-          }
-          if (dz * dz + dy * dy + dx * dx >= R2) continue;
-          int cx = kx;
-          if (wrap[0]) cx = (kx % g.dims[l][0] + g.dims[l][0]) % g.dims[l][0];
-          const uint32_t key = base + (myz | spread3((uint32_t)cx));
-          int32_t s = cstart[key];
-          if (s < 0 || s >= n || skeys[s] != key) continue;
-          int32_t e = cend[key];
-          for (int32_t p = s; p < e; ++p) {
-            int64_t b = identity ? p : (int64_t)perm[p];
-            if (b == a) continue;
-            double ddx = min_image(xa - x[b], periodic, box);
-            double ddy = min_image(ya - y[b], periodic, box);
-            double ddz = min_image(za - z[b], periodic, box);
-            if (!neighbour_test(ddx, ddy, ddz, ha, h[b])) continue;
-            if (cnt < cap) out[(int64_t)cnt * 64] = (int32_t)b;
-            ++cnt;
-          }
-        }
-      }
+  const uint32_t key = skeys[p];
+  const int l = key_level(key, g);
+  const uint32_t m = key - g.base[l];
+  const uint32_t ncell = 1u << (3 * g.bits[l]);
+  const uint32_t first = m & ~7u;
+  int64_t s0 = p, e0 = p + 1;
+  for (uint32_t j = 0; j < 8; ++j) {
+    const uint32_t mc = first + j;
+    if (mc >= ncell) break;
+    const uint32_t kc = g.base[l] + mc;
+    const int32_t s = cstart[kc];
+    if (s < 0 || s >= n || skeys[s] != kc) continue;
+    const int32_t e = cend[kc];
+    s0 = s < s0 ? s : s0;
+    e0 = e > e0 ? e : e0;
+  }
+  const int64_t off = p - s0;
+  uint32_t L = 0;
+  if (off % 64 == 0) {
+    const int64_t rem = e0 - p;
+    L = (uint32_t)(rem < 64 ? rem : 64);
+  }
+  len[p] = L;
+  flag[p] = L ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(kB) void k_tile_fill(const uint32_t* __restrict__ len, const uint32_t* __restrict__ idx,
+                                                  int64_t n, int64_t cap_tiles, int32_t* __restrict__ tile_start,
+                                                  int32_t* __restrict__ tile_cnt, DevStatus* status) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const uint32_t L = len[p];
+  if (!L) return;
+  const uint32_t t = idx[p];
+  if ((int64_t)t < cap_tiles) {
+    tile_start[t] = (int32_t)p;
+    tile_cnt[t] = (int32_t)L;
+  } else {
+    latch_error(status, SPH_E_NGB_CAPACITY, -1);
+  }
+}
+
+// Union-pool reservation: a tile of cnt targets can need at most min(ucap, cnt * cap) entries.
+__global__ __launch_bounds__(kB) void k_tile_ubound(const GridInfo* __restrict__ gp, const int32_t* __restrict__ tile_cnt,
+                                                    int64_t cap_tiles, int cap, int ucap, uint32_t* __restrict__ ub) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cap_tiles) return;
+  uint32_t v = 0;
+  if (t < (int64_t)gp->ntiles) {
+    const int64_t b = (int64_t)tile_cnt[t] * cap;
+    v = (uint32_t)(b < ucap ? b : ucap);
+  }
+  ub[t] = v;
+}
+
+// Tile neighbour lists.  Each tile is handled by one wavefront (one lane per target), in three
+// latency-friendly phases per block of 64 candidate cells:
+//  1. the 64 lanes enumerate 64 cells of the search box at once, cull them against the tile's
+//     bounding box and look up their particle ranges (parallel loads);
+//  2. the wave gathers the cells' particles 64 at a time (a wave-wide prefix sum maps lanes to
+//     (cell, offset)), pre-tests each against the tile box and appends survivors to an LDS batch;
+//  3. per batch of 64 candidates every lane runs the exact FP64 test against all of them,
+//     building a 64-bit hit mask; the OR of the masks gives the batch's new union members (in
+//     candidate order) and each lane appends the local indices of its hits.
+// Candidates enter batches in a fixed order (level, cell, sorted position), so U and the lists
+// are deterministic and each list is ascending in local index.
+struct BuildArgs {
+  const double4* __restrict__ pos4;
+  int64_t n;
+  const GridInfo* __restrict__ grid;
+  const uint32_t* __restrict__ skeys;
+  const uint32_t* __restrict__ perm;
+  int identity;
+  const int32_t* __restrict__ cstart;
+  const int32_t* __restrict__ cend;
+  const int32_t* __restrict__ tile_start;
+  const int32_t* __restrict__ tile_cnt;
+  int64_t cap_tiles, capw;
+  int cap, ucap;
+  const uint32_t* __restrict__ tile_uoff;
+  int64_t upool;
+  int32_t* __restrict__ tile_u;
+  int32_t* __restrict__ tile_usize;
+  uint16_t* __restrict__ nbr16;
+  int32_t* __restrict__ count;
+  DevStatus* status;
+};
+
+__device__ __forceinline__ double wave_min_d(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_max_d(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ __forceinline__ unsigned long long wave_or_u64(unsigned long long v) {
+  for (int off = 32; off > 0; off >>= 1) v |= __shfl_xor(v, off, 64);
+  return v;
+}
+
+struct TileState {
+  int64_t a;
+  bool valid;
+  double xa, ya, za, ha;
+  int usize, cnt, stored, ucap;
+  uint16_t* out;
+  int32_t* U;
+};
+
+// exact test of every lane's target against batch candidates cb[0..nb), nb <= 64
+__device__ __forceinline__ void run_batch(const BuildArgs& B, TileState& T, const double4* cb, const int32_t* cbi,
+                                          int nb, int periodic, double box) {
+  const int lane = threadIdx.x;
+  unsigned long long hm = 0ull;
+  if (T.valid) {
+    for (int j = 0; j < nb; ++j) {
+      const double4 pb = cb[j];
+      const bool hit = cbi[j] != T.a &&
+                       neighbour_test(min_image(T.xa - pb.x, periodic, box), min_image(T.ya - pb.y, periodic, box),
+                                      min_image(T.za - pb.z, periodic, box), T.ha, pb.w);
+      hm |= (unsigned long long)hit << j;
     }
   }
-  count[a] = cnt < cap ? cnt : cap;
-  if (cnt > cap) latch_error(status, SPH_E_NGB_CAPACITY, (int)a);
+  const unsigned long long um = wave_or_u64(hm);
+  if (!um) return;
+  const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  if ((um >> lane) & 1ull) {
+    const int loc = T.usize + __popcll(um & lt);
+    if (loc < T.ucap) T.U[loc] = cbi[lane];
+  }
+  unsigned long long mm = hm;
+  while (mm) {
+    const int j = __ffsll((long long)mm) - 1;
+    mm &= mm - 1ull;
+    const int loc = T.usize + __popcll(um & ((1ull << j) - 1ull));
+    if (T.cnt < B.cap && loc < T.ucap) {
+      T.out[(int64_t)T.cnt * B.capw] = (uint16_t)loc;
+      ++T.stored;
+    }
+    ++T.cnt;
+  }
+  T.usize += __popcll(um);
+}
+
+__global__ __launch_bounds__(64) void k_build_tiles(BuildArgs B) {
+  __shared__ int32_t c_s[64], c_o[64];
+  __shared__ double4 cb[128];
+  __shared__ int32_t cbi[128];
+  const int lane = threadIdx.x;
+  const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const GridInfo& g = *B.grid;
+  const int periodic = g.periodic;
+  const double box = g.box;
+  const int64_t ntiles = (int64_t)g.ntiles < B.cap_tiles ? (int64_t)g.ntiles : B.cap_tiles;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int32_t tcnt = B.tile_cnt[t];
+    const int64_t p = (int64_t)B.tile_start[t] + lane;
+    TileState T;
+    T.valid = lane < tcnt;
+    T.a = T.valid ? (B.identity ? p : (int64_t)B.perm[p]) : -1;
+    double4 pa = T.valid ? B.pos4[T.a] : make_double4(0.0, 0.0, 0.0, 0.0);
+    T.xa = pa.x; T.ya = pa.y; T.za = pa.z; T.ha = pa.w;
+    const double big = 1e300;
+    double lo[3], hi[3];
+    lo[0] = wave_min_d(T.valid ? pa.x : big); hi[0] = wave_max_d(T.valid ? pa.x : -big);
+    lo[1] = wave_min_d(T.valid ? pa.y : big); hi[1] = wave_max_d(T.valid ? pa.y : -big);
+    lo[2] = wave_min_d(T.valid ? pa.z : big); hi[2] = wave_max_d(T.valid ? pa.z : -big);
+    const double hmx = wave_max_d(T.valid ? pa.w : 0.0);
+    double cen[3], hw[3];
+    for (int d = 0; d < 3; ++d) { cen[d] = 0.5 * (lo[d] + hi[d]); hw[d] = 0.5 * (hi[d] - lo[d]); }
+    const uint32_t uoff = B.tile_uoff[t];
+    T.ucap = (int)((int64_t)tcnt * B.cap < B.ucap ? (int64_t)tcnt * B.cap : B.ucap);
+    if ((int64_t)uoff + T.ucap > B.upool) {
+      T.ucap = 0;
+      if (lane == 0) latch_error(B.status, SPH_E_NGB_CAPACITY, -1);
+    }
+    T.U = B.tile_u + uoff;
+    T.out = B.nbr16 + (T.valid ? p : 0);
+    T.usize = 0; T.cnt = 0; T.stored = 0;
+    int pend = 0;   // candidates waiting in cb (wave-uniform)
+    for (int l = 0; l < g.nlev; ++l) {
+      const double c = g.cell[l];
+      const double R = (hmx + g.hlev[l]) * (1.0 + 1e-9);
+      const double R2 = R * R;
+      int lo3[3], ext[3];
+      bool wrap[3];
+      for (int d = 0; d < 3; ++d) {
+        const int dim = g.dims[l][d];
+        int l0 = (int)floor((lo[d] - R - g.lo[d]) / c);
+        int h0 = (int)floor((hi[d] + R - g.lo[d]) / c);
+        wrap[d] = false;
+        if (periodic) {
+          if (h0 - l0 + 1 >= dim) { l0 = 0; h0 = dim - 1; }
+          else wrap[d] = true;
+        } else {
+          l0 = l0 < 0 ? 0 : l0;
+          h0 = h0 > dim - 1 ? dim - 1 : h0;
+        }
+        lo3[d] = l0;
+        ext[d] = h0 >= l0 ? h0 - l0 + 1 : 0;
+      }
+      const int64_t total = (int64_t)ext[0] * ext[1] * ext[2];
+      const uint32_t base = g.base[l];
+      for (int64_t q = 0; q < total; q += 64) {
+        // phase 1: 64 cells at once
+        const int64_t j = q + lane;
+        int32_t s = 0, e = 0;
+        if (j < total) {
+          const int kx = lo3[0] + (int)(j % ext[0]);
+          const int ky = lo3[1] + (int)((j / ext[0]) % ext[1]);
+          const int kz = lo3[2] + (int)(j / ((int64_t)ext[0] * ext[1]));
+          const int kk[3] = {kx, ky, kz};
+          double gap2 = 0.0;
+          int cc[3];
+          for (int d = 0; d < 3; ++d) {
+            if (!periodic || wrap[d]) {
+              const double b0 = g.lo[d] + kk[d] * c, b1 = b0 + c;
+              const double gd = fmax(0.0, fmax(b0 - hi[d], lo[d] - b1));
+              gap2 += gd * gd;
+            }
+            const int dim = g.dims[l][d];
+            cc[d] = wrap[d] ? ((kk[d] % dim) + dim) % dim : kk[d];
+          }
+          if (gap2 < R2) {
+            const uint32_t key = base + (spread3((uint32_t)cc[0]) | (spread3((uint32_t)cc[1]) << 1) |
+                                         (spread3((uint32_t)cc[2]) << 2));
+            const int32_t s0 = B.cstart[key];
+            if (s0 >= 0 && s0 < B.n && B.skeys[s0] == key) {
+              s = s0;
+              e = B.cend[key];
+            }
+          }
+        }
+        // wave prefix sum of the cells' particle counts
+        const int cntc = e - s;
+        int inc = cntc;
+        for (int off = 1; off < 64; off <<= 1) {
+          const int o = __shfl_up(inc, off, 64);
+          if (lane >= off) inc += o;
+        }
+        const int Tc = __shfl(inc, 63, 64);
+        __syncthreads();
+        c_s[lane] = s;
+        c_o[lane] = inc - cntc;
+        __syncthreads();
+        // phase 2: gather candidates 64 at a time, pre-test against the tile box
+        for (int q0 = 0; q0 < Tc; q0 += 64) {
+          const int slot = q0 + lane;
+          const bool has = slot < Tc;
+          double4 pb = make_double4(0.0, 0.0, 0.0, 0.0);
+          int32_t b = 0;
+          bool pass = false;
+          if (has) {
+            int lo_i = 0, hi_i = 63;   // last cell with c_o <= slot
+            while (lo_i < hi_i) {
+              const int mid = (lo_i + hi_i + 1) >> 1;
+              if (c_o[mid] <= slot) lo_i = mid;
+              else hi_i = mid - 1;
+            }
+            const int32_t sp = c_s[lo_i] + (slot - c_o[lo_i]);
+            b = B.identity ? sp : (int32_t)B.perm[sp];
+            pb = B.pos4[b];
+            const double ex = fmax(0.0, fabs(min_image(pb.x - cen[0], periodic, box)) - hw[0]);
+            const double ey = fmax(0.0, fabs(min_image(pb.y - cen[1], periodic, box)) - hw[1]);
+            const double ez = fmax(0.0, fabs(min_image(pb.z - cen[2], periodic, box)) - hw[2]);
+            const double Rb = (hmx + pb.w) * (1.0 + 1e-9);
+            pass = ex * ex + ey * ey + ez * ez < Rb * Rb;
+          }
+          const unsigned long long m = __ballot(pass);
+          if (pass) {
+            const int k = pend + __popcll(m & lt);
+            cb[k] = pb;
+            cbi[k] = b;
+          }
+          pend += __popcll(m);
+          __syncthreads();
+          if (pend >= 64) {   // phase 3 on a full batch
+            run_batch(B, T, cb, cbi, 64, periodic, box);
+            const int rest = pend - 64;
+            double4 mv = make_double4(0.0, 0.0, 0.0, 0.0);
+            int32_t mi = 0;
+            if (lane < rest) { mv = cb[64 + lane]; mi = cbi[64 + lane]; }
+            __syncthreads();
+            if (lane < rest) { cb[lane] = mv; cbi[lane] = mi; }
+            pend = rest;
+            __syncthreads();
+          }
+        }
+      }
+    }
+    if (pend > 0) run_batch(B, T, cb, cbi, pend, periodic, box);
+    __syncthreads();
+    if (T.valid) B.count[p] = T.stored;
+    if (lane == 0) B.tile_usize[t] = T.usize < T.ucap ? T.usize : T.ucap;
+    if (T.usize > T.ucap || T.cnt > B.cap) latch_error(B.status, SPH_E_NGB_CAPACITY, (int)(T.valid ? T.a : -1));
+  }
+}
+
+__global__ __launch_bounds__(kB) void k_count_stats(const int32_t* __restrict__ cnt, int64_t n,
+                                                    unsigned long long* total, int32_t* mx) {
+  unsigned long long s = 0;
+  int m = 0;
+  for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < n; a += (int64_t)gridDim.x * blockDim.x) {
+    s += (unsigned long long)cnt[a];
+    m = cnt[a] > m ? cnt[a] : m;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    s += __shfl_xor(s, off, 64);
+    int o = __shfl_xor(m, off, 64);
+    m = o > m ? o : m;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(total, s);
+    atomicMax(mx, m);
+  }
 }
 
 template <typename T>
@@ -309,6 +570,10 @@ sph_status permute_array(sph_ctx* c, T* arr, int64_t n) {
 
 // Bin particles into the multi-level grid and build the neighbour lists.  With permute, every
 // particle array of the state (and the half-step copies) is reordered into cell order first.
+static unsigned tile_grid(const sph_ctx* c) {
+  return (unsigned)(c->cap_tiles < 65536 ? c->cap_tiles : 65536);
+}
+
 sph_status sph_rebin(sph_ctx* c, sph_state* st, bool permute) {
   const int64_t n = st->n;
   hipStream_t s = c->stream;
@@ -317,9 +582,9 @@ sph_status sph_rebin(sph_ctx* c, sph_state* st, bool permute) {
   // absolute positions for binning (ensemble stars are placed apart in one frame)
   hipLaunchKernelGGL(k_pack_pos, dim3(nb), dim3(kB), 0, s, st->x, st->y, st->z, st->h,
                      (const int32_t*)nullptr, (const StarInfo*)nullptr, n, c->pos4, (float4*)nullptr);
-  hipLaunchKernelGGL(k_grid_reset, dim3(1), dim3(1), 0, s, c->grid);
-  hipLaunchKernelGGL(k_bounds, dim3(nred), dim3(kB), 0, s, c->pos4, n, c->grid);
-  hipLaunchKernelGGL(k_grid_setup1, dim3(1), dim3(1), 0, s, c->grid, c->p.periodic, c->p.box, c->status);
+  hipLaunchKernelGGL(k_bounds, dim3(nred), dim3(kB), 0, s, c->pos4, n, c->sort.partial);
+  hipLaunchKernelGGL(k_grid_setup1, dim3(1), dim3(64), 0, s, c->grid, c->sort.partial, (int)nred, c->p.periodic,
+                     c->p.box, c->status);
   hipLaunchKernelGGL(k_level_hmax, dim3(nred), dim3(kB), 0, s, c->pos4, n, c->grid);
   hipLaunchKernelGGL(k_grid_setup2, dim3(1), dim3(1), 0, s, c->grid, c->p.cell_div > 0 ? c->p.cell_div : 2,
                      c->max_cells, c->status);
@@ -342,14 +607,29 @@ sph_status sph_rebin(sph_ctx* c, sph_state* st, bool permute) {
     if ((e = permute_array(c, st->id, n))) return e;
     if ((e = permute_array(c, st->star, n))) return e;
     hipLaunchKernelGGL(k_identity, dim3(nb), dim3(kB), 0, s, c->vals, n);
+    hipLaunchKernelGGL(k_pack_pos, dim3(nb), dim3(kB), 0, s, st->x, st->y, st->z, st->h,
+                       (const int32_t*)nullptr, (const StarInfo*)nullptr, n, c->pos4, (float4*)nullptr);
     c->identity_perm = 1;
   } else {
     c->identity_perm = 0;
   }
   hipLaunchKernelGGL(k_cell_ranges, dim3(nb), dim3(kB), 0, s, c->keys, n, c->cell_start, c->cell_end);
-  hipLaunchKernelGGL(k_build_lists, dim3(nb), dim3(kB), 0, s, st->x, st->y, st->z, st->h, n, c->grid,
-                     c->keys, c->vals, c->identity_perm, c->cell_start, c->cell_end, c->cap, c->nbr,
-                     c->nbr_count, c->status);
+  uint32_t* tile_idx = reinterpret_cast<uint32_t*>(c->tmp);   // 0/1 tile starts, scanned in place
+  hipLaunchKernelGGL(k_tile_marks, dim3(nb), dim3(kB), 0, s, c->keys, n, c->grid, c->cell_start, c->cell_end,
+                     c->tile_flag, tile_idx);
+  if ((e = sph_scan_u32(c, tile_idx, tile_idx, n, &c->grid->ntiles))) return e;
+  hipLaunchKernelGGL(k_tile_fill, dim3(nb), dim3(kB), 0, s, c->tile_flag, tile_idx, n, c->cap_tiles, c->tile_start,
+                     c->tile_cnt, c->status);
+  hipLaunchKernelGGL(k_tile_ubound, dim3(grid_for(c->cap_tiles, kB)), dim3(kB), 0, s, c->grid, c->tile_cnt,
+                     c->cap_tiles, c->cap, c->ucap, c->tile_uoff);
+  if ((e = sph_scan_u32(c, c->tile_uoff, c->tile_uoff, c->cap_tiles, &c->grid->upool_used))) return e;
+  BuildArgs B;
+  B.pos4 = c->pos4; B.n = n; B.grid = c->grid; B.skeys = c->keys; B.perm = c->vals;
+  B.identity = c->identity_perm; B.cstart = c->cell_start; B.cend = c->cell_end;
+  B.tile_start = c->tile_start; B.tile_cnt = c->tile_cnt; B.cap_tiles = c->cap_tiles; B.capw = c->capw;
+  B.cap = c->cap; B.ucap = c->ucap; B.tile_uoff = c->tile_uoff; B.upool = c->upool; B.tile_u = c->tile_u;
+  B.tile_usize = c->tile_usize; B.nbr16 = c->nbr16; B.count = c->nbr_count; B.status = c->status;
+  hipLaunchKernelGGL(k_build_tiles, dim3(tile_grid(c)), dim3(64), 0, s, B);
   HIP_TRY(hipGetLastError());
   return launch_pack(c, st);
 }
@@ -361,4 +641,24 @@ sph_status launch_pack(sph_ctx* c, sph_state* st) {
                      st->star, c->stars, n, c->pos4, c->p.precision == SPH_FP32 ? c->pos4f : nullptr);
   HIP_TRY(hipGetLastError());
   return SPH_OK;
+}
+
+sph_status sph_count_stats(sph_ctx* c, int64_t* total, int32_t* mx) {
+  struct R { unsigned long long t; int32_t m; int32_t pad; };
+  R* d = nullptr;
+  if (hipMalloc((void**)&d, sizeof(R)) != hipSuccess) return SPH_E_OOM;
+  R h = {0ull, 0, 0};
+  sph_status e = SPH_OK;
+  if (hipMemcpy(d, &h, sizeof(R), hipMemcpyHostToDevice) != hipSuccess) e = SPH_E_HIP;
+  if (!e && c->n > 0) {
+    unsigned nb = grid_for(c->n, kB);
+    hipLaunchKernelGGL(k_count_stats, dim3(nb < 1024 ? nb : 1024), dim3(kB), 0, c->stream, c->nbr_count, c->n,
+                       &d->t, &d->m);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) e = SPH_E_HIP;
+  }
+  if (!e && hipMemcpy(&h, d, sizeof(R), hipMemcpyDeviceToHost) != hipSuccess) e = SPH_E_HIP;
+  (void)hipFree(d);
+  *total = (int64_t)h.t;
+  *mx = h.m;
+  return e;
 }

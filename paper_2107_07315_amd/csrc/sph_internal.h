@@ -29,6 +29,8 @@ struct GridInfo {
   int32_t nlev;
   int32_t periodic;
   double box;
+  uint32_t ntiles;      // tiles of the current lists (written on the device)
+  uint32_t upool_used;  // union-pool entries reserved by the tiles
 };
 
 // Per-star parameters of an ensemble (centre of the star's background, particle mass and
@@ -188,6 +190,10 @@ __device__ __forceinline__ void yield_scale(int mode, double Y0, double* s) {
 struct SortScratch {
   uint32_t *keys_alt, *vals_alt;
   uint32_t* hist;        // 256 * max_blocks
+  uint32_t* rowtot;      // 256 digit totals / offsets
+  unsigned long long* partial;  // per-block reduction partials of the grid set-up (8 per block)
+  uint32_t* scan_bsum;   // generic scan: per-block sums
+  int64_t scan_cap;      // blocks of 1024 the generic scan can take
   int max_blocks;
 };
 
@@ -211,10 +217,23 @@ struct sph_ctx {
   int32_t *cell_start, *cell_end;
   int64_t max_cells;
   SortScratch sort;
-  // neighbour lists: entry k of particle a at ((a>>6)*cap + k)*64 + (a&63)
-  int32_t* nbr;
+  // tile neighbour lists: tile t = sorted positions [tile_start[t], tile_start[t] + tile_cnt[t])
+  // (at most 64, never crossing a super-cell of 2x2x2 cells); U_t = tile_u + tile_uoff[t] holds the
+  // union of the tile's neighbours (particle indices); entry k of sorted position p is the local
+  // index nbr16[k*capw + p] into U_t; nbr_count is indexed by sorted position
+  int32_t* tile_start;
+  int32_t* tile_cnt;
+  int32_t* tile_u;      // union pool; tile t owns [tile_uoff[t], tile_uoff[t] + min(ucap, cnt*cap))
+  uint32_t* tile_uoff;
+  int64_t upool;        // pool entries
+  int32_t* tile_usize;
+  uint16_t* nbr16;
   int32_t* nbr_count;
+  uint32_t* tile_flag;  // scratch: per sorted position tile length (0 = not a tile start), then scan
+  int64_t capw;         // capacity rounded up to 64
+  int64_t cap_tiles;
   int32_t cap;
+  int32_t ucap;
   // packed gather records (FP64 and FP32 variants)
   double4* pos4;        // x, y, z, h
   double4* fv;          // vx, vy, vz, cs
@@ -250,6 +269,8 @@ sph_status launch_forces(sph_ctx* c, sph_state* st);
 sph_status launch_kick_drift(sph_ctx* c, sph_state* st, double dt);
 sph_status launch_kick_final(sph_ctx* c, sph_state* st, double dt);
 sph_status launch_pack(sph_ctx* c, sph_state* st);
+sph_status sph_count_stats(sph_ctx* c, int64_t* total, int32_t* mx);
+sph_status sph_scan_u32(sph_ctx* c, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total);
 
 enum { TIMER_CELLS = 0, TIMER_DENSITY = 1, TIMER_STRESS = 2, TIMER_FORCES = 3, TIMER_KDK = 4 };
 void timer_begin(sph_ctx* c, int which);

@@ -1,11 +1,13 @@
 // Pair passes of the particle loop: density (+ EoS epilogue), velocity gradient / stress rate,
 // and momentum/energy forces (+ fixed-background epilogue).
 //
-// One thread per target particle; a wavefront holds 64 consecutive particles of the cell order
-// and walks their neighbour lists in lockstep (the lists are interleaved per wavefront, so each
-// list read is one 256-byte segment).  Neighbour data is gathered from packed records written
-// by the previous pass.  The pair arithmetic is templated on the pair precision R: double in
-// the FP64 path, float in the mixed-precision path; epilogues (metric, EoS, GR terms) are FP64.
+// One workgroup = one wavefront = one tile of 64 consecutive particles of the cell order (one
+// lane per target).  The tile's neighbour union U is streamed through LDS in chunks of CH packed
+// records (loaded by the whole wave, runs of consecutive particles, so the loads coalesce); each
+// lane walks its ascending 16-bit local list and reads its neighbours' records from LDS.  This
+// replaces scattered per-lane gathers from L2 with one staged load per union member.  The pair
+// arithmetic is templated on the pair precision R: double in the FP64 path, float in the
+// mixed-precision path; epilogues (metric, EoS, GR terms) are FP64.
 #include "sph_internal.h"
 
 namespace {
@@ -31,23 +33,73 @@ template <> struct Rec<double> {
   using P4 = double4;
   using V4 = double4;
   using A2 = double2;
+  static constexpr int CH_POS = 256;    // LDS records per chunk: 8 KB (density)
+  static constexpr int CH_PV = 128;     // 8 KB (stress)
+  static constexpr int CH_ALL = 128;    // 10 KB (forces)
 };
 template <> struct Rec<float> {
   using P4 = float4;
   using V4 = float4;
   using A2 = float2;
+  static constexpr int CH_POS = 512;
+  static constexpr int CH_PV = 256;
+  static constexpr int CH_ALL = 256;
 };
 
 struct PassArgs {
   sph_params p;
   int64_t n;
-  int cap;
-  const int32_t* __restrict__ nbr;
+  int cap, ucap;
+  int64_t capw, cap_tiles;
+  const GridInfo* __restrict__ grid;
+  const int32_t* __restrict__ tile_start;
+  const int32_t* __restrict__ tile_cnt;
+  const int32_t* __restrict__ tile_u;
+  const uint32_t* __restrict__ tile_uoff;
+  const int32_t* __restrict__ tile_usize;
+  const uint16_t* __restrict__ nbr16;
   const int32_t* __restrict__ cnt;
+  const uint32_t* __restrict__ perm;
+  int identity;
   const int32_t* __restrict__ star;
   const StarInfo* __restrict__ stars;
   DevStatus* status;
 };
+
+constexpr int kNone = 0x7fffffff;
+
+// Per-lane view of the tile lists.
+struct TileWalk {
+  int64_t t, p, a;
+  bool valid;
+  int usize, cnt, k, next;
+  const uint16_t* lst;
+  const int32_t* U;
+  int64_t stride;
+  __device__ __forceinline__ void init(const PassArgs& A, int64_t tile) {
+    t = tile;
+    const int tc = A.tile_cnt[t];
+    p = (int64_t)A.tile_start[t] + threadIdx.x;
+    valid = (int)threadIdx.x < tc;
+    a = valid ? (A.identity ? p : (int64_t)A.perm[p]) : 0;
+    usize = A.tile_usize[t];
+    cnt = valid ? A.cnt[p] : 0;
+    stride = A.capw;
+    lst = A.nbr16 + (valid ? p : 0);
+    U = A.tile_u + A.tile_uoff[t];
+    k = 0;
+    next = cnt > 0 ? (int)lst[0] : kNone;
+  }
+  __device__ __forceinline__ void advance() {
+    ++k;
+    next = k < cnt ? (int)lst[(int64_t)k * stride] : kNone;
+  }
+};
+
+__device__ __forceinline__ int64_t num_tiles(const PassArgs& A) {
+  const int64_t nt = (int64_t)A.grid->ntiles;
+  return nt < A.cap_tiles ? nt : A.cap_tiles;
+}
 
 __device__ __forceinline__ double particle_mass(const PassArgs& A, int64_t a) {
   return (A.star && A.stars) ? A.stars[A.star[a]].m : A.p.m;
@@ -61,27 +113,31 @@ __device__ __forceinline__ void star_centre(const PassArgs& A, int64_t a, double
 }
 
 // ---- equation of state -------------------------------------------------------------------------
+__device__ __forceinline__ bool bilinear(const double* __restrict__ T, int64_t o, int nu, double a, double b,
+                                         double& v) {
+  const double f00 = T[o], f01 = T[o + 1], f10 = T[o + nu], f11 = T[o + nu + 1];
+  if (!isfinite(f00) || !isfinite(f01) || !isfinite(f10) || !isfinite(f11)) return false;
+  v = (1.0 - a) * ((1.0 - b) * f00 + b * f01) + a * ((1.0 - b) * f10 + b * f11);
+  return true;
+}
+
 __device__ __forceinline__ int eos_eval(const sph_params& p, double rho, double u, double& P, double& cs2) {
   if (p.eos == SPH_EOS_TABLE || p.eos == SPH_EOS_MLP) {
     if (!(rho > 0.0) || !(u > 0.0)) return SPH_E_EOS_DOMAIN;
-    double fr = (log(rho) - p.tab_lnr0) / p.tab_dlnr;
-    double fu = (log(u) - p.tab_lnu0) / p.tab_dlnu;
+    const double fr = (log(rho) - p.tab_lnr0) / p.tab_dlnr;
+    const double fu = (log(u) - p.tab_lnu0) / p.tab_dlnu;
     if (!(fr >= 0.0) || !(fu >= 0.0) || fr > (double)(p.tab_nr - 1) || fu > (double)(p.tab_nu - 1))
       return SPH_E_EOS_DOMAIN;
     int i = (int)floor(fr), j = (int)floor(fu);
     i = i > p.tab_nr - 2 ? p.tab_nr - 2 : i;
     j = j > p.tab_nu - 2 ? p.tab_nu - 2 : j;
-    double a = fr - (double)i, b = fu - (double)j;
-    int64_t o = (int64_t)i * p.tab_nu + j;
-    double v[2];
-    const double* T[2] = {p.tab_lnP, p.tab_lncs2};
-    for (int k = 0; k < 2; ++k) {
-      double f00 = T[k][o], f01 = T[k][o + 1], f10 = T[k][o + p.tab_nu], f11 = T[k][o + p.tab_nu + 1];
-      if (!isfinite(f00) || !isfinite(f01) || !isfinite(f10) || !isfinite(f11)) return SPH_E_EOS_DOMAIN;
-      v[k] = (1.0 - a) * ((1.0 - b) * f00 + b * f01) + a * ((1.0 - b) * f10 + b * f11);
-    }
-    P = exp(v[0]);
-    cs2 = exp(v[1]);
+    const double a = fr - (double)i, b = fu - (double)j;
+    const int64_t o = (int64_t)i * p.tab_nu + j;
+    double lp, lc;
+    if (!bilinear(p.tab_lnP, o, p.tab_nu, a, b, lp) || !bilinear(p.tab_lncs2, o, p.tab_nu, a, b, lc))
+      return SPH_E_EOS_DOMAIN;
+    P = exp(lp);
+    cs2 = exp(lc);
     return 0;
   }
   P = (p.gamma - 1.0) * rho * u;
@@ -101,31 +157,43 @@ struct DensOut {
 };
 
 template <typename R>
-__global__ __launch_bounds__(kB) void k_density(PassArgs A, const typename Rec<R>::P4* __restrict__ pos,
-                                                const double4* __restrict__ pos64, const double* __restrict__ vx, const double* __restrict__ vy,
-                                                const double* __restrict__ vz, const double* __restrict__ u,
-                                                const double* __restrict__ S, const int8_t* __restrict__ type,
-                                                const uint8_t* __restrict__ broken, DensOut O) {
-  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= A.n) return;
+__global__ __launch_bounds__(64) void k_density(PassArgs A, const typename Rec<R>::P4* __restrict__ pos,
+                                                const double4* __restrict__ pos64, const double* __restrict__ vx,
+                                                const double* __restrict__ vy, const double* __restrict__ vz,
+                                                const double* __restrict__ u, const double* __restrict__ S,
+                                                const int8_t* __restrict__ type, const uint8_t* __restrict__ broken,
+                                                DensOut O) {
+  using P4 = typename Rec<R>::P4;
+  constexpr int CH = Rec<R>::CH_POS;
+  __shared__ P4 sp[CH];
+  const int64_t ntl = num_tiles(A);
+  for (int64_t tile = blockIdx.x; tile < ntl; tile += gridDim.x) {
+  TileWalk tw;
+  tw.init(A, tile);
+  const int64_t a = tw.a;
   const sph_params& p = A.p;
-  const typename Rec<R>::P4 pa = pos[a];
   const int periodic = p.periodic;
   const R box = (R)p.box;
+  P4 pa = tw.valid ? pos[a] : P4{0, 0, 0, 1};
   R sum = wendland_self<R>(p.kernel, pa.w);
-  const int32_t* lst = A.nbr + ((a >> 6) * (int64_t)A.cap) * 64 + (a & 63);
-  const int nn = A.cnt[a];
-  for (int k = 0; k < nn; ++k) {
-    const int32_t b = lst[(int64_t)k * 64];
-    const typename Rec<R>::P4 pb = pos[b];
-    R dx = min_image<R>(pa.x - pb.x, periodic, box);
-    R dy = min_image<R>(pa.y - pb.y, periodic, box);
-    R dz = min_image<R>(pa.z - pb.z, periodic, box);
-    R r = sqrt(dx * dx + dy * dy + dz * dz);
-    R W, F;
-    wendland<R>(p.kernel, r, (R)0.5 * (pa.w + pb.w), W, F);
-    sum += W;
+  for (int c0 = 0; c0 < tw.usize; c0 += CH) {
+    __syncthreads();
+    for (int j = threadIdx.x; j < CH && c0 + j < tw.usize; j += 64) sp[j] = pos[tw.U[c0 + j]];
+    __syncthreads();
+    const int cend = c0 + CH;
+    while (tw.next < cend) {
+      const P4 pb = sp[tw.next - c0];
+      R dx = min_image<R>(pa.x - pb.x, periodic, box);
+      R dy = min_image<R>(pa.y - pb.y, periodic, box);
+      R dz = min_image<R>(pa.z - pb.z, periodic, box);
+      R r = sqrt(dx * dx + dy * dy + dz * dz);
+      R W, F;
+      wendland<R>(p.kernel, r, (R)0.5 * (pa.w + pb.w), W, F);
+      sum += W;
+      tw.advance();
+    }
   }
+  if (!tw.valid) continue;
   const double m = particle_mass(A, a);
   const double D = m * (double)sum;
   // epilogue in FP64: rest-mass density from D = rho psi^6 W_L, EoS, shear modulus, yield stress
@@ -176,47 +244,67 @@ __global__ __launch_bounds__(kB) void k_density(PassArgs A, const typename Rec<R
     for (int c = 0; c < 6; ++c) O.sigf[c * n + a] = (float)(S[c * n + a] * iD2);
   }
   if (!isfinite(D) || !isfinite(P) || !isfinite(cs)) latch_error(A.status, SPH_E_NONFINITE, (int)a);
+  }
 }
 
 // ---- velocity gradient and stress rate ---------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(kB) void k_stress(PassArgs A, const typename Rec<R>::P4* __restrict__ pos,
+__global__ __launch_bounds__(64) void k_stress(PassArgs A, const typename Rec<R>::P4* __restrict__ pos,
                                                const typename Rec<R>::V4* __restrict__ fv,
                                                const typename Rec<R>::A2* __restrict__ fa,
                                                const double* __restrict__ S, const double* __restrict__ mu,
                                                double* __restrict__ dSdt, double* __restrict__ sdot) {
-  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= A.n) return;
+  using P4 = typename Rec<R>::P4;
+  using V4 = typename Rec<R>::V4;
+  constexpr int CH = Rec<R>::CH_PV;
+  __shared__ P4 sp[CH];
+  __shared__ V4 sv[CH];
+  const int64_t ntl = num_tiles(A);
+  for (int64_t tile = blockIdx.x; tile < ntl; tile += gridDim.x) {
+  TileWalk tw;
+  tw.init(A, tile);
+  const int64_t a = tw.a;
   const int64_t n = A.n;
-  const typename Rec<R>::A2 faa = fa[a];
-  if (!(faa.y < 0)) {  // fluid particle (or fluidized): no deviatoric stress evolution
+  const typename Rec<R>::A2 faa = tw.valid ? fa[a] : typename Rec<R>::A2{0, 1};
+  const bool stressed = tw.valid && faa.y < 0;
+  if (tw.valid && !stressed) {  // fluid particle (or fluidized): no deviatoric stress evolution
     for (int c = 0; c < 6; ++c) dSdt[c * n + a] = 0.0;
     sdot[a] = 0.0;
-    return;
   }
+  if (!__ballot(stressed)) continue;   // whole tile fluid
+  if (!stressed) tw.cnt = 0, tw.next = kNone;
   const sph_params& p = A.p;
-  const typename Rec<R>::P4 pa = pos[a];
-  const typename Rec<R>::V4 va = fv[a];
+  const P4 pa = tw.valid ? pos[a] : P4{0, 0, 0, 1};
+  const V4 va = tw.valid ? fv[a] : V4{0, 0, 0, 0};
   const int periodic = p.periodic;
   const R box = (R)p.box;
   R G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  const int32_t* lst = A.nbr + ((a >> 6) * (int64_t)A.cap) * 64 + (a & 63);
-  const int nn = A.cnt[a];
-  for (int k = 0; k < nn; ++k) {
-    const int32_t b = lst[(int64_t)k * 64];
-    const typename Rec<R>::P4 pb = pos[b];
-    const typename Rec<R>::V4 vb = fv[b];
-    R d[3] = {min_image<R>(pa.x - pb.x, periodic, box), min_image<R>(pa.y - pb.y, periodic, box),
-              min_image<R>(pa.z - pb.z, periodic, box)};
-    R r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    R F = wendland_F<R>(p.kernel, r, (R)0.5 * (pa.w + pb.w));
-    R g[3] = {F * d[0], F * d[1], F * d[2]};
-    R v[3] = {vb.x - va.x, vb.y - va.y, vb.z - va.z};
+  for (int c0 = 0; c0 < tw.usize; c0 += CH) {
+    __syncthreads();
+    for (int j = threadIdx.x; j < CH && c0 + j < tw.usize; j += 64) {
+      const int32_t b = tw.U[c0 + j];
+      sp[j] = pos[b];
+      sv[j] = fv[b];
+    }
+    __syncthreads();
+    const int cend = c0 + CH;
+    while (tw.next < cend) {
+      const P4 pb = sp[tw.next - c0];
+      const V4 vb = sv[tw.next - c0];
+      R d[3] = {min_image<R>(pa.x - pb.x, periodic, box), min_image<R>(pa.y - pb.y, periodic, box),
+                min_image<R>(pa.z - pb.z, periodic, box)};
+      R r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      R F = wendland_F<R>(p.kernel, r, (R)0.5 * (pa.w + pb.w));
+      R g[3] = {F * d[0], F * d[1], F * d[2]};
+      R v[3] = {vb.x - va.x, vb.y - va.y, vb.z - va.z};
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+      for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int j = 0; j < 3; ++j) G[i][j] += v[i] * g[j];
+        for (int jj = 0; jj < 3; ++jj) G[i][jj] += v[i] * g[jj];
+      tw.advance();
+    }
   }
+  if (!stressed) continue;
   const double m = particle_mass(A, a);
   const double D = -(double)faa.y;  // stressed particles store -D
   const double iD2 = m / (2.0 * D);
@@ -257,6 +345,7 @@ __global__ __launch_bounds__(kB) void k_stress(PassArgs A, const typename Rec<R>
 #pragma unroll
     for (int j = 0; j < 3; ++j) se += Sm[i][j] * ed[i][j];
   sdot[a] = se / D;   // stress work S^ij epsdot^ij / rho of eq. solid3
+  }
 }
 
 // ---- forces -----------------------------------------------------------------------------------
@@ -265,20 +354,30 @@ struct ForceOut {
 };
 
 template <typename R>
-__global__ __launch_bounds__(kB) void k_forces(PassArgs A, const typename Rec<R>::P4* __restrict__ pos,
+__global__ __launch_bounds__(64) void k_forces(PassArgs A, const typename Rec<R>::P4* __restrict__ pos,
                                                const typename Rec<R>::V4* __restrict__ fv,
                                                const typename Rec<R>::A2* __restrict__ fa,
                                                const R* __restrict__ sig, const double4* __restrict__ pos64,
                                                const double* __restrict__ u, const double* __restrict__ P,
                                                const double* __restrict__ rho, const double* __restrict__ sdot,
                                                ForceOut O) {
-  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= A.n) return;
+  using P4 = typename Rec<R>::P4;
+  using V4 = typename Rec<R>::V4;
+  using A2 = typename Rec<R>::A2;
+  constexpr int CH = Rec<R>::CH_ALL;
+  __shared__ P4 sp[CH];
+  __shared__ V4 sv[CH];
+  __shared__ A2 sa2[CH];
+  const int64_t ntl = num_tiles(A);
+  for (int64_t tile = blockIdx.x; tile < ntl; tile += gridDim.x) {
+  TileWalk tw;
+  tw.init(A, tile);
+  const int64_t a = tw.a;
   const int64_t n = A.n;
   const sph_params& p = A.p;
-  const typename Rec<R>::P4 pa = pos[a];
-  const typename Rec<R>::V4 va = fv[a];
-  const typename Rec<R>::A2 faa = fa[a];
+  const P4 pa = tw.valid ? pos[a] : P4{0, 0, 0, 1};
+  const V4 va = tw.valid ? fv[a] : V4{0, 0, 0, 0};
+  const A2 faa = tw.valid ? fa[a] : A2{0, 1};
   const bool a_st = faa.y < 0;
   const R Da = a_st ? -faa.y : faa.y;
   const R pia = faa.x;
@@ -290,45 +389,57 @@ __global__ __launch_bounds__(kB) void k_forces(PassArgs A, const typename Rec<R>
   const R box = (R)p.box;
   const R alpha_v = (R)p.visc_alpha, beta_v = (R)p.visc_beta, eps_v = (R)p.visc_eps;
   R AP[3] = {0, 0, 0}, AS[3] = {0, 0, 0}, ud = 0;
-  const int32_t* lst = A.nbr + ((a >> 6) * (int64_t)A.cap) * 64 + (a & 63);
-  const int nn = A.cnt[a];
-  for (int k = 0; k < nn; ++k) {
-    const int32_t b = lst[(int64_t)k * 64];
-    const typename Rec<R>::P4 pb = pos[b];
-    const typename Rec<R>::V4 vb = fv[b];
-    const typename Rec<R>::A2 fab = fa[b];
-    R d[3] = {min_image<R>(pa.x - pb.x, periodic, box), min_image<R>(pa.y - pb.y, periodic, box),
-              min_image<R>(pa.z - pb.z, periodic, box)};
-    R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-    R r = sqrt(r2);
-    R hab = (R)0.5 * (pa.w + pb.w);
-    R F = wendland_F<R>(p.kernel, r, hab);
-    R g[3] = {F * d[0], F * d[1], F * d[2]};
-    R v[3] = {va.x - vb.x, va.y - vb.y, va.z - vb.z};
-    R vr = v[0] * d[0] + v[1] * d[1] + v[2] * d[2];
-    const bool b_st = fab.y < 0;
-    const R Db = b_st ? -fab.y : fab.y;
-    R Pi = 0;
-    if (vr < 0) {   // Monaghan viscosity on approaching pairs
-      R muab = hab * vr / (r2 + eps_v * hab * hab);
-      R cbar = (R)0.5 * (va.w + vb.w);
-      R Dbar = (R)0.5 * (Da + Db);
-      Pi = (-alpha_v * cbar * muab + beta_v * muab * muab) / Dbar;
+  for (int c0 = 0; c0 < tw.usize; c0 += CH) {
+    __syncthreads();
+    for (int j = threadIdx.x; j < CH && c0 + j < tw.usize; j += 64) {
+      const int32_t b = tw.U[c0 + j];
+      sp[j] = pos[b];
+      sv[j] = fv[b];
+      sa2[j] = fa[b];
     }
-    R cP = pia + fab.x + Pi;
-    AP[0] += cP * g[0];
-    AP[1] += cP * g[1];
-    AP[2] += cP * g[2];
-    ud += (pia + (R)0.5 * Pi) * (v[0] * g[0] + v[1] * g[1] + v[2] * g[2]);
-    if (a_st || b_st) {
-      R s[6];
+    __syncthreads();
+    const int cend = c0 + CH;
+    while (tw.next < cend) {
+      const int jl = tw.next - c0;
+      const P4 pb = sp[jl];
+      const V4 vb = sv[jl];
+      const A2 fab = sa2[jl];
+      R d[3] = {min_image<R>(pa.x - pb.x, periodic, box), min_image<R>(pa.y - pb.y, periodic, box),
+                min_image<R>(pa.z - pb.z, periodic, box)};
+      R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+      R r = sqrt(r2);
+      R hab = (R)0.5 * (pa.w + pb.w);
+      R F = wendland_F<R>(p.kernel, r, hab);
+      R g[3] = {F * d[0], F * d[1], F * d[2]};
+      R v[3] = {va.x - vb.x, va.y - vb.y, va.z - vb.z};
+      R vr = v[0] * d[0] + v[1] * d[1] + v[2] * d[2];
+      const bool b_st = fab.y < 0;
+      const R Db = b_st ? -fab.y : fab.y;
+      R Pi = 0;
+      if (vr < 0) {   // Monaghan viscosity on approaching pairs
+        R muab = hab * vr / (r2 + eps_v * hab * hab);
+        R cbar = (R)0.5 * (va.w + vb.w);
+        R Dbar = (R)0.5 * (Da + Db);
+        Pi = (-alpha_v * cbar * muab + beta_v * muab * muab) / Dbar;
+      }
+      R cP = pia + fab.x + Pi;
+      AP[0] += cP * g[0];
+      AP[1] += cP * g[1];
+      AP[2] += cP * g[2];
+      ud += (pia + (R)0.5 * Pi) * (v[0] * g[0] + v[1] * g[1] + v[2] * g[2]);
+      if (a_st || b_st) {
+        R s6[6];
+        const int32_t b = b_st ? tw.U[tw.next] : 0;
 #pragma unroll
-      for (int c = 0; c < 6; ++c) s[c] = sa[c] + (b_st ? sig[c * n + b] : (R)0);
-      AS[0] += s[0] * g[0] + s[3] * g[1] + s[4] * g[2];
-      AS[1] += s[3] * g[0] + s[1] * g[1] + s[5] * g[2];
-      AS[2] += s[4] * g[0] + s[5] * g[1] + s[2] * g[2];
+        for (int c = 0; c < 6; ++c) s6[c] = sa[c] + (b_st ? sig[c * n + b] : (R)0);
+        AS[0] += s6[0] * g[0] + s6[3] * g[1] + s6[4] * g[2];
+        AS[1] += s6[3] * g[0] + s6[1] * g[1] + s6[5] * g[2];
+        AS[2] += s6[4] * g[0] + s6[5] * g[1] + s6[2] * g[2];
+      }
+      tw.advance();
     }
   }
+  if (!tw.valid) continue;
   const double m = particle_mass(A, a);
   double APd[3] = {m * (double)AP[0], m * (double)AP[1], m * (double)AP[2]};
   double ASd[3] = {m * (double)AS[0], m * (double)AS[1], m * (double)AS[2]};
@@ -366,6 +477,7 @@ __global__ __launch_bounds__(kB) void k_forces(PassArgs A, const typename Rec<R>
   O.dudt[a] = du;
   if (!isfinite(acc[0]) || !isfinite(acc[1]) || !isfinite(acc[2]) || !isfinite(du))
     latch_error(A.status, SPH_E_NONFINITE, (int)a);
+  }
 }
 
 PassArgs make_args(sph_ctx* c, sph_state* st) {
@@ -373,8 +485,19 @@ PassArgs make_args(sph_ctx* c, sph_state* st) {
   A.p = c->p;
   A.n = st->n;
   A.cap = c->cap;
-  A.nbr = c->nbr;
+  A.ucap = c->ucap;
+  A.capw = c->capw;
+  A.cap_tiles = c->cap_tiles;
+  A.grid = c->grid;
+  A.tile_start = c->tile_start;
+  A.tile_cnt = c->tile_cnt;
+  A.tile_u = c->tile_u;
+  A.tile_uoff = c->tile_uoff;
+  A.tile_usize = c->tile_usize;
+  A.nbr16 = c->nbr16;
   A.cnt = c->nbr_count;
+  A.perm = c->vals;
+  A.identity = c->identity_perm;
   A.star = c->stars ? st->star : nullptr;
   A.stars = c->stars;
   A.status = c->status;
@@ -386,7 +509,7 @@ PassArgs make_args(sph_ctx* c, sph_state* st) {
 sph_status launch_density(sph_ctx* c, sph_state* st) {
   PassArgs A = make_args(c, st);
   DensOut O{st->D, st->rho, st->P, st->cs, c->mu, c->Y0, c->B, c->fv, c->fa, c->sig, c->fvf, c->faf, c->sigf};
-  dim3 g(grid_for(st->n, kB)), b(kB);
+  dim3 g((unsigned)(c->cap_tiles < 65536 ? c->cap_tiles : 65536)), b(64);
   if (c->p.precision == SPH_FP32)
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_density<float>), g, b, 0, c->stream, A, c->pos4f, c->pos4, st->vx, st->vy,
                        st->vz, st->u, st->S, st->type, st->broken, O);
@@ -399,7 +522,7 @@ sph_status launch_density(sph_ctx* c, sph_state* st) {
 
 sph_status launch_stress(sph_ctx* c, sph_state* st) {
   PassArgs A = make_args(c, st);
-  dim3 g(grid_for(st->n, kB)), b(kB);
+  dim3 g((unsigned)(c->cap_tiles < 65536 ? c->cap_tiles : 65536)), b(64);
   if (c->p.precision == SPH_FP32)
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stress<float>), g, b, 0, c->stream, A, c->pos4f, c->fvf, c->faf, st->S,
                        c->mu, st->dSdt, c->sdot);
@@ -413,7 +536,7 @@ sph_status launch_stress(sph_ctx* c, sph_state* st) {
 sph_status launch_forces(sph_ctx* c, sph_state* st) {
   PassArgs A = make_args(c, st);
   ForceOut O{st->ax, st->ay, st->az, st->dudt};
-  dim3 g(grid_for(st->n, kB)), b(kB);
+  dim3 g((unsigned)(c->cap_tiles < 65536 ? c->cap_tiles : 65536)), b(64);
   if (c->p.precision == SPH_FP32)
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forces<float>), g, b, 0, c->stream, A, c->pos4f, c->fvf, c->faf, c->sigf,
                        c->pos4, st->u, st->P, st->rho, c->sdot, O);

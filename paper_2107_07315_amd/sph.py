@@ -19,7 +19,7 @@ STATUS = {0: "SPH_OK", 1: "SPH_E_ARG", 2: "SPH_E_HIP", 3: "SPH_E_OOM", 4: "SPH_E
 
 EXPORTED = ("sph_create", "sph_destroy", "sph_set_params", "sph_build_cells", "sph_density",
             "sph_stress_rate", "sph_forces", "sph_step", "sph_sync", "sph_export_neighbours",
-            "sph_status_string", "sph_set_timing", "sph_get_timing")
+            "sph_status_string", "sph_set_timing", "sph_get_timing", "sph_neighbour_stats")
 
 _dp = ctypes.c_void_p
 
@@ -80,6 +80,7 @@ def load():
     L.sph_status_string.argtypes = [ctypes.c_int]
     L.sph_status_string.restype = ctypes.c_char_p
     L.sph_set_timing.argtypes = [vp, ctypes.c_int32]
+    L.sph_neighbour_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]
     L.sph_get_timing.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32),
                                  ctypes.POINTER(ctypes.c_double)]
     _lib = L
@@ -242,6 +243,12 @@ class Context:
         _check(self.lib.sph_get_timing(self.h, stage.encode(), ctypes.byref(n), ctypes.byref(ms)),
                "sph_get_timing")
         return n.value, ms.value
+
+    def sph_neighbour_stats(self):
+        t = ctypes.c_int64()
+        m = ctypes.c_int32()
+        _check(self.lib.sph_neighbour_stats(self.h, ctypes.byref(t), ctypes.byref(m)), "sph_neighbour_stats")
+        return t.value, m.value
 
     # convenience ---------------------------------------------------------------------------
     def evaluate(self, st: DeviceState):

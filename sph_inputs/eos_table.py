@@ -1,10 +1,15 @@
 """Synthetic tabulated equation of state: a cold piecewise polytrope plus a thermal Gamma-law part.
 
-P(rho, u) = P_cold(rho) + (Gamma_th - 1) rho (u - u_cold(rho))  (the usual hybrid form; the
-piecewise polytrope is the construction the paper cites for crust/core EoS refinement).
-Relativistic sound speed c_s^2 = dP/d(eps) at fixed entropy:
-c_s^2 = (Gamma_i P_cold + Gamma_th P_th) / (rho h),  h = 1 + u + P/rho.
-States with P <= 0 or c_s^2 <= 0 are outside the domain and stored as NaN.
+Above the cold curve (u >= u_cold(rho)) the usual hybrid form
+    P = P_cold(rho) + (Gamma_th - 1) rho (u - u_cold(rho))
+(the piecewise polytrope is the construction the paper cites for crust/core EoS refinement).
+Below the cold curve, where the linear thermal term would drive P negative, the pressure
+continues as P = P_cold exp(X), X = (Gamma_th - 1) rho (u - u_cold) / P_cold, which matches the
+hybrid form in value and first derivative at u = u_cold and stays positive.
+Relativistic sound speed c_s^2 = (dP/drho at fixed entropy) / h, h = 1 + u + P/rho:
+    above: (Gamma_i P_cold + Gamma_th P_th) / rho
+    below: (P / rho) (Gamma_i + X (1 - Gamma_i) + (Gamma_th - 1)(e^X - 1))
+Both are positive for Gamma_i > Gamma_th - 1, so every (rho, u) in the table range is valid.
 """
 from __future__ import annotations
 
@@ -27,10 +32,15 @@ def hybrid_eos(pp: PiecewisePolytrope, rho, u, gamma_th: float = 1.8):
     u = np.asarray(u, dtype=np.float64)
     Pc, uc = pp.from_rho(rho)
     Gc = pp.gamma_of(rho)
-    Pth = (gamma_th - 1.0) * rho * (u - uc)
-    P = Pc + Pth
+    g1 = gamma_th - 1.0
+    Pth = g1 * rho * (u - uc)
+    above = u >= uc
+    X = np.where(above, 0.0, Pth / Pc)
+    P = np.where(above, Pc + Pth, Pc * np.exp(X))
     h = 1.0 + u + P / rho
-    cs2 = (Gc * Pc + gamma_th * Pth) / (rho * h)
+    dPdrho = np.where(above, (Gc * Pc + gamma_th * Pth) / rho,
+                      P / rho * (Gc + X * (1.0 - Gc) + g1 * np.expm1(X)))
+    cs2 = dPdrho / h
     return P, cs2
 
 
