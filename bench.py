@@ -29,12 +29,12 @@ FORCE_BYTES_PER_PARTICLE_FP32 = 16 + 16 + 8 + 32 + 32
 PEAK = {"FP64": 78.6e12, "FP32": 157.3e12}     # published MI355X vector peaks, FLOP/s
 
 
-def run_variant(w, precision, eos, steps, warmup, timing=True):
+def run_variant(w, precision, eos, steps, warmup, timing=True, ctx_kw=None):
     import torch
 
     from paper_2107_07315_amd import sph
     p = w.params.replace(precision=precision, eos=eos)
-    ctx = sph.Context(p, capacity=w.n)
+    ctx = sph.Context(p, capacity=w.n, **(ctx_kw or {}))
     st = sph.DeviceState(w.arrays)
     ctx.evaluate(st)
     ctx.sph_step(st, w.dt, warmup)
@@ -51,7 +51,8 @@ def run_variant(w, precision, eos, steps, warmup, timing=True):
     for s in ("cells", "density", "stress", "forces", "kdk"):
         n, ms = ctx.sph_get_timing(s)
         stages[s] = {"launches": n, "ms_total": ms}
-    pairs, maxc = ctx.sph_neighbour_stats()
+    stats = ctx.sph_neighbour_stats()
+    pairs, maxc = stats["pairs"], stats["max_count"]
     ctx.sph_set_timing(False)
     ctx.close()
     del st
@@ -59,7 +60,7 @@ def run_variant(w, precision, eos, steps, warmup, timing=True):
     fl = stages["forces"]
     avg_ms = fl["ms_total"] / max(fl["launches"], 1)
     return {"ms_per_step": ms_step, "value": w.n * steps / (t1 - t0), "stages": stages,
-            "pairs": pairs, "max_neighbours": maxc, "force_avg_ms": avg_ms}
+            "pairs": pairs, "max_neighbours": maxc, "force_avg_ms": avg_ms, "stats": stats}
 
 
 def roofline(res, n, precision):
@@ -99,12 +100,23 @@ def main():
     ap.add_argument("--n", type=int, default=2_000_000)
     ap.add_argument("--variants", default="FP64,FP32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 1 GiB device-to-device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU sharding is a design note, not built)"}), flush=True)
         sys.exit(2)
 
+    if args.calibrate_copy:
+        import torch
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     from sph_inputs import workloads as W
     w = W.pp_star(args.n, seed=3, eos="TABLE", steps=args.steps)
     variants = [v.strip() for v in args.variants.split(",") if v.strip()]
@@ -134,7 +146,8 @@ def main():
         "variants": {k: {"value": v["value"], "ms_per_step": v["ms_per_step"],
                          "stages_ms_per_step": {s: round(d["ms_total"] / args.steps, 4)
                                                 for s, d in v["stages"].items()},
-                         "pairs": v["pairs"], "max_neighbours": v["max_neighbours"]}
+                         "pairs": v["pairs"], "max_neighbours": v["max_neighbours"],
+                         "lists": v["stats"]}
                      for k, v in res.items()},
         "roofline": roofline(r, w.n, head),
     }

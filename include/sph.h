@@ -18,15 +18,18 @@
  *    half-step copies, mixed-precision shadows) is allocated by sph_create for `capacity`
  *    particles and freed by sph_destroy.
  *  - Streams: every call is enqueued on the HIP stream given to sph_create and returns without
- *    waiting, except sph_sync, sph_export_neighbours and the *_get_* helpers, which wait.
+ *    waiting, except sph_sync, sph_export_neighbours, the statistics and timing getters, and
+ *    (with skin > 0) sph_build_cells and sph_step, which wait for a one-word drift test per
+ *    evaluation.
  *  - Errors: argument and call-order errors return immediately with nothing enqueued.  Errors
  *    found on the device (non-finite fields, neighbour-list overflow, states outside the EoS
  *    table) are latched in a device status word with the first offending particle and are
  *    returned by the next sph_sync.
  *  - Order: sph_build_cells -> sph_density -> sph_stress_rate -> sph_forces.  A stage called
  *    before its predecessor for the current positions returns SPH_E_ORDER.
- *  - Reordering: sph_build_cells permutes every particle array of the state in place into the
- *    cell order it uses (id follows the particles); results are reported in that order.
+ *  - Reordering: sph_build_cells (and sph_step, whenever it rebuilds the lists) permutes every
+ *    particle array of the state in place into the order it uses (id follows the particles);
+ *    results are reported in that order.
  *  - Threads: one host thread per context.
  */
 #ifndef SPH_H
@@ -107,13 +110,32 @@ typedef struct {
   double eps_break;        /* breaking strain                                                  */
   int32_t rotation;        /* OBJECTIVE R S - S R (default) or LITERAL S R - R S               */
   int32_t precision;       /* FP64, or FP32 pair sums with FP64 positions/integration/metric  */
-  int32_t max_neighbours;  /* list capacity per particle (0: 512)                              */
-  int32_t resort_every;    /* inside sph_step: full re-sort every k steps (0: 10)              */
+  int32_t max_neighbours;  /* exact-list capacity per particle (0: 512); candidate lists hold  */
+                           /*   twice as many                                                  */
   int32_t cell_div;        /* cells per smoothing diameter of the finest level (0: 2)          */
+  double tile_cut;         /* a 64-particle tile is cut where the Morton curve jumps farther  */
+                           /*   than tile_cut smoothing lengths (0: 6)                         */
+  double skin;             /* relative Verlet skin s: candidate lists hold every b with       */
+                           /*   |x_a - x_b| < (1 + s)(h_a + h_b) and are rebuilt only when a    */
+                           /*   particle has moved, plus grown in h, by more than s h since the */
+                           /*   last build.  0: rebuild at every evaluation.  Values in (0,     */
+                           /*   1e-4) act as 0; periodic runs clip s so that (1+s)(h_a+h_b)     */
+                           /*   stays below half the box.                                       */
 } sph_params;
 
+/* Neighbour-list statistics (sph_neighbour_stats). */
+typedef struct {
+  int64_t pairs;           /* exact list entries (ordered pairs a->b, b != a) of the last density */
+  int32_t max_count;       /* longest exact list                                               */
+  int32_t pad;
+  int64_t tiles;           /* tiles (at most 64 particles sharing one neighbour union)          */
+  int64_t union_total;     /* summed tile-union sizes                                          */
+  int64_t candidates;      /* summed candidate-list lengths (exact lists plus the skin)        */
+  int64_t rebuilds;        /* candidate-list builds since sph_create                           */
+} sph_list_stats;
+
 /* Create a context for up to `capacity` particles on the current HIP device (capacity rounded up
- * to 64 times max_neighbours must stay below 2^32); all work is
+ * to 64 times twice max_neighbours must stay below 2^32); all work is
  * enqueued on `hip_stream` (a hipStream_t, may be NULL for the default stream).
  * Returns SPH_E_ARG for a bad parameter set, SPH_E_OOM if scratch does not fit. */
 sph_status sph_create(const sph_params* params, void* hip_stream, int64_t capacity, sph_ctx** out);
@@ -123,16 +145,21 @@ void sph_destroy(sph_ctx* ctx);
 sph_status sph_set_params(sph_ctx* ctx, const sph_params* params);
 
 /* Neighbour search set-up (the summation runs over particles within the support radius,
- * section "Solid SPH Equations"): sort particles into a multi-level cell grid (levels by h),
- * permute all state arrays into that order, and build exact neighbour lists
- * N(a) = { b != a : |x_a - x_b|^2 < (h_a + h_b)^2 } evaluated in FP64 without contraction. */
+ * section "Solid SPH Equations").  If the candidate lists are stale (first call, new n or
+ * parameters, skin 0, or a particle moved or grew past the skin bound since the last build):
+ * permute all state arrays along a global Morton curve, sort particles into a multi-level cell
+ * grid (levels by h) and build candidate lists { b != a : |x_a - x_b| < (1 + skin)(h_a + h_b) }
+ * per tile of at most 64 consecutive particles.  The exact sets
+ * N(a) = { b != a : |x_a - x_b|^2 < (h_a + h_b)^2 }, evaluated in FP64 without contraction,
+ * are extracted from the candidates by sph_density.  With skin > 0 this call waits for the
+ * one-word drift test on the device before deciding. */
 sph_status sph_build_cells(sph_ctx* ctx, sph_state* st);
 
 /* Density summation D_a = sum_b m W(r_ab, h_ab) including b = a (section "Fixed metric
  * background": the computational density D = rho sqrt(gamma) W_L recovered by the standard
  * SPH sum), then rho = D / (psi^6 W_L), P and c_s from the EoS (eq. poly_eos family; the
  * relativistic sound speed of the setup section), the crust shear modulus and yield stress.
- * Writes D, rho, P, cs. */
+ * Also extracts the exact neighbour lists the later stages use.  Writes D, rho, P, cs. */
 sph_status sph_density(sph_ctx* ctx, sph_state* st);
 
 /* Velocity gradient and stress rate (eqs. solid4-solid6): strain and rotation rates from
@@ -153,14 +180,14 @@ sph_status sph_step(sph_ctx* ctx, sph_state* st, double dt, int32_t nsteps);
 /* Wait for the context's stream; return and clear the first latched device error. */
 sph_status sph_sync(sph_ctx* ctx);
 
-/* Copy the current neighbour lists to host memory as CSR in the particles' current order:
- * offsets[n+1] (host), ids[offsets[n]] (host, indices into the current order).  Lists are
- * written unsorted.  Returns SPH_E_NGB_CAPACITY (and offsets) if cap is too small.  Waits. */
+/* Copy the exact neighbour lists of the last sph_density to host memory as CSR in the
+ * particles' current order: offsets[n+1] (host), ids[offsets[n]] (host, indices into the
+ * current order).  Lists are written unsorted.  Returns SPH_E_ORDER before the first density
+ * evaluation, SPH_E_NGB_CAPACITY (and offsets) if cap is too small.  Waits. */
 sph_status sph_export_neighbours(sph_ctx* ctx, int64_t* offsets, int32_t* ids, int64_t cap);
 
-/* Total number of neighbour-list entries (ordered pairs a->b, b != a) and the longest list of
- * the current lists.  Waits. */
-sph_status sph_neighbour_stats(sph_ctx* ctx, int64_t* total_pairs, int32_t* max_count);
+/* Statistics of the current lists (see sph_list_stats).  Waits. */
+sph_status sph_neighbour_stats(sph_ctx* ctx, sph_list_stats* out);
 
 /* Human-readable name of a status code (static string). */
 const char* sph_status_string(sph_status s);

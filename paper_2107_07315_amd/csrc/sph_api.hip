@@ -32,6 +32,8 @@ sph_status check_params(const sph_params* p) {
   if (p->precision != SPH_FP64 && p->precision != SPH_FP32) return SPH_E_ARG;
   if (p->max_neighbours < 0 || p->max_neighbours > 4096) return SPH_E_ARG;
   if (p->cell_div < 0 || p->cell_div > 4) return SPH_E_ARG;
+  if (!(p->tile_cut >= 0.0) || p->tile_cut > 64.0) return SPH_E_ARG;
+  if (!(p->skin >= 0.0) || p->skin > 1.0) return SPH_E_ARG;
   return SPH_OK;
 }
 
@@ -89,11 +91,13 @@ void sph_destroy(sph_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
   void* bufs[] = {c->grid, c->keys, c->vals, c->cell_start, c->cell_end, c->sort.keys_alt, c->sort.vals_alt,
-                  c->sort.hist, c->sort.rowtot, c->sort.partial, c->sort.scan_bsum, c->tile_start, c->tile_cnt, c->tile_flag, c->tile_u, c->tile_uoff,
-                  c->tile_usize, c->nbr16, c->nbr_count, c->pos4, c->fv, c->fa, c->sig, c->pos4f, c->fvf,
+                  c->sort.hist, c->sort.rowtot, c->sort.partial, c->sort.scan_bsum, c->tile_u, c->tile_start, c->tile_cnt, c->tile_uoff,
+                  c->tile_usize, c->nbr16, c->nbr_count, c->nbr16s, c->nbr_count_s, c->pos_build, c->drift_flag,
+                  c->pos4, c->fv, c->fa, c->sig, c->pos4f, c->fvf,
                   c->faf, c->sigf, c->mu, c->Y0, c->B, c->sdot, c->half, c->tmp, c->stars, c->status};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
+  if (c->drift_host) (void)hipHostFree(c->drift_host);
   for (auto& t : c->timers)
     for (hipEvent_t e : t.ev) (void)hipEventDestroy(e);
   c->~sph_ctx();
@@ -113,20 +117,16 @@ sph_status sph_create(const sph_params* params, void* stream, int64_t capacity, 
   c->stream = (hipStream_t)stream;
   c->capacity = capacity;
   c->cap = params->max_neighbours > 0 ? params->max_neighbours : 512;
+  c->cap_s = (2 * c->cap + 7) / 8 * 8;
   c->ucap = 8192;   // union members per tile; local indices are 16-bit
-  c->upool = (int64_t)((capacity + 63) / 64 * 64) * c->cap;
-  if (c->upool > (int64_t)0xffffffffll) {   // pool offsets are 32-bit: lower max_neighbours
-    c->~sph_ctx();
-    free(c);
-    return SPH_E_ARG;
-  }
+  // the union pool starts at 128 entries per particle and grows to what the tiles reserve
+  c->upool = (int64_t)((capacity + 63) / 64 * 64) * 128;
+  if (c->upool > (int64_t)0xffffffffll) c->upool = (int64_t)0xffffffffll;
   (void)hipGetDevice(&c->device);
   const int64_t cap = capacity;
   const int64_t capw = (cap + 63) / 64 * 64;
   c->capw = capw;
-  // every tile holds at least one particle, so capw tiles always suffice; the union pool holds
-  // up to cap entries per particle (the worst case of one particle per tile), capped by 32-bit
-  // offsets
+  // tiles: at most one per particle; the union pool is addressed with 32-bit offsets
   c->cap_tiles = capw;
   c->sort.scan_cap = (capw + 1023) / 1024;
   c->max_cells = kMaxCells;
@@ -136,24 +136,33 @@ sph_status sph_create(const sph_params* params, void* stream, int64_t capacity, 
       (e = dalloc(&c->sort.keys_alt, cap)) || (e = dalloc(&c->sort.vals_alt, cap)) ||
       (e = dalloc(&c->sort.hist, (size_t)256 * c->sort.max_blocks)) || (e = dalloc(&c->sort.rowtot, 256)) ||
       (e = dalloc(&c->sort.partial, (size_t)8 * 1024)) ||
-      (e = dalloc(&c->tile_u, (size_t)c->upool)) || (e = dalloc(&c->tile_uoff, c->cap_tiles)) ||
-      (e = dalloc(&c->tile_usize, c->cap_tiles)) ||
+      (e = dalloc(&c->tile_u, (size_t)c->upool)) || (e = dalloc(&c->tile_usize, c->cap_tiles)) ||
       (e = dalloc(&c->tile_start, c->cap_tiles)) || (e = dalloc(&c->tile_cnt, c->cap_tiles)) ||
-      (e = dalloc(&c->tile_flag, capw)) || (e = dalloc(&c->sort.scan_bsum, c->sort.scan_cap + 1)) ||
-      (e = dalloc(&c->nbr16, (size_t)capw * c->cap)) || (e = dalloc(&c->nbr_count, capw)) ||
+      (e = dalloc(&c->tile_uoff, c->cap_tiles)) ||
+      (e = dalloc(&c->sort.scan_bsum, c->sort.scan_cap + 1)) ||
+      (e = dalloc(&c->nbr16, (size_t)capw * ((c->cap + 7) / 8 * 8))) || (e = dalloc(&c->nbr_count, capw)) ||
+      (e = dalloc(&c->nbr16s, (size_t)capw * c->cap_s)) || (e = dalloc(&c->nbr_count_s, capw)) ||
+      (e = dalloc(&c->pos_build, cap)) || (e = dalloc(&c->drift_flag, 1)) ||
       (e = dalloc(&c->pos4, cap)) || (e = dalloc(&c->fv, cap)) || (e = dalloc(&c->fa, cap)) ||
       (e = dalloc(&c->sig, 6 * cap)) || (e = dalloc(&c->pos4f, cap)) || (e = dalloc(&c->fvf, cap)) ||
       (e = dalloc(&c->faf, cap)) || (e = dalloc(&c->sigf, 6 * cap)) || (e = dalloc(&c->mu, cap)) ||
       (e = dalloc(&c->Y0, cap)) || (e = dalloc(&c->B, cap)) || (e = dalloc(&c->sdot, cap)) ||
-      (e = dalloc(&c->half, 10 * cap)) || (e = dalloc(&c->tmp, cap)) || (e = dalloc(&c->status, 1))) {
+      (e = dalloc(&c->half, 10 * cap)) || (e = dalloc(&c->tmp, capw)) || (e = dalloc(&c->status, 1))) {
     sph_destroy(c);
     return e;
+  }
+  if (hipHostMalloc((void**)&c->drift_host, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+    c->drift_host = nullptr;
+    sph_destroy(c);
+    return SPH_E_OOM;
   }
   // cell tables are validated against the sorted keys on every lookup, so they are cleared once
   if (hipMemsetAsync(c->cell_start, 0xff, sizeof(int32_t) * c->max_cells, c->stream) != hipSuccess ||
       hipMemsetAsync(c->cell_end, 0xff, sizeof(int32_t) * c->max_cells, c->stream) != hipSuccess ||
       hipMemsetAsync(c->status, 0, sizeof(DevStatus), c->stream) != hipSuccess ||
       hipMemsetAsync(c->nbr_count, 0, sizeof(int32_t) * cap, c->stream) != hipSuccess ||
+      hipMemsetAsync(c->nbr_count_s, 0, sizeof(int32_t) * cap, c->stream) != hipSuccess ||
+      hipMemsetAsync(c->drift_flag, 0, sizeof(uint32_t), c->stream) != hipSuccess ||
       hipMemsetAsync(c->Y0, 0, sizeof(double) * cap, c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess) {
     sph_destroy(c);
@@ -171,19 +180,51 @@ sph_status sph_set_params(sph_ctx* c, const sph_params* params) {
   if (cap != c->cap) return SPH_E_ARG;   // list capacity is fixed at creation
   c->p = *params;
   c->gen = 0;
+  c->lists_valid = false;
   return SPH_OK;
 }
+
+}  // extern "C"
+
+// Copy the drift word to the host and report whether the last test (check_id) saw a violation.
+static sph_status read_drift(sph_ctx* c, bool* violated) {
+  HIP_TRY(hipMemcpyAsync(c->drift_host, c->drift_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  *violated = *c->drift_host == c->check_id;
+  return SPH_OK;
+}
+
+static sph_status rebuild(sph_ctx* c, sph_state* st) {
+  timer_begin(c, TIMER_CELLS);
+  sph_status e = sph_rebin(c, st);
+  timer_end(c, TIMER_CELLS);
+  if (e) {
+    c->lists_valid = false;
+    return e;
+  }
+  c->lists_valid = true;
+  ++c->rebuilds;
+  return SPH_OK;
+}
+
+extern "C" {
 
 sph_status sph_build_cells(sph_ctx* c, sph_state* st) {
   sph_status e = check_state(c, st);
   if (e) return e;
+  if (st->n != c->n) c->lists_valid = false;
   c->n = st->n;
   if (st->n == 0) { c->gen = 1; return SPH_OK; }
-  timer_begin(c, TIMER_CELLS);
-  e = sph_rebin(c, st, true);
-  timer_end(c, TIMER_CELLS);
-  if (e) return e;
-  c->steps_since_sort = 0;
+  bool stale = !c->lists_valid || !(c->p.skin > 0.0);
+  if (!stale) {
+    ++c->check_id;
+    if ((e = launch_drift_check(c, st)) || (e = read_drift(c, &stale))) return e;
+  }
+  if (stale) {
+    if ((e = rebuild(c, st))) return e;
+  } else if ((e = launch_pack(c, st))) {
+    return e;
+  }
   c->gen = 1;
   return SPH_OK;
 }
@@ -236,17 +277,15 @@ sph_status sph_step(sph_ctx* c, sph_state* st, double dt, int32_t nsteps) {
   if (!(dt > 0.0) || nsteps < 0) return SPH_E_ARG;
   if (c->gen < 4 || st->n != c->n) return SPH_E_ORDER;
   if (st->n == 0) return SPH_OK;
-  const int every = c->p.resort_every > 0 ? c->p.resort_every : 10;
   for (int32_t k = 0; k < nsteps; ++k) {
+    const bool check = c->lists_valid && c->p.skin > 0.0;
+    if (check) ++c->check_id;
     timer_begin(c, TIMER_KDK);
-    if ((e = launch_kick_drift(c, st, dt))) return e;
+    if ((e = launch_kick_drift(c, st, dt, check))) return e;
     timer_end(c, TIMER_KDK);
-    bool resort = ++c->steps_since_sort >= every;
-    timer_begin(c, TIMER_CELLS);
-    e = sph_rebin(c, st, resort);
-    timer_end(c, TIMER_CELLS);
-    if (e) return e;
-    if (resort) c->steps_since_sort = 0;
+    bool stale = !check;
+    if (check && (e = read_drift(c, &stale))) return e;
+    if (stale && (e = rebuild(c, st))) return e;
     timer_begin(c, TIMER_DENSITY);
     if ((e = launch_density(c, st))) return e;
     timer_end(c, TIMER_DENSITY);
@@ -279,47 +318,40 @@ sph_status sph_sync(sph_ctx* c) {
 
 sph_status sph_export_neighbours(sph_ctx* c, int64_t* offsets, int32_t* ids, int64_t cap) {
   if (!c || !offsets) return SPH_E_ARG;
+  if (c->n > 0 && (c->gen < 2 || !c->lists_valid)) return SPH_E_ORDER;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return SPH_E_HIP;
   const int64_t n = c->n;
   if (n == 0) { offsets[0] = 0; return SPH_OK; }
   GridInfo g;
   if (hipMemcpy(&g, c->grid, sizeof(g), hipMemcpyDeviceToHost) != hipSuccess) return SPH_E_HIP;
-  const int64_t ntiles = (int64_t)g.ntiles < c->cap_tiles ? (int64_t)g.ntiles : c->cap_tiles;
-  std::vector<int32_t> cnt(n), usz(ntiles), tst(ntiles), tcn(ntiles);
+  const int64_t ntiles = g.ntiles;
+  std::vector<int32_t> cnt(n), tst(ntiles), tcn(ntiles);
   std::vector<uint32_t> uoff(ntiles);
   std::vector<int32_t> U((size_t)(g.upool_used < c->upool ? g.upool_used : c->upool));
-  std::vector<uint32_t> perm(n);
-  std::vector<uint16_t> raw((size_t)c->cap * c->capw);
+  std::vector<uint16_t> raw((size_t)((c->cap + 7) / 8 * 8) * c->capw);
   if (hipMemcpy(cnt.data(), c->nbr_count, sizeof(int32_t) * n, hipMemcpyDeviceToHost) != hipSuccess ||
-      hipMemcpy(usz.data(), c->tile_usize, sizeof(int32_t) * ntiles, hipMemcpyDeviceToHost) != hipSuccess ||
       hipMemcpy(tst.data(), c->tile_start, sizeof(int32_t) * ntiles, hipMemcpyDeviceToHost) != hipSuccess ||
       hipMemcpy(tcn.data(), c->tile_cnt, sizeof(int32_t) * ntiles, hipMemcpyDeviceToHost) != hipSuccess ||
       hipMemcpy(uoff.data(), c->tile_uoff, sizeof(uint32_t) * ntiles, hipMemcpyDeviceToHost) != hipSuccess ||
       (U.size() && hipMemcpy(U.data(), c->tile_u, sizeof(int32_t) * U.size(), hipMemcpyDeviceToHost) != hipSuccess) ||
-      hipMemcpy(perm.data(), c->vals, sizeof(uint32_t) * n, hipMemcpyDeviceToHost) != hipSuccess ||
       hipMemcpy(raw.data(), c->nbr16, sizeof(uint16_t) * raw.size(), hipMemcpyDeviceToHost) != hipSuccess)
     return SPH_E_HIP;
-  std::vector<int32_t> cnt_a(n, 0);
-  for (int64_t p = 0; p < n; ++p) cnt_a[c->identity_perm ? p : perm[p]] = cnt[p];
   offsets[0] = 0;
-  for (int64_t a = 0; a < n; ++a) offsets[a + 1] = offsets[a] + cnt_a[a];
+  for (int64_t a = 0; a < n; ++a) offsets[a + 1] = offsets[a] + cnt[a];
   if (offsets[n] > cap || !ids) return SPH_E_NGB_CAPACITY;
   for (int64_t t = 0; t < ntiles; ++t)
     for (int l = 0; l < tcn[t]; ++l) {
-      const int64_t p = (int64_t)tst[t] + l;
-      const int64_t a = c->identity_perm ? p : perm[p];
-      for (int k = 0; k < cnt[p]; ++k) {
-        const uint16_t loc = raw[(size_t)k * c->capw + p];
-        ids[offsets[a] + k] = U[(size_t)uoff[t] + loc];
-      }
+      const int64_t a = (int64_t)tst[t] + l;
+      for (int k = 0; k < cnt[a]; ++k)
+        ids[offsets[a] + k] = U[(size_t)uoff[t] + raw[(size_t)nbr_index(k, a, c->capw)]];
     }
   return SPH_OK;
 }
 
-sph_status sph_neighbour_stats(sph_ctx* c, int64_t* total_pairs, int32_t* max_count) {
-  if (!c || !total_pairs || !max_count) return SPH_E_ARG;
+sph_status sph_neighbour_stats(sph_ctx* c, sph_list_stats* out) {
+  if (!c || !out) return SPH_E_ARG;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return SPH_E_HIP;
-  return sph_count_stats(c, total_pairs, max_count);
+  return sph_count_stats(c, out);
 }
 
 sph_status sph_set_timing(sph_ctx* c, int32_t enable) {

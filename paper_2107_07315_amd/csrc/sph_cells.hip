@@ -66,7 +66,8 @@ __global__ __launch_bounds__(kB) void k_bounds(const double4* __restrict__ pos4,
 }
 
 __global__ __launch_bounds__(64) void k_grid_setup1(GridInfo* g, const unsigned long long* __restrict__ partial,
-                                                    int nblocks, int periodic, double box, DevStatus* st) {
+                                                    int nblocks, int periodic, double box, double skin,
+                                                    DevStatus* st) {
   unsigned long long v[8] = {~0ull, ~0ull, ~0ull, 0ull, 0ull, 0ull, ~0ull, 0ull};
   for (int b = threadIdx.x; b < nblocks; b += 64)
     for (int k = 0; k < 8; ++k) {
@@ -90,6 +91,13 @@ __global__ __launch_bounds__(64) void k_grid_setup1(GridInfo* g, const unsigned 
   g->hmax = dec_double(g->enc_hmax);
   // minimum image needs h_a + h_b < box / 2 for every pair; non-positive h is invalid
   if ((periodic && !(2.0 * g->hmax < 0.5 * box)) || !(g->hmin > 0.0)) latch_error(st, SPH_E_ARG, -1);
+  // effective skin: the widened support must stay below half a periodic box
+  double s = skin;
+  if (periodic) {
+    const double smax = 0.5 * box / (2.0 * g->hmax) * (1.0 - 1e-9) - 1.0;
+    s = s < smax ? s : smax;
+  }
+  g->skin = s >= 1e-4 ? s : 0.0;
   int L = 1;
   while (L < SPH_MAX_LEV && g->hmax >= g->hmin * (double)(1 << L)) ++L;
   g->nlev = L;
@@ -198,10 +206,6 @@ __global__ __launch_bounds__(kB) void k_gather(const T* __restrict__ src, const 
   if (i < n) dst[i] = src[perm[i]];
 }
 
-__global__ __launch_bounds__(kB) void k_identity(uint32_t* __restrict__ v, int64_t n) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) v[i] = (uint32_t)i;
-}
 
 // pos4: absolute position and h (FP64 pair passes); pos4f: position relative to the
 // particle's star centre and h (FP32 pair passes keep full precision near each star).
@@ -221,73 +225,79 @@ __global__ __launch_bounds__(kB) void k_pack_pos(const double* __restrict__ x, c
   if (pos4f) pos4f[a] = make_float4((float)(x[a] - cx), (float)(y[a] - cy), (float)(z[a] - cz), (float)h[a]);
 }
 
-// Tiles: runs of at most 64 consecutive sorted particles that never cross a super-cell (2x2x2
-// cells of one level, a Morton prefix).  Cutting at super-cells keeps every tile spatially
-// compact also in sparse levels, where 64 consecutive particles could otherwise span the star.
-__device__ __forceinline__ int key_level(uint32_t key, const GridInfo& g) {
-  int l = 0;
-  while (l < g.nlev - 1 && key >= g.base[l + 1]) ++l;
-  return l;
+// Global Morton key of a 1024^3 grid over the bounding box: the particle arrays are kept in this
+// order (re-sorted every few steps), so any 64 consecutive particles form a compact tile whatever
+// the local density; the per-level cell tables index the particles through a permutation.
+__global__ __launch_bounds__(kB) void k_gkeys(const double4* __restrict__ pos4, int64_t n,
+                                              const GridInfo* __restrict__ gp, uint32_t* __restrict__ keys,
+                                              uint32_t* __restrict__ vals) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  const GridInfo& g = *gp;
+  double ext = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    const double e = g.periodic ? g.box : dec_double(g.enc_hi[d]) - g.lo[d];
+    ext = e > ext ? e : ext;
+  }
+  const double sc = ext > 0.0 ? 1024.0 / ext : 0.0;
+  const double4 p = pos4[a];
+  uint32_t k3[3];
+  const double q[3] = {p.x, p.y, p.z};
+  for (int d = 0; d < 3; ++d) {
+    int k = (int)floor((q[d] - g.lo[d]) * sc);
+    k3[d] = (uint32_t)(k < 0 ? 0 : (k > 1023 ? 1023 : k));
+  }
+  keys[a] = spread3(k3[0]) | (spread3(k3[1]) << 1) | (spread3(k3[2]) << 2);
+  vals[a] = (uint32_t)a;
 }
 
-__global__ __launch_bounds__(kB) void k_tile_marks(const uint32_t* __restrict__ skeys, int64_t n,
-                                                   const GridInfo* __restrict__ gp,
-                                                   const int32_t* __restrict__ cstart,
-                                                   const int32_t* __restrict__ cend, uint32_t* __restrict__ len,
+// Tile table, rebuilt at every full re-sort (particles keep their array order in between).  A
+// tile starts at every multiple of 64 and wherever the Morton curve jumps: if consecutive keys first
+// differ in octree level k, the two particles only share a block of 2^(k+1) fine cells, so a tile
+// that spans the boundary could be that large.  Cutting where 2^(k+1) fine cells exceed 4 h keeps
+// every tile inside a region about 4 smoothing lengths across, in dense and sparse parts alike
+// (the factor is the tile_cut parameter).
+__global__ __launch_bounds__(kB) void k_tile_flags(const uint32_t* __restrict__ gkeys, const double4* __restrict__ pos4,
+                                                   int64_t n, const GridInfo* __restrict__ gp, double cut,
                                                    uint32_t* __restrict__ flag) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
-  const GridInfo& g = *gp;
-  const uint32_t key = skeys[p];
-  const int l = key_level(key, g);
-  const uint32_t m = key - g.base[l];
-  const uint32_t ncell = 1u << (3 * g.bits[l]);
-  const uint32_t first = m & ~7u;
-  int64_t s0 = p, e0 = p + 1;
-  for (uint32_t j = 0; j < 8; ++j) {
-    const uint32_t mc = first + j;
-    if (mc >= ncell) break;
-    const uint32_t kc = g.base[l] + mc;
-    const int32_t s = cstart[kc];
-    if (s < 0 || s >= n || skeys[s] != kc) continue;
-    const int32_t e = cend[kc];
-    s0 = s < s0 ? s : s0;
-    e0 = e > e0 ? e : e0;
+  bool start = (p & 63) == 0;
+  if (!start) {
+    const GridInfo& g = *gp;
+    double ext = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      const double e = g.periodic ? g.box : dec_double(g.enc_hi[d]) - g.lo[d];
+      ext = e > ext ? e : ext;
+    }
+    const double fine = ext / 1024.0;
+    const uint32_t x = gkeys[p] ^ gkeys[p - 1];
+    const int lvl = x ? (31 - __clz(x)) / 3 : -1;
+    start = lvl >= 0 && (double)(2 << lvl) * fine > cut * pos4[p].w;
   }
-  const int64_t off = p - s0;
-  uint32_t L = 0;
-  if (off % 64 == 0) {
-    const int64_t rem = e0 - p;
-    L = (uint32_t)(rem < 64 ? rem : 64);
-  }
-  len[p] = L;
-  flag[p] = L ? 1u : 0u;
+  flag[p] = start ? 1u : 0u;
 }
 
-__global__ __launch_bounds__(kB) void k_tile_fill(const uint32_t* __restrict__ len, const uint32_t* __restrict__ idx,
-                                                  int64_t n, int64_t cap_tiles, int32_t* __restrict__ tile_start,
-                                                  int32_t* __restrict__ tile_cnt, DevStatus* status) {
+__global__ __launch_bounds__(kB) void k_tile_fill(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ idx,
+                                                  int64_t n, int32_t* __restrict__ tile_start) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
-  const uint32_t L = len[p];
-  if (!L) return;
-  const uint32_t t = idx[p];
-  if ((int64_t)t < cap_tiles) {
-    tile_start[t] = (int32_t)p;
-    tile_cnt[t] = (int32_t)L;
-  } else {
-    latch_error(status, SPH_E_NGB_CAPACITY, -1);
-  }
+  if (flag[p]) tile_start[idx[p]] = (int32_t)p;
 }
 
-// Union-pool reservation: a tile of cnt targets can need at most min(ucap, cnt * cap) entries.
-__global__ __launch_bounds__(kB) void k_tile_ubound(const GridInfo* __restrict__ gp, const int32_t* __restrict__ tile_cnt,
-                                                    int64_t cap_tiles, int cap, int ucap, uint32_t* __restrict__ ub) {
+// tile lengths and each tile's reservation in the union pool: min(ucap, cnt * cap) entries
+__global__ __launch_bounds__(kB) void k_tile_len(const GridInfo* __restrict__ gp, int64_t n, int64_t cap_tiles,
+                                                 const int32_t* __restrict__ tile_start, int32_t* __restrict__ tile_cnt,
+                                                 int cap, int ucap, uint32_t* __restrict__ ub) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= cap_tiles) return;
+  const int64_t nt = gp->ntiles;
   uint32_t v = 0;
-  if (t < (int64_t)gp->ntiles) {
-    const int64_t b = (int64_t)tile_cnt[t] * cap;
+  if (t < nt) {
+    const int64_t e = t + 1 < nt ? tile_start[t + 1] : n;
+    const int32_t cnt = (int32_t)(e - tile_start[t]);
+    tile_cnt[t] = cnt;
+    const int64_t b = (int64_t)cnt * cap;
     v = (uint32_t)(b < ucap ? b : ucap);
   }
   ub[t] = v;
@@ -302,23 +312,22 @@ __global__ __launch_bounds__(kB) void k_tile_ubound(const GridInfo* __restrict__
 //  3. per batch of 64 candidates every lane runs the exact FP64 test against all of them,
 //     building a 64-bit hit mask; the OR of the masks gives the batch's new union members (in
 //     candidate order) and each lane appends the local indices of its hits.
-// Candidates enter batches in a fixed order (level, cell, sorted position), so U and the lists
-// are deterministic and each list is ascending in local index.
+// Tile t is particles [tile_start[t], tile_start[t] + tile_cnt[t]) of the array order (at most 64).
+// Candidates enter batches in a fixed order (level, cell, cell-sorted position), so U and the
+// lists are deterministic and each list is ascending in local index.
 struct BuildArgs {
   const double4* __restrict__ pos4;
   int64_t n;
   const GridInfo* __restrict__ grid;
   const uint32_t* __restrict__ skeys;
-  const uint32_t* __restrict__ perm;
-  int identity;
+  const uint32_t* __restrict__ perm;   // cell-sorted position -> particle index
   const int32_t* __restrict__ cstart;
   const int32_t* __restrict__ cend;
   const int32_t* __restrict__ tile_start;
   const int32_t* __restrict__ tile_cnt;
-  int64_t cap_tiles, capw;
-  int cap, ucap;
   const uint32_t* __restrict__ tile_uoff;
-  int64_t upool;
+  int64_t capw, upool;
+  int cap, ucap;
   int32_t* __restrict__ tile_u;
   int32_t* __restrict__ tile_usize;
   uint16_t* __restrict__ nbr16;
@@ -344,21 +353,22 @@ struct TileState {
   bool valid;
   double xa, ya, za, ha;
   int usize, cnt, stored, ucap;
-  uint16_t* out;
+  int64_t p;
   int32_t* U;
 };
 
-// exact test of every lane's target against batch candidates cb[0..nb), nb <= 64
+// candidate test (skin-widened, FP64) of every lane's target against batch candidates cb[0..nb),
+// nb <= 64
 __device__ __forceinline__ void run_batch(const BuildArgs& B, TileState& T, const double4* cb, const int32_t* cbi,
-                                          int nb, int periodic, double box) {
+                                          int nb, int periodic, double box, double s1) {
   const int lane = threadIdx.x;
   unsigned long long hm = 0ull;
   if (T.valid) {
     for (int j = 0; j < nb; ++j) {
       const double4 pb = cb[j];
       const bool hit = cbi[j] != T.a &&
-                       neighbour_test(min_image(T.xa - pb.x, periodic, box), min_image(T.ya - pb.y, periodic, box),
-                                      min_image(T.za - pb.z, periodic, box), T.ha, pb.w);
+                       candidate_test(min_image(T.xa - pb.x, periodic, box), min_image(T.ya - pb.y, periodic, box),
+                                      min_image(T.za - pb.z, periodic, box), T.ha, pb.w, s1);
       hm |= (unsigned long long)hit << j;
     }
   }
@@ -375,7 +385,7 @@ __device__ __forceinline__ void run_batch(const BuildArgs& B, TileState& T, cons
     mm &= mm - 1ull;
     const int loc = T.usize + __popcll(um & ((1ull << j) - 1ull));
     if (T.cnt < B.cap && loc < T.ucap) {
-      T.out[(int64_t)T.cnt * B.capw] = (uint16_t)loc;
+      B.nbr16[nbr_index(T.cnt, T.p, B.capw)] = (uint16_t)loc;
       ++T.stored;
     }
     ++T.cnt;
@@ -392,13 +402,14 @@ __global__ __launch_bounds__(64) void k_build_tiles(BuildArgs B) {
   const GridInfo& g = *B.grid;
   const int periodic = g.periodic;
   const double box = g.box;
-  const int64_t ntiles = (int64_t)g.ntiles < B.cap_tiles ? (int64_t)g.ntiles : B.cap_tiles;
+  const double s1 = 1.0 + g.skin;
+  const int64_t ntiles = g.ntiles;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int32_t tcnt = B.tile_cnt[t];
+    const int32_t tcnt = B.tile_cnt[t];   // (lists below are the candidate lists)
     const int64_t p = (int64_t)B.tile_start[t] + lane;
     TileState T;
     T.valid = lane < tcnt;
-    T.a = T.valid ? (B.identity ? p : (int64_t)B.perm[p]) : -1;
+    T.a = T.valid ? p : -1;
     double4 pa = T.valid ? B.pos4[T.a] : make_double4(0.0, 0.0, 0.0, 0.0);
     T.xa = pa.x; T.ya = pa.y; T.za = pa.z; T.ha = pa.w;
     const double big = 1e300;
@@ -416,12 +427,12 @@ __global__ __launch_bounds__(64) void k_build_tiles(BuildArgs B) {
       if (lane == 0) latch_error(B.status, SPH_E_NGB_CAPACITY, -1);
     }
     T.U = B.tile_u + uoff;
-    T.out = B.nbr16 + (T.valid ? p : 0);
+    T.p = T.valid ? p : 0;
     T.usize = 0; T.cnt = 0; T.stored = 0;
     int pend = 0;   // candidates waiting in cb (wave-uniform)
     for (int l = 0; l < g.nlev; ++l) {
       const double c = g.cell[l];
-      const double R = (hmx + g.hlev[l]) * (1.0 + 1e-9);
+      const double R = (hmx + g.hlev[l]) * s1 * (1.0 + 1e-9);
       const double R2 = R * R;
       int lo3[3], ext[3];
       bool wrap[3];
@@ -443,8 +454,10 @@ __global__ __launch_bounds__(64) void k_build_tiles(BuildArgs B) {
       const int64_t total = (int64_t)ext[0] * ext[1] * ext[2];
       const uint32_t base = g.base[l];
       for (int64_t q = 0; q < total; q += 64) {
-        // phase 1: 64 cells at once
-        const int64_t j = q + lane;
+        // phase 1: 64 cells at once; lanes take the block's cells in bit-reversed order so that
+        // consecutive union members come from all over the neighbourhood and every target's
+        // neighbours spread evenly over the LDS chunks of the pair passes
+        const int64_t j = q + (int64_t)(__brev((unsigned)lane) >> 26);
         int32_t s = 0, e = 0;
         if (j < total) {
           const int kx = lo3[0] + (int)(j % ext[0]);
@@ -499,12 +512,12 @@ __global__ __launch_bounds__(64) void k_build_tiles(BuildArgs B) {
               else hi_i = mid - 1;
             }
             const int32_t sp = c_s[lo_i] + (slot - c_o[lo_i]);
-            b = B.identity ? sp : (int32_t)B.perm[sp];
+            b = (int32_t)B.perm[sp];
             pb = B.pos4[b];
             const double ex = fmax(0.0, fabs(min_image(pb.x - cen[0], periodic, box)) - hw[0]);
             const double ey = fmax(0.0, fabs(min_image(pb.y - cen[1], periodic, box)) - hw[1]);
             const double ez = fmax(0.0, fabs(min_image(pb.z - cen[2], periodic, box)) - hw[2]);
-            const double Rb = (hmx + pb.w) * (1.0 + 1e-9);
+            const double Rb = (hmx + pb.w) * s1 * (1.0 + 1e-9);
             pass = ex * ex + ey * ey + ez * ez < Rb * Rb;
           }
           const unsigned long long m = __ballot(pass);
@@ -516,7 +529,7 @@ __global__ __launch_bounds__(64) void k_build_tiles(BuildArgs B) {
           pend += __popcll(m);
           __syncthreads();
           if (pend >= 64) {   // phase 3 on a full batch
-            run_batch(B, T, cb, cbi, 64, periodic, box);
+            run_batch(B, T, cb, cbi, 64, periodic, box, s1);
             const int rest = pend - 64;
             double4 mv = make_double4(0.0, 0.0, 0.0, 0.0);
             int32_t mi = 0;
@@ -529,7 +542,7 @@ __global__ __launch_bounds__(64) void k_build_tiles(BuildArgs B) {
         }
       }
     }
-    if (pend > 0) run_batch(B, T, cb, cbi, pend, periodic, box);
+    if (pend > 0) run_batch(B, T, cb, cbi, pend, periodic, box, s1);
     __syncthreads();
     if (T.valid) B.count[p] = T.stored;
     if (lane == 0) B.tile_usize[t] = T.usize < T.ucap ? T.usize : T.ucap;
@@ -568,30 +581,49 @@ sph_status permute_array(sph_ctx* c, T* arr, int64_t n) {
 
 }  // namespace
 
-// Bin particles into the multi-level grid and build the neighbour lists.  With permute, every
-// particle array of the state (and the half-step copies) is reordered into cell order first.
-static unsigned tile_grid(const sph_ctx* c) {
-  return (unsigned)(c->cap_tiles < 65536 ? c->cap_tiles : 65536);
+// The union pool is sized to what the tiles reserve: read the reservation total and grow the
+// pool (by a quarter more than needed) when it does not fit.  Waits for the stream.
+static sph_status ensure_pool(sph_ctx* c) {
+  uint32_t used = 0;
+  HIP_TRY(hipMemcpyAsync(c->drift_host, &c->grid->upool_used, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  used = *c->drift_host;
+  if ((int64_t)used <= c->upool) return SPH_OK;
+  int64_t want = (int64_t)used + (int64_t)used / 4;
+  if (want > (int64_t)0xffffffffll) want = (int64_t)0xffffffffll;
+  HIP_TRY(hipFree(c->tile_u));
+  c->tile_u = nullptr;
+  c->upool = 0;
+  if (hipMalloc((void**)&c->tile_u, sizeof(int32_t) * (size_t)want) != hipSuccess) {
+    c->tile_u = nullptr;
+    return SPH_E_OOM;
+  }
+  c->upool = want;
+  return SPH_OK;
 }
 
-sph_status sph_rebin(sph_ctx* c, sph_state* st, bool permute) {
+static unsigned tile_grid(int64_t cap_tiles) {
+  return (unsigned)(cap_tiles < 65536 ? cap_tiles : 65536);
+}
+
+// Candidate-list build: every particle array of the state (and the half-step copies) is reordered
+// along the global Morton curve, tiles are cut from that order, particles are binned into the
+// multi-level grid and each tile's candidates are collected; the positions and h of this build
+// are kept for the drift test.
+sph_status sph_rebin(sph_ctx* c, sph_state* st) {
   const int64_t n = st->n;
   hipStream_t s = c->stream;
   const unsigned nb = grid_for(n, kB);
   unsigned nred = nb < 1024 ? nb : 1024;
-  // absolute positions for binning (ensemble stars are placed apart in one frame)
+  sph_status e;
   hipLaunchKernelGGL(k_pack_pos, dim3(nb), dim3(kB), 0, s, st->x, st->y, st->z, st->h,
                      (const int32_t*)nullptr, (const StarInfo*)nullptr, n, c->pos4, (float4*)nullptr);
   hipLaunchKernelGGL(k_bounds, dim3(nred), dim3(kB), 0, s, c->pos4, n, c->sort.partial);
   hipLaunchKernelGGL(k_grid_setup1, dim3(1), dim3(64), 0, s, c->grid, c->sort.partial, (int)nred, c->p.periodic,
-                     c->p.box, c->status);
-  hipLaunchKernelGGL(k_level_hmax, dim3(nred), dim3(kB), 0, s, c->pos4, n, c->grid);
-  hipLaunchKernelGGL(k_grid_setup2, dim3(1), dim3(1), 0, s, c->grid, c->p.cell_div > 0 ? c->p.cell_div : 2,
-                     c->max_cells, c->status);
-  hipLaunchKernelGGL(k_keys, dim3(nb), dim3(kB), 0, s, c->pos4, n, c->grid, c->keys, c->vals);
-  sph_status e = sph_sort_pairs(c, c->keys, c->vals, n);
-  if (e) return e;
-  if (permute) {
+                     c->p.box, c->p.skin, c->status);
+  {
+    hipLaunchKernelGGL(k_gkeys, dim3(nb), dim3(kB), 0, s, c->pos4, n, c->grid, c->keys, c->vals);
+    if ((e = sph_sort_pairs(c, c->keys, c->vals, n))) return e;
     double* d64[] = {st->x, st->y, st->z, st->vx, st->vy, st->vz, st->u, st->h, st->D, st->rho,
                      st->P, st->cs, st->ax, st->ay, st->az, st->dudt};
     for (double* a : d64)
@@ -606,32 +638,59 @@ sph_status sph_rebin(sph_ctx* c, sph_state* st, bool permute) {
     if ((e = permute_array(c, st->broken, n))) return e;
     if ((e = permute_array(c, st->id, n))) return e;
     if ((e = permute_array(c, st->star, n))) return e;
-    hipLaunchKernelGGL(k_identity, dim3(nb), dim3(kB), 0, s, c->vals, n);
     hipLaunchKernelGGL(k_pack_pos, dim3(nb), dim3(kB), 0, s, st->x, st->y, st->z, st->h,
                        (const int32_t*)nullptr, (const StarInfo*)nullptr, n, c->pos4, (float4*)nullptr);
-    c->identity_perm = 1;
-  } else {
-    c->identity_perm = 0;
+    // tile table for this order
+    uint32_t* flag = reinterpret_cast<uint32_t*>(c->tmp);
+    hipLaunchKernelGGL(k_tile_flags, dim3(nb), dim3(kB), 0, s, c->keys, c->pos4, n, c->grid,
+                       c->p.tile_cut > 0.0 ? c->p.tile_cut : 6.0, flag);
+    uint32_t* idx = flag + c->capw;
+    if ((e = sph_scan_u32(c, flag, idx, n, &c->grid->ntiles))) return e;
+    hipLaunchKernelGGL(k_tile_fill, dim3(nb), dim3(kB), 0, s, flag, idx, n, c->tile_start);
+    hipLaunchKernelGGL(k_tile_len, dim3(grid_for(c->cap_tiles, kB)), dim3(kB), 0, s, c->grid, n, c->cap_tiles,
+                       c->tile_start, c->tile_cnt, c->cap_s, c->ucap, c->tile_uoff);
+    if ((e = sph_scan_u32(c, c->tile_uoff, c->tile_uoff, c->cap_tiles, &c->grid->upool_used))) return e;
+    if ((e = ensure_pool(c))) return e;
   }
+  hipLaunchKernelGGL(k_level_hmax, dim3(nred), dim3(kB), 0, s, c->pos4, n, c->grid);
+  hipLaunchKernelGGL(k_grid_setup2, dim3(1), dim3(1), 0, s, c->grid, c->p.cell_div > 0 ? c->p.cell_div : 2,
+                     c->max_cells, c->status);
+  hipLaunchKernelGGL(k_keys, dim3(nb), dim3(kB), 0, s, c->pos4, n, c->grid, c->keys, c->vals);
+  if ((e = sph_sort_pairs(c, c->keys, c->vals, n))) return e;
   hipLaunchKernelGGL(k_cell_ranges, dim3(nb), dim3(kB), 0, s, c->keys, n, c->cell_start, c->cell_end);
-  uint32_t* tile_idx = reinterpret_cast<uint32_t*>(c->tmp);   // 0/1 tile starts, scanned in place
-  hipLaunchKernelGGL(k_tile_marks, dim3(nb), dim3(kB), 0, s, c->keys, n, c->grid, c->cell_start, c->cell_end,
-                     c->tile_flag, tile_idx);
-  if ((e = sph_scan_u32(c, tile_idx, tile_idx, n, &c->grid->ntiles))) return e;
-  hipLaunchKernelGGL(k_tile_fill, dim3(nb), dim3(kB), 0, s, c->tile_flag, tile_idx, n, c->cap_tiles, c->tile_start,
-                     c->tile_cnt, c->status);
-  hipLaunchKernelGGL(k_tile_ubound, dim3(grid_for(c->cap_tiles, kB)), dim3(kB), 0, s, c->grid, c->tile_cnt,
-                     c->cap_tiles, c->cap, c->ucap, c->tile_uoff);
-  if ((e = sph_scan_u32(c, c->tile_uoff, c->tile_uoff, c->cap_tiles, &c->grid->upool_used))) return e;
   BuildArgs B;
   B.pos4 = c->pos4; B.n = n; B.grid = c->grid; B.skeys = c->keys; B.perm = c->vals;
-  B.identity = c->identity_perm; B.cstart = c->cell_start; B.cend = c->cell_end;
-  B.tile_start = c->tile_start; B.tile_cnt = c->tile_cnt; B.cap_tiles = c->cap_tiles; B.capw = c->capw;
-  B.cap = c->cap; B.ucap = c->ucap; B.tile_uoff = c->tile_uoff; B.upool = c->upool; B.tile_u = c->tile_u;
-  B.tile_usize = c->tile_usize; B.nbr16 = c->nbr16; B.count = c->nbr_count; B.status = c->status;
-  hipLaunchKernelGGL(k_build_tiles, dim3(tile_grid(c)), dim3(64), 0, s, B);
+  B.cstart = c->cell_start; B.cend = c->cell_end; B.capw = c->capw; B.cap = c->cap_s; B.ucap = c->ucap;
+  B.tile_start = c->tile_start; B.tile_cnt = c->tile_cnt; B.tile_uoff = c->tile_uoff; B.upool = c->upool;
+  B.tile_u = c->tile_u; B.tile_usize = c->tile_usize; B.nbr16 = c->nbr16s; B.count = c->nbr_count_s;
+  B.status = c->status;
+  hipLaunchKernelGGL(k_build_tiles, dim3(tile_grid(c->cap_tiles)), dim3(64), 0, s, B);
   HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(c->pos_build, c->pos4, sizeof(double4) * n, hipMemcpyDeviceToDevice, s));
   return launch_pack(c, st);
+}
+
+// Skin test of the current positions and h against the last build (for sph_build_cells; inside
+// sph_step the test is fused into the drift kernel).
+__global__ __launch_bounds__(kB) void k_drift_check(const double* __restrict__ x, const double* __restrict__ y,
+                                                    const double* __restrict__ z, const double* __restrict__ h,
+                                                    const double4* __restrict__ pb, int64_t n,
+                                                    const GridInfo* __restrict__ gp, uint32_t id,
+                                                    uint32_t* __restrict__ flag) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  const GridInfo& g = *gp;
+  const double4 b = pb[a];
+  if (skin_exceeded(min_image(x[a] - b.x, g.periodic, g.box), min_image(y[a] - b.y, g.periodic, g.box),
+                    min_image(z[a] - b.z, g.periodic, g.box), h[a], b, g.skin))
+    atomicMax(flag, id);
+}
+
+sph_status launch_drift_check(sph_ctx* c, sph_state* st) {
+  hipLaunchKernelGGL(k_drift_check, dim3(grid_for(st->n, kB)), dim3(kB), 0, c->stream, st->x, st->y, st->z,
+                     st->h, c->pos_build, st->n, c->grid, c->check_id, c->drift_flag);
+  HIP_TRY(hipGetLastError());
+  return SPH_OK;
 }
 
 // Pack the position records the pair passes read, in the current particle order.
@@ -643,22 +702,45 @@ sph_status launch_pack(sph_ctx* c, sph_state* st) {
   return SPH_OK;
 }
 
-sph_status sph_count_stats(sph_ctx* c, int64_t* total, int32_t* mx) {
-  struct R { unsigned long long t; int32_t m; int32_t pad; };
+__global__ __launch_bounds__(kB) void k_union_stats(const int32_t* __restrict__ usize, const GridInfo* __restrict__ gp,
+                                                    unsigned long long* total) {
+  unsigned long long s = 0;
+  const int64_t nt = gp->ntiles;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += (int64_t)gridDim.x * blockDim.x)
+    s += (unsigned long long)usize[t];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) atomicAdd(total, s);
+}
+
+sph_status sph_count_stats(sph_ctx* c, sph_list_stats* out) {
+  struct R { unsigned long long t, u, cs; int32_t m, ms; };
   R* d = nullptr;
   if (hipMalloc((void**)&d, sizeof(R)) != hipSuccess) return SPH_E_OOM;
-  R h = {0ull, 0, 0};
+  R h = {0ull, 0ull, 0ull, 0, 0};
   sph_status e = SPH_OK;
   if (hipMemcpy(d, &h, sizeof(R), hipMemcpyHostToDevice) != hipSuccess) e = SPH_E_HIP;
-  if (!e && c->n > 0) {
+  if (!e && c->n > 0 && c->lists_valid) {
     unsigned nb = grid_for(c->n, kB);
-    hipLaunchKernelGGL(k_count_stats, dim3(nb < 1024 ? nb : 1024), dim3(kB), 0, c->stream, c->nbr_count, c->n,
-                       &d->t, &d->m);
+    nb = nb < 1024 ? nb : 1024;
+    if (c->gen >= 2)
+      hipLaunchKernelGGL(k_count_stats, dim3(nb), dim3(kB), 0, c->stream, c->nbr_count, c->n, &d->t, &d->m);
+    hipLaunchKernelGGL(k_count_stats, dim3(nb), dim3(kB), 0, c->stream, c->nbr_count_s, c->n, &d->cs, &d->ms);
+    hipLaunchKernelGGL(k_union_stats, dim3(256), dim3(kB), 0, c->stream, c->tile_usize, c->grid, &d->u);
     if (hipStreamSynchronize(c->stream) != hipSuccess) e = SPH_E_HIP;
   }
   if (!e && hipMemcpy(&h, d, sizeof(R), hipMemcpyDeviceToHost) != hipSuccess) e = SPH_E_HIP;
   (void)hipFree(d);
-  *total = (int64_t)h.t;
-  *mx = h.m;
+  out->pairs = (int64_t)h.t;
+  out->max_count = h.m;
+  out->pad = 0;
+  out->union_total = (int64_t)h.u;
+  out->candidates = (int64_t)h.cs;
+  out->rebuilds = c->rebuilds;
+  out->tiles = 0;
+  if (!e && c->n > 0 && c->lists_valid) {
+    GridInfo g;
+    if (hipMemcpy(&g, c->grid, sizeof(g), hipMemcpyDeviceToHost) != hipSuccess) return SPH_E_HIP;
+    out->tiles = (int64_t)g.ntiles;
+  }
   return e;
 }

@@ -22,6 +22,10 @@ struct KdkArgs {
   double* half;
   const int32_t* star; const StarInfo* stars;
   DevStatus* status;
+  // drift: packed position records for the next evaluation and the skin test
+  double4* pos4; float4* pos4f;
+  const double4* pos_build; const GridInfo* grid;
+  uint32_t check_id; uint32_t* flag;   // flag == nullptr: no test
 };
 
 __device__ __forceinline__ double wrap(double q, int periodic, double box) {
@@ -32,7 +36,8 @@ __device__ __forceinline__ double wrap(double q, int periodic, double box) {
   return q;
 }
 
-// half kick, drift, and predictors (velocity, energy, yielded stress) for the evaluation
+// half kick, drift, and predictors (velocity, energy, yielded stress) for the evaluation; also
+// packs the position records of the evaluation and runs the skin test against the last build
 __global__ __launch_bounds__(kB) void k_kick_drift(KdkArgs K) {
   const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= K.n) return;
@@ -51,9 +56,30 @@ __global__ __launch_bounds__(kB) void k_kick_drift(KdkArgs K) {
   H[1 * hs + a] = vh[1];
   H[2 * hs + a] = vh[2];
   H[3 * hs + a] = uh;
-  K.x[a] = wrap(K.x[a] + K.dt * vh[0], K.p.periodic, K.p.box);
-  K.y[a] = wrap(K.y[a] + K.dt * vh[1], K.p.periodic, K.p.box);
-  K.z[a] = wrap(K.z[a] + K.dt * vh[2], K.p.periodic, K.p.box);
+  const double xn = wrap(K.x[a] + K.dt * vh[0], K.p.periodic, K.p.box);
+  const double yn = wrap(K.y[a] + K.dt * vh[1], K.p.periodic, K.p.box);
+  const double zn = wrap(K.z[a] + K.dt * vh[2], K.p.periodic, K.p.box);
+  K.x[a] = xn;
+  K.y[a] = yn;
+  K.z[a] = zn;
+  const double h = K.h[a];
+  K.pos4[a] = make_double4(xn, yn, zn, h);
+  if (K.pos4f) {
+    double cx = 0.0, cy = 0.0, cz = 0.0;
+    if (K.star && K.stars) {
+      const StarInfo si = K.stars[K.star[a]];
+      cx = si.cx; cy = si.cy; cz = si.cz;
+    }
+    K.pos4f[a] = make_float4((float)(xn - cx), (float)(yn - cy), (float)(zn - cz), (float)h);
+  }
+  if (K.flag) {
+    const double4 b = K.pos_build[a];
+    const int per = K.p.periodic;
+    const double box = K.p.box;
+    if (skin_exceeded(min_image(xn - b.x, per, box), min_image(yn - b.y, per, box), min_image(zn - b.z, per, box),
+                      h, b, K.grid->skin))
+      atomicMax(K.flag, K.check_id);
+  }
   K.vx[a] = vh[0] + hdt * K.ax[a];
   K.vy[a] = vh[1] + hdt * K.ay[a];
   K.vz[a] = vh[2] + hdt * K.az[a];
@@ -112,13 +138,20 @@ KdkArgs make_kdk(sph_ctx* c, sph_state* st, double dt) {
   K.star = c->stars ? st->star : nullptr;
   K.stars = c->stars;
   K.status = c->status;
+  K.pos4 = c->pos4;
+  K.pos4f = c->p.precision == SPH_FP32 ? c->pos4f : nullptr;
+  K.pos_build = c->pos_build;
+  K.grid = c->grid;
+  K.check_id = c->check_id;
+  K.flag = nullptr;
   return K;
 }
 
 }  // namespace
 
-sph_status launch_kick_drift(sph_ctx* c, sph_state* st, double dt) {
+sph_status launch_kick_drift(sph_ctx* c, sph_state* st, double dt, bool check) {
   KdkArgs K = make_kdk(c, st, dt);
+  if (check) K.flag = c->drift_flag;
   hipLaunchKernelGGL(k_kick_drift, dim3(grid_for(st->n, kB)), dim3(kB), 0, c->stream, K);
   HIP_TRY(hipGetLastError());
   return SPH_OK;

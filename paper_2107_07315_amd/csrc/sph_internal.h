@@ -29,7 +29,8 @@ struct GridInfo {
   int32_t nlev;
   int32_t periodic;
   double box;
-  uint32_t ntiles;      // tiles of the current lists (written on the device)
+  double skin;          // relative Verlet skin of the current candidate lists (0 or >= 1e-4)
+  uint32_t ntiles;      // tiles of the current array order (written on the device)
   uint32_t upool_used;  // union-pool entries reserved by the tiles
 };
 
@@ -96,10 +97,60 @@ __device__ __forceinline__ bool neighbour_test(double dx, double dy, double dz, 
   return r2 < H * H;
 }
 
+// r^2 in the rounding order of neighbour_test (for passes that test and then use r).
+__device__ __forceinline__ double pair_r2(double dx, double dy, double dz) {
+#pragma clang fp contract(off)
+  return (dx * dx + dy * dy) + dz * dz;
+}
+
+// The same test against the skin-widened support (1 + s)(h_a + h_b); s1 = 1 + s.  With s = 0 it
+// is bit-identical to neighbour_test.
+__device__ __forceinline__ bool candidate_test(double dx, double dy, double dz, double ha, double hb, double s1) {
+#pragma clang fp contract(off)
+  double r2 = (dx * dx + dy * dy) + dz * dz;
+  double H = (ha + hb) * s1;
+  return r2 < H * H;
+}
+
+// Verlet-skin test: candidate lists built at positions/h `b` with skin s stay a superset of the
+// exact lists while every particle satisfies |x - x_b| + max(0, h - h_b) <= s h_b: for a pair
+// now within h_a + h_b, the distance at build time was below
+// h_a + h_b + (|dx_a| + dh_a) + (|dx_b| + dh_b) <= (1 + s)(h_a,b + h_b,b).  The factor 1 - 1e-9
+// absorbs the rounding of both tests (s >= 1e-4).  NaN counts as exceeded.
+__device__ __forceinline__ bool skin_exceeded(double dx, double dy, double dz, double h, double4 b, double s) {
+  const double d = sqrt(dx * dx + dy * dy + dz * dz);
+  const double dh = h > b.w ? h - b.w : 0.0;
+  return !(d + dh <= s * b.w * (1.0 - 1e-9));
+}
+
+// ---- fast reciprocal and square root -----------------------------------------------------------
+// FP64: hardware rcp/rsq estimates refined by Newton steps (a few ulp, far inside the parity
+// tolerance; the neighbour decision never uses them).  FP32: single hardware instructions.
+__device__ __forceinline__ double rcp_fast(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(fma(-x, y, 1.0), y, y);
+  y = fma(fma(-x, y, 1.0), y, y);
+  return y;
+}
+__device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double sqrt_fast(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  double r = x * y;
+  r = fma(0.5 * y, fma(-r, r, x), r);
+  return x > 0.0 ? r : 0.0;
+}
+__device__ __forceinline__ float sqrt_fast(float x) {
+  const float r = x * __builtin_amdgcn_rsqf(x);
+  return x > 0.0f ? r : 0.0f;
+}
+
 // ---- Wendland kernels with support 2 h_ab: W and F such that grad_a W = F (x_a - x_b) -------
 template <typename R>
 __device__ __forceinline__ void wendland(int kernel, R r, R hab, R& W, R& F) {
-  R ih = (R)1 / hab;
+  R ih = rcp_fast(hab);
   R q = r * ih;
   if (q >= (R)2) { W = 0; F = 0; return; }
   R t = (R)1 - (R)0.5 * q;
@@ -209,30 +260,39 @@ struct sph_ctx {
   int64_t n;            // particles at the last build
   int device;
   int32_t gen;          // stage order: 1 cells, 2 density, 3 stress, 4 forces
-  int32_t identity_perm;
-  int32_t steps_since_sort;
+  bool lists_valid;     // candidate lists match the current n, order and parameters
+  uint32_t check_id;    // id of the last drift test (written to drift_flag by violators)
+  uint32_t* drift_flag; // device word: largest check id that saw a skin violation
+  uint32_t* drift_host; // pinned host copy
+  int64_t rebuilds;
+  double4* pos_build;   // x, y, z, h at the last candidate-list build
   // grid and sort
   GridInfo* grid;       // device
-  uint32_t *keys, *vals;  // sorted keys and permutation (sorted position -> particle index)
+  uint32_t *keys, *vals;  // cell-sorted keys and permutation (sorted position -> particle index)
   int32_t *cell_start, *cell_end;
   int64_t max_cells;
   SortScratch sort;
-  // tile neighbour lists: tile t = sorted positions [tile_start[t], tile_start[t] + tile_cnt[t])
-  // (at most 64, never crossing a super-cell of 2x2x2 cells); U_t = tile_u + tile_uoff[t] holds the
-  // union of the tile's neighbours (particle indices); entry k of sorted position p is the local
-  // index nbr16[k*capw + p] into U_t; nbr_count is indexed by sorted position
+  // tile neighbour lists: tile t = particles [tile_start[t], tile_start[t] + tile_cnt[t]) of the
+  // array order (at most 64; the array is kept along the global Morton curve); U_t = tile_u +
+  // tile_uoff[t] holds the union of the tile's candidates (particle indices).  Candidate entry k
+  // of particle p is the local index into U_t stored at nbr16s[((k/8)*capw + p)*8 + k%8] (groups
+  // of 8 entries per lane, so a lane fetches 8 entries with one 16-byte load and a wave's load is
+  // one contiguous 1 KB); the exact lists that the density pass extracts use the same layout in
+  // nbr16 with nbr_count.
   int32_t* tile_start;
   int32_t* tile_cnt;
-  int32_t* tile_u;      // union pool; tile t owns [tile_uoff[t], tile_uoff[t] + min(ucap, cnt*cap))
-  uint32_t* tile_uoff;
-  int64_t upool;        // pool entries
+  uint32_t* tile_uoff;  // tile t owns tile_u[tile_uoff[t], + min(ucap, cnt * cap_s))
+  int32_t* tile_u;
+  int64_t upool;        // entries of tile_u
+  int64_t cap_tiles;
   int32_t* tile_usize;
   uint16_t* nbr16;
   int32_t* nbr_count;
-  uint32_t* tile_flag;  // scratch: per sorted position tile length (0 = not a tile start), then scan
+  uint16_t* nbr16s;
+  int32_t* nbr_count_s;
   int64_t capw;         // capacity rounded up to 64
-  int64_t cap_tiles;
-  int32_t cap;
+  int32_t cap;          // exact-list capacity
+  int32_t cap_s;        // candidate-list capacity
   int32_t ucap;
   // packed gather records (FP64 and FP32 variants)
   double4* pos4;        // x, y, z, h
@@ -262,19 +322,24 @@ struct sph_ctx {
 
 // ---- host launchers (one per kernel file) ------------------------------------------------------
 sph_status sph_sort_pairs(sph_ctx* c, uint32_t* keys, uint32_t* vals, int64_t n);
-sph_status sph_rebin(sph_ctx* c, sph_state* st, bool permute);
+sph_status sph_rebin(sph_ctx* c, sph_state* st);
+sph_status launch_drift_check(sph_ctx* c, sph_state* st);
 sph_status launch_density(sph_ctx* c, sph_state* st);
 sph_status launch_stress(sph_ctx* c, sph_state* st);
 sph_status launch_forces(sph_ctx* c, sph_state* st);
-sph_status launch_kick_drift(sph_ctx* c, sph_state* st, double dt);
+sph_status launch_kick_drift(sph_ctx* c, sph_state* st, double dt, bool check);
 sph_status launch_kick_final(sph_ctx* c, sph_state* st, double dt);
 sph_status launch_pack(sph_ctx* c, sph_state* st);
-sph_status sph_count_stats(sph_ctx* c, int64_t* total, int32_t* mx);
+sph_status sph_count_stats(sph_ctx* c, sph_list_stats* out);
 sph_status sph_scan_u32(sph_ctx* c, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total);
 
 enum { TIMER_CELLS = 0, TIMER_DENSITY = 1, TIMER_STRESS = 2, TIMER_FORCES = 3, TIMER_KDK = 4 };
 void timer_begin(sph_ctx* c, int which);
 void timer_end(sph_ctx* c, int which);
+
+__host__ __device__ __forceinline__ int64_t nbr_index(int64_t k, int64_t p, int64_t capw) {
+  return (((k >> 3) * capw + p) << 3) + (k & 7);
+}
 
 #define HIP_TRY(expr)                                   \
   do {                                                  \

@@ -1,31 +1,62 @@
-// Pair passes of the particle loop: density (+ EoS epilogue), velocity gradient / stress rate,
-// and momentum/energy forces (+ fixed-background epilogue).
+// Pair passes of the particle loop: density (+ EoS epilogue and the exact neighbour decision),
+// velocity gradient / stress rate, and momentum/energy forces (+ fixed-background epilogue).
 //
-// One workgroup = one wavefront = one tile of 64 consecutive particles of the cell order (one
-// lane per target).  The tile's neighbour union U is streamed through LDS in chunks of CH packed
-// records (loaded by the whole wave, runs of consecutive particles, so the loads coalesce); each
-// lane walks its ascending 16-bit local list and reads its neighbours' records from LDS.  This
-// replaces scattered per-lane gathers from L2 with one staged load per union member.  The pair
-// arithmetic is templated on the pair precision R: double in the FP64 path, float in the
-// mixed-precision path; epilogues (metric, EoS, GR terms) are FP64.
+// One workgroup = one wavefront = one tile of at most 64 consecutive particles (one lane per
+// target).  The tile's neighbour union U is streamed through LDS in chunks of CH packed records
+// (loaded by the whole wave); each lane walks its ascending 16-bit local list and reads its
+// neighbours' records from LDS.  The walk is software-pipelined: list entries arrive 8 per
+// 16-byte load one group ahead of use, and the next neighbour's LDS record is read before the
+// current pair's arithmetic.  Kernel type and periodicity are compile-time parameters so the
+// inner loops are straight-line code.  The pair arithmetic is templated on the pair precision
+// R: double in the FP64 path, float in the mixed-precision path; epilogues (metric, EoS, GR
+// terms) are FP64.
+#include <type_traits>
+
 #include "sph_internal.h"
 
 namespace {
 
 constexpr int kB = 256;
 
-template <typename R>
-__device__ __forceinline__ R wendland_F(int kernel, R r, R hab) {
-  R ih = (R)1 / hab;
-  R q = r * ih;
-  if (q >= (R)2) return (R)0;
-  R t = (R)1 - (R)0.5 * q;
-  R ih2 = ih * ih, ih5 = ih2 * ih2 * ih;
-  if (kernel == SPH_WC4) {
-    R t2 = t * t;
-    return -(R)(1155.0 / (128.0 * SPH_PI)) * ih5 * t2 * t2 * t * ((R)1 + (R)2.5 * q);
+// minimum image with selects (same result as min_image, no branches)
+template <bool PER, typename T>
+__device__ __forceinline__ T wrap_sel(T d, T box, T half) {
+  if constexpr (PER) {
+    const T lo = d - box, hi = d + box;
+    return d > half ? lo : (d < -half ? hi : d);
+  } else {
+    return d;
   }
-  return -(R)(105.0 / (16.0 * SPH_PI)) * ih5 * t * t * t;
+}
+
+// Wendland kernel value and gradient factor (grad_a W = F (x_a - x_b)) for 1/h_ab = ih; the
+// factor (1 - q/2) is clamped at 0 so that no branch is needed outside the support.
+template <typename R, int KER>
+__device__ __forceinline__ R kern_W(R r, R ih) {
+  const R q = r * ih;
+  R t = (R)1 - (R)0.5 * q;
+  t = t > (R)0 ? t : (R)0;
+  const R ih3 = ih * ih * ih;
+  if constexpr (KER == SPH_WC4) {
+    const R t2 = t * t, t6 = t2 * t2 * t2;
+    return (R)(495.0 / (256.0 * SPH_PI)) * ih3 * t6 * ((R)1 + (R)3 * q + (R)(35.0 / 12.0) * q * q);
+  } else {
+    const R t2 = t * t;
+    return (R)(21.0 / (16.0 * SPH_PI)) * ih3 * t2 * t2 * ((R)1 + (R)2 * q);
+  }
+}
+template <typename R, int KER>
+__device__ __forceinline__ R kern_F(R r, R ih) {
+  const R q = r * ih;
+  R t = (R)1 - (R)0.5 * q;
+  t = t > (R)0 ? t : (R)0;
+  const R ih2 = ih * ih, ih5 = ih2 * ih2 * ih;
+  if constexpr (KER == SPH_WC4) {
+    const R t2 = t * t;
+    return -(R)(1155.0 / (128.0 * SPH_PI)) * ih5 * t2 * t2 * t * ((R)1 + (R)2.5 * q);
+  } else {
+    return -(R)(105.0 / (16.0 * SPH_PI)) * ih5 * t * t * t;
+  }
 }
 
 template <typename R> struct Rec;
@@ -33,34 +64,34 @@ template <> struct Rec<double> {
   using P4 = double4;
   using V4 = double4;
   using A2 = double2;
-  static constexpr int CH_POS = 256;    // LDS records per chunk: 8 KB (density)
-  static constexpr int CH_PV = 128;     // 8 KB (stress)
-  static constexpr int CH_ALL = 128;    // 10 KB (forces)
+  static constexpr int CH_D = 256;   // LDS records per chunk: density 8 KB
+  static constexpr int CH_S = 128;   // stress 8 KB
+  static constexpr int CH_F = 128;   // forces 10 KB
 };
 template <> struct Rec<float> {
   using P4 = float4;
   using V4 = float4;
   using A2 = float2;
-  static constexpr int CH_POS = 512;
-  static constexpr int CH_PV = 256;
-  static constexpr int CH_ALL = 256;
+  static constexpr int CH_D = 256;   // density records are FP64 in both precisions
+  static constexpr int CH_S = 256;
+  static constexpr int CH_F = 256;
 };
 
 struct PassArgs {
   sph_params p;
   int64_t n;
   int cap, ucap;
-  int64_t capw, cap_tiles;
+  int64_t capw;
   const GridInfo* __restrict__ grid;
   const int32_t* __restrict__ tile_start;
   const int32_t* __restrict__ tile_cnt;
-  const int32_t* __restrict__ tile_u;
   const uint32_t* __restrict__ tile_uoff;
+  const int32_t* __restrict__ tile_u;
   const int32_t* __restrict__ tile_usize;
-  const uint16_t* __restrict__ nbr16;
+  const uint16_t* __restrict__ nbr16;    // exact lists (written by the density pass)
   const int32_t* __restrict__ cnt;
-  const uint32_t* __restrict__ perm;
-  int identity;
+  const uint16_t* __restrict__ nbr16s;   // candidate lists of the last build
+  const int32_t* __restrict__ cnt_s;
   const int32_t* __restrict__ star;
   const StarInfo* __restrict__ stars;
   DevStatus* status;
@@ -68,38 +99,49 @@ struct PassArgs {
 
 constexpr int kNone = 0x7fffffff;
 
-// Per-lane view of the tile lists.
+// Per-lane view of the tile lists.  Entries come 8 per 16-byte load; the group after the current
+// one is always in flight, and the current group is consumed by funnel shifts.
 struct TileWalk {
-  int64_t t, p, a;
+  int64_t p, a;
   bool valid;
   int usize, cnt, k, next;
-  const uint16_t* lst;
+  const uint4* grp_base;   // group g of this lane at grp_base[g * capw]
+  int64_t capw;
+  uint4 cur, nxt;
   const int32_t* U;
-  int64_t stride;
-  __device__ __forceinline__ void init(const PassArgs& A, int64_t tile) {
-    t = tile;
-    const int tc = A.tile_cnt[t];
-    p = (int64_t)A.tile_start[t] + threadIdx.x;
-    valid = (int)threadIdx.x < tc;
-    a = valid ? (A.identity ? p : (int64_t)A.perm[p]) : 0;
-    usize = A.tile_usize[t];
-    cnt = valid ? A.cnt[p] : 0;
-    stride = A.capw;
-    lst = A.nbr16 + (valid ? p : 0);
-    U = A.tile_u + A.tile_uoff[t];
+  __device__ __forceinline__ void init(const PassArgs& A, int64_t tile, const uint16_t* lists,
+                                       const int32_t* counts) {
+    p = (int64_t)A.tile_start[tile] + threadIdx.x;
+    valid = (int)threadIdx.x < A.tile_cnt[tile];
+    a = valid ? p : 0;
+    usize = A.tile_usize[tile];
+    cnt = valid ? counts[p] : 0;
+    capw = A.capw;
+    grp_base = reinterpret_cast<const uint4*>(lists) + (valid ? p : 0);
+    U = A.tile_u + A.tile_uoff[tile];
     k = 0;
-    next = cnt > 0 ? (int)lst[0] : kNone;
+    cur = make_uint4(0u, 0u, 0u, 0u);
+    nxt = cur;
+    if (cnt > 0) cur = grp_base[0];
+    if (cnt > 8) nxt = grp_base[capw];
+    next = cnt > 0 ? (int)(cur.x & 0xffffu) : kNone;
   }
   __device__ __forceinline__ void advance() {
     ++k;
-    next = k < cnt ? (int)lst[(int64_t)k * stride] : kNone;
+    if ((k & 7) == 0) {
+      cur = nxt;
+      if (k + 8 < cnt) nxt = grp_base[(int64_t)((k >> 3) + 1) * capw];
+    } else {
+      cur.x = __builtin_amdgcn_alignbit(cur.y, cur.x, 16u);
+      cur.y = __builtin_amdgcn_alignbit(cur.z, cur.y, 16u);
+      cur.z = __builtin_amdgcn_alignbit(cur.w, cur.z, 16u);
+      cur.w >>= 16;
+    }
+    next = k < cnt ? (int)(cur.x & 0xffffu) : kNone;
   }
 };
 
-__device__ __forceinline__ int64_t num_tiles(const PassArgs& A) {
-  const int64_t nt = (int64_t)A.grid->ntiles;
-  return nt < A.cap_tiles ? nt : A.cap_tiles;
-}
+__device__ __forceinline__ int64_t num_tiles(const PassArgs& A) { return (int64_t)A.grid->ntiles; }
 
 __device__ __forceinline__ double particle_mass(const PassArgs& A, int64_t a) {
   return (A.star && A.stars) ? A.stars[A.star[a]].m : A.p.m;
@@ -156,42 +198,92 @@ struct DensOut {
   float* sigf;
 };
 
-template <typename R>
-__global__ __launch_bounds__(64) void k_density(PassArgs A, const typename Rec<R>::P4* __restrict__ pos,
-                                                const double4* __restrict__ pos64, const double* __restrict__ vx,
-                                                const double* __restrict__ vy, const double* __restrict__ vz,
-                                                const double* __restrict__ u, const double* __restrict__ S,
-                                                const int8_t* __restrict__ type, const uint8_t* __restrict__ broken,
-                                                DensOut O) {
-  using P4 = typename Rec<R>::P4;
-  constexpr int CH = Rec<R>::CH_POS;
-  __shared__ P4 sp[CH];
+// Appends 16-bit local indices to a lane's exact list, 8 per 16-byte store (the layout TileWalk
+// reads).  put() is branch-free except for the store of a full group.
+struct ListWriter {
+  uint4* base;             // group g of this lane at base[g * capw]
+  int64_t capw;
+  int cap;
+  int n;
+  uint32_t w0, w1, w2, w3;
+  __device__ __forceinline__ void put(int loc, bool hit) {
+    const uint32_t v = hit ? ((uint32_t)loc << ((n & 1) << 4)) : 0u;
+    const int ws = (n >> 1) & 3;
+    w0 |= ws == 0 ? v : 0u;
+    w1 |= ws == 1 ? v : 0u;
+    w2 |= ws == 2 ? v : 0u;
+    w3 |= ws == 3 ? v : 0u;
+    n += hit ? 1 : 0;
+    if (hit && (n & 7) == 0) {
+      if (n <= cap) base[(int64_t)((n >> 3) - 1) * capw] = make_uint4(w0, w1, w2, w3);
+      w0 = w1 = w2 = w3 = 0u;
+    }
+  }
+  __device__ __forceinline__ void flush() {
+    if ((n & 7) && n <= cap) base[(int64_t)(n >> 3) * capw] = make_uint4(w0, w1, w2, w3);
+  }
+};
+
+// Density pass.  Walks the candidate lists, takes the exact FP64 neighbour decision
+// r^2 < (h_a + h_b)^2 on every candidate (positions staged in LDS in FP64 for both precisions),
+// sums the kernel over the neighbours in R, and writes the exact lists for the stress and force
+// passes.
+template <typename R, int KER, bool PER>
+__global__ __launch_bounds__(64) void k_density(PassArgs A, const double4* __restrict__ pos64,
+                                                const double* __restrict__ vx, const double* __restrict__ vy,
+                                                const double* __restrict__ vz, const double* __restrict__ u,
+                                                const double* __restrict__ S, const int8_t* __restrict__ type,
+                                                const uint8_t* __restrict__ broken, DensOut O,
+                                                uint16_t* __restrict__ xlist, int32_t* __restrict__ xcount) {
+  constexpr int CH = Rec<R>::CH_D;
+  __shared__ double4 sp[CH];
+  const double box = A.p.box, half = 0.5 * box;
   const int64_t ntl = num_tiles(A);
   for (int64_t tile = blockIdx.x; tile < ntl; tile += gridDim.x) {
   TileWalk tw;
-  tw.init(A, tile);
+  tw.init(A, tile, A.nbr16s, A.cnt_s);
   const int64_t a = tw.a;
   const sph_params& p = A.p;
-  const int periodic = p.periodic;
-  const R box = (R)p.box;
-  P4 pa = tw.valid ? pos[a] : P4{0, 0, 0, 1};
-  R sum = wendland_self<R>(p.kernel, pa.w);
+  const double4 pa = tw.valid ? pos64[a] : make_double4(0.0, 0.0, 0.0, 1.0);
+  R sum = wendland_self<R>(KER, (R)pa.w);
+  ListWriter wr;
+  wr.base = reinterpret_cast<uint4*>(xlist) + (tw.valid ? tw.p : 0);
+  wr.capw = A.capw;
+  wr.cap = A.cap;
+  wr.n = 0;
+  wr.w0 = wr.w1 = wr.w2 = wr.w3 = 0u;
   for (int c0 = 0; c0 < tw.usize; c0 += CH) {
     __syncthreads();
-    for (int j = threadIdx.x; j < CH && c0 + j < tw.usize; j += 64) sp[j] = pos[tw.U[c0 + j]];
+    for (int j = threadIdx.x; j < CH && c0 + j < tw.usize; j += 64) sp[j] = pos64[tw.U[c0 + j]];
     __syncthreads();
     const int cend = c0 + CH;
-    while (tw.next < cend) {
-      const P4 pb = sp[tw.next - c0];
-      R dx = min_image<R>(pa.x - pb.x, periodic, box);
-      R dy = min_image<R>(pa.y - pb.y, periodic, box);
-      R dz = min_image<R>(pa.z - pb.z, periodic, box);
-      R r = sqrt(dx * dx + dy * dy + dz * dz);
-      R W, F;
-      wendland<R>(p.kernel, r, (R)0.5 * (pa.w + pb.w), W, F);
-      sum += W;
+    if (tw.next < cend) {
+      double4 pb = sp[tw.next - c0];
+      int loc = tw.next;
       tw.advance();
+      while (true) {
+        const bool more = tw.next < cend;
+        const double4 pn = sp[more ? tw.next - c0 : 0];
+        const double dx = wrap_sel<PER>(pa.x - pb.x, box, half);
+        const double dy = wrap_sel<PER>(pa.y - pb.y, box, half);
+        const double dz = wrap_sel<PER>(pa.z - pb.z, box, half);
+        const double r2 = pair_r2(dx, dy, dz);
+        const double H = pa.w + pb.w;
+        const bool hit = r2 < H * H;
+        const R W = kern_W<R, KER>(sqrt_fast((R)r2), rcp_fast((R)(0.5 * H)));
+        sum += hit ? W : (R)0;
+        wr.put(loc, hit);
+        if (!more) break;
+        pb = pn;
+        loc = tw.next;
+        tw.advance();
+      }
     }
+  }
+  wr.flush();
+  if (tw.valid) {
+    xcount[tw.p] = wr.n < A.cap ? wr.n : A.cap;
+    if (wr.n > A.cap) latch_error(A.status, SPH_E_NGB_CAPACITY, (int)a);
   }
   if (!tw.valid) continue;
   const double m = particle_mass(A, a);
@@ -248,7 +340,7 @@ __global__ __launch_bounds__(64) void k_density(PassArgs A, const typename Rec<R
 }
 
 // ---- velocity gradient and stress rate ---------------------------------------------------------
-template <typename R>
+template <typename R, int KER, bool PER>
 __global__ __launch_bounds__(64) void k_stress(PassArgs A, const typename Rec<R>::P4* __restrict__ pos,
                                                const typename Rec<R>::V4* __restrict__ fv,
                                                const typename Rec<R>::A2* __restrict__ fa,
@@ -256,13 +348,14 @@ __global__ __launch_bounds__(64) void k_stress(PassArgs A, const typename Rec<R>
                                                double* __restrict__ dSdt, double* __restrict__ sdot) {
   using P4 = typename Rec<R>::P4;
   using V4 = typename Rec<R>::V4;
-  constexpr int CH = Rec<R>::CH_PV;
+  constexpr int CH = Rec<R>::CH_S;
   __shared__ P4 sp[CH];
   __shared__ V4 sv[CH];
+  const R box = (R)A.p.box, half = (R)0.5 * box;
   const int64_t ntl = num_tiles(A);
   for (int64_t tile = blockIdx.x; tile < ntl; tile += gridDim.x) {
   TileWalk tw;
-  tw.init(A, tile);
+  tw.init(A, tile, A.nbr16, A.cnt);
   const int64_t a = tw.a;
   const int64_t n = A.n;
   const typename Rec<R>::A2 faa = tw.valid ? fa[a] : typename Rec<R>::A2{0, 1};
@@ -276,8 +369,6 @@ __global__ __launch_bounds__(64) void k_stress(PassArgs A, const typename Rec<R>
   const sph_params& p = A.p;
   const P4 pa = tw.valid ? pos[a] : P4{0, 0, 0, 1};
   const V4 va = tw.valid ? fv[a] : V4{0, 0, 0, 0};
-  const int periodic = p.periodic;
-  const R box = (R)p.box;
   R G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   for (int c0 = 0; c0 < tw.usize; c0 += CH) {
     __syncthreads();
@@ -288,20 +379,30 @@ __global__ __launch_bounds__(64) void k_stress(PassArgs A, const typename Rec<R>
     }
     __syncthreads();
     const int cend = c0 + CH;
-    while (tw.next < cend) {
-      const P4 pb = sp[tw.next - c0];
-      const V4 vb = sv[tw.next - c0];
-      R d[3] = {min_image<R>(pa.x - pb.x, periodic, box), min_image<R>(pa.y - pb.y, periodic, box),
-                min_image<R>(pa.z - pb.z, periodic, box)};
-      R r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-      R F = wendland_F<R>(p.kernel, r, (R)0.5 * (pa.w + pb.w));
-      R g[3] = {F * d[0], F * d[1], F * d[2]};
-      R v[3] = {vb.x - va.x, vb.y - va.y, vb.z - va.z};
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int jj = 0; jj < 3; ++jj) G[i][jj] += v[i] * g[jj];
+    if (tw.next < cend) {
+      P4 pb = sp[tw.next - c0];
+      V4 vb = sv[tw.next - c0];
       tw.advance();
+      while (true) {
+        const bool more = tw.next < cend;
+        const int jn = more ? tw.next - c0 : 0;
+        const P4 pn = sp[jn];
+        const V4 vn = sv[jn];
+        const R d[3] = {wrap_sel<PER>(pa.x - pb.x, box, half), wrap_sel<PER>(pa.y - pb.y, box, half),
+                        wrap_sel<PER>(pa.z - pb.z, box, half)};
+        const R r = sqrt_fast(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        const R F = kern_F<R, KER>(r, rcp_fast((R)0.5 * (pa.w + pb.w)));
+        const R g[3] = {F * d[0], F * d[1], F * d[2]};
+        const R v[3] = {vb.x - va.x, vb.y - va.y, vb.z - va.z};
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int jj = 0; jj < 3; ++jj) G[i][jj] += v[i] * g[jj];
+        if (!more) break;
+        pb = pn;
+        vb = vn;
+        tw.advance();
+      }
     }
   }
   if (!stressed) continue;
@@ -353,7 +454,7 @@ struct ForceOut {
   double *ax, *ay, *az, *dudt;
 };
 
-template <typename R>
+template <typename R, int KER, bool PER>
 __global__ __launch_bounds__(64) void k_forces(PassArgs A, const typename Rec<R>::P4* __restrict__ pos,
                                                const typename Rec<R>::V4* __restrict__ fv,
                                                const typename Rec<R>::A2* __restrict__ fa,
@@ -364,14 +465,15 @@ __global__ __launch_bounds__(64) void k_forces(PassArgs A, const typename Rec<R>
   using P4 = typename Rec<R>::P4;
   using V4 = typename Rec<R>::V4;
   using A2 = typename Rec<R>::A2;
-  constexpr int CH = Rec<R>::CH_ALL;
+  constexpr int CH = Rec<R>::CH_F;
   __shared__ P4 sp[CH];
   __shared__ V4 sv[CH];
   __shared__ A2 sa2[CH];
+  const R box = (R)A.p.box, half = (R)0.5 * box;
   const int64_t ntl = num_tiles(A);
   for (int64_t tile = blockIdx.x; tile < ntl; tile += gridDim.x) {
   TileWalk tw;
-  tw.init(A, tile);
+  tw.init(A, tile, A.nbr16, A.cnt);
   const int64_t a = tw.a;
   const int64_t n = A.n;
   const sph_params& p = A.p;
@@ -385,8 +487,6 @@ __global__ __launch_bounds__(64) void k_forces(PassArgs A, const typename Rec<R>
   if (a_st)
 #pragma unroll
     for (int c = 0; c < 6; ++c) sa[c] = sig[c * n + a];
-  const int periodic = p.periodic;
-  const R box = (R)p.box;
   const R alpha_v = (R)p.visc_alpha, beta_v = (R)p.visc_beta, eps_v = (R)p.visc_eps;
   R AP[3] = {0, 0, 0}, AS[3] = {0, 0, 0}, ud = 0;
   for (int c0 = 0; c0 < tw.usize; c0 += CH) {
@@ -399,44 +499,57 @@ __global__ __launch_bounds__(64) void k_forces(PassArgs A, const typename Rec<R>
     }
     __syncthreads();
     const int cend = c0 + CH;
-    while (tw.next < cend) {
-      const int jl = tw.next - c0;
-      const P4 pb = sp[jl];
-      const V4 vb = sv[jl];
-      const A2 fab = sa2[jl];
-      R d[3] = {min_image<R>(pa.x - pb.x, periodic, box), min_image<R>(pa.y - pb.y, periodic, box),
-                min_image<R>(pa.z - pb.z, periodic, box)};
-      R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-      R r = sqrt(r2);
-      R hab = (R)0.5 * (pa.w + pb.w);
-      R F = wendland_F<R>(p.kernel, r, hab);
-      R g[3] = {F * d[0], F * d[1], F * d[2]};
-      R v[3] = {va.x - vb.x, va.y - vb.y, va.z - vb.z};
-      R vr = v[0] * d[0] + v[1] * d[1] + v[2] * d[2];
-      const bool b_st = fab.y < 0;
-      const R Db = b_st ? -fab.y : fab.y;
-      R Pi = 0;
-      if (vr < 0) {   // Monaghan viscosity on approaching pairs
-        R muab = hab * vr / (r2 + eps_v * hab * hab);
-        R cbar = (R)0.5 * (va.w + vb.w);
-        R Dbar = (R)0.5 * (Da + Db);
-        Pi = (-alpha_v * cbar * muab + beta_v * muab * muab) / Dbar;
-      }
-      R cP = pia + fab.x + Pi;
-      AP[0] += cP * g[0];
-      AP[1] += cP * g[1];
-      AP[2] += cP * g[2];
-      ud += (pia + (R)0.5 * Pi) * (v[0] * g[0] + v[1] * g[1] + v[2] * g[2]);
-      if (a_st || b_st) {
-        R s6[6];
-        const int32_t b = b_st ? tw.U[tw.next] : 0;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) s6[c] = sa[c] + (b_st ? sig[c * n + b] : (R)0);
-        AS[0] += s6[0] * g[0] + s6[3] * g[1] + s6[4] * g[2];
-        AS[1] += s6[3] * g[0] + s6[1] * g[1] + s6[5] * g[2];
-        AS[2] += s6[4] * g[0] + s6[5] * g[1] + s6[2] * g[2];
-      }
+    if (tw.next < cend) {
+      P4 pb = sp[tw.next - c0];
+      V4 vb = sv[tw.next - c0];
+      A2 fab = sa2[tw.next - c0];
+      int loc = tw.next;
       tw.advance();
+      while (true) {
+        const bool more = tw.next < cend;
+        const int jn = more ? tw.next - c0 : 0;
+        const P4 pn = sp[jn];
+        const V4 vn = sv[jn];
+        const A2 fn = sa2[jn];
+        const R d[3] = {wrap_sel<PER>(pa.x - pb.x, box, half), wrap_sel<PER>(pa.y - pb.y, box, half),
+                        wrap_sel<PER>(pa.z - pb.z, box, half)};
+        const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        const R r = sqrt_fast(r2);
+        const R hab = (R)0.5 * (pa.w + pb.w);
+        const R F = kern_F<R, KER>(r, rcp_fast(hab));
+        const R g[3] = {F * d[0], F * d[1], F * d[2]};
+        const R v[3] = {va.x - vb.x, va.y - vb.y, va.z - vb.z};
+        const R vr = v[0] * d[0] + v[1] * d[1] + v[2] * d[2];
+        const bool b_st = fab.y < 0;
+        const R Db = b_st ? -fab.y : fab.y;
+        // Monaghan viscosity on approaching pairs: one reciprocal gives 1/X and 1/Dbar
+        const R X = r2 + eps_v * hab * hab;
+        const R Dbar = (R)0.5 * (Da + Db);
+        const R inv = rcp_fast(X * Dbar);
+        const R muab = hab * vr * (Dbar * inv);
+        const R cbar = (R)0.5 * (va.w + vb.w);
+        const R Pi = vr < (R)0 ? (-alpha_v * cbar * muab + beta_v * muab * muab) * (X * inv) : (R)0;
+        const R cP = pia + fab.x + Pi;
+        AP[0] += cP * g[0];
+        AP[1] += cP * g[1];
+        AP[2] += cP * g[2];
+        ud += (pia + (R)0.5 * Pi) * (v[0] * g[0] + v[1] * g[1] + v[2] * g[2]);
+        if (a_st || b_st) {
+          R s6[6];
+          const int32_t b = b_st ? tw.U[loc] : 0;
+#pragma unroll
+          for (int c = 0; c < 6; ++c) s6[c] = sa[c] + (b_st ? sig[c * n + b] : (R)0);
+          AS[0] += s6[0] * g[0] + s6[3] * g[1] + s6[4] * g[2];
+          AS[1] += s6[3] * g[0] + s6[1] * g[1] + s6[5] * g[2];
+          AS[2] += s6[4] * g[0] + s6[5] * g[1] + s6[2] * g[2];
+        }
+        if (!more) break;
+        pb = pn;
+        vb = vn;
+        fab = fn;
+        loc = tw.next;
+        tw.advance();
+      }
     }
   }
   if (!tw.valid) continue;
@@ -487,17 +600,16 @@ PassArgs make_args(sph_ctx* c, sph_state* st) {
   A.cap = c->cap;
   A.ucap = c->ucap;
   A.capw = c->capw;
-  A.cap_tiles = c->cap_tiles;
   A.grid = c->grid;
   A.tile_start = c->tile_start;
   A.tile_cnt = c->tile_cnt;
-  A.tile_u = c->tile_u;
   A.tile_uoff = c->tile_uoff;
+  A.tile_u = c->tile_u;
   A.tile_usize = c->tile_usize;
   A.nbr16 = c->nbr16;
   A.cnt = c->nbr_count;
-  A.perm = c->vals;
-  A.identity = c->identity_perm;
+  A.nbr16s = c->nbr16s;
+  A.cnt_s = c->nbr_count_s;
   A.star = c->stars ? st->star : nullptr;
   A.stars = c->stars;
   A.status = c->status;
@@ -506,29 +618,51 @@ PassArgs make_args(sph_ctx* c, sph_state* st) {
 
 }  // namespace
 
+// Calls f(kernel, periodic) with both as compile-time constants.
+template <typename Fn>
+static void dispatch_cfg(int kernel, int periodic, Fn&& f) {
+  if (kernel == SPH_WC4) {
+    if (periodic) f(std::integral_constant<int, SPH_WC4>{}, std::true_type{});
+    else f(std::integral_constant<int, SPH_WC4>{}, std::false_type{});
+  } else {
+    if (periodic) f(std::integral_constant<int, SPH_WC2>{}, std::true_type{});
+    else f(std::integral_constant<int, SPH_WC2>{}, std::false_type{});
+  }
+}
+
+static dim3 pass_grid(const sph_ctx* c) { return dim3((unsigned)(c->cap_tiles < 65536 ? c->cap_tiles : 65536)); }
+
 sph_status launch_density(sph_ctx* c, sph_state* st) {
   PassArgs A = make_args(c, st);
   DensOut O{st->D, st->rho, st->P, st->cs, c->mu, c->Y0, c->B, c->fv, c->fa, c->sig, c->fvf, c->faf, c->sigf};
-  dim3 g((unsigned)(c->cap_tiles < 65536 ? c->cap_tiles : 65536)), b(64);
-  if (c->p.precision == SPH_FP32)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_density<float>), g, b, 0, c->stream, A, c->pos4f, c->pos4, st->vx, st->vy,
-                       st->vz, st->u, st->S, st->type, st->broken, O);
-  else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_density<double>), g, b, 0, c->stream, A, c->pos4, c->pos4, st->vx, st->vy,
-                       st->vz, st->u, st->S, st->type, st->broken, O);
+  const dim3 g = pass_grid(c), b(64);
+  dispatch_cfg(c->p.kernel, c->p.periodic, [&](auto K, auto P) {
+    constexpr int KER = decltype(K)::value;
+    constexpr bool PER = decltype(P)::value;
+    if (c->p.precision == SPH_FP32)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_density<float, KER, PER>), g, b, 0, c->stream, A, c->pos4, st->vx, st->vy,
+                         st->vz, st->u, st->S, st->type, st->broken, O, c->nbr16, c->nbr_count);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_density<double, KER, PER>), g, b, 0, c->stream, A, c->pos4, st->vx,
+                         st->vy, st->vz, st->u, st->S, st->type, st->broken, O, c->nbr16, c->nbr_count);
+  });
   HIP_TRY(hipGetLastError());
   return SPH_OK;
 }
 
 sph_status launch_stress(sph_ctx* c, sph_state* st) {
   PassArgs A = make_args(c, st);
-  dim3 g((unsigned)(c->cap_tiles < 65536 ? c->cap_tiles : 65536)), b(64);
-  if (c->p.precision == SPH_FP32)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stress<float>), g, b, 0, c->stream, A, c->pos4f, c->fvf, c->faf, st->S,
-                       c->mu, st->dSdt, c->sdot);
-  else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stress<double>), g, b, 0, c->stream, A, c->pos4, c->fv, c->fa, st->S,
-                       c->mu, st->dSdt, c->sdot);
+  const dim3 g = pass_grid(c), b(64);
+  dispatch_cfg(c->p.kernel, c->p.periodic, [&](auto K, auto P) {
+    constexpr int KER = decltype(K)::value;
+    constexpr bool PER = decltype(P)::value;
+    if (c->p.precision == SPH_FP32)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stress<float, KER, PER>), g, b, 0, c->stream, A, c->pos4f, c->fvf, c->faf,
+                         st->S, c->mu, st->dSdt, c->sdot);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stress<double, KER, PER>), g, b, 0, c->stream, A, c->pos4, c->fv, c->fa,
+                         st->S, c->mu, st->dSdt, c->sdot);
+  });
   HIP_TRY(hipGetLastError());
   return SPH_OK;
 }
@@ -536,13 +670,17 @@ sph_status launch_stress(sph_ctx* c, sph_state* st) {
 sph_status launch_forces(sph_ctx* c, sph_state* st) {
   PassArgs A = make_args(c, st);
   ForceOut O{st->ax, st->ay, st->az, st->dudt};
-  dim3 g((unsigned)(c->cap_tiles < 65536 ? c->cap_tiles : 65536)), b(64);
-  if (c->p.precision == SPH_FP32)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forces<float>), g, b, 0, c->stream, A, c->pos4f, c->fvf, c->faf, c->sigf,
-                       c->pos4, st->u, st->P, st->rho, c->sdot, O);
-  else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forces<double>), g, b, 0, c->stream, A, c->pos4, c->fv, c->fa, c->sig,
-                       c->pos4, st->u, st->P, st->rho, c->sdot, O);
+  const dim3 g = pass_grid(c), b(64);
+  dispatch_cfg(c->p.kernel, c->p.periodic, [&](auto K, auto P) {
+    constexpr int KER = decltype(K)::value;
+    constexpr bool PER = decltype(P)::value;
+    if (c->p.precision == SPH_FP32)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forces<float, KER, PER>), g, b, 0, c->stream, A, c->pos4f, c->fvf, c->faf,
+                         c->sigf, c->pos4, st->u, st->P, st->rho, c->sdot, O);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forces<double, KER, PER>), g, b, 0, c->stream, A, c->pos4, c->fv, c->fa,
+                         c->sig, c->pos4, st->u, st->P, st->rho, c->sdot, O);
+  });
   HIP_TRY(hipGetLastError());
   return SPH_OK;
 }

@@ -37,9 +37,15 @@ class SphParams(ctypes.Structure):
         ("mu_pfactor", ctypes.c_double), ("yield_mode", ctypes.c_int32), ("y0_mode", ctypes.c_int32),
         ("y0_const", ctypes.c_double), ("y0_over_E", ctypes.c_double), ("break_mode", ctypes.c_int32),
         ("eps_break", ctypes.c_double), ("rotation", ctypes.c_int32), ("precision", ctypes.c_int32),
-        ("max_neighbours", ctypes.c_int32), ("resort_every", ctypes.c_int32),
-        ("cell_div", ctypes.c_int32),
+        ("max_neighbours", ctypes.c_int32), ("cell_div", ctypes.c_int32),
+        ("tile_cut", ctypes.c_double), ("skin", ctypes.c_double),
     ]
+
+
+class SphListStats(ctypes.Structure):
+    _fields_ = [("pairs", ctypes.c_int64), ("max_count", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("tiles", ctypes.c_int64), ("union_total", ctypes.c_int64),
+                ("candidates", ctypes.c_int64), ("rebuilds", ctypes.c_int64)]
 
 
 class SphState(ctypes.Structure):
@@ -80,7 +86,7 @@ def load():
     L.sph_status_string.argtypes = [ctypes.c_int]
     L.sph_status_string.restype = ctypes.c_char_p
     L.sph_set_timing.argtypes = [vp, ctypes.c_int32]
-    L.sph_neighbour_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]
+    L.sph_neighbour_stats.argtypes = [vp, ctypes.POINTER(SphListStats)]
     L.sph_get_timing.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32),
                                  ctypes.POINTER(ctypes.c_double)]
     _lib = L
@@ -142,8 +148,11 @@ class DeviceState:
 class Context:
     """Owns an sph_ctx and the device copies of the background and EoS tables."""
 
-    def __init__(self, params, capacity: int, stream=None, max_neighbours=0, resort_every=0,
-                 cell_div=0):
+    # relative Verlet skin of the candidate lists (0: rebuild at every evaluation)
+    DEFAULT_SKIN = 0.1
+
+    def __init__(self, params, capacity: int, stream=None, max_neighbours=0, cell_div=0, tile_cut=0.0,
+                 skin=None):
         import torch
         from sph_inputs.params import (BACKGROUNDS, BREAK_MODES, EOS_KINDS, H_MODES, KERNELS, MU_MODES,
                                        PRECISIONS, ROTATIONS, Y0_MODES, YIELD_MODES)
@@ -183,8 +192,9 @@ class Context:
         p.rotation = ROTATIONS[params.rotation]
         p.precision = PRECISIONS[params.precision]
         p.max_neighbours = max_neighbours
-        p.resort_every = resort_every
         p.cell_div = cell_div
+        p.tile_cut = tile_cut
+        p.skin = self.DEFAULT_SKIN if skin is None else skin
         self.p = p
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = ctypes.c_void_p()
@@ -245,10 +255,10 @@ class Context:
         return n.value, ms.value
 
     def sph_neighbour_stats(self):
-        t = ctypes.c_int64()
-        m = ctypes.c_int32()
-        _check(self.lib.sph_neighbour_stats(self.h, ctypes.byref(t), ctypes.byref(m)), "sph_neighbour_stats")
-        return t.value, m.value
+        s = SphListStats()
+        _check(self.lib.sph_neighbour_stats(self.h, ctypes.byref(s)), "sph_neighbour_stats")
+        return {k: getattr(s, k) for k in ("pairs", "max_count", "tiles", "union_total", "candidates",
+                                           "rebuilds")}
 
     # convenience ---------------------------------------------------------------------------
     def evaluate(self, st: DeviceState):

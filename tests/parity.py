@@ -7,7 +7,10 @@ import oracle
 FIELDS_EVAL = ("D", "rho", "P", "cs", "ax", "ay", "az", "dudt")
 
 
-def gpu_run(w, steps=0, precision=None, ctx_kw=None, params=None):
+def gpu_run(w, steps=0, precision=None, ctx_kw=None, params=None, lists=None):
+    """Evaluate (and step) on the GPU; returns the state in id order.  With lists (default: only
+    when steps == 0) the exact neighbour lists of the last evaluation come back as "_lists" (by
+    id), and the list statistics as "_stats"."""
     from paper_2107_07315_amd import sph
     p = params or w.params
     if precision:
@@ -15,23 +18,24 @@ def gpu_run(w, steps=0, precision=None, ctx_kw=None, params=None):
     ctx = sph.Context(p, capacity=w.n, **(ctx_kw or {}))
     st = sph.DeviceState(w.arrays)
     ctx.evaluate(st)
-    nb = None
-    if steps == 0:
-        off, ids = ctx.sph_export_neighbours(w.n)
-        nb = (off, ids)
     if steps:
         ctx.sph_step(st, w.dt, steps)
     ctx.sph_sync()
+    nb = None
+    if lists if lists is not None else steps == 0:
+        nb = ctx.sph_export_neighbours(w.n)
+    stats = ctx.sph_neighbour_stats()
     g = st.numpy()
     order = np.argsort(g["id"])
     out = {k: (v[..., order] if v.ndim == 2 else v[order]) for k, v in g.items()}
+    out["_stats"] = stats
     if nb is not None:
         off, ids = nb
         ident = g["id"]
-        lists = {}
+        lst = {}
         for a in range(w.n):
-            lists[int(ident[a])] = np.sort(ident[ids[off[a]:off[a + 1]]])
-        out["_lists"] = lists
+            lst[int(ident[a])] = np.sort(ident[ids[off[a]:off[a + 1]]])
+        out["_lists"] = lst
     ctx.close()
     return out
 

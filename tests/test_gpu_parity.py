@@ -188,11 +188,16 @@ def test_stage_order_and_argument_errors():
 def test_neighbour_capacity_error_is_latched():
     w = W.lattice(n_side=8)
     sph, ctx, st = _ctx_state(w, max_neighbours=40)   # each particle has 80 neighbours
-    ctx.sph_build_cells(st)
+    ctx.evaluate(st)                                  # exact lists overflow in the density pass
     with pytest.raises(sph.SphError) as e:
         ctx.sph_sync()
     assert e.value.code == 5
     ctx.sph_sync()    # the status word was cleared
+    sph, ctx, st = _ctx_state(w, max_neighbours=20)   # candidate lists (twice that) overflow too
+    ctx.sph_build_cells(st)
+    with pytest.raises(sph.SphError) as e:
+        ctx.sph_sync()
+    assert e.value.code == 5
 
 
 def test_periodic_smoothing_length_limit():
@@ -222,12 +227,22 @@ def test_nonfinite_and_eos_domain_errors():
     assert e.value.code == 7
 
 
-def test_rebin_without_resort_matches_full_resort():
-    # steps that only re-bin (perm indirection) give the same result as re-sorting every step
+def test_skin_lists_match_rebuild_every_evaluation():
+    # candidate lists kept across steps with a Verlet skin give the same exact neighbour sets and
+    # the same fields as rebuilding at every evaluation; a tiny skin forces rebuilds mid-run
     w = W.star(20000, seed=2)
-    g1 = gpu_run(w, steps=4, ctx_kw={"resort_every": 1})
-    g2 = gpu_run(w, steps=4, ctx_kw={"resort_every": 100})
-    e = field_errors(g2, g1, ("x", "vx", "u", "D", "ax", "dudt"))
-    _print("resort", e)
-    for k, v in e.items():
-        assert v < 1e-11, (k, v)
+    runs = {s: gpu_run(w, steps=8, ctx_kw={"skin": s}, lists=True) for s in (0.0, 1e-3, 0.05)}
+    ref = runs[0.0]
+    assert ref["_stats"]["rebuilds"] == 9
+    for s in (1e-3, 0.05):
+        g = runs[s]
+        bad = sum(1 for a in range(w.n) if not np.array_equal(g["_lists"][a], ref["_lists"][a]))
+        assert bad == 0, (s, bad)
+        assert g["_stats"]["pairs"] == ref["_stats"]["pairs"]
+        assert g["_stats"]["candidates"] > g["_stats"]["pairs"]
+        e = field_errors(g, ref, ("x", "vx", "u", "D", "ax", "dudt"))
+        _print(f"skin {s} rebuilds={g['_stats']['rebuilds']}", e)
+        for k, v in e.items():
+            assert v < 1e-11, (s, k, v)
+    assert runs[0.05]["_stats"]["rebuilds"] <= runs[1e-3]["_stats"]["rebuilds"] <= 9
+    assert runs[1e-3]["_stats"]["rebuilds"] >= 2
