@@ -16,17 +16,46 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work of the force pass, counted from the kernel source (fma = 2 FLOP; sqrt,
-# reciprocal and division counted as 1 each): per ordered pair visit 62 FLOP, per particle
-# epilogue 60 FLOP (fixed-background terms).  Algorithmic HBM bytes per particle: the
-# neighbour list (4 B per entry) plus the particle's own records read once (position 32 B,
-# velocity/sound speed 32 B, P/D^2 and D 16 B, u/P/rho/S:epsdot 32 B) and 32 B written;
-# neighbour records are re-reads served by cache, not algorithmic traffic.
-FORCE_FLOP_PER_PAIR = 62
-FORCE_FLOP_PER_PARTICLE = 60
-FORCE_BYTES_PER_PARTICLE_FP64 = 32 + 32 + 16 + 32 + 32
-FORCE_BYTES_PER_PARTICLE_FP32 = 16 + 16 + 8 + 32 + 32
+# Algorithmic work of the two dominant pair passes, counted from the kernel source (add, mul =
+# 1 FLOP, fma = 2, sqrt and reciprocal 1 each; the crust-only stress terms are left out).
+#  density: per candidate the exact FP64 test (3 sub, r^2 5, H and H^2 2) = 10; per neighbour
+#           pair the kernel value (sqrt, rcp, 0.5 H, q, 1 - q/2, powers, polynomial, sum) = 20;
+#           per particle the epilogue (metric, Lorentz factor, EoS table, moduli) ~ 110.
+#  forces:  per neighbour pair 73 (distance 8, kernel gradient 18, viscosity 26, sums 21);
+#           per particle the fixed-background epilogue ~ 110.
+# Algorithmic HBM bytes: lists at 2 B per entry (candidate lists read and exact lists written by
+# the density pass, exact lists read by the force pass) plus each particle's own records read
+# and results written once; neighbour records staged through LDS are re-reads served by the
+# caches and are not counted.
+DENS_FLOP = {"candidate": 10, "pair": 20, "particle": 110}
+FORCE_FLOP = {"pair": 73, "particle": 110}
+DENS_BYTES = {"FP64": 274, "FP32": 226, "candidate": 2, "pair": 2}
+FORCE_BYTES = {"FP64": 176, "FP32": 136, "pair": 2}
 PEAK = {"FP64": 78.6e12, "FP32": 157.3e12}     # published MI355X vector peaks, FLOP/s
+KERNEL_SOURCES = ("paper_2107_07315_amd/csrc/sph_pairs.hip", "paper_2107_07315_amd/csrc/sph_internal.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pair_passes_2M_traffic.json")
+
+
+def sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
+    or None if they were taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("sources") != sources_digest() or kernel not in t.get("kernels", {}):
+        return None
+    return t["kernels"][kernel]["bytes_per_launch"]
 
 
 def run_variant(w, precision, eos, steps, warmup, timing=True, ctx_kw=None):
@@ -57,24 +86,34 @@ def run_variant(w, precision, eos, steps, warmup, timing=True, ctx_kw=None):
     ctx.close()
     del st
     torch.cuda.empty_cache()
-    fl = stages["forces"]
-    avg_ms = fl["ms_total"] / max(fl["launches"], 1)
     return {"ms_per_step": ms_step, "value": w.n * steps / (t1 - t0), "stages": stages,
-            "pairs": pairs, "max_neighbours": maxc, "force_avg_ms": avg_ms, "stats": stats}
+            "pairs": pairs, "max_neighbours": maxc, "stats": stats}
 
 
 def roofline(res, n, precision):
-    flop = res["pairs"] * FORCE_FLOP_PER_PAIR + n * FORCE_FLOP_PER_PARTICLE
-    sec = res["force_avg_ms"] * 1e-3
+    """Roofline entry of the variant's dominant pair pass (longest average launch)."""
+    st = res["stats"]
+    pairs, cand = st["pairs"], st["candidates"]
+    f32 = precision == "FP32"
+    passes = {
+        "density": (f"k_density<{'float' if f32 else 'double'}>",
+                    cand * DENS_FLOP["candidate"] + pairs * DENS_FLOP["pair"] + n * DENS_FLOP["particle"],
+                    n * DENS_BYTES[precision] + cand * DENS_BYTES["candidate"] + pairs * DENS_BYTES["pair"]),
+        "forces": (f"k_forces<{'float' if f32 else 'double'}>",
+                   pairs * FORCE_FLOP["pair"] + n * FORCE_FLOP["particle"],
+                   n * FORCE_BYTES[precision] + pairs * FORCE_BYTES["pair"]),
+    }
+    avg = {k: res["stages"][k]["ms_total"] / max(res["stages"][k]["launches"], 1) for k in passes}
+    stage = max(avg, key=avg.get)
+    kernel, flop, nbytes = passes[stage]
+    sec = avg[stage] * 1e-3
     achieved = flop / sec / 1e12
     peak = PEAK[precision] / 1e12
-    nbytes = res["pairs"] * 4 + n * (FORCE_BYTES_PER_PARTICLE_FP64 if precision == "FP64"
-                                     else FORCE_BYTES_PER_PARTICLE_FP32)
-    return {"kernel": f"k_forces<{'double' if precision == 'FP64' else 'float'}>", "bound": "alu",
-            "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": None,
-            "algorithmic_GBps": round(nbytes / sec / 1e9, 1),
-            "flop_per_launch": flop, "launch_ms": round(res["force_avg_ms"], 4)}
+    return {"kernel": kernel, "bound": "alu", "achieved": round(achieved, 3), "peak": peak,
+            "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": measured_traffic(kernel),
+            "algorithmic_bytes": nbytes, "algorithmic_GBps": round(nbytes / sec / 1e9, 1),
+            "flop_per_launch": flop, "launch_ms": round(avg[stage], 4),
+            "other_pass_ms": {k: round(v, 4) for k, v in avg.items() if k != stage}}
 
 
 def cpu_baseline(w):

@@ -90,7 +90,7 @@ const char* sph_status_string(sph_status s) {
 void sph_destroy(sph_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
-  void* bufs[] = {c->grid, c->keys, c->vals, c->cell_start, c->cell_end, c->sort.keys_alt, c->sort.vals_alt,
+  void* bufs[] = {c->grid, c->keys, c->vals, c->cell_se, c->pos_sorted, c->sort.keys_alt, c->sort.vals_alt,
                   c->sort.hist, c->sort.rowtot, c->sort.partial, c->sort.scan_bsum, c->tile_u, c->tile_start, c->tile_cnt, c->tile_uoff,
                   c->tile_usize, c->nbr16, c->nbr_count, c->nbr16s, c->nbr_count_s, c->pos_build, c->drift_flag,
                   c->pos4, c->fv, c->fa, c->sig, c->pos4f, c->fvf,
@@ -132,7 +132,7 @@ sph_status sph_create(const sph_params* params, void* stream, int64_t capacity, 
   c->max_cells = kMaxCells;
   c->sort.max_blocks = (int)((cap + 4095) / 4096);
   if ((e = dalloc(&c->grid, 1)) || (e = dalloc(&c->keys, cap)) || (e = dalloc(&c->vals, cap)) ||
-      (e = dalloc(&c->cell_start, c->max_cells)) || (e = dalloc(&c->cell_end, c->max_cells)) ||
+      (e = dalloc(&c->cell_se, c->max_cells)) || (e = dalloc(&c->pos_sorted, cap)) ||
       (e = dalloc(&c->sort.keys_alt, cap)) || (e = dalloc(&c->sort.vals_alt, cap)) ||
       (e = dalloc(&c->sort.hist, (size_t)256 * c->sort.max_blocks)) || (e = dalloc(&c->sort.rowtot, 256)) ||
       (e = dalloc(&c->sort.partial, (size_t)8 * 1024)) ||
@@ -156,10 +156,7 @@ sph_status sph_create(const sph_params* params, void* stream, int64_t capacity, 
     sph_destroy(c);
     return SPH_E_OOM;
   }
-  // cell tables are validated against the sorted keys on every lookup, so they are cleared once
-  if (hipMemsetAsync(c->cell_start, 0xff, sizeof(int32_t) * c->max_cells, c->stream) != hipSuccess ||
-      hipMemsetAsync(c->cell_end, 0xff, sizeof(int32_t) * c->max_cells, c->stream) != hipSuccess ||
-      hipMemsetAsync(c->status, 0, sizeof(DevStatus), c->stream) != hipSuccess ||
+  if (hipMemsetAsync(c->status, 0, sizeof(DevStatus), c->stream) != hipSuccess ||
       hipMemsetAsync(c->nbr_count, 0, sizeof(int32_t) * cap, c->stream) != hipSuccess ||
       hipMemsetAsync(c->nbr_count_s, 0, sizeof(int32_t) * cap, c->stream) != hipSuccess ||
       hipMemsetAsync(c->drift_flag, 0, sizeof(uint32_t), c->stream) != hipSuccess ||

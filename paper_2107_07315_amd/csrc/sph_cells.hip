@@ -83,7 +83,13 @@ __global__ __launch_bounds__(64) void k_grid_setup1(GridInfo* g, const unsigned 
   for (int d = 0; d < 3; ++d) { g->enc_lo[d] = v[d]; g->enc_hi[d] = v[3 + d]; }
   g->enc_hmin = v[6];
   g->enc_hmax = v[7];
-  for (int l = 0; l < SPH_MAX_LEV; ++l) g->hlev_bits[l] = 0ull;
+  for (int l = 0; l < SPH_MAX_LEV; ++l) {
+    g->hlev_bits[l] = 0ull;
+    for (int d = 0; d < 3; ++d) {
+      g->lev_lo[l][d] = ~0ull;
+      g->lev_hi[l][d] = 0ull;
+    }
+  }
   g->periodic = periodic;
   g->box = box;
   for (int d = 0; d < 3; ++d) g->lo[d] = periodic ? 0.0 : dec_double(g->enc_lo[d]);
@@ -103,19 +109,42 @@ __global__ __launch_bounds__(64) void k_grid_setup1(GridInfo* g, const unsigned 
   g->nlev = L;
 }
 
+// Per level: largest h and the bounding box of the level's particles (a tile's search at a level
+// is clipped to that box, which keeps large-h tiles from enumerating the empty fine cells of
+// levels that only occupy the core).
 __global__ __launch_bounds__(kB) void k_level_hmax(const double4* __restrict__ pos4, int64_t n, GridInfo* g) {
   __shared__ unsigned long long m[SPH_MAX_LEV];
-  if (threadIdx.x < SPH_MAX_LEV) m[threadIdx.x] = 0ull;
+  __shared__ unsigned long long blo[SPH_MAX_LEV][3], bhi[SPH_MAX_LEV][3];
+  if (threadIdx.x < SPH_MAX_LEV) {
+    m[threadIdx.x] = 0ull;
+    for (int d = 0; d < 3; ++d) {
+      blo[threadIdx.x][d] = ~0ull;
+      bhi[threadIdx.x][d] = 0ull;
+    }
+  }
   __syncthreads();
   GridInfo G = *g;
   for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < n;
        a += (int64_t)gridDim.x * blockDim.x) {
-    double h = pos4[a].w;
-    int l = particle_level(h, G);
-    atomicMax(&m[l], (unsigned long long)__double_as_longlong(h));
+    const double4 q = pos4[a];
+    const int l = particle_level(q.w, G);
+    atomicMax(&m[l], (unsigned long long)__double_as_longlong(q.w));
+    const double c[3] = {q.x, q.y, q.z};
+    for (int d = 0; d < 3; ++d) {
+      const unsigned long long e = enc_double(c[d]);
+      atomicMin(&blo[l][d], e);
+      atomicMax(&bhi[l][d], e);
+    }
   }
   __syncthreads();
-  if (threadIdx.x < SPH_MAX_LEV && m[threadIdx.x]) atomicMax(&g->hlev_bits[threadIdx.x], m[threadIdx.x]);
+  if (threadIdx.x < SPH_MAX_LEV && m[threadIdx.x]) {
+    const int l = threadIdx.x;
+    atomicMax(&g->hlev_bits[l], m[l]);
+    for (int d = 0; d < 3; ++d) {
+      atomicMin(&g->lev_lo[l][d], blo[l][d]);
+      atomicMax(&g->lev_hi[l][d], bhi[l][d]);
+    }
+  }
 }
 
 __global__ void k_grid_setup2(GridInfo* g, int cell_div, int64_t max_cells, DevStatus* st) {
@@ -190,13 +219,20 @@ __global__ __launch_bounds__(kB) void k_keys(const double4* __restrict__ pos4, i
   vals[a] = (uint32_t)a;
 }
 
+// Clears the cells in use (base[nlev] entries) to empty ranges.
+__global__ __launch_bounds__(kB) void k_cells_clear(int2* __restrict__ se, const GridInfo* __restrict__ gp) {
+  const int64_t total = gp->base[gp->nlev];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
+    se[i] = make_int2(0, 0);
+}
+
 __global__ __launch_bounds__(kB) void k_cell_ranges(const uint32_t* __restrict__ keys, int64_t n,
-                                                    int32_t* __restrict__ cstart, int32_t* __restrict__ cend) {
+                                                    int2* __restrict__ se) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   uint32_t k = keys[i];
-  if (i == 0 || keys[i - 1] != k) cstart[k] = (int32_t)i;
-  if (i == n - 1 || keys[i + 1] != k) cend[k] = (int32_t)(i + 1);
+  if (i == 0 || keys[i - 1] != k) se[k].x = (int32_t)i;
+  if (i == n - 1 || keys[i + 1] != k) se[k].y = (int32_t)(i + 1);
 }
 
 template <typename T>
@@ -319,10 +355,9 @@ struct BuildArgs {
   const double4* __restrict__ pos4;
   int64_t n;
   const GridInfo* __restrict__ grid;
-  const uint32_t* __restrict__ skeys;
   const uint32_t* __restrict__ perm;   // cell-sorted position -> particle index
-  const int32_t* __restrict__ cstart;
-  const int32_t* __restrict__ cend;
+  const double4* __restrict__ pos_sorted;
+  const int2* __restrict__ cell_se;
   const int32_t* __restrict__ tile_start;
   const int32_t* __restrict__ tile_cnt;
   const uint32_t* __restrict__ tile_uoff;
@@ -343,6 +378,15 @@ __device__ __forceinline__ double wave_max_d(double v) {
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
   return v;
 }
+// min / max over aligned groups of 8 lanes
+__device__ __forceinline__ double grp8_min(double v) {
+  for (int off = 1; off < 8; off <<= 1) v = fmin(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ __forceinline__ double grp8_max(double v) {
+  for (int off = 1; off < 8; off <<= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
 __device__ __forceinline__ unsigned long long wave_or_u64(unsigned long long v) {
   for (int off = 32; off > 0; off >>= 1) v |= __shfl_xor(v, off, 64);
   return v;
@@ -352,24 +396,42 @@ struct TileState {
   int64_t a;
   bool valid;
   double xa, ya, za, ha;
-  int usize, cnt, stored, ucap;
+  int usize, cnt, ucap;
   int64_t p;
   int32_t* U;
+  uint32_t w0, w1, w2, w3;   // the lane's current group of 8 list entries
 };
 
+// Stores the lane's group g of 8 entries (16 bytes, the layout the pair passes read).
+__device__ __forceinline__ void store_group(const BuildArgs& B, const TileState& T, int g) {
+  reinterpret_cast<uint4*>(B.nbr16)[(int64_t)g * B.capw + T.p] = make_uint4(T.w0, T.w1, T.w2, T.w3);
+}
+
 // candidate test (skin-widened, FP64) of every lane's target against batch candidates cb[0..nb),
-// nb <= 64
+// nb <= 64; NB > 0 fixes nb at compile time (full batches, fully unrolled)
+template <int NB, bool PER>
 __device__ __forceinline__ void run_batch(const BuildArgs& B, TileState& T, const double4* cb, const int32_t* cbi,
-                                          int nb, int periodic, double box, double s1) {
+                                          int nb, double box, double s1) {
   const int lane = threadIdx.x;
   unsigned long long hm = 0ull;
+  auto test = [&](int j) -> bool {
+    const double4 pb = cb[j];
+    return cbi[j] != T.a &&
+           candidate_test(min_image(T.xa - pb.x, (int)PER, box), min_image(T.ya - pb.y, (int)PER, box),
+                          min_image(T.za - pb.z, (int)PER, box), T.ha, pb.w, s1);
+  };
   if (T.valid) {
-    for (int j = 0; j < nb; ++j) {
-      const double4 pb = cb[j];
-      const bool hit = cbi[j] != T.a &&
-                       candidate_test(min_image(T.xa - pb.x, periodic, box), min_image(T.ya - pb.y, periodic, box),
-                                      min_image(T.za - pb.z, periodic, box), T.ha, pb.w, s1);
-      hm |= (unsigned long long)hit << j;
+    if constexpr (NB > 0) {
+      // 8 candidates per step with constant bit positions
+#pragma unroll 1
+      for (int jb = 0; jb < NB; jb += 8) {
+        uint32_t m8 = 0u;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) m8 |= test(jb + k) ? (1u << k) : 0u;
+        hm |= (unsigned long long)m8 << jb;
+      }
+    } else {
+      for (int j = 0; j < nb; ++j) hm |= test(j) ? (1ull << j) : 0ull;
     }
   }
   const unsigned long long um = wave_or_u64(hm);
@@ -383,43 +445,221 @@ __device__ __forceinline__ void run_batch(const BuildArgs& B, TileState& T, cons
   while (mm) {
     const int j = __ffsll((long long)mm) - 1;
     mm &= mm - 1ull;
-    const int loc = T.usize + __popcll(um & ((1ull << j) - 1ull));
-    if (T.cnt < B.cap && loc < T.ucap) {
-      B.nbr16[nbr_index(T.cnt, T.p, B.capw)] = (uint16_t)loc;
-      ++T.stored;
-    }
+    int loc = T.usize + __popcll(um & ((1ull << j) - 1ull));
+    loc = loc < T.ucap ? loc : T.ucap - 1;   // union overflow: keep reads in range, error latched
+    const uint32_t v = (uint32_t)loc << ((T.cnt & 1) << 4);
+    const int ws = (T.cnt >> 1) & 3;
+    T.w0 |= ws == 0 ? v : 0u;
+    T.w1 |= ws == 1 ? v : 0u;
+    T.w2 |= ws == 2 ? v : 0u;
+    T.w3 |= ws == 3 ? v : 0u;
     ++T.cnt;
+    if ((T.cnt & 7) == 0) {
+      if (T.cnt <= B.cap) store_group(B, T, (T.cnt >> 3) - 1);
+      T.w0 = T.w1 = T.w2 = T.w3 = 0u;
+    }
   }
   T.usize += __popcll(um);
 }
 
+// Geometry of one tile, shared by the cost and build kernels: whole-tile box and max h
+// (wave-uniform), and in LDS the sub-boxes of the 8 groups of 8 consecutive particles with their
+// own max h.  Candidates and cells are tested against the sub-boxes, which stays tight where a
+// tile mixes small and large h (a candidate within (h_a + h_b)(1 + skin) of a particle a is that
+// close to a's sub-box).
+struct TileGeom {
+  double lo[3], hi[3], hmx;
+};
+
+__device__ __forceinline__ void tile_geometry(const double4 pa, bool valid, TileGeom& G, double (*sub)[8]) {
+  const int lane = threadIdx.x;
+  const double big = 1e300;
+  const double q[3] = {pa.x, pa.y, pa.z};
+  for (int d = 0; d < 3; ++d) {
+    G.lo[d] = wave_min_d(valid ? q[d] : big);
+    G.hi[d] = wave_max_d(valid ? q[d] : -big);
+  }
+  G.hmx = wave_max_d(valid ? pa.w : 0.0);
+  double gl[3], gh[3];
+  for (int d = 0; d < 3; ++d) {
+    gl[d] = grp8_min(valid ? q[d] : big);
+    gh[d] = grp8_max(valid ? q[d] : -big);
+  }
+  const double gx = grp8_max(valid ? pa.w : 0.0);
+  __syncthreads();
+  if ((lane & 7) == 0) {
+    for (int d = 0; d < 3; ++d) {
+      sub[lane >> 3][d] = 0.5 * (gl[d] + gh[d]);
+      sub[lane >> 3][3 + d] = 0.5 * (gh[d] - gl[d]);
+    }
+    sub[lane >> 3][6] = gx;
+  }
+  __syncthreads();
+}
+
+// Cells of level l that can hold candidates of the tile: the tile box widened by
+// (hmx + hlev[l])(1 + skin), clipped to the cells that hold the level's particles.
+struct LevelBox {
+  int lo3[3], ext[3];
+  bool wrap[3];
+  int64_t total;
+  double c;
+  uint32_t base;
+};
+
+template <bool PER>
+__device__ __forceinline__ bool level_box(const GridInfo& g, int l, const TileGeom& G, double s1, LevelBox& L) {
+  if (!g.hlev_bits[l]) return false;   // no particles at this level
+  L.c = g.cell[l];
+  L.base = g.base[l];
+  const double R = (G.hmx + g.hlev[l]) * s1 * (1.0 + 1e-9);
+  for (int d = 0; d < 3; ++d) {
+    const int dim = g.dims[l][d];
+    int l0 = (int)floor((G.lo[d] - R - g.lo[d]) / L.c);
+    int h0 = (int)floor((G.hi[d] + R - g.lo[d]) / L.c);
+    L.wrap[d] = false;
+    if (PER) {
+      if (h0 - l0 + 1 >= dim) { l0 = 0; h0 = dim - 1; }
+      else L.wrap[d] = true;
+    } else {
+      const int b0 = cell_coord(dec_double(g.lev_lo[l][d]), g.lo[d], L.c, dim);
+      const int b1 = cell_coord(dec_double(g.lev_hi[l][d]), g.lo[d], L.c, dim);
+      l0 = l0 < b0 ? b0 : l0;
+      h0 = h0 > b1 ? b1 : h0;
+    }
+    L.lo3[d] = l0;
+    L.ext[d] = h0 >= l0 ? h0 - l0 + 1 : 0;
+  }
+  L.total = (int64_t)L.ext[0] * L.ext[1] * L.ext[2];
+  return L.total > 0;
+}
+
+// Particle range [s, e) of the cell with linear index j of the level box (empty if the cell is
+// farther than (hmax_g + hlev[l])(1 + skin) from every sub-box).
+template <bool PER>
+__device__ __forceinline__ void cell_range(const GridInfo& g, int l, const LevelBox& L, int64_t j, double s1,
+                                           const double (*sub)[8], const int2* __restrict__ cell_se, int& s, int& e) {
+  s = e = 0;
+  if (j >= L.total) return;
+  const int kk[3] = {L.lo3[0] + (int)(j % L.ext[0]), L.lo3[1] + (int)((j / L.ext[0]) % L.ext[1]),
+                     L.lo3[2] + (int)(j / ((int64_t)L.ext[0] * L.ext[1]))};
+  int cc[3];
+  double b0[3], b1[3];
+  bool gapd[3];
+  for (int d = 0; d < 3; ++d) {
+    gapd[d] = !PER || L.wrap[d];
+    b0[d] = g.lo[d] + kk[d] * L.c;
+    b1[d] = b0[d] + L.c;
+    const int dim = g.dims[l][d];
+    cc[d] = L.wrap[d] ? ((kk[d] % dim) + dim) % dim : kk[d];
+  }
+  bool need = false;
+#pragma unroll 1
+  for (int gi = 0; gi < 8; ++gi) {
+    double gap2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      const double gd = fmax(0.0, fmax(b0[d] - (sub[gi][d] + sub[gi][3 + d]), (sub[gi][d] - sub[gi][3 + d]) - b1[d]));
+      gap2 += gapd[d] ? gd * gd : 0.0;
+    }
+    const double Rg = (sub[gi][6] + g.hlev[l]) * s1 * (1.0 + 1e-9);
+    need = need || (gap2 < Rg * Rg && sub[gi][6] > 0.0);
+  }
+  if (need) {
+    const uint32_t key = L.base + (spread3((uint32_t)cc[0]) | (spread3((uint32_t)cc[1]) << 1) |
+                                   (spread3((uint32_t)cc[2]) << 2));
+    const int2 se = cell_se[key];
+    s = se.x;
+    e = se.y;
+  }
+}
+
+// Cost estimate of each tile: the number of particles in the cells its build would gather.
+template <bool PER>
+__global__ __launch_bounds__(64) void k_tile_cost(const double4* __restrict__ pos4, const GridInfo* __restrict__ gp,
+                                                  const int32_t* __restrict__ tile_start,
+                                                  const int32_t* __restrict__ tile_cnt, const int2* __restrict__ cell_se,
+                                                  int32_t* __restrict__ cost) {
+  __shared__ double sub[8][8];
+  const int lane = threadIdx.x;
+  const GridInfo& g = *gp;
+  const double s1 = 1.0 + g.skin;
+  const int64_t ntiles = g.ntiles;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const bool valid = lane < tile_cnt[t];
+    const double4 pa = valid ? pos4[tile_start[t] + lane] : make_double4(0.0, 0.0, 0.0, 0.0);
+    TileGeom G;
+    tile_geometry(pa, valid, G, sub);
+    int64_t tot = 0;
+    for (int l = 0; l < g.nlev; ++l) {
+      LevelBox L;
+      if (!level_box<PER>(g, l, G, s1, L)) continue;
+      for (int64_t q = 0; q < L.total; q += 64) {
+        int s, e;
+        cell_range<PER>(g, l, L, q + lane, s1, sub, cell_se, s, e);
+        tot += e - s;
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off, 64);
+    if (lane == 0) cost[t] = (int32_t)(tot < 0x7fffffff ? tot : 0x7fffffff);
+    __syncthreads();
+  }
+}
+
+// Splits expensive tiles: a particle also starts a tile at every 16th (cost > kSplit16) or 8th
+// (cost > kSplit8) position of its tile.  Reads the tile of p from the scan of the old flags.
+constexpr int32_t kSplit16 = 6000, kSplit8 = 20000;
+__global__ __launch_bounds__(kB) void k_tile_split(uint32_t* __restrict__ flag, const uint32_t* __restrict__ idx,
+                                                   int64_t n, const int32_t* __restrict__ tile_start,
+                                                   const int32_t* __restrict__ cost) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const uint32_t f = flag[p];
+  const int64_t t = (int64_t)idx[p] + f - 1;
+  const int32_t c = cost[t];
+  const int64_t off = p - tile_start[t];
+  const int size = c > kSplit8 ? 8 : (c > kSplit16 ? 16 : 64);
+  flag[p] = (f || (off % size) == 0) ? 1u : 0u;
+}
+
+// Tile neighbour lists.  Each tile is handled by one wavefront (one lane per target), in three
+// latency-friendly phases per block of 64 candidate cells:
+//  1. the 64 lanes take 64 cells of the level box at once, cull them against the sub-boxes and
+//     load their particle ranges;
+//  2. the wave gathers the cells' particles 64 at a time (a wave-wide prefix sum maps lanes to
+//     (cell, offset)), pre-tests each against the sub-boxes and appends survivors to an LDS batch;
+//  3. per batch of 64 candidates every lane runs the skin-widened FP64 test against all of them,
+//     building a 64-bit hit mask; the OR of the masks gives the batch's new union members (in
+//     candidate order) and each lane appends the local indices of its hits.
+// Tile t is particles [tile_start[t], tile_start[t] + tile_cnt[t]) of the array order (at most 64).
+// Candidates enter batches in a fixed order (level, cell, cell-sorted position), so U and the
+// lists are deterministic and each list is ascending in local index.
+template <bool PER>
 __global__ __launch_bounds__(64) void k_build_tiles(BuildArgs B) {
   __shared__ int32_t c_s[64], c_o[64];
+  __shared__ double sub[8][8];   // per group of 8 tile particles: centre xyz, half-width xyz, max h
+  __shared__ double4 tp[64];     // the tile's particles (exact pre-filter of small tiles)
   __shared__ double4 cb[128];
   __shared__ int32_t cbi[128];
   const int lane = threadIdx.x;
   const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
   const GridInfo& g = *B.grid;
-  const int periodic = g.periodic;
   const double box = g.box;
   const double s1 = 1.0 + g.skin;
   const int64_t ntiles = g.ntiles;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int32_t tcnt = B.tile_cnt[t];   // (lists below are the candidate lists)
+    const int32_t tcnt = B.tile_cnt[t];
     const int64_t p = (int64_t)B.tile_start[t] + lane;
     TileState T;
     T.valid = lane < tcnt;
     T.a = T.valid ? p : -1;
-    double4 pa = T.valid ? B.pos4[T.a] : make_double4(0.0, 0.0, 0.0, 0.0);
+    const double4 pa = T.valid ? B.pos4[T.a] : make_double4(0.0, 0.0, 0.0, 0.0);
     T.xa = pa.x; T.ya = pa.y; T.za = pa.z; T.ha = pa.w;
-    const double big = 1e300;
-    double lo[3], hi[3];
-    lo[0] = wave_min_d(T.valid ? pa.x : big); hi[0] = wave_max_d(T.valid ? pa.x : -big);
-    lo[1] = wave_min_d(T.valid ? pa.y : big); hi[1] = wave_max_d(T.valid ? pa.y : -big);
-    lo[2] = wave_min_d(T.valid ? pa.z : big); hi[2] = wave_max_d(T.valid ? pa.z : -big);
-    const double hmx = wave_max_d(T.valid ? pa.w : 0.0);
-    double cen[3], hw[3];
-    for (int d = 0; d < 3; ++d) { cen[d] = 0.5 * (lo[d] + hi[d]); hw[d] = 0.5 * (hi[d] - lo[d]); }
+    TileGeom G;
+    tile_geometry(pa, T.valid, G, sub);
+    tp[lane] = pa;
+    // small tiles (split because they are expensive) pre-filter candidates exactly against
+    // their own particles: far fewer batches, each of which would use only tcnt lanes
+    const bool small = tcnt <= 16;
     const uint32_t uoff = B.tile_uoff[t];
     T.ucap = (int)((int64_t)tcnt * B.cap < B.ucap ? (int64_t)tcnt * B.cap : B.ucap);
     if ((int64_t)uoff + T.ucap > B.upool) {
@@ -428,63 +668,18 @@ __global__ __launch_bounds__(64) void k_build_tiles(BuildArgs B) {
     }
     T.U = B.tile_u + uoff;
     T.p = T.valid ? p : 0;
-    T.usize = 0; T.cnt = 0; T.stored = 0;
+    T.usize = 0; T.cnt = 0;
+    T.w0 = T.w1 = T.w2 = T.w3 = 0u;
     int pend = 0;   // candidates waiting in cb (wave-uniform)
     for (int l = 0; l < g.nlev; ++l) {
-      const double c = g.cell[l];
-      const double R = (hmx + g.hlev[l]) * s1 * (1.0 + 1e-9);
-      const double R2 = R * R;
-      int lo3[3], ext[3];
-      bool wrap[3];
-      for (int d = 0; d < 3; ++d) {
-        const int dim = g.dims[l][d];
-        int l0 = (int)floor((lo[d] - R - g.lo[d]) / c);
-        int h0 = (int)floor((hi[d] + R - g.lo[d]) / c);
-        wrap[d] = false;
-        if (periodic) {
-          if (h0 - l0 + 1 >= dim) { l0 = 0; h0 = dim - 1; }
-          else wrap[d] = true;
-        } else {
-          l0 = l0 < 0 ? 0 : l0;
-          h0 = h0 > dim - 1 ? dim - 1 : h0;
-        }
-        lo3[d] = l0;
-        ext[d] = h0 >= l0 ? h0 - l0 + 1 : 0;
-      }
-      const int64_t total = (int64_t)ext[0] * ext[1] * ext[2];
-      const uint32_t base = g.base[l];
-      for (int64_t q = 0; q < total; q += 64) {
+      LevelBox L;
+      if (!level_box<PER>(g, l, G, s1, L)) continue;
+      for (int64_t q = 0; q < L.total; q += 64) {
         // phase 1: 64 cells at once; lanes take the block's cells in bit-reversed order so that
         // consecutive union members come from all over the neighbourhood and every target's
         // neighbours spread evenly over the LDS chunks of the pair passes
-        const int64_t j = q + (int64_t)(__brev((unsigned)lane) >> 26);
-        int32_t s = 0, e = 0;
-        if (j < total) {
-          const int kx = lo3[0] + (int)(j % ext[0]);
-          const int ky = lo3[1] + (int)((j / ext[0]) % ext[1]);
-          const int kz = lo3[2] + (int)(j / ((int64_t)ext[0] * ext[1]));
-          const int kk[3] = {kx, ky, kz};
-          double gap2 = 0.0;
-          int cc[3];
-          for (int d = 0; d < 3; ++d) {
-            if (!periodic || wrap[d]) {
-              const double b0 = g.lo[d] + kk[d] * c, b1 = b0 + c;
-              const double gd = fmax(0.0, fmax(b0 - hi[d], lo[d] - b1));
-              gap2 += gd * gd;
-            }
-            const int dim = g.dims[l][d];
-            cc[d] = wrap[d] ? ((kk[d] % dim) + dim) % dim : kk[d];
-          }
-          if (gap2 < R2) {
-            const uint32_t key = base + (spread3((uint32_t)cc[0]) | (spread3((uint32_t)cc[1]) << 1) |
-                                         (spread3((uint32_t)cc[2]) << 2));
-            const int32_t s0 = B.cstart[key];
-            if (s0 >= 0 && s0 < B.n && B.skeys[s0] == key) {
-              s = s0;
-              e = B.cend[key];
-            }
-          }
-        }
+        int s, e;
+        cell_range<PER>(g, l, L, q + (int64_t)(__brev((unsigned)lane) >> 26), s1, sub, B.cell_se, s, e);
         // wave prefix sum of the cells' particle counts
         const int cntc = e - s;
         int inc = cntc;
@@ -497,54 +692,79 @@ __global__ __launch_bounds__(64) void k_build_tiles(BuildArgs B) {
         c_s[lane] = s;
         c_o[lane] = inc - cntc;
         __syncthreads();
-        // phase 2: gather candidates 64 at a time, pre-test against the tile box
-        for (int q0 = 0; q0 < Tc; q0 += 64) {
-          const int slot = q0 + lane;
-          const bool has = slot < Tc;
-          double4 pb = make_double4(0.0, 0.0, 0.0, 0.0);
-          int32_t b = 0;
-          bool pass = false;
-          if (has) {
-            int lo_i = 0, hi_i = 63;   // last cell with c_o <= slot
-            while (lo_i < hi_i) {
-              const int mid = (lo_i + hi_i + 1) >> 1;
-              if (c_o[mid] <= slot) lo_i = mid;
-              else hi_i = mid - 1;
+        // phase 2: gather candidates, 4 rounds of 64 per pass (loads of all 4 issued together),
+        // pre-test against the sub-boxes (small tiles: against their particles) and append the
+        // survivors to the batch in slot order
+        for (int q0 = 0; q0 < Tc; q0 += 256) {
+          double4 pbu[4];
+          int32_t bu[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int slot = q0 + 64 * u + lane;
+            pbu[u] = make_double4(0.0, 0.0, 0.0, 0.0);
+            bu[u] = -1;
+            if (slot < Tc) {
+              int lo_i = 0, hi_i = 63;   // last cell with c_o <= slot
+              while (lo_i < hi_i) {
+                const int mid = (lo_i + hi_i + 1) >> 1;
+                if (c_o[mid] <= slot) lo_i = mid;
+                else hi_i = mid - 1;
+              }
+              const int32_t sp = c_s[lo_i] + (slot - c_o[lo_i]);
+              bu[u] = (int32_t)B.perm[sp];
+              pbu[u] = B.pos_sorted[sp];
             }
-            const int32_t sp = c_s[lo_i] + (slot - c_o[lo_i]);
-            b = (int32_t)B.perm[sp];
-            pb = B.pos4[b];
-            const double ex = fmax(0.0, fabs(min_image(pb.x - cen[0], periodic, box)) - hw[0]);
-            const double ey = fmax(0.0, fabs(min_image(pb.y - cen[1], periodic, box)) - hw[1]);
-            const double ez = fmax(0.0, fabs(min_image(pb.z - cen[2], periodic, box)) - hw[2]);
-            const double Rb = (hmx + pb.w) * s1 * (1.0 + 1e-9);
-            pass = ex * ex + ey * ey + ez * ez < Rb * Rb;
           }
-          const unsigned long long m = __ballot(pass);
-          if (pass) {
-            const int k = pend + __popcll(m & lt);
-            cb[k] = pb;
-            cbi[k] = b;
-          }
-          pend += __popcll(m);
-          __syncthreads();
-          if (pend >= 64) {   // phase 3 on a full batch
-            run_batch(B, T, cb, cbi, 64, periodic, box, s1);
-            const int rest = pend - 64;
-            double4 mv = make_double4(0.0, 0.0, 0.0, 0.0);
-            int32_t mi = 0;
-            if (lane < rest) { mv = cb[64 + lane]; mi = cbi[64 + lane]; }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if (q0 + 64 * u >= Tc) break;
+            const double4 pb = pbu[u];
+            bool pass = false;
+            if (bu[u] >= 0) {
+              if (small) {
+                for (int k = 0; k < tcnt; ++k) {
+                  const double4 q = tp[k];
+                  pass = pass || candidate_test(min_image(q.x - pb.x, (int)PER, box), min_image(q.y - pb.y, (int)PER, box),
+                                                min_image(q.z - pb.z, (int)PER, box), q.w, pb.w, s1);
+                }
+              } else {
+#pragma unroll 1
+                for (int gi = 0; gi < 8; ++gi) {
+                  const double ex = fmax(0.0, fabs(min_image(pb.x - sub[gi][0], (int)PER, box)) - sub[gi][3]);
+                  const double ey = fmax(0.0, fabs(min_image(pb.y - sub[gi][1], (int)PER, box)) - sub[gi][4]);
+                  const double ez = fmax(0.0, fabs(min_image(pb.z - sub[gi][2], (int)PER, box)) - sub[gi][5]);
+                  const double Rb = (sub[gi][6] + pb.w) * s1 * (1.0 + 1e-9);
+                  pass = pass || (ex * ex + ey * ey + ez * ez < Rb * Rb && sub[gi][6] > 0.0);
+                }
+              }
+            }
+            const unsigned long long m = __ballot(pass);
+            if (pass) {
+              const int k = pend + __popcll(m & lt);
+              cb[k] = pb;
+              cbi[k] = bu[u];
+            }
+            pend += __popcll(m);
             __syncthreads();
-            if (lane < rest) { cb[lane] = mv; cbi[lane] = mi; }
-            pend = rest;
-            __syncthreads();
+            if (pend >= 64) {   // phase 3 on a full batch
+              run_batch<64, PER>(B, T, cb, cbi, 64, box, s1);
+              const int rest = pend - 64;
+              double4 mv = make_double4(0.0, 0.0, 0.0, 0.0);
+              int32_t mi = 0;
+              if (lane < rest) { mv = cb[64 + lane]; mi = cbi[64 + lane]; }
+              __syncthreads();
+              if (lane < rest) { cb[lane] = mv; cbi[lane] = mi; }
+              pend = rest;
+              __syncthreads();
+            }
           }
         }
       }
     }
-    if (pend > 0) run_batch(B, T, cb, cbi, pend, periodic, box, s1);
+    if (pend > 0) run_batch<0, PER>(B, T, cb, cbi, pend, box, s1);
     __syncthreads();
-    if (T.valid) B.count[p] = T.stored;
+    if (T.valid && (T.cnt & 7) && T.cnt <= B.cap) store_group(B, T, T.cnt >> 3);
+    if (T.valid) B.count[p] = T.cnt < B.cap ? T.cnt : B.cap;
     if (lane == 0) B.tile_usize[t] = T.usize < T.ucap ? T.usize : T.ucap;
     if (T.usize > T.ucap || T.cnt > B.cap) latch_error(B.status, SPH_E_NGB_CAPACITY, (int)(T.valid ? T.a : -1));
   }
@@ -640,31 +860,48 @@ sph_status sph_rebin(sph_ctx* c, sph_state* st) {
     if ((e = permute_array(c, st->star, n))) return e;
     hipLaunchKernelGGL(k_pack_pos, dim3(nb), dim3(kB), 0, s, st->x, st->y, st->z, st->h,
                        (const int32_t*)nullptr, (const StarInfo*)nullptr, n, c->pos4, (float4*)nullptr);
-    // tile table for this order
-    uint32_t* flag = reinterpret_cast<uint32_t*>(c->tmp);
-    hipLaunchKernelGGL(k_tile_flags, dim3(nb), dim3(kB), 0, s, c->keys, c->pos4, n, c->grid,
-                       c->p.tile_cut > 0.0 ? c->p.tile_cut : 6.0, flag);
-    uint32_t* idx = flag + c->capw;
-    if ((e = sph_scan_u32(c, flag, idx, n, &c->grid->ntiles))) return e;
-    hipLaunchKernelGGL(k_tile_fill, dim3(nb), dim3(kB), 0, s, flag, idx, n, c->tile_start);
-    hipLaunchKernelGGL(k_tile_len, dim3(grid_for(c->cap_tiles, kB)), dim3(kB), 0, s, c->grid, n, c->cap_tiles,
-                       c->tile_start, c->tile_cnt, c->cap_s, c->ucap, c->tile_uoff);
-    if ((e = sph_scan_u32(c, c->tile_uoff, c->tile_uoff, c->cap_tiles, &c->grid->upool_used))) return e;
-    if ((e = ensure_pool(c))) return e;
   }
+  // tile starts along the Morton order (the keys are overwritten by the cell sort below)
+  uint32_t* flag = reinterpret_cast<uint32_t*>(c->tmp);
+  uint32_t* idx = flag + c->capw;
+  hipLaunchKernelGGL(k_tile_flags, dim3(nb), dim3(kB), 0, s, c->keys, c->pos4, n, c->grid,
+                     c->p.tile_cut > 0.0 ? c->p.tile_cut : 6.0, flag);
   hipLaunchKernelGGL(k_level_hmax, dim3(nred), dim3(kB), 0, s, c->pos4, n, c->grid);
   hipLaunchKernelGGL(k_grid_setup2, dim3(1), dim3(1), 0, s, c->grid, c->p.cell_div > 0 ? c->p.cell_div : 2,
                      c->max_cells, c->status);
   hipLaunchKernelGGL(k_keys, dim3(nb), dim3(kB), 0, s, c->pos4, n, c->grid, c->keys, c->vals);
   if ((e = sph_sort_pairs(c, c->keys, c->vals, n))) return e;
-  hipLaunchKernelGGL(k_cell_ranges, dim3(nb), dim3(kB), 0, s, c->keys, n, c->cell_start, c->cell_end);
+  hipLaunchKernelGGL(k_cells_clear, dim3(2048), dim3(kB), 0, s, c->cell_se, c->grid);
+  hipLaunchKernelGGL(k_cell_ranges, dim3(nb), dim3(kB), 0, s, c->keys, n, c->cell_se);
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gather<double4>), dim3(nb), dim3(kB), 0, s, c->pos4, c->vals, n, c->pos_sorted);
+  // tile table: Morton cuts, then tiles whose candidate cells hold many particles are split
+  const bool per = c->p.periodic != 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    if ((e = sph_scan_u32(c, flag, idx, n, &c->grid->ntiles))) return e;
+    hipLaunchKernelGGL(k_tile_fill, dim3(nb), dim3(kB), 0, s, flag, idx, n, c->tile_start);
+    hipLaunchKernelGGL(k_tile_len, dim3(grid_for(c->cap_tiles, kB)), dim3(kB), 0, s, c->grid, n, c->cap_tiles,
+                       c->tile_start, c->tile_cnt, c->cap_s, c->ucap, c->tile_uoff);
+    if (pass == 1) break;
+    if (per)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_tile_cost<true>), dim3(tile_grid(c->cap_tiles)), dim3(64), 0, s, c->pos4,
+                         c->grid, c->tile_start, c->tile_cnt, c->cell_se, c->tile_usize);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_tile_cost<false>), dim3(tile_grid(c->cap_tiles)), dim3(64), 0, s, c->pos4,
+                         c->grid, c->tile_start, c->tile_cnt, c->cell_se, c->tile_usize);
+    hipLaunchKernelGGL(k_tile_split, dim3(nb), dim3(kB), 0, s, flag, idx, n, c->tile_start, c->tile_usize);
+  }
+  if ((e = sph_scan_u32(c, c->tile_uoff, c->tile_uoff, c->cap_tiles, &c->grid->upool_used))) return e;
+  if ((e = ensure_pool(c))) return e;
   BuildArgs B;
-  B.pos4 = c->pos4; B.n = n; B.grid = c->grid; B.skeys = c->keys; B.perm = c->vals;
-  B.cstart = c->cell_start; B.cend = c->cell_end; B.capw = c->capw; B.cap = c->cap_s; B.ucap = c->ucap;
+  B.pos4 = c->pos4; B.n = n; B.grid = c->grid; B.perm = c->vals; B.pos_sorted = c->pos_sorted;
+  B.cell_se = c->cell_se; B.capw = c->capw; B.cap = c->cap_s; B.ucap = c->ucap;
   B.tile_start = c->tile_start; B.tile_cnt = c->tile_cnt; B.tile_uoff = c->tile_uoff; B.upool = c->upool;
   B.tile_u = c->tile_u; B.tile_usize = c->tile_usize; B.nbr16 = c->nbr16s; B.count = c->nbr_count_s;
   B.status = c->status;
-  hipLaunchKernelGGL(k_build_tiles, dim3(tile_grid(c->cap_tiles)), dim3(64), 0, s, B);
+  if (per)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_build_tiles<true>), dim3(tile_grid(c->cap_tiles)), dim3(64), 0, s, B);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_build_tiles<false>), dim3(tile_grid(c->cap_tiles)), dim3(64), 0, s, B);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(c->pos_build, c->pos4, sizeof(double4) * n, hipMemcpyDeviceToDevice, s));
   return launch_pack(c, st);

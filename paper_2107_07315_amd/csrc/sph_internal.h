@@ -19,6 +19,7 @@ struct GridInfo {
   unsigned long long enc_lo[3], enc_hi[3];   // order-preserving encodings for atomics
   unsigned long long enc_hmin, enc_hmax;
   unsigned long long hlev_bits[SPH_MAX_LEV]; // max h per level (positive-double bits)
+  unsigned long long lev_lo[SPH_MAX_LEV][3], lev_hi[SPH_MAX_LEV][3];  // per-level bounding boxes (encoded)
   double lo[3];
   double hmin, hmax;
   double hlev[SPH_MAX_LEV];
@@ -269,8 +270,9 @@ struct sph_ctx {
   // grid and sort
   GridInfo* grid;       // device
   uint32_t *keys, *vals;  // cell-sorted keys and permutation (sorted position -> particle index)
-  int32_t *cell_start, *cell_end;
+  int2* cell_se;        // per cell [start, end) in the cell-sorted order; cleared at every build
   int64_t max_cells;
+  double4* pos_sorted;  // x, y, z, h in the cell-sorted order (candidate gathers of the build)
   SortScratch sort;
   // tile neighbour lists: tile t = particles [tile_start[t], tile_start[t] + tile_cnt[t]) of the
   // array order (at most 64; the array is kept along the global Morton curve); U_t = tile_u +
