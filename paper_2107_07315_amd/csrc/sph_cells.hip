@@ -584,7 +584,9 @@ __global__ __launch_bounds__(64) void k_tile_cost(const double4* __restrict__ po
   const GridInfo& g = *gp;
   const double s1 = 1.0 + g.skin;
   const int64_t ntiles = g.ntiles;
-  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  for (int64_t k_ = blockIdx.x / SPH_XCD, chunk_ = xcd_chunk(ntiles); k_ < chunk_; k_ += gridDim.x / SPH_XCD) {
+    const int64_t t = (int64_t)(blockIdx.x % SPH_XCD) * chunk_ + k_;
+    if (t >= ntiles) break;
     const bool valid = lane < tile_cnt[t];
     const double4 pa = valid ? pos4[tile_start[t] + lane] : make_double4(0.0, 0.0, 0.0, 0.0);
     TileGeom G;
@@ -646,7 +648,9 @@ __global__ __launch_bounds__(64) void k_build_tiles(BuildArgs B) {
   const double box = g.box;
   const double s1 = 1.0 + g.skin;
   const int64_t ntiles = g.ntiles;
-  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  for (int64_t k_ = blockIdx.x / SPH_XCD, chunk_ = xcd_chunk(ntiles); k_ < chunk_; k_ += gridDim.x / SPH_XCD) {
+    const int64_t t = (int64_t)(blockIdx.x % SPH_XCD) * chunk_ + k_;
+    if (t >= ntiles) break;
     const int32_t tcnt = B.tile_cnt[t];
     const int64_t p = (int64_t)B.tile_start[t] + lane;
     TileState T;

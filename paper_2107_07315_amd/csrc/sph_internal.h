@@ -124,6 +124,14 @@ __device__ __forceinline__ bool skin_exceeded(double dx, double dy, double dz, d
   return !(d + dh <= s * b.w * (1.0 - 1e-9));
 }
 
+// ---- XCD-aware tile schedule ------------------------------------------------------------------
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip (block b runs on XCD b % 8),
+// each with its own L2.  Tile kernels give each XCD a contiguous range of tiles, so the
+// neighbour records that consecutive (spatially adjacent) tiles share stay in that XCD's L2.
+// Launch grids are multiples of SPH_XCD.
+#define SPH_XCD 8
+__device__ __forceinline__ int64_t xcd_chunk(int64_t ntiles) { return (ntiles + SPH_XCD - 1) / SPH_XCD; }
+
 // ---- fast reciprocal and square root -----------------------------------------------------------
 // FP64: hardware rcp/rsq estimates refined by Newton steps (a few ulp, far inside the parity
 // tolerance; the neighbour decision never uses them).  FP32: single hardware instructions.

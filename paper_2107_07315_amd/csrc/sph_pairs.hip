@@ -239,7 +239,9 @@ __global__ __launch_bounds__(64) void k_density(PassArgs A, const double4* __res
   __shared__ double4 sp[CH];
   const double box = A.p.box, half = 0.5 * box;
   const int64_t ntl = num_tiles(A);
-  for (int64_t tile = blockIdx.x; tile < ntl; tile += gridDim.x) {
+  for (int64_t k_ = blockIdx.x / SPH_XCD, chunk_ = xcd_chunk(ntl); k_ < chunk_; k_ += gridDim.x / SPH_XCD) {
+    const int64_t tile = (int64_t)(blockIdx.x % SPH_XCD) * chunk_ + k_;
+    if (tile >= ntl) break;
   TileWalk tw;
   tw.init(A, tile, A.nbr16s, A.cnt_s);
   const int64_t a = tw.a;
@@ -353,7 +355,9 @@ __global__ __launch_bounds__(64) void k_stress(PassArgs A, const typename Rec<R>
   __shared__ V4 sv[CH];
   const R box = (R)A.p.box, half = (R)0.5 * box;
   const int64_t ntl = num_tiles(A);
-  for (int64_t tile = blockIdx.x; tile < ntl; tile += gridDim.x) {
+  for (int64_t k_ = blockIdx.x / SPH_XCD, chunk_ = xcd_chunk(ntl); k_ < chunk_; k_ += gridDim.x / SPH_XCD) {
+    const int64_t tile = (int64_t)(blockIdx.x % SPH_XCD) * chunk_ + k_;
+    if (tile >= ntl) break;
   TileWalk tw;
   tw.init(A, tile, A.nbr16, A.cnt);
   const int64_t a = tw.a;
@@ -471,7 +475,9 @@ __global__ __launch_bounds__(64) void k_forces(PassArgs A, const typename Rec<R>
   __shared__ A2 sa2[CH];
   const R box = (R)A.p.box, half = (R)0.5 * box;
   const int64_t ntl = num_tiles(A);
-  for (int64_t tile = blockIdx.x; tile < ntl; tile += gridDim.x) {
+  for (int64_t k_ = blockIdx.x / SPH_XCD, chunk_ = xcd_chunk(ntl); k_ < chunk_; k_ += gridDim.x / SPH_XCD) {
+    const int64_t tile = (int64_t)(blockIdx.x % SPH_XCD) * chunk_ + k_;
+    if (tile >= ntl) break;
   TileWalk tw;
   tw.init(A, tile, A.nbr16, A.cnt);
   const int64_t a = tw.a;
