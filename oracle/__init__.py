@@ -238,3 +238,35 @@ def yield_scale(orc: Oracle, S6n: np.ndarray, Y0: np.ndarray):
     Y = np.ascontiguousarray(Y0, dtype=np.float64)
     lib().orc_yield(ctypes.byref(orc.p), S.shape[1], _ptr(S), _ptr(Y))
     return S
+
+
+# ---- EoS surrogate network ---------------------------------------------------------------------
+MLP_NPARAM = 8642
+
+
+def _mlp_lib():
+    L = lib()
+    L.orc_mlp_forward.argtypes = [_dp, ctypes.c_int64, _dp, _dp]
+    L.orc_mlp_forward.restype = None
+    L.orc_mlp_loss_grad.argtypes = [_dp, ctypes.c_int64, _dp, _dp, _dp]
+    L.orc_mlp_loss_grad.restype = ctypes.c_double
+    return L
+
+
+def mlp_forward(w, x):
+    """Network outputs for normalised inputs x[n, 2] with flat FP64 parameters w."""
+    w = np.ascontiguousarray(w, np.float64)
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.zeros_like(x)
+    _mlp_lib().orc_mlp_forward(_ptr(w), x.shape[0], _ptr(x), _ptr(y))
+    return y
+
+
+def mlp_loss_grad(w, x, t):
+    """(loss, dloss/dw) of the mean squared error over samples x[n, 2], targets t[n, 2]."""
+    w = np.ascontiguousarray(w, np.float64)
+    x = np.ascontiguousarray(x, np.float64)
+    t = np.ascontiguousarray(t, np.float64)
+    g = np.zeros(MLP_NPARAM)
+    loss = _mlp_lib().orc_mlp_loss_grad(_ptr(w), x.shape[0], _ptr(x), _ptr(t), _ptr(g))
+    return loss, g

@@ -749,3 +749,115 @@ int orc_step(const orc_params* p, orc_state* st, double dt, int32_t nsteps, int3
   free(vh);
   return e;
 }
+
+/* ------------------------------------------------------------------------------------ */
+/* EoS surrogate network: forward pass and backpropagation in FP64                       */
+
+#define MH ORC_MLP_H
+/* offsets of the parameter blocks in the flat array */
+#define OW1 0
+#define OB1 (OW1 + MH * 2)
+#define OW2 (OB1 + MH)
+#define OB2 (OW2 + MH * MH)
+#define OW3 (OB2 + MH)
+#define OB3 (OW3 + MH * MH)
+#define OW4 (OB3 + MH)
+#define OB4 (OW4 + 2 * MH)
+
+static double silu(double z) { return z / (1.0 + exp(-z)); }
+static double dsilu(double z) {
+  double s = 1.0 / (1.0 + exp(-z));
+  return s * (1.0 + z * (1.0 - s));
+}
+
+/* one sample: pre-activations z1..z3 and the output y */
+static void mlp_sample(const double* w, const double* x, double* z1, double* z2, double* z3, double* y) {
+  double h1[MH], h2[MH], h3[MH];
+  for (int f = 0; f < MH; ++f) {
+    z1[f] = w[OW1 + 2 * f] * x[0] + w[OW1 + 2 * f + 1] * x[1] + w[OB1 + f];
+    h1[f] = silu(z1[f]);
+  }
+  for (int f = 0; f < MH; ++f) {
+    double a = w[OB2 + f];
+    for (int g = 0; g < MH; ++g) a += w[OW2 + MH * f + g] * h1[g];
+    z2[f] = a;
+    h2[f] = silu(a);
+  }
+  for (int f = 0; f < MH; ++f) {
+    double a = w[OB3 + f];
+    for (int g = 0; g < MH; ++g) a += w[OW3 + MH * f + g] * h2[g];
+    z3[f] = a;
+    h3[f] = silu(a);
+  }
+  for (int o = 0; o < 2; ++o) {
+    double a = w[OB4 + o];
+    for (int g = 0; g < MH; ++g) a += w[OW4 + MH * o + g] * h3[g];
+    y[o] = a;
+  }
+}
+
+void orc_mlp_forward(const double* w, int64_t n, const double* x, double* y) {
+#pragma omp parallel for schedule(static)
+  for (int64_t s = 0; s < n; ++s) {
+    double z1[MH], z2[MH], z3[MH];
+    mlp_sample(w, x + 2 * s, z1, z2, z3, y + 2 * s);
+  }
+}
+
+double orc_mlp_loss_grad(const double* w, int64_t n, const double* x, const double* t, double* grad) {
+  memset(grad, 0, sizeof(double) * ORC_MLP_NPARAM);
+  double loss = 0.0;
+  const double inv_n = n > 0 ? 1.0 / (double)n : 0.0;
+  for (int64_t s = 0; s < n; ++s) {   /* serial: a fixed summation order */
+    const double* xs = x + 2 * s;
+    double z1[MH], z2[MH], z3[MH], y[2];
+    mlp_sample(w, xs, z1, z2, z3, y);
+    double dy[2];
+    for (int o = 0; o < 2; ++o) {
+      const double e = y[o] - t[2 * s + o];
+      loss += 0.5 * e * e * inv_n;
+      dy[o] = e * inv_n;            /* dL/dy */
+    }
+    /* output layer */
+    double g3[MH];
+    for (int f = 0; f < MH; ++f) {
+      const double h3 = silu(z3[f]);
+      double dh = 0.0;
+      for (int o = 0; o < 2; ++o) {
+        grad[OW4 + MH * o + f] += dy[o] * h3;
+        dh += w[OW4 + MH * o + f] * dy[o];
+      }
+      g3[f] = dh * dsilu(z3[f]);
+    }
+    for (int o = 0; o < 2; ++o) grad[OB4 + o] += dy[o];
+    /* layer 3 */
+    double g2[MH];
+    for (int g = 0; g < MH; ++g) {
+      double dh = 0.0;
+      for (int f = 0; f < MH; ++f) dh += w[OW3 + MH * f + g] * g3[f];
+      g2[g] = dh * dsilu(z2[g]);
+    }
+    for (int f = 0; f < MH; ++f) {
+      grad[OB3 + f] += g3[f];
+      for (int g = 0; g < MH; ++g) grad[OW3 + MH * f + g] += g3[f] * silu(z2[g]);
+    }
+    /* layer 2 */
+    double g1[MH];
+    for (int g = 0; g < MH; ++g) {
+      double dh = 0.0;
+      for (int f = 0; f < MH; ++f) dh += w[OW2 + MH * f + g] * g2[f];
+      g1[g] = dh * dsilu(z1[g]);
+    }
+    for (int f = 0; f < MH; ++f) {
+      grad[OB2 + f] += g2[f];
+      for (int g = 0; g < MH; ++g) grad[OW2 + MH * f + g] += g2[f] * silu(z1[g]);
+    }
+    /* layer 1 */
+    for (int f = 0; f < MH; ++f) {
+      grad[OB1 + f] += g1[f];
+      grad[OW1 + 2 * f] += g1[f] * xs[0];
+      grad[OW1 + 2 * f + 1] += g1[f] * xs[1];
+    }
+  }
+  return loss;
+}

@@ -117,4 +117,21 @@ int orc_evaluate(const orc_params* p, orc_state* st, int32_t ngb_mode);
 #ifdef __cplusplus
 }
 #endif
+/* ---- EoS surrogate network ------------------------------------------------------------------
+ * A multilayer perceptron 2 -> 64 -> 64 -> 64 -> 2 with SiLU activations, silu(z) = z/(1+e^-z),
+ * mapping normalised (ln rho, ln u) to normalised (ln P, ln c_s^2).  Parameters are a flat array
+ * of ORC_MLP_NPARAM doubles in the order
+ *   W1[64][2], b1[64], W2[64][64], b2[64], W3[64][64], b3[64], W4[2][64], b4[2]
+ * with W[out][in] row-major.  The training loss over n samples is
+ *   L = 1/(2n) sum_s sum_o (y_so - t_so)^2.
+ * Parity: pinned by central finite differences of L and by closed-form special cases. */
+#define ORC_MLP_H 64
+#define ORC_MLP_NPARAM 8642
+
+/* y[2n] = network(x[2n]) (sample-major pairs). */
+void orc_mlp_forward(const double* w, int64_t n, const double* x, double* y);
+
+/* Returns L and writes dL/dw to grad[ORC_MLP_NPARAM] (backpropagation, summed over samples). */
+double orc_mlp_loss_grad(const double* w, int64_t n, const double* x, const double* t, double* grad);
+
 #endif
