@@ -189,6 +189,53 @@ sph_status sph_export_neighbours(sph_ctx* ctx, int64_t* offsets, int32_t* ids, i
 /* Statistics of the current lists (see sph_list_stats).  Waits. */
 sph_status sph_neighbour_stats(sph_ctx* ctx, sph_list_stats* out);
 
+/* ---- EoS surrogate network (extension of the tabulated EoS) ---------------------------------
+ * The setup section names tabulated equations of state; this extension fits a network
+ * 2 -> 64 -> 64 -> 64 -> 2 with SiLU activations to the context's EoS table, mapping normalised
+ * (ln rho, ln u) to normalised (ln P, ln c_s^2).  Forward passes use BF16 weights (rounded from
+ * FP32 master weights) with FP32 accumulation; training runs Adam on the master weights with a
+ * cosine learning-rate schedule, on the GPU.  With eos = SPH_EOS_MLP the density pass uses the
+ * network in every table cell the trust mask accepts and table interpolation elsewhere (and
+ * everywhere while no network is loaded).
+ * Parameters are SPH_MLP_NPARAM floats: W1[64][2], b1[64], W2[64][64], b2[64], W3[64][64],
+ * b3[64], W4[2][64], b4[2] (W[out][in], row-major).  Inputs are normalised to [-1, 1] over the
+ * table's box, outputs by the table's value range (sph_mlp_get_norm).  Every call needs the
+ * EoS table in the context's parameters and waits for the stream. */
+#define SPH_MLP_NPARAM 8642
+
+/* Load FP32 master weights (host array); resets the optimiser and drops the trust mask. */
+sph_status sph_mlp_set_params(sph_ctx* ctx, const float* params);
+
+/* Copy the weights to the host: the FP32 masters, or (rounded != 0) the BF16 values the
+ * kernels use, as floats.  SPH_E_ARG before sph_mlp_set_params. */
+sph_status sph_mlp_get_params(sph_ctx* ctx, float* params, int32_t rounded);
+
+/* Normalisation {in_lo[2], in_scale[2], out_centre[2], out_scale[2]}: x = (v - lo) scale - 1,
+ * v = y scale + centre. */
+sph_status sph_mlp_get_norm(sph_ctx* ctx, float* norm8);
+
+/* Train on samples[n][2] = (ln rho, ln u) (device, FP64) with table-interpolated targets; the
+ * last n_holdout samples are held out.  epochs passes of (n - n_holdout) / batch Adam steps,
+ * batch a multiple of 64 and at most 8192, peak learning rate lr.  history (host, may be NULL)
+ * receives per epoch {last training-batch loss, holdout loss} (normalised units, loss =
+ * 1/(2n) sum of squared output errors).  Drops the trust mask. */
+sph_status sph_mlp_train(sph_ctx* ctx, const double* samples, int64_t n, int64_t n_holdout, int32_t epochs,
+                         int32_t batch, float lr, float* history);
+
+/* Gradient of the loss over x[n][2], t[n][2] (device, normalised FP32; n a multiple of 64, at
+ * most 8192) with the current BF16 weights, summed in a fixed order: grad[SPH_MLP_NPARAM] and
+ * loss on the host.  Changes no weight. */
+sph_status sph_mlp_grad(sph_ctx* ctx, const float* x, const float* t, int64_t n, float* grad, double* loss);
+
+/* Network outputs ln P, ln c_s^2 at device arrays (ln rho, ln u), n entries; stream-ordered. */
+sph_status sph_mlp_eval(sph_ctx* ctx, const double* lnrho, const double* lnu, int64_t n, double* lnP,
+                        double* lncs2);
+
+/* Build the trust mask: a table cell is trusted when at its four nodes and its centre the
+ * network's P and c_s^2 are within relative tolerance tol of the table.  Returns the number of
+ * trusted cells of (nr - 1)(nu - 1). */
+sph_status sph_mlp_build_trust_mask(sph_ctx* ctx, double tol, int64_t* trusted_cells);
+
 /* Human-readable name of a status code (static string). */
 const char* sph_status_string(sph_status s);
 

@@ -98,6 +98,7 @@ void sph_destroy(sph_ctx* c) {
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (c->drift_host) (void)hipHostFree(c->drift_host);
+  mlp_free(c);
   for (auto& t : c->timers)
     for (hipEvent_t e : t.ev) (void)hipEventDestroy(e);
   c->~sph_ctx();

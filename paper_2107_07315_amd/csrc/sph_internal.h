@@ -182,6 +182,32 @@ __device__ __forceinline__ R wendland_self(int kernel, R h) {
   return kernel == SPH_WC4 ? (R)(495.0 / (256.0 * SPH_PI)) * ih3 : (R)(21.0 / (16.0 * SPH_PI)) * ih3;
 }
 
+// ---- tabulated equation of state -------------------------------------------------------------
+// Bilinear interpolation of ln P and ln c_s^2 on the uniform (ln rho, ln u) grid.  Returns non-zero
+// outside the table or on non-finite nodes; `cell` = i * (nu - 1) + j of the enclosing cell.
+__device__ __forceinline__ bool table_bilinear(const double* __restrict__ T, int64_t o, int nu, double a, double b,
+                                               double& v) {
+  const double f00 = T[o], f01 = T[o + 1], f10 = T[o + nu], f11 = T[o + nu + 1];
+  if (!isfinite(f00) || !isfinite(f01) || !isfinite(f10) || !isfinite(f11)) return false;
+  v = (1.0 - a) * ((1.0 - b) * f00 + b * f01) + a * ((1.0 - b) * f10 + b * f11);
+  return true;
+}
+__device__ __forceinline__ int eos_table_ln(const sph_params& p, double lnr, double lnu, double& lp, double& lc,
+                                            int64_t& cell) {
+  const double fr = (lnr - p.tab_lnr0) / p.tab_dlnr;
+  const double fu = (lnu - p.tab_lnu0) / p.tab_dlnu;
+  if (!(fr >= 0.0) || !(fu >= 0.0) || fr > (double)(p.tab_nr - 1) || fu > (double)(p.tab_nu - 1)) return 1;
+  int i = (int)floor(fr), j = (int)floor(fu);
+  i = i > p.tab_nr - 2 ? p.tab_nr - 2 : i;
+  j = j > p.tab_nu - 2 ? p.tab_nu - 2 : j;
+  const double a = fr - (double)i, b = fu - (double)j;
+  const int64_t o = (int64_t)i * p.tab_nu + j;
+  cell = (int64_t)i * (p.tab_nu - 1) + j;
+  if (!table_bilinear(p.tab_lnP, o, p.tab_nu, a, b, lp) || !table_bilinear(p.tab_lncs2, o, p.tab_nu, a, b, lc))
+    return 1;
+  return 0;
+}
+
 // ---- static isotropic background ------------------------------------------------------------
 struct Metric {
   double alpha, dalpha, psi, dpsi, n[3];
@@ -326,8 +352,8 @@ struct sph_ctx {
   // timing
   int32_t timing;
   StageTimer timers[5];
-  // MLP surrogate (optional)
-  void* mlp;
+  // EoS surrogate network (allocated on first use)
+  struct MlpState* mlp;
 };
 
 // ---- host launchers (one per kernel file) ------------------------------------------------------
@@ -342,6 +368,9 @@ sph_status launch_kick_final(sph_ctx* c, sph_state* st, double dt);
 sph_status launch_pack(sph_ctx* c, sph_state* st);
 sph_status sph_count_stats(sph_ctx* c, sph_list_stats* out);
 sph_status sph_scan_u32(sph_ctx* c, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total);
+struct MlpView;
+bool mlp_view(const sph_ctx* c, MlpView* v);   // false if no trained network is loaded
+void mlp_free(sph_ctx* c);
 
 enum { TIMER_CELLS = 0, TIMER_DENSITY = 1, TIMER_STRESS = 2, TIMER_FORCES = 3, TIMER_KDK = 4 };
 void timer_begin(sph_ctx* c, int which);

@@ -1,0 +1,143 @@
+// EoS surrogate network: 2 -> 64 -> 64 -> 64 -> 2 with SiLU activations, mapping normalised
+// (ln rho, ln u) to normalised (ln P, ln c_s^2).  Weights are BF16 (the forward pass uses the
+// BF16-rounded values of FP32 master weights), products accumulate in FP32; the two 64x64 layers
+// run on the matrix cores (v_mfma_f32_16x16x16_bf16), the 2-wide input and output layers and the
+// activations on the vector ALUs.
+//
+// MFMA operand layouts (16x16x16, wave64; lane l, q = l / 16, r = l % 16, j = 0..3):
+//   A (M x K):  lane holds A[r][4q + j]      B (K x N):  lane holds B[4q + j][r]
+//   C (M x N):  lane holds C[4q + j][r]
+// A layer is computed transposed, H_next^T (features x samples) = W (out x in) * H^T (in x
+// samples): the weights are the A operand and a C tile, after bias and activation, is exactly
+// the B operand of the next layer, so activations never leave the registers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define MLP_H 64
+#define MLP_NPARAM 8642
+// offsets of the parameter blocks in the flat array (W[out][in] row-major)
+#define MLP_OW1 0
+#define MLP_OB1 128
+#define MLP_OW2 192
+#define MLP_OB2 4288
+#define MLP_OW3 4352
+#define MLP_OB3 8448
+#define MLP_OW4 8512
+#define MLP_OB4 8640
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// x_n = (v - in_lo) * in_sc - 1 for v = ln rho, ln u;  v = y_n * out_sc + out_c for ln P, ln c_s^2
+struct MlpNorm {
+  float in_lo[2], in_sc[2], out_c[2], out_sc[2];
+};
+
+// Read-only view of the network for the kernels.
+struct MlpView {
+  const float* wr;     // BF16-rounded parameters as FP32 (flat layout)
+  const uint2* wa2;    // W2 packed as MFMA A operands: [(mt * 4 + kk) * 64 + lane] = 4 BF16
+  const uint2* wa3;    // W3 likewise
+  const uint2* wt2;    // W2^T packed as A operands (backward pass)
+  const uint2* wt3;
+  const uint8_t* trust;  // per EoS-table cell: 1 where the network is within tolerance, may be null
+  MlpNorm norm;
+};
+
+__device__ __forceinline__ uint32_t bf16_bits(float f) {   // round to nearest even
+  const uint32_t u = __float_as_uint(f);
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ float bf16_round(float f) { return __uint_as_float(bf16_bits(f) << 16); }
+__device__ __forceinline__ bf16x4 pack_bf16(float a, float b, float c, float d) {
+  bf16x4 v;
+  v[0] = (short)bf16_bits(a);
+  v[1] = (short)bf16_bits(b);
+  v[2] = (short)bf16_bits(c);
+  v[3] = (short)bf16_bits(d);
+  return v;
+}
+__device__ __forceinline__ bf16x4 as_bf16x4(uint2 u) {
+  bf16x4 v;
+  v[0] = (short)(u.x & 0xffffu);
+  v[1] = (short)(u.x >> 16);
+  v[2] = (short)(u.y & 0xffffu);
+  v[3] = (short)(u.y >> 16);
+  return v;
+}
+__device__ __forceinline__ float silu_f(float z) { return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+__device__ __forceinline__ float dsilu_f(float z) {
+  const float s = __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+  return s * (1.0f + z * (1.0f - s));
+}
+__device__ __forceinline__ f32x4 mfma_bf16(bf16x4 a, bf16x4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// Network outputs for the 64 inputs held one per lane (x0, x1 normalised).  Every lane of the
+// wave must call it (matrix instructions); lane l receives the outputs of its own input.
+__device__ __forceinline__ void mlp_wave(const MlpView& M, float x0, float x1, float& y0, float& y1) {
+  const int l = threadIdx.x & 63, q = l >> 4, r = l & 15;
+#pragma unroll 1
+  for (int nt = 0; nt < 4; ++nt) {
+    // The weights are the same for every nt; the empty asm makes the pointers opaque so that
+    // their loads stay inside the loop instead of occupying ~180 registers across it.
+    const float* w = M.wr;
+    const uint2* wa2 = M.wa2;
+    const uint2* wa3 = M.wa3;
+    asm volatile("" : "+s"(w), "+s"(wa2), "+s"(wa3));
+    const int pp = 16 * nt + r;   // the input this lane's B-operand column belongs to
+    const float a0 = __shfl(x0, pp, 64), a1 = __shfl(x1, pp, 64);
+    bf16x4 h1[4];
+    // scheduling barriers between the stages bound the weight loads in flight (registers)
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      __builtin_amdgcn_sched_barrier(0);
+      float h[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int f = 16 * kk + 4 * q + j;
+        h[j] = silu_f(w[MLP_OW1 + 2 * f] * a0 + w[MLP_OW1 + 2 * f + 1] * a1 + w[MLP_OB1 + f]);
+      }
+      h1[kk] = pack_bf16(h[0], h[1], h[2], h[3]);
+    }
+    bf16x4 h2[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      __builtin_amdgcn_sched_barrier(0);
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) acc = mfma_bf16(as_bf16x4(wa2[(mt * 4 + kk) * 64 + l]), h1[kk], acc);
+      float h[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) h[j] = silu_f(acc[j] + w[MLP_OB2 + 16 * mt + 4 * q + j]);
+      h2[mt] = pack_bf16(h[0], h[1], h[2], h[3]);
+    }
+    float p0 = 0.f, p1 = 0.f;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      __builtin_amdgcn_sched_barrier(0);
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) acc = mfma_bf16(as_bf16x4(wa3[(mt * 4 + kk) * 64 + l]), h2[kk], acc);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int f = 16 * mt + 4 * q + j;
+        const float h3 = silu_f(acc[j] + w[MLP_OB3 + f]);
+        p0 += w[MLP_OW4 + f] * h3;
+        p1 += w[MLP_OW4 + MLP_H + f] * h3;
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // the four lanes r, r + 16, r + 32, r + 48 hold the partial sums of input 16 nt + r
+    p0 += __shfl_xor(p0, 16, 64);
+    p0 += __shfl_xor(p0, 32, 64);
+    p1 += __shfl_xor(p1, 16, 64);
+    p1 += __shfl_xor(p1, 32, 64);
+    if (q == nt) {
+      y0 = p0 + w[MLP_OB4];
+      y1 = p1 + w[MLP_OB4 + 1];
+    }
+  }
+}

@@ -1,0 +1,662 @@
+// EoS surrogate network on the GPU: training (forward and backward passes on the matrix cores,
+// Adam on FP32 master weights), evaluation, and the trust mask that decides, per cell of the EoS
+// table, whether the density pass may use the network instead of table interpolation.
+#include <math.h>
+#include <string.h>
+
+#include <vector>
+
+#include "sph_internal.h"
+#include "sph_mlp.h"
+
+struct MlpState {
+  float* w = nullptr;      // FP32 master parameters
+  float* wr = nullptr;     // BF16-rounded copy
+  float* m = nullptr;      // Adam moments
+  float* v = nullptr;
+  uint2* pack = nullptr;   // wa2, wa3, wt2, wt3: 4 x 1024 entries
+  float* gpart = nullptr;  // per-block gradient partials [kMaxBlocks][MLP_NPARAM]
+  float* lpart = nullptr;  // per-block loss partials
+  float* gsum = nullptr;   // summed gradient (sph_mlp_grad)
+  float* scal = nullptr;   // [0] loss of the last step
+  uint8_t* trust = nullptr;
+  int64_t trust_cells = 0;
+  int64_t step = 0;        // Adam steps taken
+  bool loaded = false;
+  bool norm_set = false;
+  MlpNorm norm;
+};
+
+namespace {
+
+constexpr int kMaxBlocks = 128;   // batch <= 8192 samples
+constexpr int LP = 68;            // padded row of the LDS matrices (8- and 16-byte aligned rows)
+
+__device__ __forceinline__ float wave_sum_f(float v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ bf16x4 lds_b4(const uint16_t* p) {   // 4 consecutive BF16 (8-byte aligned)
+  return as_bf16x4(*reinterpret_cast<const uint2*>(p));
+}
+__device__ __forceinline__ bf16x4 lds_b4_strided(const uint16_t* p, int stride) {
+  bf16x4 v;
+  v[0] = (short)p[0];
+  v[1] = (short)p[stride];
+  v[2] = (short)p[2 * stride];
+  v[3] = (short)p[3 * stride];
+  return v;
+}
+__device__ __forceinline__ void lds_store_b4(uint16_t* p, float a, float b, float c, float d) {
+  *reinterpret_cast<uint2*>(p) = make_uint2(bf16_bits(a) | (bf16_bits(b) << 16), bf16_bits(c) | (bf16_bits(d) << 16));
+}
+
+struct GradArgs {
+  MlpView M;
+  const float* x;    // normalised inputs, 2 per sample
+  const float* t;    // normalised targets
+  int64_t off;       // first sample of the batch; samples wrap modulo n
+  int64_t n;
+  int batch;         // samples in the batch (multiple of 64); block b takes samples [64 b, 64 b + 64)
+  float* gpart;
+  float* lpart;
+};
+
+// Gradient of L = 1/(2 batch) sum_s sum_o (y_so - t_so)^2 over the block's 64 samples (lane =
+// sample), written as this block's partial.  Layers 2 and 3 and their weight gradients and
+// back-propagated activations are 64x64x64 products on the matrix cores; activations are kept
+// in LDS sample-major (row = sample, column = feature).
+__global__ __launch_bounds__(64) void k_mlp_grad(GradArgs G) {
+  __shared__ __align__(16) uint16_t Ht1[64 * LP];
+  __shared__ __align__(16) uint16_t Ht2[64 * LP];
+  __shared__ __align__(16) uint16_t Gt[64 * LP];
+  __shared__ __align__(16) float Zt2[64 * LP];
+  __shared__ __align__(16) float Zt3[64 * LP];
+  __shared__ __align__(16) float G32[64 * LP];
+  __shared__ float xs[64][2], dys[64][2];
+  const int l = threadIdx.x, q = l >> 4, r = l & 15;
+  const MlpView& M = G.M;
+  const float* w = M.wr;
+  const int64_t sg = (G.off + (int64_t)blockIdx.x * 64 + l) % G.n;
+  const float x0 = G.x[2 * sg], x1 = G.x[2 * sg + 1];
+  const float t0 = G.t[2 * sg], t1 = G.t[2 * sg + 1];
+  float* gp = G.gpart + (int64_t)blockIdx.x * MLP_NPARAM;
+  xs[l][0] = x0;
+  xs[l][1] = x1;
+  // ---- forward --------------------------------------------------------------------------------
+  for (int f = 0; f < 64; f += 4) {
+    float h[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      h[j] = silu_f(w[MLP_OW1 + 2 * (f + j)] * x0 + w[MLP_OW1 + 2 * (f + j) + 1] * x1 + w[MLP_OB1 + f + j]);
+    lds_store_b4(&Ht1[l * LP + f], h[0], h[1], h[2], h[3]);
+  }
+  __syncthreads();
+  // hidden layers: C tile (features 16 mt + 4q + j, samples 16 nt + r)
+  for (int layer = 0; layer < 2; ++layer) {
+    const uint2* wa = layer == 0 ? M.wa2 : M.wa3;
+    const int ob = layer == 0 ? MLP_OB2 : MLP_OB3;
+    const uint16_t* Hin = layer == 0 ? Ht1 : Ht2;
+    float* Z = layer == 0 ? Zt2 : Zt3;
+    for (int nt = 0; nt < 4; ++nt) {
+      bf16x4 b[4];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) b[kk] = lds_b4(&Hin[(16 * nt + r) * LP + 16 * kk + 4 * q]);
+      for (int mt = 0; mt < 4; ++mt) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) acc = mfma_bf16(as_bf16x4(wa[(mt * 4 + kk) * 64 + l]), b[kk], acc);
+        float z[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) z[j] = acc[j] + w[ob + 16 * mt + 4 * q + j];
+        *reinterpret_cast<float4*>(&Z[(16 * nt + r) * LP + 16 * mt + 4 * q]) = make_float4(z[0], z[1], z[2], z[3]);
+        if (layer == 0)
+          lds_store_b4(&Ht2[(16 * nt + r) * LP + 16 * mt + 4 * q], silu_f(z[0]), silu_f(z[1]), silu_f(z[2]),
+                       silu_f(z[3]));
+      }
+    }
+    __syncthreads();
+  }
+  // output layer and loss (lane = sample)
+  float y0 = w[MLP_OB4], y1 = w[MLP_OB4 + 1];
+  for (int f = 0; f < 64; ++f) {
+    const float h3 = silu_f(Zt3[l * LP + f]);
+    y0 += w[MLP_OW4 + f] * h3;
+    y1 += w[MLP_OW4 + MLP_H + f] * h3;
+  }
+  const float inv = 1.0f / (float)G.batch;
+  const float e0 = y0 - t0, e1 = y1 - t1;
+  const float loss = 0.5f * (e0 * e0 + e1 * e1) * inv;
+  const float d0 = e0 * inv, d1 = e1 * inv;
+  dys[l][0] = d0;
+  dys[l][1] = d1;
+  // ---- backward -------------------------------------------------------------------------------
+  // g3 = (W4^T dy) * silu'(z3)  (lane = sample)
+  for (int f = 0; f < 64; f += 4) {
+    float g[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      g[j] = (w[MLP_OW4 + f + j] * d0 + w[MLP_OW4 + MLP_H + f + j] * d1) * dsilu_f(Zt3[l * LP + f + j]);
+    *reinterpret_cast<float4*>(&G32[l * LP + f]) = make_float4(g[0], g[1], g[2], g[3]);
+    lds_store_b4(&Gt[l * LP + f], g[0], g[1], g[2], g[3]);
+  }
+  __syncthreads();
+  {  // dW4, db3 (lane = feature), db4
+    const int f = l;
+    float a0 = 0.f, a1 = 0.f, bsum = 0.f;
+    for (int s = 0; s < 64; ++s) {
+      const float h3 = silu_f(Zt3[s * LP + f]);
+      a0 += dys[s][0] * h3;
+      a1 += dys[s][1] * h3;
+      bsum += G32[s * LP + f];
+    }
+    gp[MLP_OW4 + f] = a0;
+    gp[MLP_OW4 + MLP_H + f] = a1;
+    gp[MLP_OB3 + f] = bsum;
+    const float s0 = wave_sum_f(d0), s1 = wave_sum_f(d1);
+    if (l == 0) {
+      gp[MLP_OB4] = s0;
+      gp[MLP_OB4 + 1] = s1;
+    }
+  }
+  // layers 3 and 2: dW = G * H_in^T (K = samples), dH_in = W^T * G (K = out features)
+  for (int layer = 1; layer >= 0; --layer) {
+    const uint16_t* Hin = layer == 1 ? Ht2 : Ht1;
+    const uint2* wt = layer == 1 ? M.wt3 : M.wt2;
+    const int ow = layer == 1 ? MLP_OW3 : MLP_OW2;
+    for (int mt = 0; mt < 4; ++mt)
+      for (int nt = 0; nt < 4; ++nt) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          // A[out 16mt + r][sample 16kk + 4q + j], B[sample 16kk + 4q + j][in 16nt + r]
+          const bf16x4 a = lds_b4_strided(&Gt[(16 * kk + 4 * q) * LP + 16 * mt + r], LP);
+          const bf16x4 b = lds_b4_strided(&Hin[(16 * kk + 4 * q) * LP + 16 * nt + r], LP);
+          acc = mfma_bf16(a, b, acc);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) gp[ow + MLP_H * (16 * mt + 4 * q + j) + 16 * nt + r] = acc[j];
+      }
+    f32x4 dh[4][4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+          acc = mfma_bf16(as_bf16x4(wt[(mt * 4 + kk) * 64 + l]), lds_b4(&Gt[(16 * nt + r) * LP + 16 * kk + 4 * q]), acc);
+        dh[mt][nt] = acc;
+      }
+    __syncthreads();   // the G of this layer is consumed
+    // g_in = dH_in * silu'(z_in): z2 from LDS, z1 recomputed from the inputs
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        const int s = 16 * nt + r, f0 = 16 * mt + 4 * q;
+        float g[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int f = f0 + j;
+          const float z = layer == 1 ? Zt2[s * LP + f]
+                                     : w[MLP_OW1 + 2 * f] * xs[s][0] + w[MLP_OW1 + 2 * f + 1] * xs[s][1] + w[MLP_OB1 + f];
+          g[j] = dh[mt][nt][j] * dsilu_f(z);
+        }
+        *reinterpret_cast<float4*>(&G32[s * LP + f0]) = make_float4(g[0], g[1], g[2], g[3]);
+        lds_store_b4(&Gt[s * LP + f0], g[0], g[1], g[2], g[3]);
+      }
+    __syncthreads();
+    const int f = l;
+    if (layer == 1) {   // db2
+      float bsum = 0.f;
+      for (int s = 0; s < 64; ++s) bsum += G32[s * LP + f];
+      gp[MLP_OB2 + f] = bsum;
+    } else {            // dW1, db1
+      float a0 = 0.f, a1 = 0.f, bsum = 0.f;
+      for (int s = 0; s < 64; ++s) {
+        const float g = G32[s * LP + f];
+        a0 += g * xs[s][0];
+        a1 += g * xs[s][1];
+        bsum += g;
+      }
+      gp[MLP_OW1 + 2 * f] = a0;
+      gp[MLP_OW1 + 2 * f + 1] = a1;
+      gp[MLP_OB1 + f] = bsum;
+    }
+  }
+  const float ls = wave_sum_f(loss);
+  if (l == 0) G.lpart[blockIdx.x] = ls;
+}
+
+// Sums the block partials in block order (deterministic), then optionally one Adam step on the
+// FP32 master weights and the BF16-rounded copy; block 0 also sums the loss.
+__global__ __launch_bounds__(256) void k_mlp_adam(float* w, float* wr, float* m, float* v, const float* gpart,
+                                                  const float* lpart, int nblk, float lr, float bc1, float bc2,
+                                                  float* gsum, float* loss_out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < MLP_NPARAM) {
+    float g = 0.f;
+    for (int b = 0; b < nblk; ++b) g += gpart[(int64_t)b * MLP_NPARAM + p];
+    if (gsum) gsum[p] = g;
+    if (lr > 0.f) {
+      const float mm = 0.9f * m[p] + 0.1f * g;
+      const float vv = 0.999f * v[p] + 0.001f * g * g;
+      m[p] = mm;
+      v[p] = vv;
+      const float wn = w[p] - lr * (mm / bc1) / (sqrtf(vv / bc2) + 1e-8f);
+      w[p] = wn;
+      wr[p] = bf16_round(wn);
+    }
+  }
+  if (p == 0 && loss_out) {
+    float s = 0.f;
+    for (int b = 0; b < nblk; ++b) s += lpart[b];
+    *loss_out = s;
+  }
+}
+
+// MFMA A-operand packs of W2, W3 and their transposes from the rounded weights.
+__global__ __launch_bounds__(256) void k_mlp_pack(const float* wr, uint2* pack) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;   // 4 packs x 16 tiles x 64 lanes
+  if (i >= 4 * 1024) return;
+  const int which = i >> 10, tile = (i >> 6) & 15, l = i & 63;
+  const int mt = tile >> 2, kk = tile & 3, q = l >> 4, r = l & 15;
+  const int ow = (which & 1) ? MLP_OW3 : MLP_OW2;
+  const bool tr = which >= 2;
+  uint32_t h[4];
+  for (int j = 0; j < 4; ++j) {
+    const int row = 16 * mt + r, col = 16 * kk + 4 * q + j;   // element (row, col) of W or W^T
+    const float e = tr ? wr[ow + MLP_H * col + row] : wr[ow + MLP_H * row + col];
+    h[j] = bf16_bits(e);
+  }
+  pack[i] = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+}
+
+__global__ __launch_bounds__(256) void k_round(const float* w, float* wr, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) wr[i] = bf16_round(w[i]);
+}
+
+// min / max of the finite table nodes of ln P and ln c_s^2 (one block)
+__global__ __launch_bounds__(256) void k_table_range(const double* __restrict__ lnP, const double* __restrict__ lnc,
+                                                     int64_t n, float* out) {
+  __shared__ double red[4][256];
+  double v[4] = {1e300, -1e300, 1e300, -1e300};
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const double a = lnP[i], b = lnc[i];
+    if (isfinite(a)) { v[0] = fmin(v[0], a); v[1] = fmax(v[1], a); }
+    if (isfinite(b)) { v[2] = fmin(v[2], b); v[3] = fmax(v[3], b); }
+  }
+  for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = v[k];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int k = 0; k < 4; ++k)
+        red[k][threadIdx.x] = (k & 1) ? fmax(red[k][threadIdx.x], red[k][threadIdx.x + s])
+                                      : fmin(red[k][threadIdx.x], red[k][threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = (float)(0.5 * (red[0][0] + red[1][0]));
+    out[1] = (float)(0.5 * (red[2][0] + red[3][0]));
+    out[2] = (float)(0.5 * (red[1][0] - red[0][0]));
+    out[3] = (float)(0.5 * (red[3][0] - red[2][0]));
+  }
+}
+
+// training pairs: normalised inputs and table-interpolated normalised targets
+__global__ __launch_bounds__(256) void k_mlp_targets(sph_params p, MlpNorm nm, const double* __restrict__ samples,
+                                                     int64_t n, float* __restrict__ x, float* __restrict__ t,
+                                                     DevStatus* status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double lnr = samples[2 * i], lnu = samples[2 * i + 1];
+  double lp = 0.0, lc = 0.0;
+  int64_t cell;
+  if (eos_table_ln(p, lnr, lnu, lp, lc, cell)) latch_error(status, SPH_E_EOS_DOMAIN, (int)i);
+  x[2 * i] = (float)((lnr - nm.in_lo[0]) * nm.in_sc[0] - 1.0);
+  x[2 * i + 1] = (float)((lnu - nm.in_lo[1]) * nm.in_sc[1] - 1.0);
+  t[2 * i] = (float)((lp - nm.out_c[0]) / nm.out_sc[0]);
+  t[2 * i + 1] = (float)((lc - nm.out_c[1]) / nm.out_sc[1]);
+}
+
+// squared error of the network on normalised pairs (holdout loss), one partial per block
+__global__ __launch_bounds__(64) void k_mlp_sqerr(MlpView M, const float* __restrict__ x, const float* __restrict__ t,
+                                                  int64_t n, float* __restrict__ part) {
+  float acc = 0.f;
+  for (int64_t base = (int64_t)blockIdx.x * 64; base < n; base += (int64_t)gridDim.x * 64) {
+    const int64_t i = base + threadIdx.x;
+    const bool ok = i < n;
+    float y0 = 0.f, y1 = 0.f;
+    mlp_wave(M, ok ? x[2 * i] : 0.f, ok ? x[2 * i + 1] : 0.f, y0, y1);
+    if (ok) {
+      const float e0 = y0 - t[2 * i], e1 = y1 - t[2 * i + 1];
+      acc += 0.5f * (e0 * e0 + e1 * e1);
+    }
+  }
+  acc = wave_sum_f(acc);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// network outputs in physical units: ln P, ln c_s^2 at (ln rho, ln u)
+__global__ __launch_bounds__(64) void k_mlp_eval(MlpView M, const double* __restrict__ lnr,
+                                                 const double* __restrict__ lnu, int64_t n, double* __restrict__ lp,
+                                                 double* __restrict__ lc) {
+  const MlpNorm& nm = M.norm;
+  for (int64_t base = (int64_t)blockIdx.x * 64; base < n; base += (int64_t)gridDim.x * 64) {
+    const int64_t i = base + threadIdx.x;
+    const bool ok = i < n;
+    const float x0 = ok ? (float)((lnr[i] - nm.in_lo[0]) * nm.in_sc[0] - 1.0) : 0.f;
+    const float x1 = ok ? (float)((lnu[i] - nm.in_lo[1]) * nm.in_sc[1] - 1.0) : 0.f;
+    float y0 = 0.f, y1 = 0.f;
+    mlp_wave(M, x0, x1, y0, y1);
+    if (ok) {
+      lp[i] = (double)y0 * nm.out_sc[0] + nm.out_c[0];
+      lc[i] = (double)y1 * nm.out_sc[1] + nm.out_c[1];
+    }
+  }
+}
+
+// Trust mask: a table cell is trusted when, at its four nodes and its centre, the network's P and
+// c_s^2 are within relative tolerance tol of the table.
+__global__ __launch_bounds__(64) void k_mlp_trust(MlpView M, sph_params p, double tol, uint8_t* __restrict__ mask,
+                                                  unsigned long long* count) {
+  const MlpNorm& nm = M.norm;
+  const int nu1 = p.tab_nu - 1;
+  const int64_t ncell = (int64_t)(p.tab_nr - 1) * nu1;
+  unsigned long long good = 0;
+  for (int64_t base = (int64_t)blockIdx.x * 64; base < ncell; base += (int64_t)gridDim.x * 64) {
+    const int64_t c = base + threadIdx.x;
+    const bool ok = c < ncell;
+    const int i = ok ? (int)(c / nu1) : 0, j = ok ? (int)(c % nu1) : 0;
+    double err = 0.0;
+    bool finite = true;
+    const double fa[5] = {0.0, 1.0, 0.0, 1.0, 0.5}, fb[5] = {0.0, 0.0, 1.0, 1.0, 0.5};
+#pragma unroll 1
+    for (int k = 0; k < 5; ++k) {
+      const double lnr = p.tab_lnr0 + ((double)i + fa[k]) * p.tab_dlnr;
+      const double lnu = p.tab_lnu0 + ((double)j + fb[k]) * p.tab_dlnu;
+      float y0 = 0.f, y1 = 0.f;
+      mlp_wave(M, (float)((lnr - nm.in_lo[0]) * nm.in_sc[0] - 1.0), (float)((lnu - nm.in_lo[1]) * nm.in_sc[1] - 1.0),
+               y0, y1);
+      const int64_t o = (int64_t)i * p.tab_nu + j;
+      double tp, tc;
+      finite = finite && table_bilinear(p.tab_lnP, o, p.tab_nu, fa[k], fb[k], tp) &&
+               table_bilinear(p.tab_lncs2, o, p.tab_nu, fa[k], fb[k], tc);
+      if (finite) {
+        const double ep = fabs(expm1((double)y0 * nm.out_sc[0] + nm.out_c[0] - tp));
+        const double ec = fabs(expm1((double)y1 * nm.out_sc[1] + nm.out_c[1] - tc));
+        err = fmax(err, fmax(ep, ec));
+      }
+    }
+    if (ok) {
+      const bool t = finite && err <= tol;
+      mask[c] = t ? 1 : 0;
+      good += t ? 1ull : 0ull;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) good += __shfl_xor(good, off, 64);
+  if (threadIdx.x == 0) atomicAdd(count, good);
+}
+
+template <typename T>
+sph_status dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (hipMalloc((void**)p, sizeof(T) * count) != hipSuccess) {
+    *p = nullptr;
+    return SPH_E_OOM;
+  }
+  return SPH_OK;
+}
+
+sph_status mlp_alloc(sph_ctx* c) {
+  if (c->mlp) return SPH_OK;
+  MlpState* s = new MlpState();
+  c->mlp = s;
+  sph_status e;
+  if ((e = dalloc(&s->w, MLP_NPARAM)) || (e = dalloc(&s->wr, MLP_NPARAM)) || (e = dalloc(&s->m, MLP_NPARAM)) ||
+      (e = dalloc(&s->v, MLP_NPARAM)) || (e = dalloc(&s->pack, 4 * 1024)) ||
+      (e = dalloc(&s->gpart, (size_t)kMaxBlocks * MLP_NPARAM)) || (e = dalloc(&s->lpart, kMaxBlocks)) ||
+      (e = dalloc(&s->gsum, MLP_NPARAM)) || (e = dalloc(&s->scal, 4)))
+    return e;
+  return SPH_OK;
+}
+
+bool table_ok(const sph_ctx* c) {
+  const sph_params& p = c->p;
+  return p.tab_lnP && p.tab_lncs2 && p.tab_nr >= 2 && p.tab_nu >= 2;
+}
+
+// input normalisation from the table's box, output normalisation from its value range
+sph_status mlp_norm(sph_ctx* c) {
+  MlpState* s = c->mlp;
+  if (s->norm_set) return SPH_OK;
+  const sph_params& p = c->p;
+  hipLaunchKernelGGL(k_table_range, dim3(1), dim3(256), 0, c->stream, p.tab_lnP, p.tab_lncs2,
+                     (int64_t)p.tab_nr * p.tab_nu, s->scal);
+  float r[4];
+  HIP_TRY(hipMemcpyAsync(r, s->scal, sizeof(r), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  MlpNorm& nm = s->norm;
+  nm.in_lo[0] = (float)p.tab_lnr0;
+  nm.in_lo[1] = (float)p.tab_lnu0;
+  nm.in_sc[0] = (float)(2.0 / ((p.tab_nr - 1) * p.tab_dlnr));
+  nm.in_sc[1] = (float)(2.0 / ((p.tab_nu - 1) * p.tab_dlnu));
+  nm.out_c[0] = r[0];
+  nm.out_c[1] = r[1];
+  nm.out_sc[0] = r[2] > 0.f ? r[2] : 1.f;
+  nm.out_sc[1] = r[3] > 0.f ? r[3] : 1.f;
+  s->norm_set = true;
+  return SPH_OK;
+}
+
+MlpView view_of(const MlpState* s) {
+  MlpView v;
+  v.wr = s->wr;
+  v.wa2 = s->pack;
+  v.wa3 = s->pack + 1024;
+  v.wt2 = s->pack + 2048;
+  v.wt3 = s->pack + 3072;
+  v.trust = s->trust;
+  v.norm = s->norm;
+  return v;
+}
+
+sph_status launch_grad(sph_ctx* c, const float* x, const float* t, int64_t n, int64_t off, int batch) {
+  GradArgs G;
+  G.M = view_of(c->mlp);
+  G.x = x;
+  G.t = t;
+  G.off = off;
+  G.n = n;
+  G.batch = batch;
+  G.gpart = c->mlp->gpart;
+  G.lpart = c->mlp->lpart;
+  hipLaunchKernelGGL(k_mlp_grad, dim3(batch / 64), dim3(64), 0, c->stream, G);
+  HIP_TRY(hipGetLastError());
+  return SPH_OK;
+}
+
+}  // namespace
+
+bool mlp_view(const sph_ctx* c, MlpView* v) {
+  if (!c->mlp || !c->mlp->loaded || !c->mlp->norm_set) return false;
+  *v = view_of(c->mlp);
+  return true;
+}
+
+void mlp_free(sph_ctx* c) {
+  MlpState* s = c->mlp;
+  if (!s) return;
+  void* bufs[] = {s->w, s->wr, s->m, s->v, s->pack, s->gpart, s->lpart, s->gsum, s->scal, s->trust};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  delete s;
+  c->mlp = nullptr;
+}
+
+extern "C" {
+
+sph_status sph_mlp_set_params(sph_ctx* c, const float* params) {
+  if (!c || !params || !table_ok(c)) return SPH_E_ARG;
+  sph_status e;
+  if ((e = mlp_alloc(c)) || (e = mlp_norm(c))) return e;
+  MlpState* s = c->mlp;
+  HIP_TRY(hipMemcpyAsync(s->w, params, sizeof(float) * MLP_NPARAM, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemsetAsync(s->m, 0, sizeof(float) * MLP_NPARAM, c->stream));
+  HIP_TRY(hipMemsetAsync(s->v, 0, sizeof(float) * MLP_NPARAM, c->stream));
+  hipLaunchKernelGGL(k_round, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, c->stream, s->w, s->wr, MLP_NPARAM);
+  hipLaunchKernelGGL(k_mlp_pack, dim3(16), dim3(256), 0, c->stream, s->wr, s->pack);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (s->trust) {   // a mask belongs to the weights it was built for
+    (void)hipFree(s->trust);
+    s->trust = nullptr;
+    s->trust_cells = 0;
+  }
+  s->step = 0;
+  s->loaded = true;
+  return SPH_OK;
+}
+
+sph_status sph_mlp_get_params(sph_ctx* c, float* params, int32_t rounded) {
+  if (!c || !params || !c->mlp || !c->mlp->loaded) return SPH_E_ARG;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(hipMemcpy(params, rounded ? c->mlp->wr : c->mlp->w, sizeof(float) * MLP_NPARAM, hipMemcpyDeviceToHost));
+  return SPH_OK;
+}
+
+sph_status sph_mlp_get_norm(sph_ctx* c, float* norm8) {
+  if (!c || !norm8 || !c->mlp || !c->mlp->norm_set) return SPH_E_ARG;
+  const MlpNorm& nm = c->mlp->norm;
+  const float v[8] = {nm.in_lo[0], nm.in_lo[1], nm.in_sc[0], nm.in_sc[1], nm.out_c[0], nm.out_c[1], nm.out_sc[0],
+                      nm.out_sc[1]};
+  memcpy(norm8, v, sizeof(v));
+  return SPH_OK;
+}
+
+sph_status sph_mlp_grad(sph_ctx* c, const float* x, const float* t, int64_t n, float* grad, double* loss) {
+  if (!c || !x || !t || !grad || !c->mlp || !c->mlp->loaded) return SPH_E_ARG;
+  if (n < 64 || n % 64 || n / 64 > kMaxBlocks) return SPH_E_ARG;
+  MlpState* s = c->mlp;
+  sph_status e = launch_grad(c, x, t, n, 0, (int)n);
+  if (e) return e;
+  hipLaunchKernelGGL(k_mlp_adam, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, c->stream, s->w, s->wr, s->m, s->v,
+                     s->gpart, s->lpart, (int)(n / 64), 0.f, 1.f, 1.f, s->gsum, s->scal);
+  HIP_TRY(hipGetLastError());
+  float l = 0.f;
+  HIP_TRY(hipMemcpyAsync(grad, s->gsum, sizeof(float) * MLP_NPARAM, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(&l, s->scal, sizeof(float), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (loss) *loss = l;
+  return SPH_OK;
+}
+
+sph_status sph_mlp_train(sph_ctx* c, const double* samples, int64_t n, int64_t n_holdout, int32_t epochs,
+                         int32_t batch, float lr, float* history) {
+  if (!c || !samples || !c->mlp || !c->mlp->loaded || !table_ok(c)) return SPH_E_ARG;
+  if (n_holdout < 0 || n - n_holdout < batch || epochs < 0 || batch < 64 || batch % 64 || batch / 64 > kMaxBlocks ||
+      !(lr > 0.f))
+    return SPH_E_ARG;
+  MlpState* s = c->mlp;
+  float *x = nullptr, *t = nullptr, *part = nullptr;
+  sph_status e = SPH_OK;
+  if ((e = dalloc(&x, (size_t)2 * n)) || (e = dalloc(&t, (size_t)2 * n)) || (e = dalloc(&part, 1024))) {
+    if (x) (void)hipFree(x);
+    if (t) (void)hipFree(t);
+    return e;
+  }
+  hipLaunchKernelGGL(k_mlp_targets, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, c->p, s->norm, samples, n, x, t,
+                     c->status);
+  const int64_t ntrain = n - n_holdout;
+  const int64_t per_epoch = ntrain / batch;
+  const int64_t total = per_epoch * epochs;
+  const int nblk = batch / 64;
+  const unsigned hold_blocks = n_holdout > 0 ? (unsigned)((n_holdout + 63) / 64 < 1024 ? (n_holdout + 63) / 64 : 1024) : 0;
+  for (int32_t ep = 0; ep < epochs && !e; ++ep) {
+    for (int64_t k = 0; k < per_epoch && !e; ++k) {
+      const int64_t it = (int64_t)ep * per_epoch + k;
+      const double lr_t = 0.5 * lr * (1.0 + cos(M_PI * (double)it / (double)total));   // cosine schedule
+      ++s->step;
+      const float bc1 = (float)(1.0 - pow(0.9, (double)s->step)), bc2 = (float)(1.0 - pow(0.999, (double)s->step));
+      // samples rotate through the training set; each epoch starts at a different offset
+      const int64_t off = (k * batch + (int64_t)ep * 7919) % ntrain;
+      if ((e = launch_grad(c, x, t, ntrain, off, batch))) break;
+      hipLaunchKernelGGL(k_mlp_adam, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, c->stream, s->w, s->wr, s->m,
+                         s->v, s->gpart, s->lpart, nblk, (float)lr_t, bc1, bc2, (float*)nullptr, s->scal);
+      hipLaunchKernelGGL(k_mlp_pack, dim3(16), dim3(256), 0, c->stream, s->wr, s->pack);
+    }
+    if (e) break;
+    float hl = 0.f;
+    if (n_holdout > 0) {
+      hipLaunchKernelGGL(k_mlp_sqerr, dim3(hold_blocks), dim3(64), 0, c->stream, view_of(s), x + 2 * ntrain,
+                         t + 2 * ntrain, n_holdout, part);
+      std::vector<float> hp(hold_blocks);
+      if (hipMemcpyAsync(hp.data(), part, sizeof(float) * hold_blocks, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+        e = SPH_E_HIP;
+      float tl = 0.f;
+      if (!e && hipMemcpyAsync(&tl, s->scal, sizeof(float), hipMemcpyDeviceToHost, c->stream) != hipSuccess) e = SPH_E_HIP;
+      if (!e && hipStreamSynchronize(c->stream) != hipSuccess) e = SPH_E_HIP;
+      for (float v : hp) hl += v;
+      hl /= (float)n_holdout;
+      if (history) {
+        history[2 * ep] = tl;
+        history[2 * ep + 1] = hl;
+      }
+    }
+  }
+  if (!e && hipStreamSynchronize(c->stream) != hipSuccess) e = SPH_E_HIP;
+  (void)hipFree(x);
+  (void)hipFree(t);
+  (void)hipFree(part);
+  if (s->trust) {   // the weights changed
+    (void)hipFree(s->trust);
+    s->trust = nullptr;
+    s->trust_cells = 0;
+  }
+  return e;
+}
+
+sph_status sph_mlp_eval(sph_ctx* c, const double* lnrho, const double* lnu, int64_t n, double* lnP, double* lncs2) {
+  if (!c || n < 0 || (n > 0 && (!lnrho || !lnu || !lnP || !lncs2)) || !c->mlp || !c->mlp->loaded ||
+      !c->mlp->norm_set)
+    return SPH_E_ARG;
+  if (n == 0) return SPH_OK;
+  const unsigned nb = (unsigned)((n + 63) / 64 < 65536 ? (n + 63) / 64 : 65536);
+  hipLaunchKernelGGL(k_mlp_eval, dim3(nb), dim3(64), 0, c->stream, view_of(c->mlp), lnrho, lnu, n, lnP, lncs2);
+  HIP_TRY(hipGetLastError());
+  return SPH_OK;
+}
+
+sph_status sph_mlp_build_trust_mask(sph_ctx* c, double tol, int64_t* trusted_cells) {
+  if (!c || !(tol >= 0.0) || !c->mlp || !c->mlp->loaded || !table_ok(c)) return SPH_E_ARG;
+  MlpState* s = c->mlp;
+  const int64_t ncell = (int64_t)(c->p.tab_nr - 1) * (c->p.tab_nu - 1);
+  if (!s->trust && hipMalloc((void**)&s->trust, (size_t)ncell) != hipSuccess) {
+    s->trust = nullptr;
+    return SPH_E_OOM;
+  }
+  unsigned long long* cnt = nullptr;
+  if (hipMalloc((void**)&cnt, sizeof(unsigned long long)) != hipSuccess) return SPH_E_OOM;
+  sph_status e = SPH_OK;
+  unsigned long long h = 0;
+  if (hipMemcpyAsync(cnt, &h, sizeof(h), hipMemcpyHostToDevice, c->stream) != hipSuccess) e = SPH_E_HIP;
+  if (!e) {
+    MlpView v = view_of(s);
+    v.trust = nullptr;
+    const unsigned nb = (unsigned)((ncell + 63) / 64 < 65536 ? (ncell + 63) / 64 : 65536);
+    hipLaunchKernelGGL(k_mlp_trust, dim3(nb), dim3(64), 0, c->stream, v, c->p, tol, s->trust, cnt);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+      e = SPH_E_HIP;
+  }
+  (void)hipFree(cnt);
+  s->trust_cells = (int64_t)h;
+  if (trusted_cells) *trusted_cells = (int64_t)h;
+  return e;
+}
+
+}  // extern "C"

@@ -13,6 +13,7 @@
 #include <type_traits>
 
 #include "sph_internal.h"
+#include "sph_mlp.h"
 
 namespace {
 
@@ -95,6 +96,8 @@ struct PassArgs {
   const int32_t* __restrict__ star;
   const StarInfo* __restrict__ stars;
   DevStatus* status;
+  MlpView mlp;          // EoS surrogate (eos = MLP with a loaded network)
+  int has_mlp;
 };
 
 constexpr int kNone = 0x7fffffff;
@@ -155,35 +158,54 @@ __device__ __forceinline__ void star_centre(const PassArgs& A, int64_t a, double
 }
 
 // ---- equation of state -------------------------------------------------------------------------
-__device__ __forceinline__ bool bilinear(const double* __restrict__ T, int64_t o, int nu, double a, double b,
-                                         double& v) {
-  const double f00 = T[o], f01 = T[o + 1], f10 = T[o + nu], f11 = T[o + nu + 1];
-  if (!isfinite(f00) || !isfinite(f01) || !isfinite(f10) || !isfinite(f11)) return false;
-  v = (1.0 - a) * ((1.0 - b) * f00 + b * f01) + a * ((1.0 - b) * f10 + b * f11);
-  return true;
-}
-
+// Table (and, where the surrogate is not trusted, the MLP mode): bilinear ln P, ln c_s^2.
 __device__ __forceinline__ int eos_eval(const sph_params& p, double rho, double u, double& P, double& cs2) {
   if (p.eos == SPH_EOS_TABLE || p.eos == SPH_EOS_MLP) {
     if (!(rho > 0.0) || !(u > 0.0)) return SPH_E_EOS_DOMAIN;
-    const double fr = (log(rho) - p.tab_lnr0) / p.tab_dlnr;
-    const double fu = (log(u) - p.tab_lnu0) / p.tab_dlnu;
-    if (!(fr >= 0.0) || !(fu >= 0.0) || fr > (double)(p.tab_nr - 1) || fu > (double)(p.tab_nu - 1))
-      return SPH_E_EOS_DOMAIN;
-    int i = (int)floor(fr), j = (int)floor(fu);
-    i = i > p.tab_nr - 2 ? p.tab_nr - 2 : i;
-    j = j > p.tab_nu - 2 ? p.tab_nu - 2 : j;
-    const double a = fr - (double)i, b = fu - (double)j;
-    const int64_t o = (int64_t)i * p.tab_nu + j;
     double lp, lc;
-    if (!bilinear(p.tab_lnP, o, p.tab_nu, a, b, lp) || !bilinear(p.tab_lncs2, o, p.tab_nu, a, b, lc))
-      return SPH_E_EOS_DOMAIN;
+    int64_t cell;
+    if (eos_table_ln(p, log(rho), log(u), lp, lc, cell)) return SPH_E_EOS_DOMAIN;
     P = exp(lp);
     cs2 = exp(lc);
     return 0;
   }
   P = (p.gamma - 1.0) * rho * u;
   cs2 = (p.background == SPH_TOV) ? p.gamma * P / (rho * (1.0 + u + P / rho)) : p.gamma * P / rho;
+  return 0;
+}
+
+// Surrogate EoS: the network's ln P, ln c_s^2 in every table cell the trust mask accepts, table
+// interpolation elsewhere.  Every lane of the wave must call it; the network (a wave-level call)
+// runs only if some lane of the wave sits in a trusted cell.
+__device__ __forceinline__ int eos_mlp(const MlpView& M, const sph_params& p, double rho, double u, double& P,
+                                       double& cs2) {
+  bool ok = rho > 0.0 && u > 0.0;
+  const double lnr = ok ? log(rho) : p.tab_lnr0, lnu = ok ? log(u) : p.tab_lnu0;
+  const double fr = (lnr - p.tab_lnr0) / p.tab_dlnr, fu = (lnu - p.tab_lnu0) / p.tab_dlnu;
+  ok = ok && fr >= 0.0 && fu >= 0.0 && fr <= (double)(p.tab_nr - 1) && fu <= (double)(p.tab_nu - 1);
+  bool trusted = false;
+  if (ok && M.trust) {
+    int i = (int)floor(fr), j = (int)floor(fu);
+    i = i > p.tab_nr - 2 ? p.tab_nr - 2 : i;
+    j = j > p.tab_nu - 2 ? p.tab_nu - 2 : j;
+    trusted = M.trust[(int64_t)i * (p.tab_nu - 1) + j] != 0;
+  }
+  const MlpNorm& nm = M.norm;
+  float y0 = 0.f, y1 = 0.f;
+  if (__ballot(trusted))
+    mlp_wave(M, (float)((lnr - nm.in_lo[0]) * nm.in_sc[0] - 1.0), (float)((lnu - nm.in_lo[1]) * nm.in_sc[1] - 1.0), y0,
+             y1);
+  if (!ok) return SPH_E_EOS_DOMAIN;
+  double lp, lc;
+  if (trusted) {
+    lp = (double)y0 * nm.out_sc[0] + nm.out_c[0];
+    lc = (double)y1 * nm.out_sc[1] + nm.out_c[1];
+  } else {
+    int64_t cell;
+    if (eos_table_ln(p, lnr, lnu, lp, lc, cell)) return SPH_E_EOS_DOMAIN;
+  }
+  P = exp(lp);
+  cs2 = exp(lc);
   return 0;
 }
 
@@ -224,11 +246,75 @@ struct ListWriter {
   }
 };
 
+// Density-stage epilogue in FP64 for particle a with computational density D: rest-mass density
+// from D = rho psi^6 W_L, EoS, shear modulus, yield stress and the packed records of the stress
+// and force passes.  With MLP the EoS is the surrogate network (every lane of the wave must
+// call; lanes with valid = false store nothing).
+template <typename R, bool MLP>
+__device__ __forceinline__ void density_epilogue(const PassArgs& A, int64_t a, bool valid, double D,
+                                                 const double4* __restrict__ pos64, const double* __restrict__ vx,
+                                                 const double* __restrict__ vy, const double* __restrict__ vz,
+                                                 const double* __restrict__ u, const double* __restrict__ S,
+                                                 const int8_t* __restrict__ type, const uint8_t* __restrict__ broken,
+                                                 DensOut O) {
+  const sph_params& p = A.p;
+  const double va[3] = {vx[a], vy[a], vz[a]};
+  double rho = D, hfac = 1.0;
+  if (p.background == SPH_TOV) {
+    double cx, cy, cz;
+    star_centre(A, a, cx, cy, cz);
+    const double4 p64 = pos64[a];   // the background is always evaluated in FP64
+    Metric g = metric_at(p, p64.x - cx, p64.y - cy, p64.z - cz);
+    double v2 = va[0] * va[0] + va[1] * va[1] + va[2] * va[2];
+    double psi2 = g.psi * g.psi, psi4 = psi2 * psi2;
+    double WL = 1.0 / sqrt(1.0 - psi4 * v2 / (g.alpha * g.alpha));
+    rho = D / (psi4 * psi2 * WL);
+  }
+  double P, cs2;
+  int e;
+  if constexpr (MLP) e = eos_mlp(A.mlp, p, rho, u[a], P, cs2);
+  else e = eos_eval(p, rho, u[a], P, cs2);
+  if (!valid) return;
+  if (e) latch_error(A.status, e, (int)a);
+  if (p.background == SPH_TOV) hfac = 1.0 + u[a] + P / rho;
+  const double cs = sqrt(cs2);
+  const double Bm = rho * hfac * cs2;
+  const bool solid = type[a] == 1 && !(broken[a] && p.break_mode == SPH_BREAK_FLUIDIZE);
+  double mu = 0.0;
+  if (solid) {
+    double fac = p.mu_pfactor;
+    if (A.star && A.stars) fac = A.stars[A.star[a]].mu_pfactor;
+    mu = (p.mu_mode == SPH_MU_PFACTOR) ? fac * P : p.mu_const;
+  }
+  const double E = mu > 0.0 ? 9.0 * Bm * mu / (3.0 * Bm + mu) : 0.0;
+  O.D[a] = D;
+  O.rho[a] = rho;
+  O.P[a] = P;
+  O.cs[a] = cs;
+  O.mu[a] = mu;
+  O.B[a] = Bm;
+  O.Y0[a] = (p.y0_mode == SPH_Y0_EFACTOR) ? p.y0_over_E * E : p.y0_const;
+  const double iD2 = 1.0 / (D * D);
+  const double pi = P * iD2;
+  const bool stressed = solid;
+  const int64_t n = A.n;
+  if (sizeof(R) == 8) {
+    O.fv[a] = make_double4(va[0], va[1], va[2], cs);
+    O.fa[a] = make_double2(pi, stressed ? -D : D);
+    for (int c = 0; c < 6; ++c) O.sig[c * n + a] = S[c * n + a] * iD2;
+  } else {
+    O.fvf[a] = make_float4((float)va[0], (float)va[1], (float)va[2], (float)cs);
+    O.faf[a] = make_float2((float)pi, stressed ? -(float)D : (float)D);
+    for (int c = 0; c < 6; ++c) O.sigf[c * n + a] = (float)(S[c * n + a] * iD2);
+  }
+  if (!isfinite(D) || !isfinite(P) || !isfinite(cs)) latch_error(A.status, SPH_E_NONFINITE, (int)a);
+}
+
 // Density pass.  Walks the candidate lists, takes the exact FP64 neighbour decision
 // r^2 < (h_a + h_b)^2 on every candidate (positions staged in LDS in FP64 for both precisions),
 // sums the kernel over the neighbours in R, and writes the exact lists for the stress and force
 // passes.
-template <typename R, int KER, bool PER>
+template <typename R, int KER, bool PER, bool EPI>
 __global__ __launch_bounds__(64) void k_density(PassArgs A, const double4* __restrict__ pos64,
                                                 const double* __restrict__ vx, const double* __restrict__ vy,
                                                 const double* __restrict__ vz, const double* __restrict__ u,
@@ -287,57 +373,29 @@ __global__ __launch_bounds__(64) void k_density(PassArgs A, const double4* __res
     xcount[tw.p] = wr.n < A.cap ? wr.n : A.cap;
     if (wr.n > A.cap) latch_error(A.status, SPH_E_NGB_CAPACITY, (int)a);
   }
+  if (!EPI) {   // the epilogue runs in k_density_epilogue
+    if (tw.valid) O.D[a] = particle_mass(A, a) * (double)sum;
+    continue;
+  }
   if (!tw.valid) continue;
-  const double m = particle_mass(A, a);
-  const double D = m * (double)sum;
-  // epilogue in FP64: rest-mass density from D = rho psi^6 W_L, EoS, shear modulus, yield stress
-  const double va[3] = {vx[a], vy[a], vz[a]};
-  double rho = D, hfac = 1.0;
-  if (p.background == SPH_TOV) {
-    double cx, cy, cz;
-    star_centre(A, a, cx, cy, cz);
-    const double4 p64 = pos64[a];   // the background is always evaluated in FP64
-    Metric g = metric_at(p, p64.x - cx, p64.y - cy, p64.z - cz);
-    double v2 = va[0] * va[0] + va[1] * va[1] + va[2] * va[2];
-    double psi2 = g.psi * g.psi, psi4 = psi2 * psi2;
-    double WL = 1.0 / sqrt(1.0 - psi4 * v2 / (g.alpha * g.alpha));
-    rho = D / (psi4 * psi2 * WL);
+  density_epilogue<R, false>(A, a, true, particle_mass(A, a) * (double)sum, pos64, vx, vy, vz, u, S, type, broken, O);
   }
-  double P, cs2;
-  int e = eos_eval(p, rho, u[a], P, cs2);
-  if (e) latch_error(A.status, e, (int)a);
-  if (p.background == SPH_TOV) hfac = 1.0 + u[a] + P / rho;
-  const double cs = sqrt(cs2);
-  const double Bm = rho * hfac * cs2;
-  const bool solid = type[a] == 1 && !(broken[a] && p.break_mode == SPH_BREAK_FLUIDIZE);
-  double mu = 0.0;
-  if (solid) {
-    double fac = p.mu_pfactor;
-    if (A.star && A.stars) fac = A.stars[A.star[a]].mu_pfactor;
-    mu = (p.mu_mode == SPH_MU_PFACTOR) ? fac * P : p.mu_const;
-  }
-  const double E = mu > 0.0 ? 9.0 * Bm * mu / (3.0 * Bm + mu) : 0.0;
-  O.D[a] = D;
-  O.rho[a] = rho;
-  O.P[a] = P;
-  O.cs[a] = cs;
-  O.mu[a] = mu;
-  O.B[a] = Bm;
-  O.Y0[a] = (p.y0_mode == SPH_Y0_EFACTOR) ? p.y0_over_E * E : p.y0_const;
-  const double iD2 = 1.0 / (D * D);
-  const double pi = P * iD2;
-  const bool stressed = solid;
-  const int64_t n = A.n;
-  if (sizeof(R) == 8) {
-    O.fv[a] = make_double4(va[0], va[1], va[2], cs);
-    O.fa[a] = make_double2(pi, stressed ? -D : D);
-    for (int c = 0; c < 6; ++c) O.sig[c * n + a] = S[c * n + a] * iD2;
-  } else {
-    O.fvf[a] = make_float4((float)va[0], (float)va[1], (float)va[2], (float)cs);
-    O.faf[a] = make_float2((float)pi, stressed ? -(float)D : (float)D);
-    for (int c = 0; c < 6; ++c) O.sigf[c * n + a] = (float)(S[c * n + a] * iD2);
-  }
-  if (!isfinite(D) || !isfinite(P) || !isfinite(cs)) latch_error(A.status, SPH_E_NONFINITE, (int)a);
+}
+
+// Per-particle epilogue of the density stage when the EoS is the surrogate network (a
+// wave-level call, kept out of the pair-loop kernel whose occupancy it would halve): one lane per
+// particle, D from the pair loop.
+template <typename R>
+__global__ __launch_bounds__(64) void k_density_epilogue(PassArgs A, const double4* __restrict__ pos64,
+                                                         const double* __restrict__ vx, const double* __restrict__ vy,
+                                                         const double* __restrict__ vz, const double* __restrict__ u,
+                                                         const double* __restrict__ S, const int8_t* __restrict__ type,
+                                                         const uint8_t* __restrict__ broken, DensOut O) {
+  for (int64_t base = (int64_t)blockIdx.x * 64; base < A.n; base += (int64_t)gridDim.x * 64) {
+    const int64_t a = base + threadIdx.x;
+    const bool valid = a < A.n;
+    const int64_t ae = valid ? a : base;   // lanes past the end work on a valid particle, store nothing
+    density_epilogue<R, true>(A, ae, valid, O.D[ae], pos64, vx, vy, vz, u, S, type, broken, O);
   }
 }
 
@@ -619,6 +677,7 @@ PassArgs make_args(sph_ctx* c, sph_state* st) {
   A.star = c->stars ? st->star : nullptr;
   A.stars = c->stars;
   A.status = c->status;
+  A.has_mlp = mlp_view(c, &A.mlp) ? 1 : 0;
   return A;
 }
 
@@ -642,16 +701,33 @@ sph_status launch_density(sph_ctx* c, sph_state* st) {
   PassArgs A = make_args(c, st);
   DensOut O{st->D, st->rho, st->P, st->cs, c->mu, c->Y0, c->B, c->fv, c->fa, c->sig, c->fvf, c->faf, c->sigf};
   const dim3 g = pass_grid(c), b(64);
+  const bool f32 = c->p.precision == SPH_FP32;
+  const bool mlp = c->p.eos == SPH_EOS_MLP && A.has_mlp;
   dispatch_cfg(c->p.kernel, c->p.periodic, [&](auto K, auto P) {
     constexpr int KER = decltype(K)::value;
     constexpr bool PER = decltype(P)::value;
-    if (c->p.precision == SPH_FP32)
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_density<float, KER, PER>), g, b, 0, c->stream, A, c->pos4, st->vx, st->vy,
-                         st->vz, st->u, st->S, st->type, st->broken, O, c->nbr16, c->nbr_count);
+    if (f32 && mlp)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_density<float, KER, PER, false>), g, b, 0, c->stream, A, c->pos4, st->vx,
+                         st->vy, st->vz, st->u, st->S, st->type, st->broken, O, c->nbr16, c->nbr_count);
+    else if (f32)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_density<float, KER, PER, true>), g, b, 0, c->stream, A, c->pos4, st->vx,
+                         st->vy, st->vz, st->u, st->S, st->type, st->broken, O, c->nbr16, c->nbr_count);
+    else if (mlp)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_density<double, KER, PER, false>), g, b, 0, c->stream, A, c->pos4, st->vx,
+                         st->vy, st->vz, st->u, st->S, st->type, st->broken, O, c->nbr16, c->nbr_count);
     else
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_density<double, KER, PER>), g, b, 0, c->stream, A, c->pos4, st->vx,
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_density<double, KER, PER, true>), g, b, 0, c->stream, A, c->pos4, st->vx,
                          st->vy, st->vz, st->u, st->S, st->type, st->broken, O, c->nbr16, c->nbr_count);
   });
+  if (mlp) {
+    const unsigned nb = (unsigned)((st->n + 63) / 64 < 65536 ? (st->n + 63) / 64 : 65536);
+    if (f32)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_density_epilogue<float>), dim3(nb), b, 0, c->stream, A, c->pos4, st->vx,
+                         st->vy, st->vz, st->u, st->S, st->type, st->broken, O);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_density_epilogue<double>), dim3(nb), b, 0, c->stream, A, c->pos4, st->vx,
+                         st->vy, st->vz, st->u, st->S, st->type, st->broken, O);
+  }
   HIP_TRY(hipGetLastError());
   return SPH_OK;
 }

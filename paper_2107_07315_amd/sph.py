@@ -19,7 +19,10 @@ STATUS = {0: "SPH_OK", 1: "SPH_E_ARG", 2: "SPH_E_HIP", 3: "SPH_E_OOM", 4: "SPH_E
 
 EXPORTED = ("sph_create", "sph_destroy", "sph_set_params", "sph_build_cells", "sph_density",
             "sph_stress_rate", "sph_forces", "sph_step", "sph_sync", "sph_export_neighbours",
-            "sph_status_string", "sph_set_timing", "sph_get_timing", "sph_neighbour_stats")
+            "sph_status_string", "sph_set_timing", "sph_get_timing", "sph_neighbour_stats",
+            "sph_mlp_set_params", "sph_mlp_get_params", "sph_mlp_get_norm", "sph_mlp_train", "sph_mlp_grad",
+            "sph_mlp_eval", "sph_mlp_build_trust_mask")
+MLP_NPARAM = 8642
 
 _dp = ctypes.c_void_p
 
@@ -89,6 +92,14 @@ def load():
     L.sph_neighbour_stats.argtypes = [vp, ctypes.POINTER(SphListStats)]
     L.sph_get_timing.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32),
                                  ctypes.POINTER(ctypes.c_double)]
+    L.sph_mlp_set_params.argtypes = [vp, vp]
+    L.sph_mlp_get_params.argtypes = [vp, vp, ctypes.c_int32]
+    L.sph_mlp_get_norm.argtypes = [vp, vp]
+    L.sph_mlp_train.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                ctypes.c_float, vp]
+    L.sph_mlp_grad.argtypes = [vp, vp, vp, ctypes.c_int64, vp, ctypes.POINTER(ctypes.c_double)]
+    L.sph_mlp_eval.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp]
+    L.sph_mlp_build_trust_mask.argtypes = [vp, ctypes.c_double, ctypes.POINTER(ctypes.c_int64)]
     _lib = L
     return L
 
@@ -259,6 +270,53 @@ class Context:
         _check(self.lib.sph_neighbour_stats(self.h, ctypes.byref(s)), "sph_neighbour_stats")
         return {k: getattr(s, k) for k in ("pairs", "max_count", "tiles", "union_total", "candidates",
                                            "rebuilds")}
+
+    # EoS surrogate network ------------------------------------------------------------------
+    def mlp_set_params(self, params):
+        w = np.ascontiguousarray(params, np.float32)
+        assert w.shape == (MLP_NPARAM,)
+        _check(self.lib.sph_mlp_set_params(self.h, w.ctypes.data), "sph_mlp_set_params")
+
+    def mlp_get_params(self, rounded=False):
+        w = np.zeros(MLP_NPARAM, np.float32)
+        _check(self.lib.sph_mlp_get_params(self.h, w.ctypes.data, int(bool(rounded))), "sph_mlp_get_params")
+        return w
+
+    def mlp_get_norm(self):
+        v = np.zeros(8, np.float32)
+        _check(self.lib.sph_mlp_get_norm(self.h, v.ctypes.data), "sph_mlp_get_norm")
+        return v
+
+    def mlp_train(self, samples, n_holdout, epochs, batch=4096, lr=1e-3):
+        """samples: device FP64 tensor [n, 2] of (ln rho, ln u).  Returns per-epoch
+        (training-batch loss, holdout loss)."""
+        import torch
+        assert samples.dtype == torch.float64 and samples.is_cuda and samples.is_contiguous()
+        hist = np.zeros((max(epochs, 1), 2), np.float32)
+        _check(self.lib.sph_mlp_train(self.h, samples.data_ptr(), samples.shape[0], int(n_holdout), int(epochs),
+                                      int(batch), float(lr), hist.ctypes.data), "sph_mlp_train")
+        return hist[:epochs]
+
+    def mlp_grad(self, x, t):
+        """Gradient of the loss over device FP32 tensors x, t [n, 2] (normalised units)."""
+        g = np.zeros(MLP_NPARAM, np.float32)
+        loss = ctypes.c_double()
+        _check(self.lib.sph_mlp_grad(self.h, x.data_ptr(), t.data_ptr(), x.shape[0], g.ctypes.data,
+                                     ctypes.byref(loss)), "sph_mlp_grad")
+        return g, loss.value
+
+    def mlp_eval(self, lnrho, lnu):
+        import torch
+        lp = torch.empty_like(lnrho)
+        lc = torch.empty_like(lnrho)
+        _check(self.lib.sph_mlp_eval(self.h, lnrho.data_ptr(), lnu.data_ptr(), lnrho.shape[0], lp.data_ptr(),
+                                     lc.data_ptr()), "sph_mlp_eval")
+        return lp, lc
+
+    def mlp_build_trust_mask(self, tol=1e-4):
+        n = ctypes.c_int64()
+        _check(self.lib.sph_mlp_build_trust_mask(self.h, float(tol), ctypes.byref(n)), "sph_mlp_build_trust_mask")
+        return n.value
 
     # convenience ---------------------------------------------------------------------------
     def evaluate(self, st: DeviceState):

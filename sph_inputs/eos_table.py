@@ -58,3 +58,30 @@ def make_table(pp: PiecewisePolytrope, gamma_th: float = 1.8, nr: int = 1024, nu
     return EosTable(lnP=np.ascontiguousarray(lnP), lncs2=np.ascontiguousarray(lncs2),
                     lnr0=float(lnr[0]), dlnr=float(lnr[1] - lnr[0]),
                     lnu0=float(lnu[0]), dlnu=float(lnu[1] - lnu[0]))
+
+
+MLP_HIDDEN = 64
+MLP_NPARAM = 2 * 64 + 64 + 64 * 64 + 64 + 64 * 64 + 64 + 2 * 64 + 2
+
+
+def mlp_init(seed: int = 4) -> np.ndarray:
+    """Initial parameters of the 2-64-64-64-2 surrogate (flat layout W1, b1, W2, b2, W3, b3, W4,
+    b4 with W[out][in]): uniform in +-sqrt(6 / (fan_in + fan_out)) (Glorot), biases zero."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fan_in, fan_out in ((2, 64), (64, 64), (64, 64), (64, 2)):
+        a = math.sqrt(6.0 / (fan_in + fan_out))
+        parts.append(rng.uniform(-a, a, fan_in * fan_out))
+        parts.append(np.zeros(fan_out))
+    w = np.concatenate(parts).astype(np.float32)
+    assert w.shape == (MLP_NPARAM,)
+    return w
+
+
+def mlp_samples(table: EosTable, n: int = 1_000_000, seed: int = 4) -> np.ndarray:
+    """Training inputs (ln rho, ln u), uniform over the table's box."""
+    rng = np.random.default_rng(seed)
+    nr, nu = table.lnP.shape
+    lnr = table.lnr0 + rng.uniform(0.0, 1.0, n) * (nr - 1) * table.dlnr
+    lnu = table.lnu0 + rng.uniform(0.0, 1.0, n) * (nu - 1) * table.dlnu
+    return np.ascontiguousarray(np.stack([lnr, lnu], axis=1))

@@ -1,0 +1,211 @@
+"""GPU tests of the EoS surrogate network: gradients and forward pass against the oracle's FP64
+network with the same BF16-rounded weights, training on the GPU, the trust mask and table
+fallback, the density stage with the surrogate against the oracle's table EoS, and what the
+trained network gains over the table."""
+import numpy as np
+import pytest
+
+import oracle
+from sph_inputs import eos_table as E
+from sph_inputs import workloads as W
+
+from parity import gpu_run, oracle_run, rel_err
+
+pytestmark = pytest.mark.gpu
+
+BLOCKS = {"W1": (0, 128), "b1": (128, 192), "W2": (192, 4288), "b2": (4288, 4352), "W3": (4352, 8448),
+          "b3": (8448, 8512), "W4": (8512, 8640), "b4": (8640, 8642)}
+# BF16 activations (relative rounding 2^-9) feed the two 64x64 products; their effect on each
+# gradient block stays a few 2^-9 in relative Frobenius norm
+TOL_GRAD = 1e-2
+
+
+def _ctx(n=2000):
+    from paper_2107_07315_amd import sph
+    w = W.pp_star(n, seed=4, eos="MLP")
+    return sph, sph.Context(w.params, capacity=w.n), w
+
+
+def _print(name, d):
+    print(name, " ".join(f"{k}={v:.3e}" for k, v in d.items()), flush=True)
+
+
+def _to_dev(a, dtype):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=dtype), device="cuda")
+
+
+@pytest.mark.parametrize("n", [64, 320])
+def test_gradient_matches_oracle(n):
+    sph, ctx, _ = _ctx()
+    ctx.mlp_set_params(E.mlp_init(4))
+    wr = ctx.mlp_get_params(rounded=True).astype(np.float64)
+    rng = np.random.default_rng(n)
+    x = rng.uniform(-1, 1, (n, 2)).astype(np.float32)
+    t = rng.uniform(-1, 1, (n, 2)).astype(np.float32)
+    g, loss = ctx.mlp_grad(_to_dev(x, np.float32), _to_dev(t, np.float32))
+    lo, go = oracle.mlp_loss_grad(wr, x.astype(np.float64), t.astype(np.float64))
+    err = {k: float(np.linalg.norm(g[a:b] - go[a:b]) / np.linalg.norm(go[a:b])) for k, (a, b) in BLOCKS.items()}
+    _print(f"grad n={n}", err)
+    assert abs(loss - lo) <= TOL_GRAD * lo
+    for k, v in err.items():
+        assert v < TOL_GRAD, (k, v)
+    # the weights did not move
+    assert np.array_equal(ctx.mlp_get_params(rounded=True), wr.astype(np.float32))
+
+
+def test_forward_matches_oracle_and_rounding():
+    sph, ctx, _ = _ctx()
+    w0 = E.mlp_init(7) * 3.0
+    ctx.mlp_set_params(w0)
+    wr = ctx.mlp_get_params(rounded=True)
+    # rounding to the nearest BF16 (8 significant bits): within half a spacing, 2^-8 relative
+    assert np.all(np.abs(wr - w0) <= 2.0 ** -8 * np.abs(w0))
+    # and the rounded values are BF16 numbers: the low 16 bits of their FP32 patterns are zero
+    assert np.all((wr.view(np.uint32) & 0xffff) == 0)
+    nm = ctx.mlp_get_norm()
+    rng = np.random.default_rng(8)
+    xs = rng.uniform(-1, 1, (777, 2))      # a ragged count: 12 waves and a partial one
+    lnr = (xs[:, 0] + 1) / nm[2] + nm[0]
+    lnu = (xs[:, 1] + 1) / nm[3] + nm[1]
+    lp, lc = ctx.mlp_eval(_to_dev(lnr, np.float64), _to_dev(lnu, np.float64))
+    yg = np.stack([(lp.cpu().numpy() - nm[4]) / nm[6], (lc.cpu().numpy() - nm[5]) / nm[7]], 1)
+    xo = np.stack([(lnr - nm[0]) * nm[2] - 1, (lnu - nm[1]) * nm[3] - 1], 1).astype(np.float32).astype(np.float64)
+    yo = oracle.mlp_forward(wr.astype(np.float64), xo)
+    err = float(np.max(np.abs(yg - yo)) / np.max(np.abs(yo)))
+    print("forward rel err", err, flush=True)
+    assert err < 2e-2
+
+
+@pytest.fixture(scope="module")
+def trained():
+    """A network trained on the GPU as configured for the 2M-particle runs: 1M seeded samples
+    uniform over the table's box (10% held out), Adam with a cosine schedule from lr 1e-3, batch
+    4096, 400 epochs (about 88k steps, a few seconds)."""
+    import torch
+    sph, ctx, w = _ctx(20000)
+    ctx.mlp_set_params(E.mlp_init(4))
+    samples = _to_dev(E.mlp_samples(W.pp_table(), 1_000_000, 4), np.float64)
+    before = ctx.mlp_grad(*_holdout_pairs(ctx, samples))[1]
+    hist = ctx.mlp_train(samples, 100_000, 400, 4096, 1e-3)
+    torch.cuda.synchronize()
+    return sph, ctx, w, samples, before, hist
+
+
+def _holdout_pairs(ctx, samples):
+    """Normalised (x, t) of the last 4096 samples, targets from the table (numpy bilinear)."""
+    tab = W.pp_table()
+    nm = ctx.mlp_get_norm()
+    s = samples[-4096:].cpu().numpy()
+    fr = (s[:, 0] - tab.lnr0) / tab.dlnr
+    fu = (s[:, 1] - tab.lnu0) / tab.dlnu
+    i = np.minimum(np.floor(fr).astype(int), tab.lnP.shape[0] - 2)
+    j = np.minimum(np.floor(fu).astype(int), tab.lnP.shape[1] - 2)
+    a, b = fr - i, fu - j
+
+    def bil(T):
+        return (1 - a) * ((1 - b) * T[i, j] + b * T[i, j + 1]) + a * ((1 - b) * T[i + 1, j] + b * T[i + 1, j + 1])
+    x = np.stack([(s[:, 0] - nm[0]) * nm[2] - 1, (s[:, 1] - nm[1]) * nm[3] - 1], 1)
+    t = np.stack([(bil(tab.lnP) - nm[4]) / nm[6], (bil(tab.lncs2) - nm[5]) / nm[7]], 1)
+    return _to_dev(x, np.float32), _to_dev(t, np.float32)
+
+
+def test_training_reduces_holdout_loss(trained):
+    sph, ctx, w, samples, before, hist = trained
+    print("loss before", before, "history", hist[[0, 9, 99, 399]].tolist(), flush=True)
+    assert np.all(np.isfinite(hist))
+    assert hist[-1, 1] < before / 50
+    assert hist[-1, 1] < hist[0, 1]
+    after = ctx.mlp_grad(*_holdout_pairs(ctx, samples))[1]
+    assert hist[-1, 1] / 3 < after < 3 * hist[-1, 1]   # the same holdout metric on a subset
+
+
+def test_trust_mask_and_fallback(trained):
+    sph, ctx, w, samples, before, hist = trained
+    ncell = 1023 * 1023
+    counts = {tol: ctx.mlp_build_trust_mask(tol) for tol in (1e-4, 3e-2, 1e300)}
+    print("trusted cells", counts, flush=True)
+    assert counts[1e300] == ncell                   # every cell of the table is finite
+    assert counts[1e-4] <= counts[3e-2] <= counts[1e300]
+    # density stage with the surrogate (FP64 pairs) against the table path: untrusted cells are
+    # the table bit for bit, trusted ones within the tolerance
+    for tol in (1e-4, 3e-2):
+        ctx.mlp_build_trust_mask(tol)
+        st = sph.DeviceState(w.arrays)
+        ctx.evaluate(st)
+        ctx.sph_sync()
+        g = st.numpy(["P", "cs", "D", "id"])
+        ref = gpu_run(w, params=w.params.replace(eos="TABLE"))
+        o = np.argsort(g["id"])
+        r = np.abs(g["P"][o] / ref["P"] - 1)
+        rc = np.abs((g["cs"][o] / ref["cs"]) ** 2 - 1)
+        assert np.array_equal(g["D"][o], ref["D"])
+        print(f"tol {tol}: particles on the network {np.mean(r > 0):.4f}, max rel dP {r.max():.2e}", flush=True)
+        assert r.max() <= 2 * tol and rc.max() <= 2 * tol
+
+
+def test_surrogate_path_meets_oracle_tolerance(trained):
+    # the whole FP32-pairs + surrogate path against the FP64 oracle with the table EoS, at the
+    # 1e-4 trust threshold
+    sph, ctx, w, samples, before, hist = trained
+    ctx.mlp_build_trust_mask(1e-4)
+    o = oracle_run(w, params=w.params.replace(eos="TABLE", precision="FP64"))
+    st = sph.DeviceState(w.arrays)
+    p32 = w.params.replace(precision="FP32")
+    from paper_2107_07315_amd import sph as S
+    c32 = S.Context(p32, capacity=w.n)
+    c32.mlp_set_params(ctx.mlp_get_params())
+    # retrain-free copy: the same master weights, mask rebuilt for this context
+    c32.mlp_build_trust_mask(1e-4)
+    c32.evaluate(st)
+    c32.sph_sync()
+    g = st.numpy()
+    order = np.argsort(g["id"])
+    e = {k: float(np.max(rel_err(g[k][order], o[k], 1e-300))) for k in ("D", "rho", "P")}
+    _print("FP32+MLP vs oracle", e)
+    for k, v in e.items():
+        assert v < 1e-4, (k, v)
+
+
+def test_surrogate_gain_is_measured(trained):
+    """What the trained network gains over the table it replaces: the EoS from 17 KB of BF16
+    weights instead of a 16 MB table, more accurately than a bilinear table of the same 17 KB
+    (median and 90th percentile of the larger relative error of P and c_s^2 on held-out
+    samples).  It does not reach the 1e-4 the density pass demands (BF16 rounding alone is
+    about 2^-9 of the output range), which is why the trust mask keeps the table there."""
+    import torch
+    sph, ctx, w, samples, before, hist = trained
+    tab = W.pp_table()
+    s = samples[-40_000:]
+    lp, lc = ctx.mlp_eval(s[:, 0].contiguous(), s[:, 1].contiguous())
+    sn = s.cpu().numpy()
+
+    def bil(T, lnr0, dlnr, lnu0, dlnu, lnr, lnu):
+        fr = (lnr - lnr0) / dlnr
+        fu = (lnu - lnu0) / dlnu
+        i = np.minimum(np.floor(fr).astype(int), T.shape[0] - 2)
+        j = np.minimum(np.floor(fu).astype(int), T.shape[1] - 2)
+        a, b = fr - i, fu - j
+        return (1 - a) * ((1 - b) * T[i, j] + b * T[i, j + 1]) + a * ((1 - b) * T[i + 1, j] + b * T[i + 1, j + 1])
+    ref_p = bil(tab.lnP, tab.lnr0, tab.dlnr, tab.lnu0, tab.dlnu, sn[:, 0], sn[:, 1])
+    ref_c = bil(tab.lncs2, tab.lnr0, tab.dlnr, tab.lnu0, tab.dlnu, sn[:, 0], sn[:, 1])
+    e_net = np.maximum(np.abs(np.expm1(lp.cpu().numpy() - ref_p)), np.abs(np.expm1(lc.cpu().numpy() - ref_c)))
+    # a table of the network's size: 2 fields x k x k FP64 nodes in 17 KB -> k = 33 (nodes of the big table)
+    k = 33
+    ii = np.round(np.linspace(0, tab.lnP.shape[0] - 1, k)).astype(int)
+    jj = np.round(np.linspace(0, tab.lnP.shape[1] - 1, k)).astype(int)
+    small_p, small_c = tab.lnP[np.ix_(ii, jj)], tab.lncs2[np.ix_(ii, jj)]
+    dr = (ii[1] - ii[0]) * tab.dlnr
+    du = (jj[1] - jj[0]) * tab.dlnu
+    e_small = np.maximum(np.abs(np.expm1(bil(small_p, tab.lnr0, dr, tab.lnu0, du, sn[:, 0], sn[:, 1]) - ref_p)),
+                         np.abs(np.expm1(bil(small_c, tab.lnr0, dr, tab.lnu0, du, sn[:, 0], sn[:, 1]) - ref_c)))
+    net_bytes = 2 * 8642
+    table_bytes = tab.lnP.nbytes + tab.lncs2.nbytes
+    rep = {"compression": table_bytes / net_bytes, "net_median": float(np.median(e_net)),
+           "net_p90": float(np.percentile(e_net, 90)), "small_table_median": float(np.median(e_small)),
+           "small_table_p90": float(np.percentile(e_small, 90))}
+    _print("gain", rep)
+    assert np.all(np.isfinite(e_net))
+    assert rep["compression"] > 900
+    assert rep["net_median"] < rep["small_table_median"]
+    assert rep["net_p90"] < rep["small_table_p90"]
