@@ -58,12 +58,36 @@ def measured_traffic(kernel):
     return t["kernels"][kernel]["bytes_per_launch"]
 
 
-def run_variant(w, precision, eos, steps, warmup, timing=True, ctx_kw=None):
+def train_surrogate(w, epochs=400):
+    """Train the EoS network on the GPU (1M seeded samples, 10% held out, batch 4096, lr 1e-3):
+    returns (parameters, seconds, final holdout loss)."""
+    import torch
+
+    from paper_2107_07315_amd import sph
+    from sph_inputs import eos_table as E
+    ctx = sph.Context(w.params.replace(eos="MLP"), capacity=64)
+    ctx.mlp_set_params(E.mlp_init(4))
+    samples = torch.as_tensor(E.mlp_samples(w.params.table, 1_000_000, 4), device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = ctx.mlp_train(samples, 100_000, epochs, 4096, 1e-3)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    params = ctx.mlp_get_params()
+    ctx.close()
+    return params, dt, float(hist[-1, 1])
+
+
+def run_variant(w, precision, eos, steps, warmup, timing=True, ctx_kw=None, mlp=None):
     import torch
 
     from paper_2107_07315_amd import sph
     p = w.params.replace(precision=precision, eos=eos)
     ctx = sph.Context(p, capacity=w.n, **(ctx_kw or {}))
+    trusted = None
+    if mlp is not None:            # (network parameters, trust tolerance)
+        ctx.mlp_set_params(mlp[0])
+        trusted = ctx.mlp_build_trust_mask(mlp[1])
     st = sph.DeviceState(w.arrays)
     ctx.evaluate(st)
     ctx.sph_step(st, w.dt, warmup)
@@ -87,7 +111,7 @@ def run_variant(w, precision, eos, steps, warmup, timing=True, ctx_kw=None):
     del st
     torch.cuda.empty_cache()
     return {"ms_per_step": ms_step, "value": w.n * steps / (t1 - t0), "stages": stages,
-            "pairs": pairs, "max_neighbours": maxc, "stats": stats}
+            "pairs": pairs, "max_neighbours": maxc, "stats": stats, "trusted_cells": trusted}
 
 
 def roofline(res, n, precision):
@@ -116,19 +140,21 @@ def roofline(res, n, precision):
             "other_pass_ms": {k: round(v, 4) for k, v in avg.items() if k != stage}}
 
 
-def cpu_baseline(w):
+def cpu_baseline(w, steps=4):
+    """The FP64 oracle on the host cores: `steps` kick-drift-kick steps of the same star after one
+    untimed evaluation (about 10 s on 16 cores)."""
     import oracle
     orc = oracle.Oracle(w.params.replace(precision="FP64", eos="TABLE"))
     st = oracle.OracleState(w.arrays)
     oracle.run_stages(orc, st)             # rates at t = 0 (untimed)
     t0 = time.perf_counter()
-    oracle.step(orc, st, w.dt, 1)
+    oracle.step(orc, st, w.dt, steps)
     t1 = time.perf_counter()
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(w.n / (t1 - t0), 1), "unit": "particle-updates/s", "cores": cores,
-            "kind": "oracle", "sample": f"1 kick-drift-kick step (neighbours, density, stress rate, "
-            f"forces) of the same {w.n}-particle star in FP64 after one untimed evaluation; "
-            f"{t1 - t0:.1f} s"}
+    return {"value": round(w.n * steps / (t1 - t0), 1), "unit": "particle-updates/s", "cores": cores,
+            "kind": "oracle", "sample": f"{steps} kick-drift-kick steps (neighbours, density, stress rate, "
+            f"forces) of the same {w.n}-particle star in FP64 with the table EoS, after one untimed "
+            f"evaluation; {t1 - t0:.1f} s"}
 
 
 def main():
@@ -137,7 +163,10 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=2_000_000)
-    ap.add_argument("--variants", default="FP64,FP32")
+    ap.add_argument("--variants", default="FP64,FP32,FP32+MLP,FP32+MLP@3e-2",
+                    help="FP64 / FP32 pair sums with the table EoS; +MLP: the EoS network where its "
+                         "trust mask (tolerance 1e-4, or @tol) accepts the table cell")
+    ap.add_argument("--mlp-epochs", type=int, default=400)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference for HBM byte counters)")
@@ -159,12 +188,24 @@ def main():
     from sph_inputs import workloads as W
     w = W.pp_star(args.n, seed=3, eos="TABLE", steps=args.steps)
     variants = [v.strip() for v in args.variants.split(",") if v.strip()]
+    surrogate = None
+    if any("MLP" in v for v in variants):
+        params, secs, hold = train_surrogate(w, args.mlp_epochs)
+        surrogate = {"params": params, "train_seconds": round(secs, 2), "holdout_loss": hold,
+                     "epochs": args.mlp_epochs}
+        print(f"# EoS network trained on the GPU in {secs:.2f} s (holdout loss {hold:.3g})",
+              file=sys.stderr, flush=True)
     res = {}
     for v in variants:
-        res[v] = run_variant(w, v, "TABLE", args.steps, args.warmup)
+        prec = "FP32" if v.startswith("FP32") else "FP64"
+        mlp = None
+        if "MLP" in v:
+            tol = float(v.split("@")[1]) if "@" in v else 1e-4
+            mlp = (surrogate["params"], tol)
+        res[v] = run_variant(w, prec, "MLP" if mlp else "TABLE", args.steps, args.warmup, mlp=mlp)
         print(f"# {v}: {res[v]['ms_per_step']:.3f} ms/step, {res[v]['value']:.4g} particle-updates/s",
               file=sys.stderr, flush=True)
-    head = "FP32" if "FP32" in res else variants[0]
+    head = "FP32+MLP" if "FP32+MLP" in res else ("FP32" if "FP32" in res else variants[0])
     r = res[head]
     out = {
         "metric": "particle-updates/s at 2M particles: FP64 plain vs FP32+EoS-MLP, 1 GPU",
@@ -177,21 +218,25 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 pair sums + f64 integration" if head == "FP32" else "f64",
+        "dtype": {"FP32": "f32 pair sums + f64 integration",
+                  "FP32+MLP": "f32 pair sums + f64 integration + bf16 EoS network"}.get(head, "f64"),
         "data": "synthetic",
         "config": {"workload": f"piecewise-polytrope TOV star, {w.n} particles, Wendland C4 "
                                f"(~100 neighbours), l=2 A=1e-2, plastic + breaking, tabulated EoS",
-                   "n_particles": w.n, "dt": w.dt, "eos": "TABLE", "precision": head},
+                   "n_particles": w.n, "dt": w.dt, "eos": "MLP" if "MLP" in head else "TABLE",
+                   "precision": head},
         "variants": {k: {"value": v["value"], "ms_per_step": v["ms_per_step"],
                          "stages_ms_per_step": {s: round(d["ms_total"] / args.steps, 4)
                                                 for s, d in v["stages"].items()},
                          "pairs": v["pairs"], "max_neighbours": v["max_neighbours"],
-                         "lists": v["stats"]}
+                         "lists": v["stats"], "trusted_cells": v["trusted_cells"]}
                      for k, v in res.items()},
-        "roofline": roofline(r, w.n, head),
+        "roofline": roofline(r, w.n, "FP32" if head.startswith("FP32") else "FP64"),
     }
-    if "FP64" in res and "FP32" in res:
-        out["speedup_fp32_vs_fp64"] = round(res["FP32"]["value"] / res["FP64"]["value"], 3)
+    if surrogate:
+        out["eos_network"] = {k: v for k, v in surrogate.items() if k != "params"}
+    if "FP64" in res:
+        out["speedup_vs_fp64"] = round(r["value"] / res["FP64"]["value"], 3)
         out["roofline_fp64"] = roofline(res["FP64"], w.n, "FP64")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
