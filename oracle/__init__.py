@@ -48,6 +48,7 @@ class OrcParams(ctypes.Structure):
         ("y0_over_E", ctypes.c_double),
         ("break_mode", ctypes.c_int32), ("eps_break", ctypes.c_double),
         ("rotation", ctypes.c_int32),
+        ("nstars", ctypes.c_int32), ("star_info", _dp),
     ]
 
 
@@ -56,7 +57,7 @@ class OrcState(ctypes.Structure):
                 ("x", "y", "z", "vx", "vy", "vz", "u", "h", "S")] + [
         ("type", ctypes.POINTER(ctypes.c_int8)), ("broken", ctypes.POINTER(ctypes.c_uint8))] + [
         (k, _dp) for k in ("D", "rho", "P", "cs", "mu", "Y0", "B", "ax", "ay", "az", "dudt", "dSdt",
-                           "sdot")]
+                           "sdot")] + [("star", ctypes.POINTER(ctypes.c_int32))]
 
 
 _lib = None
@@ -107,7 +108,9 @@ def _check(rc, what):
 class Oracle:
     """Holds an orc_params struct (and the arrays it points to) for one MethodParams."""
 
-    def __init__(self, params):
+    def __init__(self, params, star_info=None):
+        """star_info: optional [nstars, 5] array of (centre x, y, z, particle mass, shear factor)
+        for an ensemble of stars (the state then carries each particle's star)."""
         from sph_inputs.params import (BACKGROUNDS, BREAK_MODES, H_MODES, KERNELS,
                                                         MU_MODES, ROTATIONS, Y0_MODES, YIELD_MODES)
         self.params = params
@@ -142,6 +145,11 @@ class Oracle:
         p.break_mode = BREAK_MODES[params.break_mode]
         p.eps_break = params.eps_break
         p.rotation = ROTATIONS[params.rotation]
+        if star_info is not None:
+            si = np.ascontiguousarray(star_info, dtype=np.float64)
+            assert si.ndim == 2 and si.shape[1] == 5
+            self._keep.append(si)
+            p.nstars, p.star_info = si.shape[0], _ptr(si)
         self.p = p
 
     # -- neighbour sets --------------------------------------------------------------
@@ -178,6 +186,8 @@ class OracleState:
             self.a[k] = np.zeros(n)
         self.a["dSdt"] = np.zeros((6, n))
         self.a["id"] = np.asarray(arrays.get("id", np.arange(n)), dtype=np.int32).copy()
+        if arrays.get("star") is not None:
+            self.a["star"] = np.ascontiguousarray(arrays["star"], dtype=np.int32).copy()
 
     def __getitem__(self, k):
         return self.a[k]
@@ -189,6 +199,7 @@ class OracleState:
             setattr(s, k, _ptr(self.a[k]))
         s.type = _ptr(self.a["type"], ctypes.c_int8)
         s.broken = _ptr(self.a["broken"], ctypes.c_uint8)
+        s.star = _ptr(self.a["star"], ctypes.c_int32) if "star" in self.a else None
         return s
 
 

@@ -281,6 +281,20 @@ int orc_neighbours(const orc_params* p, int64_t n, const double* x, const double
 
 typedef struct { double alpha, dalpha, psi, dpsi, n[3], rbar; } metric_t;
 
+/* particle mass, shear factor and background centre of particle a (its star's in an ensemble) */
+static inline int has_stars(const orc_params* p, const orc_state* st) { return p->nstars > 0 && p->star_info && st->star; }
+static inline double pmass(const orc_params* p, const orc_state* st, int64_t a) {
+  return has_stars(p, st) ? p->star_info[5 * st->star[a] + 3] : p->m;
+}
+static inline double pmufac(const orc_params* p, const orc_state* st, int64_t a) {
+  return has_stars(p, st) ? p->star_info[5 * st->star[a] + 4] : p->mu_pfactor;
+}
+static inline void pcentre(const orc_params* p, const orc_state* st, int64_t a, double c[3]) {
+  c[0] = c[1] = c[2] = 0.0;
+  if (has_stars(p, st))
+    for (int k = 0; k < 3; ++k) c[k] = p->star_info[5 * st->star[a] + k];
+}
+
 static metric_t metric_at(const orc_params* p, double x, double y, double z) {
   metric_t g;
   double rb = sqrt(x * x + y * y + z * z);
@@ -364,22 +378,24 @@ int orc_density(const orc_params* p, orc_state* st, const int64_t* off, const in
     int self_done = 0;
     for (int64_t s = off[a]; s < off[a + 1]; ++s) {
       int64_t b = ids[s];
-      if (!self_done && b > a) { D += p->m * Wself; self_done = 1; }
+      if (!self_done && b > a) { D += pmass(p, st, a) * Wself; self_done = 1; }
       double dx = min_image(st->x[a] - st->x[b], p->periodic, p->box);
       double dy = min_image(st->y[a] - st->y[b], p->periodic, p->box);
       double dz = min_image(st->z[a] - st->z[b], p->periodic, p->box);
       double r = sqrt((dx * dx + dy * dy) + dz * dz);
       double W, F;
       orc_kernel(p->kernel, r, 0.5 * (st->h[a] + st->h[b]), &W, &F);
-      D += p->m * W;
+      D += pmass(p, st, b) * W;
     }
-    if (!self_done) D += p->m * Wself;
+    if (!self_done) D += pmass(p, st, a) * Wself;
     st->D[a] = D;
 
     /* rest-mass density from the computational density D = rho psi^6 W_L */
     double rho = D, hen_fac = 1.0;
     if (p->background == ORC_TOV) {
-      metric_t g = metric_at(p, st->x[a], st->y[a], st->z[a]);
+      double c[3];
+      pcentre(p, st, a, c);
+      metric_t g = metric_at(p, st->x[a] - c[0], st->y[a] - c[1], st->z[a] - c[2]);
       double v2 = st->vx[a] * st->vx[a] + st->vy[a] * st->vy[a] + st->vz[a] * st->vz[a];
       double psi2 = g.psi * g.psi, psi4 = psi2 * psi2, psi6 = psi4 * psi2;
       double vv = psi4 * v2 / (g.alpha * g.alpha);   /* v^i v_i with v^i = xdot^i / alpha */
@@ -398,7 +414,7 @@ int orc_density(const orc_params* p, orc_state* st, const int64_t* off, const in
     st->B[a] = B;
     double mu = 0.0;
     int solid = st->type[a] == 1 && !(st->broken[a] && p->break_mode == ORC_BREAK_FLUIDIZE);
-    if (solid) mu = (p->mu_mode == ORC_MU_PFACTOR) ? p->mu_pfactor * P : p->mu_const;
+    if (solid) mu = (p->mu_mode == ORC_MU_PFACTOR) ? pmufac(p, st, a) * P : p->mu_const;
     st->mu[a] = mu;
     double E = (mu > 0.0) ? 9.0 * B * mu / (3.0 * B + mu) : 0.0;
     st->Y0[a] = (p->y0_mode == ORC_Y0_EFACTOR) ? p->y0_over_E * E : p->y0_const;
@@ -447,8 +463,8 @@ int orc_stress_rate(const orc_params* p, orc_state* st, const int64_t* off, cons
       double vba[3] = {st->vx[b] - va[0], st->vy[b] - va[1], st->vz[b] - va[2]};
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
-          G[i][j] += p->m * vba[i] * g[j];
-          kap += fabs(p->m * vba[i] * g[j]) * kc;
+          G[i][j] += pmass(p, st, b) * vba[i] * g[j];
+          kap += fabs(pmass(p, st, b) * vba[i] * g[j]) * kc;
         }
     }
     if (kappa_G) kappa_G[a] = kap;
@@ -523,25 +539,26 @@ static pairsum_t pair_sums(const orc_params* p, const orc_state* st, int64_t a, 
       double Dbar = 0.5 * (Da + Db);
       Pi = (-p->visc_alpha * cbar * muab + p->visc_beta * muab * muab) / Dbar;
     }
-    double cP = p->m * (pia + pib + Pi);
+    const double mb = pmass(p, st, b);
+    double cP = mb * (pia + pib + Pi);
     double gn = fabs(g[0]) + fabs(g[1]) + fabs(g[2]);
     for (int i = 0; i < 3; ++i) o.AP[i] += cP * g[i];
     /* kappa: sum of the magnitudes of every elementary product (summation condition bound) */
-    o.kP += p->m * (fabs(pia) + fabs(pib) + fabs(Pi)) * gn * kc;
+    o.kP += mb * (fabs(pia) + fabs(pib) + fabs(Pi)) * gn * kc;
     s6_to_m(st->S, n, b, Sb);
     double Da2 = Da * Da, Db2 = Db * Db;
     for (int i = 0; i < 3; ++i) {
       double t = 0.0;
       for (int j = 0; j < 3; ++j) {
         t += (Sa[i][j] / Da2 + Sb[i][j] / Db2) * g[j];
-        o.kS += p->m * (fabs(Sa[i][j]) / Da2 + fabs(Sb[i][j]) / Db2) * fabs(g[j]) * kc;
+        o.kS += mb * (fabs(Sa[i][j]) / Da2 + fabs(Sb[i][j]) / Db2) * fabs(g[j]) * kc;
       }
-      o.AS[i] += p->m * t;
+      o.AS[i] += mb * t;
     }
     double vg = v[0] * g[0] + v[1] * g[1] + v[2] * g[2];
-    double cu = p->m * (pia + 0.5 * Pi) * vg;
+    double cu = mb * (pia + 0.5 * Pi) * vg;
     o.udot += cu;
-    o.kU += p->m * (fabs(pia) + 0.5 * fabs(Pi)) * (fabs(v[0] * g[0]) + fabs(v[1] * g[1]) + fabs(v[2] * g[2])) * kc;
+    o.kU += mb * (fabs(pia) + 0.5 * fabs(Pi)) * (fabs(v[0] * g[0]) + fabs(v[1] * g[1]) + fabs(v[2] * g[2])) * kc;
   }
   return o;
 }
@@ -557,7 +574,9 @@ int orc_forces(const orc_params* p, orc_state* st, const int64_t* off, const int
     double v[3] = {st->vx[a], st->vy[a], st->vz[a]};
     if (p->background == ORC_TOV) {
       /* trajectory equation with zero shift, static isotropic metric gamma_ij = psi^4 delta_ij */
-      metric_t g = metric_at(p, st->x[a], st->y[a], st->z[a]);
+      double c[3];
+      pcentre(p, st, a, c);
+      metric_t g = metric_at(p, st->x[a] - c[0], st->y[a] - c[1], st->z[a] - c[2]);
       double psi2 = g.psi * g.psi, psi4 = psi2 * psi2, psi6 = psi4 * psi2;
       double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
       double WL = 1.0 / sqrt(1.0 - psi4 * v2 / (g.alpha * g.alpha));
@@ -603,7 +622,7 @@ int orc_pair_forces(const orc_params* p, orc_state* st, double* Fout) {
         continue;
       int32_t id = (int32_t)b;
       pairsum_t o = pair_sums(p, st, a, &id, 1);
-      for (int i = 0; i < 3; ++i) F[i] = p->m * (-o.AP[i] + o.AS[i]);
+      for (int i = 0; i < 3; ++i) F[i] = pmass(p, st, a) * (-o.AP[i] + o.AS[i]);
     }
   }
   return ORC_OK;
@@ -744,7 +763,7 @@ int orc_step(const orc_params* p, orc_state* st, double dt, int32_t nsteps, int3
     orc_yield(p, n, st->S, st->Y0);
     apply_breaking(p, st);
     if (p->h_mode == ORC_H_ADAPTIVE)
-      for (int64_t a = 0; a < n; ++a) st->h[a] = p->eta * cbrt(p->m / st->D[a]);
+      for (int64_t a = 0; a < n; ++a) st->h[a] = p->eta * cbrt(pmass(p, st, a) / st->D[a]);
   }
   free(vh);
   return e;

@@ -57,6 +57,11 @@ typedef struct {
   int32_t yield_mode, y0_mode; double y0_const, y0_over_E;
   int32_t break_mode; double eps_break;
   int32_t rotation;
+  /* ensembles: nstars > 0 with star_info[5 * s + k] = (centre x, y, z, particle mass, shear
+   * factor) of star s replaces m and mu_pfactor per particle (state field star), and the
+   * background is evaluated about each particle's star centre */
+  int32_t nstars;
+  const double* star_info;
 } orc_params;
 
 typedef struct {
@@ -67,6 +72,7 @@ typedef struct {
   double *D, *rho, *P, *cs, *mu, *Y0, *B;
   double *ax, *ay, *az, *dudt, *dSdt;            /* dSdt: 6n */
   double *sdot;                                  /* S:epsdot/D (energy source) */
+  const int32_t* star;                           /* star of each particle (ensembles), or NULL */
 } orc_state;
 
 /* Neighbour sets N(a) = { b != a : |x_a - x_b|^2 < (h_a + h_b)^2 } (section "Solid SPH

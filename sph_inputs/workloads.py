@@ -146,3 +146,52 @@ def pp_star(N: int = 2_000_000, seed: int = 3, precision: str = "FP64", eos: str
                      1.8, pp_table(), steps, f"ppstar{N}")
     w.params = w.params.replace(eos=eos)
     return w
+
+
+def ensemble(nstars: int = 64, total: int = 8_000_000, seed: int = 5, nmin: int = 20_000, nmax: int = 500_000,
+             precision: str = "FP32", steps: int = 100, gap: float = 1.2):
+    """Independent piecewise-polytrope stars of uneven sizes in one particle set (tabulated EoS,
+    Wendland C4 with about 100 neighbours, plasticity and breaking as in pp_star).
+
+    Sizes are log-uniform in [nmin, nmax], rescaled once to `total` and clipped to the range;
+    the crust shear factor is uniform in [0.005, 0.02], the perturbation amplitude uniform in
+    [1e-3, 1e-2], l = 0 or 2 with probability 1/2 each.  Stars sit on a cubic grid far enough
+    apart that no particle lies within `gap` times the largest support of a particle of another
+    star.  Returns a Workload whose arrays carry `star` and whose star_params holds, per star,
+    (centre x, y, z, particle mass, shear factor); dt is the smallest star's CFL step."""
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(math.log(nmin), math.log(nmax), nstars))
+    sizes = np.clip(np.rint(sizes * total / sizes.sum()), nmin, nmax).astype(np.int64)
+    mus = rng.uniform(0.005, 0.02, nstars)
+    amps = rng.uniform(1e-3, 1e-2, nstars)
+    ells = rng.choice([0, 2], nstars)
+    bg = pp_background()
+    table = pp_table()
+    stars = [_star_common(bg, int(sizes[s]), seed * 1000 + s, "WC4", ETA_100, int(ells[s]), float(amps[s]),
+                          float(mus[s]), True, precision, "TABLE", 1.8, table, steps, f"ens{s}")
+             for s in range(nstars)]
+    hmax = max(float(w.arrays["h"].max()) for w in stars)
+    spacing = 2.0 * bg.Rbar + gap * 2.0 * hmax
+    side = int(math.ceil(nstars ** (1.0 / 3.0)))
+    keys = ("x", "y", "z", "vx", "vy", "vz", "u", "h", "type", "broken")
+    parts = {k: [] for k in keys}
+    S, star, info = [], [], []
+    for s, w in enumerate(stars):
+        c = np.array([s % side, (s // side) % side, s // (side * side)], np.float64) * spacing
+        a = w.arrays
+        for k in keys:
+            v = a[k]
+            if k in ("x", "y", "z"):
+                v = v + c["xyz".index(k)]
+            parts[k].append(v)
+        S.append(a["S"])
+        star.append(np.full(w.n, s, np.int32))
+        info.append([c[0], c[1], c[2], w.params.m, float(mus[s])])
+    arrays = {k: np.concatenate(v) for k, v in parts.items()}
+    arrays["S"] = np.concatenate(S, axis=1)
+    arrays["star"] = np.concatenate(star)
+    arrays["id"] = np.arange(arrays["x"].shape[0], dtype=np.int32)
+    dt = min(w.dt for w in stars)
+    return Workload(f"ensemble{nstars}", stars[0].params, arrays, dt, steps, bg,
+                    star_offsets=np.concatenate([[0], np.cumsum(sizes)]),
+                    star_params=np.asarray(info, np.float64))

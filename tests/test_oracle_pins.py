@@ -504,3 +504,34 @@ def test_redshift_formula_arithmetic():
     rS = 2 * 1.4 * 1.0 / KM     # km
     f = g["redshift"]["f_cal_Hz"] * math.sqrt(1 - rS / 14.2)
     assert abs(f - g["redshift"]["f_obs_Hz"]) < 0.15
+
+
+def test_ensemble_of_separated_stars_equals_single_stars():
+    # an ensemble (per-star particle mass, shear factor and background centre) of stars far
+    # apart is the same computation as each star on its own: no pair crosses stars, and each
+    # star's fields match its single-star run up to the rounding of the shifted positions
+    from sph_inputs import workloads as W
+    w = W.ensemble(3, 6000, seed=7, nmin=1000, nmax=3000)
+    orc = oracle.Oracle(w.params, star_info=w.star_params)
+    st = oracle.OracleState(w.arrays)
+    k = oracle.run_stages(orc, st)
+    off, ids = k["offsets"], k["ids"]
+    star = w.arrays["star"]
+    src = np.repeat(np.arange(w.n), np.diff(off))
+    assert np.array_equal(star[src], star[ids])
+    for s in range(3):
+        lo, hi = int(w.star_offsets[s]), int(w.star_offsets[s + 1])
+        cx, cy, cz, m, mu = w.star_params[s]
+        arr = {key: (v[..., lo:hi] if np.ndim(v) == 2 else v[lo:hi]).copy() for key, v in w.arrays.items()
+               if key != "star"}
+        arr["x"] -= cx
+        arr["y"] -= cy
+        arr["z"] -= cz
+        one = oracle.OracleState(arr)
+        oracle.run_stages(oracle.Oracle(w.params.replace(m=m, mu_pfactor=mu)), one)
+        for f in ("D", "rho", "P", "cs", "mu"):
+            r = np.max(np.abs(st[f][lo:hi] - one[f]) / np.maximum(np.abs(one[f]), 1e-300))
+            assert r < 1e-12, (s, f, r)
+        for f in ("ax", "ay", "az", "dudt"):
+            r = np.max(np.abs(st[f][lo:hi] - one[f])) / np.max(np.abs(one[f]))
+            assert r < 1e-9, (s, f, r)
