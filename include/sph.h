@@ -177,6 +177,14 @@ sph_status sph_forces(sph_ctx* ctx, sph_state* st);
  * (section "Solid SPH Equations"), and the adaptive smoothing length. */
 sph_status sph_step(sph_ctx* ctx, sph_state* st, double dt, int32_t nsteps);
 
+/* Ensembles of independent stars in one particle set: star_info (host) holds nstars rows of
+ * (centre x, y, z, particle mass, shear factor); each particle's star (state field `star`,
+ * required while an ensemble is set) selects its mass, its crust shear factor (mu = factor * P)
+ * and the centre about which the fixed background is evaluated.  Pair sums take the particle's
+ * own star mass, so stars must lie farther apart than any particle's support (no pair crosses
+ * stars).  nstars = 0 returns to a single star.  Waits; invalidates the stage order. */
+sph_status sph_ensemble_set(sph_ctx* ctx, int32_t nstars, const double* star_info);
+
 /* Wait for the context's stream; return and clear the first latched device error. */
 sph_status sph_sync(sph_ctx* ctx);
 

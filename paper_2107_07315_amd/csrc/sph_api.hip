@@ -7,7 +7,7 @@
 
 namespace {
 
-constexpr int64_t kMaxCells = int64_t(1) << 25;
+constexpr int64_t kMaxCells = int64_t(1) << 26;
 
 template <typename T>
 sph_status dalloc(T** p, size_t count) {
@@ -298,6 +298,31 @@ sph_status sph_step(sph_ctx* c, sph_state* st, double dt, int32_t nsteps) {
     timer_end(c, TIMER_KDK);
   }
   c->gen = 4;
+  return SPH_OK;
+}
+
+sph_status sph_ensemble_set(sph_ctx* c, int32_t nstars, const double* star_info) {
+  if (!c || nstars < 0 || (nstars > 0 && !star_info)) return SPH_E_ARG;
+  std::vector<StarInfo> h((size_t)nstars);
+  for (int32_t s = 0; s < nstars; ++s) {
+    const double* q = star_info + 5 * (int64_t)s;
+    if (!(q[3] > 0.0) || !(q[4] >= 0.0)) return SPH_E_ARG;
+    h[s] = StarInfo{q[0], q[1], q[2], q[3], q[4], {0.0, 0.0, 0.0}};
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (c->stars) (void)hipFree(c->stars);
+  c->stars = nullptr;
+  c->nstars = 0;
+  if (nstars > 0) {
+    if (hipMalloc((void**)&c->stars, sizeof(StarInfo) * nstars) != hipSuccess) {
+      c->stars = nullptr;
+      return SPH_E_OOM;
+    }
+    HIP_TRY(hipMemcpy(c->stars, h.data(), sizeof(StarInfo) * nstars, hipMemcpyHostToDevice));
+    c->nstars = nstars;
+  }
+  c->gen = 0;
+  ++c->graph_epoch;
   return SPH_OK;
 }
 

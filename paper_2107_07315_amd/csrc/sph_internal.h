@@ -296,6 +296,7 @@ struct sph_ctx {
   int device;
   int32_t gen;          // stage order: 1 cells, 2 density, 3 stress, 4 forces
   bool lists_valid;     // candidate lists match the current n, order and parameters
+  uint32_t graph_epoch; // bumped whenever a pointer or parameter that kernels capture changes
   uint32_t check_id;    // id of the last drift test (written to drift_flag by violators)
   uint32_t* drift_flag; // device word: largest check id that saw a skin violation
   uint32_t* drift_host; // pinned host copy

@@ -21,7 +21,7 @@ EXPORTED = ("sph_create", "sph_destroy", "sph_set_params", "sph_build_cells", "s
             "sph_stress_rate", "sph_forces", "sph_step", "sph_sync", "sph_export_neighbours",
             "sph_status_string", "sph_set_timing", "sph_get_timing", "sph_neighbour_stats",
             "sph_mlp_set_params", "sph_mlp_get_params", "sph_mlp_get_norm", "sph_mlp_train", "sph_mlp_grad",
-            "sph_mlp_eval", "sph_mlp_build_trust_mask")
+            "sph_mlp_eval", "sph_mlp_build_trust_mask", "sph_ensemble_set")
 MLP_NPARAM = 8642
 
 _dp = ctypes.c_void_p
@@ -100,6 +100,7 @@ def load():
     L.sph_mlp_grad.argtypes = [vp, vp, vp, ctypes.c_int64, vp, ctypes.POINTER(ctypes.c_double)]
     L.sph_mlp_eval.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp]
     L.sph_mlp_build_trust_mask.argtypes = [vp, ctypes.c_double, ctypes.POINTER(ctypes.c_int64)]
+    L.sph_ensemble_set.argtypes = [vp, ctypes.c_int32, vp]
     _lib = L
     return L
 
@@ -119,6 +120,8 @@ class DeviceState:
     F64 = ("x", "y", "z", "vx", "vy", "vz", "u", "h", "D", "rho", "P", "cs", "ax", "ay", "az", "dudt")
 
     def __init__(self, arrays: dict, device="cuda", star=None):
+        if star is None:
+            star = arrays.get("star")
         import torch
         n = int(np.asarray(arrays["x"]).shape[0])
         self.n = n
@@ -270,6 +273,15 @@ class Context:
         _check(self.lib.sph_neighbour_stats(self.h, ctypes.byref(s)), "sph_neighbour_stats")
         return {k: getattr(s, k) for k in ("pairs", "max_count", "tiles", "union_total", "candidates",
                                            "rebuilds")}
+
+    def sph_ensemble_set(self, star_info):
+        """star_info: [nstars, 5] rows of (centre x, y, z, particle mass, shear factor)."""
+        si = np.ascontiguousarray(star_info, np.float64)
+        if si.size == 0:
+            _check(self.lib.sph_ensemble_set(self.h, 0, None), "sph_ensemble_set")
+            return
+        assert si.ndim == 2 and si.shape[1] == 5
+        _check(self.lib.sph_ensemble_set(self.h, si.shape[0], si.ctypes.data), "sph_ensemble_set")
 
     # EoS surrogate network ------------------------------------------------------------------
     def mlp_set_params(self, params):

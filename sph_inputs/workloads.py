@@ -149,9 +149,11 @@ def pp_star(N: int = 2_000_000, seed: int = 3, precision: str = "FP64", eos: str
 
 
 def ensemble(nstars: int = 64, total: int = 8_000_000, seed: int = 5, nmin: int = 20_000, nmax: int = 500_000,
-             precision: str = "FP32", steps: int = 100, gap: float = 1.2):
-    """Independent piecewise-polytrope stars of uneven sizes in one particle set (tabulated EoS,
-    Wendland C4 with about 100 neighbours, plasticity and breaking as in pp_star).
+             precision: str = "FP32", steps: int = 100, gap: float = 1.2, kind: str = "pp"):
+    """Independent stars of uneven sizes in one particle set: kind "pp" for the piecewise-polytrope
+    star with the tabulated EoS (as pp_star; its outer 1 km crust holds 0.07% of the mass),
+    "gamma2" for the Gamma = 2 polytrope with the Gamma-law EoS (crust 2.9% of the mass); both
+    with Wendland C4, about 100 neighbours, plasticity and breaking.
 
     Sizes are log-uniform in [nmin, nmax], rescaled once to `total` and clipped to the range;
     the crust shear factor is uniform in [0.005, 0.02], the perturbation amplitude uniform in
@@ -165,10 +167,14 @@ def ensemble(nstars: int = 64, total: int = 8_000_000, seed: int = 5, nmin: int 
     mus = rng.uniform(0.005, 0.02, nstars)
     amps = rng.uniform(1e-3, 1e-2, nstars)
     ells = rng.choice([0, 2], nstars)
-    bg = pp_background()
-    table = pp_table()
+    if kind == "pp":
+        bg, eos, gamma, table = pp_background(), "TABLE", 1.8, pp_table()
+    elif kind == "gamma2":
+        bg, eos, gamma, table = gamma2_background(), "GAMMA_LAW", 2.0, None
+    else:
+        raise ValueError(kind)
     stars = [_star_common(bg, int(sizes[s]), seed * 1000 + s, "WC4", ETA_100, int(ells[s]), float(amps[s]),
-                          float(mus[s]), True, precision, "TABLE", 1.8, table, steps, f"ens{s}")
+                          float(mus[s]), True, precision, eos, gamma, table, steps, f"ens{s}")
              for s in range(nstars)]
     hmax = max(float(w.arrays["h"].max()) for w in stars)
     spacing = 2.0 * bg.Rbar + gap * 2.0 * hmax

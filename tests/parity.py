@@ -16,6 +16,8 @@ def gpu_run(w, steps=0, precision=None, ctx_kw=None, params=None, lists=None):
     if precision:
         p = p.replace(precision=precision)
     ctx = sph.Context(p, capacity=w.n, **(ctx_kw or {}))
+    if w.star_params is not None:
+        ctx.sph_ensemble_set(w.star_params)
     st = sph.DeviceState(w.arrays)
     ctx.evaluate(st)
     if steps:
@@ -41,7 +43,7 @@ def gpu_run(w, steps=0, precision=None, ctx_kw=None, params=None, lists=None):
 
 
 def oracle_run(w, steps=0, mode=oracle.GRID, params=None):
-    orc = oracle.Oracle(params or w.params)
+    orc = oracle.Oracle(params or w.params, star_info=w.star_params)
     st = oracle.OracleState(w.arrays)
     k = oracle.run_stages(orc, st, mode, want_kappa=True)
     if steps:
