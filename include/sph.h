@@ -121,6 +121,11 @@ typedef struct {
                            /*   last build.  0: rebuild at every evaluation.  Values in (0,     */
                            /*   1e-4) act as 0; periodic runs clip s so that (1+s)(h_a+h_b)     */
                            /*   stays below half the box.                                       */
+  int32_t pass_blocks;     /* workgroups of the pair passes: 0 = one per tile (at most 65536),  */
+                           /*   else a persistent grid of that many (rounded up to 8) that     */
+                           /*   loops over the tiles                                            */
+  int32_t graph;           /* sph_step: 1 = replay captured HIP graphs of each step's kernels  */
+                           /*   (needs skin > 0; stage timers are not recorded)                */
 } sph_params;
 
 /* Neighbour-list statistics (sph_neighbour_stats). */
@@ -184,6 +189,20 @@ sph_status sph_step(sph_ctx* ctx, sph_state* st, double dt, int32_t nsteps);
  * own star mass, so stars must lie farther apart than any particle's support (no pair crosses
  * stars).  nstars = 0 returns to a single star.  Waits; invalidates the stage order. */
 sph_status sph_ensemble_set(sph_ctx* ctx, int32_t nstars, const double* star_info);
+
+/* Launch autotuner: times `steps_per_trial` steps of copies of the state (the caller's state is
+ * not changed) under candidate settings of pass_blocks, tile_cut and skin, one parameter at a
+ * time (coordinate descent from the current settings), and keeps the fastest.  The context then
+ * needs a new evaluation (sph_build_cells ...) before sph_step.  Waits. */
+typedef struct {
+  int32_t pass_blocks;
+  int32_t trials;          /* configurations timed                                              */
+  double tile_cut, skin;
+  double ms_per_step;      /* of the chosen configuration                                       */
+  double ms_per_step_start;/* of the starting configuration                                     */
+} sph_tune_result;
+sph_status sph_autotune(sph_ctx* ctx, const sph_state* st, double dt, int32_t steps_per_trial,
+                        sph_tune_result* out);
 
 /* Wait for the context's stream; return and clear the first latched device error. */
 sph_status sph_sync(sph_ctx* ctx);

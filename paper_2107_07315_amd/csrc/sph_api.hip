@@ -3,6 +3,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <chrono>
+
 #include "sph_internal.h"
 
 namespace {
@@ -34,6 +36,7 @@ sph_status check_params(const sph_params* p) {
   if (p->cell_div < 0 || p->cell_div > 4) return SPH_E_ARG;
   if (!(p->tile_cut >= 0.0) || p->tile_cut > 64.0) return SPH_E_ARG;
   if (!(p->skin >= 0.0) || p->skin > 1.0) return SPH_E_ARG;
+  if (p->pass_blocks < 0 || p->pass_blocks > 65536 || p->graph < 0 || p->graph > 1) return SPH_E_ARG;
   return SPH_OK;
 }
 
@@ -101,6 +104,8 @@ void sph_destroy(sph_ctx* c) {
   mlp_free(c);
   for (auto& t : c->timers)
     for (hipEvent_t e : t.ev) (void)hipEventDestroy(e);
+  if (c->g_eval) (void)hipGraphExecDestroy(c->g_eval);
+  if (c->g_drift) (void)hipGraphExecDestroy(c->g_drift);
   c->~sph_ctx();
   free(c);
 }
@@ -124,6 +129,7 @@ sph_status sph_create(const sph_params* params, void* stream, int64_t capacity, 
   c->upool = (int64_t)((capacity + 63) / 64 * 64) * 128;
   if (c->upool > (int64_t)0xffffffffll) c->upool = (int64_t)0xffffffffll;
   (void)hipGetDevice(&c->device);
+  c->check_id = 1;   // the drift kernel writes this to the flag, which is cleared before each test
   const int64_t cap = capacity;
   const int64_t capw = (cap + 63) / 64 * 64;
   c->capw = capw;
@@ -179,6 +185,7 @@ sph_status sph_set_params(sph_ctx* c, const sph_params* params) {
   c->p = *params;
   c->gen = 0;
   c->lists_valid = false;
+  ++c->graph_epoch;
   return SPH_OK;
 }
 
@@ -188,7 +195,7 @@ sph_status sph_set_params(sph_ctx* c, const sph_params* params) {
 static sph_status read_drift(sph_ctx* c, bool* violated) {
   HIP_TRY(hipMemcpyAsync(c->drift_host, c->drift_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
-  *violated = *c->drift_host == c->check_id;
+  *violated = *c->drift_host != 0u;
   return SPH_OK;
 }
 
@@ -215,8 +222,7 @@ sph_status sph_build_cells(sph_ctx* c, sph_state* st) {
   if (st->n == 0) { c->gen = 1; return SPH_OK; }
   bool stale = !c->lists_valid || !(c->p.skin > 0.0);
   if (!stale) {
-    ++c->check_id;
-    if ((e = launch_drift_check(c, st)) || (e = read_drift(c, &stale))) return e;
+    if ((e = launch_flag_clear(c)) || (e = launch_drift_check(c, st)) || (e = read_drift(c, &stale))) return e;
   }
   if (stale) {
     if ((e = rebuild(c, st))) return e;
@@ -269,15 +275,88 @@ sph_status sph_forces(sph_ctx* c, sph_state* st) {
   return SPH_OK;
 }
 
+}  // extern "C"
+
+// Captures the two graphs of a step: g_drift = flag clear, kick-drift with the skin test and the
+// flag copy to pinned host memory; g_eval = density, stress rate, forces and the final kick.
+static sph_status capture_step(sph_ctx* c, sph_state* st, double dt) {
+  if (c->g_eval) (void)hipGraphExecDestroy(c->g_eval);
+  if (c->g_drift) (void)hipGraphExecDestroy(c->g_drift);
+  c->g_eval = c->g_drift = nullptr;
+  const int32_t timing = c->timing;
+  c->timing = 0;   // no event records inside the graphs
+  sph_status e = SPH_OK;
+  for (int which = 0; which < 2 && !e; ++which) {
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      e = SPH_E_HIP;
+      break;
+    }
+    sph_status le = SPH_OK;
+    if (which == 0) {
+      if (!le) le = launch_density(c, st);
+      if (!le) le = launch_stress(c, st);
+      if (!le) le = launch_forces(c, st);
+      if (!le) le = launch_kick_final(c, st, dt);
+    } else {
+      if (!le) le = launch_flag_clear(c);
+      if (!le) le = launch_kick_drift(c, st, dt, true);
+      if (!le && hipMemcpyAsync(c->drift_host, c->drift_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream) !=
+                     hipSuccess)
+        le = SPH_E_HIP;
+    }
+    const hipError_t ee = hipStreamEndCapture(c->stream, &g);
+    if (le || ee != hipSuccess) e = le ? le : SPH_E_HIP;
+    hipGraphExec_t x = nullptr;
+    if (!e && hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) e = SPH_E_HIP;
+    if (g) (void)hipGraphDestroy(g);
+    if (!e) (which == 0 ? c->g_eval : c->g_drift) = x;
+  }
+  c->timing = timing;
+  if (!e) {
+    c->g_x = st->x;
+    c->g_n = st->n;
+    c->g_dt = dt;
+    c->g_epoch = c->graph_epoch;
+  }
+  return e;
+}
+
+// sph_step with graph replay: per step, g_drift, one word read back, an eager candidate-list
+// rebuild if the skin test failed (re-capturing if that moved a buffer), then g_eval.
+static sph_status step_graphs(sph_ctx* c, sph_state* st, double dt, int32_t nsteps) {
+  sph_status e;
+  for (int32_t k = 0; k < nsteps; ++k) {
+    if (!c->g_eval || c->g_x != st->x || c->g_n != st->n || c->g_dt != dt || c->g_epoch != c->graph_epoch)
+      if ((e = capture_step(c, st, dt))) return e;
+    HIP_TRY(hipGraphLaunch(c->g_drift, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (*c->drift_host != 0u) {
+      if ((e = rebuild(c, st))) return e;
+      if (c->g_epoch != c->graph_epoch && (e = capture_step(c, st, dt))) return e;
+    }
+    HIP_TRY(hipGraphLaunch(c->g_eval, c->stream));
+  }
+  return SPH_OK;
+}
+
+extern "C" {
+
 sph_status sph_step(sph_ctx* c, sph_state* st, double dt, int32_t nsteps) {
   sph_status e = check_state(c, st);
   if (e) return e;
   if (!(dt > 0.0) || nsteps < 0) return SPH_E_ARG;
   if (c->gen < 4 || st->n != c->n) return SPH_E_ORDER;
   if (st->n == 0) return SPH_OK;
+  if (c->p.graph && !c->stream) return SPH_E_ARG;   // the legacy default stream cannot be captured
+  if (c->p.graph && c->p.skin > 0.0 && c->lists_valid) {
+    e = step_graphs(c, st, dt, nsteps);
+    if (!e) c->gen = 4;
+    return e;
+  }
   for (int32_t k = 0; k < nsteps; ++k) {
     const bool check = c->lists_valid && c->p.skin > 0.0;
-    if (check) ++c->check_id;
+    if (check && (e = launch_flag_clear(c))) return e;
     timer_begin(c, TIMER_KDK);
     if ((e = launch_kick_drift(c, st, dt, check))) return e;
     timer_end(c, TIMER_KDK);
@@ -298,6 +377,134 @@ sph_status sph_step(sph_ctx* c, sph_state* st, double dt, int32_t nsteps) {
     timer_end(c, TIMER_KDK);
   }
   c->gen = 4;
+  return SPH_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// A device copy of a state for the autotuner's trial runs.
+struct StateCopy {
+  std::vector<void*> bufs;
+  sph_state st;
+  ~StateCopy() {
+    for (void* b : bufs) (void)hipFree(b);
+  }
+  template <typename T>
+  sph_status alloc(T** p, size_t count) {
+    if (hipMalloc((void**)p, sizeof(T) * (count ? count : 1)) != hipSuccess) {
+      *p = nullptr;
+      return SPH_E_OOM;
+    }
+    bufs.push_back(*p);
+    return SPH_OK;
+  }
+  sph_status make(const sph_state* src) {
+    const size_t n = (size_t)src->n;
+    st = *src;
+    double** d64[] = {&st.x, &st.y, &st.z, &st.vx, &st.vy, &st.vz, &st.u, &st.h, &st.D, &st.rho, &st.P, &st.cs,
+                      &st.ax, &st.ay, &st.az, &st.dudt};
+    sph_status e;
+    for (double** p : d64)
+      if ((e = alloc(p, n))) return e;
+    if ((e = alloc(&st.S, 6 * n)) || (e = alloc(&st.dSdt, 6 * n)) || (e = alloc(&st.type, n)) ||
+        (e = alloc(&st.broken, n)) || (e = alloc(&st.id, n)))
+      return e;
+    if (src->star && (e = alloc(&st.star, n))) return e;
+    return SPH_OK;
+  }
+  sph_status load(const sph_state* src, hipStream_t s) {
+    const size_t n = (size_t)src->n;
+    const double* a[] = {src->x, src->y, src->z, src->vx, src->vy, src->vz, src->u, src->h};
+    double* b[] = {st.x, st.y, st.z, st.vx, st.vy, st.vz, st.u, st.h};
+    for (int k = 0; k < 8; ++k) HIP_TRY(hipMemcpyAsync(b[k], a[k], 8 * n, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(st.S, src->S, 48 * n, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(st.type, src->type, n, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(st.broken, src->broken, n, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(st.id, src->id, 4 * n, hipMemcpyDeviceToDevice, s));
+    if (src->star) HIP_TRY(hipMemcpyAsync(st.star, src->star, 4 * n, hipMemcpyDeviceToDevice, s));
+    return SPH_OK;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+sph_status sph_autotune(sph_ctx* c, const sph_state* st, double dt, int32_t steps, sph_tune_result* out) {
+  sph_status e = check_state(c, st);
+  if (e) return e;
+  if (!out || !(dt > 0.0) || steps < 1 || st->n == 0) return SPH_E_ARG;
+  StateCopy cp;
+  if ((e = cp.make(st))) return e;
+  const int32_t timing = c->timing;
+  c->timing = 0;
+  auto trial = [&](const sph_params& p, double* ms) -> sph_status {
+    c->p = p;
+    c->lists_valid = false;
+    c->gen = 0;
+    ++c->graph_epoch;
+    sph_status te;
+    if ((te = cp.load(st, c->stream)) || (te = sph_build_cells(c, &cp.st)) || (te = sph_density(c, &cp.st)) ||
+        (te = sph_stress_rate(c, &cp.st)) || (te = sph_forces(c, &cp.st)) || (te = sph_step(c, &cp.st, dt, 2)))
+      return te;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const auto t0 = std::chrono::steady_clock::now();
+    if ((te = sph_step(c, &cp.st, dt, steps))) return te;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const auto t1 = std::chrono::steady_clock::now();
+    *ms = std::chrono::duration<double, std::milli>(t1 - t0).count() / steps;
+    return sph_sync(c);
+  };
+  sph_params best = c->p;
+  if (best.tile_cut <= 0.0) best.tile_cut = 6.0;
+  double best_ms = 0.0;
+  int32_t trials = 1;
+  if ((e = trial(best, &best_ms))) {
+    c->timing = timing;
+    return e;
+  }
+  const double start_ms = best_ms;
+  // coordinate descent: workgroup schedule of the pair passes, tile cut, skin
+  for (int dim = 0; dim < 3 && !e; ++dim) {
+    const double vals[3][4] = {{0, 1024, 4096, 16384}, {4, 6, 8, -1}, {0.05, 0.1, 0.15, -1}};
+    const sph_params base = best;
+    for (int k = 0; k < 4 && !e; ++k) {
+      const double v = vals[dim][k];
+      if (v < 0) continue;
+      sph_params p = base;
+      if (dim == 0) {
+        if ((int32_t)v == base.pass_blocks) continue;
+        p.pass_blocks = (int32_t)v;
+      } else if (dim == 1) {
+        if (v == base.tile_cut) continue;
+        p.tile_cut = v;
+      } else {
+        if (v == base.skin || base.skin == 0.0) continue;
+        p.skin = v;
+      }
+      double ms;
+      e = trial(p, &ms);
+      ++trials;
+      if (!e && ms < best_ms) {
+        best_ms = ms;
+        best = p;
+      }
+    }
+  }
+  c->timing = timing;
+  c->p = best;
+  c->lists_valid = false;
+  c->gen = 0;
+  ++c->graph_epoch;
+  if (e) return e;
+  out->pass_blocks = best.pass_blocks;
+  out->tile_cut = best.tile_cut;
+  out->skin = best.skin;
+  out->trials = trials;
+  out->ms_per_step = best_ms;
+  out->ms_per_step_start = start_ms;
   return SPH_OK;
 }
 

@@ -823,6 +823,7 @@ static sph_status ensure_pool(sph_ctx* c) {
     return SPH_E_OOM;
   }
   c->upool = want;
+  ++c->graph_epoch;   // captured kernels hold the old pool pointer
   return SPH_OK;
 }
 

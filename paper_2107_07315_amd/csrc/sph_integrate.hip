@@ -149,6 +149,16 @@ KdkArgs make_kdk(sph_ctx* c, sph_state* st, double dt) {
 
 }  // namespace
 
+namespace {
+__global__ void k_flag_clear(uint32_t* f) { *f = 0u; }   // a kernel, not a memset: graph-safe
+}  // namespace
+
+sph_status launch_flag_clear(sph_ctx* c) {
+  hipLaunchKernelGGL(k_flag_clear, dim3(1), dim3(1), 0, c->stream, c->drift_flag);
+  HIP_TRY(hipGetLastError());
+  return SPH_OK;
+}
+
 sph_status launch_kick_drift(sph_ctx* c, sph_state* st, double dt, bool check) {
   KdkArgs K = make_kdk(c, st, dt);
   if (check) K.flag = c->drift_flag;

@@ -297,6 +297,12 @@ struct sph_ctx {
   int32_t gen;          // stage order: 1 cells, 2 density, 3 stress, 4 forces
   bool lists_valid;     // candidate lists match the current n, order and parameters
   uint32_t graph_epoch; // bumped whenever a pointer or parameter that kernels capture changes
+  hipGraphExec_t g_eval;   // captured density, stress rate, forces, final kick
+  hipGraphExec_t g_drift;  // captured flag clear, kick-drift with skin test, flag copy
+  const double* g_x;       // key of the captured graphs: state, size, dt, epoch
+  int64_t g_n;
+  double g_dt;
+  uint32_t g_epoch;
   uint32_t check_id;    // id of the last drift test (written to drift_flag by violators)
   uint32_t* drift_flag; // device word: largest check id that saw a skin violation
   uint32_t* drift_host; // pinned host copy
@@ -361,6 +367,7 @@ struct sph_ctx {
 sph_status sph_sort_pairs(sph_ctx* c, uint32_t* keys, uint32_t* vals, int64_t n);
 sph_status sph_rebin(sph_ctx* c, sph_state* st);
 sph_status launch_drift_check(sph_ctx* c, sph_state* st);
+sph_status launch_flag_clear(sph_ctx* c);
 sph_status launch_density(sph_ctx* c, sph_state* st);
 sph_status launch_stress(sph_ctx* c, sph_state* st);
 sph_status launch_forces(sph_ctx* c, sph_state* st);

@@ -518,6 +518,7 @@ sph_status sph_mlp_set_params(sph_ctx* c, const float* params) {
   }
   s->step = 0;
   s->loaded = true;
+  ++c->graph_epoch;
   return SPH_OK;
 }
 
@@ -616,6 +617,7 @@ sph_status sph_mlp_train(sph_ctx* c, const double* samples, int64_t n, int64_t n
     s->trust = nullptr;
     s->trust_cells = 0;
   }
+  ++c->graph_epoch;
   return e;
 }
 
@@ -655,6 +657,7 @@ sph_status sph_mlp_build_trust_mask(sph_ctx* c, double tol, int64_t* trusted_cel
   }
   (void)hipFree(cnt);
   s->trust_cells = (int64_t)h;
+  ++c->graph_epoch;
   if (trusted_cells) *trusted_cells = (int64_t)h;
   return e;
 }

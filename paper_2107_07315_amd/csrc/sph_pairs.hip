@@ -695,7 +695,15 @@ static void dispatch_cfg(int kernel, int periodic, Fn&& f) {
   }
 }
 
-static dim3 pass_grid(const sph_ctx* c) { return dim3((unsigned)(c->cap_tiles < 65536 ? c->cap_tiles : 65536)); }
+// one workgroup per tile (up to 65536), or a persistent grid of pass_blocks (a multiple of the
+// XCD count) that loops over the tiles
+static dim3 pass_grid(const sph_ctx* c) {
+  if (c->p.pass_blocks > 0) {
+    const int64_t b = ((int64_t)c->p.pass_blocks + SPH_XCD - 1) / SPH_XCD * SPH_XCD;
+    return dim3((unsigned)(b < 65536 ? b : 65536));
+  }
+  return dim3((unsigned)(c->cap_tiles < 65536 ? c->cap_tiles : 65536));
+}
 
 sph_status launch_density(sph_ctx* c, sph_state* st) {
   PassArgs A = make_args(c, st);

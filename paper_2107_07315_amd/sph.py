@@ -21,7 +21,7 @@ EXPORTED = ("sph_create", "sph_destroy", "sph_set_params", "sph_build_cells", "s
             "sph_stress_rate", "sph_forces", "sph_step", "sph_sync", "sph_export_neighbours",
             "sph_status_string", "sph_set_timing", "sph_get_timing", "sph_neighbour_stats",
             "sph_mlp_set_params", "sph_mlp_get_params", "sph_mlp_get_norm", "sph_mlp_train", "sph_mlp_grad",
-            "sph_mlp_eval", "sph_mlp_build_trust_mask", "sph_ensemble_set")
+            "sph_mlp_eval", "sph_mlp_build_trust_mask", "sph_ensemble_set", "sph_autotune")
 MLP_NPARAM = 8642
 
 _dp = ctypes.c_void_p
@@ -42,7 +42,14 @@ class SphParams(ctypes.Structure):
         ("eps_break", ctypes.c_double), ("rotation", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("max_neighbours", ctypes.c_int32), ("cell_div", ctypes.c_int32),
         ("tile_cut", ctypes.c_double), ("skin", ctypes.c_double),
+        ("pass_blocks", ctypes.c_int32), ("graph", ctypes.c_int32),
     ]
+
+
+class SphTuneResult(ctypes.Structure):
+    _fields_ = [("pass_blocks", ctypes.c_int32), ("trials", ctypes.c_int32), ("tile_cut", ctypes.c_double),
+                ("skin", ctypes.c_double), ("ms_per_step", ctypes.c_double),
+                ("ms_per_step_start", ctypes.c_double)]
 
 
 class SphListStats(ctypes.Structure):
@@ -101,6 +108,7 @@ def load():
     L.sph_mlp_eval.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp]
     L.sph_mlp_build_trust_mask.argtypes = [vp, ctypes.c_double, ctypes.POINTER(ctypes.c_int64)]
     L.sph_ensemble_set.argtypes = [vp, ctypes.c_int32, vp]
+    L.sph_autotune.argtypes = [vp, S, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(SphTuneResult)]
     _lib = L
     return L
 
@@ -166,7 +174,7 @@ class Context:
     DEFAULT_SKIN = 0.1
 
     def __init__(self, params, capacity: int, stream=None, max_neighbours=0, cell_div=0, tile_cut=0.0,
-                 skin=None):
+                 skin=None, pass_blocks=0, graph=False):
         import torch
         from sph_inputs.params import (BACKGROUNDS, BREAK_MODES, EOS_KINDS, H_MODES, KERNELS, MU_MODES,
                                        PRECISIONS, ROTATIONS, Y0_MODES, YIELD_MODES)
@@ -209,6 +217,8 @@ class Context:
         p.cell_div = cell_div
         p.tile_cut = tile_cut
         p.skin = self.DEFAULT_SKIN if skin is None else skin
+        p.pass_blocks = int(pass_blocks)
+        p.graph = int(bool(graph))
         self.p = p
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = ctypes.c_void_p()
@@ -273,6 +283,12 @@ class Context:
         _check(self.lib.sph_neighbour_stats(self.h, ctypes.byref(s)), "sph_neighbour_stats")
         return {k: getattr(s, k) for k in ("pairs", "max_count", "tiles", "union_total", "candidates",
                                            "rebuilds")}
+
+    def sph_autotune(self, st: DeviceState, dt: float, steps_per_trial: int = 8):
+        r = SphTuneResult()
+        _check(self.lib.sph_autotune(self.h, ctypes.byref(st.struct), float(dt), int(steps_per_trial),
+                                     ctypes.byref(r)), "sph_autotune")
+        return {k: getattr(r, k) for k, _ in SphTuneResult._fields_}
 
     def sph_ensemble_set(self, star_info):
         """star_info: [nstars, 5] rows of (centre x, y, z, particle mass, shear factor)."""

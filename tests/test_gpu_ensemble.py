@@ -65,3 +65,79 @@ def test_ensemble_fp32_pairs(ens):
     _print("ensemble fp32", e)
     for k in ("D", "rho", "P"):
         assert e[k] < 1e-4, (k, e[k])
+
+
+def _run_on_stream(w, steps, ctx_kw, tune=0):
+    """Evaluate and step on a non-default torch stream (graph capture needs one); with tune,
+    sph_autotune runs first (the lists are rebuilt afterwards).  Returns (state by id, stats,
+    tune result)."""
+    import torch
+
+    from paper_2107_07315_amd import sph
+    s = torch.cuda.Stream()
+    tr = None
+    with torch.cuda.stream(s):
+        ctx = sph.Context(w.params, capacity=w.n, stream=s, **ctx_kw)
+        if w.star_params is not None:
+            ctx.sph_ensemble_set(w.star_params)
+        st = sph.DeviceState(w.arrays)
+        if tune:
+            before = st.numpy()
+            tr = ctx.sph_autotune(st, w.dt, tune)
+            ctx.sph_sync()
+            after = st.numpy()
+            for k in before:   # the trials run on a copy
+                assert np.array_equal(before[k], after[k], equal_nan=True), k
+        ctx.evaluate(st)
+        ctx.sph_step(st, w.dt, steps)
+        ctx.sph_sync()
+        stats = ctx.sph_neighbour_stats()
+        g = st.numpy()
+        ctx.close()
+    s.synchronize()
+    order = np.argsort(g["id"])
+    return {k: (v[..., order] if v.ndim == 2 else v[order]) for k, v in g.items()}, stats, tr
+
+
+@pytest.mark.parametrize("skin", [1e-3, 0.05])
+def test_graph_steps_equal_eager_steps(skin):
+    # the same kernels replayed from two captured graphs per step give bit-identical states,
+    # with rebuilds of the candidate lists (and re-captures when buffers grow) in between
+    w = W.ensemble(4, 16000, seed=9, nmin=2000, nmax=8000, kind="gamma2", precision="FP64")
+    eager, se, _ = _run_on_stream(w, 12, {"skin": skin, "graph": False})
+    graph, sg, _ = _run_on_stream(w, 12, {"skin": skin, "graph": True})
+    print("rebuilds eager", se["rebuilds"], "graph", sg["rebuilds"], flush=True)
+    assert se["rebuilds"] == sg["rebuilds"]
+    if skin == 1e-3:
+        assert se["rebuilds"] >= 3
+    for k in eager:
+        assert np.array_equal(eager[k], graph[k]), k
+
+
+def test_graph_mode_needs_a_stream():
+    from paper_2107_07315_amd import sph
+    w = W.lattice(n_side=8)
+    ctx = sph.Context(w.params, capacity=w.n, graph=True)   # torch's default stream is the null stream
+    st = sph.DeviceState(w.arrays)
+    ctx.evaluate(st)
+    with pytest.raises(sph.SphError) as e:
+        ctx.sph_step(st, w.dt, 1)
+    assert e.value.code == 1
+    ctx.close()
+
+
+def test_autotune_then_steps_match_oracle():
+    w = W.star(20000, seed=3, kernel="WC4", eta=W.ETA_100, l=2, A=1e-2, plastic=True)
+    g, _, tr = _run_on_stream(w, 5, {"graph": True}, tune=3)
+    print("autotune", tr, flush=True)
+    assert tr["pass_blocks"] in (0, 1024, 4096, 16384)
+    assert tr["tile_cut"] in (4.0, 6.0, 8.0)
+    assert tr["skin"] in (0.05, 0.1, 0.15)
+    assert tr["trials"] >= 6
+    assert 0 < tr["ms_per_step"] <= tr["ms_per_step_start"]
+    o = oracle_run(w, steps=5)
+    e = field_errors(g, o, ("x", "y", "z", "vx", "vy", "vz", "u", "h", "S", "D", "ax", "dudt", "dSdt"))
+    _print("after autotune, 5 steps", e)
+    for k, v in e.items():
+        assert v < 1e-9, (k, v)
+    assert np.array_equal(g["broken"], o["broken"])
