@@ -18,18 +18,20 @@ sys.path.insert(0, ROOT)
 
 # Algorithmic work of the two dominant pair passes, counted from the kernel source (add, mul =
 # 1 FLOP, fma = 2, sqrt and reciprocal 1 each; the crust-only stress terms are left out).
-#  density: per candidate the exact FP64 test (3 sub, r^2 5, H and H^2 2) = 10; per neighbour
-#           pair the kernel value (sqrt, rcp, 0.5 H, q, 1 - q/2, powers, polynomial, sum) = 20;
-#           per particle the epilogue (metric, Lorentz factor, EoS table, moduli) ~ 110.
+#  density (pair loop; its per-particle EoS epilogue is a kernel of its own): per candidate the
+#           exact FP64 test (3 sub, r^2 5, H and H^2 2) = 10; per neighbour pair the kernel value
+#           (sqrt, rcp, 0.5 H, q, 1 - q/2, powers, polynomial, sum) = 20; per particle the self
+#           term and the mass factor ~ 12.
 #  forces:  per neighbour pair 73 (distance 8, kernel gradient 18, viscosity 26, sums 21);
 #           per particle the fixed-background epilogue ~ 110.
 # Algorithmic HBM bytes: lists at 2 B per entry (candidate lists read and exact lists written by
 # the density pass, exact lists read by the force pass) plus each particle's own records read
-# and results written once; neighbour records staged through LDS are re-reads served by the
-# caches and are not counted.
-DENS_FLOP = {"candidate": 10, "pair": 20, "particle": 110}
+# and results written once (density: FP64 position 32, candidate count 4, D 8, exact counts 8 =
+# 52 B); neighbour records staged through LDS are re-reads served by the caches and are not
+# counted.
+DENS_FLOP = {"candidate": 10, "pair": 20, "particle": 12}
 FORCE_FLOP = {"pair": 73, "particle": 110}
-DENS_BYTES = {"FP64": 274, "FP32": 226, "candidate": 2, "pair": 2}
+DENS_BYTES = {"FP64": 52, "FP32": 52, "candidate": 2, "pair": 2}
 FORCE_BYTES = {"FP64": 176, "FP32": 136, "pair": 2}
 PEAK = {"FP64": 78.6e12, "FP32": 157.3e12}     # published MI355X vector peaks, FLOP/s
 KERNEL_SOURCES = ("paper_2107_07315_amd/csrc/sph_pairs.hip", "paper_2107_07315_amd/csrc/sph_internal.h")
@@ -101,7 +103,7 @@ def run_variant(w, precision, eos, steps, warmup, timing=True, ctx_kw=None, mlp=
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / steps
     stages = {}
-    for s in ("cells", "density", "stress", "forces", "kdk"):
+    for s in ("cells", "density", "eos", "stress", "forces", "kdk"):
         n, ms = ctx.sph_get_timing(s)
         stages[s] = {"launches": n, "ms_total": ms}
     stats = ctx.sph_neighbour_stats()

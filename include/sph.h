@@ -126,6 +126,9 @@ typedef struct {
                            /*   loops over the tiles                                            */
   int32_t graph;           /* sph_step: 1 = replay captured HIP graphs of each step's kernels  */
                            /*   (needs skin > 0; stage timers are not recorded)                */
+  int32_t lanes;           /* lanes per target particle in the pair passes: 1, 2 or 4 (0: 4);  */
+                           /*   a tile of up to 64 targets is one workgroup of 64 * lanes     */
+                           /*   threads, the lanes of a target splitting its list             */
 } sph_params;
 
 /* Neighbour-list statistics (sph_neighbour_stats). */
@@ -190,15 +193,20 @@ sph_status sph_step(sph_ctx* ctx, sph_state* st, double dt, int32_t nsteps);
  * stars).  nstars = 0 returns to a single star.  Waits; invalidates the stage order. */
 sph_status sph_ensemble_set(sph_ctx* ctx, int32_t nstars, const double* star_info);
 
-/* Launch autotuner: times `steps_per_trial` steps of copies of the state (the caller's state is
- * not changed) under candidate settings of pass_blocks, tile_cut and skin, one parameter at a
- * time (coordinate descent from the current settings), and keeps the fastest.  The context then
- * needs a new evaluation (sph_build_cells ...) before sph_step.  Waits. */
+/* Launch autotuner: under candidate settings of lanes, pass_blocks, tile_cut and skin, one parameter at
+ * a time (coordinate descent from the current settings), steps a copy of the state (the caller's
+ * state is not changed) through one whole rebuild cycle of the candidate lists and keeps the
+ * setting with the least time per step, the list rebuild amortised over the cycle.  A cycle runs
+ * from just after one rebuild to the end of the step holding the next; each of its two phases
+ * (reaching the first rebuild, the cycle itself) stops after at most `steps_per_trial` steps.
+ * The context then needs a new evaluation (sph_build_cells ...) before sph_step.  Waits. */
 typedef struct {
   int32_t pass_blocks;
   int32_t trials;          /* configurations timed                                              */
+  int32_t lanes;
+  int32_t pad;
   double tile_cut, skin;
-  double ms_per_step;      /* of the chosen configuration                                       */
+  double ms_per_step;      /* of the chosen configuration, rebuilds amortised                   */
   double ms_per_step_start;/* of the starting configuration                                     */
 } sph_tune_result;
 sph_status sph_autotune(sph_ctx* ctx, const sph_state* st, double dt, int32_t steps_per_trial,
@@ -206,6 +214,11 @@ sph_status sph_autotune(sph_ctx* ctx, const sph_state* st, double dt, int32_t st
 
 /* Wait for the context's stream; return and clear the first latched device error. */
 sph_status sph_sync(sph_ctx* ctx);
+
+/* Array index (in the state's current order, i.e. after the last sph_build_cells reordering)
+ * of the particle that raised the error returned by the last failing sph_sync, or -1 when the
+ * error has no particle (a tile-level overflow) or no sph_sync has failed.  Does not wait. */
+int32_t sph_error_particle(const sph_ctx* ctx);
 
 /* Copy the exact neighbour lists of the last sph_density to host memory as CSR in the
  * particles' current order: offsets[n+1] (host), ids[offsets[n]] (host, indices into the
@@ -266,8 +279,11 @@ sph_status sph_mlp_build_trust_mask(sph_ctx* ctx, double tol, int64_t* trusted_c
 /* Human-readable name of a status code (static string). */
 const char* sph_status_string(sph_status s);
 
-/* Kernel timing of the last sph_step call: number of launches and total milliseconds of the
- * force pass, measured with HIP events on the context stream (0 if timing is off).  Waits. */
+/* Kernel timing since timing was last enabled: launches and total milliseconds of one stage,
+ * measured with HIP events on the context stream (0 while timing is off).  Stages: "cells"
+ * (candidate-list builds), "density" (pair loop of the density pass), "eos" (its per-particle
+ * epilogue: EoS, moduli, packed records), "stress", "forces", "kdk" (kick-drift and final kick).
+ * Graph-replayed steps record no times.  Waits. */
 sph_status sph_set_timing(sph_ctx* ctx, int32_t enable);
 sph_status sph_get_timing(sph_ctx* ctx, const char* stage, int32_t* launches, double* ms);
 

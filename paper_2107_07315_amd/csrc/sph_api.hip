@@ -3,6 +3,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 
 #include "sph_internal.h"
@@ -37,6 +38,7 @@ sph_status check_params(const sph_params* p) {
   if (!(p->tile_cut >= 0.0) || p->tile_cut > 64.0) return SPH_E_ARG;
   if (!(p->skin >= 0.0) || p->skin > 1.0) return SPH_E_ARG;
   if (p->pass_blocks < 0 || p->pass_blocks > 65536 || p->graph < 0 || p->graph > 1) return SPH_E_ARG;
+  if (p->lanes != 0 && p->lanes != 1 && p->lanes != 2 && p->lanes != 4) return SPH_E_ARG;
   return SPH_OK;
 }
 
@@ -95,7 +97,7 @@ void sph_destroy(sph_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   void* bufs[] = {c->grid, c->keys, c->vals, c->cell_se, c->pos_sorted, c->sort.keys_alt, c->sort.vals_alt,
                   c->sort.hist, c->sort.rowtot, c->sort.partial, c->sort.scan_bsum, c->tile_u, c->tile_start, c->tile_cnt, c->tile_uoff,
-                  c->tile_usize, c->nbr16, c->nbr_count, c->nbr16s, c->nbr_count_s, c->pos_build, c->drift_flag,
+                  c->tile_usize, c->nbr16, c->nbr_count, c->nbr_count_sl, c->nbr16s, c->nbr_count_s, c->pos_build, c->drift_flag,
                   c->pos4, c->fv, c->fa, c->sig, c->pos4f, c->fvf,
                   c->faf, c->sigf, c->mu, c->Y0, c->B, c->sdot, c->half, c->tmp, c->stars, c->status};
   for (void* b : bufs)
@@ -147,7 +149,8 @@ sph_status sph_create(const sph_params* params, void* stream, int64_t capacity, 
       (e = dalloc(&c->tile_start, c->cap_tiles)) || (e = dalloc(&c->tile_cnt, c->cap_tiles)) ||
       (e = dalloc(&c->tile_uoff, c->cap_tiles)) ||
       (e = dalloc(&c->sort.scan_bsum, c->sort.scan_cap + 1)) ||
-      (e = dalloc(&c->nbr16, (size_t)capw * ((c->cap + 7) / 8 * 8))) || (e = dalloc(&c->nbr_count, capw)) ||
+      (e = dalloc(&c->nbr16, (size_t)capw * slot_entries_max(c->cap))) || (e = dalloc(&c->nbr_count, capw)) ||
+      (e = dalloc(&c->nbr_count_sl, (size_t)capw * 4)) ||
       (e = dalloc(&c->nbr16s, (size_t)capw * c->cap_s)) || (e = dalloc(&c->nbr_count_s, capw)) ||
       (e = dalloc(&c->pos_build, cap)) || (e = dalloc(&c->drift_flag, 1)) ||
       (e = dalloc(&c->pos4, cap)) || (e = dalloc(&c->fv, cap)) || (e = dalloc(&c->fa, cap)) ||
@@ -165,6 +168,7 @@ sph_status sph_create(const sph_params* params, void* stream, int64_t capacity, 
   }
   if (hipMemsetAsync(c->status, 0, sizeof(DevStatus), c->stream) != hipSuccess ||
       hipMemsetAsync(c->nbr_count, 0, sizeof(int32_t) * cap, c->stream) != hipSuccess ||
+      hipMemsetAsync(c->nbr_count_sl, 0, sizeof(int32_t) * capw * 4, c->stream) != hipSuccess ||
       hipMemsetAsync(c->nbr_count_s, 0, sizeof(int32_t) * cap, c->stream) != hipSuccess ||
       hipMemsetAsync(c->drift_flag, 0, sizeof(uint32_t), c->stream) != hipSuccess ||
       hipMemsetAsync(c->Y0, 0, sizeof(double) * cap, c->stream) != hipSuccess ||
@@ -242,6 +246,10 @@ sph_status sph_density(sph_ctx* c, sph_state* st) {
     e = launch_density(c, st);
     timer_end(c, TIMER_DENSITY);
     if (e) return e;
+    timer_begin(c, TIMER_EOS);
+    e = launch_eos(c, st);
+    timer_end(c, TIMER_EOS);
+    if (e) return e;
   }
   c->gen = 2;
   return SPH_OK;
@@ -295,6 +303,7 @@ static sph_status capture_step(sph_ctx* c, sph_state* st, double dt) {
     sph_status le = SPH_OK;
     if (which == 0) {
       if (!le) le = launch_density(c, st);
+      if (!le) le = launch_eos(c, st);
       if (!le) le = launch_stress(c, st);
       if (!le) le = launch_forces(c, st);
       if (!le) le = launch_kick_final(c, st, dt);
@@ -366,6 +375,9 @@ sph_status sph_step(sph_ctx* c, sph_state* st, double dt, int32_t nsteps) {
     timer_begin(c, TIMER_DENSITY);
     if ((e = launch_density(c, st))) return e;
     timer_end(c, TIMER_DENSITY);
+    timer_begin(c, TIMER_EOS);
+    if ((e = launch_eos(c, st))) return e;
+    timer_end(c, TIMER_EOS);
     timer_begin(c, TIMER_STRESS);
     if ((e = launch_stress(c, st))) return e;
     timer_end(c, TIMER_STRESS);
@@ -447,18 +459,26 @@ sph_status sph_autotune(sph_ctx* c, const sph_state* st, double dt, int32_t step
     ++c->graph_epoch;
     sph_status te;
     if ((te = cp.load(st, c->stream)) || (te = sph_build_cells(c, &cp.st)) || (te = sph_density(c, &cp.st)) ||
-        (te = sph_stress_rate(c, &cp.st)) || (te = sph_forces(c, &cp.st)) || (te = sph_step(c, &cp.st, dt, 2)))
+        (te = sph_stress_rate(c, &cp.st)) || (te = sph_forces(c, &cp.st)) || (te = sph_step(c, &cp.st, dt, 1)))
       return te;
+    // phase 1: up to the first rebuild; phase 2 (timed): one rebuild cycle
+    const int64_t r0 = c->rebuilds;
+    for (int k = 0; k < steps && c->rebuilds == r0; ++k)
+      if ((te = sph_step(c, &cp.st, dt, 1))) return te;
     HIP_TRY(hipStreamSynchronize(c->stream));
     const auto t0 = std::chrono::steady_clock::now();
-    if ((te = sph_step(c, &cp.st, dt, steps))) return te;
+    const int64_t r1 = c->rebuilds;
+    int k = 0;
+    for (; k < steps && c->rebuilds == r1; ++k)
+      if ((te = sph_step(c, &cp.st, dt, 1))) return te;
     HIP_TRY(hipStreamSynchronize(c->stream));
     const auto t1 = std::chrono::steady_clock::now();
-    *ms = std::chrono::duration<double, std::milli>(t1 - t0).count() / steps;
+    *ms = std::chrono::duration<double, std::milli>(t1 - t0).count() / k;
     return sph_sync(c);
   };
   sph_params best = c->p;
   if (best.tile_cut <= 0.0) best.tile_cut = 6.0;
+  if (best.lanes <= 0) best.lanes = pass_lanes(best);
   double best_ms = 0.0;
   int32_t trials = 1;
   if ((e = trial(best, &best_ms))) {
@@ -466,18 +486,22 @@ sph_status sph_autotune(sph_ctx* c, const sph_state* st, double dt, int32_t step
     return e;
   }
   const double start_ms = best_ms;
-  // coordinate descent: workgroup schedule of the pair passes, tile cut, skin
-  for (int dim = 0; dim < 3 && !e; ++dim) {
-    const double vals[3][4] = {{0, 1024, 4096, 16384}, {4, 6, 8, -1}, {0.05, 0.1, 0.15, -1}};
+  // coordinate descent: lanes per target, workgroup schedule of the pair passes, tile cut, skin;
+  // a setting replaces the best only if it is faster by more than the timing noise (2%)
+  for (int dim = 0; dim < 4 && !e; ++dim) {
+    const double vals[4][4] = {{1, 2, 4, -1}, {0, 1024, 4096, 16384}, {4, 6, 8, -1}, {0.05, 0.1, 0.15, -1}};
     const sph_params base = best;
     for (int k = 0; k < 4 && !e; ++k) {
       const double v = vals[dim][k];
       if (v < 0) continue;
       sph_params p = base;
       if (dim == 0) {
+        if ((int32_t)v == base.lanes) continue;
+        p.lanes = (int32_t)v;
+      } else if (dim == 1) {
         if ((int32_t)v == base.pass_blocks) continue;
         p.pass_blocks = (int32_t)v;
-      } else if (dim == 1) {
+      } else if (dim == 2) {
         if (v == base.tile_cut) continue;
         p.tile_cut = v;
       } else {
@@ -487,7 +511,7 @@ sph_status sph_autotune(sph_ctx* c, const sph_state* st, double dt, int32_t step
       double ms;
       e = trial(p, &ms);
       ++trials;
-      if (!e && ms < best_ms) {
+      if (!e && ms < 0.98 * best_ms) {
         best_ms = ms;
         best = p;
       }
@@ -500,6 +524,8 @@ sph_status sph_autotune(sph_ctx* c, const sph_state* st, double dt, int32_t step
   ++c->graph_epoch;
   if (e) return e;
   out->pass_blocks = best.pass_blocks;
+  out->lanes = best.lanes;
+  out->pad = 0;
   out->tile_cut = best.tile_cut;
   out->skin = best.skin;
   out->trials = trials;
@@ -533,12 +559,15 @@ sph_status sph_ensemble_set(sph_ctx* c, int32_t nstars, const double* star_info)
   return SPH_OK;
 }
 
+int32_t sph_error_particle(const sph_ctx* c) { return c ? c->err_particle : -1; }
+
 sph_status sph_sync(sph_ctx* c) {
   if (!c) return SPH_E_ARG;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return SPH_E_HIP;
   DevStatus s;
   if (hipMemcpy(&s, c->status, sizeof(s), hipMemcpyDeviceToHost) != hipSuccess) return SPH_E_HIP;
   if (s.code) {
+    c->err_particle = s.particle;
     DevStatus z = {0, 0};
     if (hipMemcpy(c->status, &z, sizeof(z), hipMemcpyHostToDevice) != hipSuccess) return SPH_E_HIP;
     return (sph_status)s.code;
@@ -558,8 +587,11 @@ sph_status sph_export_neighbours(sph_ctx* c, int64_t* offsets, int32_t* ids, int
   std::vector<int32_t> cnt(n), tst(ntiles), tcn(ntiles);
   std::vector<uint32_t> uoff(ntiles);
   std::vector<int32_t> U((size_t)(g.upool_used < c->upool ? g.upool_used : c->upool));
-  std::vector<uint16_t> raw((size_t)((c->cap + 7) / 8 * 8) * c->capw);
+  const int L = pass_lanes(c->p);
+  std::vector<uint16_t> raw((size_t)slot_capacity(c->cap, L) * c->capw * L);
+  std::vector<int32_t> cnt_sl((size_t)n * L);
   if (hipMemcpy(cnt.data(), c->nbr_count, sizeof(int32_t) * n, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(cnt_sl.data(), c->nbr_count_sl, sizeof(int32_t) * n * L, hipMemcpyDeviceToHost) != hipSuccess ||
       hipMemcpy(tst.data(), c->tile_start, sizeof(int32_t) * ntiles, hipMemcpyDeviceToHost) != hipSuccess ||
       hipMemcpy(tcn.data(), c->tile_cnt, sizeof(int32_t) * ntiles, hipMemcpyDeviceToHost) != hipSuccess ||
       hipMemcpy(uoff.data(), c->tile_uoff, sizeof(uint32_t) * ntiles, hipMemcpyDeviceToHost) != hipSuccess ||
@@ -569,11 +601,18 @@ sph_status sph_export_neighbours(sph_ctx* c, int64_t* offsets, int32_t* ids, int
   offsets[0] = 0;
   for (int64_t a = 0; a < n; ++a) offsets[a + 1] = offsets[a] + cnt[a];
   if (offsets[n] > cap || !ids) return SPH_E_NGB_CAPACITY;
+  std::vector<uint16_t> loc;
   for (int64_t t = 0; t < ntiles; ++t)
     for (int l = 0; l < tcn[t]; ++l) {
       const int64_t a = (int64_t)tst[t] + l;
-      for (int k = 0; k < cnt[a]; ++k)
-        ids[offsets[a] + k] = U[(size_t)uoff[t] + raw[(size_t)nbr_index(k, a, c->capw)]];
+      loc.clear();   // the particle's slot lists, merged in ascending local index
+      for (int j = 0; j < L; ++j) {
+        const int64_t s = a * L + j;
+        for (int k = 0; k < cnt_sl[(size_t)s]; ++k) loc.push_back(raw[(size_t)nbr_index(k, s, c->capw * L)]);
+      }
+      std::sort(loc.begin(), loc.end());
+      if ((int64_t)loc.size() != cnt[a]) return SPH_E_NGB_CAPACITY;   // lists of an overflowed evaluation
+      for (size_t k = 0; k < loc.size(); ++k) ids[offsets[a] + (int64_t)k] = U[(size_t)uoff[t] + loc[k]];
     }
   return SPH_OK;
 }
@@ -594,9 +633,9 @@ sph_status sph_set_timing(sph_ctx* c, int32_t enable) {
 
 sph_status sph_get_timing(sph_ctx* c, const char* stage, int32_t* launches, double* ms) {
   if (!c || !stage || !launches || !ms) return SPH_E_ARG;
-  static const char* names[5] = {"cells", "density", "stress", "forces", "kdk"};
+  static const char* names[6] = {"cells", "density", "stress", "forces", "kdk", "eos"};
   int which = -1;
-  for (int k = 0; k < 5; ++k)
+  for (int k = 0; k < 6; ++k)
     if (!strcmp(stage, names[k])) which = k;
   if (which < 0) return SPH_E_ARG;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return SPH_E_HIP;

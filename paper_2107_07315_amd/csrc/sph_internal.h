@@ -329,8 +329,9 @@ struct sph_ctx {
   int64_t upool;        // entries of tile_u
   int64_t cap_tiles;
   int32_t* tile_usize;
-  uint16_t* nbr16;
-  int32_t* nbr_count;
+  uint16_t* nbr16;      // exact lists, one per slot (particle * lanes + sub-index)
+  int32_t* nbr_count;   // exact neighbours per particle
+  int32_t* nbr_count_sl;  // entries per slot list
   uint16_t* nbr16s;
   int32_t* nbr_count_s;
   int64_t capw;         // capacity rounded up to 64
@@ -356,9 +357,10 @@ struct sph_ctx {
   int32_t nstars;
   // status
   DevStatus* status;    // device
+  int32_t err_particle = -1;   // particle of the error returned by the last failing sph_sync
   // timing
   int32_t timing;
-  StageTimer timers[5];
+  StageTimer timers[6];
   // EoS surrogate network (allocated on first use)
   struct MlpState* mlp;
 };
@@ -368,7 +370,8 @@ sph_status sph_sort_pairs(sph_ctx* c, uint32_t* keys, uint32_t* vals, int64_t n)
 sph_status sph_rebin(sph_ctx* c, sph_state* st);
 sph_status launch_drift_check(sph_ctx* c, sph_state* st);
 sph_status launch_flag_clear(sph_ctx* c);
-sph_status launch_density(sph_ctx* c, sph_state* st);
+sph_status launch_density(sph_ctx* c, sph_state* st);   // pair loop
+sph_status launch_eos(sph_ctx* c, sph_state* st);       // per-particle epilogue
 sph_status launch_stress(sph_ctx* c, sph_state* st);
 sph_status launch_forces(sph_ctx* c, sph_state* st);
 sph_status launch_kick_drift(sph_ctx* c, sph_state* st, double dt, bool check);
@@ -380,12 +383,27 @@ struct MlpView;
 bool mlp_view(const sph_ctx* c, MlpView* v);   // false if no trained network is loaded
 void mlp_free(sph_ctx* c);
 
-enum { TIMER_CELLS = 0, TIMER_DENSITY = 1, TIMER_STRESS = 2, TIMER_FORCES = 3, TIMER_KDK = 4 };
+enum { TIMER_CELLS = 0, TIMER_DENSITY = 1, TIMER_STRESS = 2, TIMER_FORCES = 3, TIMER_KDK = 4, TIMER_EOS = 5 };
 void timer_begin(sph_ctx* c, int which);
 void timer_end(sph_ctx* c, int which);
 
 __host__ __device__ __forceinline__ int64_t nbr_index(int64_t k, int64_t p, int64_t capw) {
   return (((k >> 3) * capw + p) << 3) + (k & 7);
+}
+
+// Lanes per target of the pair passes, and the entries of one slot list: lanes L share a
+// particle's at most 2 cap candidates in turn, so a slot receives at most ceil(2 cap / L) exact
+// hits (and the particle's list at most cap).  Slot s of the exact lists is entry k at
+// nbr_index(k, s, capw * L).
+__host__ __device__ __forceinline__ int pass_lanes(const sph_params& p) { return p.lanes > 0 ? p.lanes : 4; }
+__host__ __device__ __forceinline__ int slot_capacity(int cap, int L) {
+  const int c = (2 * cap + L - 1) / L;
+  return ((c < cap ? c : cap) + 7) / 8 * 8;
+}
+__host__ __device__ __forceinline__ int64_t slot_entries_max(int cap) {   // per particle, over L
+  int64_t m = 0;
+  for (int L = 1; L <= 4; L *= 2) m = m > (int64_t)L * slot_capacity(cap, L) ? m : (int64_t)L * slot_capacity(cap, L);
+  return m;
 }
 
 #define HIP_TRY(expr)                                   \

@@ -89,8 +89,9 @@ struct PassArgs {
   const uint32_t* __restrict__ tile_uoff;
   const int32_t* __restrict__ tile_u;
   const int32_t* __restrict__ tile_usize;
-  const uint16_t* __restrict__ nbr16;    // exact lists (written by the density pass)
-  const int32_t* __restrict__ cnt;
+  const uint16_t* __restrict__ nbr16;    // exact lists (written by the density pass), one per slot
+  const int32_t* __restrict__ cnt_sl;   // entries per slot; slot = particle * lanes + sub-index
+  int cap_sl;                           // entries a slot holds
   const uint16_t* __restrict__ nbr16s;   // candidate lists of the last build
   const int32_t* __restrict__ cnt_s;
   const int32_t* __restrict__ star;
@@ -102,47 +103,79 @@ struct PassArgs {
 
 constexpr int kNone = 0x7fffffff;
 
-// Per-lane view of the tile lists.  Entries come 8 per 16-byte load; the group after the current
-// one is always in flight, and the current group is consumed by funnel shifts.
+// A 16-byte group of 8 list entries shifted right by 16 m bits, m in [0, 3] (a per-lane value).
+__device__ __forceinline__ uint4 shr_entries(uint4 v, int m) {
+  const bool w = (m & 2) != 0;
+  const uint4 r = make_uint4(w ? v.y : v.x, w ? v.z : v.y, w ? v.w : v.z, w ? 0u : v.w);
+  const uint4 h = make_uint4(__builtin_amdgcn_alignbit(r.y, r.x, 16u), __builtin_amdgcn_alignbit(r.z, r.y, 16u),
+                             __builtin_amdgcn_alignbit(r.w, r.z, 16u), r.w >> 16);
+  return (m & 1) ? h : r;
+}
+
+// Per-lane walk over a list stored as 16-byte groups of 8 16-bit local indices.  A lane takes the
+// entries pre, pre + STEP, pre + 2 STEP, ... of its list (STEP = 1: all of them; STEP = L with
+// pre = the lane's sub-index: the L lanes of a target share its list), 8 / STEP per group.  The
+// group after the current one is always in flight; the current one is consumed by shifts.
+template <int STEP>
 struct TileWalk {
+  static constexpr int E = 8 / STEP;
   int64_t p, a;
   bool valid;
-  int usize, cnt, k, next;
-  const uint4* grp_base;   // group g of this lane at grp_base[g * capw]
-  int64_t capw;
+  int usize, cnt, k, next, pre;
+  const uint4* grp_base;   // group g at grp_base[g * gstride]
+  int64_t gstride;
   uint4 cur, nxt;
   const int32_t* U;
-  __device__ __forceinline__ void init(const PassArgs& A, int64_t tile, const uint16_t* lists,
-                                       const int32_t* counts) {
-    p = (int64_t)A.tile_start[tile] + threadIdx.x;
-    valid = (int)threadIdx.x < A.tile_cnt[tile];
+  // target t of the tile (a = p for a valid target, 0 otherwise)
+  __device__ __forceinline__ void begin(const PassArgs& A, int64_t tile, int t) {
+    p = (int64_t)A.tile_start[tile] + t;
+    valid = t < A.tile_cnt[tile];
     a = valid ? p : 0;
     usize = A.tile_usize[tile];
-    cnt = valid ? counts[p] : 0;
-    capw = A.capw;
-    grp_base = reinterpret_cast<const uint4*>(lists) + (valid ? p : 0);
     U = A.tile_u + A.tile_uoff[tile];
+  }
+  // cnt = entries this lane takes
+  __device__ __forceinline__ void start(const uint4* base, int64_t stride, int count, int pre_) {
+    grp_base = base;
+    gstride = stride;
+    cnt = count;
+    pre = pre_;
     k = 0;
     cur = make_uint4(0u, 0u, 0u, 0u);
     nxt = cur;
-    if (cnt > 0) cur = grp_base[0];
-    if (cnt > 8) nxt = grp_base[capw];
+    if (cnt > 0) cur = STEP > 1 ? shr_entries(grp_base[0], pre) : grp_base[0];
+    if (cnt > E) nxt = grp_base[gstride];
     next = cnt > 0 ? (int)(cur.x & 0xffffu) : kNone;
   }
   __device__ __forceinline__ void advance() {
     ++k;
-    if ((k & 7) == 0) {
-      cur = nxt;
-      if (k + 8 < cnt) nxt = grp_base[(int64_t)((k >> 3) + 1) * capw];
-    } else {
+    if ((k & (E - 1)) == 0) {
+      cur = STEP > 1 ? shr_entries(nxt, pre) : nxt;
+      if (k + E < cnt) nxt = grp_base[(int64_t)(k / E + 1) * gstride];
+    } else if constexpr (STEP == 1) {
       cur.x = __builtin_amdgcn_alignbit(cur.y, cur.x, 16u);
       cur.y = __builtin_amdgcn_alignbit(cur.z, cur.y, 16u);
       cur.z = __builtin_amdgcn_alignbit(cur.w, cur.z, 16u);
       cur.w >>= 16;
+    } else if constexpr (STEP == 2) {
+      cur.x = cur.y;
+      cur.y = cur.z;
+      cur.z = cur.w;
+    } else {
+      cur.x = cur.z;
+      cur.y = cur.w;
     }
     next = k < cnt ? (int)(cur.x & 0xffffu) : kNone;
   }
 };
+
+// Sum over the L adjacent lanes that share a target (every one of them receives the sum).
+template <int L, typename T>
+__device__ __forceinline__ T lane_group_sum(T v) {
+#pragma unroll
+  for (int off = 1; off < L; off <<= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
 
 __device__ __forceinline__ int64_t num_tiles(const PassArgs& A) { return (int64_t)A.grid->ntiles; }
 
@@ -313,36 +346,39 @@ __device__ __forceinline__ void density_epilogue(const PassArgs& A, int64_t a, b
 // Density pass.  Walks the candidate lists, takes the exact FP64 neighbour decision
 // r^2 < (h_a + h_b)^2 on every candidate (positions staged in LDS in FP64 for both precisions),
 // sums the kernel over the neighbours in R, and writes the exact lists for the stress and force
-// passes.
-template <typename R, int KER, bool PER, bool EPI>
-__global__ __launch_bounds__(64) void k_density(PassArgs A, const double4* __restrict__ pos64,
-                                                const double* __restrict__ vx, const double* __restrict__ vy,
-                                                const double* __restrict__ vz, const double* __restrict__ u,
-                                                const double* __restrict__ S, const int8_t* __restrict__ type,
-                                                const uint8_t* __restrict__ broken, DensOut O,
-                                                uint16_t* __restrict__ xlist, int32_t* __restrict__ xcount) {
-  constexpr int CH = Rec<R>::CH_D;
+// passes.  A workgroup of L waves takes one tile: lane g serves target g / L and takes every L-th
+// entry of its candidate list from sub-index g % L on, writing the exact hits to its own slot
+// list (slot = particle * L + sub-index); the L partial sums are added across the lanes.  The
+// per-particle epilogue runs in k_density_epilogue, one lane per particle.
+template <typename R, int KER, bool PER, int L>
+__global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* __restrict__ pos64, DensOut O,
+                                                    uint16_t* __restrict__ xlist, int32_t* __restrict__ xcount,
+                                                    int32_t* __restrict__ xcount_sl) {
+  constexpr int CH = Rec<R>::CH_D * L;
   __shared__ double4 sp[CH];
   const double box = A.p.box, half = 0.5 * box;
+  const int tl = threadIdx.x / L, sub = threadIdx.x % L;
   const int64_t ntl = num_tiles(A);
   for (int64_t k_ = blockIdx.x / SPH_XCD, chunk_ = xcd_chunk(ntl); k_ < chunk_; k_ += gridDim.x / SPH_XCD) {
     const int64_t tile = (int64_t)(blockIdx.x % SPH_XCD) * chunk_ + k_;
     if (tile >= ntl) break;
-  TileWalk tw;
-  tw.init(A, tile, A.nbr16s, A.cnt_s);
+  TileWalk<L> tw;
+  tw.begin(A, tile, tl);
+  const int total = tw.valid ? A.cnt_s[tw.p] : 0;
+  tw.start(reinterpret_cast<const uint4*>(A.nbr16s) + tw.a, A.capw, total > sub ? (total - sub + L - 1) / L : 0, sub);
   const int64_t a = tw.a;
-  const sph_params& p = A.p;
+  const int64_t slot = a * L + sub;
   const double4 pa = tw.valid ? pos64[a] : make_double4(0.0, 0.0, 0.0, 1.0);
-  R sum = wendland_self<R>(KER, (R)pa.w);
+  R sum = sub == 0 ? wendland_self<R>(KER, (R)pa.w) : (R)0;
   ListWriter wr;
-  wr.base = reinterpret_cast<uint4*>(xlist) + (tw.valid ? tw.p : 0);
-  wr.capw = A.capw;
-  wr.cap = A.cap;
+  wr.base = reinterpret_cast<uint4*>(xlist) + slot;
+  wr.capw = A.capw * L;
+  wr.cap = A.cap_sl;
   wr.n = 0;
   wr.w0 = wr.w1 = wr.w2 = wr.w3 = 0u;
   for (int c0 = 0; c0 < tw.usize; c0 += CH) {
     __syncthreads();
-    for (int j = threadIdx.x; j < CH && c0 + j < tw.usize; j += 64) sp[j] = pos64[tw.U[c0 + j]];
+    for (int j = threadIdx.x; j < CH && c0 + j < tw.usize; j += 64 * L) sp[j] = pos64[tw.U[c0 + j]];
     __syncthreads();
     const int cend = c0 + CH;
     if (tw.next < cend) {
@@ -369,23 +405,22 @@ __global__ __launch_bounds__(64) void k_density(PassArgs A, const double4* __res
     }
   }
   wr.flush();
+  sum = lane_group_sum<L>(sum);
+  const int nexact = lane_group_sum<L>(wr.n);
   if (tw.valid) {
-    xcount[tw.p] = wr.n < A.cap ? wr.n : A.cap;
-    if (wr.n > A.cap) latch_error(A.status, SPH_E_NGB_CAPACITY, (int)a);
+    xcount_sl[slot] = wr.n < A.cap_sl ? wr.n : A.cap_sl;
+    if (sub == 0) xcount[a] = nexact < A.cap ? nexact : A.cap;
+    if (nexact > A.cap || wr.n > A.cap_sl) latch_error(A.status, SPH_E_NGB_CAPACITY, (int)a);
   }
-  if (!EPI) {   // the epilogue runs in k_density_epilogue
-    if (tw.valid) O.D[a] = particle_mass(A, a) * (double)sum;
-    continue;
-  }
-  if (!tw.valid) continue;
-  density_epilogue<R, false>(A, a, true, particle_mass(A, a) * (double)sum, pos64, vx, vy, vz, u, S, type, broken, O);
+  if (tw.valid && sub == 0) O.D[a] = particle_mass(A, a) * (double)sum;
   }
 }
 
-// Per-particle epilogue of the density stage when the EoS is the surrogate network (a
-// wave-level call, kept out of the pair-loop kernel whose occupancy it would halve): one lane per
-// particle, D from the pair loop.
-template <typename R>
+// Per-particle epilogue of the density stage (EoS, moduli, packed records), one lane per particle,
+// D from the pair loop.  Kept out of the pair-loop kernel, where only one lane of a target's L
+// would work on it and its registers would lower the loop's occupancy; with MLP the EoS is the
+// surrogate network (a wave-level call).
+template <typename R, bool MLP>
 __global__ __launch_bounds__(64) void k_density_epilogue(PassArgs A, const double4* __restrict__ pos64,
                                                          const double* __restrict__ vx, const double* __restrict__ vy,
                                                          const double* __restrict__ vz, const double* __restrict__ u,
@@ -395,20 +430,23 @@ __global__ __launch_bounds__(64) void k_density_epilogue(PassArgs A, const doubl
     const int64_t a = base + threadIdx.x;
     const bool valid = a < A.n;
     const int64_t ae = valid ? a : base;   // lanes past the end work on a valid particle, store nothing
-    density_epilogue<R, true>(A, ae, valid, O.D[ae], pos64, vx, vy, vz, u, S, type, broken, O);
+    density_epilogue<R, MLP>(A, ae, valid, O.D[ae], pos64, vx, vy, vz, u, S, type, broken, O);
   }
 }
 
 // ---- velocity gradient and stress rate ---------------------------------------------------------
-template <typename R, int KER, bool PER>
-__global__ __launch_bounds__(64) void k_stress(PassArgs A, const typename Rec<R>::P4* __restrict__ pos,
-                                               const typename Rec<R>::V4* __restrict__ fv,
-                                               const typename Rec<R>::A2* __restrict__ fa,
-                                               const double* __restrict__ S, const double* __restrict__ mu,
-                                               double* __restrict__ dSdt, double* __restrict__ sdot) {
+// Lane g of the L-wave workgroup walks the exact slot list (g / L, g % L) written by the density
+// pass; the partial velocity gradients of a target's L lanes are added before the epilogue.
+template <typename R, int KER, bool PER, int L>
+__global__ __launch_bounds__(64 * L) void k_stress(PassArgs A, const typename Rec<R>::P4* __restrict__ pos,
+                                                   const typename Rec<R>::V4* __restrict__ fv,
+                                                   const typename Rec<R>::A2* __restrict__ fa,
+                                                   const double* __restrict__ S, const double* __restrict__ mu,
+                                                   double* __restrict__ dSdt, double* __restrict__ sdot) {
   using P4 = typename Rec<R>::P4;
   using V4 = typename Rec<R>::V4;
-  constexpr int CH = Rec<R>::CH_S;
+  constexpr int CH = Rec<R>::CH_S * L;
+  const int tl = threadIdx.x / L, sub = threadIdx.x % L;
   __shared__ P4 sp[CH];
   __shared__ V4 sv[CH];
   const R box = (R)A.p.box, half = (R)0.5 * box;
@@ -416,25 +454,26 @@ __global__ __launch_bounds__(64) void k_stress(PassArgs A, const typename Rec<R>
   for (int64_t k_ = blockIdx.x / SPH_XCD, chunk_ = xcd_chunk(ntl); k_ < chunk_; k_ += gridDim.x / SPH_XCD) {
     const int64_t tile = (int64_t)(blockIdx.x % SPH_XCD) * chunk_ + k_;
     if (tile >= ntl) break;
-  TileWalk tw;
-  tw.init(A, tile, A.nbr16, A.cnt);
+  TileWalk<1> tw;
+  tw.begin(A, tile, tl);
   const int64_t a = tw.a;
+  const int64_t slot = a * L + sub;
   const int64_t n = A.n;
   const typename Rec<R>::A2 faa = tw.valid ? fa[a] : typename Rec<R>::A2{0, 1};
   const bool stressed = tw.valid && faa.y < 0;
-  if (tw.valid && !stressed) {  // fluid particle (or fluidized): no deviatoric stress evolution
+  if (tw.valid && !stressed && sub == 0) {  // fluid particle (or fluidized): no deviatoric stress evolution
     for (int c = 0; c < 6; ++c) dSdt[c * n + a] = 0.0;
     sdot[a] = 0.0;
   }
-  if (!__ballot(stressed)) continue;   // whole tile fluid
-  if (!stressed) tw.cnt = 0, tw.next = kNone;
+  if (!__syncthreads_or(stressed)) continue;   // whole tile fluid
+  tw.start(reinterpret_cast<const uint4*>(A.nbr16) + slot, A.capw * L, stressed ? A.cnt_sl[slot] : 0, 0);
   const sph_params& p = A.p;
   const P4 pa = tw.valid ? pos[a] : P4{0, 0, 0, 1};
   const V4 va = tw.valid ? fv[a] : V4{0, 0, 0, 0};
   R G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   for (int c0 = 0; c0 < tw.usize; c0 += CH) {
     __syncthreads();
-    for (int j = threadIdx.x; j < CH && c0 + j < tw.usize; j += 64) {
+    for (int j = threadIdx.x; j < CH && c0 + j < tw.usize; j += 64 * L) {
       const int32_t b = tw.U[c0 + j];
       sp[j] = pos[b];
       sv[j] = fv[b];
@@ -467,7 +506,11 @@ __global__ __launch_bounds__(64) void k_stress(PassArgs A, const typename Rec<R>
       }
     }
   }
-  if (!stressed) continue;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj) G[i][jj] = lane_group_sum<L>(G[i][jj]);
+  if (!stressed || sub != 0) continue;
   const double m = particle_mass(A, a);
   const double D = -(double)faa.y;  // stressed particles store -D
   const double iD2 = m / (2.0 * D);
@@ -516,18 +559,21 @@ struct ForceOut {
   double *ax, *ay, *az, *dudt;
 };
 
-template <typename R, int KER, bool PER>
-__global__ __launch_bounds__(64) void k_forces(PassArgs A, const typename Rec<R>::P4* __restrict__ pos,
-                                               const typename Rec<R>::V4* __restrict__ fv,
-                                               const typename Rec<R>::A2* __restrict__ fa,
-                                               const R* __restrict__ sig, const double4* __restrict__ pos64,
-                                               const double* __restrict__ u, const double* __restrict__ P,
-                                               const double* __restrict__ rho, const double* __restrict__ sdot,
-                                               ForceOut O) {
+// Lane g of the L-wave workgroup walks the exact slot list (g / L, g % L); the partial sums of a
+// target's L lanes are added before the fixed-background epilogue.
+template <typename R, int KER, bool PER, int L>
+__global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Rec<R>::P4* __restrict__ pos,
+                                                   const typename Rec<R>::V4* __restrict__ fv,
+                                                   const typename Rec<R>::A2* __restrict__ fa,
+                                                   const R* __restrict__ sig, const double4* __restrict__ pos64,
+                                                   const double* __restrict__ u, const double* __restrict__ P,
+                                                   const double* __restrict__ rho, const double* __restrict__ sdot,
+                                                   ForceOut O) {
   using P4 = typename Rec<R>::P4;
   using V4 = typename Rec<R>::V4;
   using A2 = typename Rec<R>::A2;
-  constexpr int CH = Rec<R>::CH_F;
+  constexpr int CH = Rec<R>::CH_F * L;
+  const int tl = threadIdx.x / L, sub = threadIdx.x % L;
   __shared__ P4 sp[CH];
   __shared__ V4 sv[CH];
   __shared__ A2 sa2[CH];
@@ -536,9 +582,11 @@ __global__ __launch_bounds__(64) void k_forces(PassArgs A, const typename Rec<R>
   for (int64_t k_ = blockIdx.x / SPH_XCD, chunk_ = xcd_chunk(ntl); k_ < chunk_; k_ += gridDim.x / SPH_XCD) {
     const int64_t tile = (int64_t)(blockIdx.x % SPH_XCD) * chunk_ + k_;
     if (tile >= ntl) break;
-  TileWalk tw;
-  tw.init(A, tile, A.nbr16, A.cnt);
+  TileWalk<1> tw;
+  tw.begin(A, tile, tl);
   const int64_t a = tw.a;
+  const int64_t slot = a * L + sub;
+  tw.start(reinterpret_cast<const uint4*>(A.nbr16) + slot, A.capw * L, tw.valid ? A.cnt_sl[slot] : 0, 0);
   const int64_t n = A.n;
   const sph_params& p = A.p;
   const P4 pa = tw.valid ? pos[a] : P4{0, 0, 0, 1};
@@ -555,7 +603,7 @@ __global__ __launch_bounds__(64) void k_forces(PassArgs A, const typename Rec<R>
   R AP[3] = {0, 0, 0}, AS[3] = {0, 0, 0}, ud = 0;
   for (int c0 = 0; c0 < tw.usize; c0 += CH) {
     __syncthreads();
-    for (int j = threadIdx.x; j < CH && c0 + j < tw.usize; j += 64) {
+    for (int j = threadIdx.x; j < CH && c0 + j < tw.usize; j += 64 * L) {
       const int32_t b = tw.U[c0 + j];
       sp[j] = pos[b];
       sv[j] = fv[b];
@@ -616,7 +664,13 @@ __global__ __launch_bounds__(64) void k_forces(PassArgs A, const typename Rec<R>
       }
     }
   }
-  if (!tw.valid) continue;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    AP[i] = lane_group_sum<L>(AP[i]);
+    AS[i] = lane_group_sum<L>(AS[i]);
+  }
+  ud = lane_group_sum<L>(ud);
+  if (!tw.valid || sub != 0) continue;
   const double m = particle_mass(A, a);
   double APd[3] = {m * (double)AP[0], m * (double)AP[1], m * (double)AP[2]};
   double ASd[3] = {m * (double)AS[0], m * (double)AS[1], m * (double)AS[2]};
@@ -671,7 +725,8 @@ PassArgs make_args(sph_ctx* c, sph_state* st) {
   A.tile_u = c->tile_u;
   A.tile_usize = c->tile_usize;
   A.nbr16 = c->nbr16;
-  A.cnt = c->nbr_count;
+  A.cnt_sl = c->nbr_count_sl;
+  A.cap_sl = slot_capacity(c->cap, pass_lanes(c->p));
   A.nbr16s = c->nbr16s;
   A.cnt_s = c->nbr_count_s;
   A.star = c->stars ? st->star : nullptr;
@@ -705,53 +760,72 @@ static dim3 pass_grid(const sph_ctx* c) {
   return dim3((unsigned)(c->cap_tiles < 65536 ? c->cap_tiles : 65536));
 }
 
+// Calls f(L) with the pair passes' lanes per target as a compile-time constant.
+template <typename Fn>
+static void dispatch_lanes(int lanes, Fn&& f) {
+  if (lanes == 4) f(std::integral_constant<int, 4>{});
+  else if (lanes == 2) f(std::integral_constant<int, 2>{});
+  else f(std::integral_constant<int, 1>{});
+}
+
 sph_status launch_density(sph_ctx* c, sph_state* st) {
   PassArgs A = make_args(c, st);
   DensOut O{st->D, st->rho, st->P, st->cs, c->mu, c->Y0, c->B, c->fv, c->fa, c->sig, c->fvf, c->faf, c->sigf};
-  const dim3 g = pass_grid(c), b(64);
+  const dim3 g = pass_grid(c);
+  const bool f32 = c->p.precision == SPH_FP32;
+  dispatch_cfg(c->p.kernel, c->p.periodic, [&](auto K, auto P) {
+    dispatch_lanes(pass_lanes(c->p), [&](auto LL) {
+      constexpr int KER = decltype(K)::value;
+      constexpr bool PER = decltype(P)::value;
+      constexpr int L = decltype(LL)::value;
+      const dim3 b(64 * L);
+      if (f32)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_density<float, KER, PER, L>), g, b, 0, c->stream, A, c->pos4, O,
+                           c->nbr16, c->nbr_count, c->nbr_count_sl);
+      else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_density<double, KER, PER, L>), g, b, 0, c->stream, A, c->pos4, O,
+                           c->nbr16, c->nbr_count, c->nbr_count_sl);
+    });
+  });
+  HIP_TRY(hipGetLastError());
+  return SPH_OK;
+}
+
+sph_status launch_eos(sph_ctx* c, sph_state* st) {
+  PassArgs A = make_args(c, st);
+  DensOut O{st->D, st->rho, st->P, st->cs, c->mu, c->Y0, c->B, c->fv, c->fa, c->sig, c->fvf, c->faf, c->sigf};
   const bool f32 = c->p.precision == SPH_FP32;
   const bool mlp = c->p.eos == SPH_EOS_MLP && A.has_mlp;
-  dispatch_cfg(c->p.kernel, c->p.periodic, [&](auto K, auto P) {
-    constexpr int KER = decltype(K)::value;
-    constexpr bool PER = decltype(P)::value;
-    if (f32 && mlp)
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_density<float, KER, PER, false>), g, b, 0, c->stream, A, c->pos4, st->vx,
-                         st->vy, st->vz, st->u, st->S, st->type, st->broken, O, c->nbr16, c->nbr_count);
-    else if (f32)
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_density<float, KER, PER, true>), g, b, 0, c->stream, A, c->pos4, st->vx,
-                         st->vy, st->vz, st->u, st->S, st->type, st->broken, O, c->nbr16, c->nbr_count);
-    else if (mlp)
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_density<double, KER, PER, false>), g, b, 0, c->stream, A, c->pos4, st->vx,
-                         st->vy, st->vz, st->u, st->S, st->type, st->broken, O, c->nbr16, c->nbr_count);
-    else
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_density<double, KER, PER, true>), g, b, 0, c->stream, A, c->pos4, st->vx,
-                         st->vy, st->vz, st->u, st->S, st->type, st->broken, O, c->nbr16, c->nbr_count);
-  });
-  if (mlp) {
-    const unsigned nb = (unsigned)((st->n + 63) / 64 < 65536 ? (st->n + 63) / 64 : 65536);
-    if (f32)
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_density_epilogue<float>), dim3(nb), b, 0, c->stream, A, c->pos4, st->vx,
-                         st->vy, st->vz, st->u, st->S, st->type, st->broken, O);
-    else
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_density_epilogue<double>), dim3(nb), b, 0, c->stream, A, c->pos4, st->vx,
-                         st->vy, st->vz, st->u, st->S, st->type, st->broken, O);
-  }
+  const unsigned nb = (unsigned)((st->n + 63) / 64 < 65536 ? (st->n + 63) / 64 : 65536);
+  const dim3 b(64);
+  auto epi = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(nb), b, 0, c->stream, A, c->pos4, st->vx, st->vy, st->vz, st->u, st->S, st->type,
+                       st->broken, O);
+  };
+  if (f32 && mlp) epi(k_density_epilogue<float, true>);
+  else if (f32) epi(k_density_epilogue<float, false>);
+  else if (mlp) epi(k_density_epilogue<double, true>);
+  else epi(k_density_epilogue<double, false>);
   HIP_TRY(hipGetLastError());
   return SPH_OK;
 }
 
 sph_status launch_stress(sph_ctx* c, sph_state* st) {
   PassArgs A = make_args(c, st);
-  const dim3 g = pass_grid(c), b(64);
+  const dim3 g = pass_grid(c);
   dispatch_cfg(c->p.kernel, c->p.periodic, [&](auto K, auto P) {
-    constexpr int KER = decltype(K)::value;
-    constexpr bool PER = decltype(P)::value;
-    if (c->p.precision == SPH_FP32)
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stress<float, KER, PER>), g, b, 0, c->stream, A, c->pos4f, c->fvf, c->faf,
-                         st->S, c->mu, st->dSdt, c->sdot);
-    else
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stress<double, KER, PER>), g, b, 0, c->stream, A, c->pos4, c->fv, c->fa,
-                         st->S, c->mu, st->dSdt, c->sdot);
+    dispatch_lanes(pass_lanes(c->p), [&](auto LL) {
+      constexpr int KER = decltype(K)::value;
+      constexpr bool PER = decltype(P)::value;
+      constexpr int L = decltype(LL)::value;
+      const dim3 b(64 * L);
+      if (c->p.precision == SPH_FP32)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stress<float, KER, PER, L>), g, b, 0, c->stream, A, c->pos4f, c->fvf,
+                           c->faf, st->S, c->mu, st->dSdt, c->sdot);
+      else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stress<double, KER, PER, L>), g, b, 0, c->stream, A, c->pos4, c->fv,
+                           c->fa, st->S, c->mu, st->dSdt, c->sdot);
+    });
   });
   HIP_TRY(hipGetLastError());
   return SPH_OK;
@@ -760,16 +834,20 @@ sph_status launch_stress(sph_ctx* c, sph_state* st) {
 sph_status launch_forces(sph_ctx* c, sph_state* st) {
   PassArgs A = make_args(c, st);
   ForceOut O{st->ax, st->ay, st->az, st->dudt};
-  const dim3 g = pass_grid(c), b(64);
+  const dim3 g = pass_grid(c);
   dispatch_cfg(c->p.kernel, c->p.periodic, [&](auto K, auto P) {
-    constexpr int KER = decltype(K)::value;
-    constexpr bool PER = decltype(P)::value;
-    if (c->p.precision == SPH_FP32)
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forces<float, KER, PER>), g, b, 0, c->stream, A, c->pos4f, c->fvf, c->faf,
-                         c->sigf, c->pos4, st->u, st->P, st->rho, c->sdot, O);
-    else
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forces<double, KER, PER>), g, b, 0, c->stream, A, c->pos4, c->fv, c->fa,
-                         c->sig, c->pos4, st->u, st->P, st->rho, c->sdot, O);
+    dispatch_lanes(pass_lanes(c->p), [&](auto LL) {
+      constexpr int KER = decltype(K)::value;
+      constexpr bool PER = decltype(P)::value;
+      constexpr int L = decltype(LL)::value;
+      const dim3 b(64 * L);
+      if (c->p.precision == SPH_FP32)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forces<float, KER, PER, L>), g, b, 0, c->stream, A, c->pos4f, c->fvf,
+                           c->faf, c->sigf, c->pos4, st->u, st->P, st->rho, c->sdot, O);
+      else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forces<double, KER, PER, L>), g, b, 0, c->stream, A, c->pos4, c->fv,
+                           c->fa, c->sig, c->pos4, st->u, st->P, st->rho, c->sdot, O);
+    });
   });
   HIP_TRY(hipGetLastError());
   return SPH_OK;

@@ -19,7 +19,7 @@ STATUS = {0: "SPH_OK", 1: "SPH_E_ARG", 2: "SPH_E_HIP", 3: "SPH_E_OOM", 4: "SPH_E
 
 EXPORTED = ("sph_create", "sph_destroy", "sph_set_params", "sph_build_cells", "sph_density",
             "sph_stress_rate", "sph_forces", "sph_step", "sph_sync", "sph_export_neighbours",
-            "sph_status_string", "sph_set_timing", "sph_get_timing", "sph_neighbour_stats",
+            "sph_status_string", "sph_error_particle", "sph_set_timing", "sph_get_timing", "sph_neighbour_stats",
             "sph_mlp_set_params", "sph_mlp_get_params", "sph_mlp_get_norm", "sph_mlp_train", "sph_mlp_grad",
             "sph_mlp_eval", "sph_mlp_build_trust_mask", "sph_ensemble_set", "sph_autotune")
 MLP_NPARAM = 8642
@@ -42,12 +42,13 @@ class SphParams(ctypes.Structure):
         ("eps_break", ctypes.c_double), ("rotation", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("max_neighbours", ctypes.c_int32), ("cell_div", ctypes.c_int32),
         ("tile_cut", ctypes.c_double), ("skin", ctypes.c_double),
-        ("pass_blocks", ctypes.c_int32), ("graph", ctypes.c_int32),
+        ("pass_blocks", ctypes.c_int32), ("graph", ctypes.c_int32), ("lanes", ctypes.c_int32),
     ]
 
 
 class SphTuneResult(ctypes.Structure):
-    _fields_ = [("pass_blocks", ctypes.c_int32), ("trials", ctypes.c_int32), ("tile_cut", ctypes.c_double),
+    _fields_ = [("pass_blocks", ctypes.c_int32), ("trials", ctypes.c_int32), ("lanes", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("tile_cut", ctypes.c_double),
                 ("skin", ctypes.c_double), ("ms_per_step", ctypes.c_double),
                 ("ms_per_step_start", ctypes.c_double)]
 
@@ -65,9 +66,11 @@ class SphState(ctypes.Structure):
 
 
 class SphError(RuntimeError):
-    def __init__(self, code, what):
-        super().__init__(f"{what}: {STATUS.get(code, code)}")
+    def __init__(self, code, what, particle=None):
+        at = f" (particle {particle})" if particle is not None and particle >= 0 else ""
+        super().__init__(f"{what}: {STATUS.get(code, code)}{at}")
         self.code = code
+        self.particle = particle
 
 
 _lib = None
@@ -92,6 +95,8 @@ def load():
         getattr(L, f).argtypes = [vp, S]
     L.sph_step.argtypes = [vp, S, ctypes.c_double, ctypes.c_int32]
     L.sph_sync.argtypes = [vp]
+    L.sph_error_particle.argtypes = [vp]
+    L.sph_error_particle.restype = ctypes.c_int32
     L.sph_export_neighbours.argtypes = [vp, vp, vp, ctypes.c_int64]
     L.sph_status_string.argtypes = [ctypes.c_int]
     L.sph_status_string.restype = ctypes.c_char_p
@@ -174,7 +179,7 @@ class Context:
     DEFAULT_SKIN = 0.1
 
     def __init__(self, params, capacity: int, stream=None, max_neighbours=0, cell_div=0, tile_cut=0.0,
-                 skin=None, pass_blocks=0, graph=False):
+                 skin=None, pass_blocks=0, graph=False, lanes=0):
         import torch
         from sph_inputs.params import (BACKGROUNDS, BREAK_MODES, EOS_KINDS, H_MODES, KERNELS, MU_MODES,
                                        PRECISIONS, ROTATIONS, Y0_MODES, YIELD_MODES)
@@ -219,6 +224,7 @@ class Context:
         p.skin = self.DEFAULT_SKIN if skin is None else skin
         p.pass_blocks = int(pass_blocks)
         p.graph = int(bool(graph))
+        p.lanes = int(lanes)
         self.p = p
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = ctypes.c_void_p()
@@ -254,7 +260,11 @@ class Context:
         _check(self.lib.sph_step(self.h, ctypes.byref(st.struct), float(dt), int(nsteps)), "sph_step")
 
     def sph_sync(self):
-        _check(self.lib.sph_sync(self.h), "sph_sync")
+        """Waits; raises SphError for a latched device error, with .particle the array index (in
+        the current order) of the particle that raised it, or -1."""
+        rc = self.lib.sph_sync(self.h)
+        if rc != 0:
+            raise SphError(rc, "sph_sync", int(self.lib.sph_error_particle(self.h)))
 
     def sph_export_neighbours(self, n: int, cap: int = None):
         off = np.zeros(n + 1, np.int64)
@@ -284,7 +294,7 @@ class Context:
         return {k: getattr(s, k) for k in ("pairs", "max_count", "tiles", "union_total", "candidates",
                                            "rebuilds")}
 
-    def sph_autotune(self, st: DeviceState, dt: float, steps_per_trial: int = 8):
+    def sph_autotune(self, st: DeviceState, dt: float, steps_per_trial: int = 64):
         r = SphTuneResult()
         _check(self.lib.sph_autotune(self.h, ctypes.byref(st.struct), float(dt), int(steps_per_trial),
                                      ctypes.byref(r)), "sph_autotune")

@@ -37,7 +37,7 @@ def _fibonacci_sphere(k: int):
 
 
 def place_star(bg: Background, N: int, seed: int, jitter: float = 0.05):
-    """Return (x, y, z, shell_radius) of N equal-mass particles; m = M_b / N."""
+    """Return (x, y, z, shell_radius, m) of N equal-mass particles; m = M_b / N."""
     rng = np.random.Generator(np.random.PCG64(seed))
     Mb = bg.mc[-1]
     m = Mb / N
@@ -66,6 +66,11 @@ def place_star(bg: Background, N: int, seed: int, jitter: float = 0.05):
     cum[-1] = N
     cum = np.maximum.accumulate(cum)
     counts = np.diff(cum)
+    # a last shell holding under a tenth of the particles of the one below (a tenuous envelope)
+    # is merged into it: its few particles would otherwise need supports spanning the star
+    while len(counts) > 2 and 0 < counts[-1] < 0.1 * counts[-2]:
+        counts = np.append(counts[:-2], counts[-2] + counts[-1])
+        edges = np.append(edges[:-2], edges[-1])
     pts, radii = [], []
     for k, cnt in enumerate(counts):
         if cnt <= 0:

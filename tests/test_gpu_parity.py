@@ -246,3 +246,41 @@ def test_skin_lists_match_rebuild_every_evaluation():
             assert v < 1e-11, (s, k, v)
     assert runs[0.05]["_stats"]["rebuilds"] <= runs[1e-3]["_stats"]["rebuilds"] <= 9
     assert runs[1e-3]["_stats"]["rebuilds"] >= 2
+
+
+@pytest.mark.parametrize("lanes", [1, 4])
+def test_lanes_per_target(lanes):
+    # 1 and 4 lanes per target (the default is 2): same exact neighbour sets, fields to the
+    # evaluation tolerance, steps to the state tolerance
+    w = W.star(20000, seed=3, kernel="WC4", eta=W.ETA_100, l=2, A=1e-2, plastic=True)
+    g = gpu_run(w, ctx_kw={"lanes": lanes})
+    o = oracle_run(w)
+    assert check_lists(g, o, w.n) == 0
+    _assert_eval(g, o)
+    g = gpu_run(w, steps=5, ctx_kw={"lanes": lanes})
+    o = oracle_run(w, steps=5)
+    e = field_errors(g, o, ("x", "y", "z", "vx", "vy", "vz", "u", "h", "S", "D", "ax", "dudt", "dSdt"))
+    _print(f"lanes {lanes}, 5 steps", e)
+    for k, v in e.items():
+        assert v < 1e-9, (k, v)
+    for ker, periodic in (("WC2", True), ("WC4", False)):   # ragged tiles, both kernels, periodic
+        x, y, z = random_box(1000, 1.0, 7)
+        rng = np.random.default_rng(8)
+        n = 1000
+        S = rng.normal(scale=0.2, size=(6, n))
+        S[:3] -= S[:3].mean(0)
+        typ = (rng.uniform(size=n) < 0.5).astype(np.int8)
+        S[:, typ == 0] = 0      # fluid particles carry no deviatoric stress
+        arr = dict(x=x, y=y, z=z, vx=rng.normal(scale=0.1, size=n), vy=rng.normal(scale=0.1, size=n),
+                   vz=rng.normal(scale=0.1, size=n), u=rng.uniform(0.5, 2, n), h=0.035 * rng.uniform(0.5, 2.0, n),
+                   S=S, type=typ, broken=np.zeros(n, np.uint8), id=np.arange(n, dtype=np.int32))
+        p = MethodParams(m=1.0 / n, kernel=ker, periodic=periodic, box=1.0, eos="GAMMA_LAW", gamma=5 / 3,
+                         mu_mode="CONST", mu_const=0.5, precision="FP32")
+        wr = W.Workload("rand", p, arr, 1e-3, 0)
+        g = gpu_run(wr, ctx_kw={"lanes": lanes})
+        o = oracle_run(wr, mode=oracle.BRUTE)
+        assert check_lists(g, o, n) == 0
+        ef = eval_errors(g, o)
+        _print(f"lanes {lanes} {ker} periodic={periodic} fp32", ef)
+        for k in ("D", "rho", "P", "ax", "ay", "az", "dudt"):
+            assert ef[k] < 1e-4, (k, ef[k])
