@@ -9,6 +9,8 @@ stage breakdown, the force-pass roofline and the CPU-oracle baseline ride along.
 """
 import argparse
 import json
+
+import numpy as np
 import os
 import sys
 import time
@@ -116,6 +118,56 @@ def run_variant(w, precision, eos, steps, warmup, timing=True, ctx_kw=None, mlp=
             "pairs": pairs, "max_neighbours": maxc, "stats": stats, "trusted_cells": trusted}
 
 
+def run_ensemble(surrogate, steps, warmup):
+    """64 uneven piecewise-polytrope stars, 8M particles in one particle set (per-star masses,
+    shear factors and background centres), FP32 pair sums with the EoS network: first eager with
+    the default launch settings, then with the settings the autotuner picks, replaying each step
+    from captured HIP graphs on a non-default stream."""
+    import torch
+
+    from paper_2107_07315_amd import sph
+    from sph_inputs import workloads as W
+    w = W.ensemble(64, 8_000_000, seed=5, precision="FP32", kind="pp")
+    out = {"workload": f"{len(w.star_params)} piecewise-polytrope stars of {int(min(np.diff(w.star_offsets)))} to "
+                       f"{int(max(np.diff(w.star_offsets)))} particles, {w.n} in total, FP32 pair sums, "
+                       + ("EoS network" if surrogate is not None else "tabulated EoS"),
+           "n_particles": w.n, "nstars": int(len(w.star_params)), "steps": steps}
+    s = torch.cuda.Stream()
+    for mode in ("eager", "graph_tuned"):
+        with torch.cuda.stream(s):
+            ctx = sph.Context(w.params.replace(eos="MLP" if surrogate is not None else "TABLE"), capacity=w.n,
+                              stream=s, graph=(mode != "eager"))
+            ctx.sph_ensemble_set(w.star_params)
+            if surrogate is not None:
+                ctx.mlp_set_params(surrogate["params"])
+                ctx.mlp_build_trust_mask(1e-4)
+            st = sph.DeviceState(w.arrays)
+            if mode != "eager":
+                t0 = time.perf_counter()
+                tr = ctx.sph_autotune(st, w.dt, 64)
+                tr["seconds"] = round(time.perf_counter() - t0, 2)
+                out["autotune"] = tr
+            ctx.evaluate(st)
+            ctx.sph_step(st, w.dt, warmup)
+            ctx.sph_sync()
+            r0 = ctx.sph_neighbour_stats()["rebuilds"]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.sph_step(st, w.dt, steps)
+            ctx.sph_sync()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            out[mode] = {"value": w.n * steps / (t1 - t0), "ms_per_step": (t1 - t0) * 1e3 / steps,
+                         "rebuilds": ctx.sph_neighbour_stats()["rebuilds"] - r0}
+            ctx.close()
+            del st
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        print(f"# ensemble {mode}: {out[mode]['ms_per_step']:.3f} ms/step, {out[mode]['value']:.4g} "
+              f"particle-updates/s", file=sys.stderr, flush=True)
+    return out
+
+
 def roofline(res, n, precision):
     """Roofline entry of the variant's dominant pair pass (longest average launch)."""
     st = res["stats"]
@@ -170,6 +222,8 @@ def main():
                          "trust mask (tolerance 1e-4, or @tol) accepts the table cell")
     ap.add_argument("--mlp-epochs", type=int, default=400)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ensemble-steps", type=int, default=50,
+                    help="steps of the 64-star, 8M-particle ensemble run (0: skip it)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -240,6 +294,8 @@ def main():
     if "FP64" in res:
         out["speedup_vs_fp64"] = round(r["value"] / res["FP64"]["value"], 3)
         out["roofline_fp64"] = roofline(res["FP64"], w.n, "FP64")
+    if args.ensemble_steps > 0:
+        out["ensemble"] = run_ensemble(surrogate, args.ensemble_steps, 5)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

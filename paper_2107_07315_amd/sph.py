@@ -298,7 +298,7 @@ class Context:
         r = SphTuneResult()
         _check(self.lib.sph_autotune(self.h, ctypes.byref(st.struct), float(dt), int(steps_per_trial),
                                      ctypes.byref(r)), "sph_autotune")
-        return {k: getattr(r, k) for k, _ in SphTuneResult._fields_}
+        return {k: getattr(r, k) for k, _ in SphTuneResult._fields_ if k != "pad"}
 
     def sph_ensemble_set(self, star_info):
         """star_info: [nstars, 5] rows of (centre x, y, z, particle mass, shear factor)."""
