@@ -122,7 +122,7 @@ struct TileWalk {
   int64_t p, a;
   bool valid;
   int usize, cnt, k, next, pre;
-  const uint4* grp_base;   // group g at grp_base[g * gstride]
+  const uint4* gnext;      // the group after nxt (groups are gstride apart)
   int64_t gstride;
   uint4 cur, nxt;
   const int32_t* U;
@@ -136,22 +136,25 @@ struct TileWalk {
   }
   // cnt = entries this lane takes
   __device__ __forceinline__ void start(const uint4* base, int64_t stride, int count, int pre_) {
-    grp_base = base;
     gstride = stride;
     cnt = count;
     pre = pre_;
     k = 0;
     cur = make_uint4(0u, 0u, 0u, 0u);
     nxt = cur;
-    if (cnt > 0) cur = STEP > 1 ? shr_entries(grp_base[0], pre) : grp_base[0];
-    if (cnt > E) nxt = grp_base[gstride];
+    if (cnt > 0) cur = STEP > 1 ? shr_entries(base[0], pre) : base[0];
+    if (cnt > E) nxt = base[gstride];
+    gnext = base + 2 * gstride;
     next = cnt > 0 ? (int)(cur.x & 0xffffu) : kNone;
   }
   __device__ __forceinline__ void advance() {
     ++k;
     if ((k & (E - 1)) == 0) {
       cur = STEP > 1 ? shr_entries(nxt, pre) : nxt;
-      if (k + E < cnt) nxt = grp_base[(int64_t)(k / E + 1) * gstride];
+      if (k + E < cnt) {
+        nxt = *gnext;
+        gnext += gstride;
+      }
     } else if constexpr (STEP == 1) {
       cur.x = __builtin_amdgcn_alignbit(cur.y, cur.x, 16u);
       cur.y = __builtin_amdgcn_alignbit(cur.z, cur.y, 16u);
@@ -253,29 +256,38 @@ struct DensOut {
   float* sigf;
 };
 
-// Appends 16-bit local indices to a lane's exact list, 8 per 16-byte store (the layout TileWalk
-// reads).  put() is branch-free except for the store of a full group.
+// Appends 16-bit local indices to a lane's exact list (the layout TileWalk reads).  Entries go to
+// the lane's own 16-byte row in LDS (written at every candidate, kept only on a hit); each full
+// row is stored as one 16-byte group.  No other lane touches the row, so no barrier is needed.
 struct ListWriter {
-  uint4* base;             // group g of this lane at base[g * capw]
-  int64_t capw;
+  uint4* gp;          // where this lane's next group goes
+  int64_t gstride;    // uint4 between consecutive groups
+  uint16_t* row;      // this lane's 8 entries in LDS (16-byte aligned)
   int cap;
   int n;
-  uint32_t w0, w1, w2, w3;
+  __device__ __forceinline__ void init(uint4* base, int64_t stride, uint16_t* r, int cap_) {
+    gp = base;
+    gstride = stride;
+    row = r;
+    cap = cap_;
+    n = 0;
+  }
+  __device__ __forceinline__ uint4 row_group() const {
+    uint4 g;
+    __builtin_memcpy(&g, row, sizeof(g));
+    return g;
+  }
   __device__ __forceinline__ void put(int loc, bool hit) {
-    const uint32_t v = hit ? ((uint32_t)loc << ((n & 1) << 4)) : 0u;
-    const int ws = (n >> 1) & 3;
-    w0 |= ws == 0 ? v : 0u;
-    w1 |= ws == 1 ? v : 0u;
-    w2 |= ws == 2 ? v : 0u;
-    w3 |= ws == 3 ? v : 0u;
+    const uint16_t v = (uint16_t)loc;
+    __builtin_memcpy(row + (n & 7), &v, sizeof(v));
     n += hit ? 1 : 0;
     if (hit && (n & 7) == 0) {
-      if (n <= cap) base[(int64_t)((n >> 3) - 1) * capw] = make_uint4(w0, w1, w2, w3);
-      w0 = w1 = w2 = w3 = 0u;
+      if (n <= cap) *gp = row_group();
+      gp += gstride;
     }
   }
   __device__ __forceinline__ void flush() {
-    if ((n & 7) && n <= cap) base[(int64_t)(n >> 3) * capw] = make_uint4(w0, w1, w2, w3);
+    if ((n & 7) && n <= cap) *gp = row_group();
   }
 };
 
@@ -356,6 +368,7 @@ __global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* _
                                                     int32_t* __restrict__ xcount_sl) {
   constexpr int CH = Rec<R>::CH_D * L;
   __shared__ double4 sp[CH];
+  __shared__ __align__(16) uint16_t lrow[64 * L][8];   // per-lane staging of the exact lists
   const double box = A.p.box, half = 0.5 * box;
   const int tl = threadIdx.x / L, sub = threadIdx.x % L;
   const int64_t ntl = num_tiles(A);
@@ -371,11 +384,7 @@ __global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* _
   const double4 pa = tw.valid ? pos64[a] : make_double4(0.0, 0.0, 0.0, 1.0);
   R sum = sub == 0 ? wendland_self<R>(KER, (R)pa.w) : (R)0;
   ListWriter wr;
-  wr.base = reinterpret_cast<uint4*>(xlist) + slot;
-  wr.capw = A.capw * L;
-  wr.cap = A.cap_sl;
-  wr.n = 0;
-  wr.w0 = wr.w1 = wr.w2 = wr.w3 = 0u;
+  wr.init(reinterpret_cast<uint4*>(xlist) + slot, A.capw * L, lrow[threadIdx.x], A.cap_sl);
   for (int c0 = 0; c0 < tw.usize; c0 += CH) {
     __syncthreads();
     for (int j = threadIdx.x; j < CH && c0 + j < tw.usize; j += 64 * L) sp[j] = pos64[tw.U[c0 + j]];
