@@ -390,27 +390,19 @@ __global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* _
     for (int j = threadIdx.x; j < CH && c0 + j < tw.usize; j += 64 * L) sp[j] = pos64[tw.U[c0 + j]];
     __syncthreads();
     const int cend = c0 + CH;
-    if (tw.next < cend) {
-      double4 pb = sp[tw.next - c0];
-      int loc = tw.next;
+    while (tw.next < cend) {
+      const int loc = tw.next;
+      const double4 pb = sp[loc - c0];
       tw.advance();
-      while (true) {
-        const bool more = tw.next < cend;
-        const double4 pn = sp[more ? tw.next - c0 : 0];
-        const double dx = wrap_sel<PER>(pa.x - pb.x, box, half);
-        const double dy = wrap_sel<PER>(pa.y - pb.y, box, half);
-        const double dz = wrap_sel<PER>(pa.z - pb.z, box, half);
-        const double r2 = pair_r2(dx, dy, dz);
-        const double H = pa.w + pb.w;
-        const bool hit = r2 < H * H;
-        const R W = kern_W<R, KER>(sqrt_fast((R)r2), rcp_fast((R)(0.5 * H)));
-        sum += hit ? W : (R)0;
-        wr.put(loc, hit);
-        if (!more) break;
-        pb = pn;
-        loc = tw.next;
-        tw.advance();
-      }
+      const double dx = wrap_sel<PER>(pa.x - pb.x, box, half);
+      const double dy = wrap_sel<PER>(pa.y - pb.y, box, half);
+      const double dz = wrap_sel<PER>(pa.z - pb.z, box, half);
+      const double r2 = pair_r2(dx, dy, dz);
+      const double H = pa.w + pb.w;
+      const bool hit = r2 < H * H;
+      const R W = kern_W<R, KER>(sqrt_fast((R)r2), rcp_fast((R)(0.5 * H)));
+      sum += hit ? W : (R)0;
+      wr.put(loc, hit);
     }
   }
   wr.flush();
@@ -489,30 +481,20 @@ __global__ __launch_bounds__(64 * L) void k_stress(PassArgs A, const typename Re
     }
     __syncthreads();
     const int cend = c0 + CH;
-    if (tw.next < cend) {
-      P4 pb = sp[tw.next - c0];
-      V4 vb = sv[tw.next - c0];
+    while (tw.next < cend) {
+      const P4 pb = sp[tw.next - c0];
+      const V4 vb = sv[tw.next - c0];
       tw.advance();
-      while (true) {
-        const bool more = tw.next < cend;
-        const int jn = more ? tw.next - c0 : 0;
-        const P4 pn = sp[jn];
-        const V4 vn = sv[jn];
-        const R d[3] = {wrap_sel<PER>(pa.x - pb.x, box, half), wrap_sel<PER>(pa.y - pb.y, box, half),
-                        wrap_sel<PER>(pa.z - pb.z, box, half)};
-        const R r = sqrt_fast(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-        const R F = kern_F<R, KER>(r, rcp_fast((R)0.5 * (pa.w + pb.w)));
-        const R g[3] = {F * d[0], F * d[1], F * d[2]};
-        const R v[3] = {vb.x - va.x, vb.y - va.y, vb.z - va.z};
+      const R d[3] = {wrap_sel<PER>(pa.x - pb.x, box, half), wrap_sel<PER>(pa.y - pb.y, box, half),
+                      wrap_sel<PER>(pa.z - pb.z, box, half)};
+      const R r = sqrt_fast(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      const R F = kern_F<R, KER>(r, rcp_fast((R)0.5 * (pa.w + pb.w)));
+      const R g[3] = {F * d[0], F * d[1], F * d[2]};
+      const R v[3] = {vb.x - va.x, vb.y - va.y, vb.z - va.z};
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
+      for (int i = 0; i < 3; ++i)
 #pragma unroll
-          for (int jj = 0; jj < 3; ++jj) G[i][jj] += v[i] * g[jj];
-        if (!more) break;
-        pb = pn;
-        vb = vn;
-        tw.advance();
-      }
+        for (int jj = 0; jj < 3; ++jj) G[i][jj] += v[i] * g[jj];
     }
   }
 #pragma unroll
@@ -620,56 +602,43 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
     }
     __syncthreads();
     const int cend = c0 + CH;
-    if (tw.next < cend) {
-      P4 pb = sp[tw.next - c0];
-      V4 vb = sv[tw.next - c0];
-      A2 fab = sa2[tw.next - c0];
-      int loc = tw.next;
+    while (tw.next < cend) {
+      const int loc = tw.next;
+      const P4 pb = sp[loc - c0];
+      const V4 vb = sv[loc - c0];
+      const A2 fab = sa2[loc - c0];
       tw.advance();
-      while (true) {
-        const bool more = tw.next < cend;
-        const int jn = more ? tw.next - c0 : 0;
-        const P4 pn = sp[jn];
-        const V4 vn = sv[jn];
-        const A2 fn = sa2[jn];
-        const R d[3] = {wrap_sel<PER>(pa.x - pb.x, box, half), wrap_sel<PER>(pa.y - pb.y, box, half),
-                        wrap_sel<PER>(pa.z - pb.z, box, half)};
-        const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-        const R r = sqrt_fast(r2);
-        const R hab = (R)0.5 * (pa.w + pb.w);
-        const R F = kern_F<R, KER>(r, rcp_fast(hab));
-        const R g[3] = {F * d[0], F * d[1], F * d[2]};
-        const R v[3] = {va.x - vb.x, va.y - vb.y, va.z - vb.z};
-        const R vr = v[0] * d[0] + v[1] * d[1] + v[2] * d[2];
-        const bool b_st = fab.y < 0;
-        const R Db = b_st ? -fab.y : fab.y;
-        // Monaghan viscosity on approaching pairs: one reciprocal gives 1/X and 1/Dbar
-        const R X = r2 + eps_v * hab * hab;
-        const R Dbar = (R)0.5 * (Da + Db);
-        const R inv = rcp_fast(X * Dbar);
-        const R muab = hab * vr * (Dbar * inv);
-        const R cbar = (R)0.5 * (va.w + vb.w);
-        const R Pi = vr < (R)0 ? (-alpha_v * cbar * muab + beta_v * muab * muab) * (X * inv) : (R)0;
-        const R cP = pia + fab.x + Pi;
-        AP[0] += cP * g[0];
-        AP[1] += cP * g[1];
-        AP[2] += cP * g[2];
-        ud += (pia + (R)0.5 * Pi) * (v[0] * g[0] + v[1] * g[1] + v[2] * g[2]);
-        if (a_st || b_st) {
-          R s6[6];
-          const int32_t b = b_st ? tw.U[loc] : 0;
+      const R d[3] = {wrap_sel<PER>(pa.x - pb.x, box, half), wrap_sel<PER>(pa.y - pb.y, box, half),
+                      wrap_sel<PER>(pa.z - pb.z, box, half)};
+      const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+      const R r = sqrt_fast(r2);
+      const R hab = (R)0.5 * (pa.w + pb.w);
+      const R F = kern_F<R, KER>(r, rcp_fast(hab));
+      const R g[3] = {F * d[0], F * d[1], F * d[2]};
+      const R v[3] = {va.x - vb.x, va.y - vb.y, va.z - vb.z};
+      const R vr = v[0] * d[0] + v[1] * d[1] + v[2] * d[2];
+      const bool b_st = fab.y < 0;
+      const R Db = b_st ? -fab.y : fab.y;
+      // Monaghan viscosity on approaching pairs: one reciprocal gives 1/X and 1/Dbar
+      const R X = r2 + eps_v * hab * hab;
+      const R Dbar = (R)0.5 * (Da + Db);
+      const R inv = rcp_fast(X * Dbar);
+      const R muab = hab * vr * (Dbar * inv);
+      const R cbar = (R)0.5 * (va.w + vb.w);
+      const R Pi = vr < (R)0 ? (-alpha_v * cbar * muab + beta_v * muab * muab) * (X * inv) : (R)0;
+      const R cP = pia + fab.x + Pi;
+      AP[0] += cP * g[0];
+      AP[1] += cP * g[1];
+      AP[2] += cP * g[2];
+      ud += (pia + (R)0.5 * Pi) * (v[0] * g[0] + v[1] * g[1] + v[2] * g[2]);
+      if (a_st || b_st) {
+        R s6[6];
+        const int32_t b = b_st ? tw.U[loc] : 0;
 #pragma unroll
-          for (int c = 0; c < 6; ++c) s6[c] = sa[c] + (b_st ? sig[c * n + b] : (R)0);
-          AS[0] += s6[0] * g[0] + s6[3] * g[1] + s6[4] * g[2];
-          AS[1] += s6[3] * g[0] + s6[1] * g[1] + s6[5] * g[2];
-          AS[2] += s6[4] * g[0] + s6[5] * g[1] + s6[2] * g[2];
-        }
-        if (!more) break;
-        pb = pn;
-        vb = vn;
-        fab = fn;
-        loc = tw.next;
-        tw.advance();
+        for (int c = 0; c < 6; ++c) s6[c] = sa[c] + (b_st ? sig[c * n + b] : (R)0);
+        AS[0] += s6[0] * g[0] + s6[3] * g[1] + s6[4] * g[2];
+        AS[1] += s6[3] * g[0] + s6[1] * g[1] + s6[5] * g[2];
+        AS[2] += s6[4] * g[0] + s6[5] * g[1] + s6[2] * g[2];
       }
     }
   }
