@@ -65,7 +65,8 @@ template <> struct Rec<double> {
   using P4 = double4;
   using V4 = double4;
   using A2 = double2;
-  static constexpr int CH_D = 256;   // LDS records per chunk: density 8 KB
+  static constexpr int CH_D = 256;   // LDS records per chunk and wave: density 8 KB
+  static constexpr int CHMAX_D = 768;   // per workgroup (measured best; LDS for 5 workgroups per CU)
   static constexpr int CH_S = 128;   // stress 8 KB
   static constexpr int CH_F = 128;   // forces 10 KB
 };
@@ -74,6 +75,7 @@ template <> struct Rec<float> {
   using V4 = float4;
   using A2 = float2;
   static constexpr int CH_D = 256;   // density records are FP64 in both precisions
+  static constexpr int CHMAX_D = 640;
   static constexpr int CH_S = 256;
   static constexpr int CH_F = 256;
 };
@@ -115,16 +117,18 @@ __device__ __forceinline__ uint4 shr_entries(uint4 v, int m) {
 // Per-lane walk over a list stored as 16-byte groups of 8 16-bit local indices.  A lane takes the
 // entries pre, pre + STEP, pre + 2 STEP, ... of its list (STEP = 1: all of them; STEP = L with
 // pre = the lane's sub-index: the L lanes of a target share its list), 8 / STEP per group.  The
-// group after the current one is always in flight; the current one is consumed by shifts.
+// next AHEAD groups are always in flight (about 8 entries of the lane's own ahead, which covers
+// the load latency); the current group is consumed by shifts.
 template <int STEP>
 struct TileWalk {
   static constexpr int E = 8 / STEP;
+  static constexpr int AHEAD = STEP == 1 ? 1 : (STEP == 2 ? 2 : 4);
   int64_t p, a;
   bool valid;
   int usize, cnt, k, next, pre;
-  const uint4* gnext;      // the group after nxt (groups are gstride apart)
+  const uint4* gnext;      // the group after the ones in flight (groups are gstride apart)
   int64_t gstride;
-  uint4 cur, nxt;
+  uint4 cur, q[AHEAD];
   const int32_t* U;
   // target t of the tile (a = p for a valid target, 0 otherwise)
   __device__ __forceinline__ void begin(const PassArgs& A, int64_t tile, int t) {
@@ -141,18 +145,23 @@ struct TileWalk {
     pre = pre_;
     k = 0;
     cur = make_uint4(0u, 0u, 0u, 0u);
-    nxt = cur;
     if (cnt > 0) cur = STEP > 1 ? shr_entries(base[0], pre) : base[0];
-    if (cnt > E) nxt = base[gstride];
-    gnext = base + 2 * gstride;
+#pragma unroll
+    for (int i = 0; i < AHEAD; ++i) {
+      q[i] = make_uint4(0u, 0u, 0u, 0u);
+      if (cnt > (i + 1) * E) q[i] = base[(i + 1) * gstride];
+    }
+    gnext = base + (AHEAD + 1) * gstride;
     next = cnt > 0 ? (int)(cur.x & 0xffffu) : kNone;
   }
   __device__ __forceinline__ void advance() {
     ++k;
     if ((k & (E - 1)) == 0) {
-      cur = STEP > 1 ? shr_entries(nxt, pre) : nxt;
-      if (k + E < cnt) {
-        nxt = *gnext;
+      cur = STEP > 1 ? shr_entries(q[0], pre) : q[0];
+#pragma unroll
+      for (int i = 0; i + 1 < AHEAD; ++i) q[i] = q[i + 1];
+      if (k + AHEAD * E < cnt) {
+        q[AHEAD - 1] = *gnext;
         gnext += gstride;
       }
     } else if constexpr (STEP == 1) {
@@ -366,7 +375,7 @@ template <typename R, int KER, bool PER, int L>
 __global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* __restrict__ pos64, DensOut O,
                                                     uint16_t* __restrict__ xlist, int32_t* __restrict__ xcount,
                                                     int32_t* __restrict__ xcount_sl) {
-  constexpr int CH = Rec<R>::CH_D * L;
+  constexpr int CH = Rec<R>::CH_D * L < Rec<R>::CHMAX_D ? Rec<R>::CH_D * L : Rec<R>::CHMAX_D;
   __shared__ double4 sp[CH];
   __shared__ __align__(16) uint16_t lrow[64 * L][8];   // per-lane staging of the exact lists
   const double box = A.p.box, half = 0.5 * box;
