@@ -114,7 +114,7 @@ typedef struct {
                            /*   twice as many                                                  */
   int32_t cell_div;        /* cells per smoothing diameter of the finest level (0: 2)          */
   double tile_cut;         /* a 64-particle tile is cut where the Morton curve jumps farther  */
-                           /*   than tile_cut smoothing lengths (0: 6)                         */
+                           /*   than tile_cut smoothing lengths (0: 10)                        */
   double skin;             /* relative Verlet skin s: candidate lists hold every b with       */
                            /*   |x_a - x_b| < (1 + s)(h_a + h_b) and are rebuilt only when a    */
                            /*   particle has moved, plus grown in h, by more than s h since the */

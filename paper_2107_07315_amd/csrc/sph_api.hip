@@ -477,7 +477,7 @@ sph_status sph_autotune(sph_ctx* c, const sph_state* st, double dt, int32_t step
     return sph_sync(c);
   };
   sph_params best = c->p;
-  if (best.tile_cut <= 0.0) best.tile_cut = 6.0;
+  best.tile_cut = tile_cut_of(best);
   if (best.lanes <= 0) best.lanes = pass_lanes(best);
   double best_ms = 0.0;
   int32_t trials = 1;
@@ -489,7 +489,7 @@ sph_status sph_autotune(sph_ctx* c, const sph_state* st, double dt, int32_t step
   // coordinate descent: lanes per target, workgroup schedule of the pair passes, tile cut, skin;
   // a setting replaces the best only if it is faster by more than the timing noise (2%)
   for (int dim = 0; dim < 4 && !e; ++dim) {
-    const double vals[4][4] = {{1, 2, 4, -1}, {0, 1024, 4096, 16384}, {4, 6, 8, -1}, {0.05, 0.1, 0.15, -1}};
+    const double vals[4][4] = {{1, 2, 4, -1}, {0, 1024, 4096, 16384}, {6, 8, 10, 12}, {0.05, 0.1, 0.15, -1}};
     const sph_params base = best;
     for (int k = 0; k < 4 && !e; ++k) {
       const double v = vals[dim][k];

@@ -870,7 +870,7 @@ sph_status sph_rebin(sph_ctx* c, sph_state* st) {
   uint32_t* flag = reinterpret_cast<uint32_t*>(c->tmp);
   uint32_t* idx = flag + c->capw;
   hipLaunchKernelGGL(k_tile_flags, dim3(nb), dim3(kB), 0, s, c->keys, c->pos4, n, c->grid,
-                     c->p.tile_cut > 0.0 ? c->p.tile_cut : 6.0, flag);
+                     tile_cut_of(c->p), flag);
   hipLaunchKernelGGL(k_level_hmax, dim3(nred), dim3(kB), 0, s, c->pos4, n, c->grid);
   hipLaunchKernelGGL(k_grid_setup2, dim3(1), dim3(1), 0, s, c->grid, c->p.cell_div > 0 ? c->p.cell_div : 2,
                      c->max_cells, c->status);

@@ -396,6 +396,8 @@ __host__ __device__ __forceinline__ int64_t nbr_index(int64_t k, int64_t p, int6
 // hits (and the particle's list at most cap).  Slot s of the exact lists is entry k at
 // nbr_index(k, s, capw * L).
 __host__ __device__ __forceinline__ int pass_lanes(const sph_params& p) { return p.lanes > 0 ? p.lanes : 4; }
+// Tile cut in smoothing lengths (the measured best with 4 lanes per target on the 2M star)
+__host__ __device__ __forceinline__ double tile_cut_of(const sph_params& p) { return p.tile_cut > 0.0 ? p.tile_cut : 10.0; }
 __host__ __device__ __forceinline__ int slot_capacity(int cap, int L) {
   const int c = (2 * cap + L - 1) / L;
   return ((c < cap ? c : cap) + 7) / 8 * 8;
