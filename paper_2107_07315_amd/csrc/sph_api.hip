@@ -151,7 +151,7 @@ sph_status sph_create(const sph_params* params, void* stream, int64_t capacity, 
       (e = dalloc(&c->sort.scan_bsum, c->sort.scan_cap + 1)) ||
       (e = dalloc(&c->nbr16, (size_t)capw * slot_entries_max(c->cap))) || (e = dalloc(&c->nbr_count, capw)) ||
       (e = dalloc(&c->nbr_count_sl, (size_t)capw * 4)) ||
-      (e = dalloc(&c->nbr16s, (size_t)capw * c->cap_s)) || (e = dalloc(&c->nbr_count_s, capw)) ||
+      (e = dalloc(&c->nbr16s, (size_t)capw * (c->cap_s + 32))) || (e = dalloc(&c->nbr_count_s, capw)) ||
       (e = dalloc(&c->pos_build, cap)) || (e = dalloc(&c->drift_flag, 1)) ||
       (e = dalloc(&c->pos4, cap)) || (e = dalloc(&c->fv, cap)) || (e = dalloc(&c->fa, cap)) ||
       (e = dalloc(&c->sig, 6 * cap)) || (e = dalloc(&c->pos4f, cap)) || (e = dalloc(&c->fvf, cap)) ||

@@ -365,8 +365,10 @@ struct BuildArgs {
   int cap, ucap;
   int32_t* __restrict__ tile_u;
   int32_t* __restrict__ tile_usize;
-  uint16_t* __restrict__ nbr16;
-  int32_t* __restrict__ count;
+  uint16_t* __restrict__ nbr16;     // candidate slot lists
+  int32_t* __restrict__ count;       // candidates per particle
+  int lanes;                         // slots per particle (lanes per target of the pair passes)
+  int cap_sl;                        // entries a slot holds
   DevStatus* status;
 };
 
@@ -399,12 +401,24 @@ struct TileState {
   int usize, cnt, ucap;
   int64_t p;
   int32_t* U;
-  uint32_t w0, w1, w2, w3;   // the lane's current group of 8 list entries
+  uint16_t (*row)[8];        // the lane's staging rows in LDS, one per slot
 };
 
-// Stores the lane's group g of 8 entries (16 bytes, the layout the pair passes read).
-__device__ __forceinline__ void store_group(const BuildArgs& B, const TileState& T, int g) {
-  reinterpret_cast<uint4*>(B.nbr16)[(int64_t)g * B.capw + T.p] = make_uint4(T.w0, T.w1, T.w2, T.w3);
+// Candidate k of a particle goes to its slot k % lanes, as entry k / lanes: each lane of the
+// density pass then walks one contiguous slot list.  Entries are staged in the slot's 16-byte
+// LDS row and stored a full group of 8 at a time (group g of slot s at g * capw * lanes + s).
+__device__ __forceinline__ void store_slot_group(const BuildArgs& B, const TileState& T, int sl, int g) {
+  uint4 v;
+  __builtin_memcpy(&v, T.row[sl], sizeof(v));
+  reinterpret_cast<uint4*>(B.nbr16)[(int64_t)g * B.capw * B.lanes + T.p * B.lanes + sl] = v;
+}
+__device__ __forceinline__ void append_candidate(const BuildArgs& B, TileState& T, int loc) {
+  const int sl = T.cnt & (B.lanes - 1);
+  const int pos = T.cnt / B.lanes;
+  const uint16_t v = (uint16_t)loc;
+  __builtin_memcpy(&T.row[sl][pos & 7], &v, sizeof(v));
+  ++T.cnt;
+  if ((pos & 7) == 7 && pos < B.cap_sl) store_slot_group(B, T, sl, pos >> 3);
 }
 
 // candidate test (skin-widened, FP64) of every lane's target against batch candidates cb[0..nb),
@@ -447,17 +461,7 @@ __device__ __forceinline__ void run_batch(const BuildArgs& B, TileState& T, cons
     mm &= mm - 1ull;
     int loc = T.usize + __popcll(um & ((1ull << j) - 1ull));
     loc = loc < T.ucap ? loc : T.ucap - 1;   // union overflow: keep reads in range, error latched
-    const uint32_t v = (uint32_t)loc << ((T.cnt & 1) << 4);
-    const int ws = (T.cnt >> 1) & 3;
-    T.w0 |= ws == 0 ? v : 0u;
-    T.w1 |= ws == 1 ? v : 0u;
-    T.w2 |= ws == 2 ? v : 0u;
-    T.w3 |= ws == 3 ? v : 0u;
-    ++T.cnt;
-    if ((T.cnt & 7) == 0) {
-      if (T.cnt <= B.cap) store_group(B, T, (T.cnt >> 3) - 1);
-      T.w0 = T.w1 = T.w2 = T.w3 = 0u;
-    }
+    append_candidate(B, T, loc);
   }
   T.usize += __popcll(um);
 }
@@ -642,6 +646,7 @@ __global__ __launch_bounds__(64) void k_build_tiles(BuildArgs B) {
   __shared__ double4 tp[64];     // the tile's particles (exact pre-filter of small tiles)
   __shared__ double4 cb[128];
   __shared__ int32_t cbi[128];
+  __shared__ __align__(16) uint16_t crow[64][4][8];   // per lane and slot: staging of the candidate lists
   const int lane = threadIdx.x;
   const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
   const GridInfo& g = *B.grid;
@@ -673,7 +678,7 @@ __global__ __launch_bounds__(64) void k_build_tiles(BuildArgs B) {
     T.U = B.tile_u + uoff;
     T.p = T.valid ? p : 0;
     T.usize = 0; T.cnt = 0;
-    T.w0 = T.w1 = T.w2 = T.w3 = 0u;
+    T.row = crow[lane];
     int pend = 0;   // candidates waiting in cb (wave-uniform)
     for (int l = 0; l < g.nlev; ++l) {
       LevelBox L;
@@ -767,7 +772,11 @@ __global__ __launch_bounds__(64) void k_build_tiles(BuildArgs B) {
     }
     if (pend > 0) run_batch<0, PER>(B, T, cb, cbi, pend, box, s1);
     __syncthreads();
-    if (T.valid && (T.cnt & 7) && T.cnt <= B.cap) store_group(B, T, T.cnt >> 3);
+    if (T.valid && T.cnt <= B.cap)
+      for (int sl = 0; sl < B.lanes; ++sl) {   // partly filled last group of each slot
+        const int ns = T.cnt > sl ? (T.cnt - sl + B.lanes - 1) / B.lanes : 0;
+        if ((ns & 7) && ns <= B.cap_sl) store_slot_group(B, T, sl, ns >> 3);
+      }
     if (T.valid) B.count[p] = T.cnt < B.cap ? T.cnt : B.cap;
     if (lane == 0) B.tile_usize[t] = T.usize < T.ucap ? T.usize : T.ucap;
     if (T.usize > T.ucap || T.cnt > B.cap) latch_error(B.status, SPH_E_NGB_CAPACITY, (int)(T.valid ? T.a : -1));
@@ -900,6 +909,7 @@ sph_status sph_rebin(sph_ctx* c, sph_state* st) {
   BuildArgs B;
   B.pos4 = c->pos4; B.n = n; B.grid = c->grid; B.perm = c->vals; B.pos_sorted = c->pos_sorted;
   B.cell_se = c->cell_se; B.capw = c->capw; B.cap = c->cap_s; B.ucap = c->ucap;
+  B.lanes = pass_lanes(c->p); B.cap_sl = cand_slot_capacity(c->cap_s, B.lanes);
   B.tile_start = c->tile_start; B.tile_cnt = c->tile_cnt; B.tile_uoff = c->tile_uoff; B.upool = c->upool;
   B.tile_u = c->tile_u; B.tile_usize = c->tile_usize; B.nbr16 = c->nbr16s; B.count = c->nbr_count_s;
   B.status = c->status;

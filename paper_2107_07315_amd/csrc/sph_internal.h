@@ -402,6 +402,8 @@ __host__ __device__ __forceinline__ int slot_capacity(int cap, int L) {
   const int c = (2 * cap + L - 1) / L;
   return ((c < cap ? c : cap) + 7) / 8 * 8;
 }
+// Candidate lists use the same slots: candidate k of a particle is entry k / L of slot k % L.
+__host__ __device__ __forceinline__ int cand_slot_capacity(int cap_s, int L) { return ((cap_s + L - 1) / L + 7) / 8 * 8; }
 __host__ __device__ __forceinline__ int64_t slot_entries_max(int cap) {   // per particle, over L
   int64_t m = 0;
   for (int L = 1; L <= 4; L *= 2) m = m > (int64_t)L * slot_capacity(cap, L) ? m : (int64_t)L * slot_capacity(cap, L);

@@ -105,30 +105,16 @@ struct PassArgs {
 
 constexpr int kNone = 0x7fffffff;
 
-// A 16-byte group of 8 list entries shifted right by 16 m bits, m in [0, 3] (a per-lane value).
-__device__ __forceinline__ uint4 shr_entries(uint4 v, int m) {
-  const bool w = (m & 2) != 0;
-  const uint4 r = make_uint4(w ? v.y : v.x, w ? v.z : v.y, w ? v.w : v.z, w ? 0u : v.w);
-  const uint4 h = make_uint4(__builtin_amdgcn_alignbit(r.y, r.x, 16u), __builtin_amdgcn_alignbit(r.z, r.y, 16u),
-                             __builtin_amdgcn_alignbit(r.w, r.z, 16u), r.w >> 16);
-  return (m & 1) ? h : r;
-}
-
-// Per-lane walk over a list stored as 16-byte groups of 8 16-bit local indices.  A lane takes the
-// entries pre, pre + STEP, pre + 2 STEP, ... of its list (STEP = 1: all of them; STEP = L with
-// pre = the lane's sub-index: the L lanes of a target share its list), 8 / STEP per group.  The
-// next AHEAD groups are always in flight (about 8 entries of the lane's own ahead, which covers
-// the load latency); the current group is consumed by shifts.
-template <int STEP>
+// Per-lane walk over a slot list stored as 16-byte groups of 8 16-bit local indices (group g at
+// base + g * gstride).  The group after the current one is always in flight (8 entries ahead);
+// the current group is consumed by funnel shifts.
 struct TileWalk {
-  static constexpr int E = 8 / STEP;
-  static constexpr int AHEAD = STEP == 1 ? 1 : (STEP == 2 ? 2 : 4);
   int64_t p, a;
   bool valid;
-  int usize, cnt, k, next, pre;
-  const uint4* gnext;      // the group after the ones in flight (groups are gstride apart)
+  int usize, cnt, k, next;
+  const uint4* gnext;      // the group after nxt
   int64_t gstride;
-  uint4 cur, q[AHEAD];
+  uint4 cur, nxt;
   const int32_t* U;
   // target t of the tile (a = p for a valid target, 0 otherwise)
   __device__ __forceinline__ void begin(const PassArgs& A, int64_t tile, int t) {
@@ -138,44 +124,30 @@ struct TileWalk {
     usize = A.tile_usize[tile];
     U = A.tile_u + A.tile_uoff[tile];
   }
-  // cnt = entries this lane takes
-  __device__ __forceinline__ void start(const uint4* base, int64_t stride, int count, int pre_) {
+  __device__ __forceinline__ void start(const uint4* base, int64_t stride, int count) {
     gstride = stride;
     cnt = count;
-    pre = pre_;
     k = 0;
     cur = make_uint4(0u, 0u, 0u, 0u);
-    if (cnt > 0) cur = STEP > 1 ? shr_entries(base[0], pre) : base[0];
-#pragma unroll
-    for (int i = 0; i < AHEAD; ++i) {
-      q[i] = make_uint4(0u, 0u, 0u, 0u);
-      if (cnt > (i + 1) * E) q[i] = base[(i + 1) * gstride];
-    }
-    gnext = base + (AHEAD + 1) * gstride;
+    nxt = cur;
+    if (cnt > 0) cur = base[0];
+    if (cnt > 8) nxt = base[gstride];
+    gnext = base + 2 * gstride;
     next = cnt > 0 ? (int)(cur.x & 0xffffu) : kNone;
   }
   __device__ __forceinline__ void advance() {
     ++k;
-    if ((k & (E - 1)) == 0) {
-      cur = STEP > 1 ? shr_entries(q[0], pre) : q[0];
-#pragma unroll
-      for (int i = 0; i + 1 < AHEAD; ++i) q[i] = q[i + 1];
-      if (k + AHEAD * E < cnt) {
-        q[AHEAD - 1] = *gnext;
+    if ((k & 7) == 0) {
+      cur = nxt;
+      if (k + 8 < cnt) {
+        nxt = *gnext;
         gnext += gstride;
       }
-    } else if constexpr (STEP == 1) {
+    } else {
       cur.x = __builtin_amdgcn_alignbit(cur.y, cur.x, 16u);
       cur.y = __builtin_amdgcn_alignbit(cur.z, cur.y, 16u);
       cur.z = __builtin_amdgcn_alignbit(cur.w, cur.z, 16u);
       cur.w >>= 16;
-    } else if constexpr (STEP == 2) {
-      cur.x = cur.y;
-      cur.y = cur.z;
-      cur.z = cur.w;
-    } else {
-      cur.x = cur.z;
-      cur.y = cur.w;
     }
     next = k < cnt ? (int)(cur.x & 0xffffu) : kNone;
   }
@@ -367,9 +339,9 @@ __device__ __forceinline__ void density_epilogue(const PassArgs& A, int64_t a, b
 // Density pass.  Walks the candidate lists, takes the exact FP64 neighbour decision
 // r^2 < (h_a + h_b)^2 on every candidate (positions staged in LDS in FP64 for both precisions),
 // sums the kernel over the neighbours in R, and writes the exact lists for the stress and force
-// passes.  A workgroup of L waves takes one tile: lane g serves target g / L and takes every L-th
-// entry of its candidate list from sub-index g % L on, writing the exact hits to its own slot
-// list (slot = particle * L + sub-index); the L partial sums are added across the lanes.  The
+// passes.  A workgroup of L waves takes one tile: lane g serves target g / L as sub-lane g % L,
+// walks the candidate slot list (particle * L + sub-lane) and writes the exact hits to the exact
+// slot list of the same index; the L partial sums are added across the lanes.  The
 // per-particle epilogue runs in k_density_epilogue, one lane per particle.
 template <typename R, int KER, bool PER, int L>
 __global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* __restrict__ pos64, DensOut O,
@@ -384,12 +356,12 @@ __global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* _
   for (int64_t k_ = blockIdx.x / SPH_XCD, chunk_ = xcd_chunk(ntl); k_ < chunk_; k_ += gridDim.x / SPH_XCD) {
     const int64_t tile = (int64_t)(blockIdx.x % SPH_XCD) * chunk_ + k_;
     if (tile >= ntl) break;
-  TileWalk<L> tw;
+  TileWalk tw;
   tw.begin(A, tile, tl);
   const int total = tw.valid ? A.cnt_s[tw.p] : 0;
-  tw.start(reinterpret_cast<const uint4*>(A.nbr16s) + tw.a, A.capw, total > sub ? (total - sub + L - 1) / L : 0, sub);
   const int64_t a = tw.a;
   const int64_t slot = a * L + sub;
+  tw.start(reinterpret_cast<const uint4*>(A.nbr16s) + slot, A.capw * L, total > sub ? (total - sub + L - 1) / L : 0);
   const double4 pa = tw.valid ? pos64[a] : make_double4(0.0, 0.0, 0.0, 1.0);
   R sum = sub == 0 ? wendland_self<R>(KER, (R)pa.w) : (R)0;
   ListWriter wr;
@@ -464,7 +436,7 @@ __global__ __launch_bounds__(64 * L) void k_stress(PassArgs A, const typename Re
   for (int64_t k_ = blockIdx.x / SPH_XCD, chunk_ = xcd_chunk(ntl); k_ < chunk_; k_ += gridDim.x / SPH_XCD) {
     const int64_t tile = (int64_t)(blockIdx.x % SPH_XCD) * chunk_ + k_;
     if (tile >= ntl) break;
-  TileWalk<1> tw;
+  TileWalk tw;
   tw.begin(A, tile, tl);
   const int64_t a = tw.a;
   const int64_t slot = a * L + sub;
@@ -476,7 +448,7 @@ __global__ __launch_bounds__(64 * L) void k_stress(PassArgs A, const typename Re
     sdot[a] = 0.0;
   }
   if (!__syncthreads_or(stressed)) continue;   // whole tile fluid
-  tw.start(reinterpret_cast<const uint4*>(A.nbr16) + slot, A.capw * L, stressed ? A.cnt_sl[slot] : 0, 0);
+  tw.start(reinterpret_cast<const uint4*>(A.nbr16) + slot, A.capw * L, stressed ? A.cnt_sl[slot] : 0);
   const sph_params& p = A.p;
   const P4 pa = tw.valid ? pos[a] : P4{0, 0, 0, 1};
   const V4 va = tw.valid ? fv[a] : V4{0, 0, 0, 0};
@@ -582,11 +554,11 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
   for (int64_t k_ = blockIdx.x / SPH_XCD, chunk_ = xcd_chunk(ntl); k_ < chunk_; k_ += gridDim.x / SPH_XCD) {
     const int64_t tile = (int64_t)(blockIdx.x % SPH_XCD) * chunk_ + k_;
     if (tile >= ntl) break;
-  TileWalk<1> tw;
+  TileWalk tw;
   tw.begin(A, tile, tl);
   const int64_t a = tw.a;
   const int64_t slot = a * L + sub;
-  tw.start(reinterpret_cast<const uint4*>(A.nbr16) + slot, A.capw * L, tw.valid ? A.cnt_sl[slot] : 0, 0);
+  tw.start(reinterpret_cast<const uint4*>(A.nbr16) + slot, A.capw * L, tw.valid ? A.cnt_sl[slot] : 0);
   const int64_t n = A.n;
   const sph_params& p = A.p;
   const P4 pa = tw.valid ? pos[a] : P4{0, 0, 0, 1};
