@@ -75,7 +75,7 @@ template <> struct Rec<float> {
   using V4 = float4;
   using A2 = float2;
   static constexpr int CH_D = 256;   // density records are FP64 in both precisions
-  static constexpr int CHMAX_D = 640;
+  static constexpr int CHMAX_D = 768;
   static constexpr int CH_S = 256;
   static constexpr int CH_F = 256;
 };
