@@ -74,8 +74,8 @@ template <> struct Rec<float> {
   using P4 = float4;
   using V4 = float4;
   using A2 = float2;
-  static constexpr int CH_D = 256;   // density records are FP64 in both precisions
-  static constexpr int CHMAX_D = 768;
+  static constexpr int CH_D = 256;   // density records: FP32 tile-relative (x, y, z, h), 4 KB
+  static constexpr int CHMAX_D = 1024;
   static constexpr int CH_S = 256;
   static constexpr int CH_F = 256;
 };
@@ -336,21 +336,36 @@ __device__ __forceinline__ void density_epilogue(const PassArgs& A, int64_t a, b
   if (!isfinite(D) || !isfinite(P) || !isfinite(cs)) latch_error(A.status, SPH_E_NONFINITE, (int)a);
 }
 
-// Density pass.  Walks the candidate lists, takes the exact FP64 neighbour decision
-// r^2 < (h_a + h_b)^2 on every candidate (positions staged in LDS in FP64 for both precisions),
-// sums the kernel over the neighbours in R, and writes the exact lists for the stress and force
-// passes.  A workgroup of L waves takes one tile: lane g serves target g / L as sub-lane g % L,
-// walks the candidate slot list (particle * L + sub-lane) and writes the exact hits to the exact
-// slot list of the same index; the L partial sums are added across the lanes.  The
-// per-particle epilogue runs in k_density_epilogue, one lane per particle.
+// Width of the FP32 guard band of the neighbour decision, relative to M H + H^2 (M the largest
+// coordinate magnitude of the pair relative to the tile's reference particle, H = h_a + h_b):
+// 64 u with u = 2^-24.  With coordinates and smoothing lengths rounded to FP32 and r^2, H^2
+// evaluated in FP32, |r2_f - r^2| <= 4 sqrt(3) u M |d| + 5 u r^2 and |H2_f - H^2| <= 7 u H^2 (to
+// first order), which stays below 64 u (M H + H^2) for every |d| <= 3.4 H; beyond that the FP32
+// decision cannot be wrong.  Outside the band the FP32 decision therefore equals the FP64 one.
+constexpr float kBand = 3.814697265625e-06f;   // 2^-18
+
+// Density pass.  Walks the candidate lists, takes the exact neighbour decision r^2 < (h_a + h_b)^2
+// of the FP64 positions on every candidate, sums the kernel over the neighbours in R, and writes
+// the exact lists for the stress and force passes.  A workgroup of L waves takes one tile: lane g
+// serves target g / L as sub-lane g % L, walks the candidate slot list (particle * L + sub-lane)
+// and writes the exact hits to the exact slot list of the same index; the L partial sums are
+// added across the lanes.  The per-particle epilogue runs in k_density_epilogue, one lane per
+// particle.
+//   FP64 (R = double): union records staged in LDS as FP64 (x, y, z, h), FP64 test.
+//   FP32 (R = float): union records staged as FP32 coordinates relative to the tile's first
+//   particle (16 bytes), the decision taken in FP32 and, inside the guard band kBand, again
+//   exactly from the FP64 positions; the lists are the same as in FP64.
 template <typename R, int KER, bool PER, int L>
 __global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* __restrict__ pos64, DensOut O,
                                                     uint16_t* __restrict__ xlist, int32_t* __restrict__ xcount,
                                                     int32_t* __restrict__ xcount_sl) {
+  constexpr bool F32 = std::is_same<R, float>::value;
+  using SR = typename std::conditional<F32, float4, double4>::type;
   constexpr int CH = Rec<R>::CH_D * L < Rec<R>::CHMAX_D ? Rec<R>::CH_D * L : Rec<R>::CHMAX_D;
-  __shared__ double4 sp[CH];
+  __shared__ SR sp[CH];
   __shared__ __align__(16) uint16_t lrow[64 * L][8];   // per-lane staging of the exact lists
   const double box = A.p.box, half = 0.5 * box;
+  const float boxf = (float)box, halff = (float)half;
   const int tl = threadIdx.x / L, sub = threadIdx.x % L;
   const int64_t ntl = num_tiles(A);
   for (int64_t k_ = blockIdx.x / SPH_XCD, chunk_ = xcd_chunk(ntl); k_ < chunk_; k_ += gridDim.x / SPH_XCD) {
@@ -363,25 +378,61 @@ __global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* _
   const int64_t slot = a * L + sub;
   tw.start(reinterpret_cast<const uint4*>(A.nbr16s) + slot, A.capw * L, total > sub ? (total - sub + L - 1) / L : 0);
   const double4 pa = tw.valid ? pos64[a] : make_double4(0.0, 0.0, 0.0, 1.0);
+  const double4 ref = pos64[A.tile_start[tile]];
+  float4 paf = make_float4(0.f, 0.f, 0.f, 1.f);
+  float Ma = 0.f;
+  if constexpr (F32) {
+    paf = make_float4((float)wrap_sel<PER>(pa.x - ref.x, box, half), (float)wrap_sel<PER>(pa.y - ref.y, box, half),
+                      (float)wrap_sel<PER>(pa.z - ref.z, box, half), (float)pa.w);
+    Ma = fmaxf(fabsf(paf.x), fmaxf(fabsf(paf.y), fabsf(paf.z)));
+  }
   R sum = sub == 0 ? wendland_self<R>(KER, (R)pa.w) : (R)0;
   ListWriter wr;
   wr.init(reinterpret_cast<uint4*>(xlist) + slot, A.capw * L, lrow[threadIdx.x], A.cap_sl);
   for (int c0 = 0; c0 < tw.usize; c0 += CH) {
     __syncthreads();
-    for (int j = threadIdx.x; j < CH && c0 + j < tw.usize; j += 64 * L) sp[j] = pos64[tw.U[c0 + j]];
+    for (int j = threadIdx.x; j < CH && c0 + j < tw.usize; j += 64 * L) {
+      const double4 q = pos64[tw.U[c0 + j]];
+      if constexpr (F32)
+        sp[j] = make_float4((float)wrap_sel<PER>(q.x - ref.x, box, half), (float)wrap_sel<PER>(q.y - ref.y, box, half),
+                            (float)wrap_sel<PER>(q.z - ref.z, box, half), (float)q.w);
+      else
+        sp[j] = q;
+    }
     __syncthreads();
     const int cend = c0 + CH;
     while (tw.next < cend) {
       const int loc = tw.next;
-      const double4 pb = sp[loc - c0];
+      const SR pb = sp[loc - c0];
       tw.advance();
-      const double dx = wrap_sel<PER>(pa.x - pb.x, box, half);
-      const double dy = wrap_sel<PER>(pa.y - pb.y, box, half);
-      const double dz = wrap_sel<PER>(pa.z - pb.z, box, half);
-      const double r2 = pair_r2(dx, dy, dz);
-      const double H = pa.w + pb.w;
-      const bool hit = r2 < H * H;
-      const R W = kern_W<R, KER>(sqrt_fast((R)r2), rcp_fast((R)(0.5 * H)));
+      bool hit;
+      R W;
+      if constexpr (F32) {
+        const float dx = wrap_sel<PER>(paf.x - pb.x, boxf, halff);
+        const float dy = wrap_sel<PER>(paf.y - pb.y, boxf, halff);
+        const float dz = wrap_sel<PER>(paf.z - pb.z, boxf, halff);
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        const float H = paf.w + pb.w;
+        const float H2 = H * H;
+        const float M = fmaxf(Ma, fmaxf(fabsf(pb.x), fmaxf(fabsf(pb.y), fabsf(pb.z))));
+        hit = r2 < H2;
+        if (fabsf(r2 - H2) <= kBand * (M * H + H2)) {   // near the support edge: decide in FP64
+          const double4 q = pos64[tw.U[loc]];
+          const double r2d = pair_r2(wrap_sel<PER>(pa.x - q.x, box, half), wrap_sel<PER>(pa.y - q.y, box, half),
+                                     wrap_sel<PER>(pa.z - q.z, box, half));
+          const double Hd = pa.w + q.w;
+          hit = r2d < Hd * Hd;
+        }
+        W = kern_W<float, KER>(sqrt_fast(r2), rcp_fast(0.5f * H));
+      } else {
+        const double dx = wrap_sel<PER>(pa.x - pb.x, box, half);
+        const double dy = wrap_sel<PER>(pa.y - pb.y, box, half);
+        const double dz = wrap_sel<PER>(pa.z - pb.z, box, half);
+        const double r2 = pair_r2(dx, dy, dz);
+        const double H = pa.w + pb.w;
+        hit = r2 < H * H;
+        W = kern_W<R, KER>(sqrt_fast((R)r2), rcp_fast((R)(0.5 * H)));
+      }
       sum += hit ? W : (R)0;
       wr.put(loc, hit);
     }

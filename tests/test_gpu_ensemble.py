@@ -61,6 +61,7 @@ def test_ensemble_fp32_pairs(ens):
     w = ens
     g = gpu_run(w, precision="FP32")
     o = oracle_run(w)
+    assert check_lists(g, o, w.n) == 0
     e = eval_errors(g, o)
     _print("ensemble fp32", e)
     for k in ("D", "rho", "P"):

@@ -114,9 +114,12 @@ def test_table_eos_star():
 
 
 def test_fp32_pairs_error_per_field():
+    # the FP32 path takes the neighbour decision in FP32 with an FP64 guard band: its exact lists
+    # must still equal the FP64 ones
     w = W.star(20000, seed=3, kernel="WC4", eta=W.ETA_100, l=2, A=1e-2, plastic=True)
     g = gpu_run(w, precision="FP32")
     o = oracle_run(w)
+    assert check_lists(g, o, w.n) == 0
     e = eval_errors(g, o)
     _print("fp32 eval", e)
     for k in ("D", "rho", "P"):
