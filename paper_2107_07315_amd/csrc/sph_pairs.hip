@@ -238,38 +238,44 @@ struct DensOut {
 };
 
 // Appends 16-bit local indices to a lane's exact list (the layout TileWalk reads).  Entries go to
-// the lane's own 16-byte row in LDS (written at every candidate, kept only on a hit); each full
-// row is stored as one 16-byte group.  No other lane touches the row, so no barrier is needed.
+// a ring of RB 16-byte rows of the lane's own in LDS (written at every candidate, kept only on a
+// hit); the rows are stored as 16-byte groups only when the ring is full or at the end.  Stores
+// in the pair loop would make each wait for a list load also wait for them (one counter tracks
+// both), so a lane with at most 8 RB hits stores nothing until the loop is over.  No other lane
+// touches the ring, so no barrier is needed.
+template <int RB>
 struct ListWriter {
-  uint4* gp;          // where this lane's next group goes
+  uint4* gp;          // where the lane's next unstored group goes
   int64_t gstride;    // uint4 between consecutive groups
-  uint16_t* row;      // this lane's 8 entries in LDS (16-byte aligned)
+  uint16_t* ring;     // RB rows of 8 entries (16-byte aligned)
   int cap;
-  int n;
+  int n;              // entries appended
+  int stored;         // groups stored
   __device__ __forceinline__ void init(uint4* base, int64_t stride, uint16_t* r, int cap_) {
     gp = base;
     gstride = stride;
-    row = r;
+    ring = r;
     cap = cap_;
     n = 0;
+    stored = 0;
   }
-  __device__ __forceinline__ uint4 row_group() const {
-    uint4 g;
-    __builtin_memcpy(&g, row, sizeof(g));
-    return g;
-  }
-  __device__ __forceinline__ void put(int loc, bool hit) {
-    const uint16_t v = (uint16_t)loc;
-    __builtin_memcpy(row + (n & 7), &v, sizeof(v));
-    n += hit ? 1 : 0;
-    if (hit && (n & 7) == 0) {
-      if (n <= cap) *gp = row_group();
+  __device__ __forceinline__ void store_rows(int upto) {   // groups [stored, upto)
+    for (; stored < upto; ++stored) {
+      if (stored * 8 < cap) {   // groups past the slot's capacity are not stored (error latched)
+        uint4 g;
+        __builtin_memcpy(&g, ring + 8 * (stored & (RB - 1)), sizeof(g));
+        *gp = g;
+      }
       gp += gstride;
     }
   }
-  __device__ __forceinline__ void flush() {
-    if ((n & 7) && n <= cap) *gp = row_group();
+  __device__ __forceinline__ void put(int loc, bool hit) {
+    const uint16_t v = (uint16_t)loc;
+    __builtin_memcpy(ring + (n & (8 * RB - 1)), &v, sizeof(v));
+    n += hit ? 1 : 0;
+    if (hit && (n & (8 * RB - 1)) == 0) store_rows(n >> 3);   // ring full
   }
+  __device__ __forceinline__ void flush() { store_rows((n + 7) >> 3); }
 };
 
 // Density-stage epilogue in FP64 for particle a with computational density D: rest-mass density
@@ -363,7 +369,8 @@ __global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* _
   using SR = typename std::conditional<F32, float4, double4>::type;
   constexpr int CH = Rec<R>::CH_D * L < Rec<R>::CHMAX_D ? Rec<R>::CH_D * L : Rec<R>::CHMAX_D;
   __shared__ SR sp[CH];
-  __shared__ __align__(16) uint16_t lrow[64 * L][8];   // per-lane staging of the exact lists
+  constexpr int RB = 4;
+  __shared__ __align__(16) uint16_t lring[64 * L][8 * RB];   // per-lane staging of the exact lists
   const double box = A.p.box, half = 0.5 * box;
   const float boxf = (float)box, halff = (float)half;
   const int tl = threadIdx.x / L, sub = threadIdx.x % L;
@@ -387,8 +394,8 @@ __global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* _
     Ma = fmaxf(fabsf(paf.x), fmaxf(fabsf(paf.y), fabsf(paf.z)));
   }
   R sum = sub == 0 ? wendland_self<R>(KER, (R)pa.w) : (R)0;
-  ListWriter wr;
-  wr.init(reinterpret_cast<uint4*>(xlist) + slot, A.capw * L, lrow[threadIdx.x], A.cap_sl);
+  ListWriter<RB> wr;
+  wr.init(reinterpret_cast<uint4*>(xlist) + slot, A.capw * L, lring[threadIdx.x], A.cap_sl);
   for (int c0 = 0; c0 < tw.usize; c0 += CH) {
     __syncthreads();
     for (int j = threadIdx.x; j < CH && c0 + j < tw.usize; j += 64 * L) {
