@@ -652,8 +652,7 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
       const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
       const R r = sqrt_fast(r2);
       const R hab = (R)0.5 * (pa.w + pb.w);
-      const R F = kern_F<R, KER>(r, rcp_fast(hab));
-      const R g[3] = {F * d[0], F * d[1], F * d[2]};
+      const R F = kern_F<R, KER>(r, rcp_fast(hab));   // grad_a W = F d
       const R v[3] = {va.x - vb.x, va.y - vb.y, va.z - vb.z};
       const R vr = v[0] * d[0] + v[1] * d[1] + v[2] * d[2];
       const bool b_st = fab.y < 0;
@@ -665,12 +664,13 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
       const R muab = hab * vr * (Dbar * inv);
       const R cbar = (R)0.5 * (va.w + vb.w);
       const R Pi = vr < (R)0 ? (-alpha_v * cbar * muab + beta_v * muab * muab) * (X * inv) : (R)0;
-      const R cP = pia + fab.x + Pi;
-      AP[0] += cP * g[0];
-      AP[1] += cP * g[1];
-      AP[2] += cP * g[2];
-      ud += (pia + (R)0.5 * Pi) * (v[0] * g[0] + v[1] * g[1] + v[2] * g[2]);
+      const R cPF = (pia + fab.x + Pi) * F;
+      AP[0] += cPF * d[0];
+      AP[1] += cPF * d[1];
+      AP[2] += cPF * d[2];
+      ud += (pia + (R)0.5 * Pi) * (F * vr);   // v_ab . grad_a W = F (v_ab . d)
       if (a_st || b_st) {
+        const R g[3] = {F * d[0], F * d[1], F * d[2]};
         R s6[6];
         const int32_t b = b_st ? tw.U[loc] : 0;
 #pragma unroll
