@@ -108,6 +108,7 @@ void sph_destroy(sph_ctx* c) {
     for (hipEvent_t e : t.ev) (void)hipEventDestroy(e);
   if (c->g_eval) (void)hipGraphExecDestroy(c->g_eval);
   if (c->g_drift) (void)hipGraphExecDestroy(c->g_drift);
+  if (c->g_chain) (void)hipGraphExecDestroy(c->g_chain);
   c->~sph_ctx();
   free(c);
 }
@@ -285,16 +286,19 @@ sph_status sph_forces(sph_ctx* c, sph_state* st) {
 
 }  // extern "C"
 
-// Captures the two graphs of a step: g_drift = flag clear, kick-drift with the skin test and the
-// flag copy to pinned host memory; g_eval = density, stress rate, forces and the final kick.
+// Captures the three graphs of a step: g_drift = flag clear, kick-drift with the skin test and
+// the flag copy to pinned host memory (first step of a call); g_chain = the same with the final
+// kick of the previous step fused in (later steps); g_eval = density, epilogue, stress rate and
+// forces.  The final kick of the call's last step is launched on its own.
 static sph_status capture_step(sph_ctx* c, sph_state* st, double dt) {
   if (c->g_eval) (void)hipGraphExecDestroy(c->g_eval);
   if (c->g_drift) (void)hipGraphExecDestroy(c->g_drift);
-  c->g_eval = c->g_drift = nullptr;
+  if (c->g_chain) (void)hipGraphExecDestroy(c->g_chain);
+  c->g_eval = c->g_drift = c->g_chain = nullptr;
   const int32_t timing = c->timing;
   c->timing = 0;   // no event records inside the graphs
   sph_status e = SPH_OK;
-  for (int which = 0; which < 2 && !e; ++which) {
+  for (int which = 0; which < 3 && !e; ++which) {
     hipGraph_t g = nullptr;
     if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
       e = SPH_E_HIP;
@@ -306,10 +310,9 @@ static sph_status capture_step(sph_ctx* c, sph_state* st, double dt) {
       if (!le) le = launch_eos(c, st);
       if (!le) le = launch_stress(c, st);
       if (!le) le = launch_forces(c, st);
-      if (!le) le = launch_kick_final(c, st, dt);
     } else {
       if (!le) le = launch_flag_clear(c);
-      if (!le) le = launch_kick_drift(c, st, dt, true);
+      if (!le) le = which == 1 ? launch_kick_drift(c, st, dt, true) : launch_kick_final_drift(c, st, dt, true);
       if (!le && hipMemcpyAsync(c->drift_host, c->drift_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream) !=
                      hipSuccess)
         le = SPH_E_HIP;
@@ -319,7 +322,7 @@ static sph_status capture_step(sph_ctx* c, sph_state* st, double dt) {
     hipGraphExec_t x = nullptr;
     if (!e && hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) e = SPH_E_HIP;
     if (g) (void)hipGraphDestroy(g);
-    if (!e) (which == 0 ? c->g_eval : c->g_drift) = x;
+    if (!e) (which == 0 ? c->g_eval : which == 1 ? c->g_drift : c->g_chain) = x;
   }
   c->timing = timing;
   if (!e) {
@@ -331,14 +334,15 @@ static sph_status capture_step(sph_ctx* c, sph_state* st, double dt) {
   return e;
 }
 
-// sph_step with graph replay: per step, g_drift, one word read back, an eager candidate-list
-// rebuild if the skin test failed (re-capturing if that moved a buffer), then g_eval.
+// sph_step with graph replay: per step, g_drift (first step) or g_chain, one word read back, an
+// eager candidate-list rebuild if the skin test failed (re-capturing if that moved a buffer), then
+// g_eval; the last final kick on its own.
 static sph_status step_graphs(sph_ctx* c, sph_state* st, double dt, int32_t nsteps) {
   sph_status e;
   for (int32_t k = 0; k < nsteps; ++k) {
     if (!c->g_eval || c->g_x != st->x || c->g_n != st->n || c->g_dt != dt || c->g_epoch != c->graph_epoch)
       if ((e = capture_step(c, st, dt))) return e;
-    HIP_TRY(hipGraphLaunch(c->g_drift, c->stream));
+    HIP_TRY(hipGraphLaunch(k == 0 ? c->g_drift : c->g_chain, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     if (*c->drift_host != 0u) {
       if ((e = rebuild(c, st))) return e;
@@ -346,7 +350,7 @@ static sph_status step_graphs(sph_ctx* c, sph_state* st, double dt, int32_t nste
     }
     HIP_TRY(hipGraphLaunch(c->g_eval, c->stream));
   }
-  return SPH_OK;
+  return nsteps > 0 ? launch_kick_final(c, st, dt) : SPH_OK;
 }
 
 extern "C" {
@@ -363,11 +367,13 @@ sph_status sph_step(sph_ctx* c, sph_state* st, double dt, int32_t nsteps) {
     if (!e) c->gen = 4;
     return e;
   }
+  // Steps are chained: the final kick of step k and the kick-drift of step k + 1 run as one
+  // kernel; the last step of the call ends with its own final kick.
   for (int32_t k = 0; k < nsteps; ++k) {
     const bool check = c->lists_valid && c->p.skin > 0.0;
     if (check && (e = launch_flag_clear(c))) return e;
     timer_begin(c, TIMER_KDK);
-    if ((e = launch_kick_drift(c, st, dt, check))) return e;
+    if ((e = k == 0 ? launch_kick_drift(c, st, dt, check) : launch_kick_final_drift(c, st, dt, check))) return e;
     timer_end(c, TIMER_KDK);
     bool stale = !check;
     if (check && (e = read_drift(c, &stale))) return e;
@@ -384,10 +390,10 @@ sph_status sph_step(sph_ctx* c, sph_state* st, double dt, int32_t nsteps) {
     timer_begin(c, TIMER_FORCES);
     if ((e = launch_forces(c, st))) return e;
     timer_end(c, TIMER_FORCES);
-    timer_begin(c, TIMER_KDK);
-    if ((e = launch_kick_final(c, st, dt))) return e;
-    timer_end(c, TIMER_KDK);
   }
+  timer_begin(c, TIMER_KDK);
+  if ((e = launch_kick_final(c, st, dt))) return e;
+  timer_end(c, TIMER_KDK);
   c->gen = 4;
   return SPH_OK;
 }

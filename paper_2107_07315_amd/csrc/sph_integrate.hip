@@ -36,21 +36,23 @@ __device__ __forceinline__ double wrap(double q, int periodic, double box) {
   return q;
 }
 
-// half kick, drift, and predictors (velocity, energy, yielded stress) for the evaluation; also
-// packs the position records of the evaluation and runs the skin test against the last build
-__global__ __launch_bounds__(kB) void k_kick_drift(KdkArgs K) {
-  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= K.n) return;
+// First half kick, drift and predictors of particle a from its start-of-step v, u, S and h:
+// stores the half-step copies, x, the predicted v, u and (yielded) S, the packed position records,
+// and runs the skin test.
+__device__ __forceinline__ void kick_drift_from(const KdkArgs& K, int64_t a, const double v0[3], double u0,
+                                                const double S0[6], double h) {
   const double hdt = 0.5 * K.dt;
   const int64_t n = K.n, hs = K.hstride;
   double* H = K.half;
-  double vh[3] = {K.vx[a] + hdt * K.ax[a], K.vy[a] + hdt * K.ay[a], K.vz[a] + hdt * K.az[a]};
-  double uh = K.u[a] + hdt * K.dudt[a];
+  const double ax = K.ax[a], ay = K.ay[a], az = K.az[a], du = K.dudt[a];
+  double vh[3] = {v0[0] + hdt * ax, v0[1] + hdt * ay, v0[2] + hdt * az};
+  double uh = u0 + hdt * du;
   double s[6];
   for (int c = 0; c < 6; ++c) {
-    double sh = K.S[c * n + a] + hdt * K.dSdt[c * n + a];
+    const double ds = K.dSdt[c * n + a];
+    double sh = S0[c] + hdt * ds;
     H[(4 + c) * hs + a] = sh;
-    s[c] = sh + hdt * K.dSdt[c * n + a];
+    s[c] = sh + hdt * ds;
   }
   H[0 * hs + a] = vh[0];
   H[1 * hs + a] = vh[1];
@@ -62,7 +64,6 @@ __global__ __launch_bounds__(kB) void k_kick_drift(KdkArgs K) {
   K.x[a] = xn;
   K.y[a] = yn;
   K.z[a] = zn;
-  const double h = K.h[a];
   K.pos4[a] = make_double4(xn, yn, zn, h);
   if (K.pos4f) {
     double cx = 0.0, cy = 0.0, cz = 0.0;
@@ -80,26 +81,25 @@ __global__ __launch_bounds__(kB) void k_kick_drift(KdkArgs K) {
                       h, b, K.grid->skin))
       atomicMax(K.flag, K.check_id);
   }
-  K.vx[a] = vh[0] + hdt * K.ax[a];
-  K.vy[a] = vh[1] + hdt * K.ay[a];
-  K.vz[a] = vh[2] + hdt * K.az[a];
-  K.u[a] = uh + hdt * K.dudt[a];
+  K.vx[a] = vh[0] + hdt * ax;
+  K.vy[a] = vh[1] + hdt * ay;
+  K.vz[a] = vh[2] + hdt * az;
+  K.u[a] = uh + hdt * du;
   yield_scale(K.p.yield_mode, K.Y0[a], s);
   for (int c = 0; c < 6; ++c) K.S[c * n + a] = s[c];
 }
 
-// second half kick, yield, breaking and the adaptive smoothing length
-__global__ __launch_bounds__(kB) void k_kick_final(KdkArgs K) {
-  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= K.n) return;
+// Second half kick of particle a from the half-step copies: end-of-step v, u and S (yield scaling
+// and the breaking test applied; breaking is recorded), and the adaptive h of the step's density.
+__device__ __forceinline__ void final_kick_of(const KdkArgs& K, int64_t a, double v[3], double& u, double s[6],
+                                              double& h) {
   const double hdt = 0.5 * K.dt;
   const int64_t n = K.n, hs = K.hstride;
   const double* H = K.half;
-  K.vx[a] = H[0 * hs + a] + hdt * K.ax[a];
-  K.vy[a] = H[1 * hs + a] + hdt * K.ay[a];
-  K.vz[a] = H[2 * hs + a] + hdt * K.az[a];
-  K.u[a] = H[3 * hs + a] + hdt * K.dudt[a];
-  double s[6];
+  v[0] = H[0 * hs + a] + hdt * K.ax[a];
+  v[1] = H[1 * hs + a] + hdt * K.ay[a];
+  v[2] = H[2 * hs + a] + hdt * K.az[a];
+  u = H[3 * hs + a] + hdt * K.dudt[a];
   for (int c = 0; c < 6; ++c) s[c] = H[(4 + c) * hs + a] + hdt * K.dSdt[c * n + a];
   yield_scale(K.p.yield_mode, K.Y0[a], s);
   if (K.p.break_mode != SPH_BREAK_OFF && K.type[a] == 1 && !K.broken[a]) {
@@ -114,11 +114,49 @@ __global__ __launch_bounds__(kB) void k_kick_final(KdkArgs K) {
       }
     }
   }
-  for (int c = 0; c < 6; ++c) K.S[c * n + a] = s[c];
+  h = K.h[a];
   if (K.p.h_mode == SPH_H_ADAPTIVE) {
     double m = (K.star && K.stars) ? K.stars[K.star[a]].m : K.p.m;
-    K.h[a] = K.p.eta * cbrt(m / K.D[a]);
+    h = K.p.eta * cbrt(m / K.D[a]);
   }
+}
+
+// half kick, drift, and predictors (velocity, energy, yielded stress) for the evaluation; also
+// packs the position records of the evaluation and runs the skin test against the last build
+__global__ __launch_bounds__(kB) void k_kick_drift(KdkArgs K) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= K.n) return;
+  const int64_t n = K.n;
+  const double v0[3] = {K.vx[a], K.vy[a], K.vz[a]};
+  double S0[6];
+  for (int c = 0; c < 6; ++c) S0[c] = K.S[c * n + a];
+  kick_drift_from(K, a, v0, K.u[a], S0, K.h[a]);
+}
+
+// second half kick: end-of-step state
+__global__ __launch_bounds__(kB) void k_kick_final(KdkArgs K) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= K.n) return;
+  const int64_t n = K.n;
+  double v[3], u, s[6], h;
+  final_kick_of(K, a, v, u, s, h);
+  K.vx[a] = v[0];
+  K.vy[a] = v[1];
+  K.vz[a] = v[2];
+  K.u[a] = u;
+  for (int c = 0; c < 6; ++c) K.S[c * n + a] = s[c];
+  K.h[a] = h;
+}
+
+// The second half kick of one step and the first half kick and drift of the next in one pass:
+// the end-of-step v, u, S and h stay in registers (the same arithmetic as the two kernels).
+__global__ __launch_bounds__(kB) void k_kick_final_drift(KdkArgs K) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= K.n) return;
+  double v[3], u, s[6], h;
+  final_kick_of(K, a, v, u, s, h);
+  K.h[a] = h;
+  kick_drift_from(K, a, v, u, s, h);
 }
 
 KdkArgs make_kdk(sph_ctx* c, sph_state* st, double dt) {
@@ -147,9 +185,6 @@ KdkArgs make_kdk(sph_ctx* c, sph_state* st, double dt) {
   return K;
 }
 
-}  // namespace
-
-namespace {
 __global__ void k_flag_clear(uint32_t* f) { *f = 0u; }   // a kernel, not a memset: graph-safe
 }  // namespace
 
@@ -163,6 +198,14 @@ sph_status launch_kick_drift(sph_ctx* c, sph_state* st, double dt, bool check) {
   KdkArgs K = make_kdk(c, st, dt);
   if (check) K.flag = c->drift_flag;
   hipLaunchKernelGGL(k_kick_drift, dim3(grid_for(st->n, kB)), dim3(kB), 0, c->stream, K);
+  HIP_TRY(hipGetLastError());
+  return SPH_OK;
+}
+
+sph_status launch_kick_final_drift(sph_ctx* c, sph_state* st, double dt, bool check) {
+  KdkArgs K = make_kdk(c, st, dt);
+  if (check) K.flag = c->drift_flag;
+  hipLaunchKernelGGL(k_kick_final_drift, dim3(grid_for(st->n, kB)), dim3(kB), 0, c->stream, K);
   HIP_TRY(hipGetLastError());
   return SPH_OK;
 }

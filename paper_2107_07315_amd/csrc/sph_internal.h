@@ -297,8 +297,9 @@ struct sph_ctx {
   int32_t gen;          // stage order: 1 cells, 2 density, 3 stress, 4 forces
   bool lists_valid;     // candidate lists match the current n, order and parameters
   uint32_t graph_epoch; // bumped whenever a pointer or parameter that kernels capture changes
-  hipGraphExec_t g_eval;   // captured density, stress rate, forces, final kick
+  hipGraphExec_t g_eval;   // captured density, epilogue, stress rate, forces
   hipGraphExec_t g_drift;  // captured flag clear, kick-drift with skin test, flag copy
+  hipGraphExec_t g_chain;  // the same with the previous step's final kick fused in
   const double* g_x;       // key of the captured graphs: state, size, dt, epoch
   int64_t g_n;
   double g_dt;
@@ -376,6 +377,8 @@ sph_status launch_stress(sph_ctx* c, sph_state* st);
 sph_status launch_forces(sph_ctx* c, sph_state* st);
 sph_status launch_kick_drift(sph_ctx* c, sph_state* st, double dt, bool check);
 sph_status launch_kick_final(sph_ctx* c, sph_state* st, double dt);
+// the final kick of one step fused with the kick-drift of the next (inside a multi-step call)
+sph_status launch_kick_final_drift(sph_ctx* c, sph_state* st, double dt, bool check);
 sph_status launch_pack(sph_ctx* c, sph_state* st);
 sph_status sph_count_stats(sph_ctx* c, sph_list_stats* out);
 sph_status sph_scan_u32(sph_ctx* c, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total);
