@@ -182,7 +182,10 @@ sph_status sph_forces(sph_ctx* ctx, sph_state* st);
 /* nsteps kick-drift-kick steps of size dt (dt > 0).  On entry the rates must be those of a full
  * evaluation at the current state (build_cells, density, stress_rate, forces).  Applies the
  * von Mises yield scaling after each stress update and the maximum-strain breaking test
- * (section "Solid SPH Equations"), and the adaptive smoothing length. */
+ * (section "Solid SPH Equations"), and the adaptive smoothing length.  Within one call the final
+ * kick of a step and the kick-drift of the next run as one kernel, so the state between two steps
+ * of the call is never written out; on return the state is the end of the last step and the
+ * rates are those of its evaluation. */
 sph_status sph_step(sph_ctx* ctx, sph_state* st, double dt, int32_t nsteps);
 
 /* Ensembles of independent stars in one particle set: star_info (host) holds nstars rows of
