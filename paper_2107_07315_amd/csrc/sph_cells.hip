@@ -258,7 +258,7 @@ __global__ __launch_bounds__(kB) void k_pack_pos(const double* __restrict__ x, c
     cx = s.cx; cy = s.cy; cz = s.cz;
   }
   pos4[a] = make_double4(x[a], y[a], z[a], h[a]);
-  if (pos4f) pos4f[a] = make_float4((float)(x[a] - cx), (float)(y[a] - cy), (float)(z[a] - cz), (float)h[a]);
+  if (pos4f) pos4f[a] = make_float4((float)(x[a] - cx), (float)(y[a] - cy), (float)(z[a] - cz), (float)(0.5 * h[a]));
 }
 
 // Global Morton key of a 1024^3 grid over the bounding box: the particle arrays are kept in this

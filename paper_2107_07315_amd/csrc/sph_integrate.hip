@@ -71,7 +71,7 @@ __device__ __forceinline__ void kick_drift_from(const KdkArgs& K, int64_t a, con
       const StarInfo si = K.stars[K.star[a]];
       cx = si.cx; cy = si.cy; cz = si.cz;
     }
-    K.pos4f[a] = make_float4((float)(xn - cx), (float)(yn - cy), (float)(zn - cz), (float)h);
+    K.pos4f[a] = make_float4((float)(xn - cx), (float)(yn - cy), (float)(zn - cz), (float)(0.5 * h));   // h/2
   }
   if (K.flag) {
     const double4 b = K.pos_build[a];

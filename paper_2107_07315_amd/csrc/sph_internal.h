@@ -344,9 +344,9 @@ struct sph_ctx {
   double4* fv;          // vx, vy, vz, cs
   double2* fa;          // P/D^2, D (negative D marks a particle that carries deviatoric stress)
   double* sig;          // S/D^2, 6*cap
-  float4* pos4f;        // x, y, z, h (relative to the star centre)
-  float4* fvf;
-  float2* faf;
+  float4* pos4f;        // x, y, z (relative to the star centre), h/2
+  float4* fvf;          // vx, vy, vz, cs/2
+  float2* faf;          // P/D^2, D/2 (negative: carries deviatoric stress)
   float* sigf;
   // internal per-particle fields
   double *mu, *Y0, *B, *sdot;

@@ -61,7 +61,11 @@ __device__ __forceinline__ R kern_F(R r, R ih) {
 }
 
 template <typename R> struct Rec;
+// Record scale: the FP64 records hold h, c_s and D; the FP32 ones hold h/2, c_s/2 and D/2 (exact
+// halvings), so the pair means 0.5 (h_a + h_b), 0.5 (c_a + c_b), 0.5 (D_a + D_b) are HS times the
+// sum of the two record values and HS = 1 saves the multiply in FP32.
 template <> struct Rec<double> {
+  static constexpr double HS = 0.5;
   using P4 = double4;
   using V4 = double4;
   using A2 = double2;
@@ -71,6 +75,7 @@ template <> struct Rec<double> {
   static constexpr int CH_F = 128;   // forces 10 KB
 };
 template <> struct Rec<float> {
+  static constexpr float HS = 1.0f;
   using P4 = float4;
   using V4 = float4;
   using A2 = float2;
@@ -335,8 +340,8 @@ __device__ __forceinline__ void density_epilogue(const PassArgs& A, int64_t a, b
     O.fa[a] = make_double2(pi, stressed ? -D : D);
     for (int c = 0; c < 6; ++c) O.sig[c * n + a] = S[c * n + a] * iD2;
   } else {
-    O.fvf[a] = make_float4((float)va[0], (float)va[1], (float)va[2], (float)cs);
-    O.faf[a] = make_float2((float)pi, stressed ? -(float)D : (float)D);
+    O.fvf[a] = make_float4((float)va[0], (float)va[1], (float)va[2], (float)(0.5 * cs));
+    O.faf[a] = make_float2((float)pi, stressed ? -(float)(0.5 * D) : (float)(0.5 * D));
     for (int c = 0; c < 6; ++c) O.sigf[c * n + a] = (float)(S[c * n + a] * iD2);
   }
   if (!isfinite(D) || !isfinite(P) || !isfinite(cs)) latch_error(A.status, SPH_E_NONFINITE, (int)a);
@@ -527,7 +532,7 @@ __global__ __launch_bounds__(64 * L) void k_stress(PassArgs A, const typename Re
       const R d[3] = {wrap_sel<PER>(pa.x - pb.x, box, half), wrap_sel<PER>(pa.y - pb.y, box, half),
                       wrap_sel<PER>(pa.z - pb.z, box, half)};
       const R r = sqrt_fast(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-      const R F = kern_F<R, KER>(r, rcp_fast((R)0.5 * (pa.w + pb.w)));
+      const R F = kern_F<R, KER>(r, rcp_fast(Rec<R>::HS * (pa.w + pb.w)));
       const R g[3] = {F * d[0], F * d[1], F * d[2]};
       const R v[3] = {vb.x - va.x, vb.y - va.y, vb.z - va.z};
 #pragma unroll
@@ -542,7 +547,7 @@ __global__ __launch_bounds__(64 * L) void k_stress(PassArgs A, const typename Re
     for (int jj = 0; jj < 3; ++jj) G[i][jj] = lane_group_sum<L>(G[i][jj]);
   if (!stressed || sub != 0) continue;
   const double m = particle_mass(A, a);
-  const double D = -(double)faa.y;  // stressed particles store -D
+  const double D = -(double)faa.y * (2.0 * (double)Rec<R>::HS);  // stressed particles store -D (FP32: -D/2)
   const double iD2 = m / (2.0 * D);
   double ed[3][3], Rd[3][3];
 #pragma unroll
@@ -651,7 +656,7 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
                       wrap_sel<PER>(pa.z - pb.z, box, half)};
       const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
       const R r = sqrt_fast(r2);
-      const R hab = (R)0.5 * (pa.w + pb.w);
+      const R hab = Rec<R>::HS * (pa.w + pb.w);
       const R F = kern_F<R, KER>(r, rcp_fast(hab));   // grad_a W = F d
       const R v[3] = {va.x - vb.x, va.y - vb.y, va.z - vb.z};
       const R vr = v[0] * d[0] + v[1] * d[1] + v[2] * d[2];
@@ -659,10 +664,10 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
       const R Db = b_st ? -fab.y : fab.y;
       // Monaghan viscosity on approaching pairs: one reciprocal gives 1/X and 1/Dbar
       const R X = r2 + eps_v * hab * hab;
-      const R Dbar = (R)0.5 * (Da + Db);
+      const R Dbar = Rec<R>::HS * (Da + Db);
       const R inv = rcp_fast(X * Dbar);
       const R muab = hab * vr * (Dbar * inv);
-      const R cbar = (R)0.5 * (va.w + vb.w);
+      const R cbar = Rec<R>::HS * (va.w + vb.w);
       const R Pi = vr < (R)0 ? (-alpha_v * cbar * muab + beta_v * muab * muab) * (X * inv) : (R)0;
       const R cPF = (pia + fab.x + Pi) * F;
       AP[0] += cPF * d[0];
