@@ -124,7 +124,7 @@ def test_fp32_pairs_error_per_field():
     _print("fp32 eval", e)
     for k in ("D", "rho", "P"):
         assert e[k] < 1e-4, (k, e[k])
-    for k in ("ax", "ay", "az", "dudt"):
+    for k in ("ax", "ay", "az", "dudt", "dSdt"):
         assert e[k] < 1e-4, (k, e[k])
 
 
@@ -251,9 +251,9 @@ def test_skin_lists_match_rebuild_every_evaluation():
     assert runs[1e-3]["_stats"]["rebuilds"] >= 2
 
 
-@pytest.mark.parametrize("lanes", [1, 4])
+@pytest.mark.parametrize("lanes", [1, 2])
 def test_lanes_per_target(lanes):
-    # 1 and 4 lanes per target (the default is 2): same exact neighbour sets, fields to the
+    # 1 and 2 lanes per target (the default is 4): same exact neighbour sets, fields to the
     # evaluation tolerance, steps to the state tolerance
     w = W.star(20000, seed=3, kernel="WC4", eta=W.ETA_100, l=2, A=1e-2, plastic=True)
     g = gpu_run(w, ctx_kw={"lanes": lanes})
@@ -285,5 +285,5 @@ def test_lanes_per_target(lanes):
         assert check_lists(g, o, n) == 0
         ef = eval_errors(g, o)
         _print(f"lanes {lanes} {ker} periodic={periodic} fp32", ef)
-        for k in ("D", "rho", "P", "ax", "ay", "az", "dudt"):
+        for k in ("D", "rho", "P", "ax", "ay", "az", "dudt", "dSdt"):
             assert ef[k] < 1e-4, (k, ef[k])
