@@ -196,13 +196,13 @@ sph_status sph_step(sph_ctx* ctx, sph_state* st, double dt, int32_t nsteps);
  * stars).  nstars = 0 returns to a single star.  Waits; invalidates the stage order. */
 sph_status sph_ensemble_set(sph_ctx* ctx, int32_t nstars, const double* star_info);
 
-/* Launch autotuner: under candidate settings of lanes, pass_blocks, tile_cut and skin, one parameter at
- * a time (coordinate descent from the current settings), steps a copy of the state (the caller's
- * state is not changed) through one whole rebuild cycle of the candidate lists and keeps the
- * setting with the least time per step, the list rebuild amortised over the cycle.  A cycle runs
- * from just after one rebuild to the end of the step holding the next; each of its two phases
- * (reaching the first rebuild, the cycle itself) stops after at most `steps_per_trial` steps.
- * The context then needs a new evaluation (sph_build_cells ...) before sph_step.  Waits. */
+/* Launch autotuner: under candidate settings of lanes, pass_blocks, tile_cut and skin, one parameter
+ * at a time (coordinate descent from the current settings), times one sph_step call of
+ * `steps_per_trial` steps (with the candidate-list rebuilds they need) on a copy of the state (the
+ * caller's state is not changed), and keeps the setting with the least time per step; a setting
+ * replaces the best only if it is more than 2% faster.  Use enough steps for several rebuilds
+ * (64 at skin 0.1).  The context then needs a new evaluation (sph_build_cells ...) before
+ * sph_step.  Waits. */
 typedef struct {
   int32_t pass_blocks;
   int32_t trials;          /* configurations timed                                              */

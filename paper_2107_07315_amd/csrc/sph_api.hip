@@ -467,19 +467,13 @@ sph_status sph_autotune(sph_ctx* c, const sph_state* st, double dt, int32_t step
     if ((te = cp.load(st, c->stream)) || (te = sph_build_cells(c, &cp.st)) || (te = sph_density(c, &cp.st)) ||
         (te = sph_stress_rate(c, &cp.st)) || (te = sph_forces(c, &cp.st)) || (te = sph_step(c, &cp.st, dt, 1)))
       return te;
-    // phase 1: up to the first rebuild; phase 2 (timed): one rebuild cycle
-    const int64_t r0 = c->rebuilds;
-    for (int k = 0; k < steps && c->rebuilds == r0; ++k)
-      if ((te = sph_step(c, &cp.st, dt, 1))) return te;
+    // timed: one call of `steps` chained steps, with the list rebuilds they need (as in a run)
     HIP_TRY(hipStreamSynchronize(c->stream));
     const auto t0 = std::chrono::steady_clock::now();
-    const int64_t r1 = c->rebuilds;
-    int k = 0;
-    for (; k < steps && c->rebuilds == r1; ++k)
-      if ((te = sph_step(c, &cp.st, dt, 1))) return te;
+    if ((te = sph_step(c, &cp.st, dt, steps))) return te;
     HIP_TRY(hipStreamSynchronize(c->stream));
     const auto t1 = std::chrono::steady_clock::now();
-    *ms = std::chrono::duration<double, std::milli>(t1 - t0).count() / k;
+    *ms = std::chrono::duration<double, std::milli>(t1 - t0).count() / steps;
     return sph_sync(c);
   };
   sph_params best = c->p;
