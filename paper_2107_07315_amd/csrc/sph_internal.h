@@ -385,6 +385,7 @@ sph_status sph_scan_u32(sph_ctx* c, const uint32_t* in, uint32_t* out, int64_t n
 struct MlpView;
 bool mlp_view(const sph_ctx* c, MlpView* v);   // false if no trained network is loaded
 void mlp_free(sph_ctx* c);
+int64_t mlp_trusted_cells(const sph_ctx* c);   // EoS-table cells the network may serve
 
 enum { TIMER_CELLS = 0, TIMER_DENSITY = 1, TIMER_STRESS = 2, TIMER_FORCES = 3, TIMER_KDK = 4, TIMER_EOS = 5 };
 void timer_begin(sph_ctx* c, int which);

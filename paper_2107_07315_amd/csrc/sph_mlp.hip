@@ -487,6 +487,10 @@ bool mlp_view(const sph_ctx* c, MlpView* v) {
   return true;
 }
 
+int64_t mlp_trusted_cells(const sph_ctx* c) {
+  return (c->mlp && c->mlp->trust) ? c->mlp->trust_cells : 0;
+}
+
 void mlp_free(sph_ctx* c) {
   MlpState* s = c->mlp;
   if (!s) return;

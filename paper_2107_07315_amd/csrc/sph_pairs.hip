@@ -817,7 +817,9 @@ sph_status launch_eos(sph_ctx* c, sph_state* st) {
   PassArgs A = make_args(c, st);
   DensOut O{st->D, st->rho, st->P, st->cs, c->mu, c->Y0, c->B, c->fv, c->fa, c->sig, c->fvf, c->faf, c->sigf};
   const bool f32 = c->p.precision == SPH_FP32;
-  const bool mlp = c->p.eos == SPH_EOS_MLP && A.has_mlp;
+  // the network path only where some table cell is trusted; with none, every particle takes the
+  // table (the same values), so the table kernel runs
+  const bool mlp = c->p.eos == SPH_EOS_MLP && A.has_mlp && mlp_trusted_cells(c) > 0;
   const unsigned nb = (unsigned)((st->n + 63) / 64 < 65536 ? (st->n + 63) / 64 : 65536);
   const dim3 b(64);
   auto epi = [&](auto kern) {
