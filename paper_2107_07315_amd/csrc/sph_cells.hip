@@ -398,6 +398,7 @@ struct TileState {
   int64_t a;
   bool valid;
   double xa, ya, za, ha;
+  double hs;                 // ha (1 + skin)(1 + 2^-40), the candidate test's scaled h
   int usize, cnt, ucap;
   int64_t p;
   int32_t* U;
@@ -422,7 +423,11 @@ __device__ __forceinline__ void append_candidate(const BuildArgs& B, TileState& 
 }
 
 // candidate test (skin-widened, FP64) of every lane's target against batch candidates cb[0..nb),
-// nb <= 64; NB > 0 fixes nb at compile time (full batches, fully unrolled)
+// nb <= 64; NB > 0 fixes nb at compile time (full batches, fully unrolled).  The test is
+// r^2 < (h_a' + h_b')^2 with h' = h (1 + skin)(1 + 2^-40) (T.hs, cb[j].w) and r^2 by FMA: the
+// factor 1 + 2^-40 exceeds the few ulp by which this rounding can differ from the exact decision
+// of the density pass, so the candidates always contain every pair that test can accept (with a
+// positive skin the rebuild test's own margin of 1e-9 is larger still).
 template <int NB, bool PER>
 __device__ __forceinline__ void run_batch(const BuildArgs& B, TileState& T, const double4* cb, const int32_t* cbi,
                                           int nb, double box, double s1) {
@@ -430,9 +435,10 @@ __device__ __forceinline__ void run_batch(const BuildArgs& B, TileState& T, cons
   unsigned long long hm = 0ull;
   auto test = [&](int j) -> bool {
     const double4 pb = cb[j];
-    return cbi[j] != T.a &&
-           candidate_test(min_image(T.xa - pb.x, (int)PER, box), min_image(T.ya - pb.y, (int)PER, box),
-                          min_image(T.za - pb.z, (int)PER, box), T.ha, pb.w, s1);
+    const double dx = min_image(T.xa - pb.x, (int)PER, box), dy = min_image(T.ya - pb.y, (int)PER, box),
+                 dz = min_image(T.za - pb.z, (int)PER, box);
+    const double H = T.hs + pb.w;
+    return cbi[j] != T.a && fma(dz, dz, fma(dy, dy, dx * dx)) < H * H;
   };
   if (T.valid) {
     if constexpr (NB > 0) {
@@ -652,6 +658,7 @@ __global__ __launch_bounds__(64) void k_build_tiles(BuildArgs B) {
   const GridInfo& g = *B.grid;
   const double box = g.box;
   const double s1 = 1.0 + g.skin;
+  const double s1w = s1 * (1.0 + 0x1p-40);   // the batch test's widened factor
   const int64_t ntiles = g.ntiles;
   for (int64_t k_ = blockIdx.x / SPH_XCD, chunk_ = xcd_chunk(ntiles); k_ < chunk_; k_ += gridDim.x / SPH_XCD) {
     const int64_t t = (int64_t)(blockIdx.x % SPH_XCD) * chunk_ + k_;
@@ -662,7 +669,7 @@ __global__ __launch_bounds__(64) void k_build_tiles(BuildArgs B) {
     T.valid = lane < tcnt;
     T.a = T.valid ? p : -1;
     const double4 pa = T.valid ? B.pos4[T.a] : make_double4(0.0, 0.0, 0.0, 0.0);
-    T.xa = pa.x; T.ya = pa.y; T.za = pa.z; T.ha = pa.w;
+    T.xa = pa.x; T.ya = pa.y; T.za = pa.z; T.ha = pa.w; T.hs = pa.w * s1w;
     TileGeom G;
     tile_geometry(pa, T.valid, G, sub);
     tp[lane] = pa;
@@ -750,7 +757,7 @@ __global__ __launch_bounds__(64) void k_build_tiles(BuildArgs B) {
             const unsigned long long m = __ballot(pass);
             if (pass) {
               const int k = pend + __popcll(m & lt);
-              cb[k] = pb;
+              cb[k] = make_double4(pb.x, pb.y, pb.z, pb.w * s1w);
               cbi[k] = bu[u];
             }
             pend += __popcll(m);
