@@ -195,6 +195,7 @@ def test_neighbour_capacity_error_is_latched():
     with pytest.raises(sph.SphError) as e:
         ctx.sph_sync()
     assert e.value.code == 5
+    assert 0 <= e.value.particle < w.n                # the first particle that overflowed
     ctx.sph_sync()    # the status word was cleared
     sph, ctx, st = _ctx_state(w, max_neighbours=20)   # candidate lists (twice that) overflow too
     ctx.sph_build_cells(st)
@@ -287,3 +288,36 @@ def test_lanes_per_target(lanes):
         _print(f"lanes {lanes} {ker} periodic={periodic} fp32", ef)
         for k in ("D", "rho", "P", "ax", "ay", "az", "dudt", "dSdt"):
             assert ef[k] < 1e-4, (k, ef[k])
+
+
+def test_fp32_neighbour_decision_at_the_support_edge():
+    # isolated pairs whose separation is within 1e-12 (relative) of the support h_a + h_b, where
+    # the FP32 test cannot decide and the FP64 fallback must: the lists equal the oracle's, and the
+    # error reported through sph_error_particle is absent
+    eps = np.array([-1e-6, -1e-9, -1e-12, -1e-15, 0.0, 1e-15, 1e-12, 1e-9, 1e-6])
+    rng = np.random.default_rng(12)
+    xs, ys, zs, hs = [], [], [], []
+    for k, e in enumerate(eps):
+        ha, hb = 0.05 * rng.uniform(0.8, 1.2), 0.05 * rng.uniform(0.8, 1.2)
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        c = np.array([3.0 * k + 1.0, 2.0, 2.0])
+        b = c + d * (ha + hb) * (1.0 + e)
+        xs += [c[0], b[0]]
+        ys += [c[1], b[1]]
+        zs += [c[2], b[2]]
+        hs += [ha, hb]
+    n = len(xs)
+    arr = dict(x=np.array(xs), y=np.array(ys), z=np.array(zs), vx=np.zeros(n), vy=np.zeros(n), vz=np.zeros(n),
+               u=np.ones(n), h=np.array(hs), S=np.zeros((6, n)), type=np.zeros(n, np.int8),
+               broken=np.zeros(n, np.uint8), id=np.arange(n, dtype=np.int32))
+    for precision in ("FP32", "FP64"):
+        p = MethodParams(m=1e-3, kernel="WC4", periodic=False, box=0.0, eos="GAMMA_LAW", gamma=5 / 3,
+                         mu_mode="CONST", mu_const=0.0, precision=precision)
+        w = W.Workload("edge", p, dict(arr), 1e-3, 0)
+        g = gpu_run(w)
+        o = oracle_run(w, mode=oracle.BRUTE)
+        assert check_lists(g, o, n) == 0, precision
+        pairs = len(o["ids"])   # ordered pairs; the 4 pairs inside the support at least 1e-12 count twice
+        print(precision, "ordered pairs in the oracle lists:", pairs, flush=True)
+        assert 8 <= pairs <= 12
