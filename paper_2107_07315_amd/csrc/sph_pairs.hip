@@ -158,6 +158,27 @@ struct TileWalk {
   }
 };
 
+// Walk of a whole slot list when the tile's union fits one LDS chunk: f(local index) for every
+// entry, a 16-byte group (8 entries) per round with the entries taken at fixed positions (no
+// shifts or per-entry boundary tests), the next group in flight during the current one's 8 pairs.
+template <typename F>
+__device__ __forceinline__ void walk_groups(const uint4* base, int64_t gstride, int cnt, F&& f) {
+  uint4 g = make_uint4(0u, 0u, 0u, 0u);
+  if (cnt > 0) g = base[0];
+  const uint4* gp = base + gstride;
+  for (int k0 = 0; k0 < cnt; k0 += 8) {
+    uint4 nx = g;
+    if (k0 + 8 < cnt) nx = *gp;
+    gp += gstride;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const uint32_t w = i < 2 ? g.x : (i < 4 ? g.y : (i < 6 ? g.z : g.w));
+      if (k0 + i < cnt) f((int)((i & 1) ? (w >> 16) : (w & 0xffffu)));
+    }
+    g = nx;
+  }
+}
+
 // Sum over the L adjacent lanes that share a target (every one of them receives the sum).
 template <int L, typename T>
 __device__ __forceinline__ T lane_group_sum(T v) {
@@ -388,7 +409,8 @@ __global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* _
   const int total = tw.valid ? A.cnt_s[tw.p] : 0;
   const int64_t a = tw.a;
   const int64_t slot = a * L + sub;
-  tw.start(reinterpret_cast<const uint4*>(A.nbr16s) + slot, A.capw * L, total > sub ? (total - sub + L - 1) / L : 0);
+  const uint4* lst = reinterpret_cast<const uint4*>(A.nbr16s) + slot;
+  const int cnt = total > sub ? (total - sub + L - 1) / L : 0;
   const double4 pa = tw.valid ? pos64[a] : make_double4(0.0, 0.0, 0.0, 1.0);
   const double4 ref = pos64[A.tile_start[tile]];
   float4 paf = make_float4(0.f, 0.f, 0.f, 1.f);
@@ -401,8 +423,41 @@ __global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* _
   R sum = sub == 0 ? wendland_self<R>(KER, (R)pa.w) : (R)0;
   ListWriter<RB> wr;
   wr.init(reinterpret_cast<uint4*>(xlist) + slot, A.capw * L, lring[threadIdx.x], A.cap_sl);
-  for (int c0 = 0; c0 < tw.usize; c0 += CH) {
-    __syncthreads();
+  // candidate union member loc, whose record sits in LDS slot j
+  auto cand = [&](int loc, int j) {
+    const SR pb = sp[j];
+    bool hit;
+    R W;
+    if constexpr (F32) {
+      const float dx = wrap_sel<PER>(paf.x - pb.x, boxf, halff);
+      const float dy = wrap_sel<PER>(paf.y - pb.y, boxf, halff);
+      const float dz = wrap_sel<PER>(paf.z - pb.z, boxf, halff);
+      const float r2 = dx * dx + dy * dy + dz * dz;
+      const float H = paf.w + pb.w;
+      const float H2 = H * H;
+      const float M = fmaxf(Ma, fmaxf(fabsf(pb.x), fmaxf(fabsf(pb.y), fabsf(pb.z))));
+      hit = r2 < H2;
+      if (fabsf(r2 - H2) <= kBand * (M * H + H2)) {   // near the support edge: decide in FP64
+        const double4 q = pos64[tw.U[loc]];
+        const double r2d = pair_r2(wrap_sel<PER>(pa.x - q.x, box, half), wrap_sel<PER>(pa.y - q.y, box, half),
+                                   wrap_sel<PER>(pa.z - q.z, box, half));
+        const double Hd = pa.w + q.w;
+        hit = r2d < Hd * Hd;
+      }
+      W = kern_W<float, KER>(sqrt_fast(r2), rcp_fast(0.5f * H));
+    } else {
+      const double dx = wrap_sel<PER>(pa.x - pb.x, box, half);
+      const double dy = wrap_sel<PER>(pa.y - pb.y, box, half);
+      const double dz = wrap_sel<PER>(pa.z - pb.z, box, half);
+      const double r2 = pair_r2(dx, dy, dz);
+      const double H = pa.w + pb.w;
+      hit = r2 < H * H;
+      W = kern_W<R, KER>(sqrt_fast((R)r2), rcp_fast((R)(0.5 * H)));
+    }
+    sum += hit ? W : (R)0;
+    wr.put(loc, hit);
+  };
+  auto stage = [&](int c0) {
     for (int j = threadIdx.x; j < CH && c0 + j < tw.usize; j += 64 * L) {
       const double4 q = pos64[tw.U[c0 + j]];
       if constexpr (F32)
@@ -411,42 +466,24 @@ __global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* _
       else
         sp[j] = q;
     }
+  };
+  if (F32 && tw.usize <= CH) {   // FP32, whole union in one chunk: group walk
     __syncthreads();
-    const int cend = c0 + CH;
-    while (tw.next < cend) {
-      const int loc = tw.next;
-      const SR pb = sp[loc - c0];
-      tw.advance();
-      bool hit;
-      R W;
-      if constexpr (F32) {
-        const float dx = wrap_sel<PER>(paf.x - pb.x, boxf, halff);
-        const float dy = wrap_sel<PER>(paf.y - pb.y, boxf, halff);
-        const float dz = wrap_sel<PER>(paf.z - pb.z, boxf, halff);
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        const float H = paf.w + pb.w;
-        const float H2 = H * H;
-        const float M = fmaxf(Ma, fmaxf(fabsf(pb.x), fmaxf(fabsf(pb.y), fabsf(pb.z))));
-        hit = r2 < H2;
-        if (fabsf(r2 - H2) <= kBand * (M * H + H2)) {   // near the support edge: decide in FP64
-          const double4 q = pos64[tw.U[loc]];
-          const double r2d = pair_r2(wrap_sel<PER>(pa.x - q.x, box, half), wrap_sel<PER>(pa.y - q.y, box, half),
-                                     wrap_sel<PER>(pa.z - q.z, box, half));
-          const double Hd = pa.w + q.w;
-          hit = r2d < Hd * Hd;
-        }
-        W = kern_W<float, KER>(sqrt_fast(r2), rcp_fast(0.5f * H));
-      } else {
-        const double dx = wrap_sel<PER>(pa.x - pb.x, box, half);
-        const double dy = wrap_sel<PER>(pa.y - pb.y, box, half);
-        const double dz = wrap_sel<PER>(pa.z - pb.z, box, half);
-        const double r2 = pair_r2(dx, dy, dz);
-        const double H = pa.w + pb.w;
-        hit = r2 < H * H;
-        W = kern_W<R, KER>(sqrt_fast((R)r2), rcp_fast((R)(0.5 * H)));
+    stage(0);
+    __syncthreads();
+    walk_groups(lst, A.capw * L, cnt, [&](int loc) { cand(loc, loc); });
+  } else {
+    tw.start(lst, A.capw * L, cnt);
+    for (int c0 = 0; c0 < tw.usize; c0 += CH) {
+      __syncthreads();
+      stage(c0);
+      __syncthreads();
+      const int cend = c0 + CH;
+      while (tw.next < cend) {
+        const int loc = tw.next;
+        tw.advance();
+        cand(loc, loc - c0);
       }
-      sum += hit ? W : (R)0;
-      wr.put(loc, hit);
     }
   }
   wr.flush();
@@ -621,7 +658,8 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
   tw.begin(A, tile, tl);
   const int64_t a = tw.a;
   const int64_t slot = a * L + sub;
-  tw.start(reinterpret_cast<const uint4*>(A.nbr16) + slot, A.capw * L, tw.valid ? A.cnt_sl[slot] : 0);
+  const uint4* lst = reinterpret_cast<const uint4*>(A.nbr16) + slot;
+  const int cnt = tw.valid ? A.cnt_sl[slot] : 0;
   const int64_t n = A.n;
   const sph_params& p = A.p;
   const P4 pa = tw.valid ? pos[a] : P4{0, 0, 0, 1};
@@ -636,53 +674,70 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
     for (int c = 0; c < 6; ++c) sa[c] = sig[c * n + a];
   const R alpha_v = (R)p.visc_alpha, beta_v = (R)p.visc_beta, eps_v = (R)p.visc_eps;
   R AP[3] = {0, 0, 0}, AS[3] = {0, 0, 0}, ud = 0;
-  for (int c0 = 0; c0 < tw.usize; c0 += CH) {
-    __syncthreads();
+  // pair with union member loc, whose records sit in LDS slot j
+  auto pair = [&](int loc, int j) {
+    const P4 pb = sp[j];
+    const V4 vb = sv[j];
+    const A2 fab = sa2[j];
+    const R d[3] = {wrap_sel<PER>(pa.x - pb.x, box, half), wrap_sel<PER>(pa.y - pb.y, box, half),
+                    wrap_sel<PER>(pa.z - pb.z, box, half)};
+    const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    const R r = sqrt_fast(r2);
+    const R hab = Rec<R>::HS * (pa.w + pb.w);
+    const R F = kern_F<R, KER>(r, rcp_fast(hab));   // grad_a W = F d
+    const R v[3] = {va.x - vb.x, va.y - vb.y, va.z - vb.z};
+    const R vr = v[0] * d[0] + v[1] * d[1] + v[2] * d[2];
+    const bool b_st = fab.y < 0;
+    const R Db = b_st ? -fab.y : fab.y;
+    // Monaghan viscosity on approaching pairs: one reciprocal gives 1/X and 1/Dbar
+    const R X = r2 + eps_v * hab * hab;
+    const R Dbar = Rec<R>::HS * (Da + Db);
+    const R inv = rcp_fast(X * Dbar);
+    const R muab = hab * vr * (Dbar * inv);
+    const R cbar = Rec<R>::HS * (va.w + vb.w);
+    const R Pi = vr < (R)0 ? (-alpha_v * cbar * muab + beta_v * muab * muab) * (X * inv) : (R)0;
+    const R cPF = (pia + fab.x + Pi) * F;
+    AP[0] += cPF * d[0];
+    AP[1] += cPF * d[1];
+    AP[2] += cPF * d[2];
+    ud += (pia + (R)0.5 * Pi) * (F * vr);   // v_ab . grad_a W = F (v_ab . d)
+    if (a_st || b_st) {
+      const R g[3] = {F * d[0], F * d[1], F * d[2]};
+      R s6[6];
+      const int32_t b = b_st ? tw.U[loc] : 0;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) s6[c] = sa[c] + (b_st ? sig[c * n + b] : (R)0);
+      AS[0] += s6[0] * g[0] + s6[3] * g[1] + s6[4] * g[2];
+      AS[1] += s6[3] * g[0] + s6[1] * g[1] + s6[5] * g[2];
+      AS[2] += s6[4] * g[0] + s6[5] * g[1] + s6[2] * g[2];
+    }
+  };
+  auto stage = [&](int c0) {
     for (int j = threadIdx.x; j < CH && c0 + j < tw.usize; j += 64 * L) {
       const int32_t b = tw.U[c0 + j];
       sp[j] = pos[b];
       sv[j] = fv[b];
       sa2[j] = fa[b];
     }
+  };
+  // FP32 with the whole union in one chunk (the usual case): group walk.  (In FP64 the 8 inlined
+  // copies of the longer pair body run slower than the shifting walk, measured.)
+  if (std::is_same<R, float>::value && tw.usize <= CH) {
     __syncthreads();
-    const int cend = c0 + CH;
-    while (tw.next < cend) {
-      const int loc = tw.next;
-      const P4 pb = sp[loc - c0];
-      const V4 vb = sv[loc - c0];
-      const A2 fab = sa2[loc - c0];
-      tw.advance();
-      const R d[3] = {wrap_sel<PER>(pa.x - pb.x, box, half), wrap_sel<PER>(pa.y - pb.y, box, half),
-                      wrap_sel<PER>(pa.z - pb.z, box, half)};
-      const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-      const R r = sqrt_fast(r2);
-      const R hab = Rec<R>::HS * (pa.w + pb.w);
-      const R F = kern_F<R, KER>(r, rcp_fast(hab));   // grad_a W = F d
-      const R v[3] = {va.x - vb.x, va.y - vb.y, va.z - vb.z};
-      const R vr = v[0] * d[0] + v[1] * d[1] + v[2] * d[2];
-      const bool b_st = fab.y < 0;
-      const R Db = b_st ? -fab.y : fab.y;
-      // Monaghan viscosity on approaching pairs: one reciprocal gives 1/X and 1/Dbar
-      const R X = r2 + eps_v * hab * hab;
-      const R Dbar = Rec<R>::HS * (Da + Db);
-      const R inv = rcp_fast(X * Dbar);
-      const R muab = hab * vr * (Dbar * inv);
-      const R cbar = Rec<R>::HS * (va.w + vb.w);
-      const R Pi = vr < (R)0 ? (-alpha_v * cbar * muab + beta_v * muab * muab) * (X * inv) : (R)0;
-      const R cPF = (pia + fab.x + Pi) * F;
-      AP[0] += cPF * d[0];
-      AP[1] += cPF * d[1];
-      AP[2] += cPF * d[2];
-      ud += (pia + (R)0.5 * Pi) * (F * vr);   // v_ab . grad_a W = F (v_ab . d)
-      if (a_st || b_st) {
-        const R g[3] = {F * d[0], F * d[1], F * d[2]};
-        R s6[6];
-        const int32_t b = b_st ? tw.U[loc] : 0;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) s6[c] = sa[c] + (b_st ? sig[c * n + b] : (R)0);
-        AS[0] += s6[0] * g[0] + s6[3] * g[1] + s6[4] * g[2];
-        AS[1] += s6[3] * g[0] + s6[1] * g[1] + s6[5] * g[2];
-        AS[2] += s6[4] * g[0] + s6[5] * g[1] + s6[2] * g[2];
+    stage(0);
+    __syncthreads();
+    walk_groups(lst, A.capw * L, cnt, [&](int loc) { pair(loc, loc); });
+  } else {
+    tw.start(lst, A.capw * L, cnt);
+    for (int c0 = 0; c0 < tw.usize; c0 += CH) {
+      __syncthreads();
+      stage(c0);
+      __syncthreads();
+      const int cend = c0 + CH;
+      while (tw.next < cend) {
+        const int loc = tw.next;
+        tw.advance();
+        pair(loc, loc - c0);
       }
     }
   }
