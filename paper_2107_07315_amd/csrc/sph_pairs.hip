@@ -467,7 +467,7 @@ __global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* _
         sp[j] = q;
     }
   };
-  if (F32 && tw.usize <= CH) {   // FP32, whole union in one chunk: group walk
+  if (tw.usize <= CH) {   // whole union in one chunk: group walk
     __syncthreads();
     stage(0);
     __syncthreads();
