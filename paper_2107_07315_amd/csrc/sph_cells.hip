@@ -314,6 +314,36 @@ __global__ __launch_bounds__(kB) void k_tile_flags(const uint32_t* __restrict__ 
   flag[p] = start ? 1u : 0u;
 }
 
+// Work list of the stress pass: the tiles that hold a particle of type 1 (crust).  Breaking only
+// removes particles from the stressed set and type never changes, so the list stays a superset
+// until the next build.  Every other particle is of type 0 and has zero stress rates, which
+// k_zero_fluid_rates sets once per build (the rates of type-1 particles are written by the pass).
+__global__ __launch_bounds__(kB) void k_stress_flags(const GridInfo* __restrict__ gp, int64_t cap_tiles,
+                                                     const int32_t* __restrict__ tile_start,
+                                                     const int32_t* __restrict__ tile_cnt,
+                                                     const int8_t* __restrict__ type, uint32_t* __restrict__ flag) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cap_tiles) return;
+  uint32_t f = 0u;
+  if (t < (int64_t)gp->ntiles) {
+    const int32_t s = tile_start[t], e = s + tile_cnt[t];
+    for (int32_t q = s; q < e; ++q) f |= type[q] == 1 ? 1u : 0u;
+  }
+  flag[t] = f;
+}
+__global__ __launch_bounds__(kB) void k_stress_list(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ idx,
+                                                    int64_t cap_tiles, int32_t* __restrict__ list) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < cap_tiles && flag[t]) list[idx[t]] = (int32_t)t;
+}
+__global__ __launch_bounds__(kB) void k_zero_fluid_rates(const int8_t* __restrict__ type, int64_t n,
+                                                         double* __restrict__ dSdt, double* __restrict__ sdot) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n || type[a] == 1) return;
+  for (int c = 0; c < 6; ++c) dSdt[c * n + a] = 0.0;
+  sdot[a] = 0.0;
+}
+
 __global__ __launch_bounds__(kB) void k_tile_fill(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ idx,
                                                   int64_t n, int32_t* __restrict__ tile_start) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -924,6 +954,14 @@ sph_status sph_rebin(sph_ctx* c, sph_state* st) {
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_build_tiles<true>), dim3(tile_grid(c->cap_tiles)), dim3(64), 0, s, B);
   else
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_build_tiles<false>), dim3(tile_grid(c->cap_tiles)), dim3(64), 0, s, B);
+  HIP_TRY(hipGetLastError());
+  // stress-pass work list and the zero rates of every type-0 particle
+  hipLaunchKernelGGL(k_stress_flags, dim3(grid_for(c->cap_tiles, kB)), dim3(kB), 0, s, c->grid, c->cap_tiles,
+                     c->tile_start, c->tile_cnt, st->type, flag);
+  if ((e = sph_scan_u32(c, flag, idx, c->cap_tiles, &c->grid->nstress))) return e;
+  hipLaunchKernelGGL(k_stress_list, dim3(grid_for(c->cap_tiles, kB)), dim3(kB), 0, s, flag, idx, c->cap_tiles,
+                     c->stress_tiles);
+  hipLaunchKernelGGL(k_zero_fluid_rates, dim3(grid_for(n, kB)), dim3(kB), 0, s, st->type, n, st->dSdt, c->sdot);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(c->pos_build, c->pos4, sizeof(double4) * n, hipMemcpyDeviceToDevice, s));
   return launch_pack(c, st);

@@ -33,6 +33,7 @@ struct GridInfo {
   double skin;          // relative Verlet skin of the current candidate lists (0 or >= 1e-4)
   uint32_t ntiles;      // tiles of the current array order (written on the device)
   uint32_t upool_used;  // union-pool entries reserved by the tiles
+  uint32_t nstress;     // tiles holding a particle of type 1 (the stress pass's work list)
 };
 
 // Per-star parameters of an ensemble (centre of the star's background, particle mass and
@@ -330,6 +331,7 @@ struct sph_ctx {
   int64_t upool;        // entries of tile_u
   int64_t cap_tiles;
   int32_t* tile_usize;
+  int32_t* stress_tiles;  // tiles with a type-1 particle, in tile order (nstress of them)
   uint16_t* nbr16;      // exact lists, one per slot (particle * lanes + sub-index)
   int32_t* nbr_count;   // exact neighbours per particle
   int32_t* nbr_count_sl;  // entries per slot list

@@ -96,6 +96,7 @@ struct PassArgs {
   const uint32_t* __restrict__ tile_uoff;
   const int32_t* __restrict__ tile_u;
   const int32_t* __restrict__ tile_usize;
+  const int32_t* __restrict__ stress_tiles;
   const uint16_t* __restrict__ nbr16;    // exact lists (written by the density pass), one per slot
   const int32_t* __restrict__ cnt_sl;   // entries per slot; slot = particle * lanes + sub-index
   int cap_sl;                           // entries a slot holds
@@ -532,10 +533,11 @@ __global__ __launch_bounds__(64 * L) void k_stress(PassArgs A, const typename Re
   __shared__ P4 sp[CH];
   __shared__ V4 sv[CH];
   const R box = (R)A.p.box, half = (R)0.5 * box;
-  const int64_t ntl = num_tiles(A);
-  for (int64_t k_ = blockIdx.x / SPH_XCD, chunk_ = xcd_chunk(ntl); k_ < chunk_; k_ += gridDim.x / SPH_XCD) {
-    const int64_t tile = (int64_t)(blockIdx.x % SPH_XCD) * chunk_ + k_;
-    if (tile >= ntl) break;
+  // only the tiles of the work list (tiles with a type-1 particle); every other particle's rates
+  // are zero since the last build
+  const int64_t nst = (int64_t)A.grid->nstress;
+  for (int64_t w = blockIdx.x; w < nst; w += gridDim.x) {
+    const int64_t tile = A.stress_tiles[w];
   TileWalk tw;
   tw.begin(A, tile, tl);
   const int64_t a = tw.a;
@@ -801,6 +803,7 @@ PassArgs make_args(sph_ctx* c, sph_state* st) {
   A.tile_uoff = c->tile_uoff;
   A.tile_u = c->tile_u;
   A.tile_usize = c->tile_usize;
+  A.stress_tiles = c->stress_tiles;
   A.nbr16 = c->nbr16;
   A.cnt_sl = c->nbr_count_sl;
   A.cap_sl = slot_capacity(c->cap, pass_lanes(c->p));
@@ -891,7 +894,7 @@ sph_status launch_eos(sph_ctx* c, sph_state* st) {
 
 sph_status launch_stress(sph_ctx* c, sph_state* st) {
   PassArgs A = make_args(c, st);
-  const dim3 g = pass_grid(c);
+  const dim3 g((unsigned)(c->cap_tiles < 4096 ? c->cap_tiles : 4096));   // loops over the work list
   dispatch_cfg(c->p.kernel, c->p.periodic, [&](auto K, auto P) {
     dispatch_lanes(pass_lanes(c->p), [&](auto LL) {
       constexpr int KER = decltype(K)::value;
