@@ -360,11 +360,13 @@ __device__ __forceinline__ void density_epilogue(const PassArgs& A, int64_t a, b
   if (sizeof(R) == 8) {
     O.fv[a] = make_double4(va[0], va[1], va[2], cs);
     O.fa[a] = make_double2(pi, stressed ? -D : D);
-    for (int c = 0; c < 6; ++c) O.sig[c * n + a] = S[c * n + a] * iD2;
+    if (stressed)   // S/D^2 is read only for stressed particles (the sign of D in fa marks them)
+      for (int c = 0; c < 6; ++c) O.sig[c * n + a] = S[c * n + a] * iD2;
   } else {
     O.fvf[a] = make_float4((float)va[0], (float)va[1], (float)va[2], (float)(0.5 * cs));
     O.faf[a] = make_float2((float)pi, stressed ? -(float)(0.5 * D) : (float)(0.5 * D));
-    for (int c = 0; c < 6; ++c) O.sigf[c * n + a] = (float)(S[c * n + a] * iD2);
+    if (stressed)
+      for (int c = 0; c < 6; ++c) O.sigf[c * n + a] = (float)(S[c * n + a] * iD2);
   }
   if (!isfinite(D) || !isfinite(P) || !isfinite(cs)) latch_error(A.status, SPH_E_NONFINITE, (int)a);
 }
