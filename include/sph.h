@@ -68,7 +68,9 @@ enum { SPH_FP64 = 0, SPH_FP32 = 1 };
  * energy, deviatoric stress; equal mass per particle, section "Fixed metric background").
  * x,y,z: coordinate positions (isotropic coordinates with the TOV background).
  * vx,vy,vz: coordinate velocity dx/dt.  u: specific internal energy.  h: smoothing length.
- * S: deviatoric stress (6 comps).  type: 0 fluid core, 1 solid crust.  broken: 1 once the
+ * S: deviatoric stress (6 comps).  type: 0 fluid core, 1 solid crust; a fluid particle carries no
+ * deviatoric stress: every candidate-list build (sph_build_cells, and sph_step when particles
+ * have moved past the skin) sets S and dSdt of type-0 particles to 0.  broken: 1 once the
  * maximum-strain criterion fired.  id: caller's particle id, permuted with the particles.
  * star: optional (may be NULL) index into the ensemble table of sph_ensemble_set.
  * Outputs: D computational density, rho rest-mass density, P pressure, cs sound speed,

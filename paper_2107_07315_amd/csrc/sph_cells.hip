@@ -316,8 +316,9 @@ __global__ __launch_bounds__(kB) void k_tile_flags(const uint32_t* __restrict__ 
 
 // Work list of the stress pass: the tiles that hold a particle of type 1 (crust).  Breaking only
 // removes particles from the stressed set and type never changes, so the list stays a superset
-// until the next build.  Every other particle is of type 0 and has zero stress rates, which
-// k_zero_fluid_rates sets once per build (the rates of type-1 particles are written by the pass).
+// until the next build.  Every other particle is of type 0, carries no deviatoric stress and has
+// zero stress rates, which k_zero_fluid_rates sets once per build (the kicks then skip the stress
+// arrays of type-0 particles; the rates of type-1 particles are written by the pass).
 __global__ __launch_bounds__(kB) void k_stress_flags(const GridInfo* __restrict__ gp, int64_t cap_tiles,
                                                      const int32_t* __restrict__ tile_start,
                                                      const int32_t* __restrict__ tile_cnt,
@@ -337,10 +338,14 @@ __global__ __launch_bounds__(kB) void k_stress_list(const uint32_t* __restrict__
   if (t < cap_tiles && flag[t]) list[idx[t]] = (int32_t)t;
 }
 __global__ __launch_bounds__(kB) void k_zero_fluid_rates(const int8_t* __restrict__ type, int64_t n,
-                                                         double* __restrict__ dSdt, double* __restrict__ sdot) {
+                                                         double* __restrict__ S, double* __restrict__ dSdt,
+                                                         double* __restrict__ sdot) {
   const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= n || type[a] == 1) return;
-  for (int c = 0; c < 6; ++c) dSdt[c * n + a] = 0.0;
+  for (int c = 0; c < 6; ++c) {
+    S[c * n + a] = 0.0;   // fluid (type 0) carries no deviatoric stress
+    dSdt[c * n + a] = 0.0;
+  }
   sdot[a] = 0.0;
 }
 
@@ -961,7 +966,8 @@ sph_status sph_rebin(sph_ctx* c, sph_state* st) {
   if ((e = sph_scan_u32(c, flag, idx, c->cap_tiles, &c->grid->nstress))) return e;
   hipLaunchKernelGGL(k_stress_list, dim3(grid_for(c->cap_tiles, kB)), dim3(kB), 0, s, flag, idx, c->cap_tiles,
                      c->stress_tiles);
-  hipLaunchKernelGGL(k_zero_fluid_rates, dim3(grid_for(n, kB)), dim3(kB), 0, s, st->type, n, st->dSdt, c->sdot);
+  hipLaunchKernelGGL(k_zero_fluid_rates, dim3(grid_for(n, kB)), dim3(kB), 0, s, st->type, n, st->S, st->dSdt,
+                     c->sdot);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(c->pos_build, c->pos4, sizeof(double4) * n, hipMemcpyDeviceToDevice, s));
   return launch_pack(c, st);

@@ -38,22 +38,24 @@ __device__ __forceinline__ double wrap(double q, int periodic, double box) {
 
 // First half kick, drift and predictors of particle a from its start-of-step v, u, S and h:
 // stores the half-step copies, x, the predicted v, u and (yielded) S, the packed position records,
-// and runs the skin test.
+// and runs the skin test.  Type-0 particles carry no deviatoric stress (S and its rate are zero,
+// set at every list build), so their stress arrays are neither read nor written.
 __device__ __forceinline__ void kick_drift_from(const KdkArgs& K, int64_t a, const double v0[3], double u0,
-                                                const double S0[6], double h) {
+                                                const double S0[6], double h, bool solid) {
   const double hdt = 0.5 * K.dt;
   const int64_t n = K.n, hs = K.hstride;
   double* H = K.half;
   const double ax = K.ax[a], ay = K.ay[a], az = K.az[a], du = K.dudt[a];
   double vh[3] = {v0[0] + hdt * ax, v0[1] + hdt * ay, v0[2] + hdt * az};
   double uh = u0 + hdt * du;
-  double s[6];
-  for (int c = 0; c < 6; ++c) {
-    const double ds = K.dSdt[c * n + a];
-    double sh = S0[c] + hdt * ds;
-    H[(4 + c) * hs + a] = sh;
-    s[c] = sh + hdt * ds;
-  }
+  double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (solid)
+    for (int c = 0; c < 6; ++c) {
+      const double ds = K.dSdt[c * n + a];
+      double sh = S0[c] + hdt * ds;
+      H[(4 + c) * hs + a] = sh;
+      s[c] = sh + hdt * ds;
+    }
   H[0 * hs + a] = vh[0];
   H[1 * hs + a] = vh[1];
   H[2 * hs + a] = vh[2];
@@ -85,14 +87,16 @@ __device__ __forceinline__ void kick_drift_from(const KdkArgs& K, int64_t a, con
   K.vy[a] = vh[1] + hdt * ay;
   K.vz[a] = vh[2] + hdt * az;
   K.u[a] = uh + hdt * du;
-  yield_scale(K.p.yield_mode, K.Y0[a], s);
-  for (int c = 0; c < 6; ++c) K.S[c * n + a] = s[c];
+  if (solid) {
+    yield_scale(K.p.yield_mode, K.Y0[a], s);
+    for (int c = 0; c < 6; ++c) K.S[c * n + a] = s[c];
+  }
 }
 
 // Second half kick of particle a from the half-step copies: end-of-step v, u and S (yield scaling
 // and the breaking test applied; breaking is recorded), and the adaptive h of the step's density.
 __device__ __forceinline__ void final_kick_of(const KdkArgs& K, int64_t a, double v[3], double& u, double s[6],
-                                              double& h) {
+                                              double& h, bool solid) {
   const double hdt = 0.5 * K.dt;
   const int64_t n = K.n, hs = K.hstride;
   const double* H = K.half;
@@ -100,9 +104,12 @@ __device__ __forceinline__ void final_kick_of(const KdkArgs& K, int64_t a, doubl
   v[1] = H[1 * hs + a] + hdt * K.ay[a];
   v[2] = H[2 * hs + a] + hdt * K.az[a];
   u = H[3 * hs + a] + hdt * K.dudt[a];
-  for (int c = 0; c < 6; ++c) s[c] = H[(4 + c) * hs + a] + hdt * K.dSdt[c * n + a];
-  yield_scale(K.p.yield_mode, K.Y0[a], s);
-  if (K.p.break_mode != SPH_BREAK_OFF && K.type[a] == 1 && !K.broken[a]) {
+  for (int c = 0; c < 6; ++c) s[c] = 0.0;
+  if (solid) {
+    for (int c = 0; c < 6; ++c) s[c] = H[(4 + c) * hs + a] + hdt * K.dSdt[c * n + a];
+    yield_scale(K.p.yield_mode, K.Y0[a], s);
+  }
+  if (solid && K.p.break_mode != SPH_BREAK_OFF && !K.broken[a]) {
     const double mu = K.mu[a], Bm = K.B[a];
     if (mu > 0.0) {
       const double E = 9.0 * Bm * mu / (3.0 * Bm + mu);
@@ -127,10 +134,12 @@ __global__ __launch_bounds__(kB) void k_kick_drift(KdkArgs K) {
   const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= K.n) return;
   const int64_t n = K.n;
+  const bool solid = K.type[a] == 1;
   const double v0[3] = {K.vx[a], K.vy[a], K.vz[a]};
-  double S0[6];
-  for (int c = 0; c < 6; ++c) S0[c] = K.S[c * n + a];
-  kick_drift_from(K, a, v0, K.u[a], S0, K.h[a]);
+  double S0[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (solid)
+    for (int c = 0; c < 6; ++c) S0[c] = K.S[c * n + a];
+  kick_drift_from(K, a, v0, K.u[a], S0, K.h[a], solid);
 }
 
 // second half kick: end-of-step state
@@ -138,13 +147,15 @@ __global__ __launch_bounds__(kB) void k_kick_final(KdkArgs K) {
   const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= K.n) return;
   const int64_t n = K.n;
+  const bool solid = K.type[a] == 1;
   double v[3], u, s[6], h;
-  final_kick_of(K, a, v, u, s, h);
+  final_kick_of(K, a, v, u, s, h, solid);
   K.vx[a] = v[0];
   K.vy[a] = v[1];
   K.vz[a] = v[2];
   K.u[a] = u;
-  for (int c = 0; c < 6; ++c) K.S[c * n + a] = s[c];
+  if (solid)
+    for (int c = 0; c < 6; ++c) K.S[c * n + a] = s[c];
   K.h[a] = h;
 }
 
@@ -153,10 +164,11 @@ __global__ __launch_bounds__(kB) void k_kick_final(KdkArgs K) {
 __global__ __launch_bounds__(kB) void k_kick_final_drift(KdkArgs K) {
   const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= K.n) return;
+  const bool solid = K.type[a] == 1;
   double v[3], u, s[6], h;
-  final_kick_of(K, a, v, u, s, h);
+  final_kick_of(K, a, v, u, s, h, solid);
   K.h[a] = h;
-  kick_drift_from(K, a, v, u, s, h);
+  kick_drift_from(K, a, v, u, s, h, solid);
 }
 
 KdkArgs make_kdk(sph_ctx* c, sph_state* st, double dt) {
