@@ -435,76 +435,79 @@ struct TileState {
   double xa, ya, za, ha;
   double hs;                 // ha (1 + skin)(1 + 2^-40), the candidate test's scaled h
   int usize, cnt, ucap;
-  int64_t p;
   int32_t* U;
   uint16_t (*row)[8];        // the lane's staging rows in LDS, one per slot
+  uint4* slot0;              // group 0 of the lane's first slot
+  int64_t gstride;           // groups between consecutive groups of one slot (capw * lanes)
 };
 
-// Candidate k of a particle goes to its slot k % lanes, as entry k / lanes: each lane of the
-// density pass then walks one contiguous slot list.  Entries are staged in the slot's 16-byte
-// LDS row and stored a full group of 8 at a time (group g of slot s at g * capw * lanes + s).
-__device__ __forceinline__ void store_slot_group(const BuildArgs& B, const TileState& T, int sl, int g) {
+// Candidate k of a particle goes to its slot k % L, as entry k / L (L = lanes per target of the
+// pair passes): each lane of the density pass then walks one contiguous slot list.  Entries are
+// staged in the slot's 16-byte LDS row and stored a full group of 8 at a time (group g of slot s
+// at g * capw * L + s).
+__device__ __forceinline__ void store_slot_group(const TileState& T, int sl, int g) {
   uint4 v;
   __builtin_memcpy(&v, T.row[sl], sizeof(v));
-  reinterpret_cast<uint4*>(B.nbr16)[(int64_t)g * B.capw * B.lanes + T.p * B.lanes + sl] = v;
+  T.slot0[(int64_t)g * T.gstride + sl] = v;
 }
+template <int L>
 __device__ __forceinline__ void append_candidate(const BuildArgs& B, TileState& T, int loc) {
-  const int sl = T.cnt & (B.lanes - 1);
-  const int pos = T.cnt / B.lanes;
+  const unsigned k = (unsigned)T.cnt;
+  const int sl = (int)(k & (L - 1));
+  const int pos = (int)(k / L);
   const uint16_t v = (uint16_t)loc;
   __builtin_memcpy(&T.row[sl][pos & 7], &v, sizeof(v));
   ++T.cnt;
-  if ((pos & 7) == 7 && pos < B.cap_sl) store_slot_group(B, T, sl, pos >> 3);
+  if ((pos & 7) == 7 && pos < B.cap_sl) store_slot_group(T, sl, pos >> 3);
 }
 
 // candidate test (skin-widened, FP64) of every lane's target against batch candidates cb[0..nb),
-// nb <= 64; NB > 0 fixes nb at compile time (full batches, fully unrolled).  The test is
+// nb <= 64; NB > 0 fixes nb at compile time (full batches).  The test is
 // r^2 < (h_a' + h_b')^2 with h' = h (1 + skin)(1 + 2^-40) (T.hs, cb[j].w) and r^2 by FMA: the
 // factor 1 + 2^-40 exceeds the few ulp by which this rounding can differ from the exact decision
 // of the density pass, so the candidates always contain every pair that test can accept (with a
 // positive skin the rebuild test's own margin of 1e-9 is larger still).
-template <int NB, bool PER>
+// Candidates are taken one at a time: the wave's ballot decides at once whether candidate j joins
+// the union (as its next member), and the lanes that hit it append that local index, so the
+// lists come out ascending in local index and U in candidate order.
+template <int L, int NB, bool PER>
 __device__ __forceinline__ void run_batch(const BuildArgs& B, TileState& T, const double4* cb, const int32_t* cbi,
-                                          int nb, double box, double s1) {
+                                          int nb, double box) {
   const int lane = threadIdx.x;
-  unsigned long long hm = 0ull;
+  unsigned long long um = 0ull;   // the batch's union members (wave-uniform)
+  int nm = 0;
   auto test = [&](int j) -> bool {
     const double4 pb = cb[j];
     const double dx = min_image(T.xa - pb.x, (int)PER, box), dy = min_image(T.ya - pb.y, (int)PER, box),
                  dz = min_image(T.za - pb.z, (int)PER, box);
     const double H = T.hs + pb.w;
-    return cbi[j] != T.a && fma(dz, dz, fma(dy, dy, dx * dx)) < H * H;
+    return T.valid & (cbi[j] != T.a) & (fma(dz, dz, fma(dy, dy, dx * dx)) < H * H);
   };
-  if (T.valid) {
-    if constexpr (NB > 0) {
-      // 8 candidates per step with constant bit positions
-#pragma unroll 1
-      for (int jb = 0; jb < NB; jb += 8) {
-        uint32_t m8 = 0u;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) m8 |= test(jb + k) ? (1u << k) : 0u;
-        hm |= (unsigned long long)m8 << jb;
-      }
-    } else {
-      for (int j = 0; j < nb; ++j) hm |= test(j) ? (1ull << j) : 0ull;
+  auto take = [&](int j, bool hit) {
+    if (__ballot(hit)) {
+      um |= 1ull << j;
+      int loc = T.usize + nm;
+      ++nm;
+      loc = loc < T.ucap ? loc : T.ucap - 1;   // union overflow: keep reads in range, error latched
+      if (hit) append_candidate<L>(B, T, loc);
     }
+  };
+  if constexpr (NB > 0) {
+#pragma unroll 1
+    for (int jb = 0; jb < NB; jb += 8) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) take(jb + k, test(jb + k));
+    }
+  } else {
+    for (int j = 0; j < nb; ++j) take(j, test(j));
   }
-  const unsigned long long um = wave_or_u64(hm);
   if (!um) return;
   const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
   if ((um >> lane) & 1ull) {
     const int loc = T.usize + __popcll(um & lt);
     if (loc < T.ucap) T.U[loc] = cbi[lane];
   }
-  unsigned long long mm = hm;
-  while (mm) {
-    const int j = __ffsll((long long)mm) - 1;
-    mm &= mm - 1ull;
-    int loc = T.usize + __popcll(um & ((1ull << j) - 1ull));
-    loc = loc < T.ucap ? loc : T.ucap - 1;   // union overflow: keep reads in range, error latched
-    append_candidate(B, T, loc);
-  }
-  T.usize += __popcll(um);
+  T.usize += nm;
 }
 
 // Geometry of one tile, shared by the cost and build kernels: whole-tile box and max h
@@ -586,8 +589,10 @@ __device__ __forceinline__ void cell_range(const GridInfo& g, int l, const Level
                                            const double (*sub)[8], const int2* __restrict__ cell_se, int& s, int& e) {
   s = e = 0;
   if (j >= L.total) return;
-  const int kk[3] = {L.lo3[0] + (int)(j % L.ext[0]), L.lo3[1] + (int)((j / L.ext[0]) % L.ext[1]),
-                     L.lo3[2] + (int)(j / ((int64_t)L.ext[0] * L.ext[1]))};
+  // the box holds at most 2^30 cells (10 bits per axis), so 32-bit index arithmetic suffices
+  const unsigned jj = (unsigned)j, e0 = (unsigned)L.ext[0], e1 = (unsigned)L.ext[1];
+  const unsigned j1 = jj / e0;
+  const int kk[3] = {L.lo3[0] + (int)(jj - j1 * e0), L.lo3[1] + (int)(j1 % e1), L.lo3[2] + (int)(j1 / e1)};
   int cc[3];
   double b0[3], b1[3];
   bool gapd[3];
@@ -680,11 +685,11 @@ __global__ __launch_bounds__(kB) void k_tile_split(uint32_t* __restrict__ flag, 
 // Tile t is particles [tile_start[t], tile_start[t] + tile_cnt[t]) of the array order (at most 64).
 // Candidates enter batches in a fixed order (level, cell, cell-sorted position), so U and the
 // lists are deterministic and each list is ascending in local index.
-template <bool PER>
-__global__ __launch_bounds__(64) void k_build_tiles(BuildArgs B) {
+template <bool PER, int NL>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_build_tiles(BuildArgs B) {
   __shared__ int32_t c_s[64], c_o[64];
   __shared__ double sub[8][8];   // per group of 8 tile particles: centre xyz, half-width xyz, max h
-  __shared__ double4 tp[64];     // the tile's particles (exact pre-filter of small tiles)
+  __shared__ double4 tp[16];     // the particles of a small tile (its exact pre-filter)
   __shared__ double4 cb[128];
   __shared__ int32_t cbi[128];
   __shared__ __align__(16) uint16_t crow[64][4][8];   // per lane and slot: staging of the candidate lists
@@ -707,7 +712,7 @@ __global__ __launch_bounds__(64) void k_build_tiles(BuildArgs B) {
     T.xa = pa.x; T.ya = pa.y; T.za = pa.z; T.ha = pa.w; T.hs = pa.w * s1w;
     TileGeom G;
     tile_geometry(pa, T.valid, G, sub);
-    tp[lane] = pa;
+    if (lane < 16) tp[lane] = pa;
     // small tiles (split because they are expensive) pre-filter candidates exactly against
     // their own particles: far fewer batches, each of which would use only tcnt lanes
     const bool small = tcnt <= 16;
@@ -718,9 +723,10 @@ __global__ __launch_bounds__(64) void k_build_tiles(BuildArgs B) {
       if (lane == 0) latch_error(B.status, SPH_E_NGB_CAPACITY, -1);
     }
     T.U = B.tile_u + uoff;
-    T.p = T.valid ? p : 0;
     T.usize = 0; T.cnt = 0;
     T.row = crow[lane];
+    T.slot0 = reinterpret_cast<uint4*>(B.nbr16) + (T.valid ? p : 0) * NL;
+    T.gstride = B.capw * NL;
     int pend = 0;   // candidates waiting in cb (wave-uniform)
     for (int l = 0; l < g.nlev; ++l) {
       LevelBox L;
@@ -798,7 +804,7 @@ __global__ __launch_bounds__(64) void k_build_tiles(BuildArgs B) {
             pend += __popcll(m);
             __syncthreads();
             if (pend >= 64) {   // phase 3 on a full batch
-              run_batch<64, PER>(B, T, cb, cbi, 64, box, s1);
+              run_batch<NL, 64, PER>(B, T, cb, cbi, 64, box);
               const int rest = pend - 64;
               double4 mv = make_double4(0.0, 0.0, 0.0, 0.0);
               int32_t mi = 0;
@@ -812,12 +818,12 @@ __global__ __launch_bounds__(64) void k_build_tiles(BuildArgs B) {
         }
       }
     }
-    if (pend > 0) run_batch<0, PER>(B, T, cb, cbi, pend, box, s1);
+    if (pend > 0) run_batch<NL, 0, PER>(B, T, cb, cbi, pend, box);
     __syncthreads();
     if (T.valid && T.cnt <= B.cap)
-      for (int sl = 0; sl < B.lanes; ++sl) {   // partly filled last group of each slot
-        const int ns = T.cnt > sl ? (T.cnt - sl + B.lanes - 1) / B.lanes : 0;
-        if ((ns & 7) && ns <= B.cap_sl) store_slot_group(B, T, sl, ns >> 3);
+      for (int sl = 0; sl < NL; ++sl) {   // partly filled last group of each slot
+        const int ns = T.cnt > sl ? (T.cnt - sl + NL - 1) / NL : 0;
+        if ((ns & 7) && ns <= B.cap_sl) store_slot_group(T, sl, ns >> 3);
       }
     if (T.valid) B.count[p] = T.cnt < B.cap ? T.cnt : B.cap;
     if (lane == 0) B.tile_usize[t] = T.usize < T.ucap ? T.usize : T.ucap;
@@ -880,6 +886,20 @@ static sph_status ensure_pool(sph_ctx* c) {
 
 static unsigned tile_grid(int64_t cap_tiles) {
   return (unsigned)(cap_tiles < 65536 ? cap_tiles : 65536);
+}
+
+template <bool PER>
+static void launch_build_per(const BuildArgs& B, dim3 grid, hipStream_t s) {
+  if (B.lanes == 1)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_build_tiles<PER, 1>), grid, dim3(64), 0, s, B);
+  else if (B.lanes == 2)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_build_tiles<PER, 2>), grid, dim3(64), 0, s, B);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_build_tiles<PER, 4>), grid, dim3(64), 0, s, B);
+}
+static void launch_build(const BuildArgs& B, bool per, dim3 grid, hipStream_t s) {
+  if (per) launch_build_per<true>(B, grid, s);
+  else launch_build_per<false>(B, grid, s);
 }
 
 // Candidate-list build: every particle array of the state (and the half-step copies) is reordered
@@ -955,10 +975,7 @@ sph_status sph_rebin(sph_ctx* c, sph_state* st) {
   B.tile_start = c->tile_start; B.tile_cnt = c->tile_cnt; B.tile_uoff = c->tile_uoff; B.upool = c->upool;
   B.tile_u = c->tile_u; B.tile_usize = c->tile_usize; B.nbr16 = c->nbr16s; B.count = c->nbr_count_s;
   B.status = c->status;
-  if (per)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_build_tiles<true>), dim3(tile_grid(c->cap_tiles)), dim3(64), 0, s, B);
-  else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_build_tiles<false>), dim3(tile_grid(c->cap_tiles)), dim3(64), 0, s, B);
+  launch_build(B, per, dim3(tile_grid(c->cap_tiles)), s);
   HIP_TRY(hipGetLastError());
   // stress-pass work list and the zero rates of every type-0 particle
   hipLaunchKernelGGL(k_stress_flags, dim3(grid_for(c->cap_tiles, kB)), dim3(kB), 0, s, c->grid, c->cap_tiles,
