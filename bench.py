@@ -96,7 +96,6 @@ def run_variant(w, precision, eos, steps, warmup, timing=True, ctx_kw=None, mlp=
     ctx.evaluate(st)
     ctx.sph_step(st, w.dt, warmup)
     ctx.sph_sync()
-    ctx.sph_set_timing(timing)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx.sph_step(st, w.dt, steps)
@@ -104,13 +103,19 @@ def run_variant(w, precision, eos, steps, warmup, timing=True, ctx_kw=None, mlp=
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / steps
+    # stage breakdown: the next `steps` steps with HIP events around every stage (the events cost
+    # a few percent, so they stay out of the timed run above)
     stages = {}
-    for s in ("cells", "density", "eos", "stress", "forces", "kdk"):
-        n, ms = ctx.sph_get_timing(s)
-        stages[s] = {"launches": n, "ms_total": ms}
+    if timing:
+        ctx.sph_set_timing(True)
+        ctx.sph_step(st, w.dt, steps)
+        ctx.sph_sync()
+        for s in ("cells", "density", "eos", "stress", "forces", "kdk"):
+            n, ms = ctx.sph_get_timing(s)
+            stages[s] = {"launches": n, "ms_total": ms}
+        ctx.sph_set_timing(False)
     stats = ctx.sph_neighbour_stats()
     pairs, maxc = stats["pairs"], stats["max_count"]
-    ctx.sph_set_timing(False)
     ctx.close()
     del st
     torch.cuda.empty_cache()

@@ -106,6 +106,8 @@ void sph_destroy(sph_ctx* c) {
   mlp_free(c);
   for (auto& t : c->timers)
     for (hipEvent_t e : t.ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->step_ev)
+    if (e) (void)hipEventDestroy(e);
   if (c->g_eval) (void)hipGraphExecDestroy(c->g_eval);
   if (c->g_drift) (void)hipGraphExecDestroy(c->g_drift);
   if (c->g_chain) (void)hipGraphExecDestroy(c->g_chain);
@@ -313,7 +315,7 @@ static sph_status capture_step(sph_ctx* c, sph_state* st, double dt) {
       if (!le) le = launch_forces(c, st);
     } else {
       if (!le) le = launch_flag_clear(c);
-      if (!le) le = which == 1 ? launch_kick_drift(c, st, dt, true) : launch_kick_final_drift(c, st, dt, true);
+      if (!le) le = which == 1 ? launch_kick_drift(c, st, dt, 1u) : launch_kick_final_drift(c, st, dt, 1u);
       if (!le && hipMemcpyAsync(c->drift_host, c->drift_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream) !=
                      hipSuccess)
         le = SPH_E_HIP;
@@ -356,6 +358,41 @@ static sph_status step_graphs(sph_ctx* c, sph_state* st, double dt, int32_t nste
 
 extern "C" {
 
+// kick of step k of a call: kick-drift for the first, else the previous final kick fused in
+static sph_status queue_kick(sph_ctx* c, sph_state* st, double dt, int32_t k, uint32_t check) {
+  timer_begin(c, TIMER_KDK);
+  const sph_status e = k == 0 ? launch_kick_drift(c, st, dt, check) : launch_kick_final_drift(c, st, dt, check);
+  timer_end(c, TIMER_KDK);
+  return e;
+}
+
+// density, EoS, stress rate and forces at the drifted positions; seq > 0: a run-ahead evaluation
+// of step number seq (cancelled on the device when the skin test of that or an earlier step failed)
+static sph_status queue_evaluation(sph_ctx* c, sph_state* st, uint32_t seq) {
+  c->eval_seq = seq;
+  sph_status e;
+  timer_begin(c, TIMER_DENSITY);
+  e = launch_density(c, st);
+  timer_end(c, TIMER_DENSITY);
+  if (!e) {
+    timer_begin(c, TIMER_EOS);
+    e = launch_eos(c, st);
+    timer_end(c, TIMER_EOS);
+  }
+  if (!e) {
+    timer_begin(c, TIMER_STRESS);
+    e = launch_stress(c, st);
+    timer_end(c, TIMER_STRESS);
+  }
+  if (!e) {
+    timer_begin(c, TIMER_FORCES);
+    e = launch_forces(c, st);
+    timer_end(c, TIMER_FORCES);
+  }
+  c->eval_seq = 0u;
+  return e;
+}
+
 sph_status sph_step(sph_ctx* c, sph_state* st, double dt, int32_t nsteps) {
   sph_status e = check_state(c, st);
   if (e) return e;
@@ -370,31 +407,49 @@ sph_status sph_step(sph_ctx* c, sph_state* st, double dt, int32_t nsteps) {
   }
   // Steps are chained: the final kick of step k and the kick-drift of step k + 1 run as one
   // kernel; the last step of the call ends with its own final kick.
-  for (int32_t k = 0; k < nsteps; ++k) {
-    const bool check = c->lists_valid && c->p.skin > 0.0;
-    if (check && (e = launch_flag_clear(c))) return e;
-    timer_begin(c, TIMER_KDK);
-    if ((e = k == 0 ? launch_kick_drift(c, st, dt, check) : launch_kick_final_drift(c, st, dt, check))) return e;
-    timer_end(c, TIMER_KDK);
-    bool stale = !check;
-    if (check && (e = read_drift(c, &stale))) return e;
-    if (stale && (e = rebuild(c, st))) return e;
-    timer_begin(c, TIMER_DENSITY);
-    if ((e = launch_density(c, st))) return e;
-    timer_end(c, TIMER_DENSITY);
-    timer_begin(c, TIMER_EOS);
-    if ((e = launch_eos(c, st))) return e;
-    timer_end(c, TIMER_EOS);
-    timer_begin(c, TIMER_STRESS);
-    if ((e = launch_stress(c, st))) return e;
-    timer_end(c, TIMER_STRESS);
-    timer_begin(c, TIMER_FORCES);
-    if ((e = launch_forces(c, st))) return e;
-    timer_end(c, TIMER_FORCES);
+  // With valid lists and a positive skin the host queues step k + 1 before it reads the skin test
+  // of step k back, so the device never waits for the host.  Steps carry their number since the
+  // test word was cleared: a kick or evaluation behind a failed test finds a smaller number there
+  // and does nothing; the host then rebuilds the lists, evaluates the failed step again and
+  // carries on after it.
+  for (hipEvent_t& ev : c->step_ev)
+    if (!ev) HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  int32_t k = 0;
+  while (k < nsteps) {
+    if (!(c->lists_valid && c->p.skin > 0.0)) {   // no lists to test: build them for this step
+      if ((e = queue_kick(c, st, dt, k, 0u)) || (e = rebuild(c, st)) || (e = queue_evaluation(c, st, 0u))) return e;
+      ++k;
+      continue;
+    }
+    if ((e = launch_flag_clear(c))) return e;
+    const int32_t k0 = k;   // step k0 + q - 1 has number q
+    int32_t queued = k;
+    while (k < nsteps) {
+      while (queued < nsteps && queued <= k + 1) {
+        const uint32_t q = (uint32_t)(queued - k0 + 1);
+        if ((e = queue_kick(c, st, dt, queued, q)) || (e = queue_evaluation(c, st, q))) return e;
+        HIP_TRY(hipMemcpyAsync(c->drift_host, c->drift_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipEventRecord(c->step_ev[queued & 1], c->stream));
+        ++queued;
+      }
+      HIP_TRY(hipEventSynchronize(c->step_ev[k & 1]));
+      const uint32_t f = *c->drift_host;   // a later step's copy may have landed too: still exact
+      if (f == 0u) {
+        ++k;
+        continue;
+      }
+      // the drift of step v broke the skin bound; the steps queued after it did nothing
+      const int32_t v = k0 + (int32_t)f - 1;
+      if ((e = rebuild(c, st)) || (e = queue_evaluation(c, st, 0u))) return e;
+      k = v + 1;
+      break;
+    }
   }
-  timer_begin(c, TIMER_KDK);
-  if ((e = launch_kick_final(c, st, dt))) return e;
-  timer_end(c, TIMER_KDK);
+  if (nsteps > 0) {
+    timer_begin(c, TIMER_KDK);
+    if ((e = launch_kick_final(c, st, dt))) return e;
+    timer_end(c, TIMER_KDK);
+  }
   c->gen = 4;
   return SPH_OK;
 }

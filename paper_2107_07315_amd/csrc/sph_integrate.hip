@@ -25,8 +25,18 @@ struct KdkArgs {
   // drift: packed position records for the next evaluation and the skin test
   double4* pos4; float4* pos4f;
   const double4* pos_build; const GridInfo* grid;
-  uint32_t check_id; uint32_t* flag;   // flag == nullptr: no test
+  // skin test: a violating particle raises *flag to check_id, this step's number since the flag
+  // was cleared; a step finds a smaller non-zero value there when an earlier step (run ahead of
+  // the host's test) broke the bound, and then leaves the state alone.  flag == nullptr: no test
+  uint32_t check_id; uint32_t* flag;
 };
+
+// a kick of a step that runs ahead of a failed skin test does nothing
+__device__ __forceinline__ bool kick_cancelled(const KdkArgs& K) {
+  if (!K.flag) return false;
+  const uint32_t f = *K.flag;
+  return f != 0u && f < K.check_id;
+}
 
 __device__ __forceinline__ double wrap(double q, int periodic, double box) {
   if (periodic) {
@@ -132,7 +142,7 @@ __device__ __forceinline__ void final_kick_of(const KdkArgs& K, int64_t a, doubl
 // packs the position records of the evaluation and runs the skin test against the last build
 __global__ __launch_bounds__(kB) void k_kick_drift(KdkArgs K) {
   const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= K.n) return;
+  if (a >= K.n || kick_cancelled(K)) return;
   const int64_t n = K.n;
   const bool solid = K.type[a] == 1;
   const double v0[3] = {K.vx[a], K.vy[a], K.vz[a]};
@@ -163,7 +173,7 @@ __global__ __launch_bounds__(kB) void k_kick_final(KdkArgs K) {
 // the end-of-step v, u, S and h stay in registers (the same arithmetic as the two kernels).
 __global__ __launch_bounds__(kB) void k_kick_final_drift(KdkArgs K) {
   const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= K.n) return;
+  if (a >= K.n || kick_cancelled(K)) return;
   const bool solid = K.type[a] == 1;
   double v[3], u, s[6], h;
   final_kick_of(K, a, v, u, s, h, solid);
@@ -206,17 +216,17 @@ sph_status launch_flag_clear(sph_ctx* c) {
   return SPH_OK;
 }
 
-sph_status launch_kick_drift(sph_ctx* c, sph_state* st, double dt, bool check) {
+sph_status launch_kick_drift(sph_ctx* c, sph_state* st, double dt, uint32_t check) {
   KdkArgs K = make_kdk(c, st, dt);
-  if (check) K.flag = c->drift_flag;
+  if (check) { K.flag = c->drift_flag; K.check_id = check; }
   hipLaunchKernelGGL(k_kick_drift, dim3(grid_for(st->n, kB)), dim3(kB), 0, c->stream, K);
   HIP_TRY(hipGetLastError());
   return SPH_OK;
 }
 
-sph_status launch_kick_final_drift(sph_ctx* c, sph_state* st, double dt, bool check) {
+sph_status launch_kick_final_drift(sph_ctx* c, sph_state* st, double dt, uint32_t check) {
   KdkArgs K = make_kdk(c, st, dt);
-  if (check) K.flag = c->drift_flag;
+  if (check) { K.flag = c->drift_flag; K.check_id = check; }
   hipLaunchKernelGGL(k_kick_final_drift, dim3(grid_for(st->n, kB)), dim3(kB), 0, c->stream, K);
   HIP_TRY(hipGetLastError());
   return SPH_OK;

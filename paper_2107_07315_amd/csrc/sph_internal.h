@@ -306,8 +306,10 @@ struct sph_ctx {
   double g_dt;
   uint32_t g_epoch;
   uint32_t check_id;    // id of the last drift test (written to drift_flag by violators)
-  uint32_t* drift_flag; // device word: largest check id that saw a skin violation
+  uint32_t* drift_flag; // device word: largest check id (step number) that saw a skin violation
   uint32_t* drift_host; // pinned host copy
+  uint32_t eval_seq;    // step number of a run-ahead evaluation being queued (0: none)
+  hipEvent_t step_ev[2];   // run-ahead steps: the skin-test word of a step has reached the host
   int64_t rebuilds;
   double4* pos_build;   // x, y, z, h at the last candidate-list build
   // grid and sort
@@ -377,10 +379,12 @@ sph_status launch_density(sph_ctx* c, sph_state* st);   // pair loop
 sph_status launch_eos(sph_ctx* c, sph_state* st);       // per-particle epilogue
 sph_status launch_stress(sph_ctx* c, sph_state* st);
 sph_status launch_forces(sph_ctx* c, sph_state* st);
-sph_status launch_kick_drift(sph_ctx* c, sph_state* st, double dt, bool check);
+// check: 0 no skin test, else the step's number since drift_flag was cleared (a larger value
+// already in the flag cancels the kick)
+sph_status launch_kick_drift(sph_ctx* c, sph_state* st, double dt, uint32_t check);
 sph_status launch_kick_final(sph_ctx* c, sph_state* st, double dt);
 // the final kick of one step fused with the kick-drift of the next (inside a multi-step call)
-sph_status launch_kick_final_drift(sph_ctx* c, sph_state* st, double dt, bool check);
+sph_status launch_kick_final_drift(sph_ctx* c, sph_state* st, double dt, uint32_t check);
 sph_status launch_pack(sph_ctx* c, sph_state* st);
 sph_status sph_count_stats(sph_ctx* c, sph_list_stats* out);
 sph_status sph_scan_u32(sph_ctx* c, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total);

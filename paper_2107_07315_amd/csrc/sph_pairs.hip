@@ -107,6 +107,10 @@ struct PassArgs {
   DevStatus* status;
   MlpView mlp;          // EoS surrogate (eos = MLP with a loaded network)
   int has_mlp;
+  // run-ahead evaluation of step number seq: cancelled when the skin-test word `stop` holds a
+  // step number in [1, seq] (that step's drift broke the skin bound); stop == nullptr: never
+  const uint32_t* stop;
+  uint32_t seq;
 };
 
 constexpr int kNone = 0x7fffffff;
@@ -188,7 +192,16 @@ __device__ __forceinline__ T lane_group_sum(T v) {
   return v;
 }
 
-__device__ __forceinline__ int64_t num_tiles(const PassArgs& A) { return (int64_t)A.grid->ntiles; }
+__device__ __forceinline__ bool cancelled(const PassArgs& A) {
+  if (!A.stop) return false;
+  const uint32_t f = *A.stop;
+  return f != 0u && f <= A.seq;
+}
+// work-item counts of the passes (zero for a cancelled evaluation)
+__device__ __forceinline__ int64_t num_tiles(const PassArgs& A) {
+  const int64_t nt = (int64_t)A.grid->ntiles;
+  return cancelled(A) ? 0 : nt;
+}
 
 __device__ __forceinline__ double particle_mass(const PassArgs& A, int64_t a) {
   return (A.star && A.stars) ? A.stars[A.star[a]].m : A.p.m;
@@ -511,9 +524,10 @@ __global__ __launch_bounds__(64) void k_density_epilogue(PassArgs A, const doubl
                                                          const double* __restrict__ vz, const double* __restrict__ u,
                                                          const double* __restrict__ S, const int8_t* __restrict__ type,
                                                          const uint8_t* __restrict__ broken, DensOut O) {
-  for (int64_t base = (int64_t)blockIdx.x * 64; base < A.n; base += (int64_t)gridDim.x * 64) {
+  const int64_t n = cancelled(A) ? 0 : A.n;
+  for (int64_t base = (int64_t)blockIdx.x * 64; base < n; base += (int64_t)gridDim.x * 64) {
     const int64_t a = base + threadIdx.x;
-    const bool valid = a < A.n;
+    const bool valid = a < n;
     const int64_t ae = valid ? a : base;   // lanes past the end work on a valid particle, store nothing
     density_epilogue<R, MLP>(A, ae, valid, O.D[ae], pos64, vx, vy, vz, u, S, type, broken, O);
   }
@@ -537,7 +551,7 @@ __global__ __launch_bounds__(64 * L) void k_stress(PassArgs A, const typename Re
   const R box = (R)A.p.box, half = (R)0.5 * box;
   // only the tiles of the work list (tiles with a type-1 particle); every other particle's rates
   // are zero since the last build
-  const int64_t nst = (int64_t)A.grid->nstress;
+  const int64_t nst = cancelled(A) ? 0 : (int64_t)A.grid->nstress;
   for (int64_t w = blockIdx.x; w < nst; w += gridDim.x) {
     const int64_t tile = A.stress_tiles[w];
   TileWalk tw;
@@ -815,6 +829,8 @@ PassArgs make_args(sph_ctx* c, sph_state* st) {
   A.stars = c->stars;
   A.status = c->status;
   A.has_mlp = mlp_view(c, &A.mlp) ? 1 : 0;
+  A.stop = c->eval_seq ? c->drift_flag : nullptr;
+  A.seq = c->eval_seq;
   return A;
 }
 
