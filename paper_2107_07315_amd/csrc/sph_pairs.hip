@@ -60,6 +60,40 @@ __device__ __forceinline__ R kern_F(R r, R ih) {
   }
 }
 
+// FP32 pair-loop forms of W and F without their constant factor (kern_W = kW * kern_W_unit,
+// kern_F = kF * kern_F_unit; the passes apply the factor once to the sums), with t^k / h^k formed
+// as (t / h)^k.  Outside the support t = 0, so both vanish there without a test.
+template <int KER>
+constexpr double kern_W_const() { return KER == SPH_WC4 ? 495.0 / (256.0 * SPH_PI) : 21.0 / (16.0 * SPH_PI); }
+template <int KER>
+constexpr double kern_F_const() { return KER == SPH_WC4 ? -1155.0 / (128.0 * SPH_PI) : -105.0 / (16.0 * SPH_PI); }
+template <int KER>
+__device__ __forceinline__ float kern_W_unit(float r, float ih) {
+  const float q = r * ih;
+  const float t = fmaxf(fmaf(-0.5f, q, 1.0f), 0.0f);
+  if constexpr (KER == SPH_WC4) {
+    const float w = t * t * ih;   // t^6 / h^3 = w^3
+    return w * w * w * fmaf(fmaf((float)(35.0 / 12.0), q, 3.0f), q, 1.0f);
+  } else {
+    const float w = t * ih;       // t^4 / h^3 = w^3 t
+    return w * w * w * t * fmaf(2.0f, q, 1.0f);
+  }
+}
+template <int KER>
+__device__ __forceinline__ float kern_F_unit(float r, float ih) {
+  const float q = r * ih;
+  const float t = fmaxf(fmaf(-0.5f, q, 1.0f), 0.0f);
+  const float w = t * ih;
+  if constexpr (KER == SPH_WC4) {
+    const float w2 = w * w;       // t^5 / h^5 = w^5
+    return w2 * w2 * w * fmaf(2.5f, q, 1.0f);
+  } else {
+    return w * w * w * (ih * ih); // t^3 / h^5
+  }
+}
+// |d| from r^2 in FP32: the hardware square root (about 1 ulp; 0 at 0)
+__device__ __forceinline__ float sqrt_hw(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 template <typename R> struct Rec;
 // Record scale: the FP64 records hold h, c_s and D; the FP32 ones hold h/2, c_s/2 and D/2 (exact
 // halvings), so the pair means 0.5 (h_a + h_b), 0.5 (c_a + c_b), 0.5 (D_a + D_b) are HS times the
@@ -384,12 +418,15 @@ __device__ __forceinline__ void density_epilogue(const PassArgs& A, int64_t a, b
   if (!isfinite(D) || !isfinite(P) || !isfinite(cs)) latch_error(A.status, SPH_E_NONFINITE, (int)a);
 }
 
-// Width of the FP32 guard band of the neighbour decision, relative to M H + H^2 (M the largest
-// coordinate magnitude of the pair relative to the tile's reference particle, H = h_a + h_b):
-// 64 u with u = 2^-24.  With coordinates and smoothing lengths rounded to FP32 and r^2, H^2
-// evaluated in FP32, |r2_f - r^2| <= 4 sqrt(3) u M |d| + 5 u r^2 and |H2_f - H^2| <= 7 u H^2 (to
-// first order), which stays below 64 u (M H + H^2) for every |d| <= 3.4 H; beyond that the FP32
-// decision cannot be wrong.  Outside the band the FP32 decision therefore equals the FP64 one.
+// Width of the FP32 guard band of the neighbour decision, relative to M_a H + H^2 (M_a the
+// largest coordinate magnitude of the target relative to the tile's reference particle,
+// H = h_a + h_b): 64 u with u = 2^-24.  With coordinates and smoothing lengths rounded to FP32 and
+// r^2, H^2 evaluated in FP32, |r2_f - r^2| <= 4 sqrt(3) u M |d| + 5 u r^2 and
+// |H2_f - H^2| <= 7 u H^2 (to first order), M the larger coordinate magnitude of the pair.  The
+// FP32 decision can differ from the exact one only if r^2 lies within that error of H^2, i.e.
+// |d| = H (1 + O(u)); then M <= M_a + |d| and the error is at most
+// 4 sqrt(3) u M_a H + (4 sqrt(3) + 12) u H^2 < 64 u (M_a H + H^2).  Outside the band the FP32
+// decision therefore equals the FP64 one.
 constexpr float kBand = 3.814697265625e-06f;   // 2^-18
 
 // Density pass.  Walks the candidate lists, takes the exact neighbour decision r^2 < (h_a + h_b)^2
@@ -436,7 +473,7 @@ __global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* _
                       (float)wrap_sel<PER>(pa.z - ref.z, box, half), (float)pa.w);
     Ma = fmaxf(fabsf(paf.x), fmaxf(fabsf(paf.y), fabsf(paf.z)));
   }
-  R sum = sub == 0 ? wendland_self<R>(KER, (R)pa.w) : (R)0;
+  R sum = 0;
   ListWriter<RB> wr;
   wr.init(reinterpret_cast<uint4*>(xlist) + slot, A.capw * L, lring[threadIdx.x], A.cap_sl);
   // candidate union member loc, whose record sits in LDS slot j
@@ -451,16 +488,15 @@ __global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* _
       const float r2 = dx * dx + dy * dy + dz * dz;
       const float H = paf.w + pb.w;
       const float H2 = H * H;
-      const float M = fmaxf(Ma, fmaxf(fabsf(pb.x), fmaxf(fabsf(pb.y), fabsf(pb.z))));
       hit = r2 < H2;
-      if (fabsf(r2 - H2) <= kBand * (M * H + H2)) {   // near the support edge: decide in FP64
+      if (fabsf(r2 - H2) <= kBand * fmaf(Ma, H, H2)) {   // near the support edge: decide in FP64
         const double4 q = pos64[tw.U[loc]];
         const double r2d = pair_r2(wrap_sel<PER>(pa.x - q.x, box, half), wrap_sel<PER>(pa.y - q.y, box, half),
                                    wrap_sel<PER>(pa.z - q.z, box, half));
         const double Hd = pa.w + q.w;
         hit = r2d < Hd * Hd;
       }
-      W = kern_W<float, KER>(sqrt_fast(r2), rcp_fast(0.5f * H));
+      W = kern_W_unit<KER>(sqrt_hw(r2), rcp_fast(0.5f * H));   // zero for misses
     } else {
       const double dx = wrap_sel<PER>(pa.x - pb.x, box, half);
       const double dy = wrap_sel<PER>(pa.y - pb.y, box, half);
@@ -469,8 +505,9 @@ __global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* _
       const double H = pa.w + pb.w;
       hit = r2 < H * H;
       W = kern_W<R, KER>(sqrt_fast((R)r2), rcp_fast((R)(0.5 * H)));
+      W = hit ? W : (R)0;
     }
-    sum += hit ? W : (R)0;
+    sum += W;
     wr.put(loc, hit);
   };
   auto stage = [&](int c0) {
@@ -510,7 +547,10 @@ __global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* _
     if (sub == 0) xcount[a] = nexact < A.cap ? nexact : A.cap;
     if (nexact > A.cap || wr.n > A.cap_sl) latch_error(A.status, SPH_E_NGB_CAPACITY, (int)a);
   }
-  if (tw.valid && sub == 0) O.D[a] = particle_mass(A, a) * (double)sum;
+  if (tw.valid && sub == 0) {
+    const double W0 = wendland_self<double>(KER, pa.w);   // the particle's own term
+    O.D[a] = particle_mass(A, a) * (F32 ? fma(kern_W_const<KER>(), (double)sum, W0) : (double)sum + W0);
+  }
   }
 }
 
@@ -586,8 +626,11 @@ __global__ __launch_bounds__(64 * L) void k_stress(PassArgs A, const typename Re
       tw.advance();
       const R d[3] = {wrap_sel<PER>(pa.x - pb.x, box, half), wrap_sel<PER>(pa.y - pb.y, box, half),
                       wrap_sel<PER>(pa.z - pb.z, box, half)};
-      const R r = sqrt_fast(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-      const R F = kern_F<R, KER>(r, rcp_fast(Rec<R>::HS * (pa.w + pb.w)));
+      const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+      const R ih = rcp_fast(Rec<R>::HS * (pa.w + pb.w));
+      R F;   // FP32: without the kernel's constant, applied below
+      if constexpr (std::is_same<R, float>::value) F = kern_F_unit<KER>(sqrt_hw(r2), ih);
+      else F = kern_F<R, KER>(sqrt_fast(r2), ih);
       const R g[3] = {F * d[0], F * d[1], F * d[2]};
       const R v[3] = {vb.x - va.x, vb.y - va.y, vb.z - va.z};
 #pragma unroll
@@ -601,7 +644,7 @@ __global__ __launch_bounds__(64 * L) void k_stress(PassArgs A, const typename Re
 #pragma unroll
     for (int jj = 0; jj < 3; ++jj) G[i][jj] = lane_group_sum<L>(G[i][jj]);
   if (!stressed || sub != 0) continue;
-  const double m = particle_mass(A, a);
+  const double m = particle_mass(A, a) * (std::is_same<R, float>::value ? kern_F_const<KER>() : 1.0);
   const double D = -(double)faa.y * (2.0 * (double)Rec<R>::HS);  // stressed particles store -D (FP32: -D/2)
   const double iD2 = m / (2.0 * D);
   double ed[3][3], Rd[3][3];
@@ -700,9 +743,10 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
     const R d[3] = {wrap_sel<PER>(pa.x - pb.x, box, half), wrap_sel<PER>(pa.y - pb.y, box, half),
                     wrap_sel<PER>(pa.z - pb.z, box, half)};
     const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-    const R r = sqrt_fast(r2);
     const R hab = Rec<R>::HS * (pa.w + pb.w);
-    const R F = kern_F<R, KER>(r, rcp_fast(hab));   // grad_a W = F d
+    R F;   // grad_a W = F d (FP32: without the kernel's constant, applied to the sums)
+    if constexpr (std::is_same<R, float>::value) F = kern_F_unit<KER>(sqrt_hw(r2), rcp_fast(hab));
+    else F = kern_F<R, KER>(sqrt_fast(r2), rcp_fast(hab));
     const R v[3] = {va.x - vb.x, va.y - vb.y, va.z - vb.z};
     const R vr = v[0] * d[0] + v[1] * d[1] + v[2] * d[2];
     const bool b_st = fab.y < 0;
@@ -766,7 +810,7 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
   }
   ud = lane_group_sum<L>(ud);
   if (!tw.valid || sub != 0) continue;
-  const double m = particle_mass(A, a);
+  const double m = particle_mass(A, a) * (std::is_same<R, float>::value ? kern_F_const<KER>() : 1.0);
   double APd[3] = {m * (double)AP[0], m * (double)AP[1], m * (double)AP[2]};
   double ASd[3] = {m * (double)AS[0], m * (double)AS[1], m * (double)AS[2]};
   double acc[3];
