@@ -99,7 +99,7 @@ void sph_destroy(sph_ctx* c) {
                   c->sort.hist, c->sort.rowtot, c->sort.partial, c->sort.scan_bsum, c->tile_u, c->tile_start, c->tile_cnt, c->tile_uoff,
                   c->tile_usize, c->stress_tiles, c->nbr16, c->nbr_count, c->nbr_count_sl, c->nbr16s, c->nbr_count_s, c->pos_build, c->drift_flag,
                   c->pos4, c->fv, c->fa, c->sig, c->pos4f, c->fvf,
-                  c->faf, c->sigf, c->mu, c->Y0, c->B, c->sdot, c->half, c->tmp, c->stars, c->status};
+                  c->faf, c->sigf, c->mu, c->Y0, c->B, c->sdot, c->tovf, c->half, c->tmp, c->stars, c->status};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (c->drift_host) (void)hipHostFree(c->drift_host);
@@ -161,6 +161,7 @@ sph_status sph_create(const sph_params* params, void* stream, int64_t capacity, 
       (e = dalloc(&c->sig, 6 * cap)) || (e = dalloc(&c->pos4f, cap)) || (e = dalloc(&c->fvf, cap)) ||
       (e = dalloc(&c->faf, cap)) || (e = dalloc(&c->sigf, 6 * cap)) || (e = dalloc(&c->mu, cap)) ||
       (e = dalloc(&c->Y0, cap)) || (e = dalloc(&c->B, cap)) || (e = dalloc(&c->sdot, cap)) ||
+      (e = dalloc(&c->tovf, cap)) ||
       (e = dalloc(&c->half, 10 * cap)) || (e = dalloc(&c->tmp, capw)) || (e = dalloc(&c->status, 1))) {
     sph_destroy(c);
     return e;

@@ -354,6 +354,7 @@ struct sph_ctx {
   float* sigf;
   // internal per-particle fields
   double *mu, *Y0, *B, *sdot;
+  double4* tovf;        // per particle: fixed-background force coefficients (k_P, B_x, B_y, B_z)
   // half-step copies for kick-drift-kick
   double* half;         // 10*cap: vx, vy, vz, u, S[6]
   double* tmp;          // permutation staging, 8 bytes * cap

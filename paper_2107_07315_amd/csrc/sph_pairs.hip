@@ -303,6 +303,7 @@ __device__ __forceinline__ int eos_mlp(const MlpView& M, const sph_params& p, do
 // ---- density --------------------------------------------------------------------------------
 struct DensOut {
   double *D, *rho, *P, *cs, *mu, *Y0, *B;
+  double4* tov;     // fixed-background force coefficients (TOV background only)
   double4* fv;
   double2* fa;
   double* sig;
@@ -365,15 +366,19 @@ __device__ __forceinline__ void density_epilogue(const PassArgs& A, int64_t a, b
                                                  DensOut O) {
   const sph_params& p = A.p;
   const double va[3] = {vx[a], vy[a], vz[a]};
+  const bool tov = p.background == SPH_TOV;
   double rho = D, hfac = 1.0;
-  if (p.background == SPH_TOV) {
+  Metric g{};
+  double v2 = 0.0, psi2 = 1.0, psi4 = 1.0, WL = 1.0;
+  if (tov) {
     double cx, cy, cz;
     star_centre(A, a, cx, cy, cz);
     const double4 p64 = pos64[a];   // the background is always evaluated in FP64
-    Metric g = metric_at(p, p64.x - cx, p64.y - cy, p64.z - cz);
-    double v2 = va[0] * va[0] + va[1] * va[1] + va[2] * va[2];
-    double psi2 = g.psi * g.psi, psi4 = psi2 * psi2;
-    double WL = 1.0 / sqrt(1.0 - psi4 * v2 / (g.alpha * g.alpha));
+    g = metric_at(p, p64.x - cx, p64.y - cy, p64.z - cz);
+    v2 = va[0] * va[0] + va[1] * va[1] + va[2] * va[2];
+    psi2 = g.psi * g.psi;
+    psi4 = psi2 * psi2;
+    WL = 1.0 / sqrt(1.0 - psi4 * v2 / (g.alpha * g.alpha));
     rho = D / (psi4 * psi2 * WL);
   }
   double P, cs2;
@@ -382,7 +387,23 @@ __device__ __forceinline__ void density_epilogue(const PassArgs& A, int64_t a, b
   else e = eos_eval(p, rho, u[a], P, cs2);
   if (!valid) return;
   if (e) latch_error(A.status, e, (int)a);
-  if (p.background == SPH_TOV) hfac = 1.0 + u[a] + P / rho;
+  if (tov) {
+    hfac = 1.0 + u[a] + P / rho;
+    // coefficients of the trajectory equation (zero shift, gamma_ij = psi^4 delta_ij) for the
+    // force pass, acc = -k_P m A^P + B + m A^S with A^P, A^S its pair sums: the pressure
+    // coefficient k_P = alpha^2 psi^6 / (W_L h psi^4) (1/(W_L rho h) per unit D, so that a TOV
+    // star is static with grad P ~= D A^P) and
+    // B_i = -(alpha dalpha n_i + 4 psi^3 dpsi ((n.v) v_i - v^2 n_i / 2)) / psi^4 + 2 (dalpha / alpha) (n.v) v_i
+    const double ipsi4 = 1.0 / psi4;
+    const double kP = g.alpha * g.alpha * psi2 / (WL * hfac);
+    const double nv = g.n[0] * va[0] + g.n[1] * va[1] + g.n[2] * va[2];
+    const double c0 = 2.0 * g.dalpha / g.alpha * nv;
+    const double cg = 4.0 * psi2 * g.psi * g.dpsi;
+    double Bv[3];
+    for (int i = 0; i < 3; ++i)
+      Bv[i] = -(g.alpha * g.dalpha * g.n[i] + cg * (nv * va[i] - 0.5 * v2 * g.n[i])) * ipsi4 + c0 * va[i];
+    O.tov[a] = make_double4(kP, Bv[0], Bv[1], Bv[2]);
+  }
   const double cs = sqrt(cs2);
   const double Bm = rho * hfac * cs2;
   const bool solid = type[a] == 1 && !(broken[a] && p.break_mode == SPH_BREAK_FLUIDIZE);
@@ -698,10 +719,8 @@ template <typename R, int KER, bool PER, int L>
 __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Rec<R>::P4* __restrict__ pos,
                                                    const typename Rec<R>::V4* __restrict__ fv,
                                                    const typename Rec<R>::A2* __restrict__ fa,
-                                                   const R* __restrict__ sig, const double4* __restrict__ pos64,
-                                                   const double* __restrict__ u, const double* __restrict__ P,
-                                                   const double* __restrict__ rho, const double* __restrict__ sdot,
-                                                   ForceOut O) {
+                                                   const R* __restrict__ sig, const double4* __restrict__ tov,
+                                                   const double* __restrict__ sdot, ForceOut O) {
   using P4 = typename Rec<R>::P4;
   using V4 = typename Rec<R>::V4;
   using A2 = typename Rec<R>::A2;
@@ -815,27 +834,11 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
   double ASd[3] = {m * (double)AS[0], m * (double)AS[1], m * (double)AS[2]};
   double acc[3];
   if (p.background == SPH_TOV) {
-    // trajectory equation, zero shift, gamma_ij = psi^4 delta_ij; pressure coefficient
-    // 1/(W~^2 rho h) so that a TOV star is static; grad P ~= D A^P
-    double cx, cy, cz;
-    star_centre(A, a, cx, cy, cz);
-    const double4 p64 = pos64[a];
-    Metric g = metric_at(p, p64.x - cx, p64.y - cy, p64.z - cz);
-    const double vv[3] = {(double)va.x, (double)va.y, (double)va.z};
-    const double psi2 = g.psi * g.psi, psi4 = psi2 * psi2, psi6 = psi4 * psi2;
-    const double v2 = vv[0] * vv[0] + vv[1] * vv[1] + vv[2] * vv[2];
-    const double WL = 1.0 / sqrt(1.0 - psi4 * v2 / (g.alpha * g.alpha));
-    const double hen = 1.0 + u[a] + P[a] / rho[a];
-    const double fP = g.alpha * g.alpha * psi6 / (WL * hen);
-    const double nv = g.n[0] * vv[0] + g.n[1] * vv[1] + g.n[2] * vv[2];
-    const double c0 = 2.0 * g.dalpha / g.alpha * nv;
-    const double cg = 4.0 * psi2 * g.psi * g.dpsi;
-    const double ipsi4 = 1.0 / psi4;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      double Gi = g.alpha * g.dalpha * g.n[i] + cg * (nv * vv[i] - 0.5 * v2 * g.n[i]);
-      acc[i] = -(fP * APd[i] + Gi) * ipsi4 + c0 * vv[i] + ASd[i];
-    }
+    // trajectory equation with the coefficients of the density-stage epilogue
+    const double4 tc = tov[a];
+    acc[0] = -tc.x * APd[0] + tc.y + ASd[0];
+    acc[1] = -tc.x * APd[1] + tc.z + ASd[1];
+    acc[2] = -tc.x * APd[2] + tc.w + ASd[2];
   } else {
 #pragma unroll
     for (int i = 0; i < 3; ++i) acc[i] = -APd[i] + ASd[i];   // eq. solid2
@@ -912,7 +915,7 @@ static void dispatch_lanes(int lanes, Fn&& f) {
 
 sph_status launch_density(sph_ctx* c, sph_state* st) {
   PassArgs A = make_args(c, st);
-  DensOut O{st->D, st->rho, st->P, st->cs, c->mu, c->Y0, c->B, c->fv, c->fa, c->sig, c->fvf, c->faf, c->sigf};
+  DensOut O{st->D, st->rho, st->P, st->cs, c->mu, c->Y0, c->B, c->tovf, c->fv, c->fa, c->sig, c->fvf, c->faf, c->sigf};
   const dim3 g = pass_grid(c);
   const bool f32 = c->p.precision == SPH_FP32;
   dispatch_cfg(c->p.kernel, c->p.periodic, [&](auto K, auto P) {
@@ -935,7 +938,7 @@ sph_status launch_density(sph_ctx* c, sph_state* st) {
 
 sph_status launch_eos(sph_ctx* c, sph_state* st) {
   PassArgs A = make_args(c, st);
-  DensOut O{st->D, st->rho, st->P, st->cs, c->mu, c->Y0, c->B, c->fv, c->fa, c->sig, c->fvf, c->faf, c->sigf};
+  DensOut O{st->D, st->rho, st->P, st->cs, c->mu, c->Y0, c->B, c->tovf, c->fv, c->fa, c->sig, c->fvf, c->faf, c->sigf};
   const bool f32 = c->p.precision == SPH_FP32;
   // the network path only where some table cell is trusted; with none, every particle takes the
   // table (the same values), so the table kernel runs
@@ -987,10 +990,10 @@ sph_status launch_forces(sph_ctx* c, sph_state* st) {
       const dim3 b(64 * L);
       if (c->p.precision == SPH_FP32)
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forces<float, KER, PER, L>), g, b, 0, c->stream, A, c->pos4f, c->fvf,
-                           c->faf, c->sigf, c->pos4, st->u, st->P, st->rho, c->sdot, O);
+                           c->faf, c->sigf, c->tovf, c->sdot, O);
       else
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forces<double, KER, PER, L>), g, b, 0, c->stream, A, c->pos4, c->fv,
-                           c->fa, c->sig, c->pos4, st->u, st->P, st->rho, c->sdot, O);
+                           c->fa, c->sig, c->tovf, c->sdot, O);
     });
   });
   HIP_TRY(hipGetLastError());
