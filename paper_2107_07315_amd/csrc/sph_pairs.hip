@@ -232,6 +232,30 @@ __device__ __forceinline__ bool cancelled(const PassArgs& A) {
   return f != 0u && f <= A.seq;
 }
 // work-item counts of the passes (zero for a cancelled evaluation)
+// Stages union members [c0, c0 + CH) of a tile into LDS with NT threads: each thread loads the
+// indices of its (at most ceil(CH / NT)) members first and then all their records, so staging
+// waits for two memory latencies instead of two per member.  load(b) returns the records of
+// particle b, put(j, r) stores them to LDS slot j.
+template <int NT, int CH, typename Load, typename Put>
+__device__ __forceinline__ void stage_union(const int32_t* __restrict__ U, int c0, int usize, Load&& load,
+                                            Put&& put) {
+  constexpr int NJ = (CH + NT - 1) / NT;
+  using Recs = decltype(load(0));
+  int32_t b[NJ];
+#pragma unroll
+  for (int k = 0; k < NJ; ++k) {
+    const int j = (int)threadIdx.x + k * NT;
+    b[k] = (j < CH && c0 + j < usize) ? U[c0 + j] : -1;
+  }
+  Recs r[NJ];
+#pragma unroll
+  for (int k = 0; k < NJ; ++k)
+    if (b[k] >= 0) r[k] = load(b[k]);
+#pragma unroll
+  for (int k = 0; k < NJ; ++k)
+    if (b[k] >= 0) put((int)threadIdx.x + k * NT, r[k]);
+}
+
 __device__ __forceinline__ int64_t num_tiles(const PassArgs& A) {
   const int64_t nt = (int64_t)A.grid->ntiles;
   return cancelled(A) ? 0 : nt;
@@ -532,14 +556,13 @@ __global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* _
     wr.put(loc, hit);
   };
   auto stage = [&](int c0) {
-    for (int j = threadIdx.x; j < CH && c0 + j < tw.usize; j += 64 * L) {
-      const double4 q = pos64[tw.U[c0 + j]];
+    stage_union<64 * L, CH>(tw.U, c0, tw.usize, [&](int32_t b) { return pos64[b]; }, [&](int j, const double4& q) {
       if constexpr (F32)
         sp[j] = make_float4((float)wrap_sel<PER>(q.x - ref.x, box, half), (float)wrap_sel<PER>(q.y - ref.y, box, half),
                             (float)wrap_sel<PER>(q.z - ref.z, box, half), (float)q.w);
       else
         sp[j] = q;
-    }
+    });
   };
   if (tw.usize <= CH) {   // whole union in one chunk: group walk
     __syncthreads();
@@ -634,11 +657,9 @@ __global__ __launch_bounds__(64 * L) void k_stress(PassArgs A, const typename Re
   R G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   for (int c0 = 0; c0 < tw.usize; c0 += CH) {
     __syncthreads();
-    for (int j = threadIdx.x; j < CH && c0 + j < tw.usize; j += 64 * L) {
-      const int32_t b = tw.U[c0 + j];
-      sp[j] = pos[b];
-      sv[j] = fv[b];
-    }
+    struct Recs { P4 p; V4 v; };
+    stage_union<64 * L, CH>(tw.U, c0, tw.usize, [&](int32_t b) { return Recs{pos[b], fv[b]}; },
+                            [&](int j, const Recs& r) { sp[j] = r.p; sv[j] = r.v; });
     __syncthreads();
     const int cend = c0 + CH;
     while (tw.next < cend) {
@@ -793,13 +814,10 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
       AS[2] += s6[4] * g[0] + s6[5] * g[1] + s6[2] * g[2];
     }
   };
+  struct Recs { P4 p; V4 v; A2 f; };
   auto stage = [&](int c0) {
-    for (int j = threadIdx.x; j < CH && c0 + j < tw.usize; j += 64 * L) {
-      const int32_t b = tw.U[c0 + j];
-      sp[j] = pos[b];
-      sv[j] = fv[b];
-      sa2[j] = fa[b];
-    }
+    stage_union<64 * L, CH>(tw.U, c0, tw.usize, [&](int32_t b) { return Recs{pos[b], fv[b], fa[b]}; },
+                            [&](int j, const Recs& r) { sp[j] = r.p; sv[j] = r.v; sa2[j] = r.f; });
   };
   // FP32 with the whole union in one chunk (the usual case): group walk.  (In FP64 the 8 inlined
   // copies of the longer pair body run slower than the shifting walk, measured.)
