@@ -772,31 +772,43 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
               pbu[u] = B.pos_sorted[sp];
             }
           }
+          // pre-test of the 4 rounds: each sub-box (particle) is read from LDS once for all 4
+          bool pass[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) pass[u] = false;
+          if (small) {
+            for (int k = 0; k < tcnt; ++k) {
+              const double4 q = tp[k];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const double4 pb = pbu[u];
+                pass[u] |= candidate_test(min_image(q.x - pb.x, (int)PER, box), min_image(q.y - pb.y, (int)PER, box),
+                                          min_image(q.z - pb.z, (int)PER, box), q.w, pb.w, s1);
+              }
+            }
+          } else {
+#pragma unroll 1
+            for (int gi = 0; gi < 8; ++gi) {
+              const double cx = sub[gi][0], cy = sub[gi][1], cz = sub[gi][2];
+              const double wx = sub[gi][3], wy = sub[gi][4], wz = sub[gi][5], hg = sub[gi][6];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const double4 pb = pbu[u];
+                const double ex = fmax(0.0, fabs(min_image(pb.x - cx, (int)PER, box)) - wx);
+                const double ey = fmax(0.0, fabs(min_image(pb.y - cy, (int)PER, box)) - wy);
+                const double ez = fmax(0.0, fabs(min_image(pb.z - cz, (int)PER, box)) - wz);
+                const double Rb = (hg + pb.w) * s1 * (1.0 + 1e-9);
+                pass[u] |= ex * ex + ey * ey + ez * ez < Rb * Rb && hg > 0.0;
+              }
+            }
+          }
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             if (q0 + 64 * u >= Tc) break;
             const double4 pb = pbu[u];
-            bool pass = false;
-            if (bu[u] >= 0) {
-              if (small) {
-                for (int k = 0; k < tcnt; ++k) {
-                  const double4 q = tp[k];
-                  pass = pass || candidate_test(min_image(q.x - pb.x, (int)PER, box), min_image(q.y - pb.y, (int)PER, box),
-                                                min_image(q.z - pb.z, (int)PER, box), q.w, pb.w, s1);
-                }
-              } else {
-#pragma unroll 1
-                for (int gi = 0; gi < 8; ++gi) {
-                  const double ex = fmax(0.0, fabs(min_image(pb.x - sub[gi][0], (int)PER, box)) - sub[gi][3]);
-                  const double ey = fmax(0.0, fabs(min_image(pb.y - sub[gi][1], (int)PER, box)) - sub[gi][4]);
-                  const double ez = fmax(0.0, fabs(min_image(pb.z - sub[gi][2], (int)PER, box)) - sub[gi][5]);
-                  const double Rb = (sub[gi][6] + pb.w) * s1 * (1.0 + 1e-9);
-                  pass = pass || (ex * ex + ey * ey + ez * ez < Rb * Rb && sub[gi][6] > 0.0);
-                }
-              }
-            }
-            const unsigned long long m = __ballot(pass);
-            if (pass) {
+            pass[u] = pass[u] && bu[u] >= 0;
+            const unsigned long long m = __ballot(pass[u]);
+            if (pass[u]) {
               const int k = pend + __popcll(m & lt);
               cb[k] = make_double4(pb.x, pb.y, pb.z, pb.w * s1w);
               cbi[k] = bu[u];
