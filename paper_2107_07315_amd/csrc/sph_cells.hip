@@ -476,12 +476,11 @@ __device__ __forceinline__ void run_batch(const BuildArgs& B, TileState& T, cons
   const int lane = threadIdx.x;
   unsigned long long um = 0ull;   // the batch's union members (wave-uniform)
   int nm = 0;
-  auto test = [&](int j) -> bool {
-    const double4 pb = cb[j];
+  auto test = [&](const double4& pb, int32_t bj) -> bool {
     const double dx = min_image(T.xa - pb.x, (int)PER, box), dy = min_image(T.ya - pb.y, (int)PER, box),
                  dz = min_image(T.za - pb.z, (int)PER, box);
     const double H = T.hs + pb.w;
-    return T.valid & (cbi[j] != T.a) & (fma(dz, dz, fma(dy, dy, dx * dx)) < H * H);
+    return T.valid & (bj != T.a) & (fma(dz, dz, fma(dy, dy, dx * dx)) < H * H);
   };
   auto take = [&](int j, bool hit) {
     if (__ballot(hit)) {
@@ -493,13 +492,24 @@ __device__ __forceinline__ void run_batch(const BuildArgs& B, TileState& T, cons
     }
   };
   if constexpr (NB > 0) {
+    // the next candidate's record is read from LDS while this one is tested and appended
+    double4 nx = cb[0];
+    int32_t nbi = cbi[0];
 #pragma unroll 1
     for (int jb = 0; jb < NB; jb += 8) {
 #pragma unroll
-      for (int k = 0; k < 8; ++k) take(jb + k, test(jb + k));
+      for (int k = 0; k < 8; ++k) {
+        const double4 pb = nx;
+        const int32_t bj = nbi;
+        if (jb + k + 1 < NB) {
+          nx = cb[jb + k + 1];
+          nbi = cbi[jb + k + 1];
+        }
+        take(jb + k, test(pb, bj));
+      }
     }
   } else {
-    for (int j = 0; j < nb; ++j) take(j, test(j));
+    for (int j = 0; j < nb; ++j) take(j, test(cb[j], cbi[j]));
   }
   if (!um) return;
   const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
