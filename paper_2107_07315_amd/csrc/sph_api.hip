@@ -208,9 +208,10 @@ static sph_status read_drift(sph_ctx* c, bool* violated) {
   return SPH_OK;
 }
 
-static sph_status rebuild(sph_ctx* c, sph_state* st) {
+// outputs_recomputed: an evaluation follows at once, so the output arrays need not be reordered
+static sph_status rebuild(sph_ctx* c, sph_state* st, bool outputs_recomputed = false) {
   timer_begin(c, TIMER_CELLS);
-  sph_status e = sph_rebin(c, st);
+  sph_status e = sph_rebin(c, st, outputs_recomputed);
   timer_end(c, TIMER_CELLS);
   if (e) {
     c->lists_valid = false;
@@ -349,7 +350,7 @@ static sph_status step_graphs(sph_ctx* c, sph_state* st, double dt, int32_t nste
     HIP_TRY(hipGraphLaunch(k == 0 ? c->g_drift : c->g_chain, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     if (*c->drift_host != 0u) {
-      if ((e = rebuild(c, st))) return e;
+      if ((e = rebuild(c, st, true))) return e;
       if (c->g_epoch != c->graph_epoch && (e = capture_step(c, st, dt))) return e;
     }
     HIP_TRY(hipGraphLaunch(c->g_eval, c->stream));
@@ -418,7 +419,7 @@ sph_status sph_step(sph_ctx* c, sph_state* st, double dt, int32_t nsteps) {
   int32_t k = 0;
   while (k < nsteps) {
     if (!(c->lists_valid && c->p.skin > 0.0)) {   // no lists to test: build them for this step
-      if ((e = queue_kick(c, st, dt, k, 0u)) || (e = rebuild(c, st)) || (e = queue_evaluation(c, st, 0u))) return e;
+      if ((e = queue_kick(c, st, dt, k, 0u)) || (e = rebuild(c, st, true)) || (e = queue_evaluation(c, st, 0u))) return e;
       ++k;
       continue;
     }
@@ -441,7 +442,7 @@ sph_status sph_step(sph_ctx* c, sph_state* st, double dt, int32_t nsteps) {
       }
       // the drift of step v broke the skin bound; the steps queued after it did nothing
       const int32_t v = k0 + (int32_t)f - 1;
-      if ((e = rebuild(c, st)) || (e = queue_evaluation(c, st, 0u))) return e;
+      if ((e = rebuild(c, st, true)) || (e = queue_evaluation(c, st, 0u))) return e;
       k = v + 1;
       break;
     }

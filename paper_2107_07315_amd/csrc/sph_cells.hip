@@ -928,7 +928,7 @@ static void launch_build(const BuildArgs& B, bool per, dim3 grid, hipStream_t s)
 // along the global Morton curve, tiles are cut from that order, particles are binned into the
 // multi-level grid and each tile's candidates are collected; the positions and h of this build
 // are kept for the drift test.
-sph_status sph_rebin(sph_ctx* c, sph_state* st) {
+sph_status sph_rebin(sph_ctx* c, sph_state* st, bool outputs_recomputed) {
   const int64_t n = st->n;
   hipStream_t s = c->stream;
   const unsigned nb = grid_for(n, kB);
@@ -942,13 +942,17 @@ sph_status sph_rebin(sph_ctx* c, sph_state* st) {
   {
     hipLaunchKernelGGL(k_gkeys, dim3(nb), dim3(kB), 0, s, c->pos4, n, c->grid, c->keys, c->vals);
     if ((e = sph_sort_pairs(c, c->keys, c->vals, n))) return e;
-    double* d64[] = {st->x, st->y, st->z, st->vx, st->vy, st->vz, st->u, st->h, st->D, st->rho,
-                     st->P, st->cs, st->ax, st->ay, st->az, st->dudt};
+    double* d64[] = {st->x, st->y, st->z, st->vx, st->vy, st->vz, st->u, st->h};
     for (double* a : d64)
       if ((e = permute_array(c, a, n))) return e;
-    for (int k = 0; k < 6; ++k) {
+    for (int k = 0; k < 6; ++k)
       if ((e = permute_array(c, st->S + k * n, n))) return e;
-      if ((e = permute_array(c, st->dSdt + k * n, n))) return e;
+    if (!outputs_recomputed) {
+      double* out64[] = {st->D, st->rho, st->P, st->cs, st->ax, st->ay, st->az, st->dudt};
+      for (double* a : out64)
+        if ((e = permute_array(c, a, n))) return e;
+      for (int k = 0; k < 6; ++k)
+        if ((e = permute_array(c, st->dSdt + k * n, n))) return e;
     }
     for (int k = 0; k < 10; ++k)
       if ((e = permute_array(c, c->half + (int64_t)k * c->capacity, n))) return e;

@@ -345,11 +345,11 @@ struct sph_ctx {
   int32_t ucap;
   // packed gather records (FP64 and FP32 variants)
   double4* pos4;        // x, y, z, h
-  double4* fv;          // vx, vy, vz, cs
+  double4* fv;          // vx, vy, vz, alpha cs (alpha: viscosity coefficient)
   double2* fa;          // P/D^2, D (negative D marks a particle that carries deviatoric stress)
   double* sig;          // S/D^2, 6*cap
   float4* pos4f;        // x, y, z (relative to the star centre), h/2
-  float4* fvf;          // vx, vy, vz, cs/2
+  float4* fvf;          // vx, vy, vz, alpha cs/2
   float2* faf;          // P/D^2, D/2 (negative: carries deviatoric stress)
   float* sigf;
   // internal per-particle fields
@@ -373,7 +373,9 @@ struct sph_ctx {
 
 // ---- host launchers (one per kernel file) ------------------------------------------------------
 sph_status sph_sort_pairs(sph_ctx* c, uint32_t* keys, uint32_t* vals, int64_t n);
-sph_status sph_rebin(sph_ctx* c, sph_state* st);
+// outputs_recomputed: the outputs (D, rho, P, c_s, accelerations, du/dt, dS/dt) are recomputed
+// before they are next read, so they are not reordered
+sph_status sph_rebin(sph_ctx* c, sph_state* st, bool outputs_recomputed);
 sph_status launch_drift_check(sph_ctx* c, sph_state* st);
 sph_status launch_flag_clear(sph_ctx* c);
 sph_status launch_density(sph_ctx* c, sph_state* st);   // pair loop

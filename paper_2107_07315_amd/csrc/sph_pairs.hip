@@ -95,9 +95,10 @@ __device__ __forceinline__ float kern_F_unit(float r, float ih) {
 __device__ __forceinline__ float sqrt_hw(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 template <typename R> struct Rec;
-// Record scale: the FP64 records hold h, c_s and D; the FP32 ones hold h/2, c_s/2 and D/2 (exact
-// halvings), so the pair means 0.5 (h_a + h_b), 0.5 (c_a + c_b), 0.5 (D_a + D_b) are HS times the
-// sum of the two record values and HS = 1 saves the multiply in FP32.
+// Record scale: the FP64 records hold h, alpha c_s and D; the FP32 ones hold h/2, alpha c_s/2 and
+// D/2 (exact halvings), so the pair means 0.5 (h_a + h_b), 0.5 alpha (c_a + c_b), 0.5 (D_a + D_b)
+// are HS times the sum of the two record values and HS = 1 saves the multiply in FP32 (alpha: the
+// viscosity coefficient, which multiplies the mean sound speed wherever it is used).
 template <> struct Rec<double> {
   static constexpr double HS = 0.5;
   using P4 = double4;
@@ -438,24 +439,25 @@ __device__ __forceinline__ void density_epilogue(const PassArgs& A, int64_t a, b
     mu = (p.mu_mode == SPH_MU_PFACTOR) ? fac * P : p.mu_const;
   }
   const double E = mu > 0.0 ? 9.0 * Bm * mu / (3.0 * Bm + mu) : 0.0;
-  O.D[a] = D;
-  O.rho[a] = rho;
+  O.rho[a] = rho;   // D stays as the pair loop wrote it
   O.P[a] = P;
   O.cs[a] = cs;
-  O.mu[a] = mu;
-  O.B[a] = Bm;
-  O.Y0[a] = (p.y0_mode == SPH_Y0_EFACTOR) ? p.y0_over_E * E : p.y0_const;
+  if (type[a] == 1) {   // the moduli and the yield stress are read for crust particles only
+    O.mu[a] = mu;
+    O.B[a] = Bm;
+    O.Y0[a] = (p.y0_mode == SPH_Y0_EFACTOR) ? p.y0_over_E * E : p.y0_const;
+  }
   const double iD2 = 1.0 / (D * D);
   const double pi = P * iD2;
   const bool stressed = solid;
   const int64_t n = A.n;
   if (sizeof(R) == 8) {
-    O.fv[a] = make_double4(va[0], va[1], va[2], cs);
+    O.fv[a] = make_double4(va[0], va[1], va[2], p.visc_alpha * cs);   // alpha c_s for the viscosity
     O.fa[a] = make_double2(pi, stressed ? -D : D);
     if (stressed)   // S/D^2 is read only for stressed particles (the sign of D in fa marks them)
       for (int c = 0; c < 6; ++c) O.sig[c * n + a] = S[c * n + a] * iD2;
   } else {
-    O.fvf[a] = make_float4((float)va[0], (float)va[1], (float)va[2], (float)(0.5 * cs));
+    O.fvf[a] = make_float4((float)va[0], (float)va[1], (float)va[2], (float)(0.5 * p.visc_alpha * cs));
     O.faf[a] = make_float2((float)pi, stressed ? -(float)(0.5 * D) : (float)(0.5 * D));
     if (stressed)
       for (int c = 0; c < 6; ++c) O.sigf[c * n + a] = (float)(S[c * n + a] * iD2);
@@ -790,14 +792,14 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
     const R v[3] = {va.x - vb.x, va.y - vb.y, va.z - vb.z};
     const R vr = v[0] * d[0] + v[1] * d[1] + v[2] * d[2];
     const bool b_st = fab.y < 0;
-    const R Db = b_st ? -fab.y : fab.y;
+    const R Db = fabs(fab.y);
     // Monaghan viscosity on approaching pairs: one reciprocal gives 1/X and 1/Dbar
     const R X = r2 + eps_v * hab * hab;
     const R Dbar = Rec<R>::HS * (Da + Db);
     const R inv = rcp_fast(X * Dbar);
     const R muab = hab * vr * (Dbar * inv);
-    const R cbar = Rec<R>::HS * (va.w + vb.w);
-    const R Pi = vr < (R)0 ? (-alpha_v * cbar * muab + beta_v * muab * muab) * (X * inv) : (R)0;
+    const R acbar = Rec<R>::HS * (va.w + vb.w);   // alpha c_bar (the records hold alpha c_s)
+    const R Pi = vr < (R)0 ? muab * fma(beta_v, muab, -acbar) * (X * inv) : (R)0;
     const R cPF = (pia + fab.x + Pi) * F;
     AP[0] += cPF * d[0];
     AP[1] += cPF * d[1];
