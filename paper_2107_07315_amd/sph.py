@@ -176,7 +176,7 @@ class Context:
     """Owns an sph_ctx and the device copies of the background and EoS tables."""
 
     # relative Verlet skin of the candidate lists (0: rebuild at every evaluation)
-    DEFAULT_SKIN = 0.1
+    DEFAULT_SKIN = 0.14
 
     def __init__(self, params, capacity: int, stream=None, max_neighbours=0, cell_div=0, tile_cut=0.0,
                  skin=None, pass_blocks=0, graph=False, lanes=0):
