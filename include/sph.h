@@ -203,7 +203,7 @@ sph_status sph_ensemble_set(sph_ctx* ctx, int32_t nstars, const double* star_inf
  * `steps_per_trial` steps (with the candidate-list rebuilds they need) on a copy of the state (the
  * caller's state is not changed), and keeps the setting with the least time per step; a setting
  * replaces the best only if it is more than 2% faster.  Use enough steps for several rebuilds
- * (64 at skin 0.1).  The context then needs a new evaluation (sph_build_cells ...) before
+ * (64 or more at the default skin).  The context then needs a new evaluation (sph_build_cells ...) before
  * sph_step.  Waits. */
 typedef struct {
   int32_t pass_blocks;

@@ -252,6 +252,36 @@ def test_skin_lists_match_rebuild_every_evaluation():
     assert runs[1e-3]["_stats"]["rebuilds"] >= 2
 
 
+def test_one_multi_step_call_equals_single_step_calls():
+    # inside one sph_step call the host queues each step before reading the previous step's skin
+    # test back and a step behind a failed test is cancelled on the device and re-run after the
+    # rebuild; the result must equal stepping one call at a time (where no step runs ahead), bit
+    # for bit, with the same list builds
+    from paper_2107_07315_amd import sph
+    w = W.star(20000, seed=5)
+    out = {}
+    for mode in ("one_call", "single_calls"):
+        ctx = sph.Context(w.params.replace(precision="FP32"), capacity=w.n, skin=0.01)
+        st = sph.DeviceState(w.arrays)
+        ctx.evaluate(st)
+        if mode == "one_call":
+            ctx.sph_step(st, w.dt, 16)
+        else:
+            for _ in range(16):
+                ctx.sph_step(st, w.dt, 1)
+        ctx.sph_sync()
+        g = st.numpy()
+        order = np.argsort(g["id"])
+        out[mode] = ({k: (v[..., order] if v.ndim == 2 else v[order]) for k, v in g.items()},
+                     ctx.sph_neighbour_stats()["rebuilds"])
+        ctx.close()
+    (a, ra), (b, rb) = out["one_call"], out["single_calls"]
+    _print(f"rebuilds {ra} (one call) {rb} (single calls)", {})
+    assert ra == rb and ra >= 3
+    for k in ("x", "y", "z", "vx", "vy", "vz", "u", "h", "S", "D", "ax", "dudt"):
+        assert np.array_equal(a[k], b[k]), k
+
+
 @pytest.mark.parametrize("lanes", [1, 2])
 def test_lanes_per_target(lanes):
     # 1 and 2 lanes per target (the default is 4): same exact neighbour sets, fields to the
