@@ -114,8 +114,8 @@ template <> struct Rec<float> {
   using P4 = float4;
   using V4 = float4;
   using A2 = float2;
-  static constexpr int CH_D = 256;   // density records: FP32 tile-relative (x, y, z, h), 4 KB
-  static constexpr int CHMAX_D = 1024;
+  static constexpr int CH_D = 384;   // density records: FP32 tile-relative (x, y, z, h), 6 KB
+  static constexpr int CHMAX_D = 1280;   // per workgroup: 20 KB, 4 workgroups per CU (measured best)
   static constexpr int CH_S = 256;
   static constexpr int CH_F = 256;
 };
