@@ -235,7 +235,7 @@ def main():
                     help="run one 1 GiB device-to-device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+        print(json.dumps({"error": "bench.py runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU sharding is a design note, not built)"}), flush=True)
         sys.exit(2)
 

@@ -129,7 +129,7 @@ class Oracle:
         if params.eos == "GAMMA_LAW":
             p.eos = 0
         elif params.eos in ("TABLE", "MLP"):
-            p.eos = 1   # the oracle judges every EoS mode against the table itself
+            p.eos = 1   # the oracle evaluates every EoS mode with the table itself
         p.gamma = params.gamma
         if params.table is not None:
             t = params.table

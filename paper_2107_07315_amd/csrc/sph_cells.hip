@@ -925,9 +925,9 @@ static void launch_build(const BuildArgs& B, bool per, dim3 grid, hipStream_t s)
 }
 
 // Candidate-list build: every particle array of the state (and the half-step copies) is reordered
-// along the global Morton curve, tiles are cut from that order, particles are binned into the
-// multi-level grid and each tile's candidates are collected; the positions and h of this build
-// are kept for the drift test.
+// along the global Morton curve (the outputs only when outputs_recomputed is false), tiles are cut
+// from that order, particles are binned into the multi-level grid and each tile's candidates are
+// collected; the positions and h at the list build are kept for the drift test.
 sph_status sph_rebin(sph_ctx* c, sph_state* st, bool outputs_recomputed) {
   const int64_t n = st->n;
   hipStream_t s = c->stream;
