@@ -360,11 +360,23 @@ static sph_status step_graphs(sph_ctx* c, sph_state* st, double dt, int32_t nste
 
 extern "C" {
 
-// kick of step k of a call: kick-drift for the first, else the previous final kick fused in
-static sph_status queue_kick(sph_ctx* c, sph_state* st, double dt, int32_t k, uint32_t check) {
+// The state's x, y, z, h brought up to date from pos4 after deferred kicks.
+static sph_status sync_positions(sph_ctx* c, sph_state* st) {
+  if (!c->pos_deferred) return SPH_OK;
+  c->pos_deferred = false;
+  return launch_unpack_pos(c, st);
+}
+
+// kick of step k of a call: kick-drift for the first, else the previous final kick fused in.
+// deferred: positions and h stay in pos4 (the state's copies are synced before a list build and
+// at the end of the call)
+static sph_status queue_kick(sph_ctx* c, sph_state* st, double dt, int32_t k, uint32_t check, bool deferred) {
+  sph_status e;
+  if (!deferred && (e = sync_positions(c, st))) return e;
   timer_begin(c, TIMER_KDK);
-  const sph_status e = k == 0 ? launch_kick_drift(c, st, dt, check) : launch_kick_final_drift(c, st, dt, check);
+  e = k == 0 ? launch_kick_drift(c, st, dt, check, deferred) : launch_kick_final_drift(c, st, dt, check, deferred);
   timer_end(c, TIMER_KDK);
+  if (!e && deferred) c->pos_deferred = true;
   return e;
 }
 
@@ -395,31 +407,21 @@ static sph_status queue_evaluation(sph_ctx* c, sph_state* st, uint32_t seq) {
   return e;
 }
 
-sph_status sph_step(sph_ctx* c, sph_state* st, double dt, int32_t nsteps) {
-  sph_status e = check_state(c, st);
-  if (e) return e;
-  if (!(dt > 0.0) || nsteps < 0) return SPH_E_ARG;
-  if (c->gen < 4 || st->n != c->n) return SPH_E_ORDER;
-  if (st->n == 0) return SPH_OK;
-  if (c->p.graph && !c->stream) return SPH_E_ARG;   // the legacy default stream cannot be captured
-  if (c->p.graph && c->p.skin > 0.0 && c->lists_valid) {
-    e = step_graphs(c, st, dt, nsteps);
-    if (!e) c->gen = 4;
-    return e;
-  }
-  // Steps are chained: the final kick of step k and the kick-drift of step k + 1 run as one
-  // kernel; the last step of the call ends with its own final kick.
-  // With valid lists and a positive skin the host queues step k + 1 before it reads the skin test
-  // of step k back, so the device never waits for the host.  Steps carry their number since the
-  // test word was cleared: a kick or evaluation behind a failed test finds a smaller number there
-  // and does nothing; the host then rebuilds the lists, evaluates the failed step again and
-  // carries on after it.
-  for (hipEvent_t& ev : c->step_ev)
-    if (!ev) HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+// Steps are chained: the final kick of step k and the kick-drift of step k + 1 run as one
+// kernel; the last step of the call ends with its own final kick.
+// With valid lists and a positive skin the host queues step k + 1 before it reads the skin test
+// of step k back, so the device never waits for the host.  Steps carry their number since the
+// test word was cleared: a kick or evaluation behind a failed test finds a smaller number there
+// and does nothing; the host then rebuilds the lists, evaluates the failed step again and
+// carries on after it.
+static sph_status step_loop(sph_ctx* c, sph_state* st, double dt, int32_t nsteps) {
+  sph_status e;
   int32_t k = 0;
   while (k < nsteps) {
     if (!(c->lists_valid && c->p.skin > 0.0)) {   // no lists to test: build them for this step
-      if ((e = queue_kick(c, st, dt, k, 0u)) || (e = rebuild(c, st, true)) || (e = queue_evaluation(c, st, 0u))) return e;
+      if ((e = queue_kick(c, st, dt, k, 0u, false)) || (e = rebuild(c, st, true)) ||
+          (e = queue_evaluation(c, st, 0u)))
+        return e;
       ++k;
       continue;
     }
@@ -429,7 +431,7 @@ sph_status sph_step(sph_ctx* c, sph_state* st, double dt, int32_t nsteps) {
     while (k < nsteps) {
       while (queued < nsteps && queued <= k + 1) {
         const uint32_t q = (uint32_t)(queued - k0 + 1);
-        if ((e = queue_kick(c, st, dt, queued, q)) || (e = queue_evaluation(c, st, q))) return e;
+        if ((e = queue_kick(c, st, dt, queued, q, true)) || (e = queue_evaluation(c, st, q))) return e;
         HIP_TRY(hipMemcpyAsync(c->drift_host, c->drift_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(hipEventRecord(c->step_ev[queued & 1], c->stream));
         ++queued;
@@ -442,11 +444,32 @@ sph_status sph_step(sph_ctx* c, sph_state* st, double dt, int32_t nsteps) {
       }
       // the drift of step v broke the skin bound; the steps queued after it did nothing
       const int32_t v = k0 + (int32_t)f - 1;
-      if ((e = rebuild(c, st, true)) || (e = queue_evaluation(c, st, 0u))) return e;
+      if ((e = sync_positions(c, st)) || (e = rebuild(c, st, true)) || (e = queue_evaluation(c, st, 0u))) return e;
       k = v + 1;
       break;
     }
   }
+  return SPH_OK;
+}
+
+sph_status sph_step(sph_ctx* c, sph_state* st, double dt, int32_t nsteps) {
+  sph_status e = check_state(c, st);
+  if (e) return e;
+  if (!(dt > 0.0) || nsteps < 0) return SPH_E_ARG;
+  if (c->gen < 4 || st->n != c->n) return SPH_E_ORDER;
+  if (st->n == 0) return SPH_OK;
+  if (c->p.graph && !c->stream) return SPH_E_ARG;   // the legacy default stream cannot be captured
+  if (c->p.graph && c->p.skin > 0.0 && c->lists_valid) {
+    e = step_graphs(c, st, dt, nsteps);
+    if (!e) c->gen = 4;
+    return e;
+  }
+  for (hipEvent_t& ev : c->step_ev)
+    if (!ev) HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  e = step_loop(c, st, dt, nsteps);
+  const sph_status es = sync_positions(c, st);   // also after an error: the state stays whole
+  if (e) return e;
+  if (es) return es;
   if (nsteps > 0) {
     timer_begin(c, TIMER_KDK);
     if ((e = launch_kick_final(c, st, dt))) return e;
@@ -455,6 +478,7 @@ sph_status sph_step(sph_ctx* c, sph_state* st, double dt, int32_t nsteps) {
   c->gen = 4;
   return SPH_OK;
 }
+
 
 }  // extern "C"
 

@@ -29,6 +29,9 @@ struct KdkArgs {
   // was cleared; a step finds a smaller non-zero value there when an earlier step (run ahead of
   // the host's test) broke the bound, and then leaves the state alone.  flag == nullptr: no test
   uint32_t check_id; uint32_t* flag;
+  // positions and h read from and written to pos4 only (inside a multi-step call the public
+  // x, y, z, h are brought up to date once, before a list build and at the end of the call)
+  bool deferred;
 };
 
 // a kick of a step that runs ahead of a failed skin test does nothing
@@ -50,8 +53,8 @@ __device__ __forceinline__ double wrap(double q, int periodic, double box) {
 // stores the half-step copies, x, the predicted v, u and (yielded) S, the packed position records,
 // and runs the skin test.  Type-0 particles carry no deviatoric stress (S and its rate are zero,
 // set at every list build), so their stress arrays are neither read nor written.
-__device__ __forceinline__ void kick_drift_from(const KdkArgs& K, int64_t a, const double v0[3], double u0,
-                                                const double S0[6], double h, bool solid) {
+__device__ __forceinline__ void kick_drift_from(const KdkArgs& K, int64_t a, const double x0[3], const double v0[3],
+                                                double u0, const double S0[6], double h, bool solid) {
   const double hdt = 0.5 * K.dt;
   const int64_t n = K.n, hs = K.hstride;
   double* H = K.half;
@@ -70,12 +73,14 @@ __device__ __forceinline__ void kick_drift_from(const KdkArgs& K, int64_t a, con
   H[1 * hs + a] = vh[1];
   H[2 * hs + a] = vh[2];
   H[3 * hs + a] = uh;
-  const double xn = wrap(K.x[a] + K.dt * vh[0], K.p.periodic, K.p.box);
-  const double yn = wrap(K.y[a] + K.dt * vh[1], K.p.periodic, K.p.box);
-  const double zn = wrap(K.z[a] + K.dt * vh[2], K.p.periodic, K.p.box);
-  K.x[a] = xn;
-  K.y[a] = yn;
-  K.z[a] = zn;
+  const double xn = wrap(x0[0] + K.dt * vh[0], K.p.periodic, K.p.box);
+  const double yn = wrap(x0[1] + K.dt * vh[1], K.p.periodic, K.p.box);
+  const double zn = wrap(x0[2] + K.dt * vh[2], K.p.periodic, K.p.box);
+  if (!K.deferred) {
+    K.x[a] = xn;
+    K.y[a] = yn;
+    K.z[a] = zn;
+  }
   K.pos4[a] = make_double4(xn, yn, zn, h);
   if (K.pos4f) {
     double cx = 0.0, cy = 0.0, cz = 0.0;
@@ -131,10 +136,11 @@ __device__ __forceinline__ void final_kick_of(const KdkArgs& K, int64_t a, doubl
       }
     }
   }
-  h = K.h[a];
   if (K.p.h_mode == SPH_H_ADAPTIVE) {
     double m = (K.star && K.stars) ? K.stars[K.star[a]].m : K.p.m;
     h = K.p.eta * cbrt(m / K.D[a]);
+  } else {
+    h = K.h[a];   // constant h: the state's value is always current
   }
 }
 
@@ -145,11 +151,12 @@ __global__ __launch_bounds__(kB) void k_kick_drift(KdkArgs K) {
   if (a >= K.n || kick_cancelled(K)) return;
   const int64_t n = K.n;
   const bool solid = K.type[a] == 1;
+  const double x0[3] = {K.x[a], K.y[a], K.z[a]};
   const double v0[3] = {K.vx[a], K.vy[a], K.vz[a]};
   double S0[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (solid)
     for (int c = 0; c < 6; ++c) S0[c] = K.S[c * n + a];
-  kick_drift_from(K, a, v0, K.u[a], S0, K.h[a], solid);
+  kick_drift_from(K, a, x0, v0, K.u[a], S0, K.h[a], solid);
 }
 
 // second half kick: end-of-step state
@@ -175,10 +182,17 @@ __global__ __launch_bounds__(kB) void k_kick_final_drift(KdkArgs K) {
   const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= K.n || kick_cancelled(K)) return;
   const bool solid = K.type[a] == 1;
+  double x0[3];
+  if (K.deferred) {
+    const double4 q = K.pos4[a];
+    x0[0] = q.x; x0[1] = q.y; x0[2] = q.z;
+  } else {
+    x0[0] = K.x[a]; x0[1] = K.y[a]; x0[2] = K.z[a];
+  }
   double v[3], u, s[6], h;
   final_kick_of(K, a, v, u, s, h, solid);
-  K.h[a] = h;
-  kick_drift_from(K, a, v, u, s, h, solid);
+  if (!K.deferred) K.h[a] = h;
+  kick_drift_from(K, a, x0, v, u, s, h, solid);
 }
 
 KdkArgs make_kdk(sph_ctx* c, sph_state* st, double dt) {
@@ -204,7 +218,21 @@ KdkArgs make_kdk(sph_ctx* c, sph_state* st, double dt) {
   K.grid = c->grid;
   K.check_id = c->check_id;
   K.flag = nullptr;
+  K.deferred = false;
   return K;
+}
+
+// x, y, z, h of the state from the packed position records
+__global__ __launch_bounds__(kB) void k_unpack_pos(const double4* __restrict__ pos4, int64_t n, double* __restrict__ x,
+                                                   double* __restrict__ y, double* __restrict__ z,
+                                                   double* __restrict__ h) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  const double4 q = pos4[a];
+  x[a] = q.x;
+  y[a] = q.y;
+  z[a] = q.z;
+  h[a] = q.w;
 }
 
 __global__ void k_flag_clear(uint32_t* f) { *f = 0u; }   // a kernel, not a memset: graph-safe
@@ -216,18 +244,27 @@ sph_status launch_flag_clear(sph_ctx* c) {
   return SPH_OK;
 }
 
-sph_status launch_kick_drift(sph_ctx* c, sph_state* st, double dt, uint32_t check) {
+sph_status launch_kick_drift(sph_ctx* c, sph_state* st, double dt, uint32_t check, bool deferred) {
   KdkArgs K = make_kdk(c, st, dt);
   if (check) { K.flag = c->drift_flag; K.check_id = check; }
+  K.deferred = deferred;
   hipLaunchKernelGGL(k_kick_drift, dim3(grid_for(st->n, kB)), dim3(kB), 0, c->stream, K);
   HIP_TRY(hipGetLastError());
   return SPH_OK;
 }
 
-sph_status launch_kick_final_drift(sph_ctx* c, sph_state* st, double dt, uint32_t check) {
+sph_status launch_kick_final_drift(sph_ctx* c, sph_state* st, double dt, uint32_t check, bool deferred) {
   KdkArgs K = make_kdk(c, st, dt);
   if (check) { K.flag = c->drift_flag; K.check_id = check; }
+  K.deferred = deferred;
   hipLaunchKernelGGL(k_kick_final_drift, dim3(grid_for(st->n, kB)), dim3(kB), 0, c->stream, K);
+  HIP_TRY(hipGetLastError());
+  return SPH_OK;
+}
+
+sph_status launch_unpack_pos(sph_ctx* c, sph_state* st) {
+  hipLaunchKernelGGL(k_unpack_pos, dim3(grid_for(st->n, kB)), dim3(kB), 0, c->stream, c->pos4, st->n, st->x, st->y,
+                     st->z, st->h);
   HIP_TRY(hipGetLastError());
   return SPH_OK;
 }

@@ -309,6 +309,7 @@ struct sph_ctx {
   uint32_t* drift_flag; // device word: largest check id (step number) that saw a skin violation
   uint32_t* drift_host; // pinned host copy
   uint32_t eval_seq;    // step number of a run-ahead evaluation being queued (0: none)
+  bool pos_deferred;    // st->x, y, z, h lag behind pos4 (kicks inside a multi-step call)
   hipEvent_t step_ev[2];   // run-ahead steps: the skin-test word of a step has reached the host
   int64_t rebuilds;
   double4* pos_build;   // x, y, z, h at the last candidate-list build
@@ -384,10 +385,14 @@ sph_status launch_stress(sph_ctx* c, sph_state* st);
 sph_status launch_forces(sph_ctx* c, sph_state* st);
 // check: 0 no skin test, else the step's number since drift_flag was cleared (a larger value
 // already in the flag cancels the kick)
-sph_status launch_kick_drift(sph_ctx* c, sph_state* st, double dt, uint32_t check);
+// deferred: positions and h are read from and written to pos4 only (st->x, y, z, h lag behind
+// until launch_unpack_pos)
+sph_status launch_kick_drift(sph_ctx* c, sph_state* st, double dt, uint32_t check, bool deferred = false);
 sph_status launch_kick_final(sph_ctx* c, sph_state* st, double dt);
 // the final kick of one step fused with the kick-drift of the next (inside a multi-step call)
-sph_status launch_kick_final_drift(sph_ctx* c, sph_state* st, double dt, uint32_t check);
+sph_status launch_kick_final_drift(sph_ctx* c, sph_state* st, double dt, uint32_t check, bool deferred = false);
+// st->x, y, z, h from pos4 (after deferred kicks)
+sph_status launch_unpack_pos(sph_ctx* c, sph_state* st);
 sph_status launch_pack(sph_ctx* c, sph_state* st);
 sph_status sph_count_stats(sph_ctx* c, sph_list_stats* out);
 sph_status sph_scan_u32(sph_ctx* c, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total);
