@@ -593,8 +593,9 @@ __device__ __forceinline__ bool level_box(const GridInfo& g, int l, const TileGe
 }
 
 // Particle range [s, e) of the cell with linear index j of the level box (empty if the cell is
-// farther than (hmax_g + hlev[l])(1 + skin) from every sub-box).
-template <bool PER>
+// farther than (hmax_g + hlev[l])(1 + skin) from every sub-box).  UNR: sub-boxes tested per
+// unrolled step (their LDS reads issued together; more registers).
+template <bool PER, int UNR>
 __device__ __forceinline__ void cell_range(const GridInfo& g, int l, const LevelBox& L, int64_t j, double s1,
                                            const double (*sub)[8], const int2* __restrict__ cell_se, int& s, int& e) {
   s = e = 0;
@@ -614,7 +615,7 @@ __device__ __forceinline__ void cell_range(const GridInfo& g, int l, const Level
     cc[d] = L.wrap[d] ? ((kk[d] % dim) + dim) % dim : kk[d];
   }
   bool need = false;
-#pragma unroll 1
+#pragma unroll UNR
   for (int gi = 0; gi < 8; ++gi) {
     double gap2 = 0.0;
     for (int d = 0; d < 3; ++d) {
@@ -622,7 +623,7 @@ __device__ __forceinline__ void cell_range(const GridInfo& g, int l, const Level
       gap2 += gapd[d] ? gd * gd : 0.0;
     }
     const double Rg = (sub[gi][6] + g.hlev[l]) * s1 * (1.0 + 1e-9);
-    need = need || (gap2 < Rg * Rg && sub[gi][6] > 0.0);
+    need |= gap2 < Rg * Rg && sub[gi][6] > 0.0;
   }
   if (need) {
     const uint32_t key = L.base + (spread3((uint32_t)cc[0]) | (spread3((uint32_t)cc[1]) << 1) |
@@ -657,7 +658,7 @@ __global__ __launch_bounds__(64) void k_tile_cost(const double4* __restrict__ po
       if (!level_box<PER>(g, l, G, s1, L)) continue;
       for (int64_t q = 0; q < L.total; q += 64) {
         int s, e;
-        cell_range<PER>(g, l, L, q + lane, s1, sub, cell_se, s, e);
+        cell_range<PER, 4>(g, l, L, q + lane, s1, sub, cell_se, s, e);
         tot += e - s;
       }
     }
@@ -746,7 +747,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         // consecutive union members come from all over the neighbourhood and every target's
         // neighbours spread evenly over the LDS chunks of the pair passes
         int s, e;
-        cell_range<PER>(g, l, L, q + (int64_t)(__brev((unsigned)lane) >> 26), s1, sub, B.cell_se, s, e);
+        cell_range<PER, 2>(g, l, L, q + (int64_t)(__brev((unsigned)lane) >> 26), s1, sub, B.cell_se, s, e);
         // wave prefix sum of the cells' particle counts
         const int cntc = e - s;
         int inc = cntc;
