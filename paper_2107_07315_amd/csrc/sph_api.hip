@@ -571,7 +571,7 @@ sph_status sph_autotune(sph_ctx* c, const sph_state* st, double dt, int32_t step
   // coordinate descent: lanes per target, workgroup schedule of the pair passes, tile cut, skin;
   // a setting replaces the best only if it is faster by more than the timing noise (2%)
   for (int dim = 0; dim < 4 && !e; ++dim) {
-    const double vals[4][4] = {{1, 2, 4, -1}, {0, 1024, 4096, 16384}, {6, 8, 10, 12}, {0.1, 0.14, 0.18, -1}};
+    const double vals[4][4] = {{1, 2, 4, -1}, {0, 1024, 4096, 16384}, {6, 8, 10, 12}, {0.07, 0.1, 0.14, 0.18}};
     const sph_params base = best;
     for (int k = 0; k < 4 && !e; ++k) {
       const double v = vals[dim][k];
