@@ -30,63 +30,36 @@ __device__ __forceinline__ T wrap_sel(T d, T box, T half) {
   }
 }
 
-// Wendland kernel value and gradient factor (grad_a W = F (x_a - x_b)) for 1/h_ab = ih; the
-// factor (1 - q/2) is clamped at 0 so that no branch is needed outside the support.
-template <typename R, int KER>
-__device__ __forceinline__ R kern_W(R r, R ih) {
-  const R q = r * ih;
-  R t = (R)1 - (R)0.5 * q;
-  t = t > (R)0 ? t : (R)0;
-  const R ih3 = ih * ih * ih;
-  if constexpr (KER == SPH_WC4) {
-    const R t2 = t * t, t6 = t2 * t2 * t2;
-    return (R)(495.0 / (256.0 * SPH_PI)) * ih3 * t6 * ((R)1 + (R)3 * q + (R)(35.0 / 12.0) * q * q);
-  } else {
-    const R t2 = t * t;
-    return (R)(21.0 / (16.0 * SPH_PI)) * ih3 * t2 * t2 * ((R)1 + (R)2 * q);
-  }
-}
-template <typename R, int KER>
-__device__ __forceinline__ R kern_F(R r, R ih) {
-  const R q = r * ih;
-  R t = (R)1 - (R)0.5 * q;
-  t = t > (R)0 ? t : (R)0;
-  const R ih2 = ih * ih, ih5 = ih2 * ih2 * ih;
-  if constexpr (KER == SPH_WC4) {
-    const R t2 = t * t;
-    return -(R)(1155.0 / (128.0 * SPH_PI)) * ih5 * t2 * t2 * t * ((R)1 + (R)2.5 * q);
-  } else {
-    return -(R)(105.0 / (16.0 * SPH_PI)) * ih5 * t * t * t;
-  }
-}
-
-// FP32 pair-loop forms of W and F without their constant factor (kern_W = kW * kern_W_unit,
-// kern_F = kF * kern_F_unit; the passes apply the factor once to the sums), with t^k / h^k formed
-// as (t / h)^k.  Outside the support t = 0, so both vanish there without a test.
+// Wendland kernels with q = r / h_ab (1/h_ab = ih) and t = max(1 - q/2, 0), in the pair loops
+// without their constant factor, which the passes apply once to the sums:
+//   C4: W = kW h^-3 t^6 (1 + 3q + 35/12 q^2),  F = kF h^-5 t^5 (1 + 5q/2);
+//   C2: W = kW h^-3 t^4 (1 + 2q),              F = kF h^-5 t^3,
+// with grad_a W = F (x_a - x_b); t^k / h^k is formed as (t / h)^k.  Outside the support t = 0,
+// so both vanish there without a test.
 template <int KER>
 constexpr double kern_W_const() { return KER == SPH_WC4 ? 495.0 / (256.0 * SPH_PI) : 21.0 / (16.0 * SPH_PI); }
 template <int KER>
 constexpr double kern_F_const() { return KER == SPH_WC4 ? -1155.0 / (128.0 * SPH_PI) : -105.0 / (16.0 * SPH_PI); }
-template <int KER>
-__device__ __forceinline__ float kern_W_unit(float r, float ih) {
-  const float q = r * ih;
-  const float t = fmaxf(fmaf(-0.5f, q, 1.0f), 0.0f);
+template <typename R, int KER>
+__device__ __forceinline__ R kern_W_unit(R r, R ih) {
+  const R q = r * ih;
+  const R t = fmax(fma((R)-0.5, q, (R)1), (R)0);
   if constexpr (KER == SPH_WC4) {
-    const float w = t * t * ih;   // t^6 / h^3 = w^3
-    return w * w * w * fmaf(fmaf((float)(35.0 / 12.0), q, 3.0f), q, 1.0f);
+    const R w = t * t * ih;   // t^6 / h^3 = w^3
+    return w * w * w * fma(fma((R)(35.0 / 12.0), q, (R)3), q, (R)1);
   } else {
-    const float w = t * ih;       // t^4 / h^3 = w^3 t
-    return w * w * w * t * fmaf(2.0f, q, 1.0f);
+    const R w = t * ih;       // t^4 / h^3 = w^3 t
+    return w * w * w * t * fma((R)2, q, (R)1);
   }
 }
-template <int KER>
-__device__ __forceinline__ float kern_F_unit(float r, float ih) {
-  const float q = r * ih;
-  const float t = fmaxf(fmaf(-0.5f, q, 1.0f), 0.0f);
-  const float w = t * ih;
+template <typename R, int KER>
+__device__ __forceinline__ R kern_F_unit(R r, R ih) {
+  const R q = r * ih;
+  const R t = fmax(fma((R)-0.5, q, (R)1), (R)0);
+  const R w = t * ih;
   if constexpr (KER == SPH_WC4) {
-    const float w2 = w * w;       // t^5 / h^5 = w^5
-    return w2 * w2 * w * fmaf(2.5f, q, 1.0f);
+    const R w2 = w * w;       // t^5 / h^5 = w^5
+    return w2 * w2 * w * fma((R)2.5, q, (R)1);
   } else {
     return w * w * w * (ih * ih); // t^3 / h^5
   }
@@ -543,7 +516,7 @@ __global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* _
         const double Hd = pa.w + q.w;
         hit = r2d < Hd * Hd;
       }
-      W = kern_W_unit<KER>(sqrt_hw(r2), rcp_fast(0.5f * H));   // zero for misses
+      W = kern_W_unit<float, KER>(sqrt_hw(r2), rcp_fast(0.5f * H));   // zero for misses
     } else {
       const double dx = wrap_sel<PER>(pa.x - pb.x, box, half);
       const double dy = wrap_sel<PER>(pa.y - pb.y, box, half);
@@ -551,8 +524,8 @@ __global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* _
       const double r2 = pair_r2(dx, dy, dz);
       const double H = pa.w + pb.w;
       hit = r2 < H * H;
-      W = kern_W<R, KER>(sqrt_fast((R)r2), rcp_fast((R)(0.5 * H)));
-      W = hit ? W : (R)0;
+      W = kern_W_unit<R, KER>(sqrt_fast((R)r2), rcp_fast((R)(0.5 * H)));
+      W = hit ? W : (R)0;   // the exact decision also at the support edge
     }
     sum += W;
     wr.put(loc, hit);
@@ -595,7 +568,7 @@ __global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* _
   }
   if (tw.valid && sub == 0) {
     const double W0 = wendland_self<double>(KER, pa.w);   // the particle's own term
-    O.D[a] = particle_mass(A, a) * (F32 ? fma(kern_W_const<KER>(), (double)sum, W0) : (double)sum + W0);
+    O.D[a] = particle_mass(A, a) * fma(kern_W_const<KER>(), (double)sum, W0);
   }
   }
 }
@@ -672,9 +645,9 @@ __global__ __launch_bounds__(64 * L) void k_stress(PassArgs A, const typename Re
                       wrap_sel<PER>(pa.z - pb.z, box, half)};
       const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
       const R ih = rcp_fast(Rec<R>::HS * (pa.w + pb.w));
-      R F;   // FP32: without the kernel's constant, applied below
-      if constexpr (std::is_same<R, float>::value) F = kern_F_unit<KER>(sqrt_hw(r2), ih);
-      else F = kern_F<R, KER>(sqrt_fast(r2), ih);
+      R F;   // without the kernel's constant, applied in the epilogue
+      if constexpr (std::is_same<R, float>::value) F = kern_F_unit<float, KER>(sqrt_hw(r2), ih);
+      else F = kern_F_unit<R, KER>(sqrt_fast(r2), ih);
       const R g[3] = {F * d[0], F * d[1], F * d[2]};
       const R v[3] = {vb.x - va.x, vb.y - va.y, vb.z - va.z};
 #pragma unroll
@@ -688,7 +661,7 @@ __global__ __launch_bounds__(64 * L) void k_stress(PassArgs A, const typename Re
 #pragma unroll
     for (int jj = 0; jj < 3; ++jj) G[i][jj] = lane_group_sum<L>(G[i][jj]);
   if (!stressed || sub != 0) continue;
-  const double m = particle_mass(A, a) * (std::is_same<R, float>::value ? kern_F_const<KER>() : 1.0);
+  const double m = particle_mass(A, a) * kern_F_const<KER>();
   const double D = -(double)faa.y * (2.0 * (double)Rec<R>::HS);  // stressed particles store -D (FP32: -D/2)
   const double iD2 = m / (2.0 * D);
   double ed[3][3], Rd[3][3];
@@ -786,9 +759,9 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
                     wrap_sel<PER>(pa.z - pb.z, box, half)};
     const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
     const R hab = Rec<R>::HS * (pa.w + pb.w);
-    R F;   // grad_a W = F d (FP32: without the kernel's constant, applied to the sums)
-    if constexpr (std::is_same<R, float>::value) F = kern_F_unit<KER>(sqrt_hw(r2), rcp_fast(hab));
-    else F = kern_F<R, KER>(sqrt_fast(r2), rcp_fast(hab));
+    R F;   // grad_a W = kF F d (the constant kF is applied to the sums)
+    if constexpr (std::is_same<R, float>::value) F = kern_F_unit<float, KER>(sqrt_hw(r2), rcp_fast(hab));
+    else F = kern_F_unit<R, KER>(sqrt_fast(r2), rcp_fast(hab));
     const R v[3] = {va.x - vb.x, va.y - vb.y, va.z - vb.z};
     const R vr = v[0] * d[0] + v[1] * d[1] + v[2] * d[2];
     const bool b_st = fab.y < 0;
@@ -849,7 +822,7 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
   }
   ud = lane_group_sum<L>(ud);
   if (!tw.valid || sub != 0) continue;
-  const double m = particle_mass(A, a) * (std::is_same<R, float>::value ? kern_F_const<KER>() : 1.0);
+  const double m = particle_mass(A, a) * kern_F_const<KER>();
   double APd[3] = {m * (double)AP[0], m * (double)AP[1], m * (double)AP[2]};
   double ASd[3] = {m * (double)AS[0], m * (double)AS[1], m * (double)AS[2]};
   double acc[3];
