@@ -134,7 +134,7 @@ sph_status sph_create(const sph_params* params, void* stream, int64_t capacity, 
   c->upool = (int64_t)((capacity + 63) / 64 * 64) * 128;
   if (c->upool > (int64_t)0xffffffffll) c->upool = (int64_t)0xffffffffll;
   (void)hipGetDevice(&c->device);
-  c->check_id = 1;   // the drift kernel writes this to the flag, which is cleared before each test
+  c->check_id = 1;   // written by failed drift tests outside a run-ahead step (flag cleared first)
   const int64_t cap = capacity;
   const int64_t capw = (cap + 63) / 64 * 64;
   c->capw = capw;

@@ -305,7 +305,7 @@ struct sph_ctx {
   int64_t g_n;
   double g_dt;
   uint32_t g_epoch;
-  uint32_t check_id;    // id of the last drift test (written to drift_flag by violators)
+  uint32_t check_id;    // value a failed drift test writes when no step number applies (1)
   uint32_t* drift_flag; // device word: largest check id (step number) that saw a skin violation
   uint32_t* drift_host; // pinned host copy
   uint32_t eval_seq;    // step number of a run-ahead evaluation being queued (0: none)
@@ -383,8 +383,8 @@ sph_status launch_density(sph_ctx* c, sph_state* st);   // pair loop
 sph_status launch_eos(sph_ctx* c, sph_state* st);       // per-particle epilogue
 sph_status launch_stress(sph_ctx* c, sph_state* st);
 sph_status launch_forces(sph_ctx* c, sph_state* st);
-// check: 0 no skin test, else the step's number since drift_flag was cleared (a larger value
-// already in the flag cancels the kick)
+// check: 0 no skin test, else the step's number since drift_flag was cleared (a smaller non-zero
+// value already in the flag, left by an earlier step's failed test, cancels the kick)
 // deferred: positions and h are read from and written to pos4 only (st->x, y, z, h lag behind
 // until launch_unpack_pos)
 sph_status launch_kick_drift(sph_ctx* c, sph_state* st, double dt, uint32_t check, bool deferred = false);
