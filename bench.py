@@ -40,13 +40,25 @@ KERNEL_SOURCES = ("paper_2107_07315_amd/csrc/sph_pairs.hip", "paper_2107_07315_a
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pair_passes_2M_traffic.json")
 
 
-def sources_digest():
+def code_digest(texts):
+    """Hash of C++ sources with comments and blank lines removed: a comment edit keeps the digest,
+    any change to the code does not."""
     import hashlib
+    import re
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+    for text in texts:
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        h.update("\n".join(l.rstrip() for l in text.splitlines() if l.strip()).encode())
     return h.hexdigest()[:16]
+
+
+def sources_digest():
+    texts = []
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f)) as fh:
+            texts.append(fh.read())
+    return code_digest(texts)
 
 
 def measured_traffic(kernel):
