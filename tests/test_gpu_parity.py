@@ -113,6 +113,30 @@ def test_table_eos_star():
     _assert_eval(g, o)
 
 
+def test_full_size_star_matches_oracle():
+    # the benchmark workload itself (2M-particle piecewise-polytrope star, table EoS) in the
+    # configuration bench.py times (default context: 4 lanes per target, default skin, run-ahead
+    # multi-step call): one evaluation and 2 steps in FP64 against the oracle at full size, and
+    # the FP32 evaluation per field; every particle is compared
+    w = W.pp_star(2_000_000, seed=3, eos="TABLE")
+    o = oracle_run(w)
+    g = gpu_run(w, lists=False)
+    _assert_eval(g, o)
+    g32 = gpu_run(w, precision="FP32", lists=False)
+    e = eval_errors(g32, o)
+    _print("2M fp32 eval", e)
+    for k in ("D", "rho", "P", "ax", "ay", "az", "dudt", "dSdt"):
+        assert e[k] < 1e-4, (k, e[k])
+    del g, g32, o
+    g = gpu_run(w, steps=2, lists=False)
+    o = oracle_run(w, steps=2)
+    e = field_errors(g, o, ("x", "y", "z", "vx", "vy", "vz", "u", "h", "S", "D", "ax", "dudt", "dSdt"))
+    _print("2M 2 steps", e)
+    for k, v in e.items():
+        assert v < 1e-9, (k, v)
+    assert np.array_equal(g["broken"], o["broken"])
+
+
 def test_fp32_pairs_error_per_field():
     # the FP32 path takes the neighbour decision in FP32 with an FP64 guard band: its exact lists
     # must still equal the FP64 ones
