@@ -99,7 +99,8 @@ typedef struct {
   double visc_alpha, visc_beta, visc_eps;   /* Monaghan viscosity (default 1, 2, 0.01)        */
   int32_t eos;             /* GAMMA: P=(gamma-1) rho u; TABLE: bilinear ln P, ln cs^2;         */
   double gamma;            /*   MLP: surrogate with table fallback (sph_mlp_*)                */
-  const double* tab_lnP;   /* device: [i_rho * tab_nu + i_u]                                  */
+  const double* tab_lnP;   /* device: [i_rho * tab_nu + i_u]; NULL: the table of               */
+                           /*   sph_eos_table_create (stage calls return SPH_E_ARG without one) */
   const double* tab_lncs2;
   int32_t tab_nr, tab_nu;
   double tab_lnr0, tab_dlnr, tab_lnu0, tab_dlnu;
@@ -251,6 +252,12 @@ sph_status sph_neighbour_stats(sph_ctx* ctx, sph_list_stats* out);
 /* Load FP32 master weights (host array); resets the optimiser and drops the trust mask. */
 sph_status sph_mlp_set_params(sph_ctx* ctx, const float* params);
 
+/* Load a network from its BF16 weights (host array of SPH_MLP_NPARAM 16-bit patterns, the upper
+ * halves of IEEE FP32 values, in the parameter order above), e.g. weights trained elsewhere:
+ * the FP32 masters become exactly these values (so the kernels use them unchanged); resets the
+ * optimiser and drops the trust mask.  SPH_E_ARG without an EoS table.  Waits. */
+sph_status sph_mlp_load(sph_ctx* ctx, const uint16_t* bf16_weights);
+
 /* Copy the weights to the host: the FP32 masters, or (rounded != 0) the BF16 values the
  * kernels use, as floats.  SPH_E_ARG before sph_mlp_set_params. */
 sph_status sph_mlp_get_params(sph_ctx* ctx, float* params, int32_t rounded);
@@ -283,6 +290,25 @@ sph_status sph_mlp_build_trust_mask(sph_ctx* ctx, double tol, int64_t* trusted_c
 
 /* Human-readable name of a status code (static string). */
 const char* sph_status_string(sph_status s);
+
+/* Why the last failing call on this context failed: the status name followed by the argument
+ * or condition at fault (which array is NULL, which parameter is out of range, which stage has
+ * to come first), or, for a device error returned by sph_sync, the particle that latched it and
+ * what the code means.  With ctx NULL: the last failure of a call made without a context
+ * (sph_create) on this host thread.  The string belongs to the context (or the thread) and stays
+ * valid until its next failing call. */
+const char* sph_last_error_detail(const sph_ctx* ctx);
+
+/* Tabulated equation of state (section "Setting up Neutron Stars": tabulated EoS, here a table of
+ * ln P and ln c_s^2 on a uniform grid in (ln rho, ln u), interpolated bilinearly): copies the host
+ * arrays lnP[nr * nu], lncs2[nr * nu] (index i_rho * nu + i_u; NaN marks states outside the
+ * EoS's domain) into device memory the context owns, and points the context's table parameters at
+ * it; a later sph_set_params whose table pointers are NULL keeps using it.  Grid: ln rho_i =
+ * lnr0 + i dlnr, ln u_j = lnu0 + j dlnu.  A network loaded for the previous table is dropped.
+ * SPH_E_ARG for NULL arrays, nr or nu < 2 or non-positive spacing; SPH_E_OOM if the copy does not
+ * fit.  Invalidates the stage order.  Waits. */
+sph_status sph_eos_table_create(sph_ctx* ctx, const double* lnP, const double* lncs2, int32_t nr, int32_t nu,
+                                double lnr0, double dlnr, double lnu0, double dlnu);
 
 /* Kernel timing since timing was last enabled: launches and total milliseconds of one stage,
  * measured with HIP events on the context stream (0 while timing is off).  Stages: "cells"

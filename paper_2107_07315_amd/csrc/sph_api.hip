@@ -1,9 +1,11 @@
 // C-ABI entry points of libsph: context, stage calls, time stepping, status and timing.
+#include <stdarg.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 
 #include "sph_internal.h"
@@ -23,37 +25,82 @@ sph_status dalloc(T** p, size_t count) {
   return SPH_OK;
 }
 
-sph_status check_params(const sph_params* p) {
-  if (!p) return SPH_E_ARG;
-  if (p->kernel != SPH_WC2 && p->kernel != SPH_WC4) return SPH_E_ARG;
-  if (!(p->m > 0.0)) return SPH_E_ARG;
-  if (p->background == SPH_TOV && (!p->bg || p->bg_n < 2 || !(p->bg_dr > 0.0))) return SPH_E_ARG;
-  if (p->periodic && !(p->box > 0.0)) return SPH_E_ARG;
-  if ((p->eos == SPH_EOS_TABLE || p->eos == SPH_EOS_MLP) &&
-      (!p->tab_lnP || !p->tab_lncs2 || p->tab_nr < 2 || p->tab_nu < 2))
-    return SPH_E_ARG;
-  if (p->precision != SPH_FP64 && p->precision != SPH_FP32) return SPH_E_ARG;
-  if (p->max_neighbours < 0 || p->max_neighbours > 4096) return SPH_E_ARG;
-  if (p->cell_div < 0 || p->cell_div > 4) return SPH_E_ARG;
-  if (!(p->tile_cut >= 0.0) || p->tile_cut > 64.0) return SPH_E_ARG;
-  if (!(p->skin >= 0.0) || p->skin > 1.0) return SPH_E_ARG;
-  if (p->pass_blocks < 0 || p->pass_blocks > 65536 || p->graph < 0 || p->graph > 1) return SPH_E_ARG;
-  if (p->lanes != 0 && p->lanes != 1 && p->lanes != 2 && p->lanes != 4) return SPH_E_ARG;
+// Detail of the last failure of a call without a context (sph_create), per host thread.
+thread_local char g_detail[256] = "no error";
+
+sph_status vnote(sph_ctx* c, sph_status e, const char* fmt, va_list ap) {
+  char* buf = c ? c->detail : g_detail;
+  const size_t cap = c ? sizeof(c->detail) : sizeof(g_detail);
+  int k = snprintf(buf, cap, "%s: ", sph_status_string(e));
+  if (k < 0) k = 0;
+  if ((size_t)k < cap) vsnprintf(buf + k, cap - (size_t)k, fmt, ap);
+  return e;
+}
+
+sph_status check_params(sph_ctx* c, const sph_params* p) {
+  if (!p) return note(c, SPH_E_ARG, "params is NULL");
+  if (p->kernel != SPH_WC2 && p->kernel != SPH_WC4) return note(c, SPH_E_ARG, "kernel %d is not SPH_WC2 or SPH_WC4", p->kernel);
+  if (!(p->m > 0.0)) return note(c, SPH_E_ARG, "particle mass m = %g must be positive", p->m);
+  if (p->background == SPH_TOV && (!p->bg || p->bg_n < 2 || !(p->bg_dr > 0.0)))
+    return note(c, SPH_E_ARG, "background TOV needs bg (device), bg_n >= 2 and bg_dr > 0");
+  if (p->periodic && !(p->box > 0.0)) return note(c, SPH_E_ARG, "periodic needs box > 0");
+  if ((p->tab_lnP || p->tab_lncs2) && (!p->tab_lnP || !p->tab_lncs2 || p->tab_nr < 2 || p->tab_nu < 2))
+    return note(c, SPH_E_ARG, "an EoS table needs tab_lnP, tab_lncs2 and tab_nr, tab_nu >= 2");
+  if (p->precision != SPH_FP64 && p->precision != SPH_FP32) return note(c, SPH_E_ARG, "precision %d", p->precision);
+  if (p->max_neighbours < 0 || p->max_neighbours > 4096)
+    return note(c, SPH_E_ARG, "max_neighbours = %d outside [0, 4096]", p->max_neighbours);
+  if (p->cell_div < 0 || p->cell_div > 4) return note(c, SPH_E_ARG, "cell_div = %d outside [0, 4]", p->cell_div);
+  if (!(p->tile_cut >= 0.0) || p->tile_cut > 64.0) return note(c, SPH_E_ARG, "tile_cut = %g outside [0, 64]", p->tile_cut);
+  if (!(p->skin >= 0.0) || p->skin > 1.0) return note(c, SPH_E_ARG, "skin = %g outside [0, 1]", p->skin);
+  if (p->pass_blocks < 0 || p->pass_blocks > 65536)
+    return note(c, SPH_E_ARG, "pass_blocks = %d outside [0, 65536]", p->pass_blocks);
+  if (p->graph < 0 || p->graph > 1) return note(c, SPH_E_ARG, "graph = %d is not 0 or 1", p->graph);
+  if (p->lanes != 0 && p->lanes != 1 && p->lanes != 2 && p->lanes != 4)
+    return note(c, SPH_E_ARG, "lanes = %d is not 0, 1, 2 or 4", p->lanes);
   return SPH_OK;
 }
 
-sph_status check_state(const sph_ctx* c, const sph_state* st) {
-  if (!c || !st) return SPH_E_ARG;
-  if (st->n < 0 || st->n > c->capacity) return SPH_E_ARG;
-  if (st->n > 0 && (!st->x || !st->y || !st->z || !st->vx || !st->vy || !st->vz || !st->u || !st->h ||
-                    !st->S || !st->type || !st->broken || !st->id || !st->D || !st->rho || !st->P ||
-                    !st->cs || !st->ax || !st->ay || !st->az || !st->dudt || !st->dSdt))
-    return SPH_E_ARG;
-  if (c->stars && st->n > 0 && !st->star) return SPH_E_ARG;
+sph_status check_state(sph_ctx* c, const sph_state* st) {
+  if (!c) return note(nullptr, SPH_E_ARG, "context is NULL");
+  if (!st) return note(c, SPH_E_ARG, "state is NULL");
+  if (st->n < 0 || st->n > c->capacity)
+    return note(c, SPH_E_ARG, "n = %lld outside [0, capacity = %lld]", (long long)st->n, (long long)c->capacity);
+  if (st->n > 0) {
+    const void* req[] = {st->x, st->y, st->z, st->vx, st->vy, st->vz, st->u, st->h, st->S, st->type, st->broken,
+                         st->id, st->D, st->rho, st->P, st->cs, st->ax, st->ay, st->az, st->dudt, st->dSdt};
+    static const char* names[] = {"x", "y", "z", "vx", "vy", "vz", "u", "h", "S", "type", "broken", "id", "D",
+                                  "rho", "P", "cs", "ax", "ay", "az", "dudt", "dSdt"};
+    for (size_t k = 0; k < sizeof(req) / sizeof(req[0]); ++k)
+      if (!req[k]) return note(c, SPH_E_ARG, "state array %s is NULL", names[k]);
+  }
+  if (c->stars && st->n > 0 && !st->star) return note(c, SPH_E_ARG, "an ensemble is set but state array star is NULL");
+  if ((c->p.eos == SPH_EOS_TABLE || c->p.eos == SPH_EOS_MLP) && !c->p.tab_lnP)
+    return note(c, SPH_E_ARG, "eos TABLE or MLP needs a table (tab_* parameters or sph_eos_table_create)");
   return SPH_OK;
+}
+
+// The context's own table (sph_eos_table_create) stands in for table pointers left NULL.
+void use_own_table(const sph_ctx* c, sph_params* p) {
+  if (p->tab_lnP || !c->tab_own) return;
+  p->tab_lnP = c->tab_own;
+  p->tab_lncs2 = c->tab_own + (size_t)c->tab_own_nr * c->tab_own_nu;
+  p->tab_nr = c->tab_own_nr;
+  p->tab_nu = c->tab_own_nu;
+  p->tab_lnr0 = c->tab_own_g[0];
+  p->tab_dlnr = c->tab_own_g[1];
+  p->tab_lnu0 = c->tab_own_g[2];
+  p->tab_dlnu = c->tab_own_g[3];
 }
 
 }  // namespace
+
+sph_status note(sph_ctx* c, sph_status e, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vnote(c, e, fmt, ap);
+  va_end(ap);
+  return e;
+}
 
 void timer_begin(sph_ctx* c, int which) {
   if (!c->timing) return;
@@ -103,6 +150,7 @@ void sph_destroy(sph_ctx* c) {
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (c->drift_host) (void)hipHostFree(c->drift_host);
+  if (c->tab_own) (void)hipFree(c->tab_own);
   mlp_free(c);
   for (auto& t : c->timers)
     for (hipEvent_t e : t.ev) (void)hipEventDestroy(e);
@@ -116,13 +164,14 @@ void sph_destroy(sph_ctx* c) {
 }
 
 sph_status sph_create(const sph_params* params, void* stream, int64_t capacity, sph_ctx** out) {
-  if (!out) return SPH_E_ARG;
+  if (!out) return note(nullptr, SPH_E_ARG, "out is NULL");
   *out = nullptr;
-  sph_status e = check_params(params);
+  sph_status e = check_params(nullptr, params);
   if (e) return e;
-  if (capacity < 1 || capacity > (int64_t(1) << 30)) return SPH_E_ARG;
+  if (capacity < 1 || capacity > (int64_t(1) << 30))
+    return note(nullptr, SPH_E_ARG, "capacity = %lld outside [1, 2^30]", (long long)capacity);
   sph_ctx* c = (sph_ctx*)calloc(1, sizeof(sph_ctx));
-  if (!c) return SPH_E_OOM;
+  if (!c) return note(nullptr, SPH_E_OOM, "host allocation of the context failed");
   new (c) sph_ctx();
   c->p = *params;
   c->stream = (hipStream_t)stream;
@@ -164,13 +213,14 @@ sph_status sph_create(const sph_params* params, void* stream, int64_t capacity, 
       (e = dalloc(&c->tovf, cap)) ||
       (e = dalloc(&c->half, 10 * cap)) || (e = dalloc(&c->tmp, capw)) || (e = dalloc(&c->status, 1))) {
     sph_destroy(c);
-    return e;
+    return note(nullptr, e, "device scratch for capacity %lld does not fit", (long long)capacity);
   }
   if (hipHostMalloc((void**)&c->drift_host, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
     c->drift_host = nullptr;
     sph_destroy(c);
-    return SPH_E_OOM;
+    return note(nullptr, SPH_E_OOM, "pinned host word");
   }
+
   if (hipMemsetAsync(c->status, 0, sizeof(DevStatus), c->stream) != hipSuccess ||
       hipMemsetAsync(c->nbr_count, 0, sizeof(int32_t) * cap, c->stream) != hipSuccess ||
       hipMemsetAsync(c->nbr_count_sl, 0, sizeof(int32_t) * capw * 4, c->stream) != hipSuccess ||
@@ -179,19 +229,21 @@ sph_status sph_create(const sph_params* params, void* stream, int64_t capacity, 
       hipMemsetAsync(c->Y0, 0, sizeof(double) * cap, c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess) {
     sph_destroy(c);
-    return SPH_E_HIP;
+    return note(nullptr, SPH_E_HIP, "clearing the context's counters failed");
   }
+  snprintf(c->detail, sizeof(c->detail), "no error");
   *out = c;
   return SPH_OK;
 }
 
 sph_status sph_set_params(sph_ctx* c, const sph_params* params) {
-  if (!c) return SPH_E_ARG;
-  sph_status e = check_params(params);
+  if (!c) return note(nullptr, SPH_E_ARG, "context is NULL");
+  sph_status e = check_params(c, params);
   if (e) return e;
   int cap = params->max_neighbours > 0 ? params->max_neighbours : 512;
-  if (cap != c->cap) return SPH_E_ARG;   // list capacity is fixed at creation
+  if (cap != c->cap) return note(c, SPH_E_ARG, "max_neighbours cannot change after sph_create");
   c->p = *params;
+  use_own_table(c, &c->p);
   c->gen = 0;
   c->lists_valid = false;
   ++c->graph_epoch;
@@ -246,7 +298,7 @@ sph_status sph_build_cells(sph_ctx* c, sph_state* st) {
 sph_status sph_density(sph_ctx* c, sph_state* st) {
   sph_status e = check_state(c, st);
   if (e) return e;
-  if (c->gen < 1 || st->n != c->n) return SPH_E_ORDER;
+  if (c->gen < 1 || st->n != c->n) return note(c, SPH_E_ORDER, "sph_density needs sph_build_cells for this state first");
   if (st->n > 0) {
     timer_begin(c, TIMER_DENSITY);
     e = launch_density(c, st);
@@ -264,7 +316,7 @@ sph_status sph_density(sph_ctx* c, sph_state* st) {
 sph_status sph_stress_rate(sph_ctx* c, sph_state* st) {
   sph_status e = check_state(c, st);
   if (e) return e;
-  if (c->gen < 2 || st->n != c->n) return SPH_E_ORDER;
+  if (c->gen < 2 || st->n != c->n) return note(c, SPH_E_ORDER, "sph_stress_rate needs sph_density first");
   if (st->n > 0) {
     timer_begin(c, TIMER_STRESS);
     e = launch_stress(c, st);
@@ -278,7 +330,7 @@ sph_status sph_stress_rate(sph_ctx* c, sph_state* st) {
 sph_status sph_forces(sph_ctx* c, sph_state* st) {
   sph_status e = check_state(c, st);
   if (e) return e;
-  if (c->gen < 3 || st->n != c->n) return SPH_E_ORDER;
+  if (c->gen < 3 || st->n != c->n) return note(c, SPH_E_ORDER, "sph_forces needs sph_stress_rate first");
   if (st->n > 0) {
     timer_begin(c, TIMER_FORCES);
     e = launch_forces(c, st);
@@ -455,10 +507,10 @@ static sph_status step_loop(sph_ctx* c, sph_state* st, double dt, int32_t nsteps
 sph_status sph_step(sph_ctx* c, sph_state* st, double dt, int32_t nsteps) {
   sph_status e = check_state(c, st);
   if (e) return e;
-  if (!(dt > 0.0) || nsteps < 0) return SPH_E_ARG;
-  if (c->gen < 4 || st->n != c->n) return SPH_E_ORDER;
+  if (!(dt > 0.0) || nsteps < 0) return note(c, SPH_E_ARG, "dt = %g must be positive and nsteps = %d not negative", dt, nsteps);
+  if (c->gen < 4 || st->n != c->n) return note(c, SPH_E_ORDER, "sph_step needs a full evaluation (build, density, stress rate, forces) of this state first");
   if (st->n == 0) return SPH_OK;
-  if (c->p.graph && !c->stream) return SPH_E_ARG;   // the legacy default stream cannot be captured
+  if (c->p.graph && !c->stream) return note(c, SPH_E_ARG, "graph replay needs a non-default stream");
   if (c->p.graph && c->p.skin > 0.0 && c->lists_valid) {
     e = step_graphs(c, st, dt, nsteps);
     if (!e) c->gen = 4;
@@ -535,7 +587,8 @@ extern "C" {
 sph_status sph_autotune(sph_ctx* c, const sph_state* st, double dt, int32_t steps, sph_tune_result* out) {
   sph_status e = check_state(c, st);
   if (e) return e;
-  if (!out || !(dt > 0.0) || steps < 1 || st->n == 0) return SPH_E_ARG;
+  if (!out || !(dt > 0.0) || steps < 1 || st->n == 0)
+    return note(c, SPH_E_ARG, "sph_autotune needs out, dt > 0, steps_per_trial >= 1 and n > 0");
   StateCopy cp;
   if ((e = cp.make(st))) return e;
   const int32_t timing = c->timing;
@@ -617,11 +670,13 @@ sph_status sph_autotune(sph_ctx* c, const sph_state* st, double dt, int32_t step
 }
 
 sph_status sph_ensemble_set(sph_ctx* c, int32_t nstars, const double* star_info) {
-  if (!c || nstars < 0 || (nstars > 0 && !star_info)) return SPH_E_ARG;
+  if (!c) return note(nullptr, SPH_E_ARG, "context is NULL");
+  if (nstars < 0 || (nstars > 0 && !star_info)) return note(c, SPH_E_ARG, "nstars = %d needs star_info", nstars);
   std::vector<StarInfo> h((size_t)nstars);
   for (int32_t s = 0; s < nstars; ++s) {
     const double* q = star_info + 5 * (int64_t)s;
-    if (!(q[3] > 0.0) || !(q[4] >= 0.0)) return SPH_E_ARG;
+    if (!(q[3] > 0.0) || !(q[4] >= 0.0))
+      return note(c, SPH_E_ARG, "star %d: particle mass must be positive and shear factor not negative", s);
     h[s] = StarInfo{q[0], q[1], q[2], q[3], q[4], {0.0, 0.0, 0.0}};
   }
   HIP_TRY(hipStreamSynchronize(c->stream));
@@ -644,21 +699,68 @@ sph_status sph_ensemble_set(sph_ctx* c, int32_t nstars, const double* star_info)
 int32_t sph_error_particle(const sph_ctx* c) { return c ? c->err_particle : -1; }
 
 sph_status sph_sync(sph_ctx* c) {
-  if (!c) return SPH_E_ARG;
-  if (hipStreamSynchronize(c->stream) != hipSuccess) return SPH_E_HIP;
+  if (!c) return note(nullptr, SPH_E_ARG, "context is NULL");
+  hipError_t he = hipStreamSynchronize(c->stream);
+  if (he != hipSuccess) return note(c, SPH_E_HIP, "waiting for the stream: %s", hipGetErrorString(he));
   DevStatus s;
-  if (hipMemcpy(&s, c->status, sizeof(s), hipMemcpyDeviceToHost) != hipSuccess) return SPH_E_HIP;
+  if ((he = hipMemcpy(&s, c->status, sizeof(s), hipMemcpyDeviceToHost)) != hipSuccess)
+    return note(c, SPH_E_HIP, "reading the status word: %s", hipGetErrorString(he));
   if (s.code) {
     c->err_particle = s.particle;
     DevStatus z = {0, 0};
-    if (hipMemcpy(c->status, &z, sizeof(z), hipMemcpyHostToDevice) != hipSuccess) return SPH_E_HIP;
-    return (sph_status)s.code;
+    if ((he = hipMemcpy(c->status, &z, sizeof(z), hipMemcpyHostToDevice)) != hipSuccess)
+      return note(c, SPH_E_HIP, "clearing the status word: %s", hipGetErrorString(he));
+    static const char* why[8] = {"", "a periodic box too small for one image per pair (2h >= box/2)", "",
+                                 "", "", "a neighbour list exceeded its capacity (exact: max_neighbours, candidate: twice that)",
+                                 "a field became NaN or Inf", "(rho, u) outside the tabulated equation of state"};
+    const char* w = (s.code > 0 && s.code < 8) ? why[s.code] : "";
+    if (s.particle >= 0)
+      return note(c, (sph_status)s.code, "latched on the device by particle %d (index in the current order): %s",
+                  s.particle, w);
+    return note(c, (sph_status)s.code, "latched on the device by a tile: %s", w);
   }
   return SPH_OK;
 }
 
+const char* sph_last_error_detail(const sph_ctx* c) { return c ? c->detail : g_detail; }
+
+sph_status sph_eos_table_create(sph_ctx* c, const double* lnP, const double* lncs2, int32_t nr, int32_t nu,
+                                double lnr0, double dlnr, double lnu0, double dlnu) {
+  if (!c) return note(nullptr, SPH_E_ARG, "context is NULL");
+  if (!lnP || !lncs2) return note(c, SPH_E_ARG, "lnP and lncs2 (host arrays) must not be NULL");
+  if (nr < 2 || nu < 2 || (int64_t)nr * nu > (int64_t(1) << 28))
+    return note(c, SPH_E_ARG, "table size %d x %d outside [2, 2^28 nodes]", nr, nu);
+  if (!(dlnr > 0.0) || !(dlnu > 0.0) || !std::isfinite(lnr0) || !std::isfinite(lnu0))
+    return note(c, SPH_E_ARG, "table spacing must be positive and origins finite");
+  const size_t nn = (size_t)nr * nu;
+  hipError_t he = hipStreamSynchronize(c->stream);
+  if (he != hipSuccess) return note(c, SPH_E_HIP, "waiting for the stream: %s", hipGetErrorString(he));
+  double* t = nullptr;
+  if (hipMalloc((void**)&t, sizeof(double) * 2 * nn) != hipSuccess) return note(c, SPH_E_OOM, "table of %zu nodes", nn);
+  if ((he = hipMemcpy(t, lnP, sizeof(double) * nn, hipMemcpyHostToDevice)) != hipSuccess ||
+      (he = hipMemcpy(t + nn, lncs2, sizeof(double) * nn, hipMemcpyHostToDevice)) != hipSuccess) {
+    (void)hipFree(t);
+    return note(c, SPH_E_HIP, "uploading the table: %s", hipGetErrorString(he));
+  }
+  if (c->tab_own) (void)hipFree(c->tab_own);
+  c->tab_own = t;
+  c->tab_own_nr = nr;
+  c->tab_own_nu = nu;
+  c->tab_own_g[0] = lnr0;
+  c->tab_own_g[1] = dlnr;
+  c->tab_own_g[2] = lnu0;
+  c->tab_own_g[3] = dlnu;
+  c->p.tab_lnP = nullptr;
+  use_own_table(c, &c->p);
+  mlp_free(c);   // a network belongs to the table it was fitted to
+  c->gen = 0;
+  ++c->graph_epoch;
+  return SPH_OK;
+}
+
 sph_status sph_export_neighbours(sph_ctx* c, int64_t* offsets, int32_t* ids, int64_t cap) {
-  if (!c || !offsets) return SPH_E_ARG;
+  if (!c) return note(nullptr, SPH_E_ARG, "context is NULL");
+  if (!offsets) return note(c, SPH_E_ARG, "offsets is NULL");
   if (c->n > 0 && (c->gen < 2 || !c->lists_valid)) return SPH_E_ORDER;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return SPH_E_HIP;
   const int64_t n = c->n;

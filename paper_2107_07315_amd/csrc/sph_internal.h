@@ -370,7 +370,17 @@ struct sph_ctx {
   StageTimer timers[6];
   // EoS surrogate network (allocated on first use)
   struct MlpState* mlp;
+  // EoS table owned by the context (sph_eos_table_create): lnP then lncs2, nr * nu each
+  double* tab_own;
+  int32_t tab_own_nr, tab_own_nu;
+  double tab_own_g[4];   // lnr0, dlnr, lnu0, dlnu
+  // reason for the last failing call (sph_last_error_detail)
+  char detail[256];
 };
+
+// Records a human-readable reason for a failing return (sph_last_error_detail; c may be NULL for
+// calls without a context) and returns e.
+sph_status note(sph_ctx* c, sph_status e, const char* fmt, ...);
 
 // ---- host launchers (one per kernel file) ------------------------------------------------------
 sph_status sph_sort_pairs(sph_ctx* c, uint32_t* keys, uint32_t* vals, int64_t n);

@@ -504,7 +504,9 @@ void mlp_free(sph_ctx* c) {
 extern "C" {
 
 sph_status sph_mlp_set_params(sph_ctx* c, const float* params) {
-  if (!c || !params || !table_ok(c)) return SPH_E_ARG;
+  if (!c) return note(nullptr, SPH_E_ARG, "context is NULL");
+  if (!params) return note(c, SPH_E_ARG, "params is NULL");
+  if (!table_ok(c)) return note(c, SPH_E_ARG, "the network needs the context's EoS table");
   sph_status e;
   if ((e = mlp_alloc(c)) || (e = mlp_norm(c))) return e;
   MlpState* s = c->mlp;
@@ -524,6 +526,17 @@ sph_status sph_mlp_set_params(sph_ctx* c, const float* params) {
   s->loaded = true;
   ++c->graph_epoch;
   return SPH_OK;
+}
+
+sph_status sph_mlp_load(sph_ctx* c, const uint16_t* bf16_weights) {
+  if (!c) return note(nullptr, SPH_E_ARG, "context is NULL");
+  if (!bf16_weights) return note(c, SPH_E_ARG, "bf16_weights is NULL");
+  std::vector<float> w(MLP_NPARAM);
+  for (int k = 0; k < MLP_NPARAM; ++k) {   // a BF16 value is the upper half of an FP32 one
+    const uint32_t b = (uint32_t)bf16_weights[k] << 16;
+    memcpy(&w[k], &b, sizeof(float));
+  }
+  return sph_mlp_set_params(c, w.data());
 }
 
 sph_status sph_mlp_get_params(sph_ctx* c, float* params, int32_t rounded) {

@@ -21,7 +21,8 @@ EXPORTED = ("sph_create", "sph_destroy", "sph_set_params", "sph_build_cells", "s
             "sph_stress_rate", "sph_forces", "sph_step", "sph_sync", "sph_export_neighbours",
             "sph_status_string", "sph_error_particle", "sph_set_timing", "sph_get_timing", "sph_neighbour_stats",
             "sph_mlp_set_params", "sph_mlp_get_params", "sph_mlp_get_norm", "sph_mlp_train", "sph_mlp_grad",
-            "sph_mlp_eval", "sph_mlp_build_trust_mask", "sph_ensemble_set", "sph_autotune")
+            "sph_mlp_eval", "sph_mlp_build_trust_mask", "sph_ensemble_set", "sph_autotune", "sph_mlp_load",
+            "sph_last_error_detail", "sph_eos_table_create")
 MLP_NPARAM = 8642
 
 _dp = ctypes.c_void_p
@@ -66,11 +67,13 @@ class SphState(ctypes.Structure):
 
 
 class SphError(RuntimeError):
-    def __init__(self, code, what, particle=None):
+    def __init__(self, code, what, particle=None, detail=None):
         at = f" (particle {particle})" if particle is not None and particle >= 0 else ""
-        super().__init__(f"{what}: {STATUS.get(code, code)}{at}")
+        why = f" [{detail}]" if detail else ""
+        super().__init__(f"{what}: {STATUS.get(code, code)}{at}{why}")
         self.code = code
         self.particle = particle
+        self.detail = detail
 
 
 _lib = None
@@ -114,13 +117,19 @@ def load():
     L.sph_mlp_build_trust_mask.argtypes = [vp, ctypes.c_double, ctypes.POINTER(ctypes.c_int64)]
     L.sph_ensemble_set.argtypes = [vp, ctypes.c_int32, vp]
     L.sph_autotune.argtypes = [vp, S, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(SphTuneResult)]
+    L.sph_mlp_load.argtypes = [vp, vp]
+    L.sph_last_error_detail.argtypes = [vp]
+    L.sph_last_error_detail.restype = ctypes.c_char_p
+    L.sph_eos_table_create.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double]
     _lib = L
     return L
 
 
-def _check(rc, what):
+def _check(rc, what, h=None):
     if rc != 0:
-        raise SphError(rc, what)
+        d = _lib.sph_last_error_detail(h) if _lib is not None else None
+        raise SphError(rc, what, detail=d.decode() if d else None)
 
 
 # ------------------------------------------------------------------------------------------
@@ -247,26 +256,27 @@ class Context:
 
     # stage calls -----------------------------------------------------------------------------
     def sph_build_cells(self, st: DeviceState):
-        _check(self.lib.sph_build_cells(self.h, ctypes.byref(st.struct)), "sph_build_cells")
+        _check(self.lib.sph_build_cells(self.h, ctypes.byref(st.struct)), "sph_build_cells", self.h)
 
     def sph_density(self, st: DeviceState):
-        _check(self.lib.sph_density(self.h, ctypes.byref(st.struct)), "sph_density")
+        _check(self.lib.sph_density(self.h, ctypes.byref(st.struct)), "sph_density", self.h)
 
     def sph_stress_rate(self, st: DeviceState):
-        _check(self.lib.sph_stress_rate(self.h, ctypes.byref(st.struct)), "sph_stress_rate")
+        _check(self.lib.sph_stress_rate(self.h, ctypes.byref(st.struct)), "sph_stress_rate", self.h)
 
     def sph_forces(self, st: DeviceState):
-        _check(self.lib.sph_forces(self.h, ctypes.byref(st.struct)), "sph_forces")
+        _check(self.lib.sph_forces(self.h, ctypes.byref(st.struct)), "sph_forces", self.h)
 
     def sph_step(self, st: DeviceState, dt: float, nsteps: int):
-        _check(self.lib.sph_step(self.h, ctypes.byref(st.struct), float(dt), int(nsteps)), "sph_step")
+        _check(self.lib.sph_step(self.h, ctypes.byref(st.struct), float(dt), int(nsteps)), "sph_step", self.h)
 
     def sph_sync(self):
         """Waits; raises SphError for a latched device error, with .particle the array index (in
         the current order) of the particle that raised it, or -1."""
         rc = self.lib.sph_sync(self.h)
         if rc != 0:
-            raise SphError(rc, "sph_sync", int(self.lib.sph_error_particle(self.h)))
+            d = self.lib.sph_last_error_detail(self.h)
+            raise SphError(rc, "sph_sync", int(self.lib.sph_error_particle(self.h)), d.decode() if d else None)
 
     def sph_export_neighbours(self, n: int, cap: int = None):
         off = np.zeros(n + 1, np.int64)
@@ -281,7 +291,7 @@ class Context:
         return off, ids[: off[n]].copy()
 
     def sph_set_timing(self, enable: bool):
-        _check(self.lib.sph_set_timing(self.h, int(bool(enable))), "sph_set_timing")
+        _check(self.lib.sph_set_timing(self.h, int(bool(enable))), "sph_set_timing", self.h)
 
     def sph_get_timing(self, stage: str):
         n = ctypes.c_int32()
@@ -292,7 +302,7 @@ class Context:
 
     def sph_neighbour_stats(self):
         s = SphListStats()
-        _check(self.lib.sph_neighbour_stats(self.h, ctypes.byref(s)), "sph_neighbour_stats")
+        _check(self.lib.sph_neighbour_stats(self.h, ctypes.byref(s)), "sph_neighbour_stats", self.h)
         return {k: getattr(s, k) for k in ("pairs", "max_count", "tiles", "union_total", "candidates",
                                            "rebuilds")}
 
@@ -306,25 +316,42 @@ class Context:
         """star_info: [nstars, 5] rows of (centre x, y, z, particle mass, shear factor)."""
         si = np.ascontiguousarray(star_info, np.float64)
         if si.size == 0:
-            _check(self.lib.sph_ensemble_set(self.h, 0, None), "sph_ensemble_set")
+            _check(self.lib.sph_ensemble_set(self.h, 0, None), "sph_ensemble_set", self.h)
             return
         assert si.ndim == 2 and si.shape[1] == 5
-        _check(self.lib.sph_ensemble_set(self.h, si.shape[0], si.ctypes.data), "sph_ensemble_set")
+        _check(self.lib.sph_ensemble_set(self.h, si.shape[0], si.ctypes.data), "sph_ensemble_set", self.h)
 
     # EoS surrogate network ------------------------------------------------------------------
     def mlp_set_params(self, params):
         w = np.ascontiguousarray(params, np.float32)
         assert w.shape == (MLP_NPARAM,)
-        _check(self.lib.sph_mlp_set_params(self.h, w.ctypes.data), "sph_mlp_set_params")
+        _check(self.lib.sph_mlp_set_params(self.h, w.ctypes.data), "sph_mlp_set_params", self.h)
+
+    def mlp_load(self, bf16_bits):
+        """bf16_bits: uint16 array of SPH_MLP_NPARAM BF16 bit patterns."""
+        w = np.ascontiguousarray(bf16_bits, np.uint16)
+        assert w.shape == (MLP_NPARAM,)
+        _check(self.lib.sph_mlp_load(self.h, w.ctypes.data), "sph_mlp_load", self.h)
+
+    def eos_table_create(self, table):
+        """Upload an EosTable into memory the context owns (sph_eos_table_create)."""
+        a = np.ascontiguousarray(table.lnP, np.float64)
+        b = np.ascontiguousarray(table.lncs2, np.float64)
+        _check(self.lib.sph_eos_table_create(self.h, a.ctypes.data, b.ctypes.data, table.nr, table.nu, table.lnr0,
+                                             table.dlnr, table.lnu0, table.dlnu), "sph_eos_table_create", self.h)
+
+    def last_error_detail(self):
+        d = self.lib.sph_last_error_detail(self.h)
+        return d.decode() if d else ""
 
     def mlp_get_params(self, rounded=False):
         w = np.zeros(MLP_NPARAM, np.float32)
-        _check(self.lib.sph_mlp_get_params(self.h, w.ctypes.data, int(bool(rounded))), "sph_mlp_get_params")
+        _check(self.lib.sph_mlp_get_params(self.h, w.ctypes.data, int(bool(rounded))), "sph_mlp_get_params", self.h)
         return w
 
     def mlp_get_norm(self):
         v = np.zeros(8, np.float32)
-        _check(self.lib.sph_mlp_get_norm(self.h, v.ctypes.data), "sph_mlp_get_norm")
+        _check(self.lib.sph_mlp_get_norm(self.h, v.ctypes.data), "sph_mlp_get_norm", self.h)
         return v
 
     def mlp_train(self, samples, n_holdout, epochs, batch=4096, lr=1e-3):
@@ -355,7 +382,7 @@ class Context:
 
     def mlp_build_trust_mask(self, tol=1e-4):
         n = ctypes.c_int64()
-        _check(self.lib.sph_mlp_build_trust_mask(self.h, float(tol), ctypes.byref(n)), "sph_mlp_build_trust_mask")
+        _check(self.lib.sph_mlp_build_trust_mask(self.h, float(tol), ctypes.byref(n)), "sph_mlp_build_trust_mask", self.h)
         return n.value
 
     # convenience ---------------------------------------------------------------------------

@@ -129,3 +129,16 @@ def l2_perturbation(x, y, z, A, Rbar):
     vth = np.where(r > 0, vth, 0.0)
     # e_theta = (cos t cos p, cos t sin p, -sin t)
     return vth * ct * cphi, vth * ct * sphi, -vth * st
+
+
+def random_deviatoric(scale, rng):
+    """Random traceless symmetric tensors (6, n: xx, yy, zz, xy, xz, yz) with von Mises stress
+    sqrt(3/2 S:S) equal to `scale` (an array of n), directions drawn from rng."""
+    scale = np.asarray(scale, np.float64)
+    n = scale.shape[0]
+    A = rng.normal(size=(n, 3, 3))
+    A = 0.5 * (A + np.transpose(A, (0, 2, 1)))
+    A -= np.trace(A, axis1=1, axis2=2)[:, None, None] / 3.0 * np.eye(3)
+    sv = np.sqrt(1.5 * (A * A).sum(axis=(1, 2)))
+    A *= (scale / sv)[:, None, None]
+    return np.stack([A[:, 0, 0], A[:, 1, 1], A[:, 2, 2], A[:, 0, 1], A[:, 0, 2], A[:, 1, 2]])

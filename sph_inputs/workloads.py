@@ -20,7 +20,7 @@ import numpy as np
 from . import eos_table as eos_mod
 from .lattice import cfl_dt, cubic_lattice, gaussian_velocities
 from .params import MethodParams
-from .star import crust_mask, l2_perturbation, place_star, profile_at, radial_perturbation
+from .star import crust_mask, l2_perturbation, place_star, profile_at, radial_perturbation, random_deviatoric
 from .tov import Background, Polytrope, make_background, solve_tov
 
 GAMMA2_K = 83.0233
@@ -90,7 +90,7 @@ def pp_table(nr: int = 1024, nu: int = 1024):
 
 
 def _star_common(bg, N, seed, kernel, eta, l, A, mu_factor, plastic, precision, eos, gamma,
-                 table, steps, name, jitter=0.05):
+                 table, steps, name, jitter=0.05, prestress=None):
     x, y, z, rr, m = place_star(bg, N, seed, jitter)
     rho, P, u, D0 = profile_at(bg, rr)
     D0 = np.maximum(D0, D0[D0 > 0].min() if np.any(D0 > 0) else 1e-12)
@@ -111,6 +111,16 @@ def _star_common(bg, N, seed, kernel, eta, l, A, mu_factor, plastic, precision, 
     else:
         kw.update(y0_mode="CONST", y0_const=1e300, break_mode="OFF")
     p = MethodParams(**kw)
+    arrays = _arrays(x, y, z, vx, vy, vz, u, h, typ)
+    if prestress is not None:
+        # crust particles start with a deviatoric stress whose von Mises value is k P, k drawn
+        # log-uniformly in [lo, hi] (the static pressure P of the profile; seed + 1000)
+        lo, hi = prestress
+        rs = np.random.Generator(np.random.PCG64(seed + 1000))
+        k = np.exp(rs.uniform(math.log(lo), math.log(hi), N))
+        S = random_deviatoric(k * P, rs)
+        S[:, typ == 0] = 0.0
+        arrays["S"] = S
     # Courant step from the static profile: c_L^2 = c_s^2 + 4 mu / (3 rho)
     Pm = np.maximum(P, 1e-300)
     rhom = np.maximum(rho, 1e-300)
@@ -120,16 +130,17 @@ def _star_common(bg, N, seed, kernel, eta, l, A, mu_factor, plastic, precision, 
     cL = np.sqrt(cs2 + np.where(typ == 1, 4.0 * mu_factor * Pm / (3.0 * rhom), 0.0))
     vmag = np.sqrt(vx * vx + vy * vy + vz * vz)
     dt = cfl_dt(h, cL, vmag)
-    return Workload(name, p, _arrays(x, y, z, vx, vy, vz, u, h, typ), dt, steps, bg)
+    return Workload(name, p, arrays, dt, steps, bg)
 
 
 def star(N: int = 200_000, seed: int = 2, kernel: str = "WC2", eta: float = 1.3, l: int = 0,
          A: float = 1e-3, mu_factor: float = 0.01, plastic: bool = False,
-         precision: str = "FP64", steps: int = 100):
-    """Gamma = 2 polytrope star, M = 1.4, R = 12 km, Gamma-law EoS (u = K rho)."""
+         precision: str = "FP64", steps: int = 100, prestress=None):
+    """Gamma = 2 polytrope star, M = 1.4, R = 12 km, Gamma-law EoS (u = K rho).  prestress =
+    (lo, hi): crust particles start with von Mises stress k P, k log-uniform in [lo, hi]."""
     bg = gamma2_background()
     return _star_common(bg, N, seed, kernel, eta, l, A, mu_factor, plastic, precision,
-                        "GAMMA_LAW", 2.0, None, steps, f"star{N}")
+                        "GAMMA_LAW", 2.0, None, steps, f"star{N}", prestress=prestress)
 
 
 def star_2m(N: int = 2_000_000, seed: int = 3, precision: str = "FP32", steps: int = 1000):

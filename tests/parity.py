@@ -7,10 +7,11 @@ import oracle
 FIELDS_EVAL = ("D", "rho", "P", "cs", "ax", "ay", "az", "dudt")
 
 
-def gpu_run(w, steps=0, precision=None, ctx_kw=None, params=None, lists=None):
+def gpu_run(w, steps=0, precision=None, ctx_kw=None, params=None, lists=None, csr_keys=False):
     """Evaluate (and step) on the GPU; returns the state in id order.  With lists (default: only
     when steps == 0) the exact neighbour lists of the last evaluation come back as "_lists" (by
-    id), and the list statistics as "_stats"."""
+    id), and the list statistics as "_stats".  With csr_keys the lists come back instead as
+    "_keys", the sorted array of a * n + b over the ordered pairs (by id), for large n."""
     from paper_2107_07315_amd import sph
     p = params or w.params
     if precision:
@@ -24,14 +25,19 @@ def gpu_run(w, steps=0, precision=None, ctx_kw=None, params=None, lists=None):
         ctx.sph_step(st, w.dt, steps)
     ctx.sph_sync()
     nb = None
-    if lists if lists is not None else steps == 0:
+    if csr_keys or (lists if lists is not None else steps == 0):
         nb = ctx.sph_export_neighbours(w.n)
     stats = ctx.sph_neighbour_stats()
     g = st.numpy()
     order = np.argsort(g["id"])
     out = {k: (v[..., order] if v.ndim == 2 else v[order]) for k, v in g.items()}
     out["_stats"] = stats
-    if nb is not None:
+    if nb is not None and csr_keys:
+        off, ids = nb
+        ident = g["id"].astype(np.int64)
+        rows = np.repeat(ident, np.diff(off))
+        out["_keys"] = np.sort(rows * w.n + ident[ids])
+    elif nb is not None:
         off, ids = nb
         ident = g["id"]
         lst = {}
@@ -56,6 +62,13 @@ def oracle_run(w, steps=0, mode=oracle.GRID, params=None):
 
 def rel_err(a, b, floor=0.0):
     return np.abs(a - b) / np.maximum(np.abs(b), floor)
+
+
+def oracle_keys(o, n):
+    """Sorted a * n + b over the oracle's ordered pairs (its lists are ascending, by id)."""
+    off, ids = o["offsets"], o["ids"]
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(off))
+    return rows * n + ids.astype(np.int64)
 
 
 def check_lists(g, o, n):

@@ -1,7 +1,7 @@
 """GPU tests of ensembles of independent stars in one particle set (per-star mass, crust shear
 factor and background centre) against the oracle, of graph-captured stepping, and of the launch
 autotuner.  Tolerances as in test_gpu_parity: neighbour sets bit-exact, one FP64 evaluation to
-1e-12 (kappa-relative for the cancelling sums), state after steps to 1e-9 of each field's scale,
+1e-12 (kappa-relative for the cancelling sums), state after steps to 1e-12 of each field's scale,
 FP32 pair sums to 1e-4 in D, rho and P."""
 import numpy as np
 import pytest
@@ -53,7 +53,7 @@ def test_ensemble_steps(ens):
     e = field_errors(g, o, ("x", "y", "z", "vx", "vy", "vz", "u", "h", "S", "D", "ax", "dudt", "dSdt"))
     _print("ensemble 5 steps", e)
     for k, v in e.items():
-        assert v < 1e-9, (k, v)
+        assert v < 1e-12, (k, v)
     assert np.array_equal(g["broken"], o["broken"])
 
 
@@ -141,5 +141,5 @@ def test_autotune_then_steps_match_oracle():
     e = field_errors(g, o, ("x", "y", "z", "vx", "vy", "vz", "u", "h", "S", "D", "ax", "dudt", "dSdt"))
     _print("after autotune, 5 steps", e)
     for k, v in e.items():
-        assert v < 1e-9, (k, v)
+        assert v < 1e-12, (k, v)
     assert np.array_equal(g["broken"], o["broken"])
