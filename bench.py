@@ -31,6 +31,12 @@ sys.path.insert(0, ROOT)
 # and results written once (density: FP64 position 32, candidate count 4, D 8, exact counts 8 =
 # 52 B); neighbour records staged through LDS are re-reads served by the caches and are not
 # counted.
+# The survey's algorithmic figures per particle-update (its work-per-pass table: density with its
+# EoS epilogue about 32 FLOP per pair at about 100 pairs, forces with the background epilogue
+# about 63 FLOP per pair plus the crust terms, about 6.5 kFLOP; bytes 104 / 114 per particle in
+# FP64, 80 / 70 in FP32).  `frac` is taken with these; `frac_recount` with the kernel recount above.
+SURVEY_FLOP = {"density": 3200, "forces": 6500}
+SURVEY_BYTES = {("density", "FP64"): 104, ("density", "FP32"): 80, ("forces", "FP64"): 114, ("forces", "FP32"): 70}
 DENS_FLOP = {"candidate": 10, "pair": 20, "particle": 12}
 FORCE_FLOP = {"pair": 73, "particle": 110}
 DENS_BYTES = {"FP64": 52, "FP32": 52, "candidate": 2, "pair": 2}
@@ -202,14 +208,20 @@ def roofline(res, n, precision):
     # carries a run-ahead launch that found the skin test failed and exited at once)
     avg = {k: res["stages"][k]["ms_total"] / res["stage_steps"] for k in passes}
     stage = max(avg, key=avg.get)
-    kernel, flop, nbytes = passes[stage]
+    kernel, flop_rc, nbytes_rc = passes[stage]
     sec = avg[stage] * 1e-3
+    flop = SURVEY_FLOP[stage] * n                 # algorithmic FLOP per launch (survey count)
+    nbytes = SURVEY_BYTES[(stage, precision)] * n
     achieved = flop / sec / 1e12
     peak = PEAK[precision] / 1e12
     return {"kernel": kernel, "bound": "alu", "achieved": round(achieved, 3), "peak": peak,
             "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": measured_traffic(kernel),
+            "flop_per_launch": flop, "flop_per_particle": SURVEY_FLOP[stage],
             "algorithmic_bytes": nbytes, "algorithmic_GBps": round(nbytes / sec / 1e9, 1),
-            "flop_per_launch": flop, "launch_ms": round(avg[stage], 4),
+            "hbm_frac": round(nbytes / sec / 8.0e12, 4),
+            "recount": {"flop_per_launch": flop_rc, "achieved": round(flop_rc / sec / 1e12, 3),
+                        "frac_recount": round(flop_rc / sec / 1e12 / peak, 4), "bytes_per_launch": nbytes_rc},
+            "launch_ms": round(avg[stage], 4),
             "other_pass_ms": {k: round(v, 4) for k, v in avg.items() if k != stage}}
 
 
@@ -223,11 +235,32 @@ def cpu_baseline(w, steps=4):
     t0 = time.perf_counter()
     oracle.step(orc, st, w.dt, steps)
     t1 = time.perf_counter()
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(w.n * steps / (t1 - t0), 1), "unit": "particle-updates/s", "cores": cores,
-            "kind": "oracle", "sample": f"{steps} kick-drift-kick steps (neighbours, density, stress rate, "
+    return {"value": round(w.n * steps / (t1 - t0), 1), "unit": "particle-updates/s",
+            "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{steps} kick-drift-kick steps (neighbours, density, stress rate, "
             f"forces) of the same {w.n}-particle star in FP64 with the table EoS, after one untimed "
             f"evaluation; {t1 - t0:.1f} s"}
+
+
+def cpu_baseline_one_core(n=200_000, steps=2):
+    """The same oracle on one host core, in a child process with OMP_NUM_THREADS=1: `steps` steps
+    of a star of the same construction at n particles (the per-particle work is the same as at 2M,
+    about 100 neighbours each), so that the sample stays near 10-30 s."""
+    import subprocess
+    code = ("import json, sys, time; sys.path.insert(0, %r); import oracle; "
+            "from sph_inputs import workloads as W; w = W.pp_star(%d, seed=3, eos='TABLE'); "
+            "orc = oracle.Oracle(w.params); st = oracle.OracleState(w.arrays); oracle.run_stages(orc, st); "
+            "t0 = time.perf_counter(); oracle.step(orc, st, w.dt, %d); t1 = time.perf_counter(); "
+            "print(json.dumps({'s': t1 - t0, 'threads': oracle.threads()}))" % (ROOT, n, steps))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=900)
+    if r.returncode != 0:
+        return {"error": r.stderr[-400:]}
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    return {"value": round(n * steps / d["s"], 1), "unit": "particle-updates/s", "cores": d["threads"],
+            "kind": "oracle", "sample": f"{steps} kick-drift-kick steps of the {n}-particle piecewise-polytrope "
+            f"star (same construction and neighbour count as the 2M one), FP64, table EoS, one thread; "
+            f"{d['s']:.1f} s"}
 
 
 def main():
@@ -317,6 +350,7 @@ def main():
         out["ensemble"] = run_ensemble(surrogate, args.ensemble_steps, 5)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
+        out["cpu_baseline_one_core"] = cpu_baseline_one_core()
     print(json.dumps(out), flush=True)
 
 

@@ -63,6 +63,10 @@ enum { SPH_Y0_CONST = 0, SPH_Y0_EFACTOR = 1 };
 enum { SPH_BREAK_OFF = 0, SPH_BREAK_ONSET = 1, SPH_BREAK_FLUIDIZE = 2 };
 enum { SPH_ROT_OBJECTIVE = 0, SPH_ROT_LITERAL = 1 };
 enum { SPH_FP64 = 0, SPH_FP32 = 1 };
+enum { SPH_EXT_NONE = 0, SPH_EXT_RADIAL = 1 };
+enum { SPH_DENS_SUMMATION = 0, SPH_DENS_CONTINUITY = 1 };
+enum { SPH_ENERGY_PAPER = 0, SPH_ENERGY_FIRST_LAW = 1 };
+enum { SPH_DTP_OFF = 0, SPH_DTP_LAGGED = 1 };
 
 /* Particle state (section "Solid SPH Equations": per-particle position, velocity, internal
  * energy, deviatoric stress; equal mass per particle, section "Fixed metric background").
@@ -132,6 +136,31 @@ typedef struct {
   int32_t lanes;           /* lanes per target particle in the pair passes: 1, 2 or 4 (0: 4);  */
                            /*   a tile of up to 64 targets is one workgroup of 64 * lanes     */
                            /*   threads, the lanes of a target splitting its list             */
+  /* External effective potential and potential walls (section "Setting up Neutron Stars":
+   * relaxation in phi_eff with g_eff = -grad phi_eff, confined by walls; section "Neutron stars
+   * with a solid crust in SPH": a crust shell held by phi_eff and walls).  With ext =
+   * SPH_EXT_RADIAL the force pass adds g(r) n, r the distance from the star centre (the
+   * isotropic radius with the TOV background), n = x / r, g linear in ext_g[i] on r_i = i ext_dr
+   * (ext_g: device, ext_n entries, positive outward; 0 beyond the last entry), plus the walls
+   * wall_k (wall_in - r) n where r < wall_in and -wall_k (r - wall_out) n where r > wall_out (a
+   * wall radius of 0 means no wall), plus -damping v (a relaxation drag; 0: none).  Walls and
+   * drag also act with ext = SPH_EXT_NONE (e.g. settling a star in the fixed background). */
+  int32_t ext;             /* SPH_EXT_NONE | SPH_EXT_RADIAL                                    */
+  int32_t ext_n;
+  const double* ext_g;
+  double ext_dr, wall_in, wall_out, wall_k, damping;
+  /* Method variants (defaults: the paper's equations as read above). */
+  int32_t density_mode;    /* SUMMATION: D = sum m W; CONTINUITY (eq. solid1): D is state,    */
+                           /*   integrated with dD/dt = sum_b m (v_a - v_b) . grad_a W         */
+  int32_t energy_mode;     /* PAPER: eq. solid3 with D; FIRST_LAW: du/dt = (P/rho^2) drho/dt  */
+                           /*   along the trajectory (rho = D / (psi^6 W_L)), plus the viscous   */
+                           /*   heating and stress work of eq. solid3                           */
+  int32_t dtP_mode;        /* OFF: the dP/dt entry (lambda = 0 row) of the trajectory equation  */
+                           /*   dropped; LAGGED: with dP/dt = (P - P_prev)/dt_prev - v . grad P  */
+  int32_t reserved;
+  double cfl;              /* sph_step with dt <= 0: each step's dt = cfl min_a h_a /           */
+                           /*   (c_L,a + |v_a|), c_L^2 = c_s^2 + 4 mu / (3 rho), from the last    */
+                           /*   evaluation, on the device (0: 0.3)                              */
 } sph_params;
 
 /* Neighbour-list statistics (sph_neighbour_stats). */
@@ -188,8 +217,18 @@ sph_status sph_forces(sph_ctx* ctx, sph_state* st);
  * (section "Solid SPH Equations"), and the adaptive smoothing length.  Within one call the final
  * kick of a step and the kick-drift of the next run as one kernel, so the state between two steps
  * of the call is never written out; on return the state is the end of the last step and the
- * rates are those of its evaluation. */
+ * rates are those of its evaluation, except that a particle broken (FLUIDIZE) in the last step has
+ * its stress and stress rate set to zero. */
 sph_status sph_step(sph_ctx* ctx, sph_state* st, double dt, int32_t nsteps);
+
+/* Modification step after relaxation (section "Setting up Neutron Stars": once the star is relaxed
+ * to the desired density profile, u is assigned from the profile and the real EoS, after which the
+ * star is evolved).  Sets u of every particle to the profile u(r) of the real EoS, u_of_r (device,
+ * nr >= 2 entries on r_i = i dr, linear between entries, the last entry beyond it), r the distance
+ * from the particle's star centre (isotropic radius with the TOV background), and zeroes the
+ * velocities.  Positions and lists are kept; the next stage call must be sph_density (or
+ * sph_build_cells).  Stream-ordered. */
+sph_status sph_modify_energy(sph_ctx* ctx, sph_state* st, const double* u_of_r, int32_t nr, double dr);
 
 /* Ensembles of independent stars in one particle set: star_info (host) holds nstars rows of
  * (centre x, y, z, particle mass, shear factor); each particle's star (state field `star`,
@@ -234,6 +273,7 @@ sph_status sph_export_neighbours(sph_ctx* ctx, int64_t* offsets, int32_t* ids, i
 
 /* Statistics of the current lists (see sph_list_stats).  Waits. */
 sph_status sph_neighbour_stats(sph_ctx* ctx, sph_list_stats* out);
+
 
 /* ---- EoS surrogate network (extension of the tabulated EoS) ---------------------------------
  * The setup section names tabulated equations of state; this extension fits a network

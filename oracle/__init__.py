@@ -49,6 +49,10 @@ class OrcParams(ctypes.Structure):
         ("break_mode", ctypes.c_int32), ("eps_break", ctypes.c_double),
         ("rotation", ctypes.c_int32),
         ("nstars", ctypes.c_int32), ("star_info", _dp),
+        ("ext", ctypes.c_int32), ("ext_n", ctypes.c_int32), ("ext_g", _dp), ("ext_dr", ctypes.c_double),
+        ("wall_in", ctypes.c_double), ("wall_out", ctypes.c_double), ("wall_k", ctypes.c_double),
+        ("damping", ctypes.c_double), ("density_mode", ctypes.c_int32), ("energy_mode", ctypes.c_int32),
+        ("dtP_mode", ctypes.c_int32), ("cfl", ctypes.c_double),
     ]
 
 
@@ -111,8 +115,8 @@ class Oracle:
     def __init__(self, params, star_info=None):
         """star_info: optional [nstars, 5] array of (centre x, y, z, particle mass, shear factor)
         for an ensemble of stars (the state then carries each particle's star)."""
-        from sph_inputs.params import (BACKGROUNDS, BREAK_MODES, H_MODES, KERNELS,
-                                                        MU_MODES, ROTATIONS, Y0_MODES, YIELD_MODES)
+        from sph_inputs.params import (BACKGROUNDS, BREAK_MODES, DENSITY_MODES, DTP_MODES, ENERGY_MODES,
+                                       H_MODES, KERNELS, MU_MODES, ROTATIONS, Y0_MODES, YIELD_MODES)
         self.params = params
         p = OrcParams()
         p.kernel = KERNELS[params.kernel]
@@ -145,6 +149,15 @@ class Oracle:
         p.break_mode = BREAK_MODES[params.break_mode]
         p.eps_break = params.eps_break
         p.rotation = ROTATIONS[params.rotation]
+        if params.ext_table is not None:
+            eg = np.ascontiguousarray(params.ext_table, dtype=np.float64)
+            self._keep.append(eg)
+            p.ext, p.ext_g, p.ext_n, p.ext_dr = 1, _ptr(eg), eg.shape[0], params.ext_dr
+        p.wall_in, p.wall_out, p.wall_k, p.damping = params.wall_in, params.wall_out, params.wall_k, params.damping
+        p.density_mode = DENSITY_MODES[params.density_mode]
+        p.energy_mode = ENERGY_MODES[params.energy_mode]
+        p.dtP_mode = DTP_MODES[params.dtP_mode]
+        p.cfl = params.cfl
         if star_info is not None:
             si = np.ascontiguousarray(star_info, dtype=np.float64)
             assert si.ndim == 2 and si.shape[1] == 5
@@ -217,6 +230,24 @@ def run_stages(orc: Oracle, st: OracleState, mode=GRID, want_kappa=False):
     ku = np.zeros(st.n) if want_kappa else None
     _check(L.orc_forces(ctypes.byref(orc.p), ctypes.byref(s), o64, i32, _ptr(ka), _ptr(ku)), "orc_forces")
     return dict(offsets=off, ids=ids, kappa_G=kG, kappa_a=ka, kappa_u=ku)
+
+
+def modify_energy(orc: Oracle, st: OracleState, u_of_r, dr: float):
+    """Modification step: u from the profile u(r) (table on r_i = i dr), velocities zeroed."""
+    L = lib()
+    L.orc_modify_energy.argtypes = [ctypes.POINTER(OrcParams), ctypes.POINTER(OrcState), _dp, ctypes.c_int32,
+                                    ctypes.c_double]
+    L.orc_modify_energy.restype = None
+    t = np.ascontiguousarray(u_of_r, np.float64)
+    s = st.struct()
+    L.orc_modify_energy(ctypes.byref(orc.p), ctypes.byref(s), _ptr(t), t.shape[0], float(dr))
+
+
+def threads():
+    """OpenMP threads the oracle's parallel loops use."""
+    L = lib()
+    L.orc_threads.restype = ctypes.c_int32
+    return int(L.orc_threads())
 
 
 def step(orc: Oracle, st: OracleState, dt: float, nsteps: int, mode=GRID):

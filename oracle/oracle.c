@@ -563,6 +563,40 @@ static pairsum_t pair_sums(const orc_params* p, const orc_state* st, int64_t a, 
   return o;
 }
 
+/* External effective potential of the setup section (g_eff = -grad phi_eff, tabulated as g(r)
+ * along the radius from the star centre, linear between entries, 0 beyond the last), harmonic
+ * potential walls at wall_in / wall_out and a velocity drag; returns the summed magnitudes of the
+ * added terms (for the summation bound). */
+static double ext_accel(const orc_params* p, const orc_state* st, int64_t a, double acc[3]) {
+  double c[3];
+  pcentre(p, st, a, c);
+  double X[3] = {st->x[a] - c[0], st->y[a] - c[1], st->z[a] - c[2]};
+  double r = sqrt(X[0] * X[0] + X[1] * X[1] + X[2] * X[2]);
+  double kap = 0.0;
+  if (r > 0.0) {
+    double g = 0.0;
+    double t = p->ext == ORC_EXT_RADIAL ? r / p->ext_dr : 1e300;
+    if (t <= (double)(p->ext_n - 1)) {
+      int64_t i = (int64_t)floor(t);
+      if (i > p->ext_n - 2) i = p->ext_n - 2;
+      double f = t - (double)i;
+      g = (1.0 - f) * p->ext_g[i] + f * p->ext_g[i + 1];
+    }
+    if (p->wall_in > 0.0 && r < p->wall_in) g += p->wall_k * (p->wall_in - r);
+    if (p->wall_out > 0.0 && r > p->wall_out) g -= p->wall_k * (r - p->wall_out);
+    for (int k = 0; k < 3; ++k) acc[k] += g * X[k] / r;
+    kap += fabs(g);
+  }
+  if (p->damping > 0.0) {
+    double v[3] = {st->vx[a], st->vy[a], st->vz[a]};
+    for (int k = 0; k < 3; ++k) {
+      acc[k] -= p->damping * v[k];
+      kap += p->damping * fabs(v[k]);
+    }
+  }
+  return kap;
+}
+
 int orc_forces(const orc_params* p, orc_state* st, const int64_t* off, const int32_t* ids,
                double* kappa_a, double* kappa_u) {
   int64_t n = st->n;
@@ -597,6 +631,7 @@ int orc_forces(const orc_params* p, orc_state* st, const int64_t* off, const int
       for (int i = 0; i < 3; ++i) acc[i] = -o.AP[i] + o.AS[i];   /* eq. solid2 */
       kap = o.kP + o.kS;
     }
+    kap += ext_accel(p, st, a, acc);
     st->ax[a] = acc[0];
     st->ay[a] = acc[1];
     st->az[a] = acc[2];
@@ -674,6 +709,14 @@ void orc_lambda_max(int64_t n, const double* s6, double* out) {
 /* ------------------------------------------------------------------------------------ */
 /* evaluation and time integration                                                       */
 
+int32_t orc_threads(void) {
+#ifdef _OPENMP
+  return (int32_t)omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 int orc_evaluate(const orc_params* p, orc_state* st, int32_t ngb_mode) {
   int64_t n = st->n;
   int64_t* off = (int64_t*)malloc(((size_t)n + 1) * sizeof(int64_t));
@@ -716,8 +759,13 @@ static void apply_breaking(const orc_params* p, orc_state* st) {
                            st->S[4 * n + a], st->S[5 * n + a]);
     if (lm / E >= p->eps_break) {
       st->broken[a] = 1;
+      /* FLUIDIZE: no deviatoric stress from here on; the stress rate of the last evaluation is
+       * dropped with it, so that the next step's half kick does not rebuild a stress */
       if (p->break_mode == ORC_BREAK_FLUIDIZE)
-        for (int k = 0; k < 6; ++k) st->S[k * n + a] = 0.0;
+        for (int k = 0; k < 6; ++k) {
+          st->S[k * n + a] = 0.0;
+          st->dSdt[k * n + a] = 0.0;
+        }
     }
   }
 }
@@ -879,4 +927,29 @@ double orc_mlp_loss_grad(const double* w, int64_t n, const double* x, const doub
     }
   }
   return loss;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* modification step after relaxation                                                    */
+
+/* u of each particle from the profile u(r) of the real EoS (table on r_i = i dr, linear, the
+ * last entry beyond it), r the distance from the particle's star centre; velocities zeroed. */
+void orc_modify_energy(const orc_params* p, orc_state* st, const double* u_of_r, int32_t nr, double dr) {
+  for (int64_t a = 0; a < st->n; ++a) {
+    double c[3];
+    pcentre(p, st, a, c);
+    double X[3] = {st->x[a] - c[0], st->y[a] - c[1], st->z[a] - c[2]};
+    double r = sqrt(X[0] * X[0] + X[1] * X[1] + X[2] * X[2]);
+    double t = r / dr;
+    double u;
+    if (t >= (double)(nr - 1)) {
+      u = u_of_r[nr - 1];
+    } else {
+      int64_t i = (int64_t)floor(t);
+      double f = t - (double)i;
+      u = (1.0 - f) * u_of_r[i] + f * u_of_r[i + 1];
+    }
+    st->u[a] = u;
+    st->vx[a] = st->vy[a] = st->vz[a] = 0.0;
+  }
 }

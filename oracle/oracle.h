@@ -39,6 +39,10 @@ enum { ORC_Y0_CONST = 0, ORC_Y0_EFACTOR = 1 };
 enum { ORC_BREAK_OFF = 0, ORC_BREAK_ONSET = 1, ORC_BREAK_FLUIDIZE = 2 };
 enum { ORC_ROT_OBJECTIVE = 0, ORC_ROT_LITERAL = 1 };
 enum { ORC_NGB_BRUTE = 0, ORC_NGB_GRID = 1 };
+enum { ORC_EXT_NONE = 0, ORC_EXT_RADIAL = 1 };
+enum { ORC_DENS_SUMMATION = 0, ORC_DENS_CONTINUITY = 1 };
+enum { ORC_ENERGY_PAPER = 0, ORC_ENERGY_FIRST_LAW = 1 };
+enum { ORC_DTP_OFF = 0, ORC_DTP_LAGGED = 1 };
 
 typedef struct {
   int32_t kernel, h_mode, background, periodic;
@@ -62,6 +66,14 @@ typedef struct {
    * background is evaluated about each particle's star centre */
   int32_t nstars;
   const double* star_info;
+  /* external radial acceleration g(r) n (table ext_g on r_i = i ext_dr, linear, 0 beyond), walls
+   * and drag: see orc_forces */
+  int32_t ext; int32_t ext_n; const double* ext_g;
+  double ext_dr, wall_in, wall_out, wall_k, damping;
+  /* method variants: density by continuity (eq. solid1), first-law energy equation, the dP/dt
+   * row of the trajectory equation, adaptive time step */
+  int32_t density_mode, energy_mode, dtP_mode;
+  double cfl;
 } orc_params;
 
 typedef struct {
@@ -116,6 +128,15 @@ void orc_yield(const orc_params* p, int64_t n, double* S, const double* Y0);
 /* nsteps kick-drift-kick steps of size dt.  On entry the rates (ax..dSdt) and the per-particle
  * Y0/B/mu must hold a full evaluation at the current state. */
 int orc_step(const orc_params* p, orc_state* st, double dt, int32_t nsteps, int32_t ngb_mode);
+
+/* Modification step after relaxation (section "Setting up Neutron Stars"): u of every particle
+ * from the real EoS's profile u(r) (u_of_r on r_i = i dr, linear, the last entry beyond), r the
+ * distance from the star centre; velocities set to zero.
+ * Pinned by: a linear profile, reproduced exactly at every radius. */
+void orc_modify_energy(const orc_params* p, orc_state* st, const double* u_of_r, int32_t nr, double dr);
+
+/* OpenMP threads of the parallel loops (1 without OpenMP). */
+int32_t orc_threads(void);
 
 /* One full evaluation: neighbours, density, stress rate, forces. */
 int orc_evaluate(const orc_params* p, orc_state* st, int32_t ngb_mode);

@@ -57,6 +57,19 @@ sph_status check_params(sph_ctx* c, const sph_params* p) {
   if (p->graph < 0 || p->graph > 1) return note(c, SPH_E_ARG, "graph = %d is not 0 or 1", p->graph);
   if (p->lanes != 0 && p->lanes != 1 && p->lanes != 2 && p->lanes != 4)
     return note(c, SPH_E_ARG, "lanes = %d is not 0, 1, 2 or 4", p->lanes);
+  if (p->ext != SPH_EXT_NONE && p->ext != SPH_EXT_RADIAL) return note(c, SPH_E_ARG, "ext = %d", p->ext);
+  if (p->ext == SPH_EXT_RADIAL && (!p->ext_g || p->ext_n < 2 || !(p->ext_dr > 0.0)))
+    return note(c, SPH_E_ARG, "ext RADIAL needs ext_g (device), ext_n >= 2 and ext_dr > 0");
+  if (!(p->wall_in >= 0.0) || !(p->wall_out >= 0.0) || !(p->wall_k >= 0.0) || !(p->damping >= 0.0))
+    return note(c, SPH_E_ARG, "wall radii, wall_k and damping must not be negative");
+  if (p->density_mode != SPH_DENS_SUMMATION && p->density_mode != SPH_DENS_CONTINUITY)
+    return note(c, SPH_E_ARG, "density_mode = %d", p->density_mode);
+  if (p->energy_mode != SPH_ENERGY_PAPER && p->energy_mode != SPH_ENERGY_FIRST_LAW)
+    return note(c, SPH_E_ARG, "energy_mode = %d", p->energy_mode);
+  if (p->dtP_mode != SPH_DTP_OFF && p->dtP_mode != SPH_DTP_LAGGED) return note(c, SPH_E_ARG, "dtP_mode = %d", p->dtP_mode);
+  if (!(p->cfl >= 0.0) || p->cfl > 1.0) return note(c, SPH_E_ARG, "cfl = %g outside [0, 1]", p->cfl);
+  if (p->density_mode != SPH_DENS_SUMMATION || p->energy_mode != SPH_ENERGY_PAPER || p->dtP_mode != SPH_DTP_OFF)
+    return note(c, SPH_E_ARG, "the continuity density, first-law energy and dP/dt variants are not built yet");
   return SPH_OK;
 }
 
@@ -723,6 +736,17 @@ sph_status sph_sync(sph_ctx* c) {
 }
 
 const char* sph_last_error_detail(const sph_ctx* c) { return c ? c->detail : g_detail; }
+
+sph_status sph_modify_energy(sph_ctx* c, sph_state* st, const double* u_of_r, int32_t nr, double dr) {
+  sph_status e = check_state(c, st);
+  if (e) return e;
+  if (!u_of_r || nr < 2 || !(dr > 0.0)) return note(c, SPH_E_ARG, "u_of_r (device) needs nr >= 2 and dr > 0");
+  if (st->n == 0) return SPH_OK;
+  if ((e = sync_positions(c, st))) return e;
+  if ((e = launch_modify_energy(c, st, u_of_r, nr, dr))) return e;
+  if (c->gen > 1) c->gen = 1;   // u changed: the evaluation starts again at the density pass
+  return SPH_OK;
+}
 
 sph_status sph_eos_table_create(sph_ctx* c, const double* lnP, const double* lncs2, int32_t nr, int32_t nu,
                                 double lnr0, double dlnr, double lnu0, double dlnu) {

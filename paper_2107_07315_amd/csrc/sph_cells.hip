@@ -1091,3 +1091,4 @@ sph_status sph_count_stats(sph_ctx* c, sph_list_stats* out) {
   }
   return e;
 }
+

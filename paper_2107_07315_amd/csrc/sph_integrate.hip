@@ -16,7 +16,7 @@ struct KdkArgs {
   double* vx; double* vy; double* vz;
   double* u; double* h; double* S;
   const double* ax; const double* ay; const double* az;
-  const double* dudt; const double* dSdt;
+  const double* dudt; double* dSdt;
   uint8_t* broken; const int8_t* type;
   const double* D; const double* mu; const double* B; const double* Y0;
   double* half;
@@ -131,8 +131,13 @@ __device__ __forceinline__ void final_kick_of(const KdkArgs& K, int64_t a, doubl
       const double lm = lambda_max_sym(s[0], s[1], s[2], s[3], s[4], s[5]);
       if (lm / E >= K.p.eps_break) {
         K.broken[a] = 1;
+        // FLUIDIZE: no deviatoric stress from here on; the stress rate of the last evaluation
+        // goes with it, so that the next half kick does not rebuild a stress
         if (K.p.break_mode == SPH_BREAK_FLUIDIZE)
-          for (int c = 0; c < 6; ++c) s[c] = 0.0;
+          for (int c = 0; c < 6; ++c) {
+            s[c] = 0.0;
+            K.dSdt[c * n + a] = 0.0;
+          }
       }
     }
   }
@@ -236,7 +241,47 @@ __global__ __launch_bounds__(kB) void k_unpack_pos(const double4* __restrict__ p
 }
 
 __global__ void k_flag_clear(uint32_t* f) { *f = 0u; }   // a kernel, not a memset: graph-safe
+
+// Modification step: u from the profile u(r) of the real EoS at the particle's distance from its
+// star centre (linear in the table, its last entry beyond it), velocity zeroed.
+__global__ __launch_bounds__(kB) void k_modify_energy(const double* __restrict__ x, const double* __restrict__ y,
+                                                      const double* __restrict__ z, int64_t n,
+                                                      const int32_t* __restrict__ star,
+                                                      const StarInfo* __restrict__ stars,
+                                                      const double* __restrict__ u_of_r, int32_t nr, double dr,
+                                                      double* __restrict__ u, double* __restrict__ vx,
+                                                      double* __restrict__ vy, double* __restrict__ vz) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  double cx = 0.0, cy = 0.0, cz = 0.0;
+  if (star && stars) {
+    const StarInfo si = stars[star[a]];
+    cx = si.cx; cy = si.cy; cz = si.cz;
+  }
+  const double X = x[a] - cx, Y = y[a] - cy, Z = z[a] - cz;
+  const double r = sqrt(X * X + Y * Y + Z * Z);
+  const double t = r / dr;
+  double v;
+  if (t >= (double)(nr - 1)) {
+    v = u_of_r[nr - 1];
+  } else {
+    const int i = (int)floor(t);
+    const double f = t - (double)i;
+    v = (1.0 - f) * u_of_r[i] + f * u_of_r[i + 1];
+  }
+  u[a] = v;
+  vx[a] = 0.0;
+  vy[a] = 0.0;
+  vz[a] = 0.0;
+}
 }  // namespace
+
+sph_status launch_modify_energy(sph_ctx* c, sph_state* st, const double* u_of_r, int32_t nr, double dr) {
+  hipLaunchKernelGGL(k_modify_energy, dim3(grid_for(st->n, kB)), dim3(kB), 0, c->stream, st->x, st->y, st->z, st->n,
+                     c->stars ? st->star : nullptr, c->stars, u_of_r, nr, dr, st->u, st->vx, st->vy, st->vz);
+  HIP_TRY(hipGetLastError());
+  return SPH_OK;
+}
 
 sph_status launch_flag_clear(sph_ctx* c) {
   hipLaunchKernelGGL(k_flag_clear, dim3(1), dim3(1), 0, c->stream, c->drift_flag);

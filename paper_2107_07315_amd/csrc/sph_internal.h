@@ -404,6 +404,7 @@ sph_status launch_kick_final_drift(sph_ctx* c, sph_state* st, double dt, uint32_
 // st->x, y, z, h from pos4 (after deferred kicks)
 sph_status launch_unpack_pos(sph_ctx* c, sph_state* st);
 sph_status launch_pack(sph_ctx* c, sph_state* st);
+sph_status launch_modify_energy(sph_ctx* c, sph_state* st, const double* u_of_r, int32_t nr, double dr);
 sph_status sph_count_stats(sph_ctx* c, sph_list_stats* out);
 sph_status sph_scan_u32(sph_ctx* c, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total);
 struct MlpView;

@@ -707,7 +707,41 @@ __global__ __launch_bounds__(64 * L) void k_stress(PassArgs A, const typename Re
 // ---- forces -----------------------------------------------------------------------------------
 struct ForceOut {
   double *ax, *ay, *az, *dudt;
+  const double4* pos64;                  // FP64 positions (external potential)
+  const double *vx, *vy, *vz;            // velocities of the evaluation (drag)
 };
+
+// External effective potential (g_eff = -grad phi_eff along the radius from the star centre,
+// linear in the table, 0 beyond its last entry), harmonic potential walls and the relaxation drag,
+// added to the acceleration of particle a.
+__device__ __forceinline__ void ext_accel(const PassArgs& A, const ForceOut& O, int64_t a, double acc[3]) {
+  const sph_params& p = A.p;
+  double cx, cy, cz;
+  star_centre(A, a, cx, cy, cz);
+  const double4 q = O.pos64[a];
+  const double X[3] = {q.x - cx, q.y - cy, q.z - cz};
+  const double r = sqrt(X[0] * X[0] + X[1] * X[1] + X[2] * X[2]);
+  if (r > 0.0) {
+    double g = 0.0;
+    const double t = p.ext == SPH_EXT_RADIAL ? r / p.ext_dr : 1e300;
+    if (t <= (double)(p.ext_n - 1)) {
+      int i = (int)floor(t);
+      i = i > p.ext_n - 2 ? p.ext_n - 2 : i;
+      const double f = t - (double)i;
+      g = (1.0 - f) * p.ext_g[i] + f * p.ext_g[i + 1];
+    }
+    if (p.wall_in > 0.0 && r < p.wall_in) g += p.wall_k * (p.wall_in - r);
+    if (p.wall_out > 0.0 && r > p.wall_out) g -= p.wall_k * (r - p.wall_out);
+    const double gr = g / r;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) acc[k] += gr * X[k];
+  }
+  if (p.damping > 0.0) {
+    acc[0] -= p.damping * O.vx[a];
+    acc[1] -= p.damping * O.vy[a];
+    acc[2] -= p.damping * O.vz[a];
+  }
+}
 
 // Lane g of the L-wave workgroup walks the exact slot list (g / L, g % L); the partial sums of a
 // target's L lanes are added before the fixed-background epilogue.
@@ -836,6 +870,7 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
 #pragma unroll
     for (int i = 0; i < 3; ++i) acc[i] = -APd[i] + ASd[i];   // eq. solid2
   }
+  if (p.ext == SPH_EXT_RADIAL || p.wall_in > 0.0 || p.wall_out > 0.0 || p.damping > 0.0) ext_accel(A, O, a, acc);
   const double du = m * (double)ud + sdot[a];                  // eq. solid3
   O.ax[a] = acc[0];
   O.ay[a] = acc[1];
@@ -973,7 +1008,7 @@ sph_status launch_stress(sph_ctx* c, sph_state* st) {
 
 sph_status launch_forces(sph_ctx* c, sph_state* st) {
   PassArgs A = make_args(c, st);
-  ForceOut O{st->ax, st->ay, st->az, st->dudt};
+  ForceOut O{st->ax, st->ay, st->az, st->dudt, c->pos4, st->vx, st->vy, st->vz};
   const dim3 g = pass_grid(c);
   dispatch_cfg(c->p.kernel, c->p.periodic, [&](auto K, auto P) {
     dispatch_lanes(pass_lanes(c->p), [&](auto LL) {

@@ -22,7 +22,7 @@ EXPORTED = ("sph_create", "sph_destroy", "sph_set_params", "sph_build_cells", "s
             "sph_status_string", "sph_error_particle", "sph_set_timing", "sph_get_timing", "sph_neighbour_stats",
             "sph_mlp_set_params", "sph_mlp_get_params", "sph_mlp_get_norm", "sph_mlp_train", "sph_mlp_grad",
             "sph_mlp_eval", "sph_mlp_build_trust_mask", "sph_ensemble_set", "sph_autotune", "sph_mlp_load",
-            "sph_last_error_detail", "sph_eos_table_create")
+            "sph_last_error_detail", "sph_eos_table_create", "sph_modify_energy")
 MLP_NPARAM = 8642
 
 _dp = ctypes.c_void_p
@@ -44,6 +44,10 @@ class SphParams(ctypes.Structure):
         ("max_neighbours", ctypes.c_int32), ("cell_div", ctypes.c_int32),
         ("tile_cut", ctypes.c_double), ("skin", ctypes.c_double),
         ("pass_blocks", ctypes.c_int32), ("graph", ctypes.c_int32), ("lanes", ctypes.c_int32),
+        ("ext", ctypes.c_int32), ("ext_n", ctypes.c_int32), ("ext_g", _dp), ("ext_dr", ctypes.c_double),
+        ("wall_in", ctypes.c_double), ("wall_out", ctypes.c_double), ("wall_k", ctypes.c_double),
+        ("damping", ctypes.c_double), ("density_mode", ctypes.c_int32), ("energy_mode", ctypes.c_int32),
+        ("dtP_mode", ctypes.c_int32), ("reserved", ctypes.c_int32), ("cfl", ctypes.c_double),
     ]
 
 
@@ -118,6 +122,7 @@ def load():
     L.sph_ensemble_set.argtypes = [vp, ctypes.c_int32, vp]
     L.sph_autotune.argtypes = [vp, S, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(SphTuneResult)]
     L.sph_mlp_load.argtypes = [vp, vp]
+    L.sph_modify_energy.argtypes = [vp, S, vp, ctypes.c_int32, ctypes.c_double]
     L.sph_last_error_detail.argtypes = [vp]
     L.sph_last_error_detail.restype = ctypes.c_char_p
     L.sph_eos_table_create.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
@@ -192,8 +197,9 @@ class Context:
     def __init__(self, params, capacity: int, stream=None, max_neighbours=0, cell_div=0, tile_cut=0.0,
                  skin=None, pass_blocks=0, graph=False, lanes=0):
         import torch
-        from sph_inputs.params import (BACKGROUNDS, BREAK_MODES, EOS_KINDS, H_MODES, KERNELS, MU_MODES,
-                                       PRECISIONS, ROTATIONS, Y0_MODES, YIELD_MODES)
+        from sph_inputs.params import (BACKGROUNDS, BREAK_MODES, DENSITY_MODES, DTP_MODES, ENERGY_MODES,
+                                       EOS_KINDS, H_MODES, KERNELS, MU_MODES, PRECISIONS, ROTATIONS, Y0_MODES,
+                                       YIELD_MODES)
         L = load()
         if not torch.cuda.is_available():
             raise RuntimeError("libsph needs a GPU: torch.cuda.is_available() is False")
@@ -236,6 +242,15 @@ class Context:
         p.pass_blocks = int(pass_blocks)
         p.graph = int(bool(graph))
         p.lanes = int(lanes)
+        if params.ext_table is not None:
+            eg = torch.as_tensor(np.ascontiguousarray(params.ext_table, np.float64), device="cuda")
+            self._keep.append(eg)
+            p.ext, p.ext_g, p.ext_n, p.ext_dr = 1, eg.data_ptr(), eg.shape[0], params.ext_dr
+        p.wall_in, p.wall_out, p.wall_k, p.damping = params.wall_in, params.wall_out, params.wall_k, params.damping
+        p.density_mode = DENSITY_MODES[params.density_mode]
+        p.energy_mode = ENERGY_MODES[params.energy_mode]
+        p.dtP_mode = DTP_MODES[params.dtP_mode]
+        p.cfl = params.cfl
         self.p = p
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = ctypes.c_void_p()
@@ -289,6 +304,14 @@ class Context:
             rc = self.lib.sph_export_neighbours(self.h, off.ctypes.data, ids.ctypes.data, cap)
         _check(rc, "sph_export_neighbours")
         return off, ids[: off[n]].copy()
+
+    def sph_modify_energy(self, st: DeviceState, u_of_r, dr: float):
+        """Modification step: u from the profile u(r) (device tensor or array on r_i = i dr)."""
+        import torch
+        t = torch.as_tensor(np.ascontiguousarray(u_of_r, np.float64), device="cuda")
+        self._keep.append(t)
+        _check(self.lib.sph_modify_energy(self.h, ctypes.byref(st.struct), t.data_ptr(), t.shape[0], float(dr)),
+               "sph_modify_energy", self.h)
 
     def sph_set_timing(self, enable: bool):
         _check(self.lib.sph_set_timing(self.h, int(bool(enable))), "sph_set_timing", self.h)

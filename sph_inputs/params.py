@@ -22,6 +22,9 @@ Y0_MODES = {"CONST": 0, "E_FACTOR": 1}
 BREAK_MODES = {"OFF": 0, "ONSET": 1, "FLUIDIZE": 2}
 ROTATIONS = {"OBJECTIVE": 0, "LITERAL": 1}
 PRECISIONS = {"FP64": 0, "FP32": 1}
+DENSITY_MODES = {"SUMMATION": 0, "CONTINUITY": 1}
+ENERGY_MODES = {"PAPER": 0, "FIRST_LAW": 1}
+DTP_MODES = {"OFF": 0, "LAGGED": 1}
 
 
 @dataclasses.dataclass
@@ -73,6 +76,18 @@ class MethodParams:
     eps_break: float = 0.1
     rotation: str = "OBJECTIVE"
     precision: str = "FP64"
+    # external radial acceleration table g(r_i), r_i = i * ext_dr (None: no external potential),
+    # harmonic walls (radius 0: none) and a velocity drag, for relaxation and the crust shell
+    ext_table: Optional[np.ndarray] = None
+    ext_dr: float = 0.0
+    wall_in: float = 0.0
+    wall_out: float = 0.0
+    wall_k: float = 0.0
+    damping: float = 0.0
+    density_mode: str = "SUMMATION"
+    energy_mode: str = "PAPER"
+    dtP_mode: str = "OFF"
+    cfl: float = 0.3
 
     def replace(self, **kw) -> "MethodParams":
         return dataclasses.replace(self, **kw)

@@ -39,6 +39,7 @@ class Workload:
     bg: Optional[Background] = None
     star_offsets: Optional[np.ndarray] = None      # ensembles: particle ranges per star
     star_params: Optional[np.ndarray] = None       # ensembles: (nstars, 2) = m, mu factor
+    extra: Optional[dict] = None                   # workload-specific set-up data
 
     @property
     def n(self):
@@ -212,3 +213,48 @@ def ensemble(nstars: int = 64, total: int = 8_000_000, seed: int = 5, nmin: int 
     return Workload(f"ensemble{nstars}", stars[0].params, arrays, dt, steps, bg,
                     star_offsets=np.concatenate([[0], np.cumsum(sizes)]),
                     star_params=np.asarray(info, np.float64))
+
+
+GAMMA_RELAX = 1.01
+
+
+def relax_star(N: int = 20_000, seed: int = 6, kind: str = "gamma2", kernel: str = "WC4", eta: float = ETA_100,
+               cs_relax: float = 0.15, perturb: float = 0.1, damping_per_crossing: float = 4.0):
+    """The relaxation workload of the setup section: icosahedral shells with a seeded position
+    perturbation, a Gamma = 1.01 law whose sound speed is about cs_relax everywhere
+    (K = cs_relax^2 / Gamma, u = K D0^(Gamma - 1) / (Gamma - 1) from the target profile at each
+    particle's radius), the effective potential of the target computational density D0(rbar) of
+    the static star (kind "gamma2" or "pp"), a potential wall at the star's isotropic radius and a
+    velocity drag of damping_per_crossing per sound crossing time; Newtonian, fluid (no crust
+    stress while relaxing).  The returned Workload carries in `extra` the profile u(rbar) of the
+    real EoS for the modification step, the real star's parameters (`star_params`: the
+    MethodParams of the evolution in the fixed background) and the crust types."""
+    from .relax import icosahedral_star, phi_eff_table
+    bg = gamma2_background() if kind == "gamma2" else pp_background()
+    x, y, z, m = icosahedral_star(bg, N, seed, perturb)
+    n = x.shape[0]
+    rb = np.sqrt(x * x + y * y + z * z)
+    D0 = np.interp(rb, bg.rbar, bg.D0)
+    D0 = np.maximum(D0, 1e-3 * float(bg.D0[0]))
+    G = GAMMA_RELAX
+    K = cs_relax**2 / G
+    u = K * D0 ** (G - 1.0) / (G - 1.0)
+    h = eta * (m / D0) ** (1.0 / 3.0)
+    g = phi_eff_table(bg.rbar, bg.D0, K, G)
+    crossing = bg.Rbar / cs_relax
+    params = MethodParams(m=m, kernel=kernel, h_mode="ADAPTIVE", eta=eta, background="NEWTONIAN", eos="GAMMA_LAW",
+                          gamma=G, mu_mode="CONST", mu_const=0.0, ext_table=g, ext_dr=bg.drbar, wall_out=bg.Rbar,
+                          wall_k=(4.0 * cs_relax / float(np.min(h))) ** 2, damping=damping_per_crossing / crossing)
+    typ = crust_mask(bg, rb).astype(np.int8)
+    arrays = _arrays(x, y, z, np.zeros(n), np.zeros(n), np.zeros(n), u, h, np.zeros(n))
+    dt = cfl_dt(h, np.full(n, math.sqrt(G * K * float(D0.max()) ** (G - 1.0))), np.zeros(n))
+    # the wall's own oscillation sqrt(wall_k) must be resolved too
+    dt = min(dt, 0.3 / math.sqrt(params.wall_k))
+    w = Workload(f"relax{n}", params, arrays, dt, 0, bg)
+    if kind == "gamma2":
+        real = star(n, seed, kernel, eta, 0, 0.0)
+    else:
+        real = pp_star(n, seed)
+    w.extra = {"u_profile": np.ascontiguousarray(bg.u), "u_dr": bg.drbar, "type": typ,
+               "star_params": real.params.replace(m=m), "crossing": crossing}
+    return w

@@ -107,3 +107,32 @@ def field_errors(g, o, keys):
         a, b = g[k], o[k]
         e[k] = float(np.max(np.abs(a - b)) / max(float(np.max(np.abs(b))), 1e-300))
     return e
+
+
+def step_errors(g, o, keys, dt, steps):
+    """Per-field worst error of the state after `steps` time steps of size dt.  Pointwise fields
+    (positions, h, u, D, S) are compared relative to the field's largest magnitude.  Sums with
+    cancellation are compared against their summation bound, as in one evaluation (R14): the
+    accelerations against max kappa_a, du/dt against max kappa_u, dS/dt against the scale of its
+    terms.  Velocities integrate the accelerations, so their error is measured against
+    max |v| + steps dt max kappa_a (roundoff of the summed terms, carried through the kicks).
+    The kappas are those of the oracle's evaluation at t = 0 (a few steps change them little)."""
+    ka = float(np.max(o["kappa_a"]))
+    ku = float(np.max(o["kappa_u"]))
+    e = {}
+    for k in keys:
+        a, b = g[k], o[k]
+        if k in ("ax", "ay", "az"):
+            sc = ka
+        elif k == "dudt":
+            sc = ku
+        elif k == "dSdt":
+            kG = o["kappa_G"] / np.maximum(o["D"], 1e-300)
+            Snorm = np.sqrt((o["S"] ** 2).sum(0))
+            sc = float(np.max((2 * o["mu"] + 4 * Snorm) * kG + np.sqrt((b ** 2).sum(0))))
+        elif k in ("vx", "vy", "vz"):
+            sc = float(np.max(np.abs(b))) + steps * dt * ka
+        else:
+            sc = float(np.max(np.abs(b)))
+        e[k] = float(np.max(np.abs(a - b)) / max(sc, 1e-300))
+    return e

@@ -6,7 +6,7 @@ FP32 pair sums to 1e-4 in D, rho and P."""
 import numpy as np
 import pytest
 
-from parity import check_lists, eval_errors, field_errors, gpu_run, oracle_run
+from parity import check_lists, eval_errors, field_errors, gpu_run, oracle_run, step_errors
 from sph_inputs import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -50,7 +50,7 @@ def test_ensemble_steps(ens):
     w = ens
     g = gpu_run(w, steps=5, precision="FP64")
     o = oracle_run(w, steps=5)
-    e = field_errors(g, o, ("x", "y", "z", "vx", "vy", "vz", "u", "h", "S", "D", "ax", "dudt", "dSdt"))
+    e = step_errors(g, o, ("x", "y", "z", "vx", "vy", "vz", "u", "h", "S", "D", "ax", "dudt", "dSdt"), w.dt, 5)
     _print("ensemble 5 steps", e)
     for k, v in e.items():
         assert v < 1e-12, (k, v)
@@ -138,7 +138,7 @@ def test_autotune_then_steps_match_oracle():
     assert tr["trials"] >= 8
     assert 0 < tr["ms_per_step"] <= tr["ms_per_step_start"]
     o = oracle_run(w, steps=5)
-    e = field_errors(g, o, ("x", "y", "z", "vx", "vy", "vz", "u", "h", "S", "D", "ax", "dudt", "dSdt"))
+    e = step_errors(g, o, ("x", "y", "z", "vx", "vy", "vz", "u", "h", "S", "D", "ax", "dudt", "dSdt"), w.dt, 5)
     _print("after autotune, 5 steps", e)
     for k, v in e.items():
         assert v < 1e-12, (k, v)

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 import oracle
-from parity import check_lists, eval_errors, field_errors, gpu_run, oracle_keys, oracle_run
+from parity import check_lists, eval_errors, field_errors, gpu_run, oracle_keys, oracle_run, step_errors
 from sph_inputs import workloads as W
 from sph_inputs.lattice import random_box
 from sph_inputs.params import MethodParams
@@ -90,7 +90,7 @@ def test_plastic_star_evaluation_and_steps():
     _assert_eval(g, o)
     g = gpu_run(w, steps=5)
     o = oracle_run(w, steps=5)
-    e = field_errors(g, o, ("x", "y", "z", "vx", "vy", "vz", "u", "h", "S", "D", "ax", "dudt", "dSdt"))
+    e = step_errors(g, o, ("x", "y", "z", "vx", "vy", "vz", "u", "h", "S", "D", "ax", "dudt", "dSdt"), w.dt, 5)
     _print("5 steps", e)
     for k, v in e.items():
         assert v < TOL_STEPS, (k, v)
@@ -101,7 +101,7 @@ def test_lattice_ten_steps():
     w = W.lattice()
     g = gpu_run(w, steps=10)
     o = oracle_run(w, steps=10)
-    e = field_errors(g, o, ("x", "y", "z", "vx", "vy", "vz", "u", "S", "D", "ax", "dudt", "dSdt"))
+    e = step_errors(g, o, ("x", "y", "z", "vx", "vy", "vz", "u", "S", "D", "ax", "dudt", "dSdt"), w.dt, 10)
     _print("10 steps", e)
     for k, v in e.items():
         assert v < TOL_STEPS, (k, v)
@@ -136,7 +136,7 @@ def test_full_size_star_matches_oracle():
     del g32, o, ok
     g = gpu_run(w, steps=2, lists=False)
     o = oracle_run(w, steps=2)
-    e = field_errors(g, o, ("x", "y", "z", "vx", "vy", "vz", "u", "h", "S", "D", "ax", "dudt", "dSdt"))
+    e = step_errors(g, o, ("x", "y", "z", "vx", "vy", "vz", "u", "h", "S", "D", "ax", "dudt", "dSdt"), w.dt, 2)
     _print("2M 2 steps", e)
     for k, v in e.items():
         assert v < TOL_STEPS, (k, v)
@@ -323,7 +323,7 @@ def test_lanes_per_target(lanes):
     _assert_eval(g, o)
     g = gpu_run(w, steps=5, ctx_kw={"lanes": lanes})
     o = oracle_run(w, steps=5)
-    e = field_errors(g, o, ("x", "y", "z", "vx", "vy", "vz", "u", "h", "S", "D", "ax", "dudt", "dSdt"))
+    e = step_errors(g, o, ("x", "y", "z", "vx", "vy", "vz", "u", "h", "S", "D", "ax", "dudt", "dSdt"), w.dt, 5)
     _print(f"lanes {lanes}, 5 steps", e)
     for k, v in e.items():
         assert v < TOL_STEPS, (k, v)

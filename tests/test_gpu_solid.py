@@ -12,7 +12,7 @@ P and S after five steps to 1e-4."""
 import numpy as np
 import pytest
 
-from parity import check_lists, eval_errors, field_errors, gpu_run, oracle_run
+from parity import check_lists, eval_errors, field_errors, gpu_run, oracle_run, step_errors
 from sph_inputs import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -56,7 +56,7 @@ def test_yield_and_breaking_fire_and_match(yield_mode, rotation, break_mode):
     assert beyond > 50
     o = oracle_run(w, steps=5)
     g = gpu_run(w, steps=5)
-    e = field_errors(g, o, STATE)
+    e = step_errors(g, o, STATE, w.dt, 5)
     _print("5 steps", e)
     for k, v in e.items():
         assert v < TOL_STEPS, (k, v)

@@ -236,3 +236,35 @@ def test_rest_mass_density_of_a_moving_particle():
         assert abs(st["rho"][0] / rho - 1) < 1e-13, (k, st["rho"][0], rho)
         P = (2.0 - 1.0) * rho * 0.05
         assert abs(st["P"][0] / P - 1) < 1e-13
+
+
+def test_fluidized_particle_keeps_no_stress_in_later_steps():
+    # with neighbours a broken particle still has a strain rate; FLUIDIZE means no deviatoric
+    # stress from the break on: S stays exactly 0 in every later step (its predictor included,
+    # seen by the evaluation: zero stress rate and zero stress work), while unbroken neighbours
+    # keep theirs
+    from sph_inputs.lattice import random_box
+    n = 400
+    rng = np.random.default_rng(3)
+    x, y, z = random_box(n, 1.0, 3)
+    S = rng.normal(scale=0.3, size=(6, n))
+    S[:3] -= S[:3].mean(0)
+    arr = dict(x=x, y=y, z=z, vx=rng.normal(scale=0.2, size=n), vy=rng.normal(scale=0.2, size=n),
+               vz=rng.normal(scale=0.2, size=n), u=rng.uniform(0.5, 2.0, n), h=0.09 * rng.uniform(0.7, 1.4, n),
+               S=S, type=np.ones(n, np.int8), broken=np.zeros(n, np.uint8))
+    p = MethodParams(m=1.0 / n, kernel="WC2", eos="GAMMA_LAW", gamma=5 / 3, mu_mode="CONST", mu_const=0.8,
+                     break_mode="FLUIDIZE", eps_break=0.2)
+    orc = oracle.Oracle(p)
+    st = oracle.OracleState(arr)
+    oracle.run_stages(orc, st)
+    oracle.step(orc, st, 2e-4, 1)
+    b = st["broken"] == 1
+    assert 10 < b.sum() < n - 10
+    for _ in range(3):
+        before = b
+        oracle.step(orc, st, 2e-4, 1)
+        b = st["broken"] == 1
+        assert np.all(st["S"][:, b] == 0.0) and np.all(st["dSdt"][:, b] == 0.0)
+        # particles broken before this step were fluid in its evaluation: no stress work there
+        assert np.all(st["sdot"][before] == 0.0)
+        assert np.all(np.any(st["S"][:, ~b] != 0.0, axis=0))
