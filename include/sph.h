@@ -274,6 +274,14 @@ sph_status sph_export_neighbours(sph_ctx* ctx, int64_t* offsets, int32_t* ids, i
 /* Statistics of the current lists (see sph_list_stats).  Waits. */
 sph_status sph_neighbour_stats(sph_ctx* ctx, sph_list_stats* out);
 
+/* The same statistics for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): no allocation at all.  The
+ * counters live in a fixed 64-byte array in the library's device memory, one copy per GPU, held
+ * until the process ends and looked up by sph_create; any list size a context holds fits it (the
+ * counters are 64-bit).  Every call on a GPU shares that copy and clears it first, so calls that
+ * overlap on one GPU (two host threads, or two contexts on different streams) race; calls in
+ * sequence do not.  Same result as sph_neighbour_stats.  Waits. */
+sph_status sph_neighbour_stats_noalloc(sph_ctx* ctx, sph_list_stats* out);
 
 /* ---- EoS surrogate network (extension of the tabulated EoS) ---------------------------------
  * The setup section names tabulated equations of state; this extension fits a network

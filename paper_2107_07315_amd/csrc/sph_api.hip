@@ -233,6 +233,10 @@ sph_status sph_create(const sph_params* params, void* stream, int64_t capacity, 
     sph_destroy(c);
     return note(nullptr, SPH_E_OOM, "pinned host word");
   }
+  if ((e = stats_scratch_init(c))) {
+    sph_destroy(c);
+    return note(nullptr, e, "address of the statistics scratch array on device %d", c->device);
+  }
 
   if (hipMemsetAsync(c->status, 0, sizeof(DevStatus), c->stream) != hipSuccess ||
       hipMemsetAsync(c->nbr_count, 0, sizeof(int32_t) * cap, c->stream) != hipSuccess ||

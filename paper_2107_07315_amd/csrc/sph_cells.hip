@@ -9,6 +9,10 @@
 // skips cells whose box lies farther away.  Cells are addressed by Morton codes so that the
 // sorted particle order is spatially compact.  The list build writes exact FP64 lists that all
 // later passes read, grouped in tiles of 64 particles (see k_build_tiles).
+#include <string.h>
+
+#include <mutex>
+
 #include "sph_internal.h"
 
 namespace {
@@ -1092,3 +1096,72 @@ sph_status sph_count_stats(sph_ctx* c, sph_list_stats* out) {
   return e;
 }
 
+// ---- list statistics without device allocation ------------------------------------------------
+// Counters of sph_neighbour_stats_noalloc: exact pairs, union members, candidates (64-bit) and
+// the longest exact and candidate lists (32-bit, in the fourth and fifth words).  One copy per
+// GPU, held until the process ends; every call on a GPU uses that GPU's copy.  Host code never
+// names the array in a kernel argument or copy: it uses the device address looked up once per
+// device by stats_scratch_init.
+constexpr int kStatWords = 8;
+static __device__ __align__(256) unsigned long long scratch[kStatWords];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned long long* g_scratch_addr[kMaxDevices] = {};
+
+__global__ void k_clear_words(unsigned long long* __restrict__ w, int n) {
+  if ((int)threadIdx.x < n) w[threadIdx.x] = 0ull;
+}
+}  // namespace
+
+sph_status stats_scratch_init(sph_ctx* c) {
+  if (c->device < 0 || c->device >= kMaxDevices) return SPH_E_ARG;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[c->device]) {
+    int cur = -1;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != c->device) HIP_TRY(hipSetDevice(c->device));
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != c->device) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !ptr) return SPH_E_HIP;
+    g_scratch_addr[c->device] = (unsigned long long*)ptr;
+  }
+  c->stats_scratch = g_scratch_addr[c->device];
+  return SPH_OK;
+}
+
+extern "C" sph_status sph_neighbour_stats_noalloc(sph_ctx* c, sph_list_stats* out) {
+  if (!c) return note(nullptr, SPH_E_ARG, "context is NULL");
+  if (!out) return note(c, SPH_E_ARG, "out is NULL");
+  unsigned long long* d = c->stats_scratch;
+  if (!d) return note(c, SPH_E_HIP, "no statistics scratch address for device %d", c->device);
+  hipLaunchKernelGGL(k_clear_words, dim3(1), dim3(64), 0, c->stream, d, kStatWords);
+  int32_t* mx = reinterpret_cast<int32_t*>(d + 3);   // words 3 and 4 hold the two maxima
+  if (c->n > 0 && c->lists_valid) {
+    unsigned nb = grid_for(c->n, kB);
+    nb = nb < 1024 ? nb : 1024;
+    if (c->gen >= 2) hipLaunchKernelGGL(k_count_stats, dim3(nb), dim3(kB), 0, c->stream, c->nbr_count, c->n, d, mx);
+    hipLaunchKernelGGL(k_count_stats, dim3(nb), dim3(kB), 0, c->stream, c->nbr_count_s, c->n, d + 2, mx + 2);
+    hipLaunchKernelGGL(k_union_stats, dim3(256), dim3(kB), 0, c->stream, c->tile_usize, c->grid, d + 1);
+  }
+  hipError_t he = hipGetLastError();
+  unsigned long long h[kStatWords];
+  GridInfo g;
+  if (he == hipSuccess) he = hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+  if (he == hipSuccess && c->n > 0 && c->lists_valid)
+    he = hipMemcpyAsync(&g, c->grid, sizeof(g), hipMemcpyDeviceToHost, c->stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+  if (he != hipSuccess) return note(c, SPH_E_HIP, "statistics: %s", hipGetErrorString(he));
+  int32_t m[4];
+  memcpy(m, h + 3, sizeof(m));
+  out->pairs = (int64_t)h[0];
+  out->union_total = (int64_t)h[1];
+  out->candidates = (int64_t)h[2];
+  out->max_count = m[0];
+  out->pad = 0;
+  out->rebuilds = c->rebuilds;
+  out->tiles = (c->n > 0 && c->lists_valid) ? (int64_t)g.ntiles : 0;
+  return SPH_OK;
+}

@@ -376,6 +376,8 @@ struct sph_ctx {
   double tab_own_g[4];   // lnr0, dlnr, lnu0, dlnu
   // reason for the last failing call (sph_last_error_detail)
   char detail[256];
+  // device address of the statistics scratch array on this context's device
+  unsigned long long* stats_scratch;
 };
 
 // Records a human-readable reason for a failing return (sph_last_error_detail; c may be NULL for
@@ -406,6 +408,9 @@ sph_status launch_unpack_pos(sph_ctx* c, sph_state* st);
 sph_status launch_pack(sph_ctx* c, sph_state* st);
 sph_status launch_modify_energy(sph_ctx* c, sph_state* st, const double* u_of_r, int32_t nr, double dr);
 sph_status sph_count_stats(sph_ctx* c, sph_list_stats* out);
+// looks up (once per device, with that device current) the device address of the statistics
+// scratch array and stores it in the context
+sph_status stats_scratch_init(sph_ctx* c);
 sph_status sph_scan_u32(sph_ctx* c, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total);
 struct MlpView;
 bool mlp_view(const sph_ctx* c, MlpView* v);   // false if no trained network is loaded

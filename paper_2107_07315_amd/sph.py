@@ -22,7 +22,7 @@ EXPORTED = ("sph_create", "sph_destroy", "sph_set_params", "sph_build_cells", "s
             "sph_status_string", "sph_error_particle", "sph_set_timing", "sph_get_timing", "sph_neighbour_stats",
             "sph_mlp_set_params", "sph_mlp_get_params", "sph_mlp_get_norm", "sph_mlp_train", "sph_mlp_grad",
             "sph_mlp_eval", "sph_mlp_build_trust_mask", "sph_ensemble_set", "sph_autotune", "sph_mlp_load",
-            "sph_last_error_detail", "sph_eos_table_create", "sph_modify_energy")
+            "sph_last_error_detail", "sph_eos_table_create", "sph_neighbour_stats_noalloc", "sph_modify_energy")
 MLP_NPARAM = 8642
 
 _dp = ctypes.c_void_p
@@ -109,6 +109,7 @@ def load():
     L.sph_status_string.restype = ctypes.c_char_p
     L.sph_set_timing.argtypes = [vp, ctypes.c_int32]
     L.sph_neighbour_stats.argtypes = [vp, ctypes.POINTER(SphListStats)]
+    L.sph_neighbour_stats_noalloc.argtypes = [vp, ctypes.POINTER(SphListStats)]
     L.sph_get_timing.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32),
                                  ctypes.POINTER(ctypes.c_double)]
     L.sph_mlp_set_params.argtypes = [vp, vp]
@@ -326,6 +327,12 @@ class Context:
     def sph_neighbour_stats(self):
         s = SphListStats()
         _check(self.lib.sph_neighbour_stats(self.h, ctypes.byref(s)), "sph_neighbour_stats", self.h)
+        return {k: getattr(s, k) for k in ("pairs", "max_count", "tiles", "union_total", "candidates",
+                                           "rebuilds")}
+
+    def sph_neighbour_stats_noalloc(self):
+        s = SphListStats()
+        _check(self.lib.sph_neighbour_stats_noalloc(self.h, ctypes.byref(s)), "sph_neighbour_stats_noalloc", self.h)
         return {k: getattr(s, k) for k in ("pairs", "max_count", "tiles", "union_total", "candidates",
                                            "rebuilds")}
 
