@@ -230,6 +230,29 @@ sph_status sph_step(sph_ctx* ctx, sph_state* st, double dt, int32_t nsteps);
  * sph_build_cells).  Stream-ordered. */
 sph_status sph_modify_energy(sph_ctx* ctx, sph_state* st, const double* u_of_r, int32_t nr, double dr);
 
+/* Oscillation diagnostics of the current state (section "Spherically symmetric and static neutron
+ * star tests": radial modes are read from the internal energy, non-radial ones from v_theta of the
+ * particles in a slab r = slab_r +- slab_dr, theta = slab_th +- slab_dth, described by a linear
+ * fit in r and theta; section "Neutron Star Oscillations with a solid crust": the kinetic energy
+ * of the toroidally oscillating crust).  r, theta (from +z) and phi are taken about the origin,
+ * with coordinate velocities.  `out` is a DEVICE pointer to one sph_diag: calls are
+ * stream-ordered, so a time series can be recorded between sph_step calls without waiting. */
+typedef struct {
+  double r_lo, r_hi;        /* radial band of the mean u: r_lo <= r < r_hi                     */
+  double slab_r, slab_dr;   /* v_theta slab in radius ...                                      */
+  double slab_th, slab_dth; /*   ... and in theta (radians)                                     */
+} sph_diag_params;
+typedef struct {
+  double kinetic;           /* sum m |v|^2 / 2                                                 */
+  double toroidal;          /* sum m (v . e_phi)^2 / 2                                         */
+  double internal;          /* sum m u                                                          */
+  double u_band;            /* mean u over the radial band                                     */
+  double slab_c0, slab_cr, slab_cth;  /* least squares v_theta = c0 + c_r (r - slab_r) +          */
+                                      /*   c_th (theta - slab_th) over the slab (0 if < 3 there) */
+  int64_t n_band, n_slab;   /* particles in the band and in the slab                           */
+} sph_diag;
+sph_status sph_diagnostics(sph_ctx* ctx, const sph_state* st, const sph_diag_params* params, sph_diag* out);
+
 /* Ensembles of independent stars in one particle set: star_info (host) holds nstars rows of
  * (centre x, y, z, particle mass, shear factor); each particle's star (state field `star`,
  * required while an ensemble is set) selects its mass, its crust shear factor (mu = factor * P)

@@ -61,7 +61,8 @@ class OrcState(ctypes.Structure):
                 ("x", "y", "z", "vx", "vy", "vz", "u", "h", "S")] + [
         ("type", ctypes.POINTER(ctypes.c_int8)), ("broken", ctypes.POINTER(ctypes.c_uint8))] + [
         (k, _dp) for k in ("D", "rho", "P", "cs", "mu", "Y0", "B", "ax", "ay", "az", "dudt", "dSdt",
-                           "sdot")] + [("star", ctypes.POINTER(ctypes.c_int32))]
+                           "sdot")] + [("star", ctypes.POINTER(ctypes.c_int32)), ("dDdt", _dp), ("Pprev", _dp),
+                                       ("dtprev", ctypes.c_double), ("dt_next", ctypes.c_double)]
 
 
 _lib = None
@@ -186,7 +187,7 @@ class OracleState:
     """numpy-backed particle state plus every output array the oracle writes."""
 
     FIELDS = ("x", "y", "z", "vx", "vy", "vz", "u", "h")
-    OUT = ("D", "rho", "P", "cs", "mu", "Y0", "B", "ax", "ay", "az", "dudt", "sdot")
+    OUT = ("D", "rho", "P", "cs", "mu", "Y0", "B", "ax", "ay", "az", "dudt", "sdot", "dDdt", "Pprev")
 
     def __init__(self, arrays):
         n = arrays["x"].shape[0]
@@ -197,6 +198,10 @@ class OracleState:
         self.a["broken"] = np.ascontiguousarray(arrays["broken"], dtype=np.uint8).copy()
         for k in self.OUT:
             self.a[k] = np.zeros(n)
+        if arrays.get("D") is not None:      # the continuity density starts from the given D
+            self.a["D"] = np.ascontiguousarray(arrays["D"], dtype=np.float64).copy()
+        self.dtprev = 0.0
+        self.dt_next = 0.0
         self.a["dSdt"] = np.zeros((6, n))
         self.a["id"] = np.asarray(arrays.get("id", np.arange(n)), dtype=np.int32).copy()
         if arrays.get("star") is not None:
@@ -213,7 +218,16 @@ class OracleState:
         s.type = _ptr(self.a["type"], ctypes.c_int8)
         s.broken = _ptr(self.a["broken"], ctypes.c_uint8)
         s.star = _ptr(self.a["star"], ctypes.c_int32) if "star" in self.a else None
+        s.dtprev = self.dtprev
+        s.dt_next = self.dt_next
+        self._s = s
         return s
+
+    def sync_scalars(self, s=None):
+        """Copy the scalar fields the oracle wrote back from its struct."""
+        s = s or self._s
+        self.dtprev = s.dtprev
+        self.dt_next = s.dt_next
 
 
 def run_stages(orc: Oracle, st: OracleState, mode=GRID, want_kappa=False):
@@ -229,6 +243,7 @@ def run_stages(orc: Oracle, st: OracleState, mode=GRID, want_kappa=False):
     ka = np.zeros(st.n) if want_kappa else None
     ku = np.zeros(st.n) if want_kappa else None
     _check(L.orc_forces(ctypes.byref(orc.p), ctypes.byref(s), o64, i32, _ptr(ka), _ptr(ku)), "orc_forces")
+    st.sync_scalars(s)
     return dict(offsets=off, ids=ids, kappa_G=kG, kappa_a=ka, kappa_u=ku)
 
 
@@ -243,6 +258,28 @@ def modify_energy(orc: Oracle, st: OracleState, u_of_r, dr: float):
     L.orc_modify_energy(ctypes.byref(orc.p), ctypes.byref(s), _ptr(t), t.shape[0], float(dr))
 
 
+class OrcDiagParams(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in ("r_lo", "r_hi", "slab_r", "slab_dr", "slab_th", "slab_dth")]
+
+
+class OrcDiag(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in ("kinetic", "toroidal", "internal", "u_band", "slab_c0", "slab_cr",
+                                               "slab_cth")] + [("n_band", ctypes.c_int64), ("n_slab", ctypes.c_int64)]
+
+
+def diagnostics(orc: Oracle, st: OracleState, r_lo, r_hi, slab_r, slab_dr, slab_th, slab_dth):
+    """Oscillation diagnostics of the current state (see orc_diagnostics) as a dict."""
+    L = lib()
+    L.orc_diagnostics.argtypes = [ctypes.POINTER(OrcParams), ctypes.POINTER(OrcState), ctypes.POINTER(OrcDiagParams),
+                                  ctypes.POINTER(OrcDiag)]
+    L.orc_diagnostics.restype = None
+    dp = OrcDiagParams(r_lo, r_hi, slab_r, slab_dr, slab_th, slab_dth)
+    out = OrcDiag()
+    s = st.struct()
+    L.orc_diagnostics(ctypes.byref(orc.p), ctypes.byref(s), ctypes.byref(dp), ctypes.byref(out))
+    return {k: getattr(out, k) for k, _ in OrcDiag._fields_}
+
+
 def threads():
     """OpenMP threads the oracle's parallel loops use."""
     L = lib()
@@ -251,8 +288,10 @@ def threads():
 
 
 def step(orc: Oracle, st: OracleState, dt: float, nsteps: int, mode=GRID):
+    """nsteps kick-drift-kick steps; dt <= 0: each step's Courant dt from the last evaluation."""
     s = st.struct()
     _check(lib().orc_step(ctypes.byref(orc.p), ctypes.byref(s), dt, nsteps, mode), "orc_step")
+    st.sync_scalars(s)
 
 
 def kernel(kind: int, r: float, hab: float):

@@ -388,7 +388,8 @@ int orc_density(const orc_params* p, orc_state* st, const int64_t* off, const in
       D += pmass(p, st, b) * W;
     }
     if (!self_done) D += pmass(p, st, a) * Wself;
-    st->D[a] = D;
+    if (p->density_mode == ORC_DENS_CONTINUITY) D = st->D[a];   /* eq. solid1: D is integrated */
+    else st->D[a] = D;
 
     /* rest-mass density from the computational density D = rho psi^6 W_L */
     double rho = D, hen_fac = 1.0;
@@ -502,7 +503,7 @@ int orc_stress_rate(const orc_params* p, orc_state* st, const int64_t* off, cons
 /* ------------------------------------------------------------------------------------ */
 /* forces                                                                                */
 
-typedef struct { double AP[3], AS[3], udot, kP, kS, kU; } pairsum_t;
+typedef struct { double AP[3], AS[3], udot, kP, kS, kU, dd, uvisc, gp, kD, kgp; } pairsum_t;
 
 /* Momentum and energy pair sums of eqs. solid2 and solid3 for particle a (D in place of rho). */
 static pairsum_t pair_sums(const orc_params* p, const orc_state* st, int64_t a, const int32_t* list,
@@ -558,6 +559,14 @@ static pairsum_t pair_sums(const orc_params* p, const orc_state* st, int64_t a, 
     double vg = v[0] * g[0] + v[1] * g[1] + v[2] * g[2];
     double cu = mb * (pia + 0.5 * Pi) * vg;
     o.udot += cu;
+    o.dd += mb * vg;                               /* sum m v_ab . grad_a W (continuity rate) */
+    o.uvisc += mb * 0.5 * Pi * vg;                 /* viscous heating alone */
+    o.kD += mb * (fabs(v[0] * g[0]) + fabs(v[1] * g[1]) + fabs(v[2] * g[2])) * kc;
+    {                                              /* v_a . grad P / D_a, pressure terms only */
+      double vag = st->vx[a] * g[0] + st->vy[a] * g[1] + st->vz[a] * g[2];
+      o.gp += mb * (pia + pib) * vag;
+      o.kgp += mb * (fabs(pia) + fabs(pib)) * (fabs(st->vx[a] * g[0]) + fabs(st->vy[a] * g[1]) + fabs(st->vz[a] * g[2])) * kc;
+    }
     o.kU += mb * (fabs(pia) + 0.5 * fabs(Pi)) * (fabs(v[0] * g[0]) + fabs(v[1] * g[1]) + fabs(v[2] * g[2])) * kc;
   }
   return o;
@@ -627,20 +636,62 @@ int orc_forces(const orc_params* p, orc_state* st, const int64_t* off, const int
         kG += fabs(Gi) / psi4 + fabs(c0 * v[i]);
       }
       kap = fP * o.kP / psi4 + o.kS + kG;
+      kap += ext_accel(p, st, a, acc);
+      const double rho = st->rho[a], P = st->P[a], Da = st->D[a];
+      if (p->dtP_mode == ORC_DTP_LAGGED && st->dtprev > 0.0 && st->Pprev) {
+        /* the lambda = 0 row of the trajectory equation, -xdot^i dP/dt / (W~^2 rho h) with
+         * W~ = W_L / alpha, times -g^00 = 1/alpha^2: -xdot^i dP/dt / (W_L^2 rho h); the partial
+         * time derivative from the change along the path minus the advection, dP/dt|_x =
+         * (P - P_prev) / dt - xdot . grad P with grad P ~ D sum m (P_a/D_a^2 + P_b/D_b^2) grad W */
+        double dPdt = (P - st->Pprev[a]) / st->dtprev - Da * o.gp;
+        double kt = 1.0 / (WL * WL * rho * hen);
+        for (int i = 0; i < 3; ++i) acc[i] -= v[i] * kt * dPdt;
+        kap += kt * (fabs(P - st->Pprev[a]) / st->dtprev + Da * o.kgp) * (fabs(v[0]) + fabs(v[1]) + fabs(v[2]));
+      }
+      if (p->energy_mode == ORC_ENERGY_FIRST_LAW) {
+        /* du/dt = (P / rho^2) drho/dt along the path, rho = D / (psi^6 W_L):
+         * dln rho/dt = dln D/dt - 6 (psi'/psi) (n.v) - dln W_L/dt, with dln D/dt = dd / D and
+         * dln W_L/dt = W_L^2 / 2 d(psi^4 v^2 / alpha^2)/dt along the path */
+        double va = v[0] * acc[0] + v[1] * acc[1] + v[2] * acc[2];
+        double dq = (4.0 * psi2 * g.psi * g.dpsi * nv * v2 + 2.0 * psi4 * va) / (g.alpha * g.alpha) -
+                    2.0 * psi4 * v2 * g.dalpha * nv / (g.alpha * g.alpha * g.alpha);
+        double dlnrho = o.dd / Da - 6.0 * g.dpsi / g.psi * nv - 0.5 * WL * WL * dq;
+        st->dudt[a] = P / rho * dlnrho + o.uvisc + st->sdot[a];
+        if (kappa_u) kappa_u[a] = P / rho * (o.kD / Da + fabs(6.0 * g.dpsi / g.psi * nv) + fabs(0.5 * WL * WL * dq)) +
+                                  o.kU + fabs(st->sdot[a]);
+      }
     } else {
       for (int i = 0; i < 3; ++i) acc[i] = -o.AP[i] + o.AS[i];   /* eq. solid2 */
       kap = o.kP + o.kS;
+      kap += ext_accel(p, st, a, acc);
     }
-    kap += ext_accel(p, st, a, acc);
     st->ax[a] = acc[0];
     st->ay[a] = acc[1];
     st->az[a] = acc[2];
-    st->dudt[a] = o.udot + st->sdot[a];                          /* eq. solid3 */
+    if (st->dDdt) st->dDdt[a] = o.dd;
+    if (p->energy_mode == ORC_ENERGY_FIRST_LAW && p->background == ORC_TOV) {
+      /* written above */
+    } else if (p->energy_mode == ORC_ENERGY_FIRST_LAW) {
+      /* Newtonian: rho = D, so (P / D^2) dD/dt: the pressure term of eq. solid3 */
+      st->dudt[a] = st->P[a] / (st->D[a] * st->D[a]) * o.dd + o.uvisc + st->sdot[a];
+      if (kappa_u) kappa_u[a] = o.kU + fabs(st->sdot[a]);
+    } else {
+      st->dudt[a] = o.udot + st->sdot[a];                        /* eq. solid3 */
+      if (kappa_u) kappa_u[a] = o.kU + fabs(st->sdot[a]);
+    }
     if (kappa_a) kappa_a[a] = kap;
-    if (kappa_u) kappa_u[a] = o.kU + fabs(st->sdot[a]);
     if (!isfinite(acc[0]) || !isfinite(acc[1]) || !isfinite(acc[2]) || !isfinite(st->dudt[a]))
       err = ORC_E_NONFINITE;
   }
+  /* Courant step of this evaluation: cfl min_a h_a / (c_L,a + |v_a|), c_L^2 = c_s^2 + 4 mu / (3 rho) */
+  double dmin = INFINITY;
+  for (int64_t a = 0; a < n; ++a) {
+    double cl = sqrt(st->cs[a] * st->cs[a] + 4.0 * st->mu[a] / (3.0 * st->rho[a]));
+    double vm = sqrt(st->vx[a] * st->vx[a] + st->vy[a] * st->vy[a] + st->vz[a] * st->vz[a]);
+    double q = st->h[a] / (cl + vm);
+    if (q < dmin) dmin = q;
+  }
+  st->dt_next = (p->cfl > 0.0 ? p->cfl : 0.3) * dmin;
   return err;
 }
 
@@ -772,41 +823,54 @@ static void apply_breaking(const orc_params* p, orc_state* st) {
 
 int orc_step(const orc_params* p, orc_state* st, double dt, int32_t nsteps, int32_t ngb_mode) {
   int64_t n = st->n;
-  double* vh = (double*)malloc((size_t)n * 10 * sizeof(double));
+  const int cont = p->density_mode == ORC_DENS_CONTINUITY;
+  if (cont && !st->dDdt) return ORC_E_ARG;
+  if (p->dtP_mode == ORC_DTP_LAGGED && !st->Pprev) return ORC_E_ARG;
+  if (p->damping > 0.0 && dt > 0.0 && p->damping * dt >= 1.0) return ORC_E_ARG;   /* explicit drag */
+  double* vh = (double*)malloc((size_t)n * 11 * sizeof(double));
   if (!vh) return ORC_E_OOM;
-  double *vxh = vh, *vyh = vh + n, *vzh = vh + 2 * n, *uh = vh + 3 * n, *Sh = vh + 4 * n;
+  double *vxh = vh, *vyh = vh + n, *vzh = vh + 2 * n, *uh = vh + 3 * n, *Sh = vh + 4 * n, *Dh = vh + 10 * n;
   int e = 0;
   for (int32_t step = 0; step < nsteps && !e; ++step) {
+    /* fixed dt, or (dt <= 0) the Courant step of the last evaluation */
+    const double dts = dt > 0.0 ? dt : st->dt_next;
     for (int64_t a = 0; a < n; ++a) {
       /* kick: half-step velocity, energy and stress with the rates of the last evaluation */
-      vxh[a] = st->vx[a] + 0.5 * dt * st->ax[a];
-      vyh[a] = st->vy[a] + 0.5 * dt * st->ay[a];
-      vzh[a] = st->vz[a] + 0.5 * dt * st->az[a];
-      uh[a] = st->u[a] + 0.5 * dt * st->dudt[a];
-      for (int k = 0; k < 6; ++k) Sh[k * n + a] = st->S[k * n + a] + 0.5 * dt * st->dSdt[k * n + a];
+      vxh[a] = st->vx[a] + 0.5 * dts * st->ax[a];
+      vyh[a] = st->vy[a] + 0.5 * dts * st->ay[a];
+      vzh[a] = st->vz[a] + 0.5 * dts * st->az[a];
+      uh[a] = st->u[a] + 0.5 * dts * st->dudt[a];
+      for (int k = 0; k < 6; ++k) Sh[k * n + a] = st->S[k * n + a] + 0.5 * dts * st->dSdt[k * n + a];
+      if (cont) Dh[a] = st->D[a] + 0.5 * dts * st->dDdt[a];
       /* drift */
-      st->x[a] += dt * vxh[a];
-      st->y[a] += dt * vyh[a];
-      st->z[a] += dt * vzh[a];
+      st->x[a] += dts * vxh[a];
+      st->y[a] += dts * vyh[a];
+      st->z[a] += dts * vzh[a];
       wrap_box(p, &st->x[a]);
       wrap_box(p, &st->y[a]);
       wrap_box(p, &st->z[a]);
       /* predictors for the velocity-dependent evaluation */
-      st->vx[a] = vxh[a] + 0.5 * dt * st->ax[a];
-      st->vy[a] = vyh[a] + 0.5 * dt * st->ay[a];
-      st->vz[a] = vzh[a] + 0.5 * dt * st->az[a];
-      st->u[a] = uh[a] + 0.5 * dt * st->dudt[a];
-      for (int k = 0; k < 6; ++k) st->S[k * n + a] = Sh[k * n + a] + 0.5 * dt * st->dSdt[k * n + a];
+      st->vx[a] = vxh[a] + 0.5 * dts * st->ax[a];
+      st->vy[a] = vyh[a] + 0.5 * dts * st->ay[a];
+      st->vz[a] = vzh[a] + 0.5 * dts * st->az[a];
+      st->u[a] = uh[a] + 0.5 * dts * st->dudt[a];
+      for (int k = 0; k < 6; ++k) st->S[k * n + a] = Sh[k * n + a] + 0.5 * dts * st->dSdt[k * n + a];
+      if (cont) st->D[a] = Dh[a] + 0.5 * dts * st->dDdt[a];
     }
     orc_yield(p, n, st->S, st->Y0);
+    if (p->dtP_mode == ORC_DTP_LAGGED) {   /* the pressure of this evaluation's predecessor */
+      memcpy(st->Pprev, st->P, (size_t)n * sizeof(double));
+      st->dtprev = dts;
+    }
     e = orc_evaluate(p, st, ngb_mode);
     if (e) break;
     for (int64_t a = 0; a < n; ++a) {
-      st->vx[a] = vxh[a] + 0.5 * dt * st->ax[a];
-      st->vy[a] = vyh[a] + 0.5 * dt * st->ay[a];
-      st->vz[a] = vzh[a] + 0.5 * dt * st->az[a];
-      st->u[a] = uh[a] + 0.5 * dt * st->dudt[a];
-      for (int k = 0; k < 6; ++k) st->S[k * n + a] = Sh[k * n + a] + 0.5 * dt * st->dSdt[k * n + a];
+      st->vx[a] = vxh[a] + 0.5 * dts * st->ax[a];
+      st->vy[a] = vyh[a] + 0.5 * dts * st->ay[a];
+      st->vz[a] = vzh[a] + 0.5 * dts * st->az[a];
+      st->u[a] = uh[a] + 0.5 * dts * st->dudt[a];
+      for (int k = 0; k < 6; ++k) st->S[k * n + a] = Sh[k * n + a] + 0.5 * dts * st->dSdt[k * n + a];
+      if (cont) st->D[a] = Dh[a] + 0.5 * dts * st->dDdt[a];
     }
     orc_yield(p, n, st->S, st->Y0);
     apply_breaking(p, st);
@@ -952,4 +1016,67 @@ void orc_modify_energy(const orc_params* p, orc_state* st, const double* u_of_r,
     st->u[a] = u;
     st->vx[a] = st->vy[a] = st->vz[a] = 0.0;
   }
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* oscillation diagnostics                                                               */
+
+/* Sums of one state for the oscillation analyses of the test sections (radial modes from u,
+ * non-radial modes from v_theta in a slab at r = slab_r +- slab_dr, theta = slab_th +- slab_dth
+ * described by a linear fit in r and theta; the crust shell's kinetic energy).  Radius, theta
+ * and phi are taken about the origin with theta from the +z axis. */
+void orc_diagnostics(const orc_params* p, const orc_state* st, const orc_diag_params* dp, orc_diag* out) {
+  double ke = 0.0, tor = 0.0, ein = 0.0, ub = 0.0;
+  int64_t nb = 0, ns = 0;
+  double M[3][3] = {{0}}, rhs[3] = {0};
+  for (int64_t a = 0; a < st->n; ++a) {
+    const double m = pmass(p, st, a);
+    const double x = st->x[a], y = st->y[a], z = st->z[a];
+    const double vx = st->vx[a], vy = st->vy[a], vz = st->vz[a];
+    const double r = sqrt(x * x + y * y + z * z);
+    const double rc = sqrt(x * x + y * y);
+    ke += 0.5 * m * (vx * vx + vy * vy + vz * vz);
+    ein += m * st->u[a];
+    if (rc > 0.0) {
+      const double vphi = (-y * vx + x * vy) / rc;      /* e_phi = (-sin phi, cos phi, 0) */
+      tor += 0.5 * m * vphi * vphi;
+    }
+    if (r >= dp->r_lo && r < dp->r_hi) { ub += st->u[a]; ++nb; }
+    if (r > 0.0 && rc > 0.0) {
+      const double th = acos(z / r);
+      if (fabs(r - dp->slab_r) <= dp->slab_dr && fabs(th - dp->slab_th) <= dp->slab_dth) {
+        /* e_theta = (cos th cos phi, cos th sin phi, -sin th) */
+        const double ct = z / r, sth = rc / r;
+        const double vth = ct * (x * vx + y * vy) / rc - sth * vz;
+        const double f[3] = {1.0, r - dp->slab_r, th - dp->slab_th};
+        for (int i = 0; i < 3; ++i) {
+          for (int j = 0; j < 3; ++j) M[i][j] += f[i] * f[j];
+          rhs[i] += f[i] * vth;
+        }
+        ++ns;
+      }
+    }
+  }
+  out->kinetic = ke;
+  out->toroidal = tor;
+  out->internal = ein;
+  out->u_band = nb > 0 ? ub / (double)nb : 0.0;
+  out->n_band = nb;
+  out->n_slab = ns;
+  /* normal equations of the least-squares fit, solved by Cramer's rule */
+  double det = M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+               M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+  double c[3] = {0.0, 0.0, 0.0};
+  if (ns >= 3 && det != 0.0) {
+    for (int k = 0; k < 3; ++k) {
+      double A[3][3];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) A[i][j] = (j == k) ? rhs[i] : M[i][j];
+      c[k] = (A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) - A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+              A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0])) / det;
+    }
+  }
+  out->slab_c0 = c[0];
+  out->slab_cr = c[1];
+  out->slab_cth = c[2];
 }

@@ -85,6 +85,10 @@ typedef struct {
   double *ax, *ay, *az, *dudt, *dSdt;            /* dSdt: 6n */
   double *sdot;                                  /* S:epsdot/D (energy source) */
   const int32_t* star;                           /* star of each particle (ensembles), or NULL */
+  double *dDdt;                                  /* sum m (v_a - v_b) . grad_a W (continuity rate) */
+  double *Pprev;                                 /* P of the previous evaluation (dP/dt term) */
+  double dtprev;                                 /* time since that evaluation (0: none) */
+  double dt_next;                                /* cfl min h / (c_L + |v|) of the last evaluation */
 } orc_state;
 
 /* Neighbour sets N(a) = { b != a : |x_a - x_b|^2 < (h_a + h_b)^2 } (section "Solid SPH
@@ -134,6 +138,20 @@ int orc_step(const orc_params* p, orc_state* st, double dt, int32_t nsteps, int3
  * distance from the star centre; velocities set to zero.
  * Pinned by: a linear profile, reproduced exactly at every radius. */
 void orc_modify_energy(const orc_params* p, orc_state* st, const double* u_of_r, int32_t nr, double dr);
+
+/* Oscillation diagnostics of one state (sections "Spherically symmetric and static neutron star
+ * tests" and "Neutron Star Oscillations with a solid crust"): kinetic energy, its toroidal part
+ * about the z axis, total internal energy, the mean u of the radial band [r_lo, r_hi) (radial
+ * modes are read from u), and the linear least-squares fit v_theta = c0 + c_r (r - slab_r) +
+ * c_th (theta - slab_th) over the slab |r - slab_r| <= slab_dr, |theta - slab_th| <= slab_dth
+ * (non-radial modes).  About the origin, theta from +z.
+ * Pinned by: a linear v_theta field recovered exactly; closed-form kinetic energies. */
+typedef struct { double r_lo, r_hi, slab_r, slab_dr, slab_th, slab_dth; } orc_diag_params;
+typedef struct {
+  double kinetic, toroidal, internal, u_band, slab_c0, slab_cr, slab_cth;
+  int64_t n_band, n_slab;
+} orc_diag;
+void orc_diagnostics(const orc_params* p, const orc_state* st, const orc_diag_params* dp, orc_diag* out);
 
 /* OpenMP threads of the parallel loops (1 without OpenMP). */
 int32_t orc_threads(void);

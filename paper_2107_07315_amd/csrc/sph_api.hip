@@ -164,6 +164,7 @@ void sph_destroy(sph_ctx* c) {
     if (b) (void)hipFree(b);
   if (c->drift_host) (void)hipHostFree(c->drift_host);
   if (c->tab_own) (void)hipFree(c->tab_own);
+  if (c->diag_part) (void)hipFree(c->diag_part);
   mlp_free(c);
   for (auto& t : c->timers)
     for (hipEvent_t e : t.ev) (void)hipEventDestroy(e);

@@ -378,6 +378,8 @@ struct sph_ctx {
   char detail[256];
   // device address of the statistics scratch array on this context's device
   unsigned long long* stats_scratch;
+  // per-block partial sums of sph_diagnostics (allocated on first use)
+  double* diag_part;
 };
 
 // Records a human-readable reason for a failing return (sph_last_error_detail; c may be NULL for

@@ -22,7 +22,8 @@ EXPORTED = ("sph_create", "sph_destroy", "sph_set_params", "sph_build_cells", "s
             "sph_status_string", "sph_error_particle", "sph_set_timing", "sph_get_timing", "sph_neighbour_stats",
             "sph_mlp_set_params", "sph_mlp_get_params", "sph_mlp_get_norm", "sph_mlp_train", "sph_mlp_grad",
             "sph_mlp_eval", "sph_mlp_build_trust_mask", "sph_ensemble_set", "sph_autotune", "sph_mlp_load",
-            "sph_last_error_detail", "sph_eos_table_create", "sph_neighbour_stats_noalloc", "sph_modify_energy")
+            "sph_last_error_detail", "sph_eos_table_create", "sph_neighbour_stats_noalloc", "sph_modify_energy",
+            "sph_diagnostics")
 MLP_NPARAM = 8642
 
 _dp = ctypes.c_void_p
@@ -62,6 +63,13 @@ class SphListStats(ctypes.Structure):
     _fields_ = [("pairs", ctypes.c_int64), ("max_count", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("tiles", ctypes.c_int64), ("union_total", ctypes.c_int64),
                 ("candidates", ctypes.c_int64), ("rebuilds", ctypes.c_int64)]
+
+
+class SphDiagParams(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in ("r_lo", "r_hi", "slab_r", "slab_dr", "slab_th", "slab_dth")]
+
+
+DIAG_FIELDS = ("kinetic", "toroidal", "internal", "u_band", "slab_c0", "slab_cr", "slab_cth", "n_band", "n_slab")
 
 
 class SphState(ctypes.Structure):
@@ -124,6 +132,7 @@ def load():
     L.sph_autotune.argtypes = [vp, S, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(SphTuneResult)]
     L.sph_mlp_load.argtypes = [vp, vp]
     L.sph_modify_energy.argtypes = [vp, S, vp, ctypes.c_int32, ctypes.c_double]
+    L.sph_diagnostics.argtypes = [vp, S, ctypes.POINTER(SphDiagParams), vp]
     L.sph_last_error_detail.argtypes = [vp]
     L.sph_last_error_detail.restype = ctypes.c_char_p
     L.sph_eos_table_create.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
@@ -313,6 +322,22 @@ class Context:
         self._keep.append(t)
         _check(self.lib.sph_modify_energy(self.h, ctypes.byref(st.struct), t.data_ptr(), t.shape[0], float(dr)),
                "sph_modify_energy", self.h)
+
+    def sph_diagnostics(self, st: DeviceState, r_lo, r_hi, slab_r, slab_dr, slab_th, slab_dth, out=None):
+        """Oscillation diagnostics of the state.  With out (a device tensor of 72 bytes) the record is
+        written there, stream-ordered, and None is returned; without, it is read back as a dict."""
+        import torch
+        dp = SphDiagParams(r_lo, r_hi, slab_r, slab_dr, slab_th, slab_dth)
+        buf = out if out is not None else torch.zeros(9, dtype=torch.float64, device="cuda")
+        _check(self.lib.sph_diagnostics(self.h, ctypes.byref(st.struct), ctypes.byref(dp), buf.data_ptr()),
+               "sph_diagnostics", self.h)
+        if out is not None:
+            return None
+        raw = buf.cpu().numpy()
+        d = {k: float(raw[i]) for i, k in enumerate(DIAG_FIELDS[:7])}
+        d["n_band"] = int(raw[7:8].view(np.int64)[0])
+        d["n_slab"] = int(raw[8:9].view(np.int64)[0])
+        return d
 
     def sph_set_timing(self, enable: bool):
         _check(self.lib.sph_set_timing(self.h, int(bool(enable))), "sph_set_timing", self.h)

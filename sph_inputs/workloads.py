@@ -258,3 +258,95 @@ def relax_star(N: int = 20_000, seed: int = 6, kind: str = "gamma2", kernel: str
     w.extra = {"u_profile": np.ascontiguousarray(bg.u), "u_dr": bg.drbar, "type": typ,
                "star_params": real.params.replace(m=m), "crossing": crossing}
     return w
+
+
+PAPER_K, PAPER_RHOC = 100.0, 1.28e-3     # the paper's TOV test star: K = 100, Gamma = 2
+
+
+@functools.lru_cache(maxsize=1)
+def paper_background(n: int = 8192) -> Background:
+    return make_background(solve_tov(Polytrope(PAPER_K, 2.0), PAPER_RHOC), n)
+
+
+def crust_shell(N: int = 1_000_000, seed: int = 8, rho_in_cgs: float = 7e12, rho_out_cgs: float = 4e12,
+                mu_cgs: float = 1e29, solid: bool = True, amp: float = 1e-3, kernel: str = "WC2", eta: float = 1.3,
+                wall_layers: float = 0.25):
+    """The crust-shell workload of section "Neutron stars with a solid crust in SPH": the part of
+    the paper's 1.4 Msun polytrope (K = 100, Gamma = 2, rho_c = 0.00128) between the densities
+    rho_in_cgs and rho_out_cgs (7e12 and 4e12 g/cm^3: a shell about 0.06 km thick at r = 9.5),
+    Newtonian, held by the effective potential of that density profile (g = K Gamma rho^(Gamma-2)
+    d rho / dr along the areal radius) and by potential walls at its two faces; constant shear
+    modulus mu_cgs (1e29 erg/cm^3; 0 for the fluid comparison with solid=False), no yield, no
+    breaking.  Particles sit on icosahedral layers, as many as the shell holds at the spacing that
+    N particles give (two at 1M).  The imposed velocity, stored in extra["v_tor"], is the l = 2
+    toroidal field v = amp v_s 3 sin(theta) cos(theta) e_phi with v_s = sqrt(mu / rho) the shear
+    speed (the state itself starts at rest, for the radial settling the paper's walls need first).
+    Wall stiffness: a wall displacement of wall_layers spacings balances the pressure push
+    c_s^2 / spacing on a face layer."""
+    from .relax import icosphere
+    from .star import _random_rotation
+    from .tov import C_CGS, DENSITY_UNIT_CGS, areal_radius, density_from_cgs
+    bg = paper_background()
+    r_all = areal_radius(bg, bg.rbar)
+    rho = bg.rho
+    inside = rho > 0
+    r_of_rho = lambda q: float(np.interp(q, rho[inside][::-1], r_all[inside][::-1]))
+    rin, rout = r_of_rho(density_from_cgs(rho_in_cgs)), r_of_rho(density_from_cgs(rho_out_cgs))
+    # enclosed (Newtonian) shell mass on a fine radial grid
+    rr = np.linspace(rin, rout, 4001)
+    rho_r = np.interp(rr, r_all, rho)
+    dm = 4.0 * math.pi * rr**2 * rho_r
+    mcum = np.concatenate([[0.0], np.cumsum(0.5 * (dm[1:] + dm[:-1]) * np.diff(rr))])
+    Ms = float(mcum[-1])
+    m0 = Ms / N
+    ell = (m0 / float(rho_r.mean())) ** (1.0 / 3.0)
+    layers = max(1, int(math.ceil((rout - rin) / ell)))
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pts, radii = [], []
+    per = N / layers
+    for k in range(layers):
+        rk = float(np.interp((k + 0.5) / layers * Ms, mcum, rr))
+        f = max(1, int(round(math.sqrt(max(per - 2.0, 0.0) / 10.0))))
+        P = icosphere(f) @ _random_rotation(rng).T
+        pts.append(P * rk)
+        radii.append(np.full(P.shape[0], rk))
+    X = np.concatenate(pts)
+    n = X.shape[0]
+    m = Ms / n
+    x, y, z = X[:, 0].copy(), X[:, 1].copy(), X[:, 2].copy()
+    r = np.sqrt(x * x + y * y + z * z)
+    rho_p = np.interp(r, r_all, rho)
+    K, G = PAPER_K, 2.0
+    u = K * rho_p ** (G - 1.0) / (G - 1.0)
+    # smoothing length from the larger of the volume spacing (m / rho)^(1/3) and the spacing within a
+    # layer, sqrt(4 pi r^2 / particles per layer): a layer thinner than the volume spacing would
+    # otherwise leave a particle with a handful of neighbours
+    in_layer = np.sqrt(4.0 * math.pi * r**2 / (n / layers))
+    h = eta * np.maximum((m / rho_p) ** (1.0 / 3.0), in_layer)
+    # effective potential of the shell's profile on a grid from 0 to past the outer face
+    dr = (rout - rin) / 400.0
+    grid = np.arange(0.0, rout + 50 * dr, dr)
+    rho_g = np.interp(grid, r_all, rho)
+    rho_g = np.maximum(rho_g, 1e-3 * float(rho_p.min()))
+    g = K * G * rho_g ** (G - 2.0) * np.gradient(rho_g, grid)
+    mu = mu_cgs / (DENSITY_UNIT_CGS * C_CGS**2) if solid else 0.0
+    cs2 = G * K * rho_p ** (G - 1.0)
+    spacing = (m / float(rho_p.mean())) ** (1.0 / 3.0)
+    wall_k = float(cs2.max()) / spacing / (wall_layers * spacing)
+    params = MethodParams(m=m, kernel=kernel, h_mode="FIXED", eta=eta, background="NEWTONIAN", eos="GAMMA_LAW",
+                          gamma=G, mu_mode="CONST", mu_const=mu, y0_mode="CONST", y0_const=1e300, break_mode="OFF",
+                          ext_table=np.ascontiguousarray(g), ext_dr=dr, wall_in=rin, wall_out=rout, wall_k=wall_k)
+    typ = np.ones(n, np.int8) if solid else np.zeros(n, np.int8)
+    arrays = _arrays(x, y, z, np.zeros(n), np.zeros(n), np.zeros(n), u, h, typ)
+    vs = math.sqrt(mu_cgs / (DENSITY_UNIT_CGS * C_CGS**2) / float(rho_p.mean()))
+    rc = np.sqrt(x * x + y * y)
+    ct, st_ = z / r, rc / r
+    vphi = amp * vs * 3.0 * st_ * ct
+    ephi = np.stack([-y / np.maximum(rc, 1e-300), x / np.maximum(rc, 1e-300), np.zeros(n)])
+    v_tor = ephi * vphi
+    cL = np.sqrt(cs2 + 4.0 * mu / (3.0 * rho_p))
+    dt = min(cfl_dt(h, cL, np.zeros(n)), 0.3 / math.sqrt(wall_k))
+    w = Workload(f"shell{n}", params, arrays, dt, 0, bg)
+    w.extra = {"v_tor": v_tor, "r_in": rin, "r_out": rout, "layers": layers, "v_shear": vs, "R": bg.R, "M": bg.M,
+               "mu": mu, "rho_mean": float(rho_p.mean())}
+    return w

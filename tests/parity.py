@@ -123,9 +123,10 @@ def step_errors(g, o, keys, dt, steps):
     for k in keys:
         a, b = g[k], o[k]
         if k in ("ax", "ay", "az"):
-            sc = ka
+            sc = max(ka, float(np.max(np.abs(b))))
         elif k == "dudt":
-            sc = ku
+            # at t = 0 a state at rest has kappa_u = 0; the rate after steps is its own scale then
+            sc = max(ku, float(np.max(np.abs(b))))
         elif k == "dSdt":
             kG = o["kappa_G"] / np.maximum(o["D"], 1e-300)
             Snorm = np.sqrt((o["S"] ** 2).sum(0))
