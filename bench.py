@@ -134,11 +134,13 @@ def run_variant(w, precision, eos, steps, warmup, timing=True, ctx_kw=None, mlp=
         ctx.sph_set_timing(False)
     stats = ctx.sph_neighbour_stats()
     pairs, maxc = stats["pairs"], stats["max_count"]
+    served = ctx.mlp_count_served(st) if mlp is not None else None
     ctx.close()
     del st
     torch.cuda.empty_cache()
     return {"ms_per_step": ms_step, "value": w.n * steps / (t1 - t0), "stages": stages, "stage_steps": steps,
-            "pairs": pairs, "max_neighbours": maxc, "stats": stats, "trusted_cells": trusted}
+            "pairs": pairs, "max_neighbours": maxc, "stats": stats, "trusted_cells": trusted,
+            "particles_on_network": served}
 
 
 def run_ensemble(surrogate, steps, warmup):
@@ -189,6 +191,47 @@ def run_ensemble(surrogate, steps, warmup):
         print(f"# ensemble {mode}: {out[mode]['ms_per_step']:.3f} ms/step, {out[mode]['value']:.4g} "
               f"particle-updates/s", file=sys.stderr, flush=True)
     return out
+
+
+def run_shell(steps, warmup, n=1_000_000, settle=200):
+    """The crust-shell workload (the paper's 1M-particle shell of its 1.4 Msun star between 7e12 and
+    4e12 g/cm^3, two particle layers, held by the effective potential and walls, mu = 1e29
+    erg/cm^3, FP32 pair sums): settled radially with a drag, given the l = 2 toroidal velocity,
+    then timed."""
+    import math
+
+    import torch
+
+    from paper_2107_07315_amd import sph
+    from sph_inputs import workloads as W
+    w = W.crust_shell(n)
+    p = w.params.replace(precision="FP32")
+    ctx = sph.Context(p.replace(damping=min(2.0 * math.sqrt(p.wall_k), 0.3 / w.dt)), capacity=w.n)
+    st = sph.DeviceState(w.arrays)
+    ctx.evaluate(st)
+    ctx.sph_step(st, w.dt, settle)
+    ctx.sph_sync()
+    a = st.numpy()
+    ctx.close()
+    vt = w.extra["v_tor"][:, a["id"]]
+    a["vx"], a["vy"], a["vz"] = vt[0].copy(), vt[1].copy(), vt[2].copy()
+    ctx = sph.Context(p, capacity=w.n)
+    st = sph.DeviceState(a)
+    ctx.evaluate(st)
+    ctx.sph_step(st, w.dt, warmup)
+    ctx.sph_sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.sph_step(st, w.dt, steps)
+    ctx.sph_sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = ctx.sph_neighbour_stats()
+    ctx.close()
+    return {"workload": f"crust shell of the 1.4 Msun K=100 Gamma=2 star, {w.n} particles in {w.extra['layers']} "
+                        f"layers, effective potential + walls, mu=1e29 erg/cm^3, l=2 toroidal velocity, FP32 pair sums",
+            "n_particles": w.n, "steps": steps, "value": w.n * steps / (t1 - t0),
+            "ms_per_step": (t1 - t0) * 1e3 / steps, "pairs_per_particle": stats["pairs"] / w.n}
 
 
 def roofline(res, n, precision):
@@ -276,6 +319,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ensemble-steps", type=int, default=50,
                     help="steps of the 64-star, 8M-particle ensemble run (0: skip it)")
+    ap.add_argument("--shell-steps", type=int, default=100,
+                    help="steps of the 1M-particle crust-shell run (0: skip it)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -313,7 +358,13 @@ def main():
         res[v] = run_variant(w, prec, "MLP" if mlp else "TABLE", args.steps, args.warmup, mlp=mlp)
         print(f"# {v}: {res[v]['ms_per_step']:.3f} ms/step, {res[v]['value']:.4g} particle-updates/s",
               file=sys.stderr, flush=True)
-    head = "FP32+MLP" if "FP32+MLP" in res else ("FP32" if "FP32" in res else variants[0])
+    # the headline is the mixed-precision path with the network only if the network serves
+    # particles at the 1e-4 tolerance; otherwise it is the same path with the table EoS
+    served = res.get("FP32+MLP", {}).get("particles_on_network") or 0
+    if "FP32+MLP" in res and served > 0:
+        head = "FP32+MLP"
+    else:
+        head = "FP32" if "FP32" in res else variants[0]
     r = res[head]
     out = {
         "metric": "particle-updates/s at 2M particles: FP64 plain vs FP32+EoS-MLP, 1 GPU",
@@ -328,6 +379,9 @@ def main():
         "vs_baseline": None,
         "dtype": {"FP32": "f32 pair sums + f64 integration",
                   "FP32+MLP": "f32 pair sums + f64 integration + bf16 EoS network"}.get(head, "f64"),
+        "headline": {"FP32": "FP32+table: FP32 pair sums with the tabulated EoS (the EoS network serves no "
+                             "particle at the 1e-4 tolerance)",
+                     "FP32+MLP": "FP32+EoS-MLP"}.get(head, head),
         "data": "synthetic",
         "config": {"workload": f"piecewise-polytrope TOV star, {w.n} particles, Wendland C4 "
                                f"(~100 neighbours), l=2 A=1e-2, plastic + breaking, tabulated EoS",
@@ -337,7 +391,8 @@ def main():
                          "stages_ms_per_step": {s: round(d["ms_total"] / args.steps, 4)
                                                 for s, d in v["stages"].items()},
                          "pairs": v["pairs"], "max_neighbours": v["max_neighbours"],
-                         "lists": v["stats"], "trusted_cells": v["trusted_cells"]}
+                         "lists": v["stats"], "trusted_cells": v["trusted_cells"],
+                         "particles_on_network": v["particles_on_network"]}
                      for k, v in res.items()},
         "roofline": roofline(r, w.n, "FP32" if head.startswith("FP32") else "FP64"),
     }
@@ -348,6 +403,10 @@ def main():
         out["roofline_fp64"] = roofline(res["FP64"], w.n, "FP64")
     if args.ensemble_steps > 0:
         out["ensemble"] = run_ensemble(surrogate, args.ensemble_steps, 5)
+    if args.shell_steps > 0:
+        out["crust_shell"] = run_shell(args.shell_steps, 5)
+        print(f"# crust shell: {out['crust_shell']['ms_per_step']:.3f} ms/step, "
+              f"{out['crust_shell']['value']:.4g} particle-updates/s", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
         out["cpu_baseline_one_core"] = cpu_baseline_one_core()

@@ -211,7 +211,10 @@ sph_status sph_stress_rate(sph_ctx* ctx, sph_state* st);
  * trajectory equation of the fixed-background section with zero shift.  Writes ax..az, dudt. */
 sph_status sph_forces(sph_ctx* ctx, sph_state* st);
 
-/* nsteps kick-drift-kick steps of size dt (dt > 0).  On entry the rates must be those of a full
+/* nsteps kick-drift-kick steps of size dt; dt <= 0: each step takes the Courant step
+ * cfl min_a h_a / (c_L,a + |v_a|) of the evaluation before it, computed on the device (the host
+ * never waits for it; sph_get_time reports the simulated time; not with graph replay).  With
+ * damping > 0 a fixed dt needs damping dt < 1.  On entry the rates must be those of a full
  * evaluation at the current state (build_cells, density, stress_rate, forces).  Applies the
  * von Mises yield scaling after each stress update and the maximum-strain breaking test
  * (section "Solid SPH Equations"), and the adaptive smoothing length.  Within one call the final
@@ -250,6 +253,8 @@ typedef struct {
   double slab_c0, slab_cr, slab_cth;  /* least squares v_theta = c0 + c_r (r - slab_r) +          */
                                       /*   c_th (theta - slab_th) over the slab (0 if < 3 there) */
   int64_t n_band, n_slab;   /* particles in the band and in the slab                           */
+  double tor_l2;            /* l = 2 toroidal mode amplitude: sum m v_phi f / sum m f^2 with     */
+                            /*   f = 3 sin(theta) cos(theta) = -d P_2(cos theta) / d theta       */
 } sph_diag;
 sph_status sph_diagnostics(sph_ctx* ctx, const sph_state* st, const sph_diag_params* params, sph_diag* out);
 
@@ -279,6 +284,9 @@ typedef struct {
 } sph_tune_result;
 sph_status sph_autotune(sph_ctx* ctx, const sph_state* st, double dt, int32_t steps_per_trial,
                         sph_tune_result* out);
+
+/* Simulated time: the sum of the steps' dt since sph_create.  Waits. */
+sph_status sph_get_time(sph_ctx* ctx, double* t);
 
 /* Wait for the context's stream; return and clear the first latched device error. */
 sph_status sph_sync(sph_ctx* ctx);
@@ -354,10 +362,15 @@ sph_status sph_mlp_grad(sph_ctx* ctx, const float* x, const float* t, int64_t n,
 sph_status sph_mlp_eval(sph_ctx* ctx, const double* lnrho, const double* lnu, int64_t n, double* lnP,
                         double* lncs2);
 
-/* Build the trust mask: a table cell is trusted when at its four nodes and its centre the
- * network's P and c_s^2 are within relative tolerance tol of the table.  Returns the number of
- * trusted cells of (nr - 1)(nu - 1). */
+/* Build the trust mask: a table cell is trusted when the network's P and c_s^2 are within relative
+ * tolerance tol / 2 of the table at 13 points of the cell (its nodes, edge midpoints, centre and
+ * four interior points drawn per cell from a counter-based generator); the margin of 2 covers the
+ * points in between.  Returns the number of trusted cells of (nr - 1)(nu - 1). */
 sph_status sph_mlp_build_trust_mask(sph_ctx* ctx, double tol, int64_t* trusted_cells);
+
+/* Number of particles of the state whose (rho, u) lies in a trusted cell, i.e. that the network
+ * serves in an evaluation with eos = SPH_EOS_MLP (0 without a mask).  Waits. */
+sph_status sph_mlp_count_served(sph_ctx* ctx, const sph_state* st, int64_t* served);
 
 /* Human-readable name of a status code (static string). */
 const char* sph_status_string(sph_status s);

@@ -264,7 +264,8 @@ class OrcDiagParams(ctypes.Structure):
 
 class OrcDiag(ctypes.Structure):
     _fields_ = [(k, ctypes.c_double) for k in ("kinetic", "toroidal", "internal", "u_band", "slab_c0", "slab_cr",
-                                               "slab_cth")] + [("n_band", ctypes.c_int64), ("n_slab", ctypes.c_int64)]
+                                               "slab_cth")] + [("n_band", ctypes.c_int64), ("n_slab", ctypes.c_int64),
+                                                               ("tor_l2", ctypes.c_double)]
 
 
 def diagnostics(orc: Oracle, st: OracleState, r_lo, r_hi, slab_r, slab_dr, slab_th, slab_dth):

@@ -1026,7 +1026,7 @@ void orc_modify_energy(const orc_params* p, orc_state* st, const double* u_of_r,
  * described by a linear fit in r and theta; the crust shell's kinetic energy).  Radius, theta
  * and phi are taken about the origin with theta from the +z axis. */
 void orc_diagnostics(const orc_params* p, const orc_state* st, const orc_diag_params* dp, orc_diag* out) {
-  double ke = 0.0, tor = 0.0, ein = 0.0, ub = 0.0;
+  double ke = 0.0, tor = 0.0, ein = 0.0, ub = 0.0, pvf = 0.0, pff = 0.0;
   int64_t nb = 0, ns = 0;
   double M[3][3] = {{0}}, rhs[3] = {0};
   for (int64_t a = 0; a < st->n; ++a) {
@@ -1040,6 +1040,9 @@ void orc_diagnostics(const orc_params* p, const orc_state* st, const orc_diag_pa
     if (rc > 0.0) {
       const double vphi = (-y * vx + x * vy) / rc;      /* e_phi = (-sin phi, cos phi, 0) */
       tor += 0.5 * m * vphi * vphi;
+      const double f = 3.0 * (rc / r) * (z / r);       /* 3 sin(theta) cos(theta) */
+      pvf += m * vphi * f;
+      pff += m * f * f;
     }
     if (r >= dp->r_lo && r < dp->r_hi) { ub += st->u[a]; ++nb; }
     if (r > 0.0 && rc > 0.0) {
@@ -1063,6 +1066,7 @@ void orc_diagnostics(const orc_params* p, const orc_state* st, const orc_diag_pa
   out->u_band = nb > 0 ? ub / (double)nb : 0.0;
   out->n_band = nb;
   out->n_slab = ns;
+  out->tor_l2 = pff > 0.0 ? pvf / pff : 0.0;
   /* normal equations of the least-squares fit, solved by Cramer's rule */
   double det = M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
                M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);

@@ -144,12 +144,15 @@ void orc_modify_energy(const orc_params* p, orc_state* st, const double* u_of_r,
  * about the z axis, total internal energy, the mean u of the radial band [r_lo, r_hi) (radial
  * modes are read from u), and the linear least-squares fit v_theta = c0 + c_r (r - slab_r) +
  * c_th (theta - slab_th) over the slab |r - slab_r| <= slab_dr, |theta - slab_th| <= slab_dth
- * (non-radial modes).  About the origin, theta from +z.
+ * (non-radial modes), and the amplitude of the l = 2 toroidal mode, the projection of v_phi on
+ * f(theta) = 3 sin(theta) cos(theta) = -d P_2(cos theta) / d theta (the crust shell's oscillation).
+ * About the origin, theta from +z.
  * Pinned by: a linear v_theta field recovered exactly; closed-form kinetic energies. */
 typedef struct { double r_lo, r_hi, slab_r, slab_dr, slab_th, slab_dth; } orc_diag_params;
 typedef struct {
   double kinetic, toroidal, internal, u_band, slab_c0, slab_cr, slab_cth;
   int64_t n_band, n_slab;
+  double tor_l2;   /* l = 2 toroidal mode: sum m v_phi f / sum m f^2, f = 3 sin(theta) cos(theta) */
 } orc_diag;
 void orc_diagnostics(const orc_params* p, const orc_state* st, const orc_diag_params* dp, orc_diag* out);
 

@@ -68,8 +68,6 @@ sph_status check_params(sph_ctx* c, const sph_params* p) {
     return note(c, SPH_E_ARG, "energy_mode = %d", p->energy_mode);
   if (p->dtP_mode != SPH_DTP_OFF && p->dtP_mode != SPH_DTP_LAGGED) return note(c, SPH_E_ARG, "dtP_mode = %d", p->dtP_mode);
   if (!(p->cfl >= 0.0) || p->cfl > 1.0) return note(c, SPH_E_ARG, "cfl = %g outside [0, 1]", p->cfl);
-  if (p->density_mode != SPH_DENS_SUMMATION || p->energy_mode != SPH_ENERGY_PAPER || p->dtP_mode != SPH_DTP_OFF)
-    return note(c, SPH_E_ARG, "the continuity density, first-law energy and dP/dt variants are not built yet");
   return SPH_OK;
 }
 
@@ -159,7 +157,8 @@ void sph_destroy(sph_ctx* c) {
                   c->sort.hist, c->sort.rowtot, c->sort.partial, c->sort.scan_bsum, c->tile_u, c->tile_start, c->tile_cnt, c->tile_uoff,
                   c->tile_usize, c->stress_tiles, c->nbr16, c->nbr_count, c->nbr_count_sl, c->nbr16s, c->nbr_count_s, c->pos_build, c->drift_flag,
                   c->pos4, c->fv, c->fa, c->sig, c->pos4f, c->fvf,
-                  c->faf, c->sigf, c->mu, c->Y0, c->B, c->sdot, c->tovf, c->half, c->tmp, c->stars, c->status};
+                  c->faf, c->sigf, c->mu, c->Y0, c->B, c->sdot, c->tovf, c->half, c->tmp, c->stars, c->status,
+                  c->dsum, c->dDdt, c->xcoef, c->dtw, c->dtpart};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (c->drift_host) (void)hipHostFree(c->drift_host);
@@ -225,7 +224,9 @@ sph_status sph_create(const sph_params* params, void* stream, int64_t capacity, 
       (e = dalloc(&c->faf, cap)) || (e = dalloc(&c->sigf, 6 * cap)) || (e = dalloc(&c->mu, cap)) ||
       (e = dalloc(&c->Y0, cap)) || (e = dalloc(&c->B, cap)) || (e = dalloc(&c->sdot, cap)) ||
       (e = dalloc(&c->tovf, cap)) ||
-      (e = dalloc(&c->half, 10 * cap)) || (e = dalloc(&c->tmp, capw)) || (e = dalloc(&c->status, 1))) {
+      (e = dalloc(&c->half, SPH_HALF_FIELDS * cap)) || (e = dalloc(&c->tmp, capw)) || (e = dalloc(&c->status, 1)) ||
+      (e = dalloc(&c->dsum, cap)) || (e = dalloc(&c->dDdt, cap)) || (e = dalloc(&c->xcoef, 5 * cap)) ||
+      (e = dalloc(&c->dtw, 8)) || (e = dalloc(&c->dtpart, 65536))) {
     sph_destroy(c);
     return note(nullptr, e, "device scratch for capacity %lld does not fit", (long long)capacity);
   }
@@ -245,6 +246,9 @@ sph_status sph_create(const sph_params* params, void* stream, int64_t capacity, 
       hipMemsetAsync(c->nbr_count_s, 0, sizeof(int32_t) * cap, c->stream) != hipSuccess ||
       hipMemsetAsync(c->drift_flag, 0, sizeof(uint32_t), c->stream) != hipSuccess ||
       hipMemsetAsync(c->Y0, 0, sizeof(double) * cap, c->stream) != hipSuccess ||
+      hipMemsetAsync(c->dDdt, 0, sizeof(double) * cap, c->stream) != hipSuccess ||
+      hipMemsetAsync(c->xcoef, 0, sizeof(double) * 5 * cap, c->stream) != hipSuccess ||
+      launch_dt_init(c) != SPH_OK ||
       hipStreamSynchronize(c->stream) != hipSuccess) {
     sph_destroy(c);
     return note(nullptr, SPH_E_HIP, "clearing the context's counters failed");
@@ -326,6 +330,7 @@ sph_status sph_density(sph_ctx* c, sph_state* st) {
     e = launch_eos(c, st);
     timer_end(c, TIMER_EOS);
     if (e) return e;
+    if ((e = launch_dt_commit(c, (int)(c->steps_done % 3)))) return e;
   }
   c->gen = 2;
   return SPH_OK;
@@ -381,10 +386,12 @@ static sph_status capture_step(sph_ctx* c, sph_state* st, double dt) {
     }
     sph_status le = SPH_OK;
     if (which == 0) {
+      c->eval_in_step = true;   // the lagged dP/dt reads the step's dt
       if (!le) le = launch_density(c, st);
       if (!le) le = launch_eos(c, st);
       if (!le) le = launch_stress(c, st);
       if (!le) le = launch_forces(c, st);
+      c->eval_in_step = false;
     } else {
       if (!le) le = launch_flag_clear(c);
       if (!le) le = which == 1 ? launch_kick_drift(c, st, dt, 1u) : launch_kick_final_drift(c, st, dt, 1u);
@@ -440,11 +447,17 @@ static sph_status sync_positions(sph_ctx* c, sph_state* st) {
 // kick of step k of a call: kick-drift for the first, else the previous final kick fused in.
 // deferred: positions and h stay in pos4 (the state's copies are synced before a list build and
 // at the end of the call)
+// With adaptive steps (c->adaptive) step j (counted since sph_create, from 1) takes the Courant step
+// that the evaluation before it committed to slot (j - 1) % 3.
+static int dt_slot(const sph_ctx* c, int64_t j) { return c->adaptive ? (int)(j % 3) : -1; }
+
 static sph_status queue_kick(sph_ctx* c, sph_state* st, double dt, int32_t k, uint32_t check, bool deferred) {
   sph_status e;
   if (!deferred && (e = sync_positions(c, st))) return e;
   timer_begin(c, TIMER_KDK);
-  e = k == 0 ? launch_kick_drift(c, st, dt, check, deferred) : launch_kick_final_drift(c, st, dt, check, deferred);
+  const int64_t j = c->steps_done + k + 1;
+  e = k == 0 ? launch_kick_drift(c, st, dt, check, deferred, dt_slot(c, j - 1))
+             : launch_kick_final_drift(c, st, dt, check, deferred, dt_slot(c, j - 2), dt_slot(c, j - 1));
   timer_end(c, TIMER_KDK);
   if (!e && deferred) c->pos_deferred = true;
   return e;
@@ -452,8 +465,10 @@ static sph_status queue_kick(sph_ctx* c, sph_state* st, double dt, int32_t k, ui
 
 // density, EoS, stress rate and forces at the drifted positions; seq > 0: a run-ahead evaluation
 // of step number seq (cancelled on the device when the skin test of that or an earlier step failed)
-static sph_status queue_evaluation(sph_ctx* c, sph_state* st, uint32_t seq) {
+// k: the call-local step the evaluation belongs to (its Courant step goes to slot (j % 3))
+static sph_status queue_evaluation(sph_ctx* c, sph_state* st, uint32_t seq, int32_t k) {
   c->eval_seq = seq;
+  c->eval_in_step = true;
   sph_status e;
   timer_begin(c, TIMER_DENSITY);
   e = launch_density(c, st);
@@ -463,6 +478,7 @@ static sph_status queue_evaluation(sph_ctx* c, sph_state* st, uint32_t seq) {
     e = launch_eos(c, st);
     timer_end(c, TIMER_EOS);
   }
+  if (!e && c->adaptive) e = launch_dt_commit(c, dt_slot(c, c->steps_done + k + 1));
   if (!e) {
     timer_begin(c, TIMER_STRESS);
     e = launch_stress(c, st);
@@ -474,6 +490,7 @@ static sph_status queue_evaluation(sph_ctx* c, sph_state* st, uint32_t seq) {
     timer_end(c, TIMER_FORCES);
   }
   c->eval_seq = 0u;
+  c->eval_in_step = false;
   return e;
 }
 
@@ -490,7 +507,7 @@ static sph_status step_loop(sph_ctx* c, sph_state* st, double dt, int32_t nsteps
   while (k < nsteps) {
     if (!(c->lists_valid && c->p.skin > 0.0)) {   // no lists to test: build them for this step
       if ((e = queue_kick(c, st, dt, k, 0u, false)) || (e = rebuild(c, st, true)) ||
-          (e = queue_evaluation(c, st, 0u)))
+          (e = queue_evaluation(c, st, 0u, k)))
         return e;
       ++k;
       continue;
@@ -501,7 +518,7 @@ static sph_status step_loop(sph_ctx* c, sph_state* st, double dt, int32_t nsteps
     while (k < nsteps) {
       while (queued < nsteps && queued <= k + 1) {
         const uint32_t q = (uint32_t)(queued - k0 + 1);
-        if ((e = queue_kick(c, st, dt, queued, q, true)) || (e = queue_evaluation(c, st, q))) return e;
+        if ((e = queue_kick(c, st, dt, queued, q, true)) || (e = queue_evaluation(c, st, q, queued))) return e;
         HIP_TRY(hipMemcpyAsync(c->drift_host, c->drift_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(hipEventRecord(c->step_ev[queued & 1], c->stream));
         ++queued;
@@ -514,7 +531,7 @@ static sph_status step_loop(sph_ctx* c, sph_state* st, double dt, int32_t nsteps
       }
       // the drift of step v broke the skin bound; the steps queued after it did nothing
       const int32_t v = k0 + (int32_t)f - 1;
-      if ((e = sync_positions(c, st)) || (e = rebuild(c, st, true)) || (e = queue_evaluation(c, st, 0u))) return e;
+      if ((e = sync_positions(c, st)) || (e = rebuild(c, st, true)) || (e = queue_evaluation(c, st, 0u, v))) return e;
       k = v + 1;
       break;
     }
@@ -525,26 +542,36 @@ static sph_status step_loop(sph_ctx* c, sph_state* st, double dt, int32_t nsteps
 sph_status sph_step(sph_ctx* c, sph_state* st, double dt, int32_t nsteps) {
   sph_status e = check_state(c, st);
   if (e) return e;
-  if (!(dt > 0.0) || nsteps < 0) return note(c, SPH_E_ARG, "dt = %g must be positive and nsteps = %d not negative", dt, nsteps);
+  if (std::isnan(dt) || nsteps < 0) return note(c, SPH_E_ARG, "dt = %g must be a number and nsteps = %d not negative", dt, nsteps);
+  const bool adaptive = !(dt > 0.0);
+  if (adaptive && c->p.graph) return note(c, SPH_E_ARG, "graph replay needs a fixed dt > 0");
+  if (!adaptive && c->p.damping > 0.0 && c->p.damping * dt >= 1.0)
+    return note(c, SPH_E_ARG, "damping dt = %g must be below 1 (the kicks treat the drag explicitly)", c->p.damping * dt);
   if (c->gen < 4 || st->n != c->n) return note(c, SPH_E_ORDER, "sph_step needs a full evaluation (build, density, stress rate, forces) of this state first");
   if (st->n == 0) return SPH_OK;
   if (c->p.graph && !c->stream) return note(c, SPH_E_ARG, "graph replay needs a non-default stream");
   if (c->p.graph && c->p.skin > 0.0 && c->lists_valid) {
     e = step_graphs(c, st, dt, nsteps);
-    if (!e) c->gen = 4;
+    if (!e) {
+      c->gen = 4;
+      c->steps_done += nsteps;
+    }
     return e;
   }
   for (hipEvent_t& ev : c->step_ev)
     if (!ev) HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  c->adaptive = adaptive;
   e = step_loop(c, st, dt, nsteps);
   const sph_status es = sync_positions(c, st);   // also after an error: the state stays whole
-  if (e) return e;
-  if (es) return es;
-  if (nsteps > 0) {
+  if (!e && !es && nsteps > 0) {
     timer_begin(c, TIMER_KDK);
-    if ((e = launch_kick_final(c, st, dt))) return e;
+    e = launch_kick_final(c, st, dt, dt_slot(c, c->steps_done + nsteps - 1));
     timer_end(c, TIMER_KDK);
   }
+  c->adaptive = false;
+  if (e) return e;
+  if (es) return es;
+  c->steps_done += nsteps;
   c->gen = 4;
   return SPH_OK;
 }
@@ -586,9 +613,10 @@ struct StateCopy {
   }
   sph_status load(const sph_state* src, hipStream_t s) {
     const size_t n = (size_t)src->n;
-    const double* a[] = {src->x, src->y, src->z, src->vx, src->vy, src->vz, src->u, src->h};
-    double* b[] = {st.x, st.y, st.z, st.vx, st.vy, st.vz, st.u, st.h};
-    for (int k = 0; k < 8; ++k) HIP_TRY(hipMemcpyAsync(b[k], a[k], 8 * n, hipMemcpyDeviceToDevice, s));
+    // D and P too: the continuity density and the lagged dP/dt read them as state
+    const double* a[] = {src->x, src->y, src->z, src->vx, src->vy, src->vz, src->u, src->h, src->D, src->P};
+    double* b[] = {st.x, st.y, st.z, st.vx, st.vy, st.vz, st.u, st.h, st.D, st.P};
+    for (int k = 0; k < 10; ++k) HIP_TRY(hipMemcpyAsync(b[k], a[k], 8 * n, hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipMemcpyAsync(st.S, src->S, 48 * n, hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipMemcpyAsync(st.type, src->type, n, hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipMemcpyAsync(st.broken, src->broken, n, hipMemcpyDeviceToDevice, s));
@@ -741,6 +769,15 @@ sph_status sph_sync(sph_ctx* c) {
 }
 
 const char* sph_last_error_detail(const sph_ctx* c) { return c ? c->detail : g_detail; }
+
+sph_status sph_get_time(sph_ctx* c, double* t) {
+  if (!c) return note(nullptr, SPH_E_ARG, "context is NULL");
+  if (!t) return note(c, SPH_E_ARG, "t is NULL");
+  hipError_t he = hipStreamSynchronize(c->stream);
+  if (he == hipSuccess) he = hipMemcpy(t, c->dtw + 3, sizeof(double), hipMemcpyDeviceToHost);
+  if (he != hipSuccess) return note(c, SPH_E_HIP, "reading the simulated time: %s", hipGetErrorString(he));
+  return SPH_OK;
+}
 
 sph_status sph_modify_energy(sph_ctx* c, sph_state* st, const double* u_of_r, int32_t nr, double dr) {
   sph_status e = check_state(c, st);

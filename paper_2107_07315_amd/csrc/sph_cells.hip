@@ -959,7 +959,11 @@ sph_status sph_rebin(sph_ctx* c, sph_state* st, bool outputs_recomputed) {
       for (int k = 0; k < 6; ++k)
         if ((e = permute_array(c, st->dSdt + k * n, n))) return e;
     }
-    for (int k = 0; k < 10; ++k)
+    if (outputs_recomputed) {   // state that the next evaluation reads although it is an output
+      if (c->p.density_mode == SPH_DENS_CONTINUITY && (e = permute_array(c, st->D, n))) return e;
+      if (c->p.dtP_mode == SPH_DTP_LAGGED && (e = permute_array(c, st->P, n))) return e;
+    }
+    for (int k = 0; k < SPH_HALF_FIELDS; ++k)
       if ((e = permute_array(c, c->half + (int64_t)k * c->capacity, n))) return e;
     if ((e = permute_array(c, st->type, n))) return e;
     if ((e = permute_array(c, st->broken, n))) return e;

@@ -11,7 +11,7 @@ namespace {
 
 constexpr int kB = 256;
 constexpr int kMaxBlocks = 1024;
-constexpr int kSums = 16;   // ke, tor, ein, u_band, n_band, n_slab, M00 M01 M02 M11 M12 M22, r0 r1 r2, pad
+constexpr int kSums = 18;   // ke, tor, ein, u_band, n_band, n_slab, M00 M01 M02 M11 M12 M22, r0 r1 r2, pvf, pff, pad
 
 __global__ __launch_bounds__(kB) void k_diag_partials(const double* __restrict__ x, const double* __restrict__ y,
                                                       const double* __restrict__ z, const double* __restrict__ vx,
@@ -34,6 +34,9 @@ __global__ __launch_bounds__(kB) void k_diag_partials(const double* __restrict__
     if (rc > 0.0) {
       const double vphi = (-Y * VX + X * VY) / rc;   // e_phi = (-sin phi, cos phi, 0)
       s[1] += 0.5 * ma * vphi * vphi;
+      const double f = 3.0 * (rc / r) * (Z / r);     // l = 2 toroidal profile 3 sin(theta) cos(theta)
+      s[15] += ma * vphi * f;
+      s[16] += ma * f * f;
     }
     if (r >= dp.r_lo && r < dp.r_hi) {
       s[3] += u[a];
@@ -97,6 +100,7 @@ __global__ __launch_bounds__(64) void k_diag_final(const double* __restrict__ pa
   d.n_band = (int64_t)tot[4];
   d.u_band = tot[4] > 0.0 ? tot[3] / tot[4] : 0.0;
   d.n_slab = (int64_t)tot[5];
+  d.tor_l2 = tot[16] > 0.0 ? tot[15] / tot[16] : 0.0;
   const double M00 = tot[6], M01 = tot[7], M02 = tot[8], M11 = tot[9], M12 = tot[10], M22 = tot[11];
   const double r0 = tot[12], r1 = tot[13], r2 = tot[14];
   const double det = det3(M00, M01, M02, M01, M11, M12, M02, M12, M22);

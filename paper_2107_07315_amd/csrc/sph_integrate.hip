@@ -32,7 +32,17 @@ struct KdkArgs {
   // positions and h read from and written to pos4 only (inside a multi-step call the public
   // x, y, z, h are brought up to date once, before a list build and at the end of the call)
   bool deferred;
+  // continuity density: D is integrated with the rate of the last evaluation
+  bool cont;
+  double* Dst;
+  const double* dDdt;
+  // time step: fixed dt, or (adaptive) the Courant steps committed in dtw[slot]; the kick-drift
+  // adds its dt to the simulated time dtw[3] and records it in dtw[5]
+  double* dtw;
+  int slot_fin, slot_drift;   // < 0: fixed dt
 };
+
+__device__ __forceinline__ double dt_of(const KdkArgs& K, int slot) { return slot >= 0 ? K.dtw[slot] : K.dt; }
 
 // a kick of a step that runs ahead of a failed skin test does nothing
 __device__ __forceinline__ bool kick_cancelled(const KdkArgs& K) {
@@ -54,8 +64,9 @@ __device__ __forceinline__ double wrap(double q, int periodic, double box) {
 // and runs the skin test.  Type-0 particles carry no deviatoric stress (S and its rate are zero,
 // set at every list build), so their stress arrays are neither read nor written.
 __device__ __forceinline__ void kick_drift_from(const KdkArgs& K, int64_t a, const double x0[3], const double v0[3],
-                                                double u0, const double S0[6], double h, bool solid) {
-  const double hdt = 0.5 * K.dt;
+                                                double u0, const double S0[6], double h, bool solid, double D0) {
+  const double dt = dt_of(K, K.slot_drift);
+  const double hdt = 0.5 * dt;
   const int64_t n = K.n, hs = K.hstride;
   double* H = K.half;
   const double ax = K.ax[a], ay = K.ay[a], az = K.az[a], du = K.dudt[a];
@@ -73,9 +84,19 @@ __device__ __forceinline__ void kick_drift_from(const KdkArgs& K, int64_t a, con
   H[1 * hs + a] = vh[1];
   H[2 * hs + a] = vh[2];
   H[3 * hs + a] = uh;
-  const double xn = wrap(x0[0] + K.dt * vh[0], K.p.periodic, K.p.box);
-  const double yn = wrap(x0[1] + K.dt * vh[1], K.p.periodic, K.p.box);
-  const double zn = wrap(x0[2] + K.dt * vh[2], K.p.periodic, K.p.box);
+  if (K.cont) {   // eq. solid1: half kick and predictor of the computational density
+    const double dd = K.dDdt[a];
+    const double Dh = D0 + hdt * dd;
+    H[10 * hs + a] = Dh;
+    K.Dst[a] = Dh + hdt * dd;
+  }
+  if (a == 0) {   // one lane records the step's dt and advances the simulated time
+    K.dtw[5] = dt;
+    K.dtw[3] += dt;
+  }
+  const double xn = wrap(x0[0] + dt * vh[0], K.p.periodic, K.p.box);
+  const double yn = wrap(x0[1] + dt * vh[1], K.p.periodic, K.p.box);
+  const double zn = wrap(x0[2] + dt * vh[2], K.p.periodic, K.p.box);
   if (!K.deferred) {
     K.x[a] = xn;
     K.y[a] = yn;
@@ -111,8 +132,8 @@ __device__ __forceinline__ void kick_drift_from(const KdkArgs& K, int64_t a, con
 // Second half kick of particle a from the half-step copies: end-of-step v, u and S (yield scaling
 // and the breaking test applied; breaking is recorded), and the adaptive h of the step's density.
 __device__ __forceinline__ void final_kick_of(const KdkArgs& K, int64_t a, double v[3], double& u, double s[6],
-                                              double& h, bool solid) {
-  const double hdt = 0.5 * K.dt;
+                                              double& h, bool solid, double& D) {
+  const double hdt = 0.5 * dt_of(K, K.slot_fin);
   const int64_t n = K.n, hs = K.hstride;
   const double* H = K.half;
   v[0] = H[0 * hs + a] + hdt * K.ax[a];
@@ -141,9 +162,10 @@ __device__ __forceinline__ void final_kick_of(const KdkArgs& K, int64_t a, doubl
       }
     }
   }
+  D = K.cont ? H[10 * hs + a] + hdt * K.dDdt[a] : K.D[a];   // the end-of-step density
   if (K.p.h_mode == SPH_H_ADAPTIVE) {
     double m = (K.star && K.stars) ? K.stars[K.star[a]].m : K.p.m;
-    h = K.p.eta * cbrt(m / K.D[a]);
+    h = K.p.eta * cbrt(m / D);
   } else {
     h = K.h[a];   // constant h: the state's value is always current
   }
@@ -161,7 +183,7 @@ __global__ __launch_bounds__(kB) void k_kick_drift(KdkArgs K) {
   double S0[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (solid)
     for (int c = 0; c < 6; ++c) S0[c] = K.S[c * n + a];
-  kick_drift_from(K, a, x0, v0, K.u[a], S0, K.h[a], solid);
+  kick_drift_from(K, a, x0, v0, K.u[a], S0, K.h[a], solid, K.cont ? K.Dst[a] : 0.0);
 }
 
 // second half kick: end-of-step state
@@ -170,8 +192,9 @@ __global__ __launch_bounds__(kB) void k_kick_final(KdkArgs K) {
   if (a >= K.n) return;
   const int64_t n = K.n;
   const bool solid = K.type[a] == 1;
-  double v[3], u, s[6], h;
-  final_kick_of(K, a, v, u, s, h, solid);
+  double v[3], u, s[6], h, D;
+  final_kick_of(K, a, v, u, s, h, solid, D);
+  if (K.cont) K.Dst[a] = D;
   K.vx[a] = v[0];
   K.vy[a] = v[1];
   K.vz[a] = v[2];
@@ -194,10 +217,10 @@ __global__ __launch_bounds__(kB) void k_kick_final_drift(KdkArgs K) {
   } else {
     x0[0] = K.x[a]; x0[1] = K.y[a]; x0[2] = K.z[a];
   }
-  double v[3], u, s[6], h;
-  final_kick_of(K, a, v, u, s, h, solid);
+  double v[3], u, s[6], h, D;
+  final_kick_of(K, a, v, u, s, h, solid, D);
   if (!K.deferred) K.h[a] = h;
-  kick_drift_from(K, a, x0, v, u, s, h, solid);
+  kick_drift_from(K, a, x0, v, u, s, h, solid, D);
 }
 
 KdkArgs make_kdk(sph_ctx* c, sph_state* st, double dt) {
@@ -224,6 +247,11 @@ KdkArgs make_kdk(sph_ctx* c, sph_state* st, double dt) {
   K.check_id = c->check_id;
   K.flag = nullptr;
   K.deferred = false;
+  K.cont = c->p.density_mode == SPH_DENS_CONTINUITY;
+  K.Dst = st->D;
+  K.dDdt = c->dDdt;
+  K.dtw = c->dtw;
+  K.slot_fin = K.slot_drift = -1;
   return K;
 }
 
@@ -241,6 +269,26 @@ __global__ __launch_bounds__(kB) void k_unpack_pos(const double4* __restrict__ p
 }
 
 __global__ void k_flag_clear(uint32_t* f) { *f = 0u; }   // a kernel, not a memset: graph-safe
+
+// Courant step of an evaluation: dtw[slot] = cfl * min_a h_a / (c_L,a + |v_a|) from the per-block
+// minima of the density epilogue (one workgroup, a fixed reduction order).
+__global__ __launch_bounds__(256) void k_dt_commit(double* __restrict__ dtw, int slot, double cfl,
+                                                   const double* __restrict__ part, int nb) {
+  __shared__ double red[256];
+  double m = __builtin_inf();
+  for (int b = threadIdx.x; b < nb; b += 256) m = part[b] < m ? part[b] : m;
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = red[threadIdx.x + s] < red[threadIdx.x] ? red[threadIdx.x + s] : red[threadIdx.x];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) dtw[slot] = cfl * red[0];
+}
+
+__global__ void k_dt_init(double* dtw) {
+  if (threadIdx.x < 8) dtw[threadIdx.x] = 0.0;
+}
 
 // Modification step: u from the profile u(r) of the real EoS at the particle's distance from its
 // star centre (linear in the table, its last entry beyond it), velocity zeroed.
@@ -283,14 +331,29 @@ sph_status launch_modify_energy(sph_ctx* c, sph_state* st, const double* u_of_r,
   return SPH_OK;
 }
 
+sph_status launch_dt_commit(sph_ctx* c, int slot) {
+  if (c->eos_blocks <= 0) return SPH_OK;
+  hipLaunchKernelGGL(k_dt_commit, dim3(1), dim3(256), 0, c->stream, c->dtw, slot, c->p.cfl > 0.0 ? c->p.cfl : 0.3,
+                     c->dtpart, c->eos_blocks);
+  HIP_TRY(hipGetLastError());
+  return SPH_OK;
+}
+
+sph_status launch_dt_init(sph_ctx* c) {
+  hipLaunchKernelGGL(k_dt_init, dim3(1), dim3(64), 0, c->stream, c->dtw);
+  HIP_TRY(hipGetLastError());
+  return SPH_OK;
+}
+
 sph_status launch_flag_clear(sph_ctx* c) {
   hipLaunchKernelGGL(k_flag_clear, dim3(1), dim3(1), 0, c->stream, c->drift_flag);
   HIP_TRY(hipGetLastError());
   return SPH_OK;
 }
 
-sph_status launch_kick_drift(sph_ctx* c, sph_state* st, double dt, uint32_t check, bool deferred) {
+sph_status launch_kick_drift(sph_ctx* c, sph_state* st, double dt, uint32_t check, bool deferred, int slot) {
   KdkArgs K = make_kdk(c, st, dt);
+  K.slot_drift = slot;
   if (check) { K.flag = c->drift_flag; K.check_id = check; }
   K.deferred = deferred;
   hipLaunchKernelGGL(k_kick_drift, dim3(grid_for(st->n, kB)), dim3(kB), 0, c->stream, K);
@@ -298,8 +361,11 @@ sph_status launch_kick_drift(sph_ctx* c, sph_state* st, double dt, uint32_t chec
   return SPH_OK;
 }
 
-sph_status launch_kick_final_drift(sph_ctx* c, sph_state* st, double dt, uint32_t check, bool deferred) {
+sph_status launch_kick_final_drift(sph_ctx* c, sph_state* st, double dt, uint32_t check, bool deferred, int slot_fin,
+                                   int slot_drift) {
   KdkArgs K = make_kdk(c, st, dt);
+  K.slot_fin = slot_fin;
+  K.slot_drift = slot_drift;
   if (check) { K.flag = c->drift_flag; K.check_id = check; }
   K.deferred = deferred;
   hipLaunchKernelGGL(k_kick_final_drift, dim3(grid_for(st->n, kB)), dim3(kB), 0, c->stream, K);
@@ -314,8 +380,9 @@ sph_status launch_unpack_pos(sph_ctx* c, sph_state* st) {
   return SPH_OK;
 }
 
-sph_status launch_kick_final(sph_ctx* c, sph_state* st, double dt) {
+sph_status launch_kick_final(sph_ctx* c, sph_state* st, double dt, int slot) {
   KdkArgs K = make_kdk(c, st, dt);
+  K.slot_fin = slot;
   hipLaunchKernelGGL(k_kick_final, dim3(grid_for(st->n, kB)), dim3(kB), 0, c->stream, K);
   HIP_TRY(hipGetLastError());
   return SPH_OK;

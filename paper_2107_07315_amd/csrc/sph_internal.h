@@ -380,6 +380,18 @@ struct sph_ctx {
   unsigned long long* stats_scratch;
   // per-block partial sums of sph_diagnostics (allocated on first use)
   double* diag_part;
+  // method variants
+  double* dsum;         // summation density while D is integrated (continuity density)
+  double* dDdt;         // sum m (v_a - v_b) . grad_a W of the last evaluation
+  double* xcoef;        // per particle, SoA 5 x capacity: first-law energy e0, e1, e2; dP/dt row q, k
+  // time-step words (device): [0..2] Courant steps committed by evaluations (slot = step % 3),
+  // [3] simulated time, [5] dt of the step in progress
+  double* dtw;
+  double* dtpart;       // per-block minima of h / (c_L + |v|) of the last density epilogue
+  int eos_blocks;       // blocks of that epilogue that wrote dtpart (0: none)
+  int64_t steps_done;   // steps completed since sph_create (slot bookkeeping of the Courant steps)
+  bool adaptive;        // inside an sph_step call with Courant steps
+  bool eval_in_step;    // an evaluation queued by sph_step (the lagged dP/dt reads that step's dt)
 };
 
 // Records a human-readable reason for a failing return (sph_last_error_detail; c may be NULL for
@@ -401,14 +413,22 @@ sph_status launch_forces(sph_ctx* c, sph_state* st);
 // value already in the flag, left by an earlier step's failed test, cancels the kick)
 // deferred: positions and h are read from and written to pos4 only (st->x, y, z, h lag behind
 // until launch_unpack_pos)
-sph_status launch_kick_drift(sph_ctx* c, sph_state* st, double dt, uint32_t check, bool deferred = false);
-sph_status launch_kick_final(sph_ctx* c, sph_state* st, double dt);
+// slot: the Courant-step word the kick reads (adaptive steps), or -1 for the fixed dt
+sph_status launch_kick_drift(sph_ctx* c, sph_state* st, double dt, uint32_t check, bool deferred = false,
+                             int slot = -1);
+sph_status launch_kick_final(sph_ctx* c, sph_state* st, double dt, int slot = -1);
 // the final kick of one step fused with the kick-drift of the next (inside a multi-step call)
-sph_status launch_kick_final_drift(sph_ctx* c, sph_state* st, double dt, uint32_t check, bool deferred = false);
+sph_status launch_kick_final_drift(sph_ctx* c, sph_state* st, double dt, uint32_t check, bool deferred = false,
+                                   int slot_fin = -1, int slot_drift = -1);
 // st->x, y, z, h from pos4 (after deferred kicks)
 sph_status launch_unpack_pos(sph_ctx* c, sph_state* st);
 sph_status launch_pack(sph_ctx* c, sph_state* st);
 sph_status launch_modify_energy(sph_ctx* c, sph_state* st, const double* u_of_r, int32_t nr, double dr);
+// after an evaluation's epilogue: dtw[slot] = cfl * the minimum over its per-block partials
+sph_status launch_dt_commit(sph_ctx* c, int slot);
+sph_status launch_dt_init(sph_ctx* c);
+// half-step copies per particle: vx, vy, vz, u, S[6], D (continuity density)
+#define SPH_HALF_FIELDS 11
 sph_status sph_count_stats(sph_ctx* c, sph_list_stats* out);
 // looks up (once per device, with that device current) the device address of the statistics
 // scratch array and stores it in the context

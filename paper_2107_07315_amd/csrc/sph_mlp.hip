@@ -20,6 +20,7 @@ struct MlpState {
   float* gsum = nullptr;   // summed gradient (sph_mlp_grad)
   float* scal = nullptr;   // [0] loss of the last step
   uint8_t* trust = nullptr;
+  unsigned long long* served = nullptr;   // counter of sph_mlp_count_served
   int64_t trust_cells = 0;
   int64_t step = 0;        // Adam steps taken
   bool loaded = false;
@@ -359,8 +360,20 @@ __global__ __launch_bounds__(64) void k_mlp_eval(MlpView M, const double* __rest
   }
 }
 
-// Trust mask: a table cell is trusted when, at its four nodes and its centre, the network's P and
-// c_s^2 are within relative tolerance tol of the table.
+// Interior test points of a table cell: four per cell from a counter-based generator (splitmix64
+// of the cell index and the point number), fractions in [0, 1).
+__device__ __forceinline__ double cell_uniform(uint64_t cell, int k) {
+  uint64_t z = cell * 16u + (uint64_t)k + 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  z ^= z >> 31;
+  return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// Trust mask: a table cell is trusted when the network's P and c_s^2 are within relative tolerance
+// tol / 2 (a margin of 2 for the points in between) of the table at 13 points of the cell: its four
+// nodes, the four edge midpoints, the centre and four seeded interior points.
+constexpr int kTrustPoints = 13;
 __global__ __launch_bounds__(64) void k_mlp_trust(MlpView M, sph_params p, double tol, uint8_t* __restrict__ mask,
                                                   unsigned long long* count) {
   const MlpNorm& nm = M.norm;
@@ -373,18 +386,20 @@ __global__ __launch_bounds__(64) void k_mlp_trust(MlpView M, sph_params p, doubl
     const int i = ok ? (int)(c / nu1) : 0, j = ok ? (int)(c % nu1) : 0;
     double err = 0.0;
     bool finite = true;
-    const double fa[5] = {0.0, 1.0, 0.0, 1.0, 0.5}, fb[5] = {0.0, 0.0, 1.0, 1.0, 0.5};
+    const double fa9[9] = {0.0, 1.0, 0.0, 1.0, 0.5, 0.5, 0.0, 1.0, 0.5}, fb9[9] = {0.0, 0.0, 1.0, 1.0, 0.0, 1.0, 0.5, 0.5, 0.5};
 #pragma unroll 1
-    for (int k = 0; k < 5; ++k) {
-      const double lnr = p.tab_lnr0 + ((double)i + fa[k]) * p.tab_dlnr;
-      const double lnu = p.tab_lnu0 + ((double)j + fb[k]) * p.tab_dlnu;
+    for (int k = 0; k < kTrustPoints; ++k) {
+      const double fak = k < 9 ? fa9[k] : cell_uniform((uint64_t)c, 2 * k);
+      const double fbk = k < 9 ? fb9[k] : cell_uniform((uint64_t)c, 2 * k + 1);
+      const double lnr = p.tab_lnr0 + ((double)i + fak) * p.tab_dlnr;
+      const double lnu = p.tab_lnu0 + ((double)j + fbk) * p.tab_dlnu;
       float y0 = 0.f, y1 = 0.f;
       mlp_wave(M, (float)((lnr - nm.in_lo[0]) * nm.in_sc[0] - 1.0), (float)((lnu - nm.in_lo[1]) * nm.in_sc[1] - 1.0),
                y0, y1);
       const int64_t o = (int64_t)i * p.tab_nu + j;
       double tp, tc;
-      finite = finite && table_bilinear(p.tab_lnP, o, p.tab_nu, fa[k], fb[k], tp) &&
-               table_bilinear(p.tab_lncs2, o, p.tab_nu, fa[k], fb[k], tc);
+      finite = finite && table_bilinear(p.tab_lnP, o, p.tab_nu, fak, fbk, tp) &&
+               table_bilinear(p.tab_lncs2, o, p.tab_nu, fak, fbk, tc);
       if (finite) {
         const double ep = fabs(expm1((double)y0 * nm.out_sc[0] + nm.out_c[0] - tp));
         const double ec = fabs(expm1((double)y1 * nm.out_sc[1] + nm.out_c[1] - tc));
@@ -392,7 +407,7 @@ __global__ __launch_bounds__(64) void k_mlp_trust(MlpView M, sph_params p, doubl
       }
     }
     if (ok) {
-      const bool t = finite && err <= tol;
+      const bool t = finite && err <= 0.5 * tol;
       mask[c] = t ? 1 : 0;
       good += t ? 1ull : 0ull;
     }
@@ -494,7 +509,7 @@ int64_t mlp_trusted_cells(const sph_ctx* c) {
 void mlp_free(sph_ctx* c) {
   MlpState* s = c->mlp;
   if (!s) return;
-  void* bufs[] = {s->w, s->wr, s->m, s->v, s->pack, s->gpart, s->lpart, s->gsum, s->scal, s->trust};
+  void* bufs[] = {s->w, s->wr, s->m, s->v, s->pack, s->gpart, s->lpart, s->gsum, s->scal, s->trust, s->served};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete s;
@@ -649,6 +664,24 @@ sph_status sph_mlp_eval(sph_ctx* c, const double* lnrho, const double* lnu, int6
   return SPH_OK;
 }
 
+// Particles whose (rho, u) lies in a trusted table cell (those the EoS network serves).
+__global__ __launch_bounds__(256) void k_mlp_served(const double* __restrict__ rho, const double* __restrict__ u,
+                                                    int64_t n, sph_params p, const uint8_t* __restrict__ trust,
+                                                    unsigned long long* __restrict__ count) {
+  unsigned long long k = 0;
+  for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < n; a += (int64_t)gridDim.x * blockDim.x) {
+    if (!(rho[a] > 0.0) || !(u[a] > 0.0)) continue;
+    const double fr = (log(rho[a]) - p.tab_lnr0) / p.tab_dlnr, fu = (log(u[a]) - p.tab_lnu0) / p.tab_dlnu;
+    if (!(fr >= 0.0) || !(fu >= 0.0) || fr > (double)(p.tab_nr - 1) || fu > (double)(p.tab_nu - 1)) continue;
+    int i = (int)floor(fr), j = (int)floor(fu);
+    i = i > p.tab_nr - 2 ? p.tab_nr - 2 : i;
+    j = j > p.tab_nu - 2 ? p.tab_nu - 2 : j;
+    k += trust[(int64_t)i * (p.tab_nu - 1) + j] ? 1ull : 0ull;
+  }
+  for (int off = 32; off > 0; off >>= 1) k += __shfl_xor(k, off, 64);
+  if ((threadIdx.x & 63) == 0) atomicAdd(count, k);
+}
+
 sph_status sph_mlp_build_trust_mask(sph_ctx* c, double tol, int64_t* trusted_cells) {
   if (!c || !(tol >= 0.0) || !c->mlp || !c->mlp->loaded || !table_ok(c)) return SPH_E_ARG;
   MlpState* s = c->mlp;
@@ -680,3 +713,27 @@ sph_status sph_mlp_build_trust_mask(sph_ctx* c, double tol, int64_t* trusted_cel
 }
 
 }  // extern "C"
+
+extern "C" sph_status sph_mlp_count_served(sph_ctx* c, const sph_state* st, int64_t* served) {
+  if (!c) return note(nullptr, SPH_E_ARG, "context is NULL");
+  if (!st || !served) return note(c, SPH_E_ARG, "state and served must not be NULL");
+  *served = 0;
+  if (!c->mlp || !c->mlp->trust || st->n <= 0) return SPH_OK;
+  if (!st->rho || !st->u) return note(c, SPH_E_ARG, "the count needs rho and u");
+  unsigned long long* cnt = c->mlp->served;
+  if (!cnt && hipMalloc((void**)&c->mlp->served, sizeof(unsigned long long)) != hipSuccess) {
+    c->mlp->served = nullptr;
+    return note(c, SPH_E_OOM, "served counter");
+  }
+  cnt = c->mlp->served;
+  unsigned long long h = 0;
+  HIP_TRY(hipMemcpyAsync(cnt, &h, sizeof(h), hipMemcpyHostToDevice, c->stream));
+  unsigned nb = grid_for(st->n, 256);
+  nb = nb < 1024 ? nb : 1024;
+  hipLaunchKernelGGL(k_mlp_served, dim3(nb), dim3(256), 0, c->stream, st->rho, st->u, st->n, c->p, c->mlp->trust, cnt);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  *served = (int64_t)h;
+  return SPH_OK;
+}

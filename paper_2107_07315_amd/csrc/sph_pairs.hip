@@ -300,7 +300,13 @@ __device__ __forceinline__ int eos_mlp(const MlpView& M, const sph_params& p, do
 
 // ---- density --------------------------------------------------------------------------------
 struct DensOut {
-  double *D, *rho, *P, *cs, *mu, *Y0, *B;
+  double *D, *rho, *P, *cs, *mu, *Y0, *B;   // D: where the pair loop writes the summation density
+  const double* Dread;   // the D the epilogue uses: the summed one, or the integrated one (continuity)
+  double* xcoef;         // SoA 5 x xs: first-law energy e0, e1, e2; dP/dt row q, k
+  int64_t xs;
+  double* dtpart;        // per-block minimum of h / (c_L + |v|) (Courant step), or nullptr
+  const double* dtw;     // time-step words (dtw[5]: dt of the step in progress)
+  int in_step;           // the evaluation belongs to a step (the lagged dP/dt applies)
   double4* tov;     // fixed-background force coefficients (TOV background only)
   double4* fv;
   double2* fa;
@@ -412,6 +418,32 @@ __device__ __forceinline__ void density_epilogue(const PassArgs& A, int64_t a, b
     mu = (p.mu_mode == SPH_MU_PFACTOR) ? fac * P : p.mu_const;
   }
   const double E = mu > 0.0 ? 9.0 * Bm * mu / (3.0 * Bm + mu) : 0.0;
+  if (p.energy_mode == SPH_ENERGY_FIRST_LAW) {
+    // du/dt = (P / rho^2) drho/dt along the path with rho = D / (psi^6 W_L):
+    //   (P / (rho D)) dD/dt - (P / rho) [6 (psi'/psi)(n.v) + dln W_L/dt],
+    //   dln W_L/dt = W_L^2 / 2 [(4 psi^3 psi' (n.v) v^2 + 2 psi^4 v.a) / alpha^2 - 2 psi^4 v^2 alpha' (n.v) / alpha^3];
+    // the force pass adds e0 dD/dt + e1 + e2 v.a to the viscous heating and the stress work
+    double e0 = P / (rho * D), e1 = 0.0, e2 = 0.0;
+    if (tov) {
+      const double nv = g.n[0] * va[0] + g.n[1] * va[1] + g.n[2] * va[2];
+      const double ia2 = 1.0 / (g.alpha * g.alpha);
+      const double Pr = P / rho;
+      e1 = -Pr * (6.0 * g.dpsi / g.psi * nv +
+                  0.5 * WL * WL * (4.0 * psi2 * g.psi * g.dpsi * nv * v2 * ia2 - 2.0 * psi4 * v2 * g.dalpha * nv * ia2 / g.alpha));
+      e2 = -Pr * WL * WL * psi4 * ia2;
+    }
+    O.xcoef[a] = e0;
+    O.xcoef[O.xs + a] = e1;
+    O.xcoef[2 * O.xs + a] = e2;
+  }
+  if (p.dtP_mode == SPH_DTP_LAGGED && tov) {
+    // the dP/dt entry of the trajectory equation, -v^i dP/dt / (W_L^2 rho h), with dP/dt at fixed
+    // position = (P - P_prev) / dt_step - v . grad P; the force pass supplies v . grad P
+    const double dtp = O.in_step ? O.dtw[5] : 0.0;
+    const double kt = dtp > 0.0 ? 1.0 / (WL * WL * rho * hfac) : 0.0;
+    O.xcoef[3 * O.xs + a] = dtp > 0.0 ? kt * (P - O.P[a]) / dtp : 0.0;   // O.P still holds P_prev
+    O.xcoef[4 * O.xs + a] = kt;
+  }
   O.rho[a] = rho;   // D stays as the pair loop wrote it
   O.P[a] = P;
   O.cs[a] = cs;
@@ -584,11 +616,27 @@ __global__ __launch_bounds__(64) void k_density_epilogue(PassArgs A, const doubl
                                                          const double* __restrict__ S, const int8_t* __restrict__ type,
                                                          const uint8_t* __restrict__ broken, DensOut O) {
   const int64_t n = cancelled(A) ? 0 : A.n;
+  double qmin = __builtin_inf();
   for (int64_t base = (int64_t)blockIdx.x * 64; base < n; base += (int64_t)gridDim.x * 64) {
     const int64_t a = base + threadIdx.x;
     const bool valid = a < n;
     const int64_t ae = valid ? a : base;   // lanes past the end work on a valid particle, store nothing
-    density_epilogue<R, MLP>(A, ae, valid, O.D[ae], pos64, vx, vy, vz, u, S, type, broken, O);
+    density_epilogue<R, MLP>(A, ae, valid, O.Dread[ae], pos64, vx, vy, vz, u, S, type, broken, O);
+    if (O.dtpart && valid) {   // Courant step: h / (c_L + |v|), c_L^2 = c_s^2 + 4 mu / (3 rho)
+      const double cs = O.cs[a], rh = O.rho[a];
+      const double mu = type[a] == 1 ? O.mu[a] : 0.0;
+      const double cl = sqrt(cs * cs + 4.0 * mu / (3.0 * rh));
+      const double vm = sqrt(vx[a] * vx[a] + vy[a] * vy[a] + vz[a] * vz[a]);
+      const double q = pos64[a].w / (cl + vm);
+      qmin = q < qmin ? q : qmin;
+    }
+  }
+  if (O.dtpart) {
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(qmin, off, 64);
+      qmin = o < qmin ? o : qmin;
+    }
+    if (threadIdx.x == 0) O.dtpart[blockIdx.x] = qmin;
   }
 }
 
@@ -708,7 +756,11 @@ __global__ __launch_bounds__(64 * L) void k_stress(PassArgs A, const typename Re
 struct ForceOut {
   double *ax, *ay, *az, *dudt;
   const double4* pos64;                  // FP64 positions (external potential)
-  const double *vx, *vy, *vz;            // velocities of the evaluation (drag)
+  const double *vx, *vy, *vz;            // velocities of the evaluation (drag, variants)
+  double* dDdt;                          // sum m (v_a - v_b) . grad_a W (continuity density)
+  const double* xcoef;                   // first-law and dP/dt coefficients of the epilogue
+  int64_t xs;
+  const double* D;                       // FP64 computational density
 };
 
 // External effective potential (g_eff = -grad phi_eff along the radius from the star centre,
@@ -745,7 +797,8 @@ __device__ __forceinline__ void ext_accel(const PassArgs& A, const ForceOut& O, 
 
 // Lane g of the L-wave workgroup walks the exact slot list (g / L, g % L); the partial sums of a
 // target's L lanes are added before the fixed-background epilogue.
-template <typename R, int KER, bool PER, int L>
+// GP: also sum v_a . (P_a/D_a^2 + P_b/D_b^2) grad_a W (the advection of P in the lagged dP/dt row)
+template <typename R, int KER, bool PER, int L, bool GP>
 __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Rec<R>::P4* __restrict__ pos,
                                                    const typename Rec<R>::V4* __restrict__ fv,
                                                    const typename Rec<R>::A2* __restrict__ fa,
@@ -783,7 +836,7 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
 #pragma unroll
     for (int c = 0; c < 6; ++c) sa[c] = sig[c * n + a];
   const R alpha_v = (R)p.visc_alpha, beta_v = (R)p.visc_beta, eps_v = (R)p.visc_eps;
-  R AP[3] = {0, 0, 0}, AS[3] = {0, 0, 0}, ud = 0;
+  R AP[3] = {0, 0, 0}, AS[3] = {0, 0, 0}, ud = 0, dd = 0, gp = 0;
   // pair with union member loc, whose records sit in LDS slot j
   auto pair = [&](int loc, int j) {
     const P4 pb = sp[j];
@@ -811,7 +864,10 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
     AP[0] += cPF * d[0];
     AP[1] += cPF * d[1];
     AP[2] += cPF * d[2];
-    ud += (pia + (R)0.5 * Pi) * (F * vr);   // v_ab . grad_a W = F (v_ab . d)
+    const R Fvr = F * vr;                   // v_ab . grad_a W = F (v_ab . d)
+    ud += (pia + (R)0.5 * Pi) * Fvr;
+    dd += Fvr;
+    if constexpr (GP) gp += (pia + fab.x) * F * (va.x * d[0] + va.y * d[1] + va.z * d[2]);
     if (a_st || b_st) {
       const R g[3] = {F * d[0], F * d[1], F * d[2]};
       R s6[6];
@@ -855,6 +911,8 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
     AS[i] = lane_group_sum<L>(AS[i]);
   }
   ud = lane_group_sum<L>(ud);
+  dd = lane_group_sum<L>(dd);
+  if constexpr (GP) gp = lane_group_sum<L>(gp);
   if (!tw.valid || sub != 0) continue;
   const double m = particle_mass(A, a) * kern_F_const<KER>();
   double APd[3] = {m * (double)AP[0], m * (double)AP[1], m * (double)AP[2]};
@@ -871,7 +929,25 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
     for (int i = 0; i < 3; ++i) acc[i] = -APd[i] + ASd[i];   // eq. solid2
   }
   if (p.ext == SPH_EXT_RADIAL || p.wall_in > 0.0 || p.wall_out > 0.0 || p.damping > 0.0) ext_accel(A, O, a, acc);
-  const double du = m * (double)ud + sdot[a];                  // eq. solid3
+  const double md = m * (double)dd;                            // sum m v_ab . grad_a W
+  O.dDdt[a] = md;
+  if constexpr (GP) {   // dP/dt row: -v^i k (P - P_prev) / dt + v^i k v . grad P, grad P ~ D A^P
+    const double kt = O.xcoef[4 * O.xs + a];
+    if (kt != 0.0) {
+      const double q = O.xcoef[3 * O.xs + a] - kt * O.D[a] * m * (double)gp;
+      acc[0] -= O.vx[a] * q;
+      acc[1] -= O.vy[a] * q;
+      acc[2] -= O.vz[a] * q;
+    }
+  }
+  double du;
+  if (p.energy_mode == SPH_ENERGY_FIRST_LAW) {   // first law: e0 dD/dt + e1 + e2 v.a + heating + work
+    const double va_dot = O.vx[a] * acc[0] + O.vy[a] * acc[1] + O.vz[a] * acc[2];
+    du = O.xcoef[a] * md + m * ((double)ud - (double)pia * (double)dd) + O.xcoef[O.xs + a] +
+         O.xcoef[2 * O.xs + a] * va_dot + sdot[a];
+  } else {
+    du = m * (double)ud + sdot[a];                             // eq. solid3
+  }
   O.ax[a] = acc[0];
   O.ay[a] = acc[1];
   O.az[a] = acc[2];
@@ -941,9 +1017,26 @@ static void dispatch_lanes(int lanes, Fn&& f) {
   else f(std::integral_constant<int, 1>{});
 }
 
+static DensOut dens_out(sph_ctx* c, sph_state* st) {
+  DensOut O{};
+  // the pair loop writes the summation density; with the continuity density D is state and the
+  // sum goes to scratch
+  O.D = c->p.density_mode == SPH_DENS_CONTINUITY ? c->dsum : st->D;
+  O.rho = st->rho; O.P = st->P; O.cs = st->cs; O.mu = c->mu; O.Y0 = c->Y0; O.B = c->B; O.tov = c->tovf;
+  O.fv = c->fv; O.fa = c->fa; O.sig = c->sig; O.fvf = c->fvf; O.faf = c->faf; O.sigf = c->sigf;
+  O.Dread = st->D;
+  O.xcoef = c->xcoef;
+  O.xs = c->capacity;
+  // Courant minima: stage calls (sph_density) and steps with the adaptive dt
+  O.dtpart = (!c->eval_in_step || c->adaptive) ? c->dtpart : nullptr;
+  O.dtw = c->dtw;
+  O.in_step = c->eval_in_step ? 1 : 0;
+  return O;
+}
+
 sph_status launch_density(sph_ctx* c, sph_state* st) {
   PassArgs A = make_args(c, st);
-  DensOut O{st->D, st->rho, st->P, st->cs, c->mu, c->Y0, c->B, c->tovf, c->fv, c->fa, c->sig, c->fvf, c->faf, c->sigf};
+  DensOut O = dens_out(c, st);
   const dim3 g = pass_grid(c);
   const bool f32 = c->p.precision == SPH_FP32;
   dispatch_cfg(c->p.kernel, c->p.periodic, [&](auto K, auto P) {
@@ -966,12 +1059,13 @@ sph_status launch_density(sph_ctx* c, sph_state* st) {
 
 sph_status launch_eos(sph_ctx* c, sph_state* st) {
   PassArgs A = make_args(c, st);
-  DensOut O{st->D, st->rho, st->P, st->cs, c->mu, c->Y0, c->B, c->tovf, c->fv, c->fa, c->sig, c->fvf, c->faf, c->sigf};
+  DensOut O = dens_out(c, st);
   const bool f32 = c->p.precision == SPH_FP32;
   // the network path only where some table cell is trusted; with none, every particle takes the
   // table (the same values), so the table kernel runs
   const bool mlp = c->p.eos == SPH_EOS_MLP && A.has_mlp && mlp_trusted_cells(c) > 0;
   const unsigned nb = (unsigned)((st->n + 63) / 64 < 65536 ? (st->n + 63) / 64 : 65536);
+  c->eos_blocks = O.dtpart ? (int)nb : 0;
   const dim3 b(64);
   auto epi = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3(nb), b, 0, c->stream, A, c->pos4, st->vx, st->vy, st->vz, st->u, st->S, st->type,
@@ -1008,7 +1102,8 @@ sph_status launch_stress(sph_ctx* c, sph_state* st) {
 
 sph_status launch_forces(sph_ctx* c, sph_state* st) {
   PassArgs A = make_args(c, st);
-  ForceOut O{st->ax, st->ay, st->az, st->dudt, c->pos4, st->vx, st->vy, st->vz};
+  ForceOut O{st->ax, st->ay, st->az, st->dudt, c->pos4, st->vx, st->vy, st->vz, c->dDdt, c->xcoef, c->capacity, st->D};
+  const bool gp = c->p.dtP_mode == SPH_DTP_LAGGED && c->p.background == SPH_TOV;
   const dim3 g = pass_grid(c);
   dispatch_cfg(c->p.kernel, c->p.periodic, [&](auto K, auto P) {
     dispatch_lanes(pass_lanes(c->p), [&](auto LL) {
@@ -1016,12 +1111,21 @@ sph_status launch_forces(sph_ctx* c, sph_state* st) {
       constexpr bool PER = decltype(P)::value;
       constexpr int L = decltype(LL)::value;
       const dim3 b(64 * L);
-      if (c->p.precision == SPH_FP32)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forces<float, KER, PER, L>), g, b, 0, c->stream, A, c->pos4f, c->fvf,
-                           c->faf, c->sigf, c->tovf, c->sdot, O);
-      else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forces<double, KER, PER, L>), g, b, 0, c->stream, A, c->pos4, c->fv,
-                           c->fa, c->sig, c->tovf, c->sdot, O);
+      if (c->p.precision == SPH_FP32) {
+        if (gp)
+          hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forces<float, KER, PER, L, true>), g, b, 0, c->stream, A, c->pos4f,
+                             c->fvf, c->faf, c->sigf, c->tovf, c->sdot, O);
+        else
+          hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forces<float, KER, PER, L, false>), g, b, 0, c->stream, A, c->pos4f,
+                             c->fvf, c->faf, c->sigf, c->tovf, c->sdot, O);
+      } else {
+        if (gp)
+          hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forces<double, KER, PER, L, true>), g, b, 0, c->stream, A, c->pos4,
+                             c->fv, c->fa, c->sig, c->tovf, c->sdot, O);
+        else
+          hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forces<double, KER, PER, L, false>), g, b, 0, c->stream, A, c->pos4,
+                             c->fv, c->fa, c->sig, c->tovf, c->sdot, O);
+      }
     });
   });
   HIP_TRY(hipGetLastError());

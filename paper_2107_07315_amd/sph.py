@@ -23,7 +23,7 @@ EXPORTED = ("sph_create", "sph_destroy", "sph_set_params", "sph_build_cells", "s
             "sph_mlp_set_params", "sph_mlp_get_params", "sph_mlp_get_norm", "sph_mlp_train", "sph_mlp_grad",
             "sph_mlp_eval", "sph_mlp_build_trust_mask", "sph_ensemble_set", "sph_autotune", "sph_mlp_load",
             "sph_last_error_detail", "sph_eos_table_create", "sph_neighbour_stats_noalloc", "sph_modify_energy",
-            "sph_diagnostics")
+            "sph_diagnostics", "sph_get_time", "sph_mlp_count_served")
 MLP_NPARAM = 8642
 
 _dp = ctypes.c_void_p
@@ -69,7 +69,8 @@ class SphDiagParams(ctypes.Structure):
     _fields_ = [(k, ctypes.c_double) for k in ("r_lo", "r_hi", "slab_r", "slab_dr", "slab_th", "slab_dth")]
 
 
-DIAG_FIELDS = ("kinetic", "toroidal", "internal", "u_band", "slab_c0", "slab_cr", "slab_cth", "n_band", "n_slab")
+DIAG_FIELDS = ("kinetic", "toroidal", "internal", "u_band", "slab_c0", "slab_cr", "slab_cth", "n_band", "n_slab",
+               "tor_l2")
 
 
 class SphState(ctypes.Structure):
@@ -133,6 +134,8 @@ def load():
     L.sph_mlp_load.argtypes = [vp, vp]
     L.sph_modify_energy.argtypes = [vp, S, vp, ctypes.c_int32, ctypes.c_double]
     L.sph_diagnostics.argtypes = [vp, S, ctypes.POINTER(SphDiagParams), vp]
+    L.sph_get_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.sph_mlp_count_served.argtypes = [vp, S, ctypes.POINTER(ctypes.c_int64)]
     L.sph_last_error_detail.argtypes = [vp]
     L.sph_last_error_detail.restype = ctypes.c_char_p
     L.sph_eos_table_create.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
@@ -295,6 +298,11 @@ class Context:
     def sph_step(self, st: DeviceState, dt: float, nsteps: int):
         _check(self.lib.sph_step(self.h, ctypes.byref(st.struct), float(dt), int(nsteps)), "sph_step", self.h)
 
+    def sph_get_time(self):
+        t = ctypes.c_double()
+        _check(self.lib.sph_get_time(self.h, ctypes.byref(t)), "sph_get_time", self.h)
+        return t.value
+
     def sph_sync(self):
         """Waits; raises SphError for a latched device error, with .particle the array index (in
         the current order) of the particle that raised it, or -1."""
@@ -328,7 +336,7 @@ class Context:
         written there, stream-ordered, and None is returned; without, it is read back as a dict."""
         import torch
         dp = SphDiagParams(r_lo, r_hi, slab_r, slab_dr, slab_th, slab_dth)
-        buf = out if out is not None else torch.zeros(9, dtype=torch.float64, device="cuda")
+        buf = out if out is not None else torch.zeros(10, dtype=torch.float64, device="cuda")
         _check(self.lib.sph_diagnostics(self.h, ctypes.byref(st.struct), ctypes.byref(dp), buf.data_ptr()),
                "sph_diagnostics", self.h)
         if out is not None:
@@ -337,6 +345,7 @@ class Context:
         d = {k: float(raw[i]) for i, k in enumerate(DIAG_FIELDS[:7])}
         d["n_band"] = int(raw[7:8].view(np.int64)[0])
         d["n_slab"] = int(raw[8:9].view(np.int64)[0])
+        d["tor_l2"] = float(raw[9])
         return d
 
     def sph_set_timing(self, enable: bool):
@@ -434,6 +443,12 @@ class Context:
         _check(self.lib.sph_mlp_eval(self.h, lnrho.data_ptr(), lnu.data_ptr(), lnrho.shape[0], lp.data_ptr(),
                                      lc.data_ptr()), "sph_mlp_eval")
         return lp, lc
+
+    def mlp_count_served(self, st: DeviceState):
+        n = ctypes.c_int64()
+        _check(self.lib.sph_mlp_count_served(self.h, ctypes.byref(st.struct), ctypes.byref(n)), "sph_mlp_count_served",
+               self.h)
+        return n.value
 
     def mlp_build_trust_mask(self, tol=1e-4):
         n = ctypes.c_int64()

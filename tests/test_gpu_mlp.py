@@ -145,34 +145,41 @@ def test_trust_mask_and_fallback(trained):
 
 
 def test_surrogate_path_meets_oracle_tolerance(trained):
-    # the whole FP32-pairs + surrogate path against the FP64 oracle with the table EoS, at the
-    # 1e-4 trust threshold
+    # the whole FP32-pairs + surrogate path against the FP64 oracle with the table EoS.  At the
+    # 1e-4 threshold the mask trusts no cell the star's particles sit in (they lie on the cold
+    # curve, where the hybrid EoS has a kink in u that a smooth BF16 network does not resolve to
+    # 1e-4), so the served count is reported, and the path equals the table path; at 3e-2 the
+    # network serves particles and their pressure stays within that tolerance
     sph, ctx, w, samples, before, hist = trained
-    ctx.mlp_build_trust_mask(1e-4)
     o = oracle_run(w, params=w.params.replace(eos="TABLE", precision="FP64"))
-    st = sph.DeviceState(w.arrays)
     p32 = w.params.replace(precision="FP32")
     from paper_2107_07315_amd import sph as S
-    c32 = S.Context(p32, capacity=w.n)
-    c32.mlp_set_params(ctx.mlp_get_params())
-    # retrain-free copy: the same master weights, mask rebuilt for this context
-    c32.mlp_build_trust_mask(1e-4)
-    c32.evaluate(st)
-    c32.sph_sync()
-    g = st.numpy()
-    order = np.argsort(g["id"])
-    e = {k: float(np.max(rel_err(g[k][order], o[k], 1e-300))) for k in ("D", "rho", "P")}
-    _print("FP32+MLP vs oracle", e)
-    for k, v in e.items():
-        assert v < 1e-4, (k, v)
+    for tol in (1e-4, 3e-2):
+        st = sph.DeviceState(w.arrays)
+        c32 = S.Context(p32, capacity=w.n)
+        c32.mlp_set_params(ctx.mlp_get_params())
+        cells = c32.mlp_build_trust_mask(tol)
+        c32.evaluate(st)
+        c32.sph_sync()
+        served = c32.mlp_count_served(st)
+        g = st.numpy()
+        c32.close()
+        order = np.argsort(g["id"])
+        e = {k: float(np.max(rel_err(g[k][order], o[k], 1e-300))) for k in ("D", "rho", "P")}
+        _print(f"FP32+MLP at {tol}: trusted cells {cells}, particles on the network {served} of {w.n}", e)
+        assert e["D"] < 1e-4 and e["rho"] < 1e-4
+        if served == 0:
+            assert e["P"] < 1e-4
+        else:
+            assert e["P"] < 2 * tol
 
 
 def test_surrogate_gain_is_measured(trained):
-    """What the trained network gains over the table it replaces: the EoS from 17 KB of BF16
-    weights instead of a 16 MB table, more accurately than a bilinear table of the same 17 KB
-    (median and 90th percentile of the larger relative error of P and c_s^2 on held-out
-    samples).  It does not reach the 1e-4 the density pass demands (BF16 rounding alone is
-    about 2^-9 of the output range), which is why the trust mask keeps the table there."""
+    """What the trained network gains over the table it replaces, and what it costs: the EoS from
+    17 KB of BF16 weights instead of a 16 MB table, more accurately than a bilinear table of about
+    the same size (median and 90th percentile of the larger relative error of P and c_s^2 on
+    held-out samples), at a higher epilogue cost than the full table (both reported).  It does not
+    reach the 1e-4 the density pass demands, which is why the trust mask keeps the table there."""
     import torch
     sph, ctx, w, samples, before, hist = trained
     tab = W.pp_table()
@@ -190,20 +197,41 @@ def test_surrogate_gain_is_measured(trained):
     ref_p = bil(tab.lnP, tab.lnr0, tab.dlnr, tab.lnu0, tab.dlnu, sn[:, 0], sn[:, 1])
     ref_c = bil(tab.lncs2, tab.lnr0, tab.dlnr, tab.lnu0, tab.dlnu, sn[:, 0], sn[:, 1])
     e_net = np.maximum(np.abs(np.expm1(lp.cpu().numpy() - ref_p)), np.abs(np.expm1(lc.cpu().numpy() - ref_c)))
-    # a table of the network's size: 2 fields x k x k FP64 nodes in 17 KB -> k = 33 (nodes of the big table)
-    k = 33
-    ii = np.round(np.linspace(0, tab.lnP.shape[0] - 1, k)).astype(int)
-    jj = np.round(np.linspace(0, tab.lnP.shape[1] - 1, k)).astype(int)
-    small_p, small_c = tab.lnP[np.ix_(ii, jj)], tab.lncs2[np.ix_(ii, jj)]
-    dr = (ii[1] - ii[0]) * tab.dlnr
-    du = (jj[1] - jj[0]) * tab.dlnu
+    # a table of about the network's size: 34 x 34 nodes of the big table, every 31st (1023 = 33 x 31),
+    # 2 fields x 34^2 FP64 = 18.5 KB, interpolated at its own node coordinates
+    step = 31
+    k = (tab.lnP.shape[0] - 1) // step + 1
+    ii = np.arange(k) * step
+    small_p, small_c = tab.lnP[np.ix_(ii, ii)], tab.lncs2[np.ix_(ii, ii)]
+    dr = step * tab.dlnr
+    du = step * tab.dlnu
     e_small = np.maximum(np.abs(np.expm1(bil(small_p, tab.lnr0, dr, tab.lnu0, du, sn[:, 0], sn[:, 1]) - ref_p)),
                          np.abs(np.expm1(bil(small_c, tab.lnr0, dr, tab.lnu0, du, sn[:, 0], sn[:, 1]) - ref_c)))
+    # against the 1024^2 table the method uses: its error is 0 by definition (it is the reference);
+    # the cost of the density epilogue with the network (at 3e-2, where it serves particles) and
+    # with the table, per evaluation of the star
+    from paper_2107_07315_amd import sph as S
+    ms = {}
+    for mode in ("table", "network"):
+        c = S.Context(w.params.replace(precision="FP32", eos="MLP" if mode == "network" else "TABLE"), capacity=w.n)
+        if mode == "network":
+            c.mlp_set_params(ctx.mlp_get_params())
+            c.mlp_build_trust_mask(3e-2)
+        st = sph.DeviceState(w.arrays)
+        c.evaluate(st)
+        c.sph_set_timing(True)
+        for _ in range(20):
+            c.sph_density(st)
+        c.sph_sync()
+        n, t = c.sph_get_timing("eos")
+        ms[mode] = t / n
+        c.close()
     net_bytes = 2 * 8642
     table_bytes = tab.lnP.nbytes + tab.lncs2.nbytes
     rep = {"compression": table_bytes / net_bytes, "net_median": float(np.median(e_net)),
            "net_p90": float(np.percentile(e_net, 90)), "small_table_median": float(np.median(e_small)),
-           "small_table_p90": float(np.percentile(e_small, 90))}
+           "small_table_p90": float(np.percentile(e_small, 90)), "epilogue_ms_table": ms["table"],
+           "epilogue_ms_network": ms["network"]}
     _print("gain", rep)
     assert np.all(np.isfinite(e_net))
     assert rep["compression"] > 900
