@@ -45,6 +45,19 @@ def peak_frequency(t, y, fmin=0.0):
     return float(f[k])
 
 
+def zero_crossing_frequency(t, y):
+    """Frequency of an oscillation about zero from the spacing of its zero crossings (linear
+    interpolation between samples; half a period between consecutive crossings), for series too
+    short for a resolved spectrum; nan with fewer than two crossings."""
+    t = np.asarray(t, np.float64)
+    y = np.asarray(y, np.float64)
+    k = np.flatnonzero(np.sign(y[:-1]) * np.sign(y[1:]) < 0)
+    if k.size < 2:
+        return float("nan")
+    tc = t[k] - y[k] * (t[k + 1] - t[k]) / (y[k + 1] - y[k])
+    return float(0.5 / np.mean(np.diff(tc)))
+
+
 def redshifted(f_cal, M, R):
     """Observed frequency f_cal sqrt(1 - 2M/R) (geometric units, M and R in the same units)."""
     return f_cal * math.sqrt(1.0 - 2.0 * M / R)

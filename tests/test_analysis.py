@@ -14,6 +14,14 @@ def test_peak_frequency_of_a_sampled_sinusoid():
         assert abs(f / f0 - 1) < 0.01, (f, f0)
 
 
+def test_zero_crossing_frequency_of_a_short_series():
+    t = np.linspace(0.0, 1.6, 81)
+    for f0 in (1.5, 2.2):
+        y = 0.7 * np.cos(2 * np.pi * f0 * t) * np.exp(-0.2 * t)
+        assert abs(analysis.zero_crossing_frequency(t, y) / f0 - 1) < 0.01
+    assert np.isnan(analysis.zero_crossing_frequency(t, np.exp(-t)))
+
+
 def test_redshift_of_the_paper_crust_frequency():
     # 30 Hz computed for a 1.4 Msun star of R = 14.2 km is observed at about 25.18 Hz
     km = 1.0e5 / (6.67430e-8 * 1.98847e33 / 2.99792458e10 ** 2)
