@@ -82,7 +82,7 @@ def test_error_detail_names_the_cause():
         ctx.sph_sync()
     assert e.value.code == 5 and "particle" in e.value.detail and "capacity" in e.value.detail, e.value.detail
     with pytest.raises(sph.SphError) as e:
-        ctx.sph_step(st, -1.0, 1)
+        ctx.sph_step(st, float("nan"), 1)
     assert "dt" in e.value.detail
     ctx.close()
     with pytest.raises(sph.SphError) as e:

@@ -208,7 +208,7 @@ def test_stage_order_and_argument_errors():
     ctx.sph_stress_rate(st)
     ctx.sph_forces(st)
     with pytest.raises(sph.SphError) as e:
-        ctx.sph_step(st, -1.0, 1)
+        ctx.sph_step(st, float("nan"), 1)
     assert e.value.code == 1
     ctx.sph_sync()
     # more particles than the context holds
