@@ -192,6 +192,51 @@ __device__ __forceinline__ void walk_groups(const uint4* base, int64_t gstride, 
   }
 }
 
+// Software-pipelined walk of a whole slot list when the tile's union (usize records) sits in LDS
+// as one chunk.  Every lane of the wave runs the wave's longest list (cmax, wave-uniform), so the
+// body is straight-line code with no per-entry branch; entries past the lane's own count are
+// passed with valid = false and their records are read from a staged slot (below usize: the
+// records of a real particle, so every product with F = 0 stays finite).  The records of the next
+// entry are read from LDS (load(j)) before the current entry's arithmetic (f(loc, rec, valid)),
+// and the next 16-byte group of 8 entries is read from memory one group ahead.
+template <typename Ld, typename F>
+__device__ __forceinline__ void walk_groups_pf(const uint4* base, int64_t gstride, int cnt, int cmax, int usize,
+                                               Ld&& load, F&& f) {
+  auto ent = [](const uint4& q, int i) -> int {
+    const uint32_t w = i < 2 ? q.x : (i < 4 ? q.y : (i < 6 ? q.z : q.w));
+    return (int)((i & 1) ? (w >> 16) : (w & 0xffffu));
+  };
+  const int last = usize > 0 ? usize - 1 : 0;
+  auto slot = [last](int loc) { return loc < last ? loc : last; };   // entries past the count are stale
+  uint4 g = make_uint4(0u, 0u, 0u, 0u);
+  if (cnt > 0) g = base[0];
+  const uint4* gp = base + gstride;
+  auto rec = load(slot(ent(g, 0)));
+  for (int k0 = 0; k0 < cmax; k0 += 8) {
+    uint4 nx = g;
+    if (k0 + 8 < cnt) nx = *gp;
+    gp += gstride;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      if (k0 + i >= cmax) break;   // wave-uniform
+      const auto nrec = load(slot(i < 7 ? ent(g, i + 1) : ent(nx, 0)));
+      f(ent(g, i), rec, k0 + i < cnt);
+      rec = nrec;
+    }
+    g = nx;
+  }
+}
+
+// Largest value of v over the wave, as a wave-uniform (scalar) value.
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const int o = __shfl_xor(v, off, 64);
+    v = o > v ? o : v;
+  }
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
 // Sum over the L adjacent lanes that share a target (every one of them receives the sum).
 template <int L, typename T>
 __device__ __forceinline__ T lane_group_sum(T v) {
@@ -528,9 +573,9 @@ __global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* _
   R sum = 0;
   ListWriter<RB> wr;
   wr.init(reinterpret_cast<uint4*>(xlist) + slot, A.capw * L, lring[threadIdx.x], A.cap_sl);
-  // candidate union member loc, whose record sits in LDS slot j
-  auto cand = [&](int loc, int j) {
-    const SR pb = sp[j];
+  // candidate union member loc with record pb (valid = false: a padding entry of the walk, which
+  // adds nothing)
+  auto cand = [&](int loc, const SR& pb, bool valid) {
     bool hit;
     R W;
     if constexpr (F32) {
@@ -540,8 +585,8 @@ __global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* _
       const float r2 = dx * dx + dy * dy + dz * dz;
       const float H = paf.w + pb.w;
       const float H2 = H * H;
-      hit = r2 < H2;
-      if (fabsf(r2 - H2) <= kBand * fmaf(Ma, H, H2)) {   // near the support edge: decide in FP64
+      hit = valid && r2 < H2;
+      if (valid && fabsf(r2 - H2) <= kBand * fmaf(Ma, H, H2)) {   // near the support edge: decide in FP64
         const double4 q = pos64[tw.U[loc]];
         const double r2d = pair_r2(wrap_sel<PER>(pa.x - q.x, box, half), wrap_sel<PER>(pa.y - q.y, box, half),
                                    wrap_sel<PER>(pa.z - q.z, box, half));
@@ -549,13 +594,14 @@ __global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* _
         hit = r2d < Hd * Hd;
       }
       W = kern_W_unit<float, KER>(sqrt_hw(r2), rcp_fast(0.5f * H));   // zero for misses
+      W = valid ? W : 0.0f;
     } else {
       const double dx = wrap_sel<PER>(pa.x - pb.x, box, half);
       const double dy = wrap_sel<PER>(pa.y - pb.y, box, half);
       const double dz = wrap_sel<PER>(pa.z - pb.z, box, half);
       const double r2 = pair_r2(dx, dy, dz);
       const double H = pa.w + pb.w;
-      hit = r2 < H * H;
+      hit = valid && r2 < H * H;
       W = kern_W_unit<R, KER>(sqrt_fast((R)r2), rcp_fast((R)(0.5 * H)));
       W = hit ? W : (R)0;   // the exact decision also at the support edge
     }
@@ -571,11 +617,11 @@ __global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* _
         sp[j] = q;
     });
   };
-  if (tw.usize <= CH) {   // whole union in one chunk: group walk
+  if (tw.usize <= CH) {   // whole union in one chunk: pipelined group walk
     __syncthreads();
     stage(0);
     __syncthreads();
-    walk_groups(lst, A.capw * L, cnt, [&](int loc) { cand(loc, loc); });
+    walk_groups_pf(lst, A.capw * L, cnt, wave_max_i(cnt), tw.usize, [&](int j) { return sp[j]; }, cand);
   } else {
     tw.start(lst, A.capw * L, cnt);
     for (int c0 = 0; c0 < tw.usize; c0 += CH) {
@@ -586,7 +632,7 @@ __global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* _
       while (tw.next < cend) {
         const int loc = tw.next;
         tw.advance();
-        cand(loc, loc - c0);
+        cand(loc, sp[loc - c0], true);
       }
     }
   }
@@ -797,8 +843,11 @@ __device__ __forceinline__ void ext_accel(const PassArgs& A, const ForceOut& O, 
 
 // Lane g of the L-wave workgroup walks the exact slot list (g / L, g % L); the partial sums of a
 // target's L lanes are added before the fixed-background epilogue.
-// GP: also sum v_a . (P_a/D_a^2 + P_b/D_b^2) grad_a W (the advection of P in the lagged dP/dt row)
-template <typename R, int KER, bool PER, int L, bool GP>
+// XS selects the optional sums (compile-time, so that the default mode keeps its registers):
+//   kXDD: sum m v_ab . grad_a W (continuity density and first-law energy);
+//   kXGP: that and v_a . (P_a/D_a^2 + P_b/D_b^2) grad_a W (the advection of P in the lagged dP/dt row).
+constexpr int kXDD = 1, kXGP = 2;
+template <typename R, int KER, bool PER, int L, int XS>
 __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Rec<R>::P4* __restrict__ pos,
                                                    const typename Rec<R>::V4* __restrict__ fv,
                                                    const typename Rec<R>::A2* __restrict__ fa,
@@ -807,6 +856,7 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
   using P4 = typename Rec<R>::P4;
   using V4 = typename Rec<R>::V4;
   using A2 = typename Rec<R>::A2;
+  constexpr bool DD = XS != 0, GP = XS == kXGP;
   constexpr int CH = Rec<R>::CH_F * L;
   const int tl = threadIdx.x / L, sub = threadIdx.x % L;
   __shared__ P4 sp[CH];
@@ -837,11 +887,13 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
     for (int c = 0; c < 6; ++c) sa[c] = sig[c * n + a];
   const R alpha_v = (R)p.visc_alpha, beta_v = (R)p.visc_beta, eps_v = (R)p.visc_eps;
   R AP[3] = {0, 0, 0}, AS[3] = {0, 0, 0}, ud = 0, dd = 0, gp = 0;
-  // pair with union member loc, whose records sit in LDS slot j
-  auto pair = [&](int loc, int j) {
-    const P4 pb = sp[j];
-    const V4 vb = sv[j];
-    const A2 fab = sa2[j];
+  struct Recs { P4 p; V4 v; A2 f; };
+  // pair with union member loc, records r (valid = false: a padding entry of the walk, which adds
+  // nothing: F = 0 zeroes every term)
+  auto pair = [&](int loc, const Recs& r, bool valid) {
+    const P4& pb = r.p;
+    const V4& vb = r.v;
+    const A2& fab = r.f;
     const R d[3] = {wrap_sel<PER>(pa.x - pb.x, box, half), wrap_sel<PER>(pa.y - pb.y, box, half),
                     wrap_sel<PER>(pa.z - pb.z, box, half)};
     const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
@@ -849,6 +901,7 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
     R F;   // grad_a W = kF F d (the constant kF is applied to the sums)
     if constexpr (std::is_same<R, float>::value) F = kern_F_unit<float, KER>(sqrt_hw(r2), rcp_fast(hab));
     else F = kern_F_unit<R, KER>(sqrt_fast(r2), rcp_fast(hab));
+    F = valid ? F : (R)0;
     const R v[3] = {va.x - vb.x, va.y - vb.y, va.z - vb.z};
     const R vr = v[0] * d[0] + v[1] * d[1] + v[2] * d[2];
     const bool b_st = fab.y < 0;
@@ -859,16 +912,16 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
     const R inv = rcp_fast(X * Dbar);
     const R muab = hab * vr * (Dbar * inv);
     const R acbar = Rec<R>::HS * (va.w + vb.w);   // alpha c_bar (the records hold alpha c_s)
-    const R Pi = vr < (R)0 ? muab * fma(beta_v, muab, -acbar) * (X * inv) : (R)0;
+    const R Pi = (valid && vr < (R)0) ? muab * fma(beta_v, muab, -acbar) * (X * inv) : (R)0;
     const R cPF = (pia + fab.x + Pi) * F;
     AP[0] += cPF * d[0];
     AP[1] += cPF * d[1];
     AP[2] += cPF * d[2];
     const R Fvr = F * vr;                   // v_ab . grad_a W = F (v_ab . d)
     ud += (pia + (R)0.5 * Pi) * Fvr;
-    dd += Fvr;
+    if constexpr (DD) dd += Fvr;
     if constexpr (GP) gp += (pia + fab.x) * F * (va.x * d[0] + va.y * d[1] + va.z * d[2]);
-    if (a_st || b_st) {
+    if (valid && (a_st || b_st)) {
       const R g[3] = {F * d[0], F * d[1], F * d[2]};
       R s6[6];
       const int32_t b = b_st ? tw.U[loc] : 0;
@@ -879,18 +932,18 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
       AS[2] += s6[4] * g[0] + s6[5] * g[1] + s6[2] * g[2];
     }
   };
-  struct Recs { P4 p; V4 v; A2 f; };
   auto stage = [&](int c0) {
     stage_union<64 * L, CH>(tw.U, c0, tw.usize, [&](int32_t b) { return Recs{pos[b], fv[b], fa[b]}; },
                             [&](int j, const Recs& r) { sp[j] = r.p; sv[j] = r.v; sa2[j] = r.f; });
   };
-  // FP32 with the whole union in one chunk (the usual case): group walk.  (In FP64 the 8 inlined
-  // copies of the longer pair body run slower than the shifting walk, measured.)
+  // FP32 with the whole union in one chunk (the usual case): pipelined group walk.  (In FP64 the 8
+  // inlined copies of the longer pair body run slower than the shifting walk, measured.)
   if (std::is_same<R, float>::value && tw.usize <= CH) {
     __syncthreads();
     stage(0);
     __syncthreads();
-    walk_groups(lst, A.capw * L, cnt, [&](int loc) { pair(loc, loc); });
+    walk_groups_pf(lst, A.capw * L, cnt, wave_max_i(cnt), tw.usize,
+                   [&](int j) { return Recs{sp[j], sv[j], sa2[j]}; }, pair);
   } else {
     tw.start(lst, A.capw * L, cnt);
     for (int c0 = 0; c0 < tw.usize; c0 += CH) {
@@ -901,7 +954,8 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
       while (tw.next < cend) {
         const int loc = tw.next;
         tw.advance();
-        pair(loc, loc - c0);
+        const int j = loc - c0;
+        pair(loc, Recs{sp[j], sv[j], sa2[j]}, true);
       }
     }
   }
@@ -911,7 +965,7 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
     AS[i] = lane_group_sum<L>(AS[i]);
   }
   ud = lane_group_sum<L>(ud);
-  dd = lane_group_sum<L>(dd);
+  if constexpr (DD) dd = lane_group_sum<L>(dd);
   if constexpr (GP) gp = lane_group_sum<L>(gp);
   if (!tw.valid || sub != 0) continue;
   const double m = particle_mass(A, a) * kern_F_const<KER>();
@@ -928,9 +982,8 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
 #pragma unroll
     for (int i = 0; i < 3; ++i) acc[i] = -APd[i] + ASd[i];   // eq. solid2
   }
-  if (p.ext == SPH_EXT_RADIAL || p.wall_in > 0.0 || p.wall_out > 0.0 || p.damping > 0.0) ext_accel(A, O, a, acc);
   const double md = m * (double)dd;                            // sum m v_ab . grad_a W
-  O.dDdt[a] = md;
+  if constexpr (DD) O.dDdt[a] = md;
   if constexpr (GP) {   // dP/dt row: -v^i k (P - P_prev) / dt + v^i k v . grad P, grad P ~ D A^P
     const double kt = O.xcoef[4 * O.xs + a];
     if (kt != 0.0) {
@@ -941,7 +994,7 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
     }
   }
   double du;
-  if (p.energy_mode == SPH_ENERGY_FIRST_LAW) {   // first law: e0 dD/dt + e1 + e2 v.a + heating + work
+  if (DD && p.energy_mode == SPH_ENERGY_FIRST_LAW) {   // first law: e0 dD/dt + e1 + e2 v.a + heating + work
     const double va_dot = O.vx[a] * acc[0] + O.vy[a] * acc[1] + O.vz[a] * acc[2];
     du = O.xcoef[a] * md + m * ((double)ud - (double)pia * (double)dd) + O.xcoef[O.xs + a] +
          O.xcoef[2 * O.xs + a] * va_dot + sdot[a];
@@ -954,6 +1007,27 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
   O.dudt[a] = du;
   if (!isfinite(acc[0]) || !isfinite(acc[1]) || !isfinite(acc[2]) || !isfinite(du))
     latch_error(A.status, SPH_E_NONFINITE, (int)a);
+  }
+}
+
+// External effective potential, walls and drag (relaxation set-up, crust shell), added after the
+// force pass by one lane per particle: kept out of k_forces, whose registers (and so its
+// occupancy) the FP64 evaluation would otherwise raise.  With the first-law energy the
+// e2 v . a term takes the added acceleration too.
+__global__ __launch_bounds__(256) void k_ext_accel(PassArgs A, ForceOut O) {
+  const int64_t n = cancelled(A) ? 0 : A.n;
+  for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < n; a += (int64_t)gridDim.x * blockDim.x) {
+    double acc[3] = {0.0, 0.0, 0.0};
+    ext_accel(A, O, a, acc);
+    O.ax[a] += acc[0];
+    O.ay[a] += acc[1];
+    O.az[a] += acc[2];
+    if (A.p.energy_mode == SPH_ENERGY_FIRST_LAW) {
+      const double va = O.vx[a] * acc[0] + O.vy[a] * acc[1] + O.vz[a] * acc[2];
+      O.dudt[a] += O.xcoef[2 * O.xs + a] * va;
+    }
+    if (!isfinite(O.ax[a]) || !isfinite(O.ay[a]) || !isfinite(O.az[a]) || !isfinite(O.dudt[a]))
+      latch_error(A.status, SPH_E_NONFINITE, (int)a);
   }
 }
 
@@ -1103,7 +1177,9 @@ sph_status launch_stress(sph_ctx* c, sph_state* st) {
 sph_status launch_forces(sph_ctx* c, sph_state* st) {
   PassArgs A = make_args(c, st);
   ForceOut O{st->ax, st->ay, st->az, st->dudt, c->pos4, st->vx, st->vy, st->vz, c->dDdt, c->xcoef, c->capacity, st->D};
-  const bool gp = c->p.dtP_mode == SPH_DTP_LAGGED && c->p.background == SPH_TOV;
+  const int xs = (c->p.dtP_mode == SPH_DTP_LAGGED && c->p.background == SPH_TOV) ? kXGP
+                 : (c->p.density_mode == SPH_DENS_CONTINUITY || c->p.energy_mode == SPH_ENERGY_FIRST_LAW) ? kXDD
+                                                                                                        : 0;
   const dim3 g = pass_grid(c);
   dispatch_cfg(c->p.kernel, c->p.periodic, [&](auto K, auto P) {
     dispatch_lanes(pass_lanes(c->p), [&](auto LL) {
@@ -1111,23 +1187,25 @@ sph_status launch_forces(sph_ctx* c, sph_state* st) {
       constexpr bool PER = decltype(P)::value;
       constexpr int L = decltype(LL)::value;
       const dim3 b(64 * L);
-      if (c->p.precision == SPH_FP32) {
-        if (gp)
-          hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forces<float, KER, PER, L, true>), g, b, 0, c->stream, A, c->pos4f,
+      auto launch = [&](auto XX) {
+        constexpr int X = decltype(XX)::value;
+        if (c->p.precision == SPH_FP32)
+          hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forces<float, KER, PER, L, X>), g, b, 0, c->stream, A, c->pos4f,
                              c->fvf, c->faf, c->sigf, c->tovf, c->sdot, O);
         else
-          hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forces<float, KER, PER, L, false>), g, b, 0, c->stream, A, c->pos4f,
-                             c->fvf, c->faf, c->sigf, c->tovf, c->sdot, O);
-      } else {
-        if (gp)
-          hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forces<double, KER, PER, L, true>), g, b, 0, c->stream, A, c->pos4,
+          hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forces<double, KER, PER, L, X>), g, b, 0, c->stream, A, c->pos4,
                              c->fv, c->fa, c->sig, c->tovf, c->sdot, O);
-        else
-          hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forces<double, KER, PER, L, false>), g, b, 0, c->stream, A, c->pos4,
-                             c->fv, c->fa, c->sig, c->tovf, c->sdot, O);
-      }
+      };
+      if (xs == kXGP) launch(std::integral_constant<int, kXGP>{});
+      else if (xs == kXDD) launch(std::integral_constant<int, kXDD>{});
+      else launch(std::integral_constant<int, 0>{});
     });
   });
+  const sph_params& p = c->p;
+  if (p.ext == SPH_EXT_RADIAL || p.wall_in > 0.0 || p.wall_out > 0.0 || p.damping > 0.0) {
+    const int64_t nb = (A.n + 255) / 256;
+    hipLaunchKernelGGL(k_ext_accel, dim3((unsigned)(nb < 4096 ? (nb > 0 ? nb : 1) : 4096)), dim3(256), 0, c->stream, A, O);
+  }
   HIP_TRY(hipGetLastError());
   return SPH_OK;
 }
