@@ -78,7 +78,7 @@ template <> struct Rec<double> {
   using V4 = double4;
   using A2 = double2;
   static constexpr int CH_D = 256;   // LDS records per chunk and wave: density 8 KB
-  static constexpr int CHMAX_D = 768;   // per workgroup (measured best; LDS for 5 workgroups per CU)
+  static constexpr int CHMAX_D = 1024;  // per workgroup: 32 KB + 8 KB of list staging, 4 workgroups per CU
   static constexpr int CH_S = 128;   // stress 8 KB
   static constexpr int CH_F = 128;   // forces 10 KB
 };
@@ -88,7 +88,7 @@ template <> struct Rec<float> {
   using V4 = float4;
   using A2 = float2;
   static constexpr int CH_D = 384;   // density records: FP32 tile-relative (x, y, z, h), 6 KB
-  static constexpr int CHMAX_D = 1280;   // per workgroup: 20 KB, 4 workgroups per CU (measured best)
+  static constexpr int CHMAX_D = 1280;   // per workgroup: 20 KB + 8 KB of list staging, 5 workgroups per CU
   static constexpr int CH_S = 256;
   static constexpr int CH_F = 256;
 };
@@ -192,26 +192,24 @@ __device__ __forceinline__ void walk_groups(const uint4* base, int64_t gstride, 
   }
 }
 
-// Software-pipelined walk of a whole slot list when the tile's union (usize records) sits in LDS
-// as one chunk.  Every lane of the wave runs the wave's longest list (cmax, wave-uniform), so the
-// body is straight-line code with no per-entry branch; entries past the lane's own count are
-// passed with valid = false and their records are read from a staged slot (below usize: the
-// records of a real particle, so every product with F = 0 stays finite).  The records of the next
-// entry are read from LDS (load(j)) before the current entry's arithmetic (f(loc, rec, valid)),
-// and the next 16-byte group of 8 entries is read from memory one group ahead.
-template <typename Ld, typename F>
-__device__ __forceinline__ void walk_groups_pf(const uint4* base, int64_t gstride, int cnt, int cmax, int usize,
-                                               Ld&& load, F&& f) {
+// Software-pipelined walk of a whole slot list when the tile's union sits in LDS as one chunk.
+// Every lane of the wave runs the wave's longest list (cmax, wave-uniform), so the body is
+// straight-line code with no per-entry branch: entries past the lane's own count read the records
+// of LDS slot `pad`, a sentinel particle far from every target (its pair terms are exactly zero,
+// with no overflow), and pass no list entry on.  The records of the next entry are read from LDS
+// (load(j)) before the current entry's arithmetic (f(loc, rec)); the next 16-byte group of 8
+// entries is read from memory one group ahead; group_end() runs after every group of 8.
+template <typename Ld, typename F, typename G>
+__device__ __forceinline__ void walk_groups_pf(const uint4* base, int64_t gstride, int cnt, int cmax, int pad,
+                                               Ld&& load, F&& f, G&& group_end) {
   auto ent = [](const uint4& q, int i) -> int {
     const uint32_t w = i < 2 ? q.x : (i < 4 ? q.y : (i < 6 ? q.z : q.w));
     return (int)((i & 1) ? (w >> 16) : (w & 0xffffu));
   };
-  const int last = usize > 0 ? usize - 1 : 0;
-  auto slot = [last](int loc) { return loc < last ? loc : last; };   // entries past the count are stale
   uint4 g = make_uint4(0u, 0u, 0u, 0u);
   if (cnt > 0) g = base[0];
   const uint4* gp = base + gstride;
-  auto rec = load(slot(ent(g, 0)));
+  auto rec = load(cnt > 0 ? ent(g, 0) : pad);
   for (int k0 = 0; k0 < cmax; k0 += 8) {
     uint4 nx = g;
     if (k0 + 8 < cnt) nx = *gp;
@@ -219,10 +217,12 @@ __device__ __forceinline__ void walk_groups_pf(const uint4* base, int64_t gstrid
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       if (k0 + i >= cmax) break;   // wave-uniform
-      const auto nrec = load(slot(i < 7 ? ent(g, i + 1) : ent(nx, 0)));
-      f(ent(g, i), rec, k0 + i < cnt);
+      const int k1 = k0 + i + 1;
+      const auto nrec = load(k1 < cnt ? (i < 7 ? ent(g, i + 1) : ent(nx, 0)) : pad);
+      f(ent(g, i), rec);
       rec = nrec;
     }
+    group_end();
     g = nx;
   }
 }
@@ -400,6 +400,14 @@ struct ListWriter {
     if (hit && (n & (8 * RB - 1)) == 0) store_rows(n >> 3);   // ring full
   }
   __device__ __forceinline__ void flush() { store_rows((n + 7) >> 3); }
+  // append without the ring-full test: the caller stores the complete groups (store_complete) at
+  // least once every 8 appends, so at most 15 entries wait in the ring
+  __device__ __forceinline__ void put_unchecked(int loc, bool hit) {
+    const uint16_t v = (uint16_t)loc;
+    __builtin_memcpy(ring + (n & (8 * RB - 1)), &v, sizeof(v));
+    n += hit ? 1 : 0;
+  }
+  __device__ __forceinline__ void store_complete() { store_rows(n >> 3); }
 };
 
 // Density-stage epilogue in FP64 for particle a with computational density D: rest-mass density
@@ -538,18 +546,24 @@ constexpr float kBand = 3.814697265625e-06f;   // 2^-18
 //   particle (16 bytes), the decision taken in FP32 and, inside the guard band kBand, again
 //   exactly from the FP64 positions; the lists are the same as in FP64.
 template <typename R, int KER, bool PER, int L>
-__global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* __restrict__ pos64, DensOut O,
+__global__ __launch_bounds__(64 * L)
+__attribute__((amdgpu_waves_per_eu(std::is_same<R, float>::value ? 5 : 4))) void k_density(PassArgs A, const double4* __restrict__ pos64, DensOut O,
                                                     uint16_t* __restrict__ xlist, int32_t* __restrict__ xcount,
                                                     int32_t* __restrict__ xcount_sl) {
   constexpr bool F32 = std::is_same<R, float>::value;
   using SR = typename std::conditional<F32, float4, double4>::type;
   constexpr int CH = Rec<R>::CH_D * L < Rec<R>::CHMAX_D ? Rec<R>::CH_D * L : Rec<R>::CHMAX_D;
+  constexpr int CHU = CH - 1;   // union records per chunk; slot CHU holds the walk's sentinel
   __shared__ SR sp[CH];
-  constexpr int RB = 4;
+  constexpr int RB = 2;
   __shared__ __align__(16) uint16_t lring[64 * L][8 * RB];   // per-lane staging of the exact lists
   const double box = A.p.box, half = 0.5 * box;
   const float boxf = (float)box, halff = (float)half;
   const int tl = threadIdx.x / L, sub = threadIdx.x % L;
+  if (threadIdx.x == 0) {   // the sentinel: far from every target, h = 0 (no neighbour, W = 0)
+    if constexpr (F32) sp[CHU] = make_float4(1e10f, 1e10f, 1e10f, 0.0f);
+    else sp[CHU] = make_double4(1e10, 1e10, 1e10, 0.0);
+  }
   const int64_t ntl = num_tiles(A);
   for (int64_t k_ = blockIdx.x / SPH_XCD, chunk_ = xcd_chunk(ntl); k_ < chunk_; k_ += gridDim.x / SPH_XCD) {
     const int64_t tile = (int64_t)(blockIdx.x % SPH_XCD) * chunk_ + k_;
@@ -573,9 +587,8 @@ __global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* _
   R sum = 0;
   ListWriter<RB> wr;
   wr.init(reinterpret_cast<uint4*>(xlist) + slot, A.capw * L, lring[threadIdx.x], A.cap_sl);
-  // candidate union member loc with record pb (valid = false: a padding entry of the walk, which
-  // adds nothing)
-  auto cand = [&](int loc, const SR& pb, bool valid) {
+  // candidate union member loc with record pb (the sentinel: a miss with W = 0)
+  auto cand = [&](int loc, const SR& pb, auto&& put) {
     bool hit;
     R W;
     if constexpr (F32) {
@@ -585,8 +598,8 @@ __global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* _
       const float r2 = dx * dx + dy * dy + dz * dz;
       const float H = paf.w + pb.w;
       const float H2 = H * H;
-      hit = valid && r2 < H2;
-      if (valid && fabsf(r2 - H2) <= kBand * fmaf(Ma, H, H2)) {   // near the support edge: decide in FP64
+      hit = r2 < H2;
+      if (fabsf(r2 - H2) <= kBand * fmaf(Ma, H, H2)) {   // near the support edge: decide in FP64
         const double4 q = pos64[tw.U[loc]];
         const double r2d = pair_r2(wrap_sel<PER>(pa.x - q.x, box, half), wrap_sel<PER>(pa.y - q.y, box, half),
                                    wrap_sel<PER>(pa.z - q.z, box, half));
@@ -594,22 +607,21 @@ __global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* _
         hit = r2d < Hd * Hd;
       }
       W = kern_W_unit<float, KER>(sqrt_hw(r2), rcp_fast(0.5f * H));   // zero for misses
-      W = valid ? W : 0.0f;
     } else {
       const double dx = wrap_sel<PER>(pa.x - pb.x, box, half);
       const double dy = wrap_sel<PER>(pa.y - pb.y, box, half);
       const double dz = wrap_sel<PER>(pa.z - pb.z, box, half);
       const double r2 = pair_r2(dx, dy, dz);
       const double H = pa.w + pb.w;
-      hit = valid && r2 < H * H;
+      hit = r2 < H * H;
       W = kern_W_unit<R, KER>(sqrt_fast((R)r2), rcp_fast((R)(0.5 * H)));
       W = hit ? W : (R)0;   // the exact decision also at the support edge
     }
     sum += W;
-    wr.put(loc, hit);
+    put(loc, hit);
   };
   auto stage = [&](int c0) {
-    stage_union<64 * L, CH>(tw.U, c0, tw.usize, [&](int32_t b) { return pos64[b]; }, [&](int j, const double4& q) {
+    stage_union<64 * L, CHU>(tw.U, c0, tw.usize, [&](int32_t b) { return pos64[b]; }, [&](int j, const double4& q) {
       if constexpr (F32)
         sp[j] = make_float4((float)wrap_sel<PER>(q.x - ref.x, box, half), (float)wrap_sel<PER>(q.y - ref.y, box, half),
                             (float)wrap_sel<PER>(q.z - ref.z, box, half), (float)q.w);
@@ -617,22 +629,25 @@ __global__ __launch_bounds__(64 * L) void k_density(PassArgs A, const double4* _
         sp[j] = q;
     });
   };
-  if (tw.usize <= CH) {   // whole union in one chunk: pipelined group walk
+  if (tw.usize <= CHU) {   // whole union in one chunk: pipelined group walk
     __syncthreads();
     stage(0);
     __syncthreads();
-    walk_groups_pf(lst, A.capw * L, cnt, wave_max_i(cnt), tw.usize, [&](int j) { return sp[j]; }, cand);
+    walk_groups_pf(
+        lst, A.capw * L, cnt, wave_max_i(cnt), CHU, [&](int j) { return sp[j]; },
+        [&](int loc, const SR& pb) { cand(loc, pb, [&](int l, bool h) { wr.put_unchecked(l, h); }); },
+        [&]() { wr.store_complete(); });
   } else {
     tw.start(lst, A.capw * L, cnt);
-    for (int c0 = 0; c0 < tw.usize; c0 += CH) {
+    for (int c0 = 0; c0 < tw.usize; c0 += CHU) {
       __syncthreads();
       stage(c0);
       __syncthreads();
-      const int cend = c0 + CH;
+      const int cend = c0 + CHU;
       while (tw.next < cend) {
         const int loc = tw.next;
         tw.advance();
-        cand(loc, sp[loc - c0], true);
+        cand(loc, sp[loc - c0], [&](int l, bool h) { wr.put(l, h); });
       }
     }
   }
@@ -858,11 +873,17 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
   using A2 = typename Rec<R>::A2;
   constexpr bool DD = XS != 0, GP = XS == kXGP;
   constexpr int CH = Rec<R>::CH_F * L;
+  constexpr int CHU = CH - 1;   // union records per chunk; slot CHU holds the walk's sentinel
   const int tl = threadIdx.x / L, sub = threadIdx.x % L;
   __shared__ P4 sp[CH];
   __shared__ V4 sv[CH];
   __shared__ A2 sa2[CH];
   const R box = (R)A.p.box, half = (R)0.5 * box;
+  if (threadIdx.x == 0) {   // the sentinel: far from every target, at rest, h = 0, unstressed (F = 0)
+    sp[CHU] = P4{(R)1e10, (R)1e10, (R)1e10, (R)0};
+    sv[CHU] = V4{(R)0, (R)0, (R)0, (R)0};
+    sa2[CHU] = A2{(R)0, (R)1};
+  }
   const int64_t ntl = num_tiles(A);
   for (int64_t k_ = blockIdx.x / SPH_XCD, chunk_ = xcd_chunk(ntl); k_ < chunk_; k_ += gridDim.x / SPH_XCD) {
     const int64_t tile = (int64_t)(blockIdx.x % SPH_XCD) * chunk_ + k_;
@@ -888,9 +909,8 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
   const R alpha_v = (R)p.visc_alpha, beta_v = (R)p.visc_beta, eps_v = (R)p.visc_eps;
   R AP[3] = {0, 0, 0}, AS[3] = {0, 0, 0}, ud = 0, dd = 0, gp = 0;
   struct Recs { P4 p; V4 v; A2 f; };
-  // pair with union member loc, records r (valid = false: a padding entry of the walk, which adds
-  // nothing: F = 0 zeroes every term)
-  auto pair = [&](int loc, const Recs& r, bool valid) {
+  // pair with union member loc, records r (the sentinel: F = 0, which zeroes every term)
+  auto pair = [&](int loc, const Recs& r) {
     const P4& pb = r.p;
     const V4& vb = r.v;
     const A2& fab = r.f;
@@ -901,7 +921,6 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
     R F;   // grad_a W = kF F d (the constant kF is applied to the sums)
     if constexpr (std::is_same<R, float>::value) F = kern_F_unit<float, KER>(sqrt_hw(r2), rcp_fast(hab));
     else F = kern_F_unit<R, KER>(sqrt_fast(r2), rcp_fast(hab));
-    F = valid ? F : (R)0;
     const R v[3] = {va.x - vb.x, va.y - vb.y, va.z - vb.z};
     const R vr = v[0] * d[0] + v[1] * d[1] + v[2] * d[2];
     const bool b_st = fab.y < 0;
@@ -912,7 +931,7 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
     const R inv = rcp_fast(X * Dbar);
     const R muab = hab * vr * (Dbar * inv);
     const R acbar = Rec<R>::HS * (va.w + vb.w);   // alpha c_bar (the records hold alpha c_s)
-    const R Pi = (valid && vr < (R)0) ? muab * fma(beta_v, muab, -acbar) * (X * inv) : (R)0;
+    const R Pi = vr < (R)0 ? muab * fma(beta_v, muab, -acbar) * (X * inv) : (R)0;
     const R cPF = (pia + fab.x + Pi) * F;
     AP[0] += cPF * d[0];
     AP[1] += cPF * d[1];
@@ -921,7 +940,7 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
     ud += (pia + (R)0.5 * Pi) * Fvr;
     if constexpr (DD) dd += Fvr;
     if constexpr (GP) gp += (pia + fab.x) * F * (va.x * d[0] + va.y * d[1] + va.z * d[2]);
-    if (valid && (a_st || b_st)) {
+    if (a_st || b_st) {
       const R g[3] = {F * d[0], F * d[1], F * d[2]};
       R s6[6];
       const int32_t b = b_st ? tw.U[loc] : 0;
@@ -933,29 +952,30 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
     }
   };
   auto stage = [&](int c0) {
-    stage_union<64 * L, CH>(tw.U, c0, tw.usize, [&](int32_t b) { return Recs{pos[b], fv[b], fa[b]}; },
+    stage_union<64 * L, CHU>(tw.U, c0, tw.usize, [&](int32_t b) { return Recs{pos[b], fv[b], fa[b]}; },
                             [&](int j, const Recs& r) { sp[j] = r.p; sv[j] = r.v; sa2[j] = r.f; });
   };
   // FP32 with the whole union in one chunk (the usual case): pipelined group walk.  (In FP64 the 8
   // inlined copies of the longer pair body run slower than the shifting walk, measured.)
-  if (std::is_same<R, float>::value && tw.usize <= CH) {
+  if (std::is_same<R, float>::value && tw.usize <= CHU) {
     __syncthreads();
     stage(0);
     __syncthreads();
-    walk_groups_pf(lst, A.capw * L, cnt, wave_max_i(cnt), tw.usize,
-                   [&](int j) { return Recs{sp[j], sv[j], sa2[j]}; }, pair);
+    walk_groups_pf(
+        lst, A.capw * L, cnt, wave_max_i(cnt), CHU, [&](int j) { return Recs{sp[j], sv[j], sa2[j]}; }, pair,
+        [] {});
   } else {
     tw.start(lst, A.capw * L, cnt);
-    for (int c0 = 0; c0 < tw.usize; c0 += CH) {
+    for (int c0 = 0; c0 < tw.usize; c0 += CHU) {
       __syncthreads();
       stage(c0);
       __syncthreads();
-      const int cend = c0 + CH;
+      const int cend = c0 + CHU;
       while (tw.next < cend) {
         const int loc = tw.next;
         tw.advance();
         const int j = loc - c0;
-        pair(loc, Recs{sp[j], sv[j], sa2[j]}, true);
+        pair(loc, Recs{sp[j], sv[j], sa2[j]});
       }
     }
   }
