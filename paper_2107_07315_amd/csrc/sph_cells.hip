@@ -435,34 +435,52 @@ __device__ __forceinline__ unsigned long long wave_or_u64(unsigned long long v) 
 
 struct TileState {
   int64_t a;
+  int32_t a32;               // a as a 32-bit index (candidate indices are 32-bit), -1 if not valid
   bool valid;
+  unsigned long long vmask;  // the wave's valid lanes
   double xa, ya, za, ha;
   double hs;                 // ha (1 + skin)(1 + 2^-40), the candidate test's scaled h
   int usize, cnt, ucap;
   int32_t* U;
-  uint16_t (*row)[8];        // the lane's staging rows in LDS, one per slot
+  uint16_t* row;             // the lane's staging row in LDS (8 entries of each of the L slots)
   uint4* slot0;              // group 0 of the lane's first slot
   int64_t gstride;           // groups between consecutive groups of one slot (capw * lanes)
 };
 
 // Candidate k of a particle goes to its slot k % L, as entry k / L (L = lanes per target of the
-// pair passes): each lane of the density pass then walks one contiguous slot list.  Entries are
-// staged in the slot's 16-byte LDS row and stored a full group of 8 at a time (group g of slot s
-// at g * capw * L + s).
-__device__ __forceinline__ void store_slot_group(const TileState& T, int sl, int g) {
-  uint4 v;
-  __builtin_memcpy(&v, T.row[sl], sizeof(v));
-  T.slot0[(int64_t)g * T.gstride + sl] = v;
+// pair passes): each lane of the density pass then walks one contiguous slot list.  The lane's
+// LDS row holds 8 L consecutive candidates in arrival order (candidate k at k mod 8 L, so entry p
+// of slot s of the row's group sits at p L + s); when the row is full every slot has a complete
+// group of 8, and the row is stored as L groups (group g of slot s at g * capw * L + s), each
+// gathered from the row by byte permutes.  A row holds group g = k / (8 L) of every slot.
+template <int L>
+__device__ __forceinline__ void store_row_groups(const TileState& T, int g, int nslots) {
+  uint32_t D[4 * L];
+  __builtin_memcpy(D, T.row, sizeof(D));
+#pragma unroll
+  for (int s = 0; s < L; ++s) {
+    if (s >= nslots) break;
+    uint32_t w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if constexpr (L == 1) {
+        w[k] = D[k];
+      } else {
+        const int i0 = 2 * k * L + s, i1 = (2 * k + 1) * L + s;   // entries 2k, 2k+1 of slot s
+        const uint32_t sel = ((i0 & 1) ? 0x0302u : 0x0100u) | ((i1 & 1) ? 0x07060000u : 0x05040000u);
+        w[k] = __builtin_amdgcn_perm(D[i1 >> 1], D[i0 >> 1], sel);
+      }
+    }
+    T.slot0[(int64_t)g * T.gstride + s] = make_uint4(w[0], w[1], w[2], w[3]);
+  }
 }
 template <int L>
 __device__ __forceinline__ void append_candidate(const BuildArgs& B, TileState& T, int loc) {
   const unsigned k = (unsigned)T.cnt;
-  const int sl = (int)(k & (L - 1));
-  const int pos = (int)(k / L);
   const uint16_t v = (uint16_t)loc;
-  __builtin_memcpy(&T.row[sl][pos & 7], &v, sizeof(v));
+  __builtin_memcpy(T.row + (k & (8 * L - 1)), &v, sizeof(v));
   ++T.cnt;
-  if ((pos & 7) == 7 && pos < B.cap_sl) store_slot_group(T, sl, pos >> 3);
+  if ((k & (8 * L - 1)) == 8 * L - 1 && (int)(k / (8 * L)) * 8 < B.cap_sl) store_row_groups<L>(T, (int)(k / (8 * L)), L);
 }
 
 // candidate test (skin-widened, FP64) of every lane's target against batch candidates cb[0..nb),
@@ -480,14 +498,21 @@ __device__ __forceinline__ void run_batch(const BuildArgs& B, TileState& T, cons
   const int lane = threadIdx.x;
   unsigned long long um = 0ull;   // the batch's union members (wave-uniform)
   int nm = 0;
-  auto test = [&](const double4& pb, int32_t bj) -> bool {
+  // the lane's decision (hit) and the wave's mask of it, the mask from the compares themselves
+  // (ballot of the combined flag would first widen it to a vector register)
+  struct Hit { bool hit; unsigned long long m; };
+  auto test = [&](const double4& pb, int32_t bj) -> Hit {
     const double dx = min_image(T.xa - pb.x, (int)PER, box), dy = min_image(T.ya - pb.y, (int)PER, box),
                  dz = min_image(T.za - pb.z, (int)PER, box);
     const double H = T.hs + pb.w;
-    return T.valid & (bj != T.a) & (fma(dz, dz, fma(dy, dy, dx * dx)) < H * H);
+    const double r2 = fma(dz, dz, fma(dy, dy, dx * dx)), H2 = H * H;
+    return Hit{T.valid && bj != T.a32 && r2 < H2,
+               __builtin_amdgcn_fcmp(r2, H2, 4 /* ordered less than */) &
+                   __builtin_amdgcn_uicmp(bj, T.a32, 33 /* not equal */) & T.vmask};
   };
-  auto take = [&](int j, bool hit) {
-    if (__ballot(hit)) {
+  auto take = [&](int j, const Hit& t) {
+    const bool hit = t.hit;
+    if (t.m) {
       um |= 1ull << j;
       int loc = T.usize + nm;
       ++nm;
@@ -707,7 +732,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   __shared__ double4 tp[16];     // the particles of a small tile (its exact pre-filter)
   __shared__ double4 cb[128];
   __shared__ int32_t cbi[128];
-  __shared__ __align__(16) uint16_t crow[64][4][8];   // per lane and slot: staging of the candidate lists
+  __shared__ __align__(16) uint16_t crow[64][8 * NL];   // per lane: staging of the candidate lists
   const int lane = threadIdx.x;
   const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
   const GridInfo& g = *B.grid;
@@ -723,6 +748,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     TileState T;
     T.valid = lane < tcnt;
     T.a = T.valid ? p : -1;
+    T.a32 = (int32_t)T.a;
+    T.vmask = __builtin_amdgcn_ballot_w64(T.valid);
     const double4 pa = T.valid ? B.pos4[T.a] : make_double4(0.0, 0.0, 0.0, 0.0);
     T.xa = pa.x; T.ya = pa.y; T.za = pa.z; T.ha = pa.w; T.hs = pa.w * s1w;
     TileGeom G;
@@ -847,11 +874,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     }
     if (pend > 0) run_batch<NL, 0, PER>(B, T, cb, cbi, pend, box);
     __syncthreads();
-    if (T.valid && T.cnt <= B.cap)
-      for (int sl = 0; sl < NL; ++sl) {   // partly filled last group of each slot
-        const int ns = T.cnt > sl ? (T.cnt - sl + NL - 1) / NL : 0;
-        if ((ns & 7) && ns <= B.cap_sl) store_slot_group(T, sl, ns >> 3);
-      }
+    if (T.valid && T.cnt <= B.cap && (T.cnt & (8 * NL - 1))) {
+      // the partly filled last row: slots s < r hold a partial last group g (a slot's count is at
+      // most that of slot 0, so the capacity test of slot 0 covers them all)
+      const int r = T.cnt & (8 * NL - 1), g = T.cnt / (8 * NL);
+      if ((T.cnt + NL - 1) / NL <= B.cap_sl) store_row_groups<NL>(T, g, r < NL ? r : NL);
+    }
     if (T.valid) B.count[p] = T.cnt < B.cap ? T.cnt : B.cap;
     if (lane == 0) B.tile_usize[t] = T.usize < T.ucap ? T.usize : T.ucap;
     if (T.usize > T.ucap || T.cnt > B.cap) latch_error(B.status, SPH_E_NGB_CAPACITY, (int)(T.valid ? T.a : -1));
