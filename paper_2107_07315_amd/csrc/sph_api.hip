@@ -828,8 +828,12 @@ sph_status sph_export_neighbours(sph_ctx* c, int64_t* offsets, int32_t* ids, int
   if (!c) return note(nullptr, SPH_E_ARG, "context is NULL");
   if (!offsets) return note(c, SPH_E_ARG, "offsets is NULL");
   if (c->n > 0 && (c->gen < 2 || !c->lists_valid)) return SPH_E_ORDER;
-  if (hipStreamSynchronize(c->stream) != hipSuccess) return SPH_E_HIP;
   const int64_t n = c->n;
+  if (n > 0 && !exact_lists_written(c)) {
+    sph_status e = launch_exact_lists(c);
+    if (e) return e;
+  }
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return SPH_E_HIP;
   if (n == 0) { offsets[0] = 0; return SPH_OK; }
   GridInfo g;
   if (hipMemcpy(&g, c->grid, sizeof(g), hipMemcpyDeviceToHost) != hipSuccess) return SPH_E_HIP;

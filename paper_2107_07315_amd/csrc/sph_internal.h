@@ -406,6 +406,8 @@ sph_status sph_rebin(sph_ctx* c, sph_state* st, bool outputs_recomputed);
 sph_status launch_drift_check(sph_ctx* c, sph_state* st);
 sph_status launch_flag_clear(sph_ctx* c);
 sph_status launch_density(sph_ctx* c, sph_state* st);   // pair loop
+sph_status launch_exact_lists(sph_ctx* c);               // exact lists of the last evaluation (export)
+bool exact_lists_written(const sph_ctx* c);              // whether the density pass writes them
 sph_status launch_eos(sph_ctx* c, sph_state* st);       // per-particle epilogue
 sph_status launch_stress(sph_ctx* c, sph_state* st);
 sph_status launch_forces(sph_ctx* c, sph_state* st);

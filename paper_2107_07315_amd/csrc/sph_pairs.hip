@@ -110,6 +110,10 @@ struct PassArgs {
   int cap_sl;                           // entries a slot holds
   const uint16_t* __restrict__ nbr16s;   // candidate lists of the last build
   const int32_t* __restrict__ cnt_s;
+  // the stress and force passes walk the candidate lists instead of the exact ones (the pair
+  // terms vanish beyond the support, so the sums are the same; the density pass then writes no
+  // exact lists)
+  int cand_walk;
   const int32_t* __restrict__ star;
   const StarInfo* __restrict__ stars;
   DevStatus* status;
@@ -273,6 +277,20 @@ __device__ __forceinline__ void stage_union(const int32_t* __restrict__ U, int c
 #pragma unroll
   for (int k = 0; k < NJ; ++k)
     if (b[k] >= 0) put((int)threadIdx.x + k * NT, r[k]);
+}
+
+// The list a stress or force lane walks (slot = particle * L + sub-index) and its length: the exact
+// list written by the density pass, or the candidate list of the last build (candidate k of a
+// particle is entry k / L of slot k % L).
+template <int L>
+__device__ __forceinline__ const uint4* pass_list(const PassArgs& A, int64_t slot) {
+  return reinterpret_cast<const uint4*>(A.cand_walk ? A.nbr16s : A.nbr16) + slot;
+}
+template <int L>
+__device__ __forceinline__ int pass_count(const PassArgs& A, int64_t p, int sub, int64_t slot) {
+  if (!A.cand_walk) return A.cnt_sl[slot];
+  const int total = A.cnt_s[p];
+  return total > sub ? (total - sub + L - 1) / L : 0;
 }
 
 __device__ __forceinline__ int64_t num_tiles(const PassArgs& A) {
@@ -535,8 +553,9 @@ __device__ __forceinline__ void density_epilogue(const PassArgs& A, int64_t a, b
 constexpr float kBand = 3.814697265625e-06f;   // 2^-18
 
 // Density pass.  Walks the candidate lists, takes the exact neighbour decision r^2 < (h_a + h_b)^2
-// of the FP64 positions on every candidate, sums the kernel over the neighbours in R, and writes
-// the exact lists for the stress and force passes.  A workgroup of L waves takes one tile: lane g
+// of the FP64 positions on every candidate, sums the kernel over the neighbours in R and counts
+// them; with XL it also writes the exact lists (for the stress and force passes when they walk
+// exact lists, and for the neighbour export).  A workgroup of L waves takes one tile: lane g
 // serves target g / L as sub-lane g % L, walks the candidate slot list (particle * L + sub-lane)
 // and writes the exact hits to the exact slot list of the same index; the L partial sums are
 // added across the lanes.  The per-particle epilogue runs in k_density_epilogue, one lane per
@@ -545,9 +564,10 @@ constexpr float kBand = 3.814697265625e-06f;   // 2^-18
 //   FP32 (R = float): union records staged as FP32 coordinates relative to the tile's first
 //   particle (16 bytes), the decision taken in FP32 and, inside the guard band kBand, again
 //   exactly from the FP64 positions; the lists are the same as in FP64.
-template <typename R, int KER, bool PER, int L>
+template <typename R, int KER, bool PER, int L, bool XL>
 __global__ __launch_bounds__(64 * L)
-__attribute__((amdgpu_waves_per_eu(std::is_same<R, float>::value ? 5 : 4))) void k_density(PassArgs A, const double4* __restrict__ pos64, DensOut O,
+__attribute__((amdgpu_waves_per_eu(std::is_same<R, float>::value ? 5 : 4)))
+void k_density(PassArgs A, const double4* __restrict__ pos64, DensOut O,
                                                     uint16_t* __restrict__ xlist, int32_t* __restrict__ xcount,
                                                     int32_t* __restrict__ xcount_sl) {
   constexpr bool F32 = std::is_same<R, float>::value;
@@ -556,7 +576,7 @@ __attribute__((amdgpu_waves_per_eu(std::is_same<R, float>::value ? 5 : 4))) void
   constexpr int CHU = CH - 1;   // union records per chunk; slot CHU holds the walk's sentinel
   __shared__ SR sp[CH];
   constexpr int RB = 2;
-  __shared__ __align__(16) uint16_t lring[64 * L][8 * RB];   // per-lane staging of the exact lists
+  __shared__ __align__(16) uint16_t lring[XL ? 64 * L : 1][8 * RB];   // per-lane staging of the exact lists
   const double box = A.p.box, half = 0.5 * box;
   const float boxf = (float)box, halff = (float)half;
   const int tl = threadIdx.x / L, sub = threadIdx.x % L;
@@ -586,7 +606,7 @@ __attribute__((amdgpu_waves_per_eu(std::is_same<R, float>::value ? 5 : 4))) void
   }
   R sum = 0;
   ListWriter<RB> wr;
-  wr.init(reinterpret_cast<uint4*>(xlist) + slot, A.capw * L, lring[threadIdx.x], A.cap_sl);
+  wr.init(reinterpret_cast<uint4*>(xlist) + slot, A.capw * L, lring[XL ? threadIdx.x : 0], A.cap_sl);
   // candidate union member loc with record pb (the sentinel: a miss with W = 0)
   auto cand = [&](int loc, const SR& pb, auto&& put) {
     bool hit;
@@ -635,8 +655,15 @@ __attribute__((amdgpu_waves_per_eu(std::is_same<R, float>::value ? 5 : 4))) void
     __syncthreads();
     walk_groups_pf(
         lst, A.capw * L, cnt, wave_max_i(cnt), CHU, [&](int j) { return sp[j]; },
-        [&](int loc, const SR& pb) { cand(loc, pb, [&](int l, bool h) { wr.put_unchecked(l, h); }); },
-        [&]() { wr.store_complete(); });
+        [&](int loc, const SR& pb) {
+          cand(loc, pb, [&](int l, bool h) {
+            if constexpr (XL) wr.put_unchecked(l, h);
+            else wr.n += h ? 1 : 0;
+          });
+        },
+        [&]() {
+          if constexpr (XL) wr.store_complete();
+        });
   } else {
     tw.start(lst, A.capw * L, cnt);
     for (int c0 = 0; c0 < tw.usize; c0 += CHU) {
@@ -647,11 +674,14 @@ __attribute__((amdgpu_waves_per_eu(std::is_same<R, float>::value ? 5 : 4))) void
       while (tw.next < cend) {
         const int loc = tw.next;
         tw.advance();
-        cand(loc, sp[loc - c0], [&](int l, bool h) { wr.put(l, h); });
+        cand(loc, sp[loc - c0], [&](int l, bool h) {
+          if constexpr (XL) wr.put(l, h);
+          else wr.n += h ? 1 : 0;
+        });
       }
     }
   }
-  wr.flush();
+  if constexpr (XL) wr.flush();
   sum = lane_group_sum<L>(sum);
   const int nexact = lane_group_sum<L>(wr.n);
   if (tw.valid) {
@@ -734,7 +764,7 @@ __global__ __launch_bounds__(64 * L) void k_stress(PassArgs A, const typename Re
     sdot[a] = 0.0;
   }
   if (!__syncthreads_or(stressed)) continue;   // whole tile fluid
-  tw.start(reinterpret_cast<const uint4*>(A.nbr16) + slot, A.capw * L, stressed ? A.cnt_sl[slot] : 0);
+  tw.start(pass_list<L>(A, slot), A.capw * L, stressed ? pass_count<L>(A, tw.p, sub, slot) : 0);
   const sph_params& p = A.p;
   const P4 pa = tw.valid ? pos[a] : P4{0, 0, 0, 1};
   const V4 va = tw.valid ? fv[a] : V4{0, 0, 0, 0};
@@ -892,8 +922,8 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
   tw.begin(A, tile, tl);
   const int64_t a = tw.a;
   const int64_t slot = a * L + sub;
-  const uint4* lst = reinterpret_cast<const uint4*>(A.nbr16) + slot;
-  const int cnt = tw.valid ? A.cnt_sl[slot] : 0;
+  const uint4* lst = pass_list<L>(A, slot);
+  const int cnt = tw.valid ? pass_count<L>(A, tw.p, sub, slot) : 0;
   const int64_t n = A.n;
   const sph_params& p = A.p;
   const P4 pa = tw.valid ? pos[a] : P4{0, 0, 0, 1};
@@ -1070,6 +1100,7 @@ PassArgs make_args(sph_ctx* c, sph_state* st) {
   A.cap_sl = slot_capacity(c->cap, pass_lanes(c->p));
   A.nbr16s = c->nbr16s;
   A.cnt_s = c->nbr_count_s;
+  A.cand_walk = exact_lists_written(c) ? 0 : 1;
   A.star = c->stars ? st->star : nullptr;
   A.stars = c->stars;
   A.status = c->status;
@@ -1128,9 +1159,47 @@ static DensOut dens_out(sph_ctx* c, sph_state* st) {
   return O;
 }
 
+// The density pass; it writes the exact lists when the stress and force passes walk them.
 sph_status launch_density(sph_ctx* c, sph_state* st) {
   PassArgs A = make_args(c, st);
   DensOut O = dens_out(c, st);
+  const dim3 g = pass_grid(c);
+  const bool f32 = c->p.precision == SPH_FP32;
+  const bool xl = !A.cand_walk;
+  dispatch_cfg(c->p.kernel, c->p.periodic, [&](auto K, auto P) {
+    dispatch_lanes(pass_lanes(c->p), [&](auto LL) {
+      constexpr int KER = decltype(K)::value;
+      constexpr bool PER = decltype(P)::value;
+      constexpr int L = decltype(LL)::value;
+      const dim3 b(64 * L);
+      auto launch = [&](auto XX) {
+        constexpr bool XL = decltype(XX)::value;
+        if (f32)
+          hipLaunchKernelGGL(HIP_KERNEL_NAME(k_density<float, KER, PER, L, XL>), g, b, 0, c->stream, A, c->pos4, O,
+                             c->nbr16, c->nbr_count, c->nbr_count_sl);
+        else
+          hipLaunchKernelGGL(HIP_KERNEL_NAME(k_density<double, KER, PER, L, XL>), g, b, 0, c->stream, A, c->pos4, O,
+                             c->nbr16, c->nbr_count, c->nbr_count_sl);
+      };
+      if (xl) launch(std::true_type{});
+      else launch(std::false_type{});
+    });
+  });
+  HIP_TRY(hipGetLastError());
+  return SPH_OK;
+}
+
+bool exact_lists_written(const sph_ctx* c) { return c->p.precision != SPH_FP32; }
+
+// Exact lists of the last evaluation (positions and h of its packed records) when the density
+// pass did not write them: the density pass once more with XL, its sums dropped into scratch.
+sph_status launch_exact_lists(sph_ctx* c) {
+  sph_state st{};
+  st.n = c->n;
+  PassArgs A = make_args(c, &st);
+  A.stop = nullptr;
+  DensOut O{};
+  O.D = c->tmp;
   const dim3 g = pass_grid(c);
   const bool f32 = c->p.precision == SPH_FP32;
   dispatch_cfg(c->p.kernel, c->p.periodic, [&](auto K, auto P) {
@@ -1140,11 +1209,11 @@ sph_status launch_density(sph_ctx* c, sph_state* st) {
       constexpr int L = decltype(LL)::value;
       const dim3 b(64 * L);
       if (f32)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_density<float, KER, PER, L>), g, b, 0, c->stream, A, c->pos4, O,
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_density<float, KER, PER, L, true>), g, b, 0, c->stream, A, c->pos4, O,
                            c->nbr16, c->nbr_count, c->nbr_count_sl);
       else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_density<double, KER, PER, L>), g, b, 0, c->stream, A, c->pos4, O,
-                           c->nbr16, c->nbr_count, c->nbr_count_sl);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_density<double, KER, PER, L, true>), g, b, 0, c->stream, A, c->pos4,
+                           O, c->nbr16, c->nbr_count, c->nbr_count_sl);
     });
   });
   HIP_TRY(hipGetLastError());
