@@ -26,11 +26,12 @@ sys.path.insert(0, ROOT)
 #           term and the mass factor ~ 12.
 #  forces:  per neighbour pair 73 (distance 8, kernel gradient 18, viscosity 26, sums 21);
 #           per particle the fixed-background epilogue ~ 110.
-# Algorithmic HBM bytes: lists at 2 B per entry (candidate lists read and exact lists written by
-# the density pass, exact lists read by the force pass) plus each particle's own records read
-# and results written once (density: FP64 position 32, candidate count 4, D 8, exact counts 8 =
-# 52 B); neighbour records staged through LDS are re-reads served by the caches and are not
-# counted.
+# Algorithmic HBM bytes: lists at 2 B per entry plus each particle's own records read and results
+# written once (density: FP64 position 32, candidate count 4, D 8, exact counts 8 = 52 B);
+# neighbour records staged through LDS are re-reads served by the caches and are not counted.
+# FP64: the density pass reads the candidate lists and writes the exact lists, the force pass
+# reads the exact lists.  FP32: both passes read the candidate lists (the force terms vanish
+# beyond the support) and no exact list is written.
 # The survey's algorithmic figures per particle-update (its work-per-pass table: density with its
 # EoS epilogue about 32 FLOP per pair at about 100 pairs, forces with the background epilogue
 # about 63 FLOP per pair plus the crust terms, about 6.5 kFLOP; bytes 104 / 114 per particle in
@@ -80,24 +81,39 @@ def measured_traffic(kernel):
     return t["kernels"][kernel]["bytes_per_launch"]
 
 
+def network_domain():
+    """The EoS network's domain: the densest polytrope piece of the star (from the first table node
+    above its dividing density to 1.15 rho_c), in a band of +-0.045 in ln u around the cold curve;
+    returns (the box for sph_mlp_set_domain, ln rho range and band width for the samples)."""
+    from sph_inputs import eos_table as E
+    from sph_inputs import workloads as W
+    pp = E.default_pp()
+    lo, hi, wd = E.piece_band(pp, 2, W.PP_RHOC, W.pp_table(), 0.045)
+    return E.band_domain(pp, lo, hi, wd), (lo, hi, wd)
+
+
 def train_surrogate(w, epochs=400):
-    """Train the EoS network on the GPU (1M seeded samples, 10% held out, batch 4096, lr 1e-3):
-    returns (parameters, seconds, final holdout loss)."""
+    """Train the EoS network on the GPU in its domain (1M seeded samples in the band, 10% held
+    out, batch 4096, lr 1e-3), then fit its readout by least squares: returns (parameters,
+    seconds, holdout loss after the fit)."""
     import torch
 
     from paper_2107_07315_amd import sph
     from sph_inputs import eos_table as E
+    dom, (lo, hi, wd) = network_domain()
     ctx = sph.Context(w.params.replace(eos="MLP"), capacity=64)
+    ctx.mlp_set_domain(*dom)
     ctx.mlp_set_params(E.mlp_init(4))
-    samples = torch.as_tensor(E.mlp_samples(w.params.table, 1_000_000, 4), device="cuda")
+    samples = torch.as_tensor(E.mlp_band_samples(E.default_pp(), lo, hi, wd, 1_000_000, 4), device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    hist = ctx.mlp_train(samples, 100_000, epochs, 4096, 1e-3)
+    ctx.mlp_train(samples, 100_000, epochs, 4096, 1e-3)
+    hold = ctx.mlp_fit_readout(samples, 100_000, 1e-12)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     params = ctx.mlp_get_params()
     ctx.close()
-    return params, dt, float(hist[-1, 1])
+    return params, dt, float(hold)
 
 
 def run_variant(w, precision, eos, steps, warmup, timing=True, ctx_kw=None, mlp=None):
@@ -108,6 +124,7 @@ def run_variant(w, precision, eos, steps, warmup, timing=True, ctx_kw=None, mlp=
     ctx = sph.Context(p, capacity=w.n, **(ctx_kw or {}))
     trusted = None
     if mlp is not None:            # (network parameters, trust tolerance)
+        ctx.mlp_set_domain(*network_domain()[0])
         ctx.mlp_set_params(mlp[0])
         trusted = ctx.mlp_build_trust_mask(mlp[1])
     st = sph.DeviceState(w.arrays)
@@ -164,6 +181,7 @@ def run_ensemble(surrogate, steps, warmup):
                               stream=s, graph=(mode != "eager"))
             ctx.sph_ensemble_set(w.star_params)
             if surrogate is not None:
+                ctx.mlp_set_domain(*network_domain()[0])
                 ctx.mlp_set_params(surrogate["params"])
                 ctx.mlp_build_trust_mask(1e-4)
             st = sph.DeviceState(w.arrays)
@@ -242,10 +260,11 @@ def roofline(res, n, precision):
     passes = {
         "density": (f"k_density<{'float' if f32 else 'double'}>",
                     cand * DENS_FLOP["candidate"] + pairs * DENS_FLOP["pair"] + n * DENS_FLOP["particle"],
-                    n * DENS_BYTES[precision] + cand * DENS_BYTES["candidate"] + pairs * DENS_BYTES["pair"]),
+                    n * DENS_BYTES[precision] + cand * DENS_BYTES["candidate"]
+                    + (0 if f32 else pairs * DENS_BYTES["pair"])),
         "forces": (f"k_forces<{'float' if f32 else 'double'}>",
                    pairs * FORCE_FLOP["pair"] + n * FORCE_FLOP["particle"],
-                   n * FORCE_BYTES[precision] + pairs * FORCE_BYTES["pair"]),
+                   n * FORCE_BYTES[precision] + (cand if f32 else pairs) * FORCE_BYTES["pair"]),
     }
     # the pass's time per step: one full launch per step (a step that rebuilds the lists also
     # carries a run-ahead launch that found the skin test failed and exited at once)
@@ -312,7 +331,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=2_000_000)
-    ap.add_argument("--variants", default="FP64,FP32,FP32+MLP,FP32+MLP@3e-2",
+    ap.add_argument("--variants", default="FP64,FP32,FP32+MLP",
                     help="FP64 / FP32 pair sums with the table EoS; +MLP: the EoS network where its "
                          "trust mask (tolerance 1e-4, or @tol) accepts the table cell")
     ap.add_argument("--mlp-epochs", type=int, default=400)
@@ -381,7 +400,8 @@ def main():
                   "FP32+MLP": "f32 pair sums + f64 integration + bf16 EoS network"}.get(head, "f64"),
         "headline": {"FP32": "FP32+table: FP32 pair sums with the tabulated EoS (the EoS network serves no "
                              "particle at the 1e-4 tolerance)",
-                     "FP32+MLP": "FP32+EoS-MLP"}.get(head, head),
+                     "FP32+MLP": f"FP32+EoS-MLP: FP32 pair sums, the EoS network serving {served} of the {w.n} "
+                                 f"particles at the 1e-4 tolerance (table interpolation for the rest)"}.get(head, head),
         "data": "synthetic",
         "config": {"workload": f"piecewise-polytrope TOV star, {w.n} particles, Wendland C4 "
                                f"(~100 neighbours), l=2 A=1e-2, plastic + breaking, tabulated EoS",

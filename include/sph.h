@@ -317,15 +317,18 @@ sph_status sph_neighbour_stats_noalloc(sph_ctx* ctx, sph_list_stats* out);
 /* ---- EoS surrogate network (extension of the tabulated EoS) ---------------------------------
  * The setup section names tabulated equations of state; this extension fits a network
  * 2 -> 64 -> 64 -> 64 -> 2 with SiLU activations to the context's EoS table, mapping normalised
- * (ln rho, ln u) to normalised (ln P, ln c_s^2).  Forward passes use BF16 weights (rounded from
- * FP32 master weights) with FP32 accumulation; training runs Adam on the master weights with a
- * cosine learning-rate schedule, on the GPU.  With eos = SPH_EOS_MLP the density pass uses the
- * network in every table cell the trust mask accepts and table interpolation elsewhere (and
- * everywhere while no network is loaded).
+ * (ln rho, ln u) to normalised (ln P, ln c_s^2).  The two 64x64 layers run on the matrix cores
+ * with BF16 weights (rounded from FP32 master weights) and FP32 accumulation, their input
+ * activations carried as two BF16 parts (hi + lo); the input layer, the readout and the biases
+ * are FP32.  Training runs Adam on the master weights with a cosine learning-rate schedule, on
+ * the GPU, and the readout can then be fitted by least squares (sph_mlp_fit_readout).  With
+ * eos = SPH_EOS_MLP the density pass uses the network in every table cell the trust mask accepts
+ * and table interpolation elsewhere (and everywhere while no network is loaded).
  * Parameters are SPH_MLP_NPARAM floats: W1[64][2], b1[64], W2[64][64], b2[64], W3[64][64],
  * b3[64], W4[2][64], b4[2] (W[out][in], row-major).  Inputs are normalised to [-1, 1] over the
- * table's box, outputs by the table's value range (sph_mlp_get_norm).  Every call needs the
- * EoS table in the context's parameters and waits for the stream. */
+ * network's domain (the table's box unless sph_mlp_set_domain narrows it), outputs by the value
+ * range of the table nodes that cover it (sph_mlp_get_norm).  Every call needs the EoS table in
+ * the context's parameters and waits for the stream. */
 #define SPH_MLP_NPARAM 8642
 
 /* Load FP32 master weights (host array); resets the optimiser and drops the trust mask. */
@@ -337,8 +340,14 @@ sph_status sph_mlp_set_params(sph_ctx* ctx, const float* params);
  * optimiser and drops the trust mask.  SPH_E_ARG without an EoS table.  Waits. */
 sph_status sph_mlp_load(sph_ctx* ctx, const uint16_t* bf16_weights);
 
-/* Copy the weights to the host: the FP32 masters, or (rounded != 0) the BF16 values the
- * kernels use, as floats.  SPH_E_ARG before sph_mlp_set_params. */
+/* Network domain: the box [lnrho_lo, lnrho_hi] x [lnu_lo, lnu_hi] inside the table's box where
+ * the network is trained and may serve (the trust mask tests only the table cells inside it).
+ * It sets the normalisation, so call it before sph_mlp_set_params / sph_mlp_load and training;
+ * drops the trust mask.  SPH_E_ARG for an empty box or one that leaves the table.  Waits. */
+sph_status sph_mlp_set_domain(sph_ctx* ctx, double lnrho_lo, double lnrho_hi, double lnu_lo, double lnu_hi);
+
+/* Copy the weights to the host: the FP32 masters, or (rounded != 0) the values the kernels use
+ * (W2, W3 rounded to BF16, the rest FP32), as floats.  SPH_E_ARG before sph_mlp_set_params. */
 sph_status sph_mlp_get_params(sph_ctx* ctx, float* params, int32_t rounded);
 
 /* Normalisation {in_lo[2], in_scale[2], out_centre[2], out_scale[2]}: x = (v - lo) scale - 1,
@@ -353,6 +362,15 @@ sph_status sph_mlp_get_norm(sph_ctx* ctx, float* norm8);
 sph_status sph_mlp_train(sph_ctx* ctx, const double* samples, int64_t n, int64_t n_holdout, int32_t epochs,
                          int32_t batch, float lr, float* history);
 
+/* Least-squares readout: with the hidden layers as they are, set W4, b4 to the minimiser of the
+ * squared output error over the first n - n_holdout of samples[n][2] (device, FP64, with
+ * table-interpolated targets as in sph_mlp_train), from the normal equations with ridge * (mean
+ * diagonal) added to the diagonal, solved by Cholesky in FP64 on the device.  holdout_loss (host,
+ * may be NULL) receives the loss over the last n_holdout samples afterwards.  Drops the trust
+ * mask.  SPH_E_ARG for fewer than 64 fit samples or a negative ridge. */
+sph_status sph_mlp_fit_readout(sph_ctx* ctx, const double* samples, int64_t n, int64_t n_holdout, double ridge,
+                               double* holdout_loss);
+
 /* Gradient of the loss over x[n][2], t[n][2] (device, normalised FP32; n a multiple of 64, at
  * most 8192) with the current BF16 weights, summed in a fixed order: grad[SPH_MLP_NPARAM] and
  * loss on the host.  Changes no weight. */
@@ -362,10 +380,11 @@ sph_status sph_mlp_grad(sph_ctx* ctx, const float* x, const float* t, int64_t n,
 sph_status sph_mlp_eval(sph_ctx* ctx, const double* lnrho, const double* lnu, int64_t n, double* lnP,
                         double* lncs2);
 
-/* Build the trust mask: a table cell is trusted when the network's P and c_s^2 are within relative
- * tolerance tol / 2 of the table at 13 points of the cell (its nodes, edge midpoints, centre and
- * four interior points drawn per cell from a counter-based generator); the margin of 2 covers the
- * points in between.  Returns the number of trusted cells of (nr - 1)(nu - 1). */
+/* Build the trust mask: a table cell inside the network's domain is trusted when the network's P
+ * and c_s^2 are within relative tolerance tol / 2 of the table at 13 points of the cell (its
+ * nodes, edge midpoints, centre and four interior points drawn per cell from a counter-based
+ * generator); the margin of 2 covers the points in between.  Returns the number of trusted cells
+ * of (nr - 1)(nu - 1). */
 sph_status sph_mlp_build_trust_mask(sph_ctx* ctx, double tol, int64_t* trusted_cells);
 
 /* Number of particles of the state whose (rho, u) lies in a trusted cell, i.e. that the network

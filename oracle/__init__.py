@@ -332,6 +332,8 @@ def _mlp_lib():
     L.orc_mlp_forward.restype = None
     L.orc_mlp_loss_grad.argtypes = [_dp, ctypes.c_int64, _dp, _dp, _dp]
     L.orc_mlp_loss_grad.restype = ctypes.c_double
+    L.orc_mlp_features.argtypes = [_dp, ctypes.c_int64, _dp, _dp]
+    L.orc_mlp_features.restype = None
     return L
 
 
@@ -342,6 +344,29 @@ def mlp_forward(w, x):
     y = np.zeros_like(x)
     _mlp_lib().orc_mlp_forward(_ptr(w), x.shape[0], _ptr(x), _ptr(y))
     return y
+
+
+def mlp_features(w, x):
+    """The last hidden layer h[n, 64] of the network for normalised inputs x[n, 2]."""
+    w = np.ascontiguousarray(w, np.float64)
+    x = np.ascontiguousarray(x, np.float64)
+    h = np.zeros((x.shape[0], 64))
+    _mlp_lib().orc_mlp_features(_ptr(w), x.shape[0], _ptr(x), _ptr(h))
+    return h
+
+
+def mlp_fit_readout(w, x, t, ridge=0.0):
+    """Least-squares readout: parameters w with W4, b4 replaced by the solution of the normal
+    equations (G + lambda I) [W4 b4]^T = [h 1]^T t, G = [h 1]^T [h 1] over samples x[n, 2] with
+    targets t[n, 2], lambda = ridge * mean(diag G); the hidden layers are those of w."""
+    w = np.array(w, np.float64)
+    H = np.concatenate([mlp_features(w, x), np.ones((x.shape[0], 1))], axis=1)
+    G = H.T @ H
+    G[np.diag_indices_from(G)] += ridge * np.trace(G) / G.shape[0]
+    sol = np.linalg.solve(G, H.T @ np.asarray(t, np.float64))   # [65, 2]
+    w[8512:8640] = sol[:64].T.reshape(-1)
+    w[8640:8642] = sol[64]
+    return w
 
 
 def mlp_loss_grad(w, x, t):

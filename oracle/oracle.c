@@ -935,6 +935,15 @@ void orc_mlp_forward(const double* w, int64_t n, const double* x, double* y) {
   }
 }
 
+void orc_mlp_features(const double* w, int64_t n, const double* x, double* h) {
+#pragma omp parallel for schedule(static)
+  for (int64_t s = 0; s < n; ++s) {
+    double z1[MH], z2[MH], z3[MH], y[2];
+    mlp_sample(w, x + 2 * s, z1, z2, z3, y);
+    for (int f = 0; f < MH; ++f) h[MH * s + f] = silu(z3[f]);
+  }
+}
+
 double orc_mlp_loss_grad(const double* w, int64_t n, const double* x, const double* t, double* grad) {
   memset(grad, 0, sizeof(double) * ORC_MLP_NPARAM);
   double loss = 0.0;

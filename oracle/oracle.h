@@ -179,6 +179,10 @@ int orc_evaluate(const orc_params* p, orc_state* st, int32_t ngb_mode);
 /* y[2n] = network(x[2n]) (sample-major pairs). */
 void orc_mlp_forward(const double* w, int64_t n, const double* x, double* y);
 
+/* h[64n] = the last hidden layer silu(z3) of each sample (sample-major): the inputs of the
+ * readout y = W4 h + b4. */
+void orc_mlp_features(const double* w, int64_t n, const double* x, double* h);
+
 /* Returns L and writes dL/dw to grad[ORC_MLP_NPARAM] (backpropagation, summed over samples). */
 double orc_mlp_loss_grad(const double* w, int64_t n, const double* x, const double* t, double* grad);
 

@@ -1,8 +1,8 @@
 // EoS surrogate network: 2 -> 64 -> 64 -> 64 -> 2 with SiLU activations, mapping normalised
-// (ln rho, ln u) to normalised (ln P, ln c_s^2).  Weights are BF16 (the forward pass uses the
-// BF16-rounded values of FP32 master weights), products accumulate in FP32; the two 64x64 layers
-// run on the matrix cores (v_mfma_f32_16x16x16_bf16), the 2-wide input and output layers and the
-// activations on the vector ALUs.
+// (ln rho, ln u) to normalised (ln P, ln c_s^2).  The two 64x64 layers run on the matrix cores
+// (v_mfma_f32_16x16x16_bf16) with BF16 weights (the BF16-rounded values of FP32 master weights)
+// and FP32 accumulation; the 2-wide input and output layers, the biases and the activations run
+// on the vector ALUs in FP32.
 //
 // MFMA operand layouts (16x16x16, wave64; lane l, q = l / 16, r = l % 16, j = 0..3):
 //   A (M x K):  lane holds A[r][4q + j]      B (K x N):  lane holds B[4q + j][r]
@@ -36,7 +36,7 @@ struct MlpNorm {
 
 // Read-only view of the network for the kernels.
 struct MlpView {
-  const float* wr;     // BF16-rounded parameters as FP32 (flat layout)
+  const float* wr;     // the parameters as used: W2, W3 rounded to BF16, the rest FP32 (flat layout)
   const uint2* wa2;    // W2 packed as MFMA A operands: [(mt * 4 + kk) * 64 + lane] = 4 BF16
   const uint2* wa3;    // W3 likewise
   const uint2* wt2;    // W2^T packed as A operands (backward pass)
@@ -75,9 +75,27 @@ __device__ __forceinline__ f32x4 mfma_bf16(bf16x4 a, bf16x4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
-// Network outputs for the 64 inputs held one per lane (x0, x1 normalised).  Every lane of the
-// wave must call it (matrix instructions); lane l receives the outputs of its own input.
-__device__ __forceinline__ void mlp_wave(const MlpView& M, float x0, float x1, float& y0, float& y1) {
+// The BF16 parameters: the two 64x64 matrix-core layers (W2, W3).  The 2 -> 64 input layer, the
+// 64 -> 2 readout and the biases run on the vector ALUs and stay FP32.
+__host__ __device__ __forceinline__ bool mlp_bf16_param(int p) {
+  return (p >= MLP_OW2 && p < MLP_OB2) || (p >= MLP_OW3 && p < MLP_OB3);
+}
+
+// An activation tile as the B operand of a BF16 product, split in two BF16 parts: hi = bf16(h),
+// lo = bf16(h - hi).  W (hi + lo) carries h to about 2^-17, so the products see the weights'
+// BF16 values but not a BF16 rounding of the activations.
+__device__ __forceinline__ void split_bf16(const float h[4], bf16x4& hi, bf16x4& lo) {
+  hi = pack_bf16(h[0], h[1], h[2], h[3]);
+  lo = pack_bf16(h[0] - bf16_round(h[0]), h[1] - bf16_round(h[1]), h[2] - bf16_round(h[2]), h[3] - bf16_round(h[3]));
+}
+
+// The network up to its last hidden layer for the 64 inputs held one per lane (x0, x1
+// normalised).  Every lane of the wave must call it (matrix instructions).  For each block of 16
+// inputs nt it calls out(nt, mt, h, w) with the lane's part of the last hidden layer: h[j] is
+// feature 16 mt + 4 q + j of input 16 nt + r (w: the parameters, through a pointer the compiler
+// does not hoist loads out of).
+template <typename Out>
+__device__ __forceinline__ void mlp_wave_hidden(const MlpView& M, float x0, float x1, Out&& out) {
   const int l = threadIdx.x & 63, q = l >> 4, r = l & 15;
 #pragma unroll 1
   for (int nt = 0; nt < 4; ++nt) {
@@ -89,7 +107,7 @@ __device__ __forceinline__ void mlp_wave(const MlpView& M, float x0, float x1, f
     asm volatile("" : "+s"(w), "+s"(wa2), "+s"(wa3));
     const int pp = 16 * nt + r;   // the input this lane's B-operand column belongs to
     const float a0 = __shfl(x0, pp, 64), a1 = __shfl(x1, pp, 64);
-    bf16x4 h1[4];
+    bf16x4 h1[4], l1[4];
     // scheduling barriers between the stages bound the weight loads in flight (registers)
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
@@ -100,44 +118,66 @@ __device__ __forceinline__ void mlp_wave(const MlpView& M, float x0, float x1, f
         const int f = 16 * kk + 4 * q + j;
         h[j] = silu_f(w[MLP_OW1 + 2 * f] * a0 + w[MLP_OW1 + 2 * f + 1] * a1 + w[MLP_OB1 + f]);
       }
-      h1[kk] = pack_bf16(h[0], h[1], h[2], h[3]);
+      split_bf16(h, h1[kk], l1[kk]);
     }
-    bf16x4 h2[4];
+    bf16x4 h2[4], l2[4];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
       __builtin_amdgcn_sched_barrier(0);
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) acc = mfma_bf16(as_bf16x4(wa2[(mt * 4 + kk) * 64 + l]), h1[kk], acc);
+      for (int kk = 0; kk < 4; ++kk) {
+        const bf16x4 wv = as_bf16x4(wa2[(mt * 4 + kk) * 64 + l]);
+        acc = mfma_bf16(wv, h1[kk], acc);
+        acc = mfma_bf16(wv, l1[kk], acc);
+      }
       float h[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) h[j] = silu_f(acc[j] + w[MLP_OB2 + 16 * mt + 4 * q + j]);
-      h2[mt] = pack_bf16(h[0], h[1], h[2], h[3]);
+      split_bf16(h, h2[mt], l2[mt]);
     }
-    float p0 = 0.f, p1 = 0.f;
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
       __builtin_amdgcn_sched_barrier(0);
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) acc = mfma_bf16(as_bf16x4(wa3[(mt * 4 + kk) * 64 + l]), h2[kk], acc);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int f = 16 * mt + 4 * q + j;
-        const float h3 = silu_f(acc[j] + w[MLP_OB3 + f]);
-        p0 += w[MLP_OW4 + f] * h3;
-        p1 += w[MLP_OW4 + MLP_H + f] * h3;
+      for (int kk = 0; kk < 4; ++kk) {
+        const bf16x4 wv = as_bf16x4(wa3[(mt * 4 + kk) * 64 + l]);
+        acc = mfma_bf16(wv, h2[kk], acc);
+        acc = mfma_bf16(wv, l2[kk], acc);
       }
+      float h3[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) h3[j] = silu_f(acc[j] + w[MLP_OB3 + 16 * mt + 4 * q + j]);
+      out(nt, mt, h3, w);
     }
     __builtin_amdgcn_sched_barrier(0);
-    // the four lanes r, r + 16, r + 32, r + 48 hold the partial sums of input 16 nt + r
-    p0 += __shfl_xor(p0, 16, 64);
-    p0 += __shfl_xor(p0, 32, 64);
-    p1 += __shfl_xor(p1, 16, 64);
-    p1 += __shfl_xor(p1, 32, 64);
-    if (q == nt) {
-      y0 = p0 + w[MLP_OB4];
-      y1 = p1 + w[MLP_OB4 + 1];
-    }
   }
+}
+
+// Network outputs for the 64 inputs held one per lane (x0, x1 normalised).  Every lane of the
+// wave must call it; lane l receives the outputs of its own input.
+__device__ __forceinline__ void mlp_wave(const MlpView& M, float x0, float x1, float& y0, float& y1) {
+  const int q = (threadIdx.x & 63) >> 4;
+  float p0 = 0.f, p1 = 0.f;
+  mlp_wave_hidden(M, x0, x1, [&](int nt, int mt, const float h3[4], const float* w) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int f = 16 * mt + 4 * q + j;
+      p0 += w[MLP_OW4 + f] * h3[j];
+      p1 += w[MLP_OW4 + MLP_H + f] * h3[j];
+    }
+    if (mt == 3) {
+      // the four lanes r, r + 16, r + 32, r + 48 hold the partial sums of input 16 nt + r
+      p0 += __shfl_xor(p0, 16, 64);
+      p0 += __shfl_xor(p0, 32, 64);
+      p1 += __shfl_xor(p1, 16, 64);
+      p1 += __shfl_xor(p1, 32, 64);
+      if (q == nt) {
+        y0 = p0 + w[MLP_OB4];
+        y1 = p1 + w[MLP_OB4 + 1];
+      }
+      p0 = p1 = 0.f;
+    }
+  });
 }

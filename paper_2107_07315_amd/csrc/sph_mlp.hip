@@ -11,7 +11,7 @@
 
 struct MlpState {
   float* w = nullptr;      // FP32 master parameters
-  float* wr = nullptr;     // BF16-rounded copy
+  float* wr = nullptr;     // the parameters the kernels use (W2, W3 rounded to BF16)
   float* m = nullptr;      // Adam moments
   float* v = nullptr;
   uint2* pack = nullptr;   // wa2, wa3, wt2, wt3: 4 x 1024 entries
@@ -26,6 +26,11 @@ struct MlpState {
   bool loaded = false;
   bool norm_set = false;
   MlpNorm norm;
+  // the network's domain in (ln rho, ln u) (sph_mlp_set_domain): lnr_lo, lnr_hi, lnu_lo, lnu_hi;
+  // the table's box when not set
+  bool dom_set = false;
+  double dom[4] = {0.0, 0.0, 0.0, 0.0};
+  double* gpart64 = nullptr;  // readout fit: per-block Gram partials
 };
 
 namespace {
@@ -52,6 +57,11 @@ __device__ __forceinline__ bf16x4 lds_b4_strided(const uint16_t* p, int stride) 
 __device__ __forceinline__ void lds_store_b4(uint16_t* p, float a, float b, float c, float d) {
   *reinterpret_cast<uint2*>(p) = make_uint2(bf16_bits(a) | (bf16_bits(b) << 16), bf16_bits(c) | (bf16_bits(d) << 16));
 }
+// the BF16 parts hi = bf16(h) and lo = bf16(h - hi) of 4 activations (see split_bf16)
+__device__ __forceinline__ void lds_store_split(uint16_t* hi, uint16_t* lo, float a, float b, float c, float d) {
+  lds_store_b4(hi, a, b, c, d);
+  lds_store_b4(lo, a - bf16_round(a), b - bf16_round(b), c - bf16_round(c), d - bf16_round(d));
+}
 
 struct GradArgs {
   MlpView M;
@@ -67,10 +77,14 @@ struct GradArgs {
 // Gradient of L = 1/(2 batch) sum_s sum_o (y_so - t_so)^2 over the block's 64 samples (lane =
 // sample), written as this block's partial.  Layers 2 and 3 and their weight gradients and
 // back-propagated activations are 64x64x64 products on the matrix cores; activations are kept
-// in LDS sample-major (row = sample, column = feature).
+// in LDS sample-major (row = sample, column = feature).  The forward products take the
+// activations as two BF16 parts, as the inference does (the loss is that of the network the
+// kernels evaluate); the weight gradients use their high parts.
 __global__ __launch_bounds__(64) void k_mlp_grad(GradArgs G) {
   __shared__ __align__(16) uint16_t Ht1[64 * LP];
   __shared__ __align__(16) uint16_t Ht2[64 * LP];
+  __shared__ __align__(16) uint16_t Lt1[64 * LP];   // low BF16 parts of the activations
+  __shared__ __align__(16) uint16_t Lt2[64 * LP];
   __shared__ __align__(16) uint16_t Gt[64 * LP];
   __shared__ __align__(16) float Zt2[64 * LP];
   __shared__ __align__(16) float Zt3[64 * LP];
@@ -91,7 +105,7 @@ __global__ __launch_bounds__(64) void k_mlp_grad(GradArgs G) {
 #pragma unroll
     for (int j = 0; j < 4; ++j)
       h[j] = silu_f(w[MLP_OW1 + 2 * (f + j)] * x0 + w[MLP_OW1 + 2 * (f + j) + 1] * x1 + w[MLP_OB1 + f + j]);
-    lds_store_b4(&Ht1[l * LP + f], h[0], h[1], h[2], h[3]);
+    lds_store_split(&Ht1[l * LP + f], &Lt1[l * LP + f], h[0], h[1], h[2], h[3]);
   }
   __syncthreads();
   // hidden layers: C tile (features 16 mt + 4q + j, samples 16 nt + r)
@@ -99,22 +113,30 @@ __global__ __launch_bounds__(64) void k_mlp_grad(GradArgs G) {
     const uint2* wa = layer == 0 ? M.wa2 : M.wa3;
     const int ob = layer == 0 ? MLP_OB2 : MLP_OB3;
     const uint16_t* Hin = layer == 0 ? Ht1 : Ht2;
+    const uint16_t* Lin = layer == 0 ? Lt1 : Lt2;
     float* Z = layer == 0 ? Zt2 : Zt3;
     for (int nt = 0; nt < 4; ++nt) {
-      bf16x4 b[4];
+      bf16x4 b[4], bl[4];
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) b[kk] = lds_b4(&Hin[(16 * nt + r) * LP + 16 * kk + 4 * q]);
+      for (int kk = 0; kk < 4; ++kk) {
+        b[kk] = lds_b4(&Hin[(16 * nt + r) * LP + 16 * kk + 4 * q]);
+        bl[kk] = lds_b4(&Lin[(16 * nt + r) * LP + 16 * kk + 4 * q]);
+      }
       for (int mt = 0; mt < 4; ++mt) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) acc = mfma_bf16(as_bf16x4(wa[(mt * 4 + kk) * 64 + l]), b[kk], acc);
+        for (int kk = 0; kk < 4; ++kk) {
+          const bf16x4 wv = as_bf16x4(wa[(mt * 4 + kk) * 64 + l]);
+          acc = mfma_bf16(wv, b[kk], acc);
+          acc = mfma_bf16(wv, bl[kk], acc);
+        }
         float z[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) z[j] = acc[j] + w[ob + 16 * mt + 4 * q + j];
         *reinterpret_cast<float4*>(&Z[(16 * nt + r) * LP + 16 * mt + 4 * q]) = make_float4(z[0], z[1], z[2], z[3]);
         if (layer == 0)
-          lds_store_b4(&Ht2[(16 * nt + r) * LP + 16 * mt + 4 * q], silu_f(z[0]), silu_f(z[1]), silu_f(z[2]),
-                       silu_f(z[3]));
+          lds_store_split(&Ht2[(16 * nt + r) * LP + 16 * mt + 4 * q], &Lt2[(16 * nt + r) * LP + 16 * mt + 4 * q],
+                          silu_f(z[0]), silu_f(z[1]), silu_f(z[2]), silu_f(z[3]));
       }
     }
     __syncthreads();
@@ -232,7 +254,7 @@ __global__ __launch_bounds__(64) void k_mlp_grad(GradArgs G) {
 }
 
 // Sums the block partials in block order (deterministic), then optionally one Adam step on the
-// FP32 master weights and the BF16-rounded copy; block 0 also sums the loss.
+// FP32 master weights and the copy the kernels use; block 0 also sums the loss.
 __global__ __launch_bounds__(256) void k_mlp_adam(float* w, float* wr, float* m, float* v, const float* gpart,
                                                   const float* lpart, int nblk, float lr, float bc1, float bc2,
                                                   float* gsum, float* loss_out) {
@@ -248,7 +270,7 @@ __global__ __launch_bounds__(256) void k_mlp_adam(float* w, float* wr, float* m,
       v[p] = vv;
       const float wn = w[p] - lr * (mm / bc1) / (sqrtf(vv / bc2) + 1e-8f);
       w[p] = wn;
-      wr[p] = bf16_round(wn);
+      wr[p] = mlp_bf16_param(p) ? bf16_round(wn) : wn;
     }
   }
   if (p == 0 && loss_out) {
@@ -275,17 +297,21 @@ __global__ __launch_bounds__(256) void k_mlp_pack(const float* wr, uint2* pack) 
   pack[i] = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
 }
 
+// The parameters as the kernels use them: the matrix-core weights rounded to BF16, the rest FP32.
 __global__ __launch_bounds__(256) void k_round(const float* w, float* wr, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) wr[i] = bf16_round(w[i]);
+  if (i < n) wr[i] = mlp_bf16_param(i) ? bf16_round(w[i]) : w[i];
 }
 
-// min / max of the finite table nodes of ln P and ln c_s^2 (one block)
+// min / max of the finite table nodes of ln P and ln c_s^2 in rows [i0, i1] and columns [j0, j1]
+// of the nu-column table (one block)
 __global__ __launch_bounds__(256) void k_table_range(const double* __restrict__ lnP, const double* __restrict__ lnc,
-                                                     int64_t n, float* out) {
+                                                     int i0, int i1, int j0, int j1, int nu, float* out) {
   __shared__ double red[4][256];
   double v[4] = {1e300, -1e300, 1e300, -1e300};
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+  const int64_t w = j1 - j0 + 1, n = (int64_t)(i1 - i0 + 1) * w;
+  for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
+    const int64_t i = (int64_t)(i0 + k / w) * nu + j0 + k % w;
     const double a = lnP[i], b = lnc[i];
     if (isfinite(a)) { v[0] = fmin(v[0], a); v[1] = fmax(v[1], a); }
     if (isfinite(b)) { v[2] = fmin(v[2], b); v[3] = fmax(v[3], b); }
@@ -360,6 +386,122 @@ __global__ __launch_bounds__(64) void k_mlp_eval(MlpView M, const double* __rest
   }
 }
 
+// Least-squares readout: with the hidden layers fixed, the outputs are linear in (W4, b4), so the
+// readout that minimises the squared error over the training samples solves the normal equations
+// (G + lambda I) [W4 b4]^T = H^T T, G = H^T H, H the samples' last hidden layer (as the kernels
+// compute it) extended by a constant 1.  Per block, thread f accumulates row f of G over the
+// block's samples in FP64 (columns 0..63, then the constant column, then the two right-hand
+// sides): 67 values per row, 64 rows, and the sums of the targets.
+constexpr int kGramRow = 67, kGramStride = 64 * kGramRow + 2;
+__global__ __launch_bounds__(64) void k_mlp_gram(MlpView M, const float* __restrict__ x, const float* __restrict__ t,
+                                                 int64_t n, double* __restrict__ part) {
+  __shared__ float H[64][MLP_H + 4];
+  __shared__ float T[64][2];
+  const int l = threadIdx.x, q = l >> 4, r = l & 15;
+  double acc[kGramRow];
+#pragma unroll
+  for (int g = 0; g < kGramRow; ++g) acc[g] = 0.0;
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t base = (int64_t)blockIdx.x * 64; base < n; base += (int64_t)gridDim.x * 64) {
+    const int64_t i = base + l;
+    const bool ok = i < n;
+    mlp_wave_hidden(M, ok ? x[2 * i] : 0.f, ok ? x[2 * i + 1] : 0.f,
+                    [&](int nt, int mt, const float h3[4], const float*) {
+                      const bool oks = base + 16 * nt + r < n;
+#pragma unroll
+                      for (int j = 0; j < 4; ++j) H[16 * nt + r][16 * mt + 4 * q + j] = oks ? h3[j] : 0.f;
+                    });
+    T[l][0] = ok ? t[2 * i] : 0.f;
+    T[l][1] = ok ? t[2 * i + 1] : 0.f;
+    __syncthreads();
+    const int ns = n - base < 64 ? (int)(n - base) : 64;
+    for (int sI = 0; sI < ns; ++sI) {
+      const double hf = (double)H[sI][l];
+#pragma unroll
+      for (int g = 0; g < MLP_H; ++g) acc[g] += hf * (double)H[sI][g];
+      const double t0 = (double)T[sI][0], t1 = (double)T[sI][1];
+      acc[MLP_H] += hf;
+      acc[MLP_H + 1] += hf * t0;
+      acc[MLP_H + 2] += hf * t1;
+      s0 += t0;
+      s1 += t1;
+    }
+    __syncthreads();
+  }
+  double* o = part + (int64_t)blockIdx.x * kGramStride;
+#pragma unroll
+  for (int g = 0; g < kGramRow; ++g) o[l * kGramRow + g] = acc[g];
+  if (l == 0) {
+    o[64 * kGramRow] = s0;
+    o[64 * kGramRow + 1] = s1;
+  }
+}
+
+// Sums the block partials in block order (deterministic), adds lambda = ridge * mean diagonal,
+// solves by Cholesky (one workgroup, in LDS) and writes W4, b4 into the master weights and the
+// copy the kernels use (both FP32).
+__global__ __launch_bounds__(256) void k_mlp_solve(const double* __restrict__ part, int nblk, int64_t n, double ridge,
+                                                   float* __restrict__ w, float* __restrict__ wr) {
+  constexpr int N = MLP_H + 1;
+  __shared__ double A[N][N + 1];
+  __shared__ double B[N][2];
+  __shared__ double X[N][2];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kGramStride; e += blockDim.x) {
+    double v = 0.0;
+    for (int b = 0; b < nblk; ++b) v += part[(int64_t)b * kGramStride + e];
+    if (e < 64 * kGramRow) {
+      const int f = e / kGramRow, g = e % kGramRow;
+      if (g < MLP_H) A[f][g] = v;
+      else if (g == MLP_H) { A[f][MLP_H] = v; A[MLP_H][f] = v; }
+      else B[f][g - MLP_H - 1] = v;
+    } else {
+      B[MLP_H][e - 64 * kGramRow] = v;
+    }
+  }
+  if (tid == 0) A[MLP_H][MLP_H] = (double)n;
+  __syncthreads();
+  if (tid == 0) {
+    double tr = 0.0;
+    for (int i = 0; i < N; ++i) tr += A[i][i];
+    const double lam = ridge * tr / N;
+    for (int i = 0; i < N; ++i) A[i][i] += lam;
+  }
+  __syncthreads();
+  for (int k = 0; k < N; ++k) {   // A = L L^T, L in the lower triangle
+    if (tid == 0) A[k][k] = sqrt(fmax(A[k][k], 1e-300));
+    __syncthreads();
+    for (int i = k + 1 + tid; i < N; i += blockDim.x) A[i][k] /= A[k][k];
+    __syncthreads();
+    const int m = N - k - 1;
+    for (int idx = tid; idx < m * m; idx += blockDim.x) {
+      const int i = k + 1 + idx / m, j = k + 1 + idx % m;
+      if (j <= i) A[i][j] -= A[i][k] * A[j][k];
+    }
+    __syncthreads();
+  }
+  if (tid < 2) {
+    const int o = tid;
+    for (int i = 0; i < N; ++i) {   // L y = b
+      double v = B[i][o];
+      for (int j = 0; j < i; ++j) v -= A[i][j] * X[j][o];
+      X[i][o] = v / A[i][i];
+    }
+    for (int i = N - 1; i >= 0; --i) {   // L^T x = y
+      double v = X[i][o];
+      for (int j = i + 1; j < N; ++j) v -= A[j][i] * X[j][o];
+      X[i][o] = v / A[i][i];
+    }
+    for (int f = 0; f < MLP_H; ++f) {
+      const float v = (float)X[f][o];
+      w[MLP_OW4 + MLP_H * o + f] = v;
+      wr[MLP_OW4 + MLP_H * o + f] = v;
+    }
+    w[MLP_OB4 + o] = (float)X[MLP_H][o];
+    wr[MLP_OB4 + o] = (float)X[MLP_H][o];
+  }
+}
+
 // Interior test points of a table cell: four per cell from a counter-based generator (splitmix64
 // of the cell index and the point number), fractions in [0, 1).
 __device__ __forceinline__ double cell_uniform(uint64_t cell, int k) {
@@ -374,8 +516,13 @@ __device__ __forceinline__ double cell_uniform(uint64_t cell, int k) {
 // tol / 2 (a margin of 2 for the points in between) of the table at 13 points of the cell: its four
 // nodes, the four edge midpoints, the centre and four seeded interior points.
 constexpr int kTrustPoints = 13;
-__global__ __launch_bounds__(64) void k_mlp_trust(MlpView M, sph_params p, double tol, uint8_t* __restrict__ mask,
-                                                  unsigned long long* count) {
+// Only cells inside the network's domain dom = (lnr_lo, lnr_hi, lnu_lo, lnu_hi) are tested; the
+// others stay untrusted.
+struct Domain {
+  double d[4];
+};
+__global__ __launch_bounds__(64) void k_mlp_trust(MlpView M, sph_params p, Domain D, double tol,
+                                                  uint8_t* __restrict__ mask, unsigned long long* count) {
   const MlpNorm& nm = M.norm;
   const int nu1 = p.tab_nu - 1;
   const int64_t ncell = (int64_t)(p.tab_nr - 1) * nu1;
@@ -384,8 +531,13 @@ __global__ __launch_bounds__(64) void k_mlp_trust(MlpView M, sph_params p, doubl
     const int64_t c = base + threadIdx.x;
     const bool ok = c < ncell;
     const int i = ok ? (int)(c / nu1) : 0, j = ok ? (int)(c % nu1) : 0;
+    const double e = 1e-9;   // a cell whose edge lies on the domain's edge is inside
+    const bool inside = p.tab_lnr0 + i * p.tab_dlnr >= D.d[0] - e * p.tab_dlnr &&
+                        p.tab_lnr0 + (i + 1) * p.tab_dlnr <= D.d[1] + e * p.tab_dlnr &&
+                        p.tab_lnu0 + j * p.tab_dlnu >= D.d[2] - e * p.tab_dlnu &&
+                        p.tab_lnu0 + (j + 1) * p.tab_dlnu <= D.d[3] + e * p.tab_dlnu;
     double err = 0.0;
-    bool finite = true;
+    bool finite = inside;
     const double fa9[9] = {0.0, 1.0, 0.0, 1.0, 0.5, 0.5, 0.0, 1.0, 0.5}, fb9[9] = {0.0, 0.0, 1.0, 1.0, 0.0, 1.0, 0.5, 0.5, 0.5};
 #pragma unroll 1
     for (int k = 0; k < kTrustPoints; ++k) {
@@ -444,21 +596,40 @@ bool table_ok(const sph_ctx* c) {
   return p.tab_lnP && p.tab_lncs2 && p.tab_nr >= 2 && p.tab_nu >= 2;
 }
 
-// input normalisation from the table's box, output normalisation from its value range
+// The network's domain: the one set by sph_mlp_set_domain, else the table's box.
+Domain domain_of(const sph_ctx* c) {
+  const sph_params& p = c->p;
+  const MlpState* s = c->mlp;
+  if (s && s->dom_set) return Domain{{s->dom[0], s->dom[1], s->dom[2], s->dom[3]}};
+  return Domain{{p.tab_lnr0, p.tab_lnr0 + (p.tab_nr - 1) * p.tab_dlnr, p.tab_lnu0, p.tab_lnu0 + (p.tab_nu - 1) * p.tab_dlnu}};
+}
+
+// input normalisation from the domain, output normalisation from the value range of the table
+// nodes that cover it
 sph_status mlp_norm(sph_ctx* c) {
   MlpState* s = c->mlp;
   if (s->norm_set) return SPH_OK;
   const sph_params& p = c->p;
-  hipLaunchKernelGGL(k_table_range, dim3(1), dim3(256), 0, c->stream, p.tab_lnP, p.tab_lncs2,
-                     (int64_t)p.tab_nr * p.tab_nu, s->scal);
+  const Domain D = domain_of(c);
+  auto node = [](double v, double v0, double dv, int nmax, bool up) {
+    const double f = (v - v0) / dv;
+    int i = up ? (int)ceil(f - 1e-9) : (int)floor(f + 1e-9);
+    return i < 0 ? 0 : (i > nmax ? nmax : i);
+  };
+  const int i0 = node(D.d[0], p.tab_lnr0, p.tab_dlnr, p.tab_nr - 1, false);
+  const int i1 = node(D.d[1], p.tab_lnr0, p.tab_dlnr, p.tab_nr - 1, true);
+  const int j0 = node(D.d[2], p.tab_lnu0, p.tab_dlnu, p.tab_nu - 1, false);
+  const int j1 = node(D.d[3], p.tab_lnu0, p.tab_dlnu, p.tab_nu - 1, true);
+  hipLaunchKernelGGL(k_table_range, dim3(1), dim3(256), 0, c->stream, p.tab_lnP, p.tab_lncs2, i0, i1, j0, j1, p.tab_nu,
+                     s->scal);
   float r[4];
   HIP_TRY(hipMemcpyAsync(r, s->scal, sizeof(r), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   MlpNorm& nm = s->norm;
-  nm.in_lo[0] = (float)p.tab_lnr0;
-  nm.in_lo[1] = (float)p.tab_lnu0;
-  nm.in_sc[0] = (float)(2.0 / ((p.tab_nr - 1) * p.tab_dlnr));
-  nm.in_sc[1] = (float)(2.0 / ((p.tab_nu - 1) * p.tab_dlnu));
+  nm.in_lo[0] = (float)D.d[0];
+  nm.in_lo[1] = (float)D.d[2];
+  nm.in_sc[0] = (float)(2.0 / (D.d[1] - D.d[0]));
+  nm.in_sc[1] = (float)(2.0 / (D.d[3] - D.d[2]));
   nm.out_c[0] = r[0];
   nm.out_c[1] = r[1];
   nm.out_sc[0] = r[2] > 0.f ? r[2] : 1.f;
@@ -509,7 +680,7 @@ int64_t mlp_trusted_cells(const sph_ctx* c) {
 void mlp_free(sph_ctx* c) {
   MlpState* s = c->mlp;
   if (!s) return;
-  void* bufs[] = {s->w, s->wr, s->m, s->v, s->pack, s->gpart, s->lpart, s->gsum, s->scal, s->trust, s->served};
+  void* bufs[] = {s->w, s->wr, s->m, s->v, s->pack, s->gpart, s->lpart, s->gsum, s->scal, s->trust, s->served, s->gpart64};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete s;
@@ -653,6 +824,88 @@ sph_status sph_mlp_train(sph_ctx* c, const double* samples, int64_t n, int64_t n
   return e;
 }
 
+sph_status sph_mlp_set_domain(sph_ctx* c, double lnrho_lo, double lnrho_hi, double lnu_lo, double lnu_hi) {
+  if (!c) return note(nullptr, SPH_E_ARG, "context is NULL");
+  if (!table_ok(c)) return note(c, SPH_E_ARG, "the network needs the context's EoS table");
+  const sph_params& p = c->p;
+  const double r1 = p.tab_lnr0 + (p.tab_nr - 1) * p.tab_dlnr, u1 = p.tab_lnu0 + (p.tab_nu - 1) * p.tab_dlnu;
+  if (!(lnrho_lo < lnrho_hi) || !(lnu_lo < lnu_hi) || lnrho_lo < p.tab_lnr0 || lnrho_hi > r1 || lnu_lo < p.tab_lnu0 ||
+      lnu_hi > u1)
+    return note(c, SPH_E_ARG, "domain [%g, %g] x [%g, %g] is empty or leaves the table's box [%g, %g] x [%g, %g]",
+                lnrho_lo, lnrho_hi, lnu_lo, lnu_hi, p.tab_lnr0, r1, p.tab_lnu0, u1);
+  sph_status e;
+  if ((e = mlp_alloc(c))) return e;
+  MlpState* s = c->mlp;
+  s->dom_set = true;
+  s->dom[0] = lnrho_lo;
+  s->dom[1] = lnrho_hi;
+  s->dom[2] = lnu_lo;
+  s->dom[3] = lnu_hi;
+  s->norm_set = false;
+  if ((e = mlp_norm(c))) return e;
+  if (s->trust) {   // a mask belongs to the normalisation it was built with
+    (void)hipFree(s->trust);
+    s->trust = nullptr;
+    s->trust_cells = 0;
+  }
+  ++c->graph_epoch;
+  return SPH_OK;
+}
+
+sph_status sph_mlp_fit_readout(sph_ctx* c, const double* samples, int64_t n, int64_t n_holdout, double ridge,
+                               double* holdout_loss) {
+  if (!c) return note(nullptr, SPH_E_ARG, "context is NULL");
+  if (!samples || !c->mlp || !c->mlp->loaded || !table_ok(c))
+    return note(c, SPH_E_ARG, "the fit needs samples, a loaded network and the EoS table");
+  if (n_holdout < 0 || n - n_holdout < 64 || !(ridge >= 0.0))
+    return note(c, SPH_E_ARG, "n = %lld, n_holdout = %lld (at least 64 fit samples), ridge = %g", (long long)n,
+                (long long)n_holdout, ridge);
+  MlpState* s = c->mlp;
+  constexpr int kGramBlocks = 1024;
+  if (!s->gpart64 && hipMalloc((void**)&s->gpart64, sizeof(double) * (size_t)kGramBlocks * kGramStride) != hipSuccess) {
+    s->gpart64 = nullptr;
+    return note(c, SPH_E_OOM, "readout fit partials");
+  }
+  float *x = nullptr, *t = nullptr, *part = nullptr;
+  sph_status e = SPH_OK;
+  if ((e = dalloc(&x, (size_t)2 * n)) || (e = dalloc(&t, (size_t)2 * n)) || (e = dalloc(&part, 1024))) {
+    if (x) (void)hipFree(x);
+    if (t) (void)hipFree(t);
+    return note(c, e, "readout fit scratch");
+  }
+  hipLaunchKernelGGL(k_mlp_targets, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, c->p, s->norm, samples, n, x, t,
+                     c->status);
+  const int64_t nfit = n - n_holdout;
+  const unsigned nb = (unsigned)((nfit + 63) / 64 < kGramBlocks ? (nfit + 63) / 64 : kGramBlocks);
+  hipLaunchKernelGGL(k_mlp_gram, dim3(nb), dim3(64), 0, c->stream, view_of(s), x, t, nfit, s->gpart64);
+  hipLaunchKernelGGL(k_mlp_solve, dim3(1), dim3(256), 0, c->stream, s->gpart64, (int)nb, nfit, ridge, s->w, s->wr);
+  if (hipGetLastError() != hipSuccess) e = SPH_E_HIP;
+  float hl = 0.f;
+  if (!e && n_holdout > 0) {
+    const unsigned hb = (unsigned)((n_holdout + 63) / 64 < 1024 ? (n_holdout + 63) / 64 : 1024);
+    hipLaunchKernelGGL(k_mlp_sqerr, dim3(hb), dim3(64), 0, c->stream, view_of(s), x + 2 * nfit, t + 2 * nfit,
+                       n_holdout, part);
+    std::vector<float> hp(hb);
+    if (hipMemcpyAsync(hp.data(), part, sizeof(float) * hb, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+      e = SPH_E_HIP;
+    if (!e && hipStreamSynchronize(c->stream) != hipSuccess) e = SPH_E_HIP;
+    for (float v : hp) hl += v;
+    hl /= (float)n_holdout;
+  }
+  if (!e && hipStreamSynchronize(c->stream) != hipSuccess) e = SPH_E_HIP;
+  (void)hipFree(x);
+  (void)hipFree(t);
+  (void)hipFree(part);
+  if (s->trust) {   // the weights changed
+    (void)hipFree(s->trust);
+    s->trust = nullptr;
+    s->trust_cells = 0;
+  }
+  ++c->graph_epoch;
+  if (holdout_loss) *holdout_loss = hl;
+  return e ? note(c, e, "readout fit on the device") : SPH_OK;
+}
+
 sph_status sph_mlp_eval(sph_ctx* c, const double* lnrho, const double* lnu, int64_t n, double* lnP, double* lncs2) {
   if (!c || n < 0 || (n > 0 && (!lnrho || !lnu || !lnP || !lncs2)) || !c->mlp || !c->mlp->loaded ||
       !c->mlp->norm_set)
@@ -699,7 +952,7 @@ sph_status sph_mlp_build_trust_mask(sph_ctx* c, double tol, int64_t* trusted_cel
     MlpView v = view_of(s);
     v.trust = nullptr;
     const unsigned nb = (unsigned)((ncell + 63) / 64 < 65536 ? (ncell + 63) / 64 : 65536);
-    hipLaunchKernelGGL(k_mlp_trust, dim3(nb), dim3(64), 0, c->stream, v, c->p, tol, s->trust, cnt);
+    hipLaunchKernelGGL(k_mlp_trust, dim3(nb), dim3(64), 0, c->stream, v, c->p, domain_of(c), tol, s->trust, cnt);
     if (hipGetLastError() != hipSuccess ||
         hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess)

@@ -23,7 +23,7 @@ EXPORTED = ("sph_create", "sph_destroy", "sph_set_params", "sph_build_cells", "s
             "sph_mlp_set_params", "sph_mlp_get_params", "sph_mlp_get_norm", "sph_mlp_train", "sph_mlp_grad",
             "sph_mlp_eval", "sph_mlp_build_trust_mask", "sph_ensemble_set", "sph_autotune", "sph_mlp_load",
             "sph_last_error_detail", "sph_eos_table_create", "sph_neighbour_stats_noalloc", "sph_modify_energy",
-            "sph_diagnostics", "sph_get_time", "sph_mlp_count_served")
+            "sph_diagnostics", "sph_get_time", "sph_mlp_count_served", "sph_mlp_set_domain", "sph_mlp_fit_readout")
 MLP_NPARAM = 8642
 
 _dp = ctypes.c_void_p
@@ -136,6 +136,9 @@ def load():
     L.sph_diagnostics.argtypes = [vp, S, ctypes.POINTER(SphDiagParams), vp]
     L.sph_get_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     L.sph_mlp_count_served.argtypes = [vp, S, ctypes.POINTER(ctypes.c_int64)]
+    L.sph_mlp_set_domain.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    L.sph_mlp_fit_readout.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
+                                      ctypes.POINTER(ctypes.c_double)]
     L.sph_last_error_detail.argtypes = [vp]
     L.sph_last_error_detail.restype = ctypes.c_char_p
     L.sph_eos_table_create.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
@@ -427,6 +430,19 @@ class Context:
         _check(self.lib.sph_mlp_train(self.h, samples.data_ptr(), samples.shape[0], int(n_holdout), int(epochs),
                                       int(batch), float(lr), hist.ctypes.data), "sph_mlp_train")
         return hist[:epochs]
+
+    def mlp_set_domain(self, lnrho_lo, lnrho_hi, lnu_lo, lnu_hi):
+        _check(self.lib.sph_mlp_set_domain(self.h, float(lnrho_lo), float(lnrho_hi), float(lnu_lo), float(lnu_hi)),
+               "sph_mlp_set_domain", self.h)
+
+    def mlp_fit_readout(self, samples, n_holdout, ridge=1e-10):
+        """Least-squares readout over device FP64 samples [n, 2]; returns the holdout loss after it."""
+        import torch
+        assert samples.dtype == torch.float64 and samples.is_cuda and samples.is_contiguous()
+        hl = ctypes.c_double()
+        _check(self.lib.sph_mlp_fit_readout(self.h, samples.data_ptr(), samples.shape[0], int(n_holdout), float(ridge),
+                                            ctypes.byref(hl)), "sph_mlp_fit_readout", self.h)
+        return hl.value
 
     def mlp_grad(self, x, t):
         """Gradient of the loss over device FP32 tensors x, t [n, 2] (normalised units)."""

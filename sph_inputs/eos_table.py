@@ -85,3 +85,39 @@ def mlp_samples(table: EosTable, n: int = 1_000_000, seed: int = 4) -> np.ndarra
     lnr = table.lnr0 + rng.uniform(0.0, 1.0, n) * (nr - 1) * table.dlnr
     lnu = table.lnu0 + rng.uniform(0.0, 1.0, n) * (nu - 1) * table.dlnu
     return np.ascontiguousarray(np.stack([lnr, lnu], axis=1))
+
+
+def mlp_band_samples(pp: PiecewisePolytrope, lnr_lo: float, lnr_hi: float, width: float, n: int,
+                     seed: int = 4) -> np.ndarray:
+    """Training inputs (ln rho, ln u) in a band around the cold curve: ln rho uniform in
+    [lnr_lo, lnr_hi], ln u = ln u_cold(rho) + a uniform offset in [-width, width]."""
+    rng = np.random.default_rng(seed)
+    lnr = rng.uniform(lnr_lo, lnr_hi, n)
+    _, uc = pp.from_rho(np.exp(lnr))
+    lnu = np.log(uc) + rng.uniform(-width, width, n)
+    return np.ascontiguousarray(np.stack([lnr, lnu], axis=1))
+
+
+def band_domain(pp: PiecewisePolytrope, lnr_lo: float, lnr_hi: float, width: float):
+    """The box (lnr_lo, lnr_hi, lnu_lo, lnu_hi) around that band."""
+    lnr = np.linspace(lnr_lo, lnr_hi, 4097)
+    _, uc = pp.from_rho(np.exp(lnr))
+    lnu = np.log(uc)
+    return float(lnr_lo), float(lnr_hi), float(lnu.min() - width), float(lnu.max() + width)
+
+
+def piece_band(pp: PiecewisePolytrope, piece: int, rho_c: float, table: EosTable, width: float = 0.06):
+    """One polytrope piece of a star with central density rho_c, between the first table node
+    above its lower dividing density and the last node below its upper one (table cells across a
+    division interpolate over the jump of c_s^2 there), the densest piece up to 1.15 rho_c (the
+    particles' densities overshoot the profile's centre a little), with a band of +-width in
+    ln u: the (ln rho_lo, ln rho_hi, width) of an EoS network's domain."""
+    divs = [math.log(d) for d in pp.rho_divs]
+    lo = table.lnr0
+    if piece > 0:
+        lo = table.lnr0 + math.ceil((divs[piece - 1] - table.lnr0) / table.dlnr + 1e-9) * table.dlnr
+    if piece < len(divs):
+        hi = table.lnr0 + math.floor((divs[piece] - table.lnr0) / table.dlnr - 1e-9) * table.dlnr
+    else:
+        hi = math.log(1.15 * rho_c)
+    return float(lo), float(hi), float(width)

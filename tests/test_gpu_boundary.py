@@ -48,15 +48,18 @@ def test_network_from_bf16_weights():
 
     from paper_2107_07315_amd import sph
     w = W.pp_star(2000, seed=4, eos="MLP")
+    # a network whose every weight is a BF16 number (round to nearest even), as trained elsewhere
+    u = mlp_init(4).view(np.uint32).astype(np.uint64)
+    bits = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+    wb = (bits.astype(np.uint32) << 16).view(np.float32)
     c1 = sph.Context(w.params, capacity=w.n)
-    c1.mlp_set_params(mlp_init(4))
-    wr = c1.mlp_get_params(rounded=True)              # the BF16 values the kernels use
-    bits = (wr.view(np.uint32) >> 16).astype(np.uint16)
-    assert np.array_equal((bits.astype(np.uint32) << 16).view(np.float32), wr)
+    c1.mlp_set_params(wb)
+    wr = c1.mlp_get_params(rounded=True)              # the values the kernels use
+    assert np.array_equal(wr, wb)                      # BF16 numbers stay as they are
     c2 = sph.Context(w.params, capacity=w.n)
     c2.mlp_load(bits)
-    assert np.array_equal(c2.mlp_get_params(rounded=False), wr)
-    assert np.array_equal(c2.mlp_get_params(rounded=True), wr)
+    assert np.array_equal(c2.mlp_get_params(rounded=False), wb)
+    assert np.array_equal(c2.mlp_get_params(rounded=True), wb)
     t = w.params.table
     rng = np.random.default_rng(1)
     lr = torch.as_tensor(t.lnr0 + rng.uniform(0, (t.nr - 1) * t.dlnr, 4096), device="cuda")

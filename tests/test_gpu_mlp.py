@@ -1,7 +1,8 @@
 """GPU tests of the EoS surrogate network: gradients and forward pass against the oracle's FP64
-network with the same BF16-rounded weights, training on the GPU, the trust mask and table
-fallback, the density stage with the surrogate against the oracle's table EoS, and what the
-trained network gains over the table."""
+network with the same weights (the matrix-core layers' rounded to BF16), training on the GPU and
+the least-squares readout against the oracle's, the trust mask and table fallback, the density
+stage with the surrogate against the oracle's table EoS, and what the trained network gains over
+the table."""
 import numpy as np
 import pytest
 
@@ -54,15 +55,22 @@ def test_gradient_matches_oracle(n):
     assert np.array_equal(ctx.mlp_get_params(rounded=True), wr.astype(np.float32))
 
 
+def _mask(lo, hi, p):
+    return (p >= lo) & (p < hi)
+
+
 def test_forward_matches_oracle_and_rounding():
     sph, ctx, _ = _ctx()
     w0 = E.mlp_init(7) * 3.0
     ctx.mlp_set_params(w0)
     wr = ctx.mlp_get_params(rounded=True)
-    # rounding to the nearest BF16 (8 significant bits): within half a spacing, 2^-8 relative
-    assert np.all(np.abs(wr - w0) <= 2.0 ** -8 * np.abs(w0))
-    # and the rounded values are BF16 numbers: the low 16 bits of their FP32 patterns are zero
-    assert np.all((wr.view(np.uint32) & 0xffff) == 0)
+    idx = np.arange(w0.size)
+    mfma = _mask(*BLOCKS["W2"], idx) | _mask(*BLOCKS["W3"], idx)
+    # the matrix-core weights are rounded to the nearest BF16 (8 significant bits): within half a
+    # spacing, 2^-8 relative, and their FP32 patterns have zero low halves; the rest stay FP32
+    assert np.all(np.abs(wr[mfma] - w0[mfma]) <= 2.0 ** -8 * np.abs(w0[mfma]))
+    assert np.all((wr[mfma].view(np.uint32) & 0xffff) == 0)
+    assert np.array_equal(wr[~mfma], w0[~mfma].astype(np.float32))
     nm = ctx.mlp_get_norm()
     rng = np.random.default_rng(8)
     xs = rng.uniform(-1, 1, (777, 2))      # a ragged count: 12 waves and a partial one
@@ -74,59 +82,116 @@ def test_forward_matches_oracle_and_rounding():
     yo = oracle.mlp_forward(wr.astype(np.float64), xo)
     err = float(np.max(np.abs(yg - yo)) / np.max(np.abs(yo)))
     print("forward rel err", err, flush=True)
-    assert err < 2e-2
+    # FP32 arithmetic with the activations carried as two BF16 parts (about 2^-17 each)
+    assert err < 1e-4
+
+
+# The network's domain: the densest polytrope piece of the benchmark star (its central third of
+# the particles by count), from the first table node above the dividing density to 1.15 rho_c,
+# in a band of +-0.045 in ln u around the cold curve.
+def _domain():
+    pp = E.default_pp()
+    lo, hi, wd = E.piece_band(pp, 2, W.PP_RHOC, W.pp_table(), 0.045)
+    return pp, lo, hi, wd, E.band_domain(pp, lo, hi, wd)
 
 
 @pytest.fixture(scope="module")
 def trained():
-    """A network trained on the GPU as configured for the 2M-particle runs: 1M seeded samples
-    uniform over the table's box (10% held out), Adam with a cosine schedule from lr 1e-3, batch
-    4096, 400 epochs (about 88k steps, a few seconds)."""
+    """A network trained on the GPU as configured for the 2M-particle runs: 1M seeded samples in
+    the band (10% held out), Adam with a cosine schedule from lr 1e-3, batch 4096, 400 epochs
+    (about 88k steps, a few seconds), then the least-squares readout."""
     import torch
     sph, ctx, w = _ctx(20000)
+    pp, lo, hi, wd, dom = _domain()
+    ctx.mlp_set_domain(*dom)
     ctx.mlp_set_params(E.mlp_init(4))
-    samples = _to_dev(E.mlp_samples(W.pp_table(), 1_000_000, 4), np.float64)
+    samples = _to_dev(E.mlp_band_samples(pp, lo, hi, wd, 1_000_000, 4), np.float64)
     before = ctx.mlp_grad(*_holdout_pairs(ctx, samples))[1]
     hist = ctx.mlp_train(samples, 100_000, 400, 4096, 1e-3)
+    after_lsq = ctx.mlp_fit_readout(samples, 100_000, 1e-12)
     torch.cuda.synchronize()
-    return sph, ctx, w, samples, before, hist
+    return sph, ctx, w, samples, before, hist, after_lsq, dom
 
 
-def _holdout_pairs(ctx, samples):
-    """Normalised (x, t) of the last 4096 samples, targets from the table (numpy bilinear)."""
+def _holdout_pairs(ctx, samples, k=4096):
+    """Normalised (x, t) of the last k samples, targets from the table (numpy bilinear)."""
     tab = W.pp_table()
     nm = ctx.mlp_get_norm()
-    s = samples[-4096:].cpu().numpy()
-    fr = (s[:, 0] - tab.lnr0) / tab.dlnr
-    fu = (s[:, 1] - tab.lnu0) / tab.dlnu
-    i = np.minimum(np.floor(fr).astype(int), tab.lnP.shape[0] - 2)
-    j = np.minimum(np.floor(fu).astype(int), tab.lnP.shape[1] - 2)
-    a, b = fr - i, fu - j
-
-    def bil(T):
-        return (1 - a) * ((1 - b) * T[i, j] + b * T[i, j + 1]) + a * ((1 - b) * T[i + 1, j] + b * T[i + 1, j + 1])
+    s = samples[-k:].cpu().numpy()
     x = np.stack([(s[:, 0] - nm[0]) * nm[2] - 1, (s[:, 1] - nm[1]) * nm[3] - 1], 1)
-    t = np.stack([(bil(tab.lnP) - nm[4]) / nm[6], (bil(tab.lncs2) - nm[5]) / nm[7]], 1)
+    t = np.stack([(_bil(tab.lnP, tab, s[:, 0], s[:, 1]) - nm[4]) / nm[6],
+                  (_bil(tab.lncs2, tab, s[:, 0], s[:, 1]) - nm[5]) / nm[7]], 1)
     return _to_dev(x, np.float32), _to_dev(t, np.float32)
 
 
+def _bil(T, tab, lnr, lnu, lnr0=None, dlnr=None, lnu0=None, dlnu=None):
+    lnr0 = tab.lnr0 if lnr0 is None else lnr0
+    dlnr = tab.dlnr if dlnr is None else dlnr
+    lnu0 = tab.lnu0 if lnu0 is None else lnu0
+    dlnu = tab.dlnu if dlnu is None else dlnu
+    fr = (lnr - lnr0) / dlnr
+    fu = (lnu - lnu0) / dlnu
+    i = np.clip(np.floor(fr).astype(int), 0, T.shape[0] - 2)
+    j = np.clip(np.floor(fu).astype(int), 0, T.shape[1] - 2)
+    a, b = fr - i, fu - j
+    return (1 - a) * ((1 - b) * T[i, j] + b * T[i, j + 1]) + a * ((1 - b) * T[i + 1, j] + b * T[i + 1, j + 1])
+
+
 def test_training_reduces_holdout_loss(trained):
-    sph, ctx, w, samples, before, hist = trained
-    print("loss before", before, "history", hist[[0, 9, 99, 399]].tolist(), flush=True)
+    sph, ctx, w, samples, before, hist, after_lsq, dom = trained
+    print("loss before", before, "history", hist[[0, 9, 99, 399]].tolist(), "after the readout fit", after_lsq,
+          flush=True)
     assert np.all(np.isfinite(hist))
-    assert hist[-1, 1] < before / 50
+    assert hist[-1, 1] < before / 1e4
     assert hist[-1, 1] < hist[0, 1]
+    # the least-squares readout does not lose on the held-out samples
+    assert after_lsq <= 1.05 * hist[-1, 1]
     after = ctx.mlp_grad(*_holdout_pairs(ctx, samples))[1]
-    assert hist[-1, 1] / 3 < after < 3 * hist[-1, 1]   # the same holdout metric on a subset
+    assert after_lsq / 3 < after < 3 * after_lsq   # the same holdout metric on a subset
+
+
+def test_readout_fit_matches_oracle():
+    # the device's normal-equation readout against the oracle's (its FP64 features of the same
+    # hidden layers, numpy's solve) on the same normalised samples and table targets: the two fitted
+    # networks agree on held-out points to well below the 1e-4 the network serves at
+    import torch
+    sph, ctx, w = _ctx()
+    pp, lo, hi, wd, dom = _domain()
+    ctx.mlp_set_domain(*dom)
+    ctx.mlp_set_params(E.mlp_init(5) * 1.5)
+    samples = _to_dev(E.mlp_band_samples(pp, lo, hi, wd, 24_000, 9), np.float64)
+    ctx.mlp_fit_readout(samples, 4096, 1e-12)
+    torch.cuda.synchronize()
+    wg = ctx.mlp_get_params(rounded=True).astype(np.float64)
+    x_all, t_all = _holdout_pairs(ctx, samples, 24_000)
+    x_all = x_all.cpu().numpy().astype(np.float64)
+    t_all = t_all.cpu().numpy().astype(np.float64)
+    wo = oracle.mlp_fit_readout(wg, x_all[:-4096], t_all[:-4096], 1e-12)
+    # the hidden layers are the device's, the readout the fit's
+    yg = oracle.mlp_forward(wg, x_all[-4096:])
+    yo = oracle.mlp_forward(wo, x_all[-4096:])
+    nm = ctx.mlp_get_norm()
+    d = np.max(np.abs(yg - yo) * np.array([nm[6], nm[7]]))   # in ln P, ln c_s^2
+    print("readout fit: device vs oracle max |d ln| =", d, flush=True)
+    assert d < 1e-5
+
+
+def _cells_in(dom):
+    tab = W.pp_table()
+    i = np.arange(tab.lnP.shape[0] - 1)
+    j = np.arange(tab.lnP.shape[1] - 1)
+    e = 1e-9
+    ri = (tab.lnr0 + i * tab.dlnr >= dom[0] - e * tab.dlnr) & (tab.lnr0 + (i + 1) * tab.dlnr <= dom[1] + e * tab.dlnr)
+    uj = (tab.lnu0 + j * tab.dlnu >= dom[2] - e * tab.dlnu) & (tab.lnu0 + (j + 1) * tab.dlnu <= dom[3] + e * tab.dlnu)
+    return int(ri.sum()) * int(uj.sum())
 
 
 def test_trust_mask_and_fallback(trained):
-    sph, ctx, w, samples, before, hist = trained
-    ncell = 1023 * 1023
+    sph, ctx, w, samples, before, hist, after_lsq, dom = trained
     counts = {tol: ctx.mlp_build_trust_mask(tol) for tol in (1e-4, 3e-2, 1e300)}
-    print("trusted cells", counts, flush=True)
-    assert counts[1e300] == ncell                   # every cell of the table is finite
-    assert counts[1e-4] <= counts[3e-2] <= counts[1e300]
+    print("trusted cells", counts, "cells in the domain", _cells_in(dom), flush=True)
+    assert counts[1e300] == _cells_in(dom)          # every cell in the domain is tested, none outside
+    assert 0 < counts[1e-4] <= counts[3e-2] <= counts[1e300]
     # density stage with the surrogate (FP64 pairs) against the table path: untrusted cells are
     # the table bit for bit, trusted ones within the tolerance
     for tol in (1e-4, 3e-2):
@@ -141,86 +206,73 @@ def test_trust_mask_and_fallback(trained):
         rc = np.abs((g["cs"][o] / ref["cs"]) ** 2 - 1)
         assert np.array_equal(g["D"][o], ref["D"])
         print(f"tol {tol}: particles on the network {np.mean(r > 0):.4f}, max rel dP {r.max():.2e}", flush=True)
-        assert r.max() <= 2 * tol and rc.max() <= 2 * tol
+        assert np.mean(r > 0) > 0.01
+        assert r.max() <= tol and rc.max() <= tol
 
 
 def test_surrogate_path_meets_oracle_tolerance(trained):
-    # the whole FP32-pairs + surrogate path against the FP64 oracle with the table EoS.  At the
-    # 1e-4 threshold the mask trusts no cell the star's particles sit in (they lie on the cold
-    # curve, where the hybrid EoS has a kink in u that a smooth BF16 network does not resolve to
-    # 1e-4), so the served count is reported, and the path equals the table path; at 3e-2 the
-    # network serves particles and their pressure stays within that tolerance
-    sph, ctx, w, samples, before, hist = trained
+    # the whole FP32-pairs + surrogate path against the FP64 oracle with the table EoS: at the
+    # 1e-4 threshold the network serves a stated share of the particles (those in trusted cells
+    # of its domain, the star's dense core), and D, rho, P stay within 1e-4 of the oracle
+    sph, ctx, w, samples, before, hist, after_lsq, dom = trained
     o = oracle_run(w, params=w.params.replace(eos="TABLE", precision="FP64"))
     p32 = w.params.replace(precision="FP32")
     from paper_2107_07315_amd import sph as S
-    for tol in (1e-4, 3e-2):
-        st = sph.DeviceState(w.arrays)
-        c32 = S.Context(p32, capacity=w.n)
-        c32.mlp_set_params(ctx.mlp_get_params())
-        cells = c32.mlp_build_trust_mask(tol)
-        c32.evaluate(st)
-        c32.sph_sync()
-        served = c32.mlp_count_served(st)
-        g = st.numpy()
-        c32.close()
-        order = np.argsort(g["id"])
-        e = {k: float(np.max(rel_err(g[k][order], o[k], 1e-300))) for k in ("D", "rho", "P")}
-        _print(f"FP32+MLP at {tol}: trusted cells {cells}, particles on the network {served} of {w.n}", e)
-        assert e["D"] < 1e-4 and e["rho"] < 1e-4
-        if served == 0:
-            assert e["P"] < 1e-4
-        else:
-            assert e["P"] < 2 * tol
+    st = sph.DeviceState(w.arrays)
+    c32 = S.Context(p32, capacity=w.n)
+    c32.mlp_set_domain(*dom)
+    c32.mlp_set_params(ctx.mlp_get_params())
+    cells = c32.mlp_build_trust_mask(1e-4)
+    c32.evaluate(st)
+    c32.sph_sync()
+    served = c32.mlp_count_served(st)
+    g = st.numpy()
+    c32.close()
+    order = np.argsort(g["id"])
+    e = {k: float(np.max(rel_err(g[k][order], o[k], 1e-300))) for k in ("D", "rho", "P")}
+    _print(f"FP32+MLP at 1e-4: trusted cells {cells}, particles on the network {served} of {w.n}", e)
+    assert served > 0.05 * w.n
+    assert e["D"] < 1e-4 and e["rho"] < 1e-4 and e["P"] < 1e-4
 
 
 def test_surrogate_gain_is_measured(trained):
-    """What the trained network gains over the table it replaces, and what it costs: the EoS from
-    17 KB of BF16 weights instead of a 16 MB table (970x less memory), at about twice the full
-    table's epilogue time and at 0.8% median error (the full table is the reference); against a
-    bilinear table of its own size (34 x 34 nodes) it is less accurate at the median and more
-    accurate in the tail (90th percentile of the larger relative error of P and c_s^2 on held-out
-    samples).  It does not reach the 1e-4 the density pass demands, which is why the trust mask
-    keeps the table there."""
-    import torch
-    sph, ctx, w, samples, before, hist = trained
+    """What the trained network gains over the table it replaces, and what it costs, in its
+    domain: the EoS from 17 KB of weights instead of the 16 MB table (970x less memory), at about
+    1e-5 median relative error against it; a bilinear table of the network's size over the same
+    domain (34 x 34 nodes of FP64 ln P and ln c_s^2, 18.5 KB) for comparison; and the density
+    epilogue's time per evaluation with the network (serving its share at 1e-4) and with the
+    table."""
+    sph, ctx, w, samples, before, hist, after_lsq, dom = trained
     tab = W.pp_table()
     s = samples[-40_000:]
     lp, lc = ctx.mlp_eval(s[:, 0].contiguous(), s[:, 1].contiguous())
     sn = s.cpu().numpy()
-
-    def bil(T, lnr0, dlnr, lnu0, dlnu, lnr, lnu):
-        fr = (lnr - lnr0) / dlnr
-        fu = (lnu - lnu0) / dlnu
-        i = np.minimum(np.floor(fr).astype(int), T.shape[0] - 2)
-        j = np.minimum(np.floor(fu).astype(int), T.shape[1] - 2)
-        a, b = fr - i, fu - j
-        return (1 - a) * ((1 - b) * T[i, j] + b * T[i, j + 1]) + a * ((1 - b) * T[i + 1, j] + b * T[i + 1, j + 1])
-    ref_p = bil(tab.lnP, tab.lnr0, tab.dlnr, tab.lnu0, tab.dlnu, sn[:, 0], sn[:, 1])
-    ref_c = bil(tab.lncs2, tab.lnr0, tab.dlnr, tab.lnu0, tab.dlnu, sn[:, 0], sn[:, 1])
+    ref_p = _bil(tab.lnP, tab, sn[:, 0], sn[:, 1])
+    ref_c = _bil(tab.lncs2, tab, sn[:, 0], sn[:, 1])
     e_net = np.maximum(np.abs(np.expm1(lp.cpu().numpy() - ref_p)), np.abs(np.expm1(lc.cpu().numpy() - ref_c)))
-    # a table of about the network's size: 34 x 34 nodes of the big table, every 31st (1023 = 33 x 31),
-    # 2 fields x 34^2 FP64 = 18.5 KB, interpolated at its own node coordinates
-    step = 31
-    k = (tab.lnP.shape[0] - 1) // step + 1
-    ii = np.arange(k) * step
-    small_p, small_c = tab.lnP[np.ix_(ii, ii)], tab.lncs2[np.ix_(ii, ii)]
-    dr = step * tab.dlnr
-    du = step * tab.dlnu
-    e_small = np.maximum(np.abs(np.expm1(bil(small_p, tab.lnr0, dr, tab.lnu0, du, sn[:, 0], sn[:, 1]) - ref_p)),
-                         np.abs(np.expm1(bil(small_c, tab.lnr0, dr, tab.lnu0, du, sn[:, 0], sn[:, 1]) - ref_c)))
-    # against the 1024^2 table the method uses: its error is 0 by definition (it is the reference);
-    # the cost of the density epilogue with the network (at 3e-2, where it serves particles) and
-    # with the table, per evaluation of the star
+    # the small table: 34 x 34 nodes over the domain box, node values from the big table
+    k = 34
+    gr = np.linspace(dom[0], dom[1], k)
+    gu = np.linspace(dom[2], dom[3], k)
+    R, U = np.meshgrid(gr, gu, indexing="ij")
+    small_p = _bil(tab.lnP, tab, R.ravel(), U.ravel()).reshape(k, k)
+    small_c = _bil(tab.lncs2, tab, R.ravel(), U.ravel()).reshape(k, k)
+    dr, du = gr[1] - gr[0], gu[1] - gu[0]
+    e_small = np.maximum(np.abs(np.expm1(_bil(small_p, tab, sn[:, 0], sn[:, 1], dom[0], dr, dom[2], du) - ref_p)),
+                         np.abs(np.expm1(_bil(small_c, tab, sn[:, 0], sn[:, 1], dom[0], dr, dom[2], du) - ref_c)))
     from paper_2107_07315_amd import sph as S
     ms = {}
+    served = None
     for mode in ("table", "network"):
         c = S.Context(w.params.replace(precision="FP32", eos="MLP" if mode == "network" else "TABLE"), capacity=w.n)
         if mode == "network":
+            c.mlp_set_domain(*dom)
             c.mlp_set_params(ctx.mlp_get_params())
-            c.mlp_build_trust_mask(3e-2)
+            c.mlp_build_trust_mask(1e-4)
         st = sph.DeviceState(w.arrays)
         c.evaluate(st)
+        if mode == "network":
+            served = c.mlp_count_served(st)
         c.sph_set_timing(True)
         for _ in range(20):
             c.sph_density(st)
@@ -231,13 +283,11 @@ def test_surrogate_gain_is_measured(trained):
     net_bytes = 2 * 8642
     table_bytes = tab.lnP.nbytes + tab.lncs2.nbytes
     rep = {"compression": table_bytes / net_bytes, "net_median": float(np.median(e_net)),
-           "net_p90": float(np.percentile(e_net, 90)), "small_table_median": float(np.median(e_small)),
-           "small_table_p90": float(np.percentile(e_small, 90)), "epilogue_ms_table": ms["table"],
-           "epilogue_ms_network": ms["network"]}
+           "net_p90": float(np.percentile(e_net, 90)), "net_max": float(np.max(e_net)),
+           "small_table_median": float(np.median(e_small)), "small_table_p90": float(np.percentile(e_small, 90)),
+           "served": served, "epilogue_ms_table": ms["table"], "epilogue_ms_network": ms["network"]}
     _print("gain", rep)
-    # measured: the network is 970x smaller than the full table and takes about twice its epilogue
-    # time; against a table of its own size it is worse at the median and better in the tail
     assert np.all(np.isfinite(e_net))
     assert rep["compression"] > 900
-    assert rep["net_p90"] < rep["small_table_p90"]
+    assert rep["net_median"] < 5e-5
     assert rep["epilogue_ms_network"] > 0 and rep["epilogue_ms_table"] > 0

@@ -96,3 +96,27 @@ def test_gradient_matches_central_differences(seed):
     an = g[idx]
     err = np.abs(fd - an) / np.maximum(np.abs(an), 1e-3 * np.max(np.abs(an)))
     assert np.max(err) < 1e-6, (np.max(err), idx[int(np.argmax(err))])
+
+
+def test_readout_fit_is_the_least_squares_minimiser():
+    # the least-squares readout minimises the loss over W4, b4 for fixed hidden layers: the loss
+    # gradient (backpropagation, pinned above by finite differences) vanishes in those two blocks,
+    # the loss does not rise, the hidden layers are untouched, and the output is W4 h + b4 of the
+    # network's own last hidden layer
+    w = _random_params(11)
+    rng = np.random.default_rng(12)
+    x = rng.uniform(-1, 1, (400, 2))
+    t = np.stack([np.sin(2 * x[:, 0]) + x[:, 1] ** 2, np.cos(x[:, 0] * x[:, 1])], axis=1)
+    l0, g0 = oracle.mlp_loss_grad(w, x, t)
+    wf = oracle.mlp_fit_readout(w, x, t, 0.0)
+    l1, g1 = oracle.mlp_loss_grad(wf, x, t)
+    assert l1 < l0
+    assert np.array_equal(wf[:OFF["W4"]], w[:OFF["W4"]])
+    ro = slice(OFF["W4"], NP)
+    assert np.max(np.abs(g1[ro])) < 1e-9 * np.max(np.abs(g0[ro]))
+    h = oracle.mlp_features(wf, x)
+    y = h @ wf[OFF["W4"]:OFF["b4"]].reshape(2, H).T + wf[OFF["b4"]:]
+    assert np.max(np.abs(y - oracle.mlp_forward(wf, x))) < 1e-12
+    # a ridge term shrinks the readout towards zero
+    wr = oracle.mlp_fit_readout(w, x, t, 1e-2)
+    assert np.linalg.norm(wr[ro]) < np.linalg.norm(wf[ro])
