@@ -158,7 +158,7 @@ void sph_destroy(sph_ctx* c) {
                   c->tile_usize, c->stress_tiles, c->nbr16, c->nbr_count, c->nbr_count_sl, c->nbr16s, c->nbr_count_s, c->pos_build, c->drift_flag,
                   c->pos4, c->fv, c->fa, c->sig, c->pos4f, c->fvf,
                   c->faf, c->sigf, c->mu, c->Y0, c->B, c->sdot, c->tovf, c->half, c->tmp, c->stars, c->status,
-                  c->dsum, c->dDdt, c->xcoef, c->dtw, c->dtpart};
+                  c->dsum, c->dDdt, c->xcoef, c->dtw, c->dtpart, c->eos_list, c->eos_list_n};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (c->drift_host) (void)hipHostFree(c->drift_host);
@@ -226,7 +226,8 @@ sph_status sph_create(const sph_params* params, void* stream, int64_t capacity, 
       (e = dalloc(&c->tovf, cap)) ||
       (e = dalloc(&c->half, SPH_HALF_FIELDS * cap)) || (e = dalloc(&c->tmp, capw)) || (e = dalloc(&c->status, 1)) ||
       (e = dalloc(&c->dsum, cap)) || (e = dalloc(&c->dDdt, cap)) || (e = dalloc(&c->xcoef, 5 * cap)) ||
-      (e = dalloc(&c->dtw, 8)) || (e = dalloc(&c->dtpart, 65536))) {
+      (e = dalloc(&c->dtw, 8)) || (e = dalloc(&c->dtpart, 65536 + 2048)) || (e = dalloc(&c->eos_list, cap)) ||
+      (e = dalloc(&c->eos_list_n, 1))) {
     sph_destroy(c);
     return note(nullptr, e, "device scratch for capacity %lld does not fit", (long long)capacity);
   }

@@ -388,6 +388,8 @@ struct sph_ctx {
   // [3] simulated time, [5] dt of the step in progress
   double* dtw;
   double* dtpart;       // per-block minima of h / (c_L + |v|) of the last density epilogue
+  int32_t* eos_list;    // particles the EoS network serves in the current evaluation (split epilogue)
+  int32_t* eos_list_n;
   int eos_blocks;       // blocks of that epilogue that wrote dtpart (0: none)
   int64_t steps_done;   // steps completed since sph_create (slot bookkeeping of the Courant steps)
   bool adaptive;        // inside an sph_step call with Courant steps

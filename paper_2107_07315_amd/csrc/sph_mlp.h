@@ -92,19 +92,18 @@ __device__ __forceinline__ void split_bf16(const float h[4], bf16x4& hi, bf16x4&
 // The network up to its last hidden layer for the 64 inputs held one per lane (x0, x1
 // normalised).  Every lane of the wave must call it (matrix instructions).  For each block of 16
 // inputs nt it calls out(nt, mt, h, w) with the lane's part of the last hidden layer: h[j] is
-// feature 16 mt + 4 q + j of input 16 nt + r (w: the parameters, through a pointer the compiler
-// does not hoist loads out of).
-template <typename Out>
-__device__ __forceinline__ void mlp_wave_hidden(const MlpView& M, float x0, float x1, Out&& out) {
+// feature 16 mt + 4 q + j of input 16 nt + r.  ptrs(w, wa2, wa3) gives the parameters, through
+// pointers the compiler does not hoist loads out of the loop over nt (the weights are the same
+// for every nt; hoisted, their loads would occupy ~180 registers across it).
+template <typename Ptrs, typename Out>
+__device__ __forceinline__ void mlp_wave_layers(Ptrs&& ptrs, float x0, float x1, Out&& out) {
   const int l = threadIdx.x & 63, q = l >> 4, r = l & 15;
 #pragma unroll 1
   for (int nt = 0; nt < 4; ++nt) {
-    // The weights are the same for every nt; the empty asm makes the pointers opaque so that
-    // their loads stay inside the loop instead of occupying ~180 registers across it.
-    const float* w = M.wr;
-    const uint2* wa2 = M.wa2;
-    const uint2* wa3 = M.wa3;
-    asm volatile("" : "+s"(w), "+s"(wa2), "+s"(wa3));
+    const float* w;
+    const uint2* wa2;
+    const uint2* wa3;
+    ptrs(w, wa2, wa3);
     const int pp = 16 * nt + r;   // the input this lane's B-operand column belongs to
     const float a0 = __shfl(x0, pp, 64), a1 = __shfl(x1, pp, 64);
     bf16x4 h1[4], l1[4];
@@ -155,12 +154,51 @@ __device__ __forceinline__ void mlp_wave_hidden(const MlpView& M, float x0, floa
   }
 }
 
+// The same with the parameters in global memory (the view's arrays).
+template <typename Out>
+__device__ __forceinline__ void mlp_wave_hidden(const MlpView& M, float x0, float x1, Out&& out) {
+  mlp_wave_layers(
+      [&](const float*& w, const uint2*& wa2, const uint2*& wa3) {
+        w = M.wr;
+        wa2 = M.wa2;
+        wa3 = M.wa3;
+        asm volatile("" : "+s"(w), "+s"(wa2), "+s"(wa3));
+      },
+      x0, x1, out);
+}
+
+// The parameters staged in LDS by a kernel that evaluates the network for many full waves
+// (mlp_stage_lds, then a barrier): the parameters the kernels use and the MFMA packs of W2, W3.
+static __shared__ float s_mlp_w[MLP_NPARAM];
+static __shared__ uint2 s_mlp_a[2048];
+__device__ __forceinline__ void mlp_stage_lds(const MlpView& M) {
+  for (int i = threadIdx.x; i < MLP_NPARAM; i += blockDim.x) s_mlp_w[i] = M.wr[i];
+  for (int i = threadIdx.x; i < 1024; i += blockDim.x) {
+    s_mlp_a[i] = M.wa2[i];
+    s_mlp_a[1024 + i] = M.wa3[i];
+  }
+}
+template <typename Out>
+__device__ __forceinline__ void mlp_wave_hidden_lds(float x0, float x1, Out&& out) {
+  mlp_wave_layers(
+      [&](const float*& w, const uint2*& wa2, const uint2*& wa3) {
+        int z = 0;   // an offset the compiler cannot see through keeps the loads in the loop
+        asm volatile("" : "+s"(z));
+        w = s_mlp_w + z;
+        wa2 = s_mlp_a + z;
+        wa3 = s_mlp_a + 1024 + z;
+      },
+      x0, x1, out);
+}
+
 // Network outputs for the 64 inputs held one per lane (x0, x1 normalised).  Every lane of the
-// wave must call it; lane l receives the outputs of its own input.
+// wave must call it; lane l receives the outputs of its own input.  LDS: the parameters staged by
+// mlp_stage_lds.
+template <bool LDS = false>
 __device__ __forceinline__ void mlp_wave(const MlpView& M, float x0, float x1, float& y0, float& y1) {
   const int q = (threadIdx.x & 63) >> 4;
   float p0 = 0.f, p1 = 0.f;
-  mlp_wave_hidden(M, x0, x1, [&](int nt, int mt, const float h3[4], const float* w) {
+  auto out = [&](int nt, int mt, const float h3[4], const float* w) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int f = 16 * mt + 4 * q + j;
@@ -179,5 +217,7 @@ __device__ __forceinline__ void mlp_wave(const MlpView& M, float x0, float x1, f
       }
       p0 = p1 = 0.f;
     }
-  });
+  };
+  if constexpr (LDS) mlp_wave_hidden_lds(x0, x1, out);
+  else mlp_wave_hidden(M, x0, x1, out);
 }

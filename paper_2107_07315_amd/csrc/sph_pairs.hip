@@ -326,27 +326,33 @@ __device__ __forceinline__ int eos_eval(const sph_params& p, double rho, double 
   return 0;
 }
 
+// Whether (rho, u) lies in a table cell the network's trust mask accepts.
+__device__ __forceinline__ bool mlp_trusted_at(const MlpView& M, const sph_params& p, double rho, double u) {
+  if (!M.trust || !(rho > 0.0) || !(u > 0.0)) return false;
+  const double fr = (log(rho) - p.tab_lnr0) / p.tab_dlnr, fu = (log(u) - p.tab_lnu0) / p.tab_dlnu;
+  if (!(fr >= 0.0 && fu >= 0.0 && fr <= (double)(p.tab_nr - 1) && fu <= (double)(p.tab_nu - 1))) return false;
+  int i = (int)floor(fr), j = (int)floor(fu);
+  i = i > p.tab_nr - 2 ? p.tab_nr - 2 : i;
+  j = j > p.tab_nu - 2 ? p.tab_nu - 2 : j;
+  return M.trust[(int64_t)i * (p.tab_nu - 1) + j] != 0;
+}
+
 // Surrogate EoS: the network's ln P, ln c_s^2 in every table cell the trust mask accepts, table
-// interpolation elsewhere.  Every lane of the wave must call it; the network (a wave-level call)
-// runs only if some lane of the wave sits in a trusted cell.
+// interpolation elsewhere.  Every lane of the wave must call it; the network (a wave-level call,
+// its parameters staged in LDS by the calling kernel) runs only if some lane of the wave sits in
+// a trusted cell.
 __device__ __forceinline__ int eos_mlp(const MlpView& M, const sph_params& p, double rho, double u, double& P,
                                        double& cs2) {
   bool ok = rho > 0.0 && u > 0.0;
   const double lnr = ok ? log(rho) : p.tab_lnr0, lnu = ok ? log(u) : p.tab_lnu0;
   const double fr = (lnr - p.tab_lnr0) / p.tab_dlnr, fu = (lnu - p.tab_lnu0) / p.tab_dlnu;
   ok = ok && fr >= 0.0 && fu >= 0.0 && fr <= (double)(p.tab_nr - 1) && fu <= (double)(p.tab_nu - 1);
-  bool trusted = false;
-  if (ok && M.trust) {
-    int i = (int)floor(fr), j = (int)floor(fu);
-    i = i > p.tab_nr - 2 ? p.tab_nr - 2 : i;
-    j = j > p.tab_nu - 2 ? p.tab_nu - 2 : j;
-    trusted = M.trust[(int64_t)i * (p.tab_nu - 1) + j] != 0;
-  }
+  const bool trusted = ok && mlp_trusted_at(M, p, rho, u);
   const MlpNorm& nm = M.norm;
   float y0 = 0.f, y1 = 0.f;
   if (__ballot(trusted))
-    mlp_wave(M, (float)((lnr - nm.in_lo[0]) * nm.in_sc[0] - 1.0), (float)((lnu - nm.in_lo[1]) * nm.in_sc[1] - 1.0), y0,
-             y1);
+    mlp_wave<true>(M, (float)((lnr - nm.in_lo[0]) * nm.in_sc[0] - 1.0),
+                   (float)((lnu - nm.in_lo[1]) * nm.in_sc[1] - 1.0), y0, y1);
   if (!ok) return SPH_E_EOS_DOMAIN;
   double lp, lc;
   if (trusted) {
@@ -431,14 +437,16 @@ struct ListWriter {
 // Density-stage epilogue in FP64 for particle a with computational density D: rest-mass density
 // from D = rho psi^6 W_L, EoS, shear modulus, yield stress and the packed records of the stress
 // and force passes.  With MLP the EoS is the surrogate network (every lane of the wave must
-// call; lanes with valid = false store nothing).
+// call; lanes with valid = false store nothing).  With net != nullptr (the table pass of a split
+// epilogue) a particle in a cell the network serves is left to the network pass: *net is set and
+// nothing is stored.
 template <typename R, bool MLP>
 __device__ __forceinline__ void density_epilogue(const PassArgs& A, int64_t a, bool valid, double D,
                                                  const double4* __restrict__ pos64, const double* __restrict__ vx,
                                                  const double* __restrict__ vy, const double* __restrict__ vz,
                                                  const double* __restrict__ u, const double* __restrict__ S,
                                                  const int8_t* __restrict__ type, const uint8_t* __restrict__ broken,
-                                                 DensOut O) {
+                                                 DensOut O, bool* net = nullptr) {
   const sph_params& p = A.p;
   const double va[3] = {vx[a], vy[a], vz[a]};
   const bool tov = p.background == SPH_TOV;
@@ -455,6 +463,10 @@ __device__ __forceinline__ void density_epilogue(const PassArgs& A, int64_t a, b
     psi4 = psi2 * psi2;
     WL = 1.0 / sqrt(1.0 - psi4 * v2 / (g.alpha * g.alpha));
     rho = D / (psi4 * psi2 * WL);
+  }
+  if (net && mlp_trusted_at(A.mlp, p, rho, u[a])) {
+    *net = true;
+    return;
   }
   double P, cs2;
   int e;
@@ -698,38 +710,92 @@ void k_density(PassArgs A, const double4* __restrict__ pos64, DensOut O,
 
 // Per-particle epilogue of the density stage (EoS, moduli, packed records), one lane per particle,
 // D from the pair loop.  Kept out of the pair-loop kernel, where only one lane of a target's L
-// would work on it and its registers would lower the loop's occupancy; with MLP the EoS is the
-// surrogate network (a wave-level call).
-template <typename R, bool MLP>
+// would work on it and its registers would lower the loop's occupancy.  With the EoS network the
+// epilogue is split in two passes: this one (SPLIT) takes the table EoS and appends the particles
+// in cells the network serves to a list (nlist, nlist_n), which k_density_epilogue_net then
+// finishes with the network in full waves; the network's registers would otherwise lower the
+// occupancy of the whole epilogue, and its work would run for every wave with one served lane.
+__device__ __forceinline__ void courant_min(const DensOut& O, const double4* __restrict__ pos64,
+                                            const double* __restrict__ vx, const double* __restrict__ vy,
+                                            const double* __restrict__ vz, const int8_t* __restrict__ type,
+                                            int64_t a, double& qmin) {
+  // Courant step: h / (c_L + |v|), c_L^2 = c_s^2 + 4 mu / (3 rho)
+  const double cs = O.cs[a], rh = O.rho[a];
+  const double mu = type[a] == 1 ? O.mu[a] : 0.0;
+  const double cl = sqrt(cs * cs + 4.0 * mu / (3.0 * rh));
+  const double vm = sqrt(vx[a] * vx[a] + vy[a] * vy[a] + vz[a] * vz[a]);
+  const double q = pos64[a].w / (cl + vm);
+  qmin = q < qmin ? q : qmin;
+}
+__device__ __forceinline__ void courant_store(const DensOut& O, double qmin, int slot) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_xor(qmin, off, 64);
+    qmin = o < qmin ? o : qmin;
+  }
+  if (threadIdx.x == 0) O.dtpart[slot] = qmin;
+}
+template <typename R, bool SPLIT>
 __global__ __launch_bounds__(64) void k_density_epilogue(PassArgs A, const double4* __restrict__ pos64,
                                                          const double* __restrict__ vx, const double* __restrict__ vy,
                                                          const double* __restrict__ vz, const double* __restrict__ u,
                                                          const double* __restrict__ S, const int8_t* __restrict__ type,
-                                                         const uint8_t* __restrict__ broken, DensOut O) {
+                                                         const uint8_t* __restrict__ broken, DensOut O,
+                                                         int32_t* __restrict__ nlist, int32_t* __restrict__ nlist_n) {
   const int64_t n = cancelled(A) ? 0 : A.n;
+  const int lane = threadIdx.x;
   double qmin = __builtin_inf();
   for (int64_t base = (int64_t)blockIdx.x * 64; base < n; base += (int64_t)gridDim.x * 64) {
-    const int64_t a = base + threadIdx.x;
+    const int64_t a = base + lane;
     const bool valid = a < n;
     const int64_t ae = valid ? a : base;   // lanes past the end work on a valid particle, store nothing
-    density_epilogue<R, MLP>(A, ae, valid, O.Dread[ae], pos64, vx, vy, vz, u, S, type, broken, O);
-    if (O.dtpart && valid) {   // Courant step: h / (c_L + |v|), c_L^2 = c_s^2 + 4 mu / (3 rho)
-      const double cs = O.cs[a], rh = O.rho[a];
-      const double mu = type[a] == 1 ? O.mu[a] : 0.0;
-      const double cl = sqrt(cs * cs + 4.0 * mu / (3.0 * rh));
-      const double vm = sqrt(vx[a] * vx[a] + vy[a] * vy[a] + vz[a] * vz[a]);
-      const double q = pos64[a].w / (cl + vm);
-      qmin = q < qmin ? q : qmin;
+    bool net = false;
+    density_epilogue<R, false>(A, ae, valid, O.Dread[ae], pos64, vx, vy, vz, u, S, type, broken, O,
+                               SPLIT ? &net : nullptr);
+    if constexpr (SPLIT) {
+      const unsigned long long m = __ballot(valid && net);
+      if (m) {
+        int b0 = 0;
+        if (lane == 0) b0 = atomicAdd(nlist_n, __popcll(m));
+        b0 = __shfl(b0, 0, 64);
+        if (valid && net) nlist[b0 + __popcll(m & (lane ? (~0ull >> (64 - lane)) : 0ull))] = (int32_t)a;
+      }
     }
+    if (O.dtpart && valid && !net) courant_min(O, pos64, vx, vy, vz, type, a, qmin);
   }
-  if (O.dtpart) {
-    for (int off = 32; off > 0; off >>= 1) {
-      const double o = __shfl_xor(qmin, off, 64);
-      qmin = o < qmin ? o : qmin;
-    }
-    if (threadIdx.x == 0) O.dtpart[blockIdx.x] = qmin;
-  }
+  if (O.dtpart) courant_store(O, qmin, blockIdx.x);
 }
+
+// The network pass of a split epilogue: the particles of nlist[0, *nlist_n), 64 per wave, each
+// finished with the network EoS, its parameters staged in LDS once per workgroup of 4 waves;
+// wave k of block b writes its Courant minimum to dtpart[dt_off + 4 b + k].
+template <typename R>
+__global__ __launch_bounds__(256) void k_density_epilogue_net(PassArgs A, const double4* __restrict__ pos64,
+                                                              const double* __restrict__ vx,
+                                                              const double* __restrict__ vy,
+                                                              const double* __restrict__ vz,
+                                                              const double* __restrict__ u,
+                                                              const double* __restrict__ S,
+                                                              const int8_t* __restrict__ type,
+                                                              const uint8_t* __restrict__ broken, DensOut O,
+                                                              const int32_t* __restrict__ nlist,
+                                                              const int32_t* __restrict__ nlist_n, int dt_off) {
+  const int64_t cnt = cancelled(A) ? 0 : *nlist_n;
+  if ((int64_t)blockIdx.x * 256 >= cnt && !O.dtpart) return;   // no particle for this block
+  mlp_stage_lds(A.mlp);
+  __syncthreads();
+  const int wave = threadIdx.x >> 6;
+  double qmin = __builtin_inf();
+  for (int64_t base = ((int64_t)blockIdx.x * 4 + wave) * 64; base < cnt; base += (int64_t)gridDim.x * 256) {
+    const int64_t i = base + (threadIdx.x & 63);
+    const bool valid = i < cnt;
+    const int64_t a = nlist[valid ? i : base];
+    density_epilogue<R, true>(A, a, valid, O.Dread[a], pos64, vx, vy, vz, u, S, type, broken, O);
+    if (O.dtpart && valid) courant_min(O, pos64, vx, vy, vz, type, a, qmin);
+  }
+  if (O.dtpart) courant_store(O, qmin, dt_off + blockIdx.x * 4 + wave);
+}
+
+__global__ void k_word_clear(int32_t* w) { *w = 0; }   // a kernel, not a memset: graph-safe
 
 // ---- velocity gradient and stress rate ---------------------------------------------------------
 // Lane g of the L-wave workgroup walks the exact slot list (g / L, g % L) written by the density
@@ -1224,20 +1290,33 @@ sph_status launch_eos(sph_ctx* c, sph_state* st) {
   PassArgs A = make_args(c, st);
   DensOut O = dens_out(c, st);
   const bool f32 = c->p.precision == SPH_FP32;
-  // the network path only where some table cell is trusted; with none, every particle takes the
-  // table (the same values), so the table kernel runs
+  // the network passes only where some table cell is trusted; with none, every particle takes the
+  // table (the same values), so the table pass runs alone
   const bool mlp = c->p.eos == SPH_EOS_MLP && A.has_mlp && mlp_trusted_cells(c) > 0;
   const unsigned nb = (unsigned)((st->n + 63) / 64 < 65536 ? (st->n + 63) / 64 : 65536);
-  c->eos_blocks = O.dtpart ? (int)nb : 0;
+  constexpr unsigned kNetBlocks = 512;   // 4 waves each
+  c->eos_blocks = O.dtpart ? (int)nb + (mlp ? 4 * (int)kNetBlocks : 0) : 0;
   const dim3 b(64);
+  if (mlp) hipLaunchKernelGGL(k_word_clear, dim3(1), dim3(1), 0, c->stream, c->eos_list_n);
   auto epi = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3(nb), b, 0, c->stream, A, c->pos4, st->vx, st->vy, st->vz, st->u, st->S, st->type,
-                       st->broken, O);
+                       st->broken, O, c->eos_list, c->eos_list_n);
   };
-  if (f32 && mlp) epi(k_density_epilogue<float, true>);
-  else if (f32) epi(k_density_epilogue<float, false>);
-  else if (mlp) epi(k_density_epilogue<double, true>);
-  else epi(k_density_epilogue<double, false>);
+  auto net = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(kNetBlocks), dim3(256), 0, c->stream, A, c->pos4, st->vx, st->vy, st->vz, st->u, st->S,
+                       st->type, st->broken, O, c->eos_list, c->eos_list_n, (int)nb);
+  };
+  if (f32 && mlp) {
+    epi(k_density_epilogue<float, true>);
+    net(k_density_epilogue_net<float>);
+  } else if (f32) {
+    epi(k_density_epilogue<float, false>);
+  } else if (mlp) {
+    epi(k_density_epilogue<double, true>);
+    net(k_density_epilogue_net<double>);
+  } else {
+    epi(k_density_epilogue<double, false>);
+  }
   HIP_TRY(hipGetLastError());
   return SPH_OK;
 }
