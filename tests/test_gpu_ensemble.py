@@ -46,6 +46,27 @@ def test_ensemble_evaluation(ens):
         assert with_crust >= 2
 
 
+def test_full_size_ensemble_evaluation():
+    # the benchmark's ensemble itself (64 piecewise-polytrope stars of uneven sizes, 8.0M
+    # particles, per-star masses, shear factors and centres): one FP64 evaluation against the
+    # oracle at full size, every particle, and the FP32 evaluation per field
+    w = W.ensemble(64, 8_000_000, seed=5, precision="FP64", kind="pp")
+    o = oracle_run(w)
+    g = gpu_run(w, precision="FP64", lists=False)
+    assert g["_stats"]["pairs"] == int(np.sum(np.diff(o["offsets"])))
+    e = eval_errors(g, o)
+    _print(f"8M ensemble eval ({w.n} particles, {len(w.star_params)} stars)", e)
+    for k, v in e.items():
+        assert v <= 1e-12, (k, v)
+    del g
+    g32 = gpu_run(w, precision="FP32", lists=False)
+    assert g32["_stats"]["pairs"] == int(np.sum(np.diff(o["offsets"])))
+    e = eval_errors(g32, o)
+    _print("8M ensemble fp32 eval", e)
+    for k in ("D", "rho", "P", "ax", "ay", "az", "dudt"):
+        assert e[k] < 1e-4, (k, e[k])
+
+
 def test_ensemble_steps(ens):
     w = ens
     g = gpu_run(w, steps=5, precision="FP64")

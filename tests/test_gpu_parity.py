@@ -143,6 +143,26 @@ def test_full_size_star_matches_oracle():
     assert np.array_equal(g["broken"], o["broken"])
 
 
+def test_c2_star_at_its_size():
+    # configuration C2 as specified: the 200k-particle Gamma = 2 star (Wendland C2, eta 1.3, crust
+    # mu = 0.01 P, elastic, l = 0 perturbation of 1e-3), 100 steps against the oracle in FP64, and
+    # the FP32-pairs path after the same 100 steps per field
+    w = W.star(200_000, seed=2)
+    o = oracle_run(w, steps=100)
+    g = gpu_run(w, steps=100, lists=False)
+    keys = ("x", "y", "z", "vx", "vy", "vz", "u", "h", "S", "D", "ax", "dudt", "dSdt")
+    e = step_errors(g, o, keys, w.dt, 100)
+    _print("C2 200k, 100 steps", e)
+    for k, v in e.items():
+        assert v < TOL_STEPS, (k, v)
+    del g
+    g32 = gpu_run(w, steps=100, precision="FP32", lists=False)
+    e = field_errors(g32, o, ("x", "vx", "u", "h", "S", "D", "rho", "P"))
+    _print("C2 200k FP32 pairs, 100 steps", e)
+    for k in ("D", "rho", "P", "S"):
+        assert e[k] < 1e-4, (k, e[k])
+
+
 def test_fp32_pairs_error_per_field():
     # the FP32 path takes the neighbour decision in FP32 with an FP64 guard band: its exact lists
     # must still equal the FP64 ones
