@@ -226,7 +226,7 @@ sph_status sph_create(const sph_params* params, void* stream, int64_t capacity, 
       (e = dalloc(&c->tovf, cap)) ||
       (e = dalloc(&c->half, SPH_HALF_FIELDS * cap)) || (e = dalloc(&c->tmp, capw)) || (e = dalloc(&c->status, 1)) ||
       (e = dalloc(&c->dsum, cap)) || (e = dalloc(&c->dDdt, cap)) || (e = dalloc(&c->xcoef, 5 * cap)) ||
-      (e = dalloc(&c->dtw, 8)) || (e = dalloc(&c->dtpart, 65536 + 2048)) || (e = dalloc(&c->eos_list, cap)) ||
+      (e = dalloc(&c->dtw, 8)) || (e = dalloc(&c->dtpart, 65536 + 4096)) || (e = dalloc(&c->eos_list, cap)) ||
       (e = dalloc(&c->eos_list_n, 1))) {
     sph_destroy(c);
     return note(nullptr, e, "device scratch for capacity %lld does not fit", (long long)capacity);

@@ -89,21 +89,25 @@ __device__ __forceinline__ void split_bf16(const float h[4], bf16x4& hi, bf16x4&
   lo = pack_bf16(h[0] - bf16_round(h[0]), h[1] - bf16_round(h[1]), h[2] - bf16_round(h[2]), h[3] - bf16_round(h[3]));
 }
 
+// Where a wave finds the parameters: the FP32 blocks of the input layer, the biases and the
+// readout, and the MFMA packs of W2, W3.
+struct MlpP {
+  const float *w1, *b1, *b2, *b3, *w4, *b4;
+  const uint2 *wa2, *wa3;
+};
+
 // The network up to its last hidden layer for the 64 inputs held one per lane (x0, x1
 // normalised).  Every lane of the wave must call it (matrix instructions).  For each block of 16
-// inputs nt it calls out(nt, mt, h, w) with the lane's part of the last hidden layer: h[j] is
-// feature 16 mt + 4 q + j of input 16 nt + r.  ptrs(w, wa2, wa3) gives the parameters, through
-// pointers the compiler does not hoist loads out of the loop over nt (the weights are the same
-// for every nt; hoisted, their loads would occupy ~180 registers across it).
+// inputs nt it calls out(nt, mt, h, P) with the lane's part of the last hidden layer: h[j] is
+// feature 16 mt + 4 q + j of input 16 nt + r.  ptrs() gives the parameters, through pointers the
+// compiler does not hoist loads out of the loop over nt (the weights are the same for every nt;
+// hoisted, their loads would occupy ~180 registers across it).
 template <typename Ptrs, typename Out>
 __device__ __forceinline__ void mlp_wave_layers(Ptrs&& ptrs, float x0, float x1, Out&& out) {
   const int l = threadIdx.x & 63, q = l >> 4, r = l & 15;
 #pragma unroll 1
   for (int nt = 0; nt < 4; ++nt) {
-    const float* w;
-    const uint2* wa2;
-    const uint2* wa3;
-    ptrs(w, wa2, wa3);
+    const MlpP P = ptrs();
     const int pp = 16 * nt + r;   // the input this lane's B-operand column belongs to
     const float a0 = __shfl(x0, pp, 64), a1 = __shfl(x1, pp, 64);
     bf16x4 h1[4], l1[4];
@@ -115,7 +119,7 @@ __device__ __forceinline__ void mlp_wave_layers(Ptrs&& ptrs, float x0, float x1,
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int f = 16 * kk + 4 * q + j;
-        h[j] = silu_f(w[MLP_OW1 + 2 * f] * a0 + w[MLP_OW1 + 2 * f + 1] * a1 + w[MLP_OB1 + f]);
+        h[j] = silu_f(P.w1[2 * f] * a0 + P.w1[2 * f + 1] * a1 + P.b1[f]);
       }
       split_bf16(h, h1[kk], l1[kk]);
     }
@@ -126,13 +130,13 @@ __device__ __forceinline__ void mlp_wave_layers(Ptrs&& ptrs, float x0, float x1,
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
-        const bf16x4 wv = as_bf16x4(wa2[(mt * 4 + kk) * 64 + l]);
+        const bf16x4 wv = as_bf16x4(P.wa2[(mt * 4 + kk) * 64 + l]);
         acc = mfma_bf16(wv, h1[kk], acc);
         acc = mfma_bf16(wv, l1[kk], acc);
       }
       float h[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) h[j] = silu_f(acc[j] + w[MLP_OB2 + 16 * mt + 4 * q + j]);
+      for (int j = 0; j < 4; ++j) h[j] = silu_f(acc[j] + P.b2[16 * mt + 4 * q + j]);
       split_bf16(h, h2[mt], l2[mt]);
     }
 #pragma unroll
@@ -141,14 +145,14 @@ __device__ __forceinline__ void mlp_wave_layers(Ptrs&& ptrs, float x0, float x1,
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
-        const bf16x4 wv = as_bf16x4(wa3[(mt * 4 + kk) * 64 + l]);
+        const bf16x4 wv = as_bf16x4(P.wa3[(mt * 4 + kk) * 64 + l]);
         acc = mfma_bf16(wv, h2[kk], acc);
         acc = mfma_bf16(wv, l2[kk], acc);
       }
       float h3[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) h3[j] = silu_f(acc[j] + w[MLP_OB3 + 16 * mt + 4 * q + j]);
-      out(nt, mt, h3, w);
+      for (int j = 0; j < 4; ++j) h3[j] = silu_f(acc[j] + P.b3[16 * mt + 4 * q + j]);
+      out(nt, mt, h3, P);
     }
     __builtin_amdgcn_sched_barrier(0);
   }
@@ -158,21 +162,28 @@ __device__ __forceinline__ void mlp_wave_layers(Ptrs&& ptrs, float x0, float x1,
 template <typename Out>
 __device__ __forceinline__ void mlp_wave_hidden(const MlpView& M, float x0, float x1, Out&& out) {
   mlp_wave_layers(
-      [&](const float*& w, const uint2*& wa2, const uint2*& wa3) {
-        w = M.wr;
-        wa2 = M.wa2;
-        wa3 = M.wa3;
+      [&]() {
+        const float* w = M.wr;
+        const uint2* wa2 = M.wa2;
+        const uint2* wa3 = M.wa3;
         asm volatile("" : "+s"(w), "+s"(wa2), "+s"(wa3));
+        return MlpP{w + MLP_OW1, w + MLP_OB1, w + MLP_OB2, w + MLP_OB3, w + MLP_OW4, w + MLP_OB4, wa2, wa3};
       },
       x0, x1, out);
 }
 
 // The parameters staged in LDS by a kernel that evaluates the network for many full waves
-// (mlp_stage_lds, then a barrier): the parameters the kernels use and the MFMA packs of W2, W3.
-static __shared__ float s_mlp_w[MLP_NPARAM];
+// (mlp_stage_lds, then a barrier): the 450 FP32 parameters the forward pass reads (W1, b1, b2,
+// b3, W4, b4, packed in that order) and the MFMA packs of W2, W3 (18 KB in all).
+#define MLP_LDS_W 450
+static __shared__ float s_mlp_w[MLP_LDS_W];
 static __shared__ uint2 s_mlp_a[2048];
 __device__ __forceinline__ void mlp_stage_lds(const MlpView& M) {
-  for (int i = threadIdx.x; i < MLP_NPARAM; i += blockDim.x) s_mlp_w[i] = M.wr[i];
+  for (int i = threadIdx.x; i < MLP_LDS_W; i += blockDim.x) {
+    // [0, 192): W1, b1;  [192, 256): b2;  [256, 450): b3, W4, b4
+    const int src = i < 192 ? MLP_OW1 + i : (i < 256 ? MLP_OB2 + (i - 192) : MLP_OB3 + (i - 256));
+    s_mlp_w[i] = M.wr[src];
+  }
   for (int i = threadIdx.x; i < 1024; i += blockDim.x) {
     s_mlp_a[i] = M.wa2[i];
     s_mlp_a[1024 + i] = M.wa3[i];
@@ -181,12 +192,12 @@ __device__ __forceinline__ void mlp_stage_lds(const MlpView& M) {
 template <typename Out>
 __device__ __forceinline__ void mlp_wave_hidden_lds(float x0, float x1, Out&& out) {
   mlp_wave_layers(
-      [&](const float*& w, const uint2*& wa2, const uint2*& wa3) {
+      [&]() {
         int z = 0;   // an offset the compiler cannot see through keeps the loads in the loop
         asm volatile("" : "+s"(z));
-        w = s_mlp_w + z;
-        wa2 = s_mlp_a + z;
-        wa3 = s_mlp_a + 1024 + z;
+        const float* w = s_mlp_w + z;
+        return MlpP{w, w + 128, w + 192, w + 256, w + 256 + (MLP_OW4 - MLP_OB3), w + 256 + (MLP_OB4 - MLP_OB3),
+                    s_mlp_a + z, s_mlp_a + 1024 + z};
       },
       x0, x1, out);
 }
@@ -198,12 +209,12 @@ template <bool LDS = false>
 __device__ __forceinline__ void mlp_wave(const MlpView& M, float x0, float x1, float& y0, float& y1) {
   const int q = (threadIdx.x & 63) >> 4;
   float p0 = 0.f, p1 = 0.f;
-  auto out = [&](int nt, int mt, const float h3[4], const float* w) {
+  auto out = [&](int nt, int mt, const float h3[4], const MlpP& P) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int f = 16 * mt + 4 * q + j;
-      p0 += w[MLP_OW4 + f] * h3[j];
-      p1 += w[MLP_OW4 + MLP_H + f] * h3[j];
+      p0 += P.w4[f] * h3[j];
+      p1 += P.w4[MLP_H + f] * h3[j];
     }
     if (mt == 3) {
       // the four lanes r, r + 16, r + 32, r + 48 hold the partial sums of input 16 nt + r
@@ -212,8 +223,8 @@ __device__ __forceinline__ void mlp_wave(const MlpView& M, float x0, float x1, f
       p1 += __shfl_xor(p1, 16, 64);
       p1 += __shfl_xor(p1, 32, 64);
       if (q == nt) {
-        y0 = p0 + w[MLP_OB4];
-        y1 = p1 + w[MLP_OB4 + 1];
+        y0 = p0 + P.b4[0];
+        y1 = p1 + P.b4[1];
       }
       p0 = p1 = 0.f;
     }

@@ -406,7 +406,7 @@ __global__ __launch_bounds__(64) void k_mlp_gram(MlpView M, const float* __restr
     const int64_t i = base + l;
     const bool ok = i < n;
     mlp_wave_hidden(M, ok ? x[2 * i] : 0.f, ok ? x[2 * i + 1] : 0.f,
-                    [&](int nt, int mt, const float h3[4], const float*) {
+                    [&](int nt, int mt, const float h3[4], const MlpP&) {
                       const bool oks = base + 16 * nt + r < n;
 #pragma unroll
                       for (int j = 0; j < 4; ++j) H[16 * nt + r][16 * mt + 4 * q + j] = oks ? h3[j] : 0.f;

@@ -337,36 +337,6 @@ __device__ __forceinline__ bool mlp_trusted_at(const MlpView& M, const sph_param
   return M.trust[(int64_t)i * (p.tab_nu - 1) + j] != 0;
 }
 
-// Surrogate EoS: the network's ln P, ln c_s^2 in every table cell the trust mask accepts, table
-// interpolation elsewhere.  Every lane of the wave must call it; the network (a wave-level call,
-// its parameters staged in LDS by the calling kernel) runs only if some lane of the wave sits in
-// a trusted cell.
-__device__ __forceinline__ int eos_mlp(const MlpView& M, const sph_params& p, double rho, double u, double& P,
-                                       double& cs2) {
-  bool ok = rho > 0.0 && u > 0.0;
-  const double lnr = ok ? log(rho) : p.tab_lnr0, lnu = ok ? log(u) : p.tab_lnu0;
-  const double fr = (lnr - p.tab_lnr0) / p.tab_dlnr, fu = (lnu - p.tab_lnu0) / p.tab_dlnu;
-  ok = ok && fr >= 0.0 && fu >= 0.0 && fr <= (double)(p.tab_nr - 1) && fu <= (double)(p.tab_nu - 1);
-  const bool trusted = ok && mlp_trusted_at(M, p, rho, u);
-  const MlpNorm& nm = M.norm;
-  float y0 = 0.f, y1 = 0.f;
-  if (__ballot(trusted))
-    mlp_wave<true>(M, (float)((lnr - nm.in_lo[0]) * nm.in_sc[0] - 1.0),
-                   (float)((lnu - nm.in_lo[1]) * nm.in_sc[1] - 1.0), y0, y1);
-  if (!ok) return SPH_E_EOS_DOMAIN;
-  double lp, lc;
-  if (trusted) {
-    lp = (double)y0 * nm.out_sc[0] + nm.out_c[0];
-    lc = (double)y1 * nm.out_sc[1] + nm.out_c[1];
-  } else {
-    int64_t cell;
-    if (eos_table_ln(p, lnr, lnu, lp, lc, cell)) return SPH_E_EOS_DOMAIN;
-  }
-  P = exp(lp);
-  cs2 = exp(lc);
-  return 0;
-}
-
 // ---- density --------------------------------------------------------------------------------
 struct DensOut {
   double *D, *rho, *P, *cs, *mu, *Y0, *B;   // D: where the pair loop writes the summation density
@@ -436,17 +406,17 @@ struct ListWriter {
 
 // Density-stage epilogue in FP64 for particle a with computational density D: rest-mass density
 // from D = rho psi^6 W_L, EoS, shear modulus, yield stress and the packed records of the stress
-// and force passes.  With MLP the EoS is the surrogate network (every lane of the wave must
-// call; lanes with valid = false store nothing).  With net != nullptr (the table pass of a split
-// epilogue) a particle in a cell the network serves is left to the network pass: *net is set and
-// nothing is stored.
-template <typename R, bool MLP>
+// and force passes (lanes with valid = false store nothing).  With GIVEN the EoS values are the
+// network's (lnpc = ln P, ln c_s^2), otherwise the table's or the Gamma law's.  With net !=
+// nullptr (the table pass of a split epilogue) a particle in a cell the network serves is left
+// to the network pass: *net is set and only rho is stored.
+template <typename R, bool GIVEN>
 __device__ __forceinline__ void density_epilogue(const PassArgs& A, int64_t a, bool valid, double D,
                                                  const double4* __restrict__ pos64, const double* __restrict__ vx,
                                                  const double* __restrict__ vy, const double* __restrict__ vz,
                                                  const double* __restrict__ u, const double* __restrict__ S,
                                                  const int8_t* __restrict__ type, const uint8_t* __restrict__ broken,
-                                                 DensOut O, bool* net = nullptr) {
+                                                 DensOut O, bool* net = nullptr, double2 lnpc = double2{}) {
   const sph_params& p = A.p;
   const double va[3] = {vx[a], vy[a], vz[a]};
   const bool tov = p.background == SPH_TOV;
@@ -465,13 +435,18 @@ __device__ __forceinline__ void density_epilogue(const PassArgs& A, int64_t a, b
     rho = D / (psi4 * psi2 * WL);
   }
   if (net && mlp_trusted_at(A.mlp, p, rho, u[a])) {
+    if (valid) O.rho[a] = rho;   // the network pass's input
     *net = true;
     return;
   }
   double P, cs2;
-  int e;
-  if constexpr (MLP) e = eos_mlp(A.mlp, p, rho, u[a], P, cs2);
-  else e = eos_eval(p, rho, u[a], P, cs2);
+  int e = 0;
+  if constexpr (GIVEN) {
+    P = exp(lnpc.x);
+    cs2 = exp(lnpc.y);
+  } else {
+    e = eos_eval(p, rho, u[a], P, cs2);
+  }
   if (!valid) return;
   if (e) latch_error(A.status, e, (int)a);
   if (tov) {
@@ -727,49 +702,78 @@ __device__ __forceinline__ void courant_min(const DensOut& O, const double4* __r
   const double q = pos64[a].w / (cl + vm);
   qmin = q < qmin ? q : qmin;
 }
+// The Courant minimum of a wave (WAVE) or of a whole workgroup of NT threads, stored to
+// dtpart[slot] (every thread of the wave or workgroup calls).
+template <int NT, bool WAVE>
 __device__ __forceinline__ void courant_store(const DensOut& O, double qmin, int slot) {
   for (int off = 32; off > 0; off >>= 1) {
     const double o = __shfl_xor(qmin, off, 64);
     qmin = o < qmin ? o : qmin;
   }
-  if (threadIdx.x == 0) O.dtpart[slot] = qmin;
+  if constexpr (WAVE || NT == 64) {
+    if ((threadIdx.x & 63) == 0) O.dtpart[slot] = qmin;
+  } else {
+    __shared__ double s_q[NT / 64];
+    if ((threadIdx.x & 63) == 0) s_q[threadIdx.x >> 6] = qmin;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int w = 1; w < NT / 64; ++w) qmin = s_q[w] < qmin ? s_q[w] : qmin;
+      O.dtpart[slot] = qmin;
+    }
+  }
 }
+// Threads per workgroup of the table pass: 64, or 256 when it hands particles to the network
+// pass (the list is appended to once per workgroup).
+template <bool SPLIT>
+constexpr int epilogue_threads() { return SPLIT ? 256 : 64; }
+
 template <typename R, bool SPLIT>
-__global__ __launch_bounds__(64) void k_density_epilogue(PassArgs A, const double4* __restrict__ pos64,
-                                                         const double* __restrict__ vx, const double* __restrict__ vy,
-                                                         const double* __restrict__ vz, const double* __restrict__ u,
-                                                         const double* __restrict__ S, const int8_t* __restrict__ type,
-                                                         const uint8_t* __restrict__ broken, DensOut O,
-                                                         int32_t* __restrict__ nlist, int32_t* __restrict__ nlist_n) {
+__global__ __launch_bounds__(epilogue_threads<SPLIT>()) void k_density_epilogue(
+    PassArgs A, const double4* __restrict__ pos64, const double* __restrict__ vx, const double* __restrict__ vy,
+    const double* __restrict__ vz, const double* __restrict__ u, const double* __restrict__ S,
+    const int8_t* __restrict__ type, const uint8_t* __restrict__ broken, DensOut O, int32_t* __restrict__ nlist,
+    int32_t* __restrict__ nlist_n) {
+  constexpr int NT = epilogue_threads<SPLIT>(), NW = NT / 64;
   const int64_t n = cancelled(A) ? 0 : A.n;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ int s_cnt[NW + 1];
   double qmin = __builtin_inf();
-  for (int64_t base = (int64_t)blockIdx.x * 64; base < n; base += (int64_t)gridDim.x * 64) {
-    const int64_t a = base + lane;
+  for (int64_t base = (int64_t)blockIdx.x * NT; base < n; base += (int64_t)gridDim.x * NT) {
+    const int64_t a = base + tid;
     const bool valid = a < n;
     const int64_t ae = valid ? a : base;   // lanes past the end work on a valid particle, store nothing
     bool net = false;
     density_epilogue<R, false>(A, ae, valid, O.Dread[ae], pos64, vx, vy, vz, u, S, type, broken, O,
                                SPLIT ? &net : nullptr);
     if constexpr (SPLIT) {
+      // the workgroup's served particles join the list in particle order, with one atomic
       const unsigned long long m = __ballot(valid && net);
-      if (m) {
-        int b0 = 0;
-        if (lane == 0) b0 = atomicAdd(nlist_n, __popcll(m));
-        b0 = __shfl(b0, 0, 64);
-        if (valid && net) nlist[b0 + __popcll(m & (lane ? (~0ull >> (64 - lane)) : 0ull))] = (int32_t)a;
+      if (lane == 0) s_cnt[wave] = __popcll(m);
+      __syncthreads();
+      if (tid == 0) {
+        int t = 0;
+        for (int w = 0; w < NW; ++w) t += s_cnt[w];
+        s_cnt[NW] = t ? atomicAdd(nlist_n, t) : 0;
       }
+      __syncthreads();
+      if (valid && net) {
+        int off = s_cnt[NW];
+        for (int w = 0; w < wave; ++w) off += s_cnt[w];
+        nlist[off + __popcll(m & (lane ? (~0ull >> (64 - lane)) : 0ull))] = (int32_t)a;
+      }
+      __syncthreads();   // s_cnt is reused by the next round
     }
     if (O.dtpart && valid && !net) courant_min(O, pos64, vx, vy, vz, type, a, qmin);
   }
-  if (O.dtpart) courant_store(O, qmin, blockIdx.x);
+  if (O.dtpart) courant_store<NT, false>(O, qmin, blockIdx.x);
 }
 
-// The network pass of a split epilogue: the particles of nlist[0, *nlist_n), 64 per wave, each
-// finished with the network EoS, its parameters staged in LDS once per workgroup of 4 waves;
-// wave k of block b writes its Courant minimum to dtpart[dt_off + 4 b + k].
+// The network pass of a split epilogue: the particles of nlist[0, *nlist_n), 64 per wave.  A wave
+// evaluates the network for its 64 particles (ln rho from the rho the table pass stored, the
+// parameters staged in LDS once per workgroup of 4 waves) and then runs the epilogue with the
+// network's ln P, ln c_s^2; wave k of block b writes its Courant minimum to dtpart[dt_off + 4 b + k].
 template <typename R>
-__global__ __launch_bounds__(256) void k_density_epilogue_net(PassArgs A, const double4* __restrict__ pos64,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_density_epilogue_net(PassArgs A, const double4* __restrict__ pos64,
                                                               const double* __restrict__ vx,
                                                               const double* __restrict__ vy,
                                                               const double* __restrict__ vz,
@@ -784,15 +788,21 @@ __global__ __launch_bounds__(256) void k_density_epilogue_net(PassArgs A, const 
   mlp_stage_lds(A.mlp);
   __syncthreads();
   const int wave = threadIdx.x >> 6;
+  const MlpNorm nm = A.mlp.norm;
   double qmin = __builtin_inf();
   for (int64_t base = ((int64_t)blockIdx.x * 4 + wave) * 64; base < cnt; base += (int64_t)gridDim.x * 256) {
     const int64_t i = base + (threadIdx.x & 63);
     const bool valid = i < cnt;
     const int64_t a = nlist[valid ? i : base];
-    density_epilogue<R, true>(A, a, valid, O.Dread[a], pos64, vx, vy, vz, u, S, type, broken, O);
+    const double lnr = log(O.rho[a]), lnu = log(u[a]);
+    float y0 = 0.f, y1 = 0.f;
+    mlp_wave<true>(A.mlp, (float)((lnr - nm.in_lo[0]) * nm.in_sc[0] - 1.0),
+                   (float)((lnu - nm.in_lo[1]) * nm.in_sc[1] - 1.0), y0, y1);
+    const double2 lnpc = make_double2((double)y0 * nm.out_sc[0] + nm.out_c[0], (double)y1 * nm.out_sc[1] + nm.out_c[1]);
+    density_epilogue<R, true>(A, a, valid, O.Dread[a], pos64, vx, vy, vz, u, S, type, broken, O, nullptr, lnpc);
     if (O.dtpart && valid) courant_min(O, pos64, vx, vy, vz, type, a, qmin);
   }
-  if (O.dtpart) courant_store(O, qmin, dt_off + blockIdx.x * 4 + wave);
+  if (O.dtpart) courant_store<256, true>(O, qmin, dt_off + blockIdx.x * 4 + wave);
 }
 
 __global__ void k_word_clear(int32_t* w) { *w = 0; }   // a kernel, not a memset: graph-safe
@@ -1293,14 +1303,14 @@ sph_status launch_eos(sph_ctx* c, sph_state* st) {
   // the network passes only where some table cell is trusted; with none, every particle takes the
   // table (the same values), so the table pass runs alone
   const bool mlp = c->p.eos == SPH_EOS_MLP && A.has_mlp && mlp_trusted_cells(c) > 0;
-  const unsigned nb = (unsigned)((st->n + 63) / 64 < 65536 ? (st->n + 63) / 64 : 65536);
-  constexpr unsigned kNetBlocks = 512;   // 4 waves each
+  const int64_t nt = mlp ? epilogue_threads<true>() : epilogue_threads<false>();
+  const unsigned nb = (unsigned)((st->n + nt - 1) / nt < 65536 ? (st->n + nt - 1) / nt : 65536);
+  constexpr unsigned kNetBlocks = 1024;   // 4 waves each, 4 workgroups per CU (128 VGPRs)
   c->eos_blocks = O.dtpart ? (int)nb + (mlp ? 4 * (int)kNetBlocks : 0) : 0;
-  const dim3 b(64);
   if (mlp) hipLaunchKernelGGL(k_word_clear, dim3(1), dim3(1), 0, c->stream, c->eos_list_n);
   auto epi = [&](auto kern) {
-    hipLaunchKernelGGL(kern, dim3(nb), b, 0, c->stream, A, c->pos4, st->vx, st->vy, st->vz, st->u, st->S, st->type,
-                       st->broken, O, c->eos_list, c->eos_list_n);
+    hipLaunchKernelGGL(kern, dim3(nb), dim3((unsigned)nt), 0, c->stream, A, c->pos4, st->vx, st->vy, st->vz, st->u,
+                       st->S, st->type, st->broken, O, c->eos_list, c->eos_list_n);
   };
   auto net = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3(kNetBlocks), dim3(256), 0, c->stream, A, c->pos4, st->vx, st->vy, st->vz, st->u, st->S,

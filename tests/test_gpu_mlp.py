@@ -235,6 +235,37 @@ def test_surrogate_path_meets_oracle_tolerance(trained):
     assert e["D"] < 1e-4 and e["rho"] < 1e-4 and e["P"] < 1e-4
 
 
+@pytest.mark.parametrize("prec", ["FP32", "FP64"])
+def test_courant_step_with_the_network(trained, prec):
+    # dt <= 0 while the network serves particles: the step is cfl min h / (c_L + |v|) over all the
+    # particles of the evaluation before it, those finished by the table pass and by the network
+    # pass alike (every workgroup and wave of both passes leaves its minimum)
+    sph, ctx, w, samples, before, hist, after_lsq, dom = trained
+    from paper_2107_07315_amd import sph as S
+    p = w.params.replace(precision=prec)
+    c = S.Context(p, capacity=w.n)
+    c.mlp_set_domain(*dom)
+    c.mlp_set_params(ctx.mlp_get_params())
+    c.mlp_build_trust_mask(1e-4)
+    st = sph.DeviceState(w.arrays)
+    c.evaluate(st)
+    c.sph_sync()
+    served = c.mlp_count_served(st)
+    a = st.numpy()
+    c.sph_step(st, 0.0, 1)
+    t = c.sph_get_time()
+    c.sph_sync()
+    c.close()
+    solid = (a["type"] == 1) & ~((a["broken"] != 0) & (p.break_mode == "FLUIDIZE"))
+    mu = np.where(solid, p.mu_pfactor * a["P"] if p.mu_mode == "PFACTOR" else p.mu_const, 0.0)
+    cl = np.sqrt(a["cs"] * a["cs"] + 4.0 * mu / (3.0 * a["rho"]))
+    vm = np.sqrt(a["vx"] * a["vx"] + a["vy"] * a["vy"] + a["vz"] * a["vz"])
+    want = p.cfl * float(np.min(a["h"] / (cl + vm)))
+    print(f"{prec} Courant step with the network serving {served} of {w.n}: {t:.17g} (host {want:.17g})", flush=True)
+    assert served > 0.05 * w.n
+    assert abs(t / want - 1) < 1e-14
+
+
 def test_surrogate_gain_is_measured(trained):
     """What the trained network gains over the table it replaces, and what it costs, in its
     domain: the EoS from 17 KB of weights instead of the 16 MB table (970x less memory), at about
