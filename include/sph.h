@@ -119,7 +119,7 @@ typedef struct {
   int32_t precision;       /* FP64, or FP32 pair sums with FP64 positions/integration/metric  */
   int32_t max_neighbours;  /* exact-list capacity per particle (0: 512); candidate lists hold  */
                            /*   twice as many                                                  */
-  int32_t cell_div;        /* cells per smoothing diameter of the finest level (0: 2)          */
+  int32_t cell_div;        /* cells per smoothing diameter of the finest level (0: 1)          */
   double tile_cut;         /* a 64-particle tile is cut where the Morton curve jumps farther  */
                            /*   than tile_cut smoothing lengths (0: 10)                        */
   double skin;             /* relative Verlet skin s: candidate lists hold every b with       */
