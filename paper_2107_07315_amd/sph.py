@@ -208,7 +208,7 @@ class Context:
     # relative Verlet skin of the candidate lists (0: rebuild at every evaluation), by pair-sum
     # precision: a larger skin means fewer list builds but more candidates, and a candidate costs
     # more in FP64 (measured optima on the 2M-particle star)
-    DEFAULT_SKIN = {"FP32": 0.14, "FP64": 0.07}
+    DEFAULT_SKIN = {"FP32": 0.14, "FP64": 0.08}
 
     def __init__(self, params, capacity: int, stream=None, max_neighbours=0, cell_div=0, tile_cut=0.0,
                  skin=None, pass_blocks=0, graph=False, lanes=0):
