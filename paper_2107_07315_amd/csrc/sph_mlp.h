@@ -50,21 +50,19 @@ __device__ __forceinline__ uint32_t bf16_bits(float f) {   // round to nearest e
   return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
 }
 __device__ __forceinline__ float bf16_round(float f) { return __uint_as_float(bf16_bits(f) << 16); }
-__device__ __forceinline__ bf16x4 pack_bf16(float a, float b, float c, float d) {
-  bf16x4 v;
-  v[0] = (short)bf16_bits(a);
-  v[1] = (short)bf16_bits(b);
-  v[2] = (short)bf16_bits(c);
-  v[3] = (short)bf16_bits(d);
-  return v;
+// Two FP32 values rounded to BF16 (nearest even) by one hardware conversion, a in the low half.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
+  const f32x2 v = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
 }
-__device__ __forceinline__ bf16x4 as_bf16x4(uint2 u) {
-  bf16x4 v;
-  v[0] = (short)(u.x & 0xffffu);
-  v[1] = (short)(u.x >> 16);
-  v[2] = (short)(u.y & 0xffffu);
-  v[3] = (short)(u.y >> 16);
-  return v;
+// the FP32 values of the low and the high BF16 of a packed pair
+__device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+__device__ __forceinline__ bf16x4 as_bf16x4(uint2 u) { return __builtin_bit_cast(bf16x4, u); }
+__device__ __forceinline__ bf16x4 pack_bf16(float a, float b, float c, float d) {
+  return as_bf16x4(make_uint2(pk_bf16(a, b), pk_bf16(c, d)));
 }
 __device__ __forceinline__ float silu_f(float z) { return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 __device__ __forceinline__ float dsilu_f(float z) {
@@ -85,8 +83,10 @@ __host__ __device__ __forceinline__ bool mlp_bf16_param(int p) {
 // lo = bf16(h - hi).  W (hi + lo) carries h to about 2^-17, so the products see the weights'
 // BF16 values but not a BF16 rounding of the activations.
 __device__ __forceinline__ void split_bf16(const float h[4], bf16x4& hi, bf16x4& lo) {
-  hi = pack_bf16(h[0], h[1], h[2], h[3]);
-  lo = pack_bf16(h[0] - bf16_round(h[0]), h[1] - bf16_round(h[1]), h[2] - bf16_round(h[2]), h[3] - bf16_round(h[3]));
+  const uint32_t w0 = pk_bf16(h[0], h[1]), w1 = pk_bf16(h[2], h[3]);
+  hi = as_bf16x4(make_uint2(w0, w1));
+  lo = as_bf16x4(make_uint2(pk_bf16(h[0] - bf16_lo(w0), h[1] - bf16_hi(w0)),
+                            pk_bf16(h[2] - bf16_lo(w1), h[3] - bf16_hi(w1))));
 }
 
 // Where a wave finds the parameters: the FP32 blocks of the input layer, the biases and the

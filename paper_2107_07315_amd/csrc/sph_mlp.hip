@@ -55,12 +55,14 @@ __device__ __forceinline__ bf16x4 lds_b4_strided(const uint16_t* p, int stride) 
   return v;
 }
 __device__ __forceinline__ void lds_store_b4(uint16_t* p, float a, float b, float c, float d) {
-  *reinterpret_cast<uint2*>(p) = make_uint2(bf16_bits(a) | (bf16_bits(b) << 16), bf16_bits(c) | (bf16_bits(d) << 16));
+  *reinterpret_cast<uint2*>(p) = make_uint2(pk_bf16(a, b), pk_bf16(c, d));
 }
 // the BF16 parts hi = bf16(h) and lo = bf16(h - hi) of 4 activations (see split_bf16)
 __device__ __forceinline__ void lds_store_split(uint16_t* hi, uint16_t* lo, float a, float b, float c, float d) {
-  lds_store_b4(hi, a, b, c, d);
-  lds_store_b4(lo, a - bf16_round(a), b - bf16_round(b), c - bf16_round(c), d - bf16_round(d));
+  const uint32_t w0 = pk_bf16(a, b), w1 = pk_bf16(c, d);
+  *reinterpret_cast<uint2*>(hi) = make_uint2(w0, w1);
+  *reinterpret_cast<uint2*>(lo) =
+      make_uint2(pk_bf16(a - bf16_lo(w0), b - bf16_hi(w0)), pk_bf16(c - bf16_lo(w1), d - bf16_hi(w1)));
 }
 
 struct GradArgs {
