@@ -332,6 +332,37 @@ def test_one_multi_step_call_equals_single_step_calls():
         assert np.array_equal(a[k], b[k]), k
 
 
+@pytest.mark.parametrize("cell_div", [2, 4])
+def test_cell_size_leaves_the_neighbour_sets(cell_div):
+    # finer cells than the default (2, 4 per smoothing diameter instead of 1) change the cell
+    # enumeration, the tile splits and the order of the candidate unions, not the exact sets
+    w = W.star(20000, seed=3, kernel="WC4", eta=W.ETA_100, l=2, A=1e-2, plastic=True)
+    o = oracle_run(w)
+    for prec in ("FP64", "FP32"):
+        g = gpu_run(w, precision=prec, ctx_kw={"cell_div": cell_div})
+        assert check_lists(g, o, w.n) == 0, prec
+        if prec == "FP64":
+            _assert_eval(g, o)
+        else:
+            e = eval_errors(g, o)
+            for k in ("D", "rho", "P"):
+                assert e[k] < 1e-4, (k, e[k])
+    x, y, z = random_box(777, 1.0, 9)
+    rng = np.random.default_rng(10)
+    n = 777
+    arr = dict(x=x, y=y, z=z, vx=rng.normal(scale=0.1, size=n), vy=rng.normal(scale=0.1, size=n),
+               vz=rng.normal(scale=0.1, size=n), u=rng.uniform(0.5, 2, n), h=0.035 * rng.uniform(0.5, 2.0, n),
+               S=np.zeros((6, n)), type=np.zeros(n, np.int8), broken=np.zeros(n, np.uint8),
+               id=np.arange(n, dtype=np.int32))
+    for periodic in (False, True):
+        p = MethodParams(m=1.0 / n, kernel="WC2", periodic=periodic, box=1.0, eos="GAMMA_LAW", gamma=5 / 3)
+        wr = W.Workload("rand", p, dict(arr), 1e-3, 0)
+        g = gpu_run(wr, ctx_kw={"cell_div": cell_div})
+        o2 = oracle_run(wr, mode=oracle.BRUTE)
+        assert check_lists(g, o2, n) == 0, periodic
+        _assert_eval(g, o2)
+
+
 @pytest.mark.parametrize("lanes", [1, 2])
 def test_lanes_per_target(lanes):
     # 1 and 2 lanes per target (the default is 4): same exact neighbour sets, fields to the
