@@ -1031,13 +1031,13 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
     const R vr = v[0] * d[0] + v[1] * d[1] + v[2] * d[2];
     const bool b_st = fab.y < 0;
     const R Db = fabs(fab.y);
-    // Monaghan viscosity on approaching pairs: one reciprocal gives 1/X and 1/Dbar
+    // Monaghan viscosity on approaching pairs, Pi = mu (beta mu - alpha c_bar) / Dbar with
+    // mu = hab vr / X: with tv = mu / Dbar (one reciprocal), Pi = tv (beta tv Dbar - alpha c_bar)
     const R X = r2 + eps_v * hab * hab;
     const R Dbar = Rec<R>::HS * (Da + Db);
-    const R inv = rcp_fast(X * Dbar);
-    const R muab = hab * vr * (Dbar * inv);
+    const R tv = hab * vr * rcp_fast(X * Dbar);
     const R acbar = Rec<R>::HS * (va.w + vb.w);   // alpha c_bar (the records hold alpha c_s)
-    const R Pi = vr < (R)0 ? muab * fma(beta_v, muab, -acbar) * (X * inv) : (R)0;
+    const R Pi = vr < (R)0 ? tv * fma(beta_v * tv, Dbar, -acbar) : (R)0;
     const R cPF = (pia + fab.x + Pi) * F;
     AP[0] += cPF * d[0];
     AP[1] += cPF * d[1];
