@@ -52,6 +52,21 @@ __device__ __forceinline__ R kern_W_unit(R r, R ih) {
     return w * w * w * t * fma((R)2, q, (R)1);
   }
 }
+// One eighth of it from iH = 1 / (h_a + h_b) = ih / 2, which needs no halving of h_a + h_b:
+// p = r iH = q / 2, and each factor ih of the unit form becomes iH (a power-of-2 scaling, so the
+// value is exactly kern_W_unit / 8).
+template <typename R, int KER>
+__device__ __forceinline__ R kern_W_unit_eighth(R r, R iH) {
+  const R p = r * iH;
+  const R t = fmax((R)1 - p, (R)0);
+  if constexpr (KER == SPH_WC4) {
+    const R w = t * t * iH;
+    return w * w * w * fma(fma((R)(35.0 / 3.0), p, (R)6), p, (R)1);
+  } else {
+    const R w = t * iH;
+    return w * w * w * t * fma((R)4, p, (R)1);
+  }
+}
 template <typename R, int KER>
 __device__ __forceinline__ R kern_F_unit(R r, R ih) {
   const R q = r * ih;
@@ -536,7 +551,9 @@ __device__ __forceinline__ void density_epilogue(const PassArgs& A, int64_t a, b
 // FP32 decision can differ from the exact one only if r^2 lies within that error of H^2, i.e.
 // |d| = H (1 + O(u)); then M <= M_a + |d| and the error is at most
 // 4 sqrt(3) u M_a H + (4 sqrt(3) + 12) u H^2 < 64 u (M_a H + H^2).  Outside the band the FP32
-// decision therefore equals the FP64 one.
+// decision therefore equals the FP64 one.  The pass takes the decision from r2_f - H_f^2 formed
+// with one FMA (its sign is that of r2_f - H_f^2, and H_f^2 is closer to H^2 than the rounded
+// H2_f) and the band as H (kBand H + kBand M_a).
 constexpr float kBand = 3.814697265625e-06f;   // 2^-18
 
 // Density pass.  Walks the candidate lists, takes the exact neighbour decision r^2 < (h_a + h_b)^2
@@ -585,11 +602,11 @@ void k_density(PassArgs A, const double4* __restrict__ pos64, DensOut O,
   const double4 pa = tw.valid ? pos64[a] : make_double4(0.0, 0.0, 0.0, 1.0);
   const double4 ref = pos64[A.tile_start[tile]];
   float4 paf = make_float4(0.f, 0.f, 0.f, 1.f);
-  float Ma = 0.f;
+  float kMa = 0.f;   // kBand times the target's largest coordinate magnitude
   if constexpr (F32) {
     paf = make_float4((float)wrap_sel<PER>(pa.x - ref.x, box, half), (float)wrap_sel<PER>(pa.y - ref.y, box, half),
                       (float)wrap_sel<PER>(pa.z - ref.z, box, half), (float)pa.w);
-    Ma = fmaxf(fabsf(paf.x), fmaxf(fabsf(paf.y), fabsf(paf.z)));
+    kMa = kBand * fmaxf(fabsf(paf.x), fmaxf(fabsf(paf.y), fabsf(paf.z)));
   }
   R sum = 0;
   ListWriter<RB> wr;
@@ -604,16 +621,16 @@ void k_density(PassArgs A, const double4* __restrict__ pos64, DensOut O,
       const float dz = wrap_sel<PER>(paf.z - pb.z, boxf, halff);
       const float r2 = dx * dx + dy * dy + dz * dz;
       const float H = paf.w + pb.w;
-      const float H2 = H * H;
-      hit = r2 < H2;
-      if (fabsf(r2 - H2) <= kBand * fmaf(Ma, H, H2)) {   // near the support edge: decide in FP64
+      const float diff = fmaf(-H, H, r2);   // one rounding: the sign of r2 - H^2
+      hit = diff < 0.f;
+      if (fabsf(diff) <= H * fmaf(kBand, H, kMa)) {   // near the support edge: decide in FP64
         const double4 q = pos64[tw.U[loc]];
         const double r2d = pair_r2(wrap_sel<PER>(pa.x - q.x, box, half), wrap_sel<PER>(pa.y - q.y, box, half),
                                    wrap_sel<PER>(pa.z - q.z, box, half));
         const double Hd = pa.w + q.w;
         hit = r2d < Hd * Hd;
       }
-      W = kern_W_unit<float, KER>(sqrt_hw(r2), rcp_fast(0.5f * H));   // zero for misses
+      W = kern_W_unit_eighth<float, KER>(sqrt_hw(r2), rcp_fast(H));   // zero for misses
     } else {
       const double dx = wrap_sel<PER>(pa.x - pb.x, box, half);
       const double dy = wrap_sel<PER>(pa.y - pb.y, box, half);
@@ -678,7 +695,8 @@ void k_density(PassArgs A, const double4* __restrict__ pos64, DensOut O,
   }
   if (tw.valid && sub == 0) {
     const double W0 = wendland_self<double>(KER, pa.w);   // the particle's own term
-    O.D[a] = particle_mass(A, a) * fma(kern_W_const<KER>(), (double)sum, W0);
+    // the FP32 sum holds kernel values / 8 (kern_W_unit_eighth); the factor 8 is exact
+    O.D[a] = particle_mass(A, a) * fma((F32 ? 8.0 : 1.0) * kern_W_const<KER>(), (double)sum, W0);
   }
   }
 }
