@@ -231,7 +231,7 @@ sph_status sph_create(const sph_params* params, void* stream, int64_t capacity, 
     sph_destroy(c);
     return note(nullptr, e, "device scratch for capacity %lld does not fit", (long long)capacity);
   }
-  if (hipHostMalloc((void**)&c->drift_host, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void**)&c->drift_host, 4 * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
     c->drift_host = nullptr;
     sph_destroy(c);
     return note(nullptr, SPH_E_OOM, "pinned host word");

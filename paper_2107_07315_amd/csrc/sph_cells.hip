@@ -9,6 +9,7 @@
 // skips cells whose box lies farther away.  Cells are addressed by Morton codes so that the
 // sorted particle order is spatially compact.  The list build writes exact FP64 lists that all
 // later passes read, grouped in tiles of 64 particles (see k_build_tiles).
+#include <stddef.h>
 #include <string.h>
 
 #include <mutex>
@@ -922,10 +923,14 @@ sph_status permute_array(sph_ctx* c, T* arr, int64_t n) {
 // The union pool is sized to what the tiles reserve: read the reservation total and grow the
 // pool (by a quarter more than needed) when it does not fit.  Waits for the stream.
 static sph_status ensure_pool(sph_ctx* c) {
-  uint32_t used = 0;
-  HIP_TRY(hipMemcpyAsync(c->drift_host, &c->grid->upool_used, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+  // ntiles, upool_used and nstress are adjacent in GridInfo: one copy brings all three
+  static_assert(offsetof(GridInfo, upool_used) == offsetof(GridInfo, ntiles) + 4 &&
+                    offsetof(GridInfo, nstress) == offsetof(GridInfo, ntiles) + 8,
+                "GridInfo layout");
+  HIP_TRY(hipMemcpyAsync(c->drift_host, &c->grid->ntiles, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
-  used = *c->drift_host;
+  const uint32_t used = c->drift_host[1];
+  c->stress_heavy = 2ull * c->drift_host[2] > (unsigned long long)c->drift_host[0];
   if ((int64_t)used <= c->upool) return SPH_OK;
   int64_t want = (int64_t)used + (int64_t)used / 4;
   if (want > (int64_t)0xffffffffll) want = (int64_t)0xffffffffll;
@@ -1038,6 +1043,12 @@ sph_status sph_rebin(sph_ctx* c, sph_state* st, bool outputs_recomputed) {
                        cell_div_of(c->p));
   }
   if ((e = sph_scan_u32(c, c->tile_uoff, c->tile_uoff, c->cap_tiles, &c->grid->upool_used))) return e;
+  // stress-pass work list (tiles with a type-1 particle), read back with the pool size
+  hipLaunchKernelGGL(k_stress_flags, dim3(grid_for(c->cap_tiles, kB)), dim3(kB), 0, s, c->grid, c->cap_tiles,
+                     c->tile_start, c->tile_cnt, st->type, flag);
+  if ((e = sph_scan_u32(c, flag, idx, c->cap_tiles, &c->grid->nstress))) return e;
+  hipLaunchKernelGGL(k_stress_list, dim3(grid_for(c->cap_tiles, kB)), dim3(kB), 0, s, flag, idx, c->cap_tiles,
+                     c->stress_tiles);
   if ((e = ensure_pool(c))) return e;
   BuildArgs B;
   B.pos4 = c->pos4; B.n = n; B.grid = c->grid; B.perm = c->vals; B.pos_sorted = c->pos_sorted;
@@ -1048,12 +1059,7 @@ sph_status sph_rebin(sph_ctx* c, sph_state* st, bool outputs_recomputed) {
   B.status = c->status;
   launch_build(B, per, dim3(tile_grid(c->cap_tiles)), s);
   HIP_TRY(hipGetLastError());
-  // stress-pass work list and the zero rates of every type-0 particle
-  hipLaunchKernelGGL(k_stress_flags, dim3(grid_for(c->cap_tiles, kB)), dim3(kB), 0, s, c->grid, c->cap_tiles,
-                     c->tile_start, c->tile_cnt, st->type, flag);
-  if ((e = sph_scan_u32(c, flag, idx, c->cap_tiles, &c->grid->nstress))) return e;
-  hipLaunchKernelGGL(k_stress_list, dim3(grid_for(c->cap_tiles, kB)), dim3(kB), 0, s, flag, idx, c->cap_tiles,
-                     c->stress_tiles);
+  // the zero rates of every type-0 particle
   hipLaunchKernelGGL(k_zero_fluid_rates, dim3(grid_for(n, kB)), dim3(kB), 0, s, st->type, n, st->S, st->dSdt,
                      c->sdot);
   HIP_TRY(hipGetLastError());

@@ -391,6 +391,7 @@ struct sph_ctx {
   int32_t* eos_list;    // particles the EoS network serves in the current evaluation (split epilogue)
   int32_t* eos_list_n;
   int eos_blocks;       // blocks of that epilogue that wrote dtpart (0: none)
+  bool stress_heavy;    // more than half of the tiles hold a type-1 particle (last list build)
   int64_t steps_done;   // steps completed since sph_create (slot bookkeeping of the Courant steps)
   bool adaptive;        // inside an sph_step call with Courant steps
   bool eval_in_step;    // an evaluation queued by sph_step (the lagged dP/dt reads that step's dt)

@@ -106,6 +106,7 @@ template <> struct Rec<float> {
   static constexpr int CHMAX_D = 1280;   // per workgroup: 20 KB + 8 KB of list staging, 5 workgroups per CU
   static constexpr int CH_S = 256;
   static constexpr int CH_F = 256;
+  static constexpr int CH_FS = 128;   // forces with S/D^2 in LDS too (64 bytes a record): 32 KB
 };
 
 struct PassArgs {
@@ -858,35 +859,59 @@ __global__ __launch_bounds__(64 * L) void k_stress(PassArgs A, const typename Re
     sdot[a] = 0.0;
   }
   if (!__syncthreads_or(stressed)) continue;   // whole tile fluid
-  tw.start(pass_list<L>(A, slot), A.capw * L, stressed ? pass_count<L>(A, tw.p, sub, slot) : 0);
   const sph_params& p = A.p;
   const P4 pa = tw.valid ? pos[a] : P4{0, 0, 0, 1};
   const V4 va = tw.valid ? fv[a] : V4{0, 0, 0, 0};
   R G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  for (int c0 = 0; c0 < tw.usize; c0 += CH) {
-    __syncthreads();
-    struct Recs { P4 p; V4 v; };
-    stage_union<64 * L, CH>(tw.U, c0, tw.usize, [&](int32_t b) { return Recs{pos[b], fv[b]}; },
+  struct Recs { P4 p; V4 v; };
+  auto pair = [&](const Recs& r) {
+    const P4& pb = r.p;
+    const V4& vb = r.v;
+    const R d[3] = {wrap_sel<PER>(pa.x - pb.x, box, half), wrap_sel<PER>(pa.y - pb.y, box, half),
+                    wrap_sel<PER>(pa.z - pb.z, box, half)};
+    const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    const R ih = rcp_fast(Rec<R>::HS * (pa.w + pb.w));
+    R F;   // without the kernel's constant, applied in the epilogue
+    if constexpr (std::is_same<R, float>::value) F = kern_F_unit<float, KER>(sqrt_hw(r2), ih);
+    else F = kern_F_unit<R, KER>(sqrt_fast(r2), ih);
+    const R g[3] = {F * d[0], F * d[1], F * d[2]};
+    const R v[3] = {vb.x - va.x, vb.y - va.y, vb.z - va.z};
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int jj = 0; jj < 3; ++jj) G[i][jj] += v[i] * g[jj];
+  };
+  auto stage = [&](int c0, int ch) {
+    stage_union<64 * L, CH>(tw.U, c0, c0 + ch < tw.usize ? c0 + ch : tw.usize,
+                            [&](int32_t b) { return Recs{pos[b], fv[b]}; },
                             [&](int j, const Recs& r) { sp[j] = r.p; sv[j] = r.v; });
+  };
+  if (std::is_same<R, float>::value && tw.usize < CH) {
+    // FP32 with the whole union in one chunk: pipelined group walk, LDS slot CH - 1 the sentinel
+    // (far away, h = 0: F = 0)
     __syncthreads();
-    const int cend = c0 + CH;
-    while (tw.next < cend) {
-      const P4 pb = sp[tw.next - c0];
-      const V4 vb = sv[tw.next - c0];
-      tw.advance();
-      const R d[3] = {wrap_sel<PER>(pa.x - pb.x, box, half), wrap_sel<PER>(pa.y - pb.y, box, half),
-                      wrap_sel<PER>(pa.z - pb.z, box, half)};
-      const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-      const R ih = rcp_fast(Rec<R>::HS * (pa.w + pb.w));
-      R F;   // without the kernel's constant, applied in the epilogue
-      if constexpr (std::is_same<R, float>::value) F = kern_F_unit<float, KER>(sqrt_hw(r2), ih);
-      else F = kern_F_unit<R, KER>(sqrt_fast(r2), ih);
-      const R g[3] = {F * d[0], F * d[1], F * d[2]};
-      const R v[3] = {vb.x - va.x, vb.y - va.y, vb.z - va.z};
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int jj = 0; jj < 3; ++jj) G[i][jj] += v[i] * g[jj];
+    stage(0, CH - 1);
+    if (threadIdx.x == 0) {
+      sp[CH - 1] = P4{(R)1e10, (R)1e10, (R)1e10, (R)0};
+      sv[CH - 1] = V4{(R)0, (R)0, (R)0, (R)0};
+    }
+    __syncthreads();
+    const int cnt = stressed ? pass_count<L>(A, tw.p, sub, slot) : 0;
+    walk_groups_pf(
+        pass_list<L>(A, slot), A.capw * L, cnt, wave_max_i(cnt), CH - 1,
+        [&](int j) { return Recs{sp[j], sv[j]}; }, [&](int, const Recs& r) { pair(r); }, [] {});
+  } else {
+    tw.start(pass_list<L>(A, slot), A.capw * L, stressed ? pass_count<L>(A, tw.p, sub, slot) : 0);
+    for (int c0 = 0; c0 < tw.usize; c0 += CH) {
+      __syncthreads();
+      stage(c0, CH);
+      __syncthreads();
+      const int cend = c0 + CH;
+      while (tw.next < cend) {
+        const int j = tw.next - c0;
+        tw.advance();
+        pair(Recs{sp[j], sv[j]});
+      }
     }
   }
 #pragma unroll
@@ -984,8 +1009,11 @@ __device__ __forceinline__ void ext_accel(const PassArgs& A, const ForceOut& O, 
 // target's L lanes are added before the fixed-background epilogue.
 // XS selects the optional sums (compile-time, so that the default mode keeps its registers):
 //   kXDD: sum m v_ab . grad_a W (continuity density and first-law energy);
-//   kXGP: that and v_a . (P_a/D_a^2 + P_b/D_b^2) grad_a W (the advection of P in the lagged dP/dt row).
-constexpr int kXDD = 1, kXGP = 2;
+//   kXGP: that and v_a . (P_a/D_a^2 + P_b/D_b^2) grad_a W (the advection of P in the lagged dP/dt row);
+// and kXSL (FP32, with neither sum): the neighbours' S/D^2 staged in LDS with the other records,
+// for workloads where most tiles hold stressed particles (otherwise each stressed pair reads the
+// neighbour's union index and six S/D^2 values from memory).
+constexpr int kXDD = 1, kXGP = 2, kXSL = 4;
 template <typename R, int KER, bool PER, int L, int XS>
 __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Rec<R>::P4* __restrict__ pos,
                                                    const typename Rec<R>::V4* __restrict__ fv,
@@ -995,13 +1023,15 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
   using P4 = typename Rec<R>::P4;
   using V4 = typename Rec<R>::V4;
   using A2 = typename Rec<R>::A2;
-  constexpr bool DD = XS != 0, GP = XS == kXGP;
-  constexpr int CH = Rec<R>::CH_F * L;
+  constexpr bool DD = (XS & 3) != 0, GP = (XS & 3) == kXGP, SL = (XS & kXSL) != 0;
+  static_assert(!SL || std::is_same<R, float>::value, "S/D^2 in LDS: FP32 records only");
+  constexpr int CH = (SL ? Rec<float>::CH_FS : Rec<R>::CH_F) * L;
   constexpr int CHU = CH - 1;   // union records per chunk; slot CHU holds the walk's sentinel
   const int tl = threadIdx.x / L, sub = threadIdx.x % L;
   __shared__ P4 sp[CH];
   __shared__ V4 sv[CH];
   __shared__ A2 sa2[CH];
+  __shared__ R ssg[SL ? 6 : 1][SL ? CH : 1];   // kXSL: S/D^2 of the staged members (0 if unstressed)
   const R box = (R)A.p.box, half = (R)0.5 * box;
   if (threadIdx.x == 0) {   // the sentinel: far from every target, at rest, h = 0, unstressed (F = 0)
     sp[CHU] = P4{(R)1e10, (R)1e10, (R)1e10, (R)0};
@@ -1033,6 +1063,7 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
   const R alpha_v = (R)p.visc_alpha, beta_v = (R)p.visc_beta, eps_v = (R)p.visc_eps;
   R AP[3] = {0, 0, 0}, AS[3] = {0, 0, 0}, ud = 0, dd = 0, gp = 0;
   struct Recs { P4 p; V4 v; A2 f; };
+  int cbase = 0;   // union index of LDS slot 0 (the chunk's first member)
   // pair with union member loc, records r (the sentinel: F = 0, which zeroes every term)
   auto pair = [&](int loc, const Recs& r) {
     const P4& pb = r.p;
@@ -1067,17 +1098,44 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
     if (a_st || b_st) {
       const R g[3] = {F * d[0], F * d[1], F * d[2]};
       R s6[6];
-      const int32_t b = b_st ? tw.U[loc] : 0;
+      if constexpr (SL) {
+        // only a stressed member's slot: padding entries of the walk pass a stale loc with the
+        // sentinel's records
 #pragma unroll
-      for (int c = 0; c < 6; ++c) s6[c] = sa[c] + (b_st ? sig[c * n + b] : (R)0);
+        for (int c = 0; c < 6; ++c) s6[c] = sa[c] + (b_st ? ssg[c][loc - cbase] : (R)0);
+      } else {
+        const int32_t b = b_st ? tw.U[loc] : 0;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) s6[c] = sa[c] + (b_st ? sig[c * n + b] : (R)0);
+      }
       AS[0] += s6[0] * g[0] + s6[3] * g[1] + s6[4] * g[2];
       AS[1] += s6[3] * g[0] + s6[1] * g[1] + s6[5] * g[2];
       AS[2] += s6[4] * g[0] + s6[5] * g[1] + s6[2] * g[2];
     }
   };
   auto stage = [&](int c0) {
-    stage_union<64 * L, CHU>(tw.U, c0, tw.usize, [&](int32_t b) { return Recs{pos[b], fv[b], fa[b]}; },
-                            [&](int j, const Recs& r) { sp[j] = r.p; sv[j] = r.v; sa2[j] = r.f; });
+    if constexpr (SL) {
+      struct RecsS { P4 p; V4 v; A2 f; R s[6]; };
+      stage_union<64 * L, CHU>(
+          tw.U, c0, tw.usize,
+          [&](int32_t b) {
+            RecsS r{pos[b], fv[b], fa[b], {0, 0, 0, 0, 0, 0}};
+            if (r.f.y < 0)
+#pragma unroll
+              for (int c = 0; c < 6; ++c) r.s[c] = sig[c * n + b];
+            return r;
+          },
+          [&](int j, const RecsS& r) {
+            sp[j] = r.p;
+            sv[j] = r.v;
+            sa2[j] = r.f;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) ssg[c][j] = r.s[c];
+          });
+    } else {
+      stage_union<64 * L, CHU>(tw.U, c0, tw.usize, [&](int32_t b) { return Recs{pos[b], fv[b], fa[b]}; },
+                              [&](int j, const Recs& r) { sp[j] = r.p; sv[j] = r.v; sa2[j] = r.f; });
+    }
   };
   // FP32 with the whole union in one chunk (the usual case): pipelined group walk.  (In FP64 the 8
   // inlined copies of the longer pair body run slower than the shifting walk, measured.)
@@ -1094,6 +1152,7 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
       __syncthreads();
       stage(c0);
       __syncthreads();
+      cbase = c0;
       const int cend = c0 + CHU;
       while (tw.next < cend) {
         const int loc = tw.next;
@@ -1394,6 +1453,9 @@ sph_status launch_forces(sph_ctx* c, sph_state* st) {
       };
       if (xs == kXGP) launch(std::integral_constant<int, kXGP>{});
       else if (xs == kXDD) launch(std::integral_constant<int, kXDD>{});
+      else if (c->stress_heavy && c->p.precision == SPH_FP32)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forces<float, KER, PER, L, kXSL>), g, b, 0, c->stream, A, c->pos4f,
+                           c->fvf, c->faf, c->sigf, c->tovf, c->sdot, O);
       else launch(std::integral_constant<int, 0>{});
     });
   });
