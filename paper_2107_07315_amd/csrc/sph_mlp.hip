@@ -261,9 +261,22 @@ __global__ __launch_bounds__(256) void k_mlp_adam(float* w, float* wr, float* m,
                                                   const float* lpart, int nblk, float lr, float bc1, float bc2,
                                                   float* gsum, float* loss_out) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  // block partials summed in block order; their loads are issued 8 at a time (one wait per 8)
+  auto sum_parts = [&](const float* part, int64_t stride, int64_t off) {
+    float s = 0.f;
+    int b = 0;
+    for (; b + 8 <= nblk; b += 8) {
+      float t[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) t[k] = part[(int64_t)(b + k) * stride + off];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s += t[k];
+    }
+    for (; b < nblk; ++b) s += part[(int64_t)b * stride + off];
+    return s;
+  };
   if (p < MLP_NPARAM) {
-    float g = 0.f;
-    for (int b = 0; b < nblk; ++b) g += gpart[(int64_t)b * MLP_NPARAM + p];
+    const float g = sum_parts(gpart, MLP_NPARAM, p);
     if (gsum) gsum[p] = g;
     if (lr > 0.f) {
       const float mm = 0.9f * m[p] + 0.1f * g;
@@ -275,11 +288,7 @@ __global__ __launch_bounds__(256) void k_mlp_adam(float* w, float* wr, float* m,
       wr[p] = mlp_bf16_param(p) ? bf16_round(wn) : wn;
     }
   }
-  if (p == 0 && loss_out) {
-    float s = 0.f;
-    for (int b = 0; b < nblk; ++b) s += lpart[b];
-    *loss_out = s;
-  }
+  if (p == 0 && loss_out) *loss_out = sum_parts(lpart, 1, 0);
 }
 
 // MFMA A-operand packs of W2, W3 and their transposes from the rounded weights.
