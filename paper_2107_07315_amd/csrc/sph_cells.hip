@@ -247,6 +247,22 @@ __global__ __launch_bounds__(kB) void k_gather(const T* __restrict__ src, const 
   if (i < n) dst[i] = src[perm[i]];
 }
 
+// Several arrays of 8-byte elements at once: dst[k][i] = src[k][perm[i]] (gather) or
+// dst[k][i] = src[k][i] (copy) for k < na, the permutation read once per element.
+constexpr int kPermBatch = 16;
+struct PermBatch {
+  const double* src[kPermBatch];
+  double* dst[kPermBatch];
+  int na;
+};
+template <bool GATHER>
+__global__ __launch_bounds__(kB) void k_permute_batch(PermBatch B, const uint32_t* __restrict__ perm, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t j = GATHER ? (int64_t)perm[i] : i;
+  for (int k = 0; k < B.na; ++k) B.dst[k][i] = B.src[k][j];
+}
+
 
 // pos4: absolute position and h (FP64 pair passes); pos4f: position relative to the
 // particle's star centre and h (FP32 pair passes keep full precision near each star).
@@ -908,6 +924,33 @@ __global__ __launch_bounds__(kB) void k_count_stats(const int32_t* __restrict__ 
   }
 }
 
+// Permutes the 8-byte arrays arr[0, m) in place along c->vals: batches of up to kPermBatch go
+// through a staging area in one gather and one copy launch each.  The staging is the candidate-list
+// buffer, whose lists the build that follows rewrites (c->tmp, one array, where it is smaller).
+static sph_status permute_arrays(sph_ctx* c, double* const* arr, int m, int64_t n) {
+  if (n <= 0) return SPH_OK;
+  const size_t big = (size_t)c->capw * (size_t)(c->cap_s + 32) * sizeof(uint16_t);
+  double* stage = reinterpret_cast<double*>(c->nbr16s);
+  int per = (int)(big / (sizeof(double) * (size_t)n));
+  if (per < 1) { stage = c->tmp; per = 1; }
+  per = per < kPermBatch ? per : kPermBatch;
+  const unsigned nb = grid_for(n, kB);
+  for (int k0 = 0; k0 < m; k0 += per) {
+    PermBatch G{}, C{};
+    G.na = C.na = (m - k0) < per ? (m - k0) : per;
+    for (int k = 0; k < G.na; ++k) {
+      G.src[k] = arr[k0 + k];
+      G.dst[k] = stage + (int64_t)k * n;
+      C.src[k] = G.dst[k];
+      C.dst[k] = arr[k0 + k];
+    }
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_permute_batch<true>), dim3(nb), dim3(kB), 0, c->stream, G, c->vals, n);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_permute_batch<false>), dim3(nb), dim3(kB), 0, c->stream, C, c->vals, n);
+  }
+  HIP_TRY(hipGetLastError());
+  return SPH_OK;
+}
+
 template <typename T>
 sph_status permute_array(sph_ctx* c, T* arr, int64_t n) {
   if (!arr) return SPH_OK;
@@ -987,24 +1030,19 @@ sph_status sph_rebin(sph_ctx* c, sph_state* st, bool outputs_recomputed) {
   {
     hipLaunchKernelGGL(k_gkeys, dim3(nb), dim3(kB), 0, s, c->pos4, n, c->grid, c->keys, c->vals);
     if ((e = sph_sort_pairs(c, c->keys, c->vals, n))) return e;
-    double* d64[] = {st->x, st->y, st->z, st->vx, st->vy, st->vz, st->u, st->h};
-    for (double* a : d64)
-      if ((e = permute_array(c, a, n))) return e;
-    for (int k = 0; k < 6; ++k)
-      if ((e = permute_array(c, st->S + k * n, n))) return e;
+    double* d64[64];
+    int m = 0;
+    for (double* a : {st->x, st->y, st->z, st->vx, st->vy, st->vz, st->u, st->h}) d64[m++] = a;
+    for (int k = 0; k < 6; ++k) d64[m++] = st->S + k * n;
     if (!outputs_recomputed) {
-      double* out64[] = {st->D, st->rho, st->P, st->cs, st->ax, st->ay, st->az, st->dudt};
-      for (double* a : out64)
-        if ((e = permute_array(c, a, n))) return e;
-      for (int k = 0; k < 6; ++k)
-        if ((e = permute_array(c, st->dSdt + k * n, n))) return e;
+      for (double* a : {st->D, st->rho, st->P, st->cs, st->ax, st->ay, st->az, st->dudt}) d64[m++] = a;
+      for (int k = 0; k < 6; ++k) d64[m++] = st->dSdt + k * n;
+    } else {   // state that the next evaluation reads although it is an output
+      if (c->p.density_mode == SPH_DENS_CONTINUITY) d64[m++] = st->D;
+      if (c->p.dtP_mode == SPH_DTP_LAGGED) d64[m++] = st->P;
     }
-    if (outputs_recomputed) {   // state that the next evaluation reads although it is an output
-      if (c->p.density_mode == SPH_DENS_CONTINUITY && (e = permute_array(c, st->D, n))) return e;
-      if (c->p.dtP_mode == SPH_DTP_LAGGED && (e = permute_array(c, st->P, n))) return e;
-    }
-    for (int k = 0; k < SPH_HALF_FIELDS; ++k)
-      if ((e = permute_array(c, c->half + (int64_t)k * c->capacity, n))) return e;
+    for (int k = 0; k < SPH_HALF_FIELDS; ++k) d64[m++] = c->half + (int64_t)k * c->capacity;
+    if ((e = permute_arrays(c, d64, m, n))) return e;
     if ((e = permute_array(c, st->type, n))) return e;
     if ((e = permute_array(c, st->broken, n))) return e;
     if ((e = permute_array(c, st->id, n))) return e;
