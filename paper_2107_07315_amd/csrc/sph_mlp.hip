@@ -35,7 +35,9 @@ struct MlpState {
 
 namespace {
 
-constexpr int kMaxBlocks = 128;   // batch <= 8192 samples
+constexpr int kMaxBatch = 8192;   // samples per batch (a multiple of 64)
+constexpr int kGradSamples = 16;  // samples per gradient workgroup: 512 workgroups for the largest batch
+constexpr int kMaxBlocks = kMaxBatch / kGradSamples;
 constexpr int LP = 68;            // padded row of the LDS matrices (8- and 16-byte aligned rows)
 
 __device__ __forceinline__ float wave_sum_f(float v) {
@@ -71,43 +73,50 @@ struct GradArgs {
   const float* t;    // normalised targets
   int64_t off;       // first sample of the batch; samples wrap modulo n
   int64_t n;
-  int batch;         // samples in the batch (multiple of 64); block b takes samples [64 b, 64 b + 64)
+  int batch;         // samples in the batch (multiple of 64); block b takes samples [NS b, NS b + NS)
   float* gpart;
   float* lpart;
 };
 
-// Gradient of L = 1/(2 batch) sum_s sum_o (y_so - t_so)^2 over the block's 64 samples (lane =
-// sample), written as this block's partial.  Layers 2 and 3 and their weight gradients and
-// back-propagated activations are 64x64x64 products on the matrix cores; activations are kept
-// in LDS sample-major (row = sample, column = feature).  The forward products take the
-// activations as two BF16 parts, as the inference does (the loss is that of the network the
-// kernels evaluate); the weight gradients use their high parts.
+// Gradient of L = 1/(2 batch) sum_s sum_o (y_so - t_so)^2 over the block's NS samples (lane l <
+// NS = sample l), written as this block's partial.  Layers 2 and 3 and their weight gradients and
+// back-propagated activations are products on the matrix cores (64 x 64 x NS and 64 x NS x 64);
+// activations are kept in LDS sample-major (row = sample, column = feature).  The forward
+// products take the activations as two BF16 parts, as the inference does (the loss is that of the
+// network the kernels evaluate); the weight gradients use their high parts.  NS = 16 spreads a
+// 4096-sample batch over 256 workgroups, one per CU.
+template <int NS>
 __global__ __launch_bounds__(64) void k_mlp_grad(GradArgs G) {
-  __shared__ __align__(16) uint16_t Ht1[64 * LP];
-  __shared__ __align__(16) uint16_t Ht2[64 * LP];
-  __shared__ __align__(16) uint16_t Lt1[64 * LP];   // low BF16 parts of the activations
-  __shared__ __align__(16) uint16_t Lt2[64 * LP];
-  __shared__ __align__(16) uint16_t Gt[64 * LP];
-  __shared__ __align__(16) float Zt2[64 * LP];
-  __shared__ __align__(16) float Zt3[64 * LP];
-  __shared__ __align__(16) float G32[64 * LP];
-  __shared__ float xs[64][2], dys[64][2];
+  static_assert(NS % 16 == 0 && NS <= 64, "whole 16-sample tiles");
+  constexpr int NT = NS / 16;   // 16-sample tiles
+  __shared__ __align__(16) uint16_t Ht1[NS * LP];
+  __shared__ __align__(16) uint16_t Ht2[NS * LP];
+  __shared__ __align__(16) uint16_t Lt1[NS * LP];   // low BF16 parts of the activations
+  __shared__ __align__(16) uint16_t Lt2[NS * LP];
+  __shared__ __align__(16) uint16_t Gt[NS * LP];
+  __shared__ __align__(16) float Zt2[NS * LP];
+  __shared__ __align__(16) float Zt3[NS * LP];
+  __shared__ __align__(16) float G32[NS * LP];
+  __shared__ float xs[NS][2], dys[NS][2];
   const int l = threadIdx.x, q = l >> 4, r = l & 15;
+  const bool own = l < NS;   // the lane holds a sample
   const MlpView& M = G.M;
   const float* w = M.wr;
-  const int64_t sg = (G.off + (int64_t)blockIdx.x * 64 + l) % G.n;
-  const float x0 = G.x[2 * sg], x1 = G.x[2 * sg + 1];
-  const float t0 = G.t[2 * sg], t1 = G.t[2 * sg + 1];
+  const int64_t sg = (G.off + (int64_t)blockIdx.x * NS + (own ? l : 0)) % G.n;
+  const float x0 = own ? G.x[2 * sg] : 0.f, x1 = own ? G.x[2 * sg + 1] : 0.f;
+  const float t0 = own ? G.t[2 * sg] : 0.f, t1 = own ? G.t[2 * sg + 1] : 0.f;
   float* gp = G.gpart + (int64_t)blockIdx.x * MLP_NPARAM;
-  xs[l][0] = x0;
-  xs[l][1] = x1;
-  // ---- forward --------------------------------------------------------------------------------
-  for (int f = 0; f < 64; f += 4) {
-    float h[4];
+  if (own) {
+    xs[l][0] = x0;
+    xs[l][1] = x1;
+    // ---- forward ------------------------------------------------------------------------------
+    for (int f = 0; f < 64; f += 4) {
+      float h[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      h[j] = silu_f(w[MLP_OW1 + 2 * (f + j)] * x0 + w[MLP_OW1 + 2 * (f + j) + 1] * x1 + w[MLP_OB1 + f + j]);
-    lds_store_split(&Ht1[l * LP + f], &Lt1[l * LP + f], h[0], h[1], h[2], h[3]);
+      for (int j = 0; j < 4; ++j)
+        h[j] = silu_f(w[MLP_OW1 + 2 * (f + j)] * x0 + w[MLP_OW1 + 2 * (f + j) + 1] * x1 + w[MLP_OB1 + f + j]);
+      lds_store_split(&Ht1[l * LP + f], &Lt1[l * LP + f], h[0], h[1], h[2], h[3]);
+    }
   }
   __syncthreads();
   // hidden layers: C tile (features 16 mt + 4q + j, samples 16 nt + r)
@@ -117,7 +126,7 @@ __global__ __launch_bounds__(64) void k_mlp_grad(GradArgs G) {
     const uint16_t* Hin = layer == 0 ? Ht1 : Ht2;
     const uint16_t* Lin = layer == 0 ? Lt1 : Lt2;
     float* Z = layer == 0 ? Zt2 : Zt3;
-    for (int nt = 0; nt < 4; ++nt) {
+    for (int nt = 0; nt < NT; ++nt) {
       bf16x4 b[4], bl[4];
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
@@ -144,33 +153,37 @@ __global__ __launch_bounds__(64) void k_mlp_grad(GradArgs G) {
     __syncthreads();
   }
   // output layer and loss (lane = sample)
-  float y0 = w[MLP_OB4], y1 = w[MLP_OB4 + 1];
-  for (int f = 0; f < 64; ++f) {
-    const float h3 = silu_f(Zt3[l * LP + f]);
-    y0 += w[MLP_OW4 + f] * h3;
-    y1 += w[MLP_OW4 + MLP_H + f] * h3;
-  }
   const float inv = 1.0f / (float)G.batch;
-  const float e0 = y0 - t0, e1 = y1 - t1;
-  const float loss = 0.5f * (e0 * e0 + e1 * e1) * inv;
-  const float d0 = e0 * inv, d1 = e1 * inv;
-  dys[l][0] = d0;
-  dys[l][1] = d1;
-  // ---- backward -------------------------------------------------------------------------------
-  // g3 = (W4^T dy) * silu'(z3)  (lane = sample)
-  for (int f = 0; f < 64; f += 4) {
-    float g[4];
+  float loss = 0.f, d0 = 0.f, d1 = 0.f;
+  if (own) {
+    float y0 = w[MLP_OB4], y1 = w[MLP_OB4 + 1];
+    for (int f = 0; f < 64; ++f) {
+      const float h3 = silu_f(Zt3[l * LP + f]);
+      y0 += w[MLP_OW4 + f] * h3;
+      y1 += w[MLP_OW4 + MLP_H + f] * h3;
+    }
+    const float e0 = y0 - t0, e1 = y1 - t1;
+    loss = 0.5f * (e0 * e0 + e1 * e1) * inv;
+    d0 = e0 * inv;
+    d1 = e1 * inv;
+    dys[l][0] = d0;
+    dys[l][1] = d1;
+    // ---- backward -----------------------------------------------------------------------------
+    // g3 = (W4^T dy) * silu'(z3)  (lane = sample)
+    for (int f = 0; f < 64; f += 4) {
+      float g[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      g[j] = (w[MLP_OW4 + f + j] * d0 + w[MLP_OW4 + MLP_H + f + j] * d1) * dsilu_f(Zt3[l * LP + f + j]);
-    *reinterpret_cast<float4*>(&G32[l * LP + f]) = make_float4(g[0], g[1], g[2], g[3]);
-    lds_store_b4(&Gt[l * LP + f], g[0], g[1], g[2], g[3]);
+      for (int j = 0; j < 4; ++j)
+        g[j] = (w[MLP_OW4 + f + j] * d0 + w[MLP_OW4 + MLP_H + f + j] * d1) * dsilu_f(Zt3[l * LP + f + j]);
+      *reinterpret_cast<float4*>(&G32[l * LP + f]) = make_float4(g[0], g[1], g[2], g[3]);
+      lds_store_b4(&Gt[l * LP + f], g[0], g[1], g[2], g[3]);
+    }
   }
   __syncthreads();
   {  // dW4, db3 (lane = feature), db4
     const int f = l;
     float a0 = 0.f, a1 = 0.f, bsum = 0.f;
-    for (int s = 0; s < 64; ++s) {
+    for (int s = 0; s < NS; ++s) {
       const float h3 = silu_f(Zt3[s * LP + f]);
       a0 += dys[s][0] * h3;
       a1 += dys[s][1] * h3;
@@ -194,7 +207,7 @@ __global__ __launch_bounds__(64) void k_mlp_grad(GradArgs G) {
       for (int nt = 0; nt < 4; ++nt) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
+        for (int kk = 0; kk < NT; ++kk) {
           // A[out 16mt + r][sample 16kk + 4q + j], B[sample 16kk + 4q + j][in 16nt + r]
           const bf16x4 a = lds_b4_strided(&Gt[(16 * kk + 4 * q) * LP + 16 * mt + r], LP);
           const bf16x4 b = lds_b4_strided(&Hin[(16 * kk + 4 * q) * LP + 16 * nt + r], LP);
@@ -203,11 +216,11 @@ __global__ __launch_bounds__(64) void k_mlp_grad(GradArgs G) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) gp[ow + MLP_H * (16 * mt + 4 * q + j) + 16 * nt + r] = acc[j];
       }
-    f32x4 dh[4][4];
+    f32x4 dh[4][NT];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt) {
+      for (int nt = 0; nt < NT; ++nt) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk)
@@ -219,7 +232,7 @@ __global__ __launch_bounds__(64) void k_mlp_grad(GradArgs G) {
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt) {
+      for (int nt = 0; nt < NT; ++nt) {
         const int s = 16 * nt + r, f0 = 16 * mt + 4 * q;
         float g[4];
 #pragma unroll
@@ -236,11 +249,11 @@ __global__ __launch_bounds__(64) void k_mlp_grad(GradArgs G) {
     const int f = l;
     if (layer == 1) {   // db2
       float bsum = 0.f;
-      for (int s = 0; s < 64; ++s) bsum += G32[s * LP + f];
+      for (int s = 0; s < NS; ++s) bsum += G32[s * LP + f];
       gp[MLP_OB2 + f] = bsum;
     } else {            // dW1, db1
       float a0 = 0.f, a1 = 0.f, bsum = 0.f;
-      for (int s = 0; s < 64; ++s) {
+      for (int s = 0; s < NS; ++s) {
         const float g = G32[s * LP + f];
         a0 += g * xs[s][0];
         a1 += g * xs[s][1];
@@ -671,7 +684,7 @@ sph_status launch_grad(sph_ctx* c, const float* x, const float* t, int64_t n, in
   G.batch = batch;
   G.gpart = c->mlp->gpart;
   G.lpart = c->mlp->lpart;
-  hipLaunchKernelGGL(k_mlp_grad, dim3(batch / 64), dim3(64), 0, c->stream, G);
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mlp_grad<kGradSamples>), dim3(batch / kGradSamples), dim3(64), 0, c->stream, G);
   HIP_TRY(hipGetLastError());
   return SPH_OK;
 }
@@ -754,12 +767,12 @@ sph_status sph_mlp_get_norm(sph_ctx* c, float* norm8) {
 
 sph_status sph_mlp_grad(sph_ctx* c, const float* x, const float* t, int64_t n, float* grad, double* loss) {
   if (!c || !x || !t || !grad || !c->mlp || !c->mlp->loaded) return SPH_E_ARG;
-  if (n < 64 || n % 64 || n / 64 > kMaxBlocks) return SPH_E_ARG;
+  if (n < 64 || n % 64 || n > kMaxBatch) return SPH_E_ARG;
   MlpState* s = c->mlp;
   sph_status e = launch_grad(c, x, t, n, 0, (int)n);
   if (e) return e;
   hipLaunchKernelGGL(k_mlp_adam, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, c->stream, s->w, s->wr, s->m, s->v,
-                     s->gpart, s->lpart, (int)(n / 64), 0.f, 1.f, 1.f, s->gsum, s->scal);
+                     s->gpart, s->lpart, (int)(n / kGradSamples), 0.f, 1.f, 1.f, s->gsum, s->scal);
   HIP_TRY(hipGetLastError());
   float l = 0.f;
   HIP_TRY(hipMemcpyAsync(grad, s->gsum, sizeof(float) * MLP_NPARAM, hipMemcpyDeviceToHost, c->stream));
@@ -772,7 +785,7 @@ sph_status sph_mlp_grad(sph_ctx* c, const float* x, const float* t, int64_t n, f
 sph_status sph_mlp_train(sph_ctx* c, const double* samples, int64_t n, int64_t n_holdout, int32_t epochs,
                          int32_t batch, float lr, float* history) {
   if (!c || !samples || !c->mlp || !c->mlp->loaded || !table_ok(c)) return SPH_E_ARG;
-  if (n_holdout < 0 || n - n_holdout < batch || epochs < 0 || batch < 64 || batch % 64 || batch / 64 > kMaxBlocks ||
+  if (n_holdout < 0 || n - n_holdout < batch || epochs < 0 || batch < 64 || batch % 64 || batch > kMaxBatch ||
       !(lr > 0.f))
     return SPH_E_ARG;
   MlpState* s = c->mlp;
@@ -788,7 +801,7 @@ sph_status sph_mlp_train(sph_ctx* c, const double* samples, int64_t n, int64_t n
   const int64_t ntrain = n - n_holdout;
   const int64_t per_epoch = ntrain / batch;
   const int64_t total = per_epoch * epochs;
-  const int nblk = batch / 64;
+  const int nblk = batch / kGradSamples;
   const unsigned hold_blocks = n_holdout > 0 ? (unsigned)((n_holdout + 63) / 64 < 1024 ? (n_holdout + 63) / 64 : 1024) : 0;
   for (int32_t ep = 0; ep < epochs && !e; ++ep) {
     for (int64_t k = 0; k < per_epoch && !e; ++k) {
