@@ -332,6 +332,32 @@ def test_one_multi_step_call_equals_single_step_calls():
         assert np.array_equal(a[k], b[k]), k
 
 
+def test_force_pass_with_stress_records_in_lds():
+    # most tiles hold stressed particles (60% of a random box are crust), so the FP32 force pass
+    # stages the neighbours' S/D^2 in LDS; stressed and unstressed neighbours mix in every list
+    n = 3000
+    x, y, z = random_box(n, 1.0, 11)
+    rng = np.random.default_rng(12)
+    S = rng.normal(scale=0.2, size=(6, n))
+    S[:3] -= S[:3].mean(0)
+    typ = (rng.uniform(size=n) < 0.6).astype(np.int8)
+    S[:, typ == 0] = 0
+    arr = dict(x=x, y=y, z=z, vx=rng.normal(scale=0.1, size=n), vy=rng.normal(scale=0.1, size=n),
+               vz=rng.normal(scale=0.1, size=n), u=rng.uniform(0.5, 2, n), h=0.035 * rng.uniform(0.5, 2.0, n),
+               S=S, type=typ, broken=np.zeros(n, np.uint8), id=np.arange(n, dtype=np.int32))
+    for periodic in (False, True):
+        p = MethodParams(m=1.0 / n, kernel="WC4", periodic=periodic, box=1.0, eos="GAMMA_LAW", gamma=5 / 3,
+                         mu_mode="CONST", mu_const=0.5, precision="FP32")
+        wr = W.Workload("rand", p, dict(arr), 1e-3, 0)
+        o = oracle_run(wr, mode=oracle.BRUTE)
+        g = gpu_run(wr)
+        assert check_lists(g, o, n) == 0
+        e = eval_errors(g, o)
+        _print(f"S/D^2 in LDS, periodic={periodic}", e)
+        for k in ("D", "rho", "P", "ax", "ay", "az", "dudt", "dSdt"):
+            assert e[k] < 1e-4, (k, e[k])
+
+
 @pytest.mark.parametrize("cell_div", [2, 4])
 def test_cell_size_leaves_the_neighbour_sets(cell_div):
     # finer cells than the default (2, 4 per smoothing diameter instead of 1) change the cell
