@@ -155,7 +155,7 @@ void sph_destroy(sph_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   void* bufs[] = {c->grid, c->keys, c->vals, c->cell_se, c->pos_sorted, c->sort.keys_alt, c->sort.vals_alt,
                   c->sort.hist, c->sort.rowtot, c->sort.partial, c->sort.scan_bsum, c->tile_u, c->tile_start, c->tile_cnt, c->tile_uoff,
-                  c->tile_usize, c->stress_tiles, c->nbr16, c->nbr_count, c->nbr_count_sl, c->nbr16s, c->nbr_count_s, c->pos_build, c->drift_flag,
+                  c->tile_usize, c->stress_tiles, c->tile_st, c->nbr16, c->nbr_count, c->nbr_count_sl, c->nbr16s, c->nbr_count_s, c->pos_build, c->drift_flag,
                   c->pos4, c->fv, c->fa, c->sig, c->pos4f, c->fvf,
                   c->faf, c->sigf, c->mu, c->Y0, c->B, c->sdot, c->tovf, c->half, c->tmp, c->stars, c->status,
                   c->dsum, c->dDdt, c->xcoef, c->dtw, c->dtpart, c->eos_list, c->eos_list_n};
@@ -212,7 +212,7 @@ sph_status sph_create(const sph_params* params, void* stream, int64_t capacity, 
       (e = dalloc(&c->sort.partial, (size_t)8 * 1024)) ||
       (e = dalloc(&c->tile_u, (size_t)c->upool)) || (e = dalloc(&c->tile_usize, c->cap_tiles)) ||
       (e = dalloc(&c->tile_start, c->cap_tiles)) || (e = dalloc(&c->tile_cnt, c->cap_tiles)) ||
-      (e = dalloc(&c->stress_tiles, c->cap_tiles)) ||
+      (e = dalloc(&c->stress_tiles, c->cap_tiles)) || (e = dalloc(&c->tile_st, c->cap_tiles)) ||
       (e = dalloc(&c->tile_uoff, c->cap_tiles)) ||
       (e = dalloc(&c->sort.scan_bsum, c->sort.scan_cap + 1)) ||
       (e = dalloc(&c->nbr16, (size_t)capw * slot_entries_max(c->cap))) || (e = dalloc(&c->nbr_count, capw)) ||

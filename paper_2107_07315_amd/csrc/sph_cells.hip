@@ -353,6 +353,24 @@ __global__ __launch_bounds__(kB) void k_stress_flags(const GridInfo* __restrict_
   }
   flag[t] = f;
 }
+// Per tile: whether one of its particles or of its union members is of type 1 (one wave a tile).
+__global__ __launch_bounds__(64) void k_tile_union_type(const GridInfo* __restrict__ gp, const int32_t* __restrict__ tile_start,
+                                                       const int32_t* __restrict__ tile_cnt,
+                                                       const uint32_t* __restrict__ tile_uoff,
+                                                       const int32_t* __restrict__ tile_usize,
+                                                       const int32_t* __restrict__ tile_u,
+                                                       const int8_t* __restrict__ type, uint32_t* __restrict__ flag) {
+  const int lane = threadIdx.x;
+  const int64_t nt = gp->ntiles;
+  for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+    bool f = lane < tile_cnt[t] && type[tile_start[t] + lane] == 1;
+    const int32_t us = tile_usize[t];
+    const int32_t* U = tile_u + tile_uoff[t];
+    for (int j = lane; j < us && !f; j += 64) f = type[U[j]] == 1;
+    const unsigned long long m = __ballot(f);
+    if (lane == 0) flag[t] = m ? 1u : 0u;
+  }
+}
 __global__ __launch_bounds__(kB) void k_stress_list(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ idx,
                                                     int64_t cap_tiles, int32_t* __restrict__ list) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1096,6 +1114,8 @@ sph_status sph_rebin(sph_ctx* c, sph_state* st, bool outputs_recomputed) {
   B.tile_u = c->tile_u; B.tile_usize = c->tile_usize; B.nbr16 = c->nbr16s; B.count = c->nbr_count_s;
   B.status = c->status;
   launch_build(B, per, dim3(tile_grid(c->cap_tiles)), s);
+  hipLaunchKernelGGL(k_tile_union_type, dim3(tile_grid(c->cap_tiles)), dim3(64), 0, s, c->grid, c->tile_start,
+                     c->tile_cnt, c->tile_uoff, c->tile_usize, c->tile_u, st->type, c->tile_st);
   HIP_TRY(hipGetLastError());
   // the zero rates of every type-0 particle
   hipLaunchKernelGGL(k_zero_fluid_rates, dim3(grid_for(n, kB)), dim3(kB), 0, s, st->type, n, st->S, st->dSdt,

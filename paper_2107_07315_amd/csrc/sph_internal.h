@@ -335,6 +335,7 @@ struct sph_ctx {
   int64_t cap_tiles;
   int32_t* tile_usize;
   int32_t* stress_tiles;  // tiles with a type-1 particle, in tile order (nstress of them)
+  uint32_t* tile_st;      // per tile: 1 if a particle or a union member is of type 1
   uint16_t* nbr16;      // exact lists, one per slot (particle * lanes + sub-index)
   int32_t* nbr_count;   // exact neighbours per particle
   int32_t* nbr_count_sl;  // entries per slot list

@@ -130,6 +130,7 @@ struct PassArgs {
   // terms vanish beyond the support, so the sums are the same; the density pass then writes no
   // exact lists)
   int cand_walk;
+  const uint32_t* __restrict__ tile_st;   // per tile: a particle or union member of type 1 (or null)
   const int32_t* __restrict__ star;
   const StarInfo* __restrict__ stars;
   DevStatus* status;
@@ -1015,7 +1016,7 @@ __device__ __forceinline__ void ext_accel(const PassArgs& A, const ForceOut& O, 
 // neighbour's union index and six S/D^2 values from memory).
 constexpr int kXDD = 1, kXGP = 2, kXSL = 4;
 template <typename R, int KER, bool PER, int L, int XS>
-__global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Rec<R>::P4* __restrict__ pos,
+__global__ __launch_bounds__(64 * L) __attribute__((amdgpu_waves_per_eu(4))) void k_forces(PassArgs A, const typename Rec<R>::P4* __restrict__ pos,
                                                    const typename Rec<R>::V4* __restrict__ fv,
                                                    const typename Rec<R>::A2* __restrict__ fa,
                                                    const R* __restrict__ sig, const double4* __restrict__ tov,
@@ -1065,7 +1066,8 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
   struct Recs { P4 p; V4 v; A2 f; };
   int cbase = 0;   // union index of LDS slot 0 (the chunk's first member)
   // pair with union member loc, records r (the sentinel: F = 0, which zeroes every term)
-  auto pair = [&](int loc, const Recs& r) {
+  // ST: the stress term is compiled in (a stressed target or union member can occur)
+  auto pair_st = [&](int loc, const Recs& r, auto ST) {
     const P4& pb = r.p;
     const V4& vb = r.v;
     const A2& fab = r.f;
@@ -1095,7 +1097,7 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
     ud += (pia + (R)0.5 * Pi) * Fvr;
     if constexpr (DD) dd += Fvr;
     if constexpr (GP) gp += (pia + fab.x) * F * (va.x * d[0] + va.y * d[1] + va.z * d[2]);
-    if (a_st || b_st) {
+    if (decltype(ST)::value && (a_st || b_st)) {
       const R g[3] = {F * d[0], F * d[1], F * d[2]};
       R s6[6];
       if constexpr (SL) {
@@ -1137,15 +1139,23 @@ __global__ __launch_bounds__(64 * L) void k_forces(PassArgs A, const typename Re
                               [&](int j, const Recs& r) { sp[j] = r.p; sv[j] = r.v; sa2[j] = r.f; });
     }
   };
+  auto pair = [&](int loc, const Recs& r) { pair_st(loc, r, std::true_type{}); };
   // FP32 with the whole union in one chunk (the usual case): pipelined group walk.  (In FP64 the 8
   // inlined copies of the longer pair body run slower than the shifting walk, measured.)
   if (std::is_same<R, float>::value && tw.usize <= CHU) {
     __syncthreads();
     stage(0);
     __syncthreads();
-    walk_groups_pf(
-        lst, A.capw * L, cnt, wave_max_i(cnt), CHU, [&](int j) { return Recs{sp[j], sv[j], sa2[j]}; }, pair,
-        [] {});
+    // a tile whose particles and union members are all of type 0 (the list build's flag) walks
+    // without the stress term
+    const bool any_st = SL || !A.tile_st || A.tile_st[tile] != 0u;
+    auto ld = [&](int j) { return Recs{sp[j], sv[j], sa2[j]}; };
+    if (any_st)
+      walk_groups_pf(lst, A.capw * L, cnt, wave_max_i(cnt), CHU, ld, pair, [] {});
+    else
+      walk_groups_pf(
+          lst, A.capw * L, cnt, wave_max_i(cnt), CHU, ld,
+          [&](int loc, const Recs& r) { pair_st(loc, r, std::false_type{}); }, [] {});
   } else {
     tw.start(lst, A.capw * L, cnt);
     for (int c0 = 0; c0 < tw.usize; c0 += CHU) {
@@ -1254,6 +1264,7 @@ PassArgs make_args(sph_ctx* c, sph_state* st) {
   A.nbr16s = c->nbr16s;
   A.cnt_s = c->nbr_count_s;
   A.cand_walk = exact_lists_written(c) ? 0 : 1;
+  A.tile_st = c->tile_st;
   A.star = c->stars ? st->star : nullptr;
   A.stars = c->stars;
   A.status = c->status;
