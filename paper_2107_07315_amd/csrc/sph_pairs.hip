@@ -1140,15 +1140,16 @@ __global__ __launch_bounds__(64 * L) __attribute__((amdgpu_waves_per_eu(4))) voi
     }
   };
   auto pair = [&](int loc, const Recs& r) { pair_st(loc, r, std::true_type{}); };
+  // a tile whose particles and union members are all of type 0 (the list build's flag) walks
+  // without the stress term
+  auto stress_tile = [&] { return SL || !A.tile_st || A.tile_st[tile] != 0u; };
   // FP32 with the whole union in one chunk (the usual case): pipelined group walk.  (In FP64 the 8
   // inlined copies of the longer pair body run slower than the shifting walk, measured.)
   if (std::is_same<R, float>::value && tw.usize <= CHU) {
     __syncthreads();
     stage(0);
     __syncthreads();
-    // a tile whose particles and union members are all of type 0 (the list build's flag) walks
-    // without the stress term
-    const bool any_st = SL || !A.tile_st || A.tile_st[tile] != 0u;
+    const bool any_st = stress_tile();
     auto ld = [&](int j) { return Recs{sp[j], sv[j], sa2[j]}; };
     if (any_st)
       walk_groups_pf(lst, A.capw * L, cnt, wave_max_i(cnt), CHU, ld, pair, [] {});
@@ -1157,6 +1158,7 @@ __global__ __launch_bounds__(64 * L) __attribute__((amdgpu_waves_per_eu(4))) voi
           lst, A.capw * L, cnt, wave_max_i(cnt), CHU, ld,
           [&](int loc, const Recs& r) { pair_st(loc, r, std::false_type{}); }, [] {});
   } else {
+    const bool any_st = sizeof(R) == 4 || XS != 0 || stress_tile();
     tw.start(lst, A.capw * L, cnt);
     for (int c0 = 0; c0 < tw.usize; c0 += CHU) {
       __syncthreads();
@@ -1164,12 +1166,20 @@ __global__ __launch_bounds__(64 * L) __attribute__((amdgpu_waves_per_eu(4))) voi
       __syncthreads();
       cbase = c0;
       const int cend = c0 + CHU;
-      while (tw.next < cend) {
-        const int loc = tw.next;
-        tw.advance();
-        const int j = loc - c0;
-        pair(loc, Recs{sp[j], sv[j], sa2[j]});
-      }
+      auto walk = [&](auto ST) {
+        while (tw.next < cend) {
+          const int loc = tw.next;
+          tw.advance();
+          const int j = loc - c0;
+          pair_st(loc, Recs{sp[j], sv[j], sa2[j]}, ST);
+        }
+      };
+      // (FP64 only: in FP32 this walk serves the rare large unions, and a second copy slowed the
+      // pass; the FP64 variant with the extra sums keeps one walk too, a second one spills)
+      if (any_st)
+        walk(std::true_type{});
+      else
+        walk(std::false_type{});
     }
   }
 #pragma unroll
